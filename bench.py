@@ -1,0 +1,223 @@
+"""Benchmark: full-order solves/sec of the recycled-CG sequence (Algorithm 2, CG form)
+on one MI355X, plus the stencil SpMM HBM bandwidth, the roofline position of the
+dominant kernel, and the CPU oracle timed on a bounded sample of the same workload.
+
+A step = one pass of the whole path on the workload: assemble A_* (Sec. 3), run
+rom_solve_sequence over every parameter point and right-hand side (Sec. 4.3), and
+form the reduced matrices of eq. (newreduced) at the last point.  Inputs (grid,
+parameters, U_0) are resident before the timed region; one JSON line goes to stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, points, n_sample_rhs: int):
+    """The FP64 oracle, untuned, on a bounded sample: assembly plus point 0 for the first
+    n_sample_rhs right-hand sides (orthonormalise U_0, outer projections, deflated CG,
+    appends)."""
+    import threadpoolctl
+
+    import phantoms as ph
+    from oracle import operator as op
+    from oracle import sequence as oseq
+    t0 = time.perf_counter()
+    D = ph.diffusion_field(wl)
+    As = op.assemble_Astar(wl.dim, wl.N, wl.bc, D, wl.robin_A)
+    p = points[0]
+    mu = op.mu_field(wl.dim, wl.N, p.mu0, p.centers, p.radii, p.amps)
+    si, di = ph.rhs_nodes(wl)
+    ss, ds = ph.rhs_scales(wl)
+    B = oseq.rhs_matrix(wl.n, si, ss, di, ds)[:, :n_sample_rhs]
+    U0 = ph.smooth_modes(wl)
+    res = oseq.solve_sequence(As, [mu], B, U0, wl.tol, wl.trunc, keep_X=False)
+    dt = time.perf_counter() - t0
+    info = threadpoolctl.threadpool_info()
+    cores = max([d.get("num_threads", 1) for d in info] + [1])
+    its = sum(r.its for r in res.records)
+    return {"value": n_sample_rhs / dt, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{wl.name}: assembly + point 0, right-hand sides 1-{n_sample_rhs} "
+                      f"({its} CG iterations) in {dt:.1f} s; scipy.sparse products single-threaded, "
+                      f"dense NumPy/BLAS on {cores} threads"}
+
+
+def spmm_bandwidth(prob, point, k: int, reps: int = 5):
+    """HBM GB/s of the stencil SpMM Y = A(p) X over k columns (rom_apply_operator)."""
+    import torch
+    from paper_1602_00138_amd import rom as R
+    n = prob.n
+    X = torch.randn((k, n), dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    scratch = torch.empty(8 * n, dtype=torch.uint8, device="cuda")
+    R.rom_apply_operator(prob.op, point, X, Y, k, scratch)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        R.rom_apply_operator(prob.op, point, X, Y, k, scratch)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    var = prob.D_field is not None
+    by = n * (16.0 * k + 8.0 + (24.0 if var else 0.0))
+    return {"k": k, "bytes": by, "ms": ms, "GBps": by / ms / 1e6,
+            "frac_of_peak": by / ms / 1e6 / HBM_PEAK_GBS,
+            "note": "Y = A(p) X, X and Y N x k FP64; bytes = N(16k + 8) (+24N with a D field); "
+                    "the timed call also evaluates mu(p) on the nodes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--points", type=int, default=0, help="parameter points (0: the workload's)")
+    ap.add_argument("--tol", type=float, default=0.0)
+    ap.add_argument("--mode", default="independent", choices=["independent", "drift"])
+    ap.add_argument("--cpu-sample", type=int, default=4, help="oracle sample RHS (0: skip)")
+    ap.add_argument("--kernel", default="auto", help="kernel class for the roofline")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU "
+                                   "sharding is a design note, not implemented)"}))
+        sys.exit(2)
+
+    import torch
+
+    import phantoms as ph
+    from paper_1602_00138_amd import driver
+    from paper_1602_00138_amd import rom as R
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    wl = ph.WORKLOADS[args.workload]
+    if args.points:
+        wl = wl.replace(K=args.points)
+    if args.tol:
+        wl = wl.replace(tol=args.tol)
+    prob = driver.problem_from_workload(wl)
+    pts = driver.points_from_workload(wl, mode=args.mode)
+    K, n_rhs = len(pts), prob.n_rhs
+    dev = torch.device("cuda:0")
+
+    # caller-owned buffers, allocated once outside the timed region
+    opts_all = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=(1 << R.ROM_NK) - 1)
+    nbytes = R.rom_sequence_bytes(prob.op, prob.src_idx.size, prob.det_idx.size, prob.k_u, K, opts_all)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    X = torch.empty((K * n_rhs, prob.n), dtype=torch.float64, device=dev)
+    log(f"workload {wl.name}: grid {wl.N[:wl.dim]}, n={prob.n}, {n_rhs} RHS x {K} points, "
+        f"tol {wl.tol}, workspace {nbytes / 2**30:.2f} GiB")
+
+    def step(opts):
+        R.rom_assemble_operator(prob.grid, 0.0 if prob.D_field is not None else float(wl.D),
+                                prob.D_field, prob.op_mem)
+        status, basis, recs, st = R.rom_solve_sequence(
+            prob.op, pts, prob.src_idx, prob.src_scale, prob.det_idx, prob.det_scale, prob.U0,
+            prob.k_u, opts, ws, X)
+        n, m = R.rom_basis_dims(basis)
+        Ar = torch.empty((m, m), dtype=torch.float64, device=dev)
+        Br = torch.empty((prob.src_idx.size, m), dtype=torch.float64, device=dev)
+        Cr = torch.empty((prob.det_idx.size, m), dtype=torch.float64, device=dev)
+        Er = torch.empty((m, m), dtype=torch.float64, device=dev)
+        scr = torch.empty(R.rom_reduced_bytes(basis), dtype=torch.uint8, device=dev)
+        R.rom_reduced_transfer(basis, pts[-1], Ar, Br, Cr, Er, scr)
+        R.rom_basis_destroy(basis)
+        return status, recs, R.stats_dict(st)
+
+    # warmup (all kernel classes timed, to find the dominant one)
+    stats_w = None
+    for w in range(max(args.warmup, 1)):
+        t = time.perf_counter()
+        status, recs, stats_w = step(opts_all)
+        torch.cuda.synchronize()
+        log(f"warmup {w}: {time.perf_counter() - t:.2f} s, m={stats_w['m']}, "
+            f"solved {stats_w['n_solved']}/{K * n_rhs}, its {stats_w['total_its']}")
+    kern = stats_w["kernels"]
+    for name, d in kern.items():
+        if d["launches"] and d["ms"] > 0:
+            log(f"  {name:11s} launches {d['launches']:7d}  {d['ms']:9.2f} ms  "
+                f"{d['bytes'] / max(d['ms'], 1e-9) / 1e6:8.0f} GB/s (algorithmic)")
+    dom = args.kernel
+    if dom == "auto":
+        dom = max((k for k in kern if k != "other"), key=lambda k: kern[k]["ms"])
+    cls = R.KERNEL_CLASSES.index(dom)
+    opts = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=1 << cls)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg = {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0}
+    bad = 0
+    last = None
+    for s in range(args.steps):
+        status, recs, st = step(opts)
+        d = st["kernels"][dom]
+        for k in agg:
+            agg[k] += d[k]
+        bad += sum(1 for r in recs if not r["converged"])
+        last = st
+        log(f"step {s}: {st['seconds']:.3f} s in solve_sequence")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solves = K * n_rhs * args.steps
+    value = solves / dt
+
+    avg_ms = agg["ms"] / max(agg["launches"], 1)
+    bound = "mfma" if dom == "gram" else "hbm"
+    if bound == "hbm":
+        achieved = agg["bytes"] / max(agg["ms"], 1e-12) / 1e6
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    else:
+        achieved = agg["flops"] / max(agg["ms"], 1e-12) / 1e9
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+    roof.update({"kernel": dom, "launches": agg["launches"], "avg_launch_us": 1e3 * avg_ms,
+                 "bytes_per_launch": agg["bytes"] / max(agg["launches"], 1)})
+
+    spmm = spmm_bandwidth(prob, pts[-1], 64)
+    log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s)")
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline(wl, ph.parameter_points(wl, mode=args.mode), args.cpu_sample)
+        log(f"cpu oracle: {cpu['value']:.3f} solves/s ({cpu['sample']})")
+
+    out = {
+        "metric": "full-order solves/sec at 1e-8 rel. residual; SpMM HBM GB/s vs peak",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {'x'.join(map(str, wl.N[:wl.dim]))} grid, "
+                               f"{wl.n_src}+{wl.n_det} RHS, {K} points ({args.mode}), tol {wl.tol}, "
+                               f"plain FP64 recycled CG",
+                   "n": prob.n, "points": K, "rhs": n_rhs, "tol": wl.tol,
+                   "basis_m": last["m"], "inner_its": last["total_its"],
+                   "solved": last["n_solved"], "nonconverged": bad},
+        "roofline": roof,
+        "spmm": spmm,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

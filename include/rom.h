@@ -1,0 +1,197 @@
+/*
+ * rom.h -- C ABI of the MI355X (gfx950) library for inner-outer Krylov recycling in
+ * diffuse optical tomography (O'Connell, Kilmer, de Sturler, Gugercin, arXiv:1602.00138).
+ *
+ * The three calls follow the paper's statement of the problem:
+ *   rom_assemble_operator  -- the SPD zero-frequency operator A(p) = A_* + diag(mu(p))
+ *                             of Sec. 3 / eq. (sum): finite differences of
+ *                             -div(D grad eta) + mu eta with the Robin boundary
+ *                             unknowns eliminated (Schur complement of eq. (block1)).
+ *   rom_solve_sequence     -- Algorithm 2 (Sec. 4.3): solves A(p_i) X_i = [B~, C~]
+ *                             (eq. (blkeqn)) for a sequence of parameter points with
+ *                             recycled CG and grows the global basis V.
+ *   rom_reduced_transfer   -- the reduced matrices of eq. (newreduced):
+ *                             E_r = V^T V, A_r(p) = V^T A(p) V, B_r = V^T B~, C_r = V^T C~.
+ *
+ * Conventions
+ *   - Grid: unit square (dim 2) or cube (dim 3), n[a] interior nodes on axis a at
+ *     (i+1) h_a, h_a = 1/(n[a]+1); unknowns in x-fastest lexicographic order;
+ *     N = n[0]*n[1]*n[2] (n[2] = 1 in 2D).
+ *   - Faces -x,+x,-y,+y,-z,+z carry bc[] = 0 (Dirichlet, eq. (ModelPDE3)) or
+ *     1 (Robin eta + 2 A D d(eta)/d(xi) = 0, eq. (ModelPDE2), first-order difference,
+ *     eliminated: the face adds (D/h^2) h/(h + 2 A D) to the diagonal).
+ *   - mu(x; p) = mu0 + sum_b amps[b] * psi(|x - centers[b]| / radii[b]),
+ *     psi(t) = (1-t)^4 (4t+1) for t < 1 (compactly supported RBFs, Sec. 2.1, Sec. 5).
+ *   - Sources B~ and detectors C~ are scaled identity columns (Sec. 3.1): column j
+ *     is scale[j] * e_{idx[j]}.  The right-hand side block is [B~, C~], sources first.
+ *   - All dense device matrices are column-major with leading dimension N.
+ *
+ * Memory: the library never allocates device memory.  The caller provides device
+ * buffers (sizes from rom_operator_bytes / rom_sequence_bytes) and keeps them alive
+ * for as long as a handle that refers to them is in use.  Handles themselves are
+ * small host objects owned by the library and released with the *_destroy calls.
+ *
+ * Streams: every call enqueues its work on `stream` (a hipStream_t, NULL = default
+ * stream).  rom_solve_sequence synchronises that stream at its decision points
+ * (the skip test of Algorithm 2, CG convergence polls, the truncation test) and
+ * returns when all its work is complete.  rom_assemble_operator and
+ * rom_reduced_transfer return with their work enqueued (asynchronous).
+ *
+ * Errors: a call returns ROM_OK (0) or a negative status; rom_last_error() gives a
+ * message for the calling thread.  Invalid arguments are rejected before any work is
+ * enqueued.
+ */
+#ifndef ROM_H
+#define ROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ROM_API __attribute__((visibility("default")))
+#else
+#define ROM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int rom_status;
+#define ROM_OK 0
+#define ROM_EINVAL (-1)     /* bad argument (shape, pointer, size) */
+#define ROM_ENOTSPD (-2)    /* CG or Cholesky met a non-positive curvature / pivot */
+#define ROM_ENONFINITE (-3) /* NaN or Inf in the iteration */
+#define ROM_ENOCONV (-4)    /* some solve hit maxit (per-solve flags in the records) */
+#define ROM_ECAPACITY (-5)  /* workspace too small */
+#define ROM_EHIP (-6)       /* HIP runtime error */
+
+#define ROM_NJ_MAX 64       /* max columns of a per-RHS recycle space U_j */
+#define ROM_MAX_BUMPS 64
+
+typedef struct rom_operator rom_operator;
+typedef struct rom_basis rom_basis;
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  int n[3];         /* interior nodes per axis; n[2] = 1 when dim == 2 */
+  int bc[6];        /* per face -x,+x,-y,+y,-z,+z: 0 Dirichlet, 1 Robin */
+  double robin_A;   /* the constant A of eq. (ModelPDE2) */
+} rom_grid;
+
+typedef struct {
+  int nb;                 /* number of RBF bumps (0 .. ROM_MAX_BUMPS) */
+  const double* centers;  /* host, nb x dim, row-major */
+  const double* radii;    /* host, nb */
+  const double* amps;     /* host, nb */
+  double mu0;             /* background absorption */
+} rom_mu;
+
+typedef struct {
+  double tol;       /* relative residual tolerance ||b - A x|| <= tol ||b|| (Alg. 2 skip test and CG stop) */
+  double trunc;     /* keep a new basis direction iff its norm outside range(V) > trunc (unit input) */
+  int cap;          /* max basis columns (0: k_u + n_rhs * K) */
+  int maxit;        /* max inner CG iterations per solve (0: N) */
+  int check_every;  /* CG iterations between host convergence polls (0: 16) */
+  int timing;       /* bit mask over ROM_K_* classes: time every launch of those classes with
+                       HIP events (0: no events; algorithmic bytes are always counted) */
+} rom_opts;
+
+/* One record per (point i, right-hand side j), in solve order. */
+typedef struct {
+  int point, rhs;
+  double rho0;      /* relative residual after the outer projection on V */
+  int its;          /* inner CG iterations (0 when skipped) */
+  int solved;       /* 1 if the inner recycled CG ran */
+  int kept;         /* 1 if the correction was appended to V */
+  double rho;       /* norm of the normalised correction outside range(V) (-1 if not solved) */
+  double final_res; /* true relative residual of the returned solution */
+  int m;            /* basis size after this right-hand side */
+  int restarts;     /* CG restarts from the true residual */
+  int converged;    /* 1 if final_res <= tol */
+  int pad;
+} rom_record;
+
+/* Instrumented kernel classes (timing/bytes accumulated when opts.timing = 1). */
+#define ROM_K_SPMV 0        /* stencil products */
+#define ROM_K_DCG_UPDATE 1  /* CG step: g += a p, s -= a w, s^T s, (A U_j)^T s */
+#define ROM_K_DCG_DIR 2     /* CG step: p = s + b p - U_j y */
+#define ROM_K_GEMVT 3       /* V^T x (tall-skinny transposed products) */
+#define ROM_K_GEMVN 4       /* V c (tall-skinny products) */
+#define ROM_K_GRAM 5        /* V^T diag(w) V (FP64 MFMA) */
+#define ROM_K_OTHER 6
+#define ROM_NK 7
+
+typedef struct {
+  int m;                 /* final basis size */
+  int k_u;               /* columns of U_0 kept after orthonormalisation */
+  int n_solved, n_kept, n_dropped_trunc, n_dropped_cap, n_nonconv;
+  long long total_its;
+  double seconds;        /* host wall time of the call */
+  double kernel_ms[ROM_NK];      /* summed event time per class (timed classes only) */
+  double kernel_bytes[ROM_NK];   /* summed algorithmic bytes per class */
+  double kernel_flops[ROM_NK];   /* summed algorithmic flops per class */
+  long long kernel_launches[ROM_NK];
+} rom_stats;
+
+/* Device bytes needed by rom_assemble_operator (variable_D = 1 for a per-node D). */
+ROM_API rom_status rom_operator_bytes(const rom_grid* grid, int variable_D, size_t* bytes);
+
+/* Assemble A_* (Sec. 3, eq. (sum)) into caller memory `op_mem` (device, >= bytes).
+ * D_field == NULL: constant diffusion D_const (> 0).  Otherwise D_field is a device
+ * array of N per-node values (> 0): an interior face takes the harmonic mean of its
+ * two nodes, a boundary face the node value.  *op receives a host handle referring
+ * to op_mem (and to D_field's values copied into op_mem). */
+ROM_API rom_status rom_assemble_operator(const rom_grid* grid, double D_const, const double* D_field,
+                                 void* op_mem, size_t op_bytes, rom_operator** op,
+                                 void* stream);
+
+/* Y[:, c] = A(p) X[:, c] for c < k, A(p) = A_* + diag(mu(p)) (eq. (sum)).
+ * X, Y: device N x k, column-major (ld = N), must not overlap.  scratch: device,
+ * >= 8*N bytes (holds the diagonal of A(p)).  Asynchronous on `stream`. */
+ROM_API rom_status rom_apply_operator(const rom_operator* op, const rom_mu* p, const double* X,
+                                      double* Y, int k, void* scratch, size_t scratch_bytes,
+                                      void* stream);
+
+/* Device bytes of the workspace of rom_solve_sequence. */
+ROM_API rom_status rom_sequence_bytes(const rom_operator* op, int n_src, int n_det, int k_u, int K,
+                              const rom_opts* opts, size_t* bytes);
+
+/* Algorithm 2 (CG form) over K parameter points params[0..K-1] (p_0 first).
+ *   src_idx/src_scale, det_idx/det_scale: host arrays (n_src, n_det) describing B~, C~.
+ *   U0: device N x k_u (offline estimates of the low eigenvectors of A(p_0); may be
+ *       NULL when k_u == 0).  It is copied; the caller may reuse it.
+ *   workspace: device, >= rom_sequence_bytes(...).  The returned basis refers to it.
+ *   X_out: device N x (n_src+n_det) x K (column (i*(n_src+n_det) + j)), or NULL.
+ *   records: host array of K*(n_src+n_det) entries, or NULL.
+ *   stats: host, or NULL.
+ * Returns ROM_OK, or ROM_ENOCONV if some solve reached maxit (its record says which),
+ * or an error.  On success *basis receives the global basis handle. */
+ROM_API rom_status rom_solve_sequence(rom_operator* op, const rom_mu* params, int K,
+                              const int64_t* src_idx, const double* src_scale, int n_src,
+                              const int64_t* det_idx, const double* det_scale, int n_det,
+                              const double* U0, int k_u, const rom_opts* opts,
+                              void* workspace, size_t ws_bytes, rom_basis** basis,
+                              double* X_out, rom_record* records, rom_stats* stats,
+                              void* stream);
+
+/* Reduced matrices of eq. (newreduced) at parameter p for the basis V (m columns):
+ *   Ar (m x m), Er (m x m), Br (m x n_src), Cr (m x n_det): device, column-major.
+ * Any output pointer may be NULL to skip it.  scratch: device, >= rom_reduced_bytes. */
+ROM_API rom_status rom_reduced_bytes(const rom_basis* V, size_t* bytes);
+ROM_API rom_status rom_reduced_transfer(const rom_basis* V, const rom_mu* p, double* Ar, double* Br,
+                                double* Cr, double* Er, void* scratch, size_t scratch_bytes,
+                                void* stream);
+
+/* Basis queries: N, m, and a device copy of V (N x m, column-major, ld = N). */
+ROM_API rom_status rom_basis_dims(const rom_basis* V, int64_t* N, int* m);
+ROM_API rom_status rom_basis_copy(const rom_basis* V, double* dst, void* stream);
+
+ROM_API void rom_operator_destroy(rom_operator* op);
+ROM_API void rom_basis_destroy(rom_basis* V);
+ROM_API const char* rom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROM_H */

@@ -1,0 +1,253 @@
+// Deflated (recycled) CG on A g = r with the recycle space U_j (Sec. 4.2.1, CG form):
+// directions are kept A-orthogonal to U_j by p = s + beta p - U_j (U_j^T A U_j)^{-1}
+// (A U_j)^T s.  Every step is three launches (operator, update, direction).  No kernel
+// synchronises across blocks: each writes per-block partial sums and the next launch
+// reduces them; the scalar state lives in device memory (s^T s double-buffered by
+// step parity), so chunks of steps run without host round trips.  Each thread loads
+// its first row before reducing the previous launch's partials, so the reduction
+// latency hides behind the loads.
+#include "kernels.h"
+
+namespace rom {
+
+namespace {
+
+// Step kernels: 256 blocks of CgBlock threads (4 waves per SIMD on 256 CUs); the next
+// launch then reduces only 256 partial rows.
+template <int NJT>
+struct CgBlock {
+  static constexpr int value = NJT <= 32 ? 1024 : 512;
+};
+constexpr int CG_GRID = 256;
+
+__global__ void k_cg_setup(CGState* cg, double tol2, int maxit) {
+  cg->tol2 = tol2;
+  cg->maxit = maxit;
+  cg->its = 0;
+  cg->done = 0;
+  cg->flag = 0;
+  cg->gamma[0] = 0.0;
+  cg->gamma[1] = 0.0;
+  cg->pw = 0.0;
+}
+
+// ys[j] = sum_c Ginv[j + c nj] t[c] (Ginv = (U^T A U)^{-1}, symmetric), into shared memory.
+__device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv, int nj,
+                                           const double* t, double* ys) {
+  if (threadIdx.x < nj) {
+    const int j = threadIdx.x;
+    double y = 0.0;
+    for (int c = 0; c < nj; ++c) y += Ginv[j + c * nj] * t[c];
+    ys[j] = y;
+  }
+  __syncthreads();
+}
+
+// Start: y0 = G^{-1} U^T r (U^T r in cg->t), g = U y0, s = r - AU y0; partials of
+// (AU)^T s (values 0..nj-1) and s^T s (value NJT).
+template <int NJT, int B = CgBlock<NJT>::value>
+__global__ __launch_bounds__(B) void k_dcg_start(const double* __restrict__ W,
+                                                  const double* __restrict__ AW, int64_t ld,
+                                                  int64_t n, int nj,
+                                                  const double* __restrict__ Ginv,
+                                                  const double* __restrict__ r,
+                                                  double* __restrict__ g,
+                                                  double* __restrict__ s, const CGState* cg,
+                                                  double* __restrict__ part2) {
+  __shared__ double ts[NJ_MAX], ys[NJ_MAX];
+  if (threadIdx.x < nj) ts[threadIdx.x] = cg->t[threadIdx.x];
+  __syncthreads();
+  gram_apply(Ginv, nj, ts, ys);
+  double acc[NJT + 1];
+#pragma unroll
+  for (int c = 0; c <= NJT; ++c) acc[c] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
+    double gi = 0.0, si = r[i];
+    double aw[NJT];
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) {
+        aw[c] = AW[i + c * ld];
+        gi += W[i + c * ld] * ys[c];
+        si -= aw[c] * ys[c];
+      }
+    g[i] = gi;
+    s[i] = si;
+    acc[NJT] += si * si;
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) acc[c] += aw[c] * si;
+  }
+  write_partials_t<NJT + 1, B>(acc, part2, blockIdx.x, gridDim.x);
+}
+
+// Reduce the step's partials (s^T s, (AU)^T s); record s^T s for the next step, count
+// the step, stop on convergence / maxit / non-finite values; else the new direction
+// p = s + beta p - U G^{-1} (AU)^T s.  iter = -1 for the direction after the start.
+template <int NJT, int B = CgBlock<NJT>::value>
+__global__ __launch_bounds__(B) void k_dcg_dir(const double* __restrict__ W, int64_t ld,
+                                                int64_t n, int nj,
+                                                const double* __restrict__ Ginv,
+                                                const double* __restrict__ s,
+                                                double* __restrict__ p, int iter, CGState* cg,
+                                                const double* __restrict__ part2, int P2) {
+  if (cg->done) return;
+  const bool first = iter < 0;
+  // first row of this thread, loaded ahead of the reduction
+  const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
+  double w0[NJT], s0 = 0.0, p0 = 0.0;
+  if (i0 < n) {
+    s0 = s[i0];
+    if (!first) p0 = p[i0];
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) w0[c] = W[i0 + c * ld];
+  }
+  __shared__ double tot[NJT + 1];
+  __shared__ double ys[NJ_MAX];
+  sum_partials_t<NJT + 1, B>(part2, P2, tot);
+  const double gnew = tot[NJT];
+  const double gold = first ? 1.0 : cg->gamma[iter & 1];
+  const bool nonfinite = !isfinite(gnew);
+  const bool conv = gnew <= cg->tol2;
+  const bool hit = !first && iter + 1 >= cg->maxit;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cg->gamma[(iter + 1) & 1] = gnew;
+    if (!first) cg->its = iter + 1;
+    if (nonfinite) {
+      cg->flag = 2;
+      cg->done = 1;
+    } else if (conv || hit) {
+      cg->done = 1;
+    }
+  }
+  if (nonfinite || conv || hit) return;
+  gram_apply(Ginv, nj, tot, ys);
+  const double beta = first ? 0.0 : gnew / gold;
+  if (i0 < n) {
+    double pi = s0 + beta * p0;
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) pi -= w0[c] * ys[c];
+    p[i0] = pi;
+  }
+  for (int64_t i = i0 + (int64_t)gridDim.x * B; i < n; i += (int64_t)gridDim.x * B) {
+    double pi = s[i];
+    if (!first) pi += beta * p[i];
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) pi -= W[i + c * ld] * ys[c];
+    p[i] = pi;
+  }
+}
+
+// alpha = s^T s / p^T A p; g += alpha p; s -= alpha w; partials of (AU)^T s and s^T s.
+template <int NJT, int B = CgBlock<NJT>::value>
+__global__ __launch_bounds__(B) void k_dcg_update(const double* __restrict__ AW, int64_t ld,
+                                                   int64_t n, int nj,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ g,
+                                                   double* __restrict__ s, int iter, CGState* cg,
+                                                   const double* __restrict__ part1, int P1,
+                                                   double* __restrict__ part2) {
+  if (cg->done) return;
+  const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
+  double a0[NJT], p0 = 0.0, w0 = 0.0, g0 = 0.0, s0 = 0.0;
+  if (i0 < n) {
+    p0 = p[i0];
+    w0 = w[i0];
+    g0 = g[i0];
+    s0 = s[i0];
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) a0[c] = AW[i0 + c * ld];
+  }
+  __shared__ double pwt[1];
+  sum_partials<1, B>(part1, P1, pwt);
+  const double pw = pwt[0];
+  if (!(pw > 0.0) || !isfinite(pw)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      cg->flag = isfinite(pw) ? 1 : 2;
+      cg->done = 1;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cg->pw = pw;
+  const double alpha = cg->gamma[iter & 1] / pw;
+  double acc[NJT + 1];
+#pragma unroll
+  for (int c = 0; c <= NJT; ++c) acc[c] = 0.0;
+  if (i0 < n) {
+    g[i0] = g0 + alpha * p0;
+    const double si = s0 - alpha * w0;
+    s[i0] = si;
+    acc[NJT] += si * si;
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) acc[c] += a0[c] * si;
+  }
+  for (int64_t i = i0 + (int64_t)gridDim.x * B; i < n; i += (int64_t)gridDim.x * B) {
+    g[i] += alpha * p[i];
+    const double si = s[i] - alpha * w[i];
+    s[i] = si;
+    acc[NJT] += si * si;
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) acc[c] += AW[i + c * ld] * si;
+  }
+  write_partials_t<NJT + 1, B>(acc, part2, blockIdx.x, gridDim.x);
+}
+
+int njt_of(int nj) { return nj <= 8 ? 8 : nj <= 16 ? 16 : nj <= 32 ? 32 : 64; }
+
+}  // namespace
+
+int dcg_blocks(int64_t n) {
+  const int b = ceil_div(n, 512);
+  return b < CG_GRID ? (b < 1 ? 1 : b) : CG_GRID;
+}
+
+void launch_cg_setup(CGState* cg, double tol2, int maxit, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, st, cg, tol2, maxit);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_dcg_start(const double* W, const double* AW, int64_t ld, int64_t n, int nj,
+                      const double* Ginv, const double* r, double* g, double* s,
+                      const CGState* cg, double* part2, hipStream_t st) {
+  const dim3 grid(dcg_blocks(n));
+  switch (njt_of(nj)) {
+#define C(T) case T: hipLaunchKernelGGL((k_dcg_start<T>), grid, dim3(CgBlock<T>::value), 0, st, W, AW, ld, n, nj, Ginv, r, g, s, cg, part2); break;
+    C(8) C(16) C(32) C(64)
+#undef C
+  }
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_dcg_dir(const double* W, int64_t ld, int64_t n, int nj, const double* Ginv,
+                    const double* s, double* p, int iter, CGState* cg, const double* part2,
+                    hipStream_t st) {
+  const dim3 grid(dcg_blocks(n));
+  const int P2 = dcg_blocks(n);
+  switch (njt_of(nj)) {
+#define C(T) case T: hipLaunchKernelGGL((k_dcg_dir<T>), grid, dim3(CgBlock<T>::value), 0, st, W, ld, n, nj, Ginv, s, p, iter, cg, part2, P2); break;
+    C(8) C(16) C(32) C(64)
+#undef C
+  }
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_dcg_update(const double* AW, int64_t ld, int64_t n, int nj, const double* p,
+                       const double* w, double* g, double* s, int iter, CGState* cg,
+                       const double* part1, int P1, double* part2, hipStream_t st) {
+  const dim3 grid(dcg_blocks(n));
+  switch (njt_of(nj)) {
+#define C(T) case T: hipLaunchKernelGGL((k_dcg_update<T>), grid, dim3(CgBlock<T>::value), 0, st, AW, ld, n, nj, p, w, g, s, iter, cg, part1, P1, part2); break;
+    C(8) C(16) C(32) C(64)
+#undef C
+  }
+  ROM_CHECK_LAUNCH();
+}
+
+}  // namespace rom

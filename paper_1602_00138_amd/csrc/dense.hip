@@ -1,0 +1,380 @@
+// Tall-skinny products against the basis, vector helpers, and the inverse Cholesky
+// factor of the outer Gram matrix Q^T A(p) Q.
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace rom {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int GT_COLS = 32;   // columns per block of the transposed product
+
+int reduce_grid(int64_t n) {
+  int b = ceil_div(n, BS);
+  return b < 1024 ? (b < 1 ? 1 : b) : 1024;
+}
+
+// Transposed product, lanes over rows, waves over columns; one block covers
+// 64*CPL rows x GT_COLS columns.  When several row chunks exist the last block of
+// each column group sums the chunk partials in chunk order.
+template <int CPL, int NV>
+__global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int64_t ld,
+                                               int64_t rows, int cols,
+                                               const double* __restrict__ V, int64_t vstride,
+                                               double* __restrict__ out,
+                                               double* __restrict__ partials) {
+  const int64_t r0 = (int64_t)blockIdx.x * (64 * CPL);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double vr[NV][CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int64_t r = r0 + lane + 64 * q;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) vr[v][q] = r < rows ? V[r + v * vstride] : 0.0;
+  }
+  const int c0 = blockIdx.y * GT_COLS;
+  const bool single = gridDim.x == 1;
+  for (int cc = wid; cc < GT_COLS; cc += BS / 64) {
+    const int c = c0 + cc;
+    if (c >= cols) break;
+    const double* col = M + (int64_t)c * ld;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int64_t r = r0 + lane + 64 * q;
+      const double mv = r < rows ? col[r] : 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += mv * vr[v][q];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double s = wave_sum(acc[v]);
+      if (lane == 0) {
+        if (single)
+          out[v * cols + c] = s;
+        else
+          partials[((int64_t)v * cols + c) * gridDim.x + blockIdx.x] = s;
+      }
+    }
+  }
+}
+
+// out[e] = sum over chunks b of partials[e * nch + b]: one wave per output, fixed order.
+__global__ void k_gemvt_reduce(const double* __restrict__ partials, int nch, int ne,
+                               double* __restrict__ out) {
+  const int e = blockIdx.x * (BS / WAVE) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= ne) return;
+  const double* p = partials + (int64_t)e * nch;
+  double a = 0.0;
+  for (int b = lane; b < nch; b += WAVE) a += p[b];
+  a = wave_sum(a);
+  if (lane == 0) out[e] = a;
+}
+
+int gemvt_cpl(int cols) { return cols > 64 ? 16 : 4; }
+
+template <bool NRM>
+__global__ __launch_bounds__(BS) void k_gemvn(const double* __restrict__ M, int64_t ld,
+                                               int64_t rows, int cols,
+                                               const double* __restrict__ coef, double alpha,
+                                               const double* __restrict__ in, double beta,
+                                               double* __restrict__ out,
+                                               double* partials) {
+  extern __shared__ double cs[];
+  for (int c = threadIdx.x; c < cols; c += BS) cs[c] = coef[c];
+  __syncthreads();
+  double nv[1] = {0.0};
+  for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * BS) {
+    const double* p = M + r;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int c = 0;
+    for (; c + 8 <= cols; c += 8) {
+      a0 += p[(int64_t)(c + 0) * ld] * cs[c + 0];
+      a1 += p[(int64_t)(c + 1) * ld] * cs[c + 1];
+      a2 += p[(int64_t)(c + 2) * ld] * cs[c + 2];
+      a3 += p[(int64_t)(c + 3) * ld] * cs[c + 3];
+      a0 += p[(int64_t)(c + 4) * ld] * cs[c + 4];
+      a1 += p[(int64_t)(c + 5) * ld] * cs[c + 5];
+      a2 += p[(int64_t)(c + 6) * ld] * cs[c + 6];
+      a3 += p[(int64_t)(c + 7) * ld] * cs[c + 7];
+    }
+    for (; c < cols; ++c) a0 += p[(int64_t)c * ld] * cs[c];
+    const double acc = (a0 + a1) + (a2 + a3);
+    const double o = beta * acc + (in ? alpha * in[r] : 0.0);
+    out[r] = o;
+    nv[0] += o * o;
+  }
+  if (NRM) write_partials<1, BS>(nv, partials, blockIdx.x);
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
+                        const double* __restrict__ y, double* __restrict__ out, int want,
+                        double* partials) {
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double yi = y ? y[i] : 0.0;
+    const double o = a * x[i] + b * yi;
+    out[i] = o;
+    v[0] += o * o;
+    v[1] += yi * yi;
+  }
+  if (want) write_partials<2, BS>(v, partials, blockIdx.x);
+}
+
+__global__ void k_normalize(int64_t n, double* __restrict__ x, const double* nrm2) {
+  const double s = 1.0 / sqrt(nrm2[0]);
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    x[i] *= s;
+}
+
+__global__ void k_pack_cols(int64_t n, ColPtrs src, int k, double* __restrict__ dst, int64_t ld) {
+  const int c = blockIdx.y;
+  const double* s = src.p[c];
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    dst[i + c * ld] = s[i];
+}
+
+__global__ void k_gather_row(const double* __restrict__ M, int64_t ld, int cols, int64_t idx,
+                             double scale, double* __restrict__ out) {
+  const int c = blockIdx.x * BS + threadIdx.x;
+  if (c < cols) out[c] = scale * M[idx + (int64_t)c * ld];
+}
+
+__global__ void k_gather_rows(const double* __restrict__ M, int64_t ld, int cols,
+                              const int64_t* __restrict__ idx, const double* __restrict__ scale,
+                              int nidx, double* __restrict__ out, int64_t ldo) {
+  const int c = blockIdx.x * BS + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c < cols && r < nidx) out[c + r * ldo] = scale[r] * M[idx[r] + (int64_t)c * ld];
+}
+
+// Border step finalisation (one block): delta^2 = d - l^T l, new row of Linv.
+__global__ void k_linv_finish(double* Lc, double* Lr, int64_t ld, int k,
+                              const double* __restrict__ gcol, const double* __restrict__ l,
+                              const double* __restrict__ r, int* status) {
+  __shared__ double sh[BS / WAVE];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < k; i += BS) s += l[i] * l[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double ll = 0.0;
+#pragma unroll
+  for (int w = 0; w < BS / WAVE; ++w) ll += sh[w];
+  const double d2 = gcol[k] - ll;
+  const bool bad = !(d2 > 0.0) || !isfinite(d2);
+  const double inv = bad ? 0.0 : 1.0 / sqrt(d2);
+  for (int c = threadIdx.x; c < k; c += BS) {
+    const double v = -r[c] * inv;
+    Lr[c + (int64_t)k * ld] = v;
+    Lc[k + (int64_t)c * ld] = v;
+  }
+  if (threadIdx.x == 0) {
+    Lr[k + (int64_t)k * ld] = inv;
+    Lc[k + (int64_t)k * ld] = inv;
+    if (bad) status[0] = 1;
+  }
+}
+
+// Cholesky factor of a small SPD matrix in one workgroup (m <= 64), the inverse of the
+// factor (Linv) and the inverse of the matrix (Ginv = Linv^T Linv).
+__global__ void k_small_chol_inv(const double* __restrict__ G, int m, double* __restrict__ Linv,
+                                 double* __restrict__ Ginv, int* status) {
+  __shared__ double A[NJ_MAX][NJ_MAX + 1];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int i = e % m, j = e / m;
+    A[i][j] = 0.5 * (G[i + j * m] + G[j + i * m]);
+  }
+  __syncthreads();
+  // right-looking Cholesky, lower triangle
+  for (int k = 0; k < m; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = A[k][k];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = 1;
+        A[k][k] = 1.0;
+      } else {
+        A[k][k] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double piv = A[k][k];
+    for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) A[i][k] /= piv;
+    __syncthreads();
+    const int w = m - k - 1;
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+      const int i = k + 1 + e % w, j = k + 1 + e / w;
+      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+    }
+    __syncthreads();
+  }
+  // thread j: column j of Linv (L z = e_j) then column j of Ginv (L^T x = z); each
+  // thread re-reads only its own writes
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    double* z = Linv + j * m;
+    double* x = Ginv + j * m;
+    for (int i = 0; i < j; ++i) z[i] = 0.0;
+    for (int i = j; i < m; ++i) {
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int c = j; c < i; ++c) s -= A[i][c] * z[c];
+      z[i] = s / A[i][i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      double s = z[i];
+      for (int c = i + 1; c < m; ++c) s -= A[c][i] * x[c];
+      x[i] = s / A[i][i];
+    }
+  }
+  if (threadIdx.x == 0 && bad) status[0] = 1;
+}
+
+__global__ void k_border_fill(const double* __restrict__ vals, int k, double* Gs, double* Gi,
+                              int64_t ldg) {
+  const int c = blockIdx.x * BS + threadIdx.x;
+  if (c > k) return;
+  const double a = vals[c], b = vals[k + 1 + c];
+  Gs[c + k * ldg] = a;
+  Gs[k + c * ldg] = a;
+  Gi[c + k * ldg] = b;
+  Gi[k + c * ldg] = b;
+}
+
+}  // namespace
+
+void launch_border_fill(const double* vals, int k, double* Gs, double* Gi, int64_t ldg,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_border_fill, dim3(ceil_div(k + 1, BS)), dim3(BS), 0, st, vals, k, Gs, Gi,
+                     ldg);
+  ROM_CHECK_LAUNCH();
+}
+
+size_t gemvt_partials(int64_t rows, int cols, int nv) {
+  const int chunk = 64 * gemvt_cpl(cols);
+  const int64_t nch = (rows + chunk - 1) / chunk;
+  return nch <= 1 ? 0 : (size_t)nch * nv * cols;
+}
+
+size_t gemvt_partials_max(int64_t rows, int maxcols, int nv) {
+  // the chunk height switches at 64 columns; within each regime the size grows with cols
+  return std::max(gemvt_partials(rows, std::min(maxcols, 64), nv),
+                  gemvt_partials(rows, maxcols, nv));
+}
+
+void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const double* V,
+                  int64_t vstride, int nv, double* out, double* partials, hipStream_t st) {
+  if (cols <= 0) return;
+  const int cpl = gemvt_cpl(cols);
+  const int chunk = 64 * cpl;
+  dim3 grid(ceil_div(rows, chunk), ceil_div(cols, GT_COLS));
+  if (grid.x < 1) grid.x = 1;
+#define GT_LAUNCH(C, N) \
+  hipLaunchKernelGGL((k_gemvt<C, N>), grid, dim3(BS), 0, st, M, ld, rows, cols, V, vstride, out, partials)
+  if (cpl == 16) {
+    if (nv == 1) GT_LAUNCH(16, 1); else GT_LAUNCH(16, 2);
+  } else {
+    if (nv == 1) GT_LAUNCH(4, 1); else GT_LAUNCH(4, 2);
+  }
+#undef GT_LAUNCH
+  ROM_CHECK_LAUNCH();
+  if (grid.x > 1) {
+    const int ne = nv * cols;
+    hipLaunchKernelGGL(k_gemvt_reduce, dim3(ceil_div(ne, BS / WAVE)), dim3(BS), 0, st, partials,
+                       (int)grid.x, ne, out);
+    ROM_CHECK_LAUNCH();
+  }
+}
+
+void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
+                  double alpha, const double* in, double beta, double* out, double* nrm2,
+                  double* partials, hipStream_t st) {
+  const size_t shm = (size_t)(cols > 0 ? cols : 1) * sizeof(double);
+  const int grid = reduce_grid(rows);
+  if (nrm2) {
+    hipLaunchKernelGGL(k_gemvn<true>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef,
+                       alpha, in, beta, out, partials);
+    ROM_CHECK_LAUNCH();
+    launch_reduce_finish(partials, grid, 1, nrm2, st);
+  } else {
+    hipLaunchKernelGGL(k_gemvn<false>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef,
+                       alpha, in, beta, out, partials);
+    ROM_CHECK_LAUNCH();
+  }
+}
+
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
+                  double* nrm2, double* partials, hipStream_t st) {
+  const int grid = reduce_grid(n);
+  hipLaunchKernelGGL(k_axpby, dim3(grid), dim3(BS), 0, st, n, a, x, b, y, out, nrm2 ? 1 : 0,
+                     partials);
+  ROM_CHECK_LAUNCH();
+  if (nrm2) launch_reduce_finish(partials, grid, 2, nrm2, st);
+}
+
+void launch_normalize(int64_t n, double* x, const double* nrm2, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize, dim3(reduce_grid(n)), dim3(BS), 0, st, n, x, nrm2);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_pack_cols(int64_t n, const ColPtrs& src, int k, double* dst, int64_t ld,
+                      hipStream_t st) {
+  if (k <= 0) return;
+  int gx = ceil_div(n, BS);
+  if (gx > 256) gx = 256;
+  hipLaunchKernelGGL(k_pack_cols, dim3(gx, k), dim3(BS), 0, st, n, src, k, dst, ld);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_gather_row(const double* M, int64_t ld, int cols, int64_t idx, double scale,
+                       double* out, hipStream_t st) {
+  if (cols <= 0) return;
+  hipLaunchKernelGGL(k_gather_row, dim3(ceil_div(cols, BS)), dim3(BS), 0, st, M, ld, cols, idx,
+                     scale, out);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_gather_rows(const double* M, int64_t ld, int cols, const int64_t* idx,
+                        const double* scale, int nidx, double* out, int64_t ldo,
+                        hipStream_t st) {
+  if (cols <= 0 || nidx <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3(ceil_div(cols, BS), nidx), dim3(BS), 0, st, M, ld, cols,
+                     idx, scale, nidx, out, ldo);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double* gcol,
+                        double* tmp_l, double* tmp_r, int* status, double* partials,
+                        hipStream_t st) {
+  if (k > 0) {
+    // l = Linv g: row i of Linv is column i of Lr.
+    launch_gemvt(Lr, ld, k, k, gcol, 0, 1, tmp_l, partials, st);
+    // r = Linv^T l: column j of Linv is column j of Lc.
+    launch_gemvt(Lc, ld, k, k, tmp_l, 0, 1, tmp_r, partials, st);
+  }
+  hipLaunchKernelGGL(k_linv_finish, dim3(1), dim3(BS), 0, st, Lc, Lr, ld, k, gcol, tmp_l, tmp_r,
+                     status);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, const double* t,
+                       double* u, double* c, double* partials, hipStream_t st) {
+  if (m <= 0) return;
+  launch_gemvt(Lr, ld, m, m, t, 0, 1, u, partials, st);
+  launch_gemvt(Lc, ld, m, m, u, 0, 1, c, partials, st);
+}
+
+void launch_small_chol_inv(const double* G, int m, double* Linv, double* Ginv, int* status,
+                           hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_small_chol_inv, dim3(1), dim3(BS), 0, st, G, m, Linv, Ginv, status);
+  ROM_CHECK_LAUNCH();
+}
+
+}  // namespace rom

@@ -1,0 +1,142 @@
+// Launchers for the gfx950 kernels (all FP64).  Each launcher enqueues on `st`.
+#pragma once
+
+#include "common.h"
+
+namespace rom {
+
+// CG scalar state shared by the deflated-CG kernels (device memory).
+struct CGState {
+  double gamma[2];     // s^T s, double-buffered by step parity
+  double pw;           // p^T A p of the latest direction
+  double tol2;         // (tol * ||b||)^2
+  double t[NJ_MAX];    // U_j^T r for the start
+  int its;             // iterations done
+  int maxit;
+  int done;            // 1: stop (converged, maxit or breakdown)
+  int flag;            // 0 ok, 1 non-positive curvature, 2 non-finite
+};
+
+// Launch shape of the stencil products: blocks of 256 plane nodes x zc planes.
+struct StencilShape {
+  dim3 grid;
+  int zc;
+  int blocks;
+};
+StencilShape stencil_shape(const Stencil& S, int target_blocks);
+
+// Absorption bumps of one parameter point, passed by value as a kernel argument.
+struct Bumps {
+  int nb;
+  int dim;
+  double mu0;
+  double p[ROM_MAX_BUMPS * 5];  // per bump: centre (dim), radius, amplitude
+};
+
+// ---- operator -------------------------------------------------------------------
+// D == NULL: constant D_const.  fx/fy/fz (per-node +face coefficients) may be NULL.
+void launch_assemble(const rom_grid& g, double D_const, const double* D, double* diag_star,
+                     double* fx, double* fy, double* fz, hipStream_t st);
+// mu_i = mu0 + sum of bumps; diag_i = diag_star + mu_i (if diag_i); dmu = mu_i - mu0.
+void launch_mu_eval(const Stencil& S, const Bumps& bumps, const double* diag_star,
+                    double* diag_i, double* dmu, hipStream_t st);
+
+// y = A x with A = stencil(S) + diag (diag holds the full diagonal).
+void launch_spmv(const Stencil& S, const double* diag, const double* x, double* y,
+                 hipStream_t st);
+// Y[:, c] = A X[:, c] for c < k (contiguous, leading dimension ld).
+void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t ld, int k,
+                 double* Y, hipStream_t st);
+// r = scale * e_idx - A x (b is a scaled unit column) and nrm2[0] = ||r||^2.
+void launch_resid_unit(const Stencil& S, const double* diag, const double* x, int64_t idx,
+                       double scale, double* r, double* nrm2, double* partials,
+                       hipStream_t st);
+// out[r] = sum_b partials[b*R + r] for r < R (R = 1 or 2), one block, fixed order.
+void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st);
+
+// ---- tall-skinny products ---------------------------------------------------------
+// out[v * cols + c] = sum_{r < rows} M[r + c * ld] * V[r + v * vstride], v < nv (nv <= 2).
+// partials: >= gemvt_partials(rows, cols, nv) doubles.
+size_t gemvt_partials(int64_t rows, int cols, int nv);
+// max of gemvt_partials over every column count <= maxcols
+size_t gemvt_partials_max(int64_t rows, int maxcols, int nv);
+void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const double* V,
+                  int64_t vstride, int nv, double* out, double* partials, hipStream_t st);
+// out[r] = alpha * in[r] + beta * sum_{c < cols} M[r + c * ld] coef[c]  (in may be NULL)
+// and, if nrm2 != NULL, nrm2[0] = ||out||^2.  partials: >= 1024 doubles.
+void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
+                  double alpha, const double* in, double beta, double* out, double* nrm2,
+                  double* partials, hipStream_t st);
+
+// ---- vector helpers ---------------------------------------------------------------
+// out = a*x + b*y (y may be NULL); if nrm2: nrm2[0] = ||out||^2, nrm2[1] = ||y||^2.
+// partials: >= 2048 doubles.
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
+                  double* nrm2, double* partials, hipStream_t st);
+// x *= 1/sqrt(*nrm2)
+void launch_normalize(int64_t n, double* x, const double* nrm2, hipStream_t st);
+// dst[:, c] = src[c] columns (pointer table) for c < k.
+void launch_pack_cols(int64_t n, const ColPtrs& src, int k, double* dst, int64_t ld,
+                      hipStream_t st);
+// out[c] = scale * M[idx + c * ld] for c < cols (rows of a tall matrix at a node).
+void launch_gather_row(const double* M, int64_t ld, int cols, int64_t idx, double scale,
+                       double* out, hipStream_t st);
+// Out[c + r*ldo] for c < cols, r < nidx: scale[r] * M[idx[r] + c * ld] (B_r = V^T B~).
+void launch_gather_rows(const double* M, int64_t ld, int cols, const int64_t* idx,
+                        const double* scale, int nidx, double* out, int64_t ldo,
+                        hipStream_t st);
+
+// ---- Gram matrices (FP64 MFMA) ----------------------------------------------------
+// C = X^T diag(w) Y (w may be NULL = identity) for X: rows x a, Y: rows x b, contiguous
+// column-major.  sym: X == Y, only the lower tiles are computed and mirrored.
+// The result is written as C[i + j*ldc] = base[i + j*ldb] + shift*(i==j) + (X^T W Y)[i,j]
+// (base may be NULL).  Rows whose weight is zero in a whole 32-row chunk are skipped.
+size_t gram_partials(int a, int b, int64_t rows, bool sym);
+// max of gram_partials over a' <= a (b' = a' when sym) -- the split count depends on a.
+size_t gram_partials_max(int a, int b, int64_t rows, bool sym);
+void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b,
+                 int64_t rows, const double* w, bool sym, const double* base, int64_t ldb,
+                 double shift, double* C, int64_t ldc, double* partials, hipStream_t st);
+
+// ---- inverse Cholesky factor -------------------------------------------------------
+// Linv (lower, inverse of the Cholesky factor of G) kept in two layouts, Lc
+// (column-major, ld) and Lr (its transpose, column-major, ld).  Border step k: with
+// g = G[0:k, k] and d = G[k, k]: l = Linv g, delta^2 = d - l^T l,
+// Linv[k, 0:k] = -(Linv^T l)^T / delta, Linv[k, k] = 1/delta.  status[0] is set to 1
+// if delta^2 <= 0 (not SPD).
+void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double* gcol,
+                        double* tmp_l, double* tmp_r, int* status, double* partials,
+                        hipStream_t st);
+// c = Linv^T (Linv t), for m x m Linv.
+void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, const double* t,
+                       double* u, double* c, double* partials, hipStream_t st);
+// Small SPD m x m (m <= NJ_MAX) in one workgroup: Linv (inverse of its Cholesky factor)
+// and Ginv (its inverse), col-major, ld = m.  status[0] = 1 if not SPD.
+void launch_small_chol_inv(const double* G, int m, double* Linv, double* Ginv, int* status,
+                           hipStream_t st);
+
+// Symmetric border of the outer Gram matrices: for c <= k,
+// Gs[c,k] = Gs[k,c] = vals[c] and Gi[c,k] = Gi[k,c] = vals[k+1+c].
+void launch_border_fill(const double* vals, int k, double* Gs, double* Gi, int64_t ldg,
+                        hipStream_t st);
+
+// ---- deflated CG --------------------------------------------------------------------
+// W, AW: n x nj contiguous (ld), Ginv: nj x nj inverse of W^T A W.
+// part1: >= stencil_shape(S, 512).blocks doubles (p^T A p partials of the operator step);
+// part2: >= (NJ_MAX + 1) * dcg_blocks(n) doubles.  iter: 0-based step index (-1 for the
+// direction after the start).
+int dcg_blocks(int64_t n);
+void launch_cg_setup(CGState* cg, double tol2, int maxit, hipStream_t st);
+void launch_dcg_start(const double* W, const double* AW, int64_t ld, int64_t n, int nj,
+                      const double* Ginv, const double* r, double* g, double* s,
+                      const CGState* cg, double* part2, hipStream_t st);
+void launch_dcg_dir(const double* W, int64_t ld, int64_t n, int nj, const double* Ginv,
+                    const double* s, double* p, int iter, CGState* cg, const double* part2,
+                    hipStream_t st);
+void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const double* diag,
+                      const double* p, double* w, CGState* cg, double* part1, hipStream_t st);
+void launch_dcg_update(const double* AW, int64_t ld, int64_t n, int nj, const double* p,
+                       const double* w, double* g, double* s, int iter, CGState* cg,
+                       const double* part1, int P1, double* part2, hipStream_t st);
+
+}  // namespace rom

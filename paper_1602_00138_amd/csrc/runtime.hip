@@ -1,0 +1,919 @@
+// Host runtime: operator and basis handles, Algorithm 2 (recycling and global basis
+// construction, Sec. 4.3) in CG form, the reduced matrices of eq. (newreduced), and
+// the C ABI of include/rom.h.  All arithmetic runs in the kernels of this library;
+// the host only sequences launches and takes the decisions of Algorithm 2 (skip
+// test, convergence, truncation) from scalars read back at its sync points.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+struct rom_operator {
+  rom_grid grid;
+  int64_t n;
+  bool var;
+  double Dc;
+  double* diag_star;
+  double* fx;
+  double* fy;
+  double* fz;
+  rom::Stencil S;
+};
+
+struct rom_basis {
+  const rom_operator* op;
+  int64_t n, ld;
+  int m, cap;
+  double* Q;
+  double* Gstar;
+  int64_t ldg;
+  int n_src, n_det;
+  const int64_t* idx_dev;   // n_src + n_det node indices (sources first)
+  const double* scale_dev;  // n_src + n_det scales
+};
+
+namespace rom {
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr size_t ALIGN = 256;
+
+struct Arena {
+  char* base;
+  size_t off = 0;
+  explicit Arena(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + ALIGN - 1) / ALIGN * ALIGN;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Small control block read back by the host at every decision point.
+struct Ctrl {
+  double sc[16];
+  int status[4];
+  int pad[4];
+  CGState cg;
+};
+
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Per-class kernel accounting; launches of the classes in `mask` are bracketed by
+// HIP events on the launch stream and harvested at the host sync points.
+class Timer {
+ public:
+  Timer(int mask, hipStream_t st) : mask_(mask), st_(st) {
+    for (int k = 0; k < ROM_NK; ++k) ms[k] = bytes[k] = flops[k] = 0.0, launches[k] = 0;
+  }
+  ~Timer() {
+    for (auto& e : pool_) (void)hipEventDestroy(e);
+  }
+  void begin(int cls) {
+    if (!(mask_ >> cls & 1)) return;
+    hipEvent_t a = get(), b = get();
+    (void)hipEventRecord(a, st_);
+    open_.push_back({cls, a, b});
+  }
+  void end(int cls, double by, double fl = 0.0) {
+    add(cls, by, fl);
+    if (!(mask_ >> cls & 1) || open_.empty() || open_.back().cls != cls) return;
+    (void)hipEventRecord(open_.back().b, st_);
+    pending_.push_back(open_.back());
+    open_.pop_back();
+  }
+  // account a launch without events
+  void add(int cls, double by, double fl = 0.0) {
+    bytes[cls] += by;
+    flops[cls] += fl;
+    launches[cls] += 1;
+  }
+  // Undo the accounting of the last `count` launches of class cls (launches that
+  // returned at once because the iteration had already stopped).
+  void discard(int cls, int count, double by, double fl) {
+    if (count <= 0) return;
+    bytes[cls] -= by * count;
+    flops[cls] -= fl * count;
+    launches[cls] -= count;
+    if (!(mask_ >> cls & 1)) return;
+    for (int k = (int)pending_.size() - 1; k >= 0 && count > 0; --k) {
+      if (pending_[k].cls != cls) continue;
+      free_.push_back(pending_[k].a);
+      free_.push_back(pending_[k].b);
+      pending_.erase(pending_.begin() + k);
+      --count;
+    }
+  }
+  // call after a stream synchronisation
+  void harvest() {
+    for (auto& p : pending_) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) ms[p.cls] += t;
+      free_.push_back(p.a);
+      free_.push_back(p.b);
+    }
+    pending_.clear();
+  }
+  double ms[ROM_NK], bytes[ROM_NK], flops[ROM_NK];
+  long long launches[ROM_NK];
+
+ private:
+  struct Pair {
+    int cls;
+    hipEvent_t a, b;
+  };
+  hipEvent_t get() {
+    if (!free_.empty()) {
+      hipEvent_t e = free_.back();
+      free_.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    ROM_HIP(hipEventCreate(&e));
+    pool_.push_back(e);
+    return e;
+  }
+  int mask_;
+  hipStream_t st_;
+  std::vector<hipEvent_t> pool_, free_;
+  std::vector<Pair> open_, pending_;
+};
+
+Stencil make_stencil(const rom_operator& op) { return op.S; }
+
+Bumps make_bumps(const rom_mu& mu, int dim) {
+  Bumps b;
+  std::memset(&b, 0, sizeof(b));
+  b.nb = mu.nb;
+  b.dim = dim;
+  b.mu0 = mu.mu0;
+  for (int k = 0; k < mu.nb; ++k) {
+    double* p = b.p + k * (dim + 2);
+    for (int a = 0; a < dim; ++a) p[a] = mu.centers[k * dim + a];
+    p[dim] = mu.radii[k];
+    p[dim + 1] = mu.amps[k];
+  }
+  return b;
+}
+
+void check_mu(const rom_mu* mu, int dim) {
+  if (!mu) throw Error(ROM_EINVAL, "null parameter point");
+  if (mu->nb < 0 || mu->nb > ROM_MAX_BUMPS) throw Error(ROM_EINVAL, "bump count out of range");
+  if (mu->nb > 0 && (!mu->centers || !mu->radii || !mu->amps))
+    throw Error(ROM_EINVAL, "null bump arrays");
+  if (!std::isfinite(mu->mu0) || mu->mu0 < 0) throw Error(ROM_EINVAL, "mu0 must be >= 0");
+  for (int k = 0; k < mu->nb; ++k) {
+    if (!(mu->radii[k] > 0) || !std::isfinite(mu->radii[k]))
+      throw Error(ROM_EINVAL, "bump radius must be > 0");
+    if (!std::isfinite(mu->amps[k])) throw Error(ROM_EINVAL, "bump amplitude not finite");
+    for (int a = 0; a < dim; ++a)
+      if (!std::isfinite(mu->centers[k * dim + a])) throw Error(ROM_EINVAL, "bump centre not finite");
+  }
+}
+
+void check_grid(const rom_grid* g) {
+  if (!g) throw Error(ROM_EINVAL, "null grid");
+  if (g->dim != 2 && g->dim != 3) throw Error(ROM_EINVAL, "dim must be 2 or 3");
+  for (int a = 0; a < 3; ++a)
+    if (g->n[a] < 1) throw Error(ROM_EINVAL, "grid sizes must be >= 1");
+  if (g->dim == 2 && g->n[2] != 1) throw Error(ROM_EINVAL, "2D grids need n[2] == 1");
+  for (int f = 0; f < 6; ++f)
+    if (g->bc[f] != 0 && g->bc[f] != 1) throw Error(ROM_EINVAL, "bc must be 0 or 1");
+  if (!(g->robin_A >= 0) || !std::isfinite(g->robin_A)) throw Error(ROM_EINVAL, "robin_A must be >= 0");
+  const double n = (double)g->n[0] * g->n[1] * g->n[2];
+  if (n > 2.0e9) throw Error(ROM_EINVAL, "grid too large");
+}
+
+size_t operator_layout(const rom_grid& g, bool var, Arena& a, rom_operator* op) {
+  const int64_t n = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  double* diag = a.take<double>(n);
+  double *fx = nullptr, *fy = nullptr, *fz = nullptr, *Dcopy = nullptr;
+  if (var) {
+    fx = a.take<double>(n);
+    fy = a.take<double>(n);
+    fz = g.dim == 3 ? a.take<double>(n) : nullptr;
+    Dcopy = a.take<double>(n);
+  }
+  (void)Dcopy;
+  if (op) {
+    op->diag_star = diag;
+    op->fx = fx;
+    op->fy = fy;
+    op->fz = fz;
+  }
+  return a.off;
+}
+
+// ------------------------------------------------------------------------------------
+// Algorithm 2, CG form.
+
+class Sequencer {
+ public:
+  Sequencer(rom_operator* op, int n_src, int n_det, int k_u, int K, const rom_opts& o)
+      : op_(op), S_(op->S), n_(op->n), ld_(round_up(op->n, 64)), n_src_(n_src), n_det_(n_det),
+        n_rhs_(n_src + n_det), K_(K), ku_in_(k_u), o_(o) {
+    const int64_t full = (int64_t)k_u + (int64_t)n_rhs_ * K;
+    cap_ = o.cap > 0 ? (int)std::min<int64_t>(o.cap, full) : (int)std::min<int64_t>(full, 4096);
+    cap_ = (int)std::min<int64_t>(cap_, n_);
+    if (cap_ < 1) cap_ = 1;
+    ldg_ = cap_;
+    pool_cap_ = n_rhs_ + std::max(0, cap_);
+    tol_ = o.tol;
+    trunc_ = o.trunc;
+    maxit_ = o.maxit > 0 ? o.maxit : (int)std::min<int64_t>(n_, 1 << 30);
+    chunk_ = o.check_every > 0 ? o.check_every : 16;
+  }
+
+  int cap() const { return cap_; }
+
+  size_t layout(void* base) {
+    Arena a(base);
+    Q_ = a.take<double>(ld_ * cap_);
+    pool_ = a.take<double>(ld_ * pool_cap_);
+    Wp_ = a.take<double>(ld_ * NJ_MAX);
+    AWp_ = a.take<double>(ld_ * NJ_MAX);
+    x0_ = a.take<double>(ld_);
+    r_ = a.take<double>(ld_);
+    g_ = a.take<double>(ld_);
+    s_ = a.take<double>(ld_);
+    p_ = a.take<double>(ld_);
+    w_ = a.take<double>(ld_);
+    d_ = a.take<double>(ld_);
+    xt_ = a.take<double>(ld_);
+    r2_ = a.take<double>(ld_);
+    vAB_ = a.take<double>(2 * ld_);
+    diag_i_ = a.take<double>(ld_);
+    dmu_ = a.take<double>(ld_);
+    Gs_ = a.take<double>((size_t)ldg_ * cap_);
+    Gi_ = a.take<double>((size_t)ldg_ * cap_);
+    Lc_ = a.take<double>((size_t)ldg_ * cap_);
+    Lr_ = a.take<double>((size_t)ldg_ * cap_);
+    const size_t gp = std::max(gram_partials_max(cap_, cap_, n_, true),
+                               gram_partials_max(NJ_MAX, NJ_MAX, n_, false));
+    gram_part_ = a.take<double>(std::max<size_t>(gp, 1));
+    const StencilShape sh = stencil_shape(S_, 1024);
+    red_part_ = a.take<double>(std::max<size_t>(2 * 1024, (size_t)sh.blocks));
+    part1_ = a.take<double>(std::max(sh.blocks, 1));
+    part2_ = a.take<double>((size_t)(NJ_MAX + 1) * dcg_blocks(n_));
+    size_t gt = std::max(gemvt_partials_max(n_, std::max(cap_ + 1, NJ_MAX), 2),
+                         gemvt_partials_max(cap_, cap_, 1));
+    gt_part_ = a.take<double>(std::max<size_t>(gt, 1));
+    tbuf_ = a.take<double>(std::max(cap_, NJ_MAX) + 8);
+    ubuf_ = a.take<double>(cap_ + 8);
+    cbuf_ = a.take<double>(cap_ + 8);
+    tmpl_ = a.take<double>(cap_ + 8);
+    tmpr_ = a.take<double>(cap_ + 8);
+    bvals_ = a.take<double>(2 * (cap_ + 8));
+    GW_ = a.take<double>(NJ_MAX * NJ_MAX);
+    LWinv_ = a.take<double>(NJ_MAX * NJ_MAX);
+    GWinv_ = a.take<double>(NJ_MAX * NJ_MAX);
+    ctrl_ = a.take<Ctrl>(1);
+    idx_dev_ = a.take<int64_t>(n_rhs_);
+    scale_dev_ = a.take<double>(n_rhs_);
+    return a.off + ALIGN;
+  }
+
+  rom_status run(const rom_mu* params, const int64_t* src_idx, const double* src_scale,
+                 const int64_t* det_idx, const double* det_scale, const double* U0,
+                 double* X_out, rom_record* records, rom_stats* stats, hipStream_t st,
+                 rom_basis** out_basis) {
+    const auto t0 = std::chrono::steady_clock::now();
+    st_ = st;
+    Timer timer(o_.timing, st);
+    tm_ = &timer;
+    ROM_HIP(hipHostMalloc((void**)&h_, sizeof(Ctrl), hipHostMallocDefault));
+    struct Free {
+      Ctrl* h;
+      ~Free() { (void)hipHostFree(h); }
+    } guard{h_};
+
+    idx_.assign(src_idx, src_idx + n_src_);
+    idx_.insert(idx_.end(), det_idx, det_idx + n_det_);
+    scale_.assign(src_scale, src_scale + n_src_);
+    scale_.insert(scale_.end(), det_scale, det_scale + n_det_);
+    ROM_HIP(hipMemcpyAsync(idx_dev_, idx_.data(), n_rhs_ * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    ROM_HIP(hipMemcpyAsync(scale_dev_, scale_.data(), n_rhs_ * sizeof(double), hipMemcpyHostToDevice, st));
+    ROM_HIP(hipMemsetAsync(ctrl_, 0, sizeof(Ctrl), st));
+    ROM_HIP(hipMemsetAsync(Gs_, 0, sizeof(double) * ldg_ * cap_, st));
+    ROM_HIP(hipMemsetAsync(Gi_, 0, sizeof(double) * ldg_ * cap_, st));
+    ROM_HIP(hipMemsetAsync(Lc_, 0, sizeof(double) * ldg_ * cap_, st));
+    ROM_HIP(hipMemsetAsync(Lr_, 0, sizeof(double) * ldg_ * cap_, st));
+    sync();
+
+    m_ = 0;
+    extra_.assign(n_rhs_, {});
+    next_slot_ = n_rhs_;
+    rom_status status = ROM_OK;
+    std::vector<rom_record> recs;
+    recs.reserve((size_t)K_ * n_rhs_);
+    long long total_its = 0;
+    int n_solved = 0, n_kept = 0, n_drop_trunc = 0, n_drop_cap = 0, n_nonconv = 0;
+
+    for (int i = 0; i < K_; ++i) {
+      mu0_ = params[i].mu0;
+      launch_mu_eval(S_, make_bumps(params[i], S_.dim), op_->diag_star, diag_i_, dmu_, st);
+      if (i == 0) {
+        // V <- orth(U_0): CGS2 append of every column (Alg. 2 initialisation)
+        for (int c = 0; c < ku_in_; ++c) {
+          double rho;
+          append_q(U0 + (int64_t)c * n_, &rho);
+        }
+        ku_ = m_;
+      } else {
+        rebuild_gi();
+      }
+      w_key_ = -2;
+      for (int j = 0; j < n_rhs_; ++j) {
+        const int64_t idx = idx_[j];
+        const double sc = scale_[j];
+        const double nb = std::fabs(sc);
+        rom_record rec;
+        std::memset(&rec, 0, sizeof(rec));
+        rec.point = i;
+        rec.rhs = j;
+        rec.rho = -1.0;
+        // ---- outer projection on V (Galerkin in the A(p_i) inner product)
+        if (m_ > 0) {
+          launch_gather_row(Q_, ld_, m_, idx, sc, tbuf_, st);
+          launch_linv_solve(Lc_, Lr_, ldg_, m_, tbuf_, ubuf_, cbuf_, gt_part_, st);
+          tm_->begin(ROM_K_GEMVN);
+          launch_gemvn(Q_, ld_, n_, m_, cbuf_, 0.0, nullptr, 1.0, x0_, nullptr, red_part_, st);
+          tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m_ + 1), 2.0 * n_ * m_);
+        } else {
+          ROM_HIP(hipMemsetAsync(x0_, 0, sizeof(double) * n_, st));
+        }
+        launch_resid_unit(S_, diag_i_, x0_, idx, sc, r_, &ctrl_->sc[0], red_part_, st);
+        account_spmv(ROM_K_OTHER);
+        sync();
+        const double rho0 = std::sqrt(h_->sc[0]) / nb;
+        rec.rho0 = rho0;
+        double* xdst = X_out ? X_out + ((int64_t)i * n_rhs_ + j) * n_ : xt_;
+        if (rho0 <= tol_) {
+          ROM_HIP(hipMemcpyAsync(xdst, x0_, sizeof(double) * n_, hipMemcpyDeviceToDevice, st));
+          if (i == 0)
+            ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)j * ld_, x0_, sizeof(double) * n_,
+                                   hipMemcpyDeviceToDevice, st));
+          rec.final_res = rho0;
+          rec.converged = 1;
+          rec.m = m_;
+          recs.push_back(rec);
+          continue;
+        }
+        // ---- inner recycled CG on A g = r with U_j (correction equation, eq. (resi))
+        ++n_solved;
+        rec.solved = 1;
+        const int nj = make_W(i, j);
+        int flag = 0;
+        int its = cg_solve(r_, g_, nj, tol_ * nb, maxit_, flag);
+        launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
+        launch_resid_unit(S_, diag_i_, xdst, idx, sc, r2_, &ctrl_->sc[3], red_part_, st);
+        account_spmv(ROM_K_OTHER);
+        sync();
+        double res = std::sqrt(h_->sc[3]) / nb;
+        int restarts = 0;
+        while (res > tol_ && its < maxit_ && flag == 0) {
+          ++restarts;
+          its += cg_solve(r2_, d_, nj, tol_ * nb, maxit_ - its, flag);
+          launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st);
+          launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
+          launch_resid_unit(S_, diag_i_, xdst, idx, sc, r2_, &ctrl_->sc[3], red_part_, st);
+          account_spmv(ROM_K_OTHER);
+          sync();
+          res = std::sqrt(h_->sc[3]) / nb;
+        }
+        if (flag == 1) throw Error(ROM_ENOTSPD, "CG met non-positive curvature (operator not SPD)");
+        if (flag == 2) throw Error(ROM_ENONFINITE, "non-finite value in CG");
+        total_its += its;
+        rec.its = its;
+        rec.restarts = restarts;
+        rec.final_res = res;
+        rec.converged = res <= tol_;
+        if (!rec.converged) {
+          ++n_nonconv;
+          status = ROM_ENOCONV;
+        }
+        // ---- append the new information to V (CGS2 + truncation) and to U_j
+        if (m_ < cap_) {
+          double rho = 0.0;
+          const bool kept = append_q(g_, &rho);
+          rec.rho = rho;
+          rec.kept = kept;
+          if (kept) {
+            ++n_kept;
+            if (i > 0 && ku_ + (int)extra_[j].size() < NJ_MAX && next_slot_ < pool_cap_) {
+              double* slot = pool_ + (int64_t)next_slot_ * ld_;
+              launch_axpby(n_, 1.0, g_, 0.0, nullptr, slot, nullptr, red_part_, st);
+              const double ru = cgs2_inplace(slot, Wp_, nj);
+              if (ru > trunc_) {
+                launch_normalize(n_, slot, &ctrl_->sc[4], st);
+                extra_[j].push_back(next_slot_++);
+              }
+            }
+          } else {
+            ++n_drop_trunc;
+          }
+        } else {
+          ++n_drop_cap;
+        }
+        if (i == 0)
+          ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)j * ld_, xdst, sizeof(double) * n_,
+                                 hipMemcpyDeviceToDevice, st));
+        rec.m = m_;
+        recs.push_back(rec);
+      }
+      if (i == 0) {
+        // U_j <- [U_0, X_0(:, j)] (Sec. 4.2.2), X_0(:, j) orthonormalised against U_0
+        for (int j = 0; j < n_rhs_; ++j) {
+          double* slot = pool_ + (int64_t)j * ld_;
+          const double rho = cgs2_inplace(slot, Q_, ku_);
+          extra_[j].clear();
+          if (rho > trunc_ && ku_ < NJ_MAX) {
+            launch_normalize(n_, slot, &ctrl_->sc[4], st);
+            extra_[j].push_back(j);
+          }
+        }
+      }
+    }
+    sync();
+    if (records) std::memcpy(records, recs.data(), recs.size() * sizeof(rom_record));
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->m = m_;
+      stats->k_u = ku_;
+      stats->n_solved = n_solved;
+      stats->n_kept = n_kept;
+      stats->n_dropped_trunc = n_drop_trunc;
+      stats->n_dropped_cap = n_drop_cap;
+      stats->n_nonconv = n_nonconv;
+      stats->total_its = total_its;
+      stats->seconds =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (int k = 0; k < ROM_NK; ++k) {
+        stats->kernel_ms[k] = timer.ms[k];
+        stats->kernel_bytes[k] = timer.bytes[k];
+        stats->kernel_flops[k] = timer.flops[k];
+        stats->kernel_launches[k] = timer.launches[k];
+      }
+    }
+    rom_basis* V = new rom_basis;
+    V->op = op_;
+    V->n = n_;
+    V->ld = ld_;
+    V->m = m_;
+    V->cap = cap_;
+    V->Q = Q_;
+    V->Gstar = Gs_;
+    V->ldg = ldg_;
+    V->n_src = n_src_;
+    V->n_det = n_det_;
+    V->idx_dev = idx_dev_;
+    V->scale_dev = scale_dev_;
+    *out_basis = V;
+    tm_ = nullptr;
+    return status;
+  }
+
+ private:
+  void sync() {
+    ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
+    ROM_HIP(hipStreamSynchronize(st_));
+    tm_->harvest();
+    if (h_->status[0]) throw Error(ROM_ENOTSPD, "outer Gram matrix V^T A V not positive definite");
+    if (h_->status[1]) throw Error(ROM_ENOTSPD, "recycle Gram matrix U_j^T A U_j not positive definite");
+  }
+
+  void account_spmv(int cls) {
+    const double by = 8.0 * n_ * (3 + (S_.var ? S_.dim : 0));
+    tm_->add(cls, by, 13.0 * n_);
+  }
+
+  // In-place CGS2 of v against the first `cols` columns of M (orthonormal, ld_);
+  // returns the norm ratio ||v_out|| / ||v_in||; ctrl sc[4] = ||v_out||^2.
+  double cgs2_inplace(double* v, const double* M, int cols) {
+    launch_axpby(n_, 1.0, v, 0.0, nullptr, v, &ctrl_->sc[5], red_part_, st_);
+    if (cols > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        tm_->begin(ROM_K_GEMVT);
+        launch_gemvt(M, ld_, n_, cols, v, 0, 1, tbuf_, gt_part_, st_);
+        tm_->end(ROM_K_GEMVT, 8.0 * n_ * (cols + 1), 2.0 * n_ * cols);
+        tm_->begin(ROM_K_GEMVN);
+        launch_gemvn(M, ld_, n_, cols, tbuf_, 1.0, v, -1.0, v, pass ? &ctrl_->sc[4] : nullptr,
+                     red_part_, st_);
+        tm_->end(ROM_K_GEMVN, 8.0 * n_ * (cols + 2), 2.0 * n_ * cols);
+      }
+    } else {
+      ROM_HIP(hipMemcpyAsync(&ctrl_->sc[4], &ctrl_->sc[5], sizeof(double),
+                             hipMemcpyDeviceToDevice, st_));
+    }
+    sync();
+    const double a = h_->sc[4], b = h_->sc[5];
+    if (!(b > 0.0) || !std::isfinite(a) || !std::isfinite(b)) return 0.0;
+    return std::sqrt(a / b);
+  }
+
+  // Append v to V if its normalised part outside range(V) exceeds trunc; border the
+  // Gram matrices V^T A_* V and V^T A_i V and the inverse Cholesky factor.
+  bool append_q(const double* v, double* rho_out) {
+    *rho_out = -1.0;
+    if (m_ >= cap_) return false;
+    double* slot = Q_ + (int64_t)m_ * ld_;
+    launch_axpby(n_, 1.0, v, 0.0, nullptr, slot, nullptr, red_part_, st_);
+    const double rho = cgs2_inplace(slot, Q_, m_);
+    *rho_out = rho;
+    if (!(rho > trunc_) || m_ >= cap_) return false;
+    launch_normalize(n_, slot, &ctrl_->sc[4], st_);
+    border(m_);
+    ++m_;
+    return true;
+  }
+
+  void border(int k) {
+    const double* q = Q_ + (int64_t)k * ld_;
+    launch_spmv(S_, op_->diag_star, q, vAB_, st_);
+    account_spmv(ROM_K_OTHER);
+    launch_spmv(S_, diag_i_, q, vAB_ + ld_, st_);
+    account_spmv(ROM_K_OTHER);
+    tm_->begin(ROM_K_GEMVT);
+    launch_gemvt(Q_, ld_, n_, k + 1, vAB_, ld_, 2, bvals_, gt_part_, st_);
+    tm_->end(ROM_K_GEMVT, 8.0 * n_ * (k + 3), 4.0 * n_ * (k + 1));
+    launch_border_fill(bvals_, k, Gs_, Gi_, ldg_, st_);
+    launch_linv_border(Lc_, Lr_, ldg_, k, Gi_ + (int64_t)k * ldg_, tmpl_, tmpr_,
+                       &ctrl_->status[0], gt_part_, st_);
+  }
+
+  // G_i = V^T A_* V + mu0 I + V^T diag(mu_i - mu0) V, then its inverse Cholesky factor.
+  void rebuild_gi() {
+    if (m_ == 0) return;
+    tm_->begin(ROM_K_GRAM);
+    launch_gram(Q_, ld_, m_, Q_, ld_, m_, n_, dmu_, true, Gs_, ldg_, mu0_, Gi_, ldg_, gram_part_, st_);
+    tm_->end(ROM_K_GRAM, 8.0 * n_ * (m_ + 1), 2.0 * n_ * m_ * m_);
+    ROM_HIP(hipMemsetAsync(Lc_, 0, sizeof(double) * ldg_ * m_, st_));
+    ROM_HIP(hipMemsetAsync(Lr_, 0, sizeof(double) * ldg_ * m_, st_));
+    for (int k = 0; k < m_; ++k)
+      launch_linv_border(Lc_, Lr_, ldg_, k, Gi_ + (int64_t)k * ldg_, tmpl_, tmpr_,
+                         &ctrl_->status[0], gt_part_, st_);
+  }
+
+  // Pack U_j = [U_0 part of V, extra columns of RHS j] and form A_i U_j, its Gram and
+  // the inverse Cholesky factor.  At point 0 every U_j is U_0 (built once).
+  int make_W(int i, int j) {
+    const int key = i == 0 ? -1 : j;
+    ColPtrs cp;
+    int nj = 0;
+    for (int c = 0; c < ku_; ++c) cp.p[nj++] = Q_ + (int64_t)c * ld_;
+    if (i > 0)
+      for (int sl : extra_[j])
+        if (nj < NJ_MAX) cp.p[nj++] = pool_ + (int64_t)sl * ld_;
+    if (key == w_key_ && nj == w_nj_) return nj;
+    w_key_ = key;
+    w_nj_ = nj;
+    if (nj == 0) return 0;
+    launch_pack_cols(n_, cp, nj, Wp_, ld_, st_);
+    launch_spmm(S_, diag_i_, Wp_, ld_, nj, AWp_, st_);
+    tm_->begin(ROM_K_GRAM);
+    launch_gram(Wp_, ld_, nj, AWp_, ld_, nj, n_, nullptr, false, nullptr, 0, 0.0, GW_, nj,
+                gram_part_, st_);
+    tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
+    launch_small_chol_inv(GW_, nj, LWinv_, GWinv_, &ctrl_->status[1], st_);
+    return nj;
+  }
+
+  // Deflated CG on A_i d = rhs with the packed U_j; returns iterations.
+  int cg_solve(const double* rhs, double* dvec, int nj, double tol_abs, int maxit, int& flag) {
+    CGState* cg = &ctrl_->cg;
+    const StencilShape sh = stencil_shape(S_, 1024);
+    launch_cg_setup(cg, tol_abs * tol_abs, maxit, st_);
+    if (nj > 0) {
+      tm_->begin(ROM_K_GEMVT);
+      launch_gemvt(Wp_, ld_, n_, nj, rhs, 0, 1, cg->t, gt_part_, st_);
+      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (nj + 1), 2.0 * n_ * nj);
+    }
+    launch_dcg_start(Wp_, AWp_, ld_, n_, nj, GWinv_, rhs, dvec, s_, cg, part2_, st_);
+    tm_->begin(ROM_K_DCG_DIR);
+    launch_dcg_dir(Wp_, ld_, n_, nj, GWinv_, s_, p_, -1, cg, part2_, st_);
+    tm_->end(ROM_K_DCG_DIR, 8.0 * n_ * (2 + nj), n_ * (1.0 + 2.0 * nj));
+    const double by_apply = 8.0 * n_ * (3 + (S_.var ? S_.dim : 0));
+    const double fl_apply = 15.0 * n_;
+    const double by_upd = 8.0 * n_ * (6 + nj);
+    const double fl_upd = n_ * (6.0 + 2.0 * nj);
+    const double by_dir = 8.0 * n_ * (3 + nj);
+    const double fl_dir = n_ * (3.0 + 2.0 * nj);
+    int next = chunk_;
+    int its_before = 0;
+    double gam_before = -1.0;
+    for (;;) {
+      for (int c = 0; c < next; ++c) {
+        const int k = its_before + c;
+        tm_->begin(ROM_K_SPMV);
+        launch_dcg_apply(S_, sh, diag_i_, p_, w_, cg, part1_, st_);
+        tm_->end(ROM_K_SPMV, by_apply, fl_apply);
+        tm_->begin(ROM_K_DCG_UPDATE);
+        launch_dcg_update(AWp_, ld_, n_, nj, p_, w_, dvec, s_, k, cg, part1_, sh.blocks, part2_, st_);
+        tm_->end(ROM_K_DCG_UPDATE, by_upd, fl_upd);
+        tm_->begin(ROM_K_DCG_DIR);
+        launch_dcg_dir(Wp_, ld_, n_, nj, GWinv_, s_, p_, k, cg, part2_, st_);
+        tm_->end(ROM_K_DCG_DIR, by_dir, fl_dir);
+      }
+      ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
+      ROM_HIP(hipStreamSynchronize(st_));
+      // steps after the stop returned at once: drop them from the accounting (the
+      // direction update of the stopping step is one of them)
+      const int real = h_->cg.its - its_before;
+      const bool stop = h_->cg.done != 0;
+      const int noop = next - real;
+      tm_->discard(ROM_K_SPMV, noop, by_apply, fl_apply);
+      tm_->discard(ROM_K_DCG_UPDATE, noop, by_upd, fl_upd);
+      tm_->discard(ROM_K_DCG_DIR, noop + (stop ? 1 : 0), by_dir, fl_dir);
+      tm_->harvest();
+      if (stop) break;
+      // next poll: extrapolate the last chunk's contraction of s^T s to the tolerance
+      const double gam = h_->cg.gamma[h_->cg.its & 1];
+      int pred = chunk_;
+      if (gam_before > 0.0 && gam > 0.0 && gam < gam_before && real > 0) {
+        const double rate = std::log(gam / gam_before) / real;   // < 0
+        const double need = std::log(h_->cg.tol2 / gam) / rate;
+        pred = (int)std::ceil(need);
+      }
+      next = std::min(64, std::max(2, pred));
+      its_before = h_->cg.its;
+      gam_before = gam;
+    }
+    flag = h_->cg.flag;
+    return h_->cg.its;
+  }
+
+  rom_operator* op_;
+  Stencil S_;
+  int64_t n_, ld_;
+  int n_src_, n_det_, n_rhs_, K_, ku_in_;
+  rom_opts o_;
+  int cap_, ldg_, pool_cap_;
+  double tol_, trunc_;
+  int maxit_, chunk_;
+  hipStream_t st_ = nullptr;
+  Timer* tm_ = nullptr;
+  Ctrl* h_ = nullptr;
+  double mu0_ = 0.0;
+  int m_ = 0, ku_ = 0, next_slot_ = 0;
+  int w_key_ = -2, w_nj_ = -1;
+  std::vector<std::vector<int>> extra_;
+  std::vector<int64_t> idx_;
+  std::vector<double> scale_;
+  // device buffers
+  double *Q_, *pool_, *Wp_, *AWp_, *x0_, *r_, *g_, *s_, *p_, *w_, *d_, *xt_, *r2_, *vAB_;
+  double *diag_i_, *dmu_, *Gs_, *Gi_, *Lc_, *Lr_, *gram_part_, *red_part_, *gt_part_;
+  double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_;
+  Ctrl* ctrl_;
+  double *part1_, *part2_;
+  int64_t* idx_dev_;
+  double* scale_dev_;
+};
+
+rom_status fail(const Error& e) {
+  g_err = e.what();
+  return e.code;
+}
+
+void check_opts(const rom_opts* o) {
+  if (!o) throw Error(ROM_EINVAL, "null options");
+  if (!(o->tol > 0) || !std::isfinite(o->tol)) throw Error(ROM_EINVAL, "tol must be > 0");
+  if (!(o->trunc >= 0) || !std::isfinite(o->trunc)) throw Error(ROM_EINVAL, "trunc must be >= 0");
+  if (o->cap < 0 || o->cap > 4096) throw Error(ROM_EINVAL, "cap must be in [0, 4096]");
+  if (o->maxit < 0 || o->check_every < 0) throw Error(ROM_EINVAL, "maxit/check_every must be >= 0");
+}
+
+void check_counts(int n_src, int n_det, int k_u, int K) {
+  if (n_src < 0 || n_det < 0 || n_src + n_det < 1) throw Error(ROM_EINVAL, "need at least one RHS");
+  if (k_u < 0 || k_u >= NJ_MAX) throw Error(ROM_EINVAL, "k_u must be in [0, 63]");
+  if (K < 1) throw Error(ROM_EINVAL, "K must be >= 1");
+  if ((int64_t)n_src + n_det > 100000) throw Error(ROM_EINVAL, "too many right-hand sides");
+}
+
+}  // namespace
+}  // namespace rom
+
+using rom::Error;
+
+extern "C" {
+
+const char* rom_last_error(void) { return rom::g_err.c_str(); }
+
+rom_status rom_operator_bytes(const rom_grid* grid, int variable_D, size_t* bytes) {
+  try {
+    rom::check_grid(grid);
+    if (!bytes) throw Error(ROM_EINVAL, "null bytes");
+    rom::Arena a(nullptr);
+    *bytes = rom::operator_layout(*grid, variable_D != 0, a, nullptr) + rom::ALIGN;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_assemble_operator(const rom_grid* grid, double D_const, const double* D_field,
+                                 void* op_mem, size_t op_bytes, rom_operator** op,
+                                 void* stream) {
+  try {
+    rom::check_grid(grid);
+    if (!op || !op_mem) throw Error(ROM_EINVAL, "null operator memory or handle");
+    if (!D_field && (!(D_const > 0) || !std::isfinite(D_const)))
+      throw Error(ROM_EINVAL, "constant D must be > 0");
+    const bool var = D_field != nullptr;
+    rom::Arena sizing(nullptr);
+    const size_t need = rom::operator_layout(*grid, var, sizing, nullptr);
+    if (op_bytes < need) throw Error(ROM_ECAPACITY, "operator memory too small");
+    if ((uintptr_t)op_mem % 16) throw Error(ROM_EINVAL, "operator memory must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    rom_operator* o = new rom_operator;
+    o->grid = *grid;
+    o->n = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+    o->var = var;
+    o->Dc = D_const;
+    rom::Arena a(op_mem);
+    rom::operator_layout(*grid, var, a, o);
+    try {
+      rom::launch_assemble(*grid, D_const, D_field, o->diag_star, o->fx, o->fy, o->fz, st);
+    } catch (...) {
+      delete o;
+      throw;
+    }
+    rom::Stencil& S = o->S;
+    S.nx = grid->n[0];
+    S.ny = grid->n[1];
+    S.nz = grid->n[2];
+    S.dim = grid->dim;
+    S.n = o->n;
+    S.var = var ? 1 : 0;
+    const double hx = 1.0 / (S.nx + 1), hy = 1.0 / (S.ny + 1), hz = 1.0 / (S.nz + 1);
+    S.cx = var ? 0.0 : D_const / (hx * hx);
+    S.cy = var ? 0.0 : D_const / (hy * hy);
+    S.cz = (var || grid->dim == 2) ? 0.0 : D_const / (hz * hz);
+    S.fx = o->fx;
+    S.fy = o->fy;
+    S.fz = o->fz;
+    *op = o;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+void rom_operator_destroy(rom_operator* op) { delete op; }
+
+rom_status rom_apply_operator(const rom_operator* op, const rom_mu* p, const double* X,
+                              double* Y, int k, void* scratch, size_t scratch_bytes,
+                              void* stream) {
+  try {
+    if (!op || !X || !Y) throw Error(ROM_EINVAL, "null argument");
+    rom::check_mu(p, op->grid.dim);
+    if (k < 0) throw Error(ROM_EINVAL, "k must be >= 0");
+    if (!scratch || scratch_bytes < sizeof(double) * (size_t)op->n)
+      throw Error(ROM_ECAPACITY, "scratch too small");
+    if (k == 0) return ROM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    double* diag = (double*)scratch;
+    // diag(A(p)) = diag(A_*) + mu(p); the bump part goes through Y's first column as
+    // temporary storage before the product overwrites it
+    rom::launch_mu_eval(op->S, rom::make_bumps(*p, op->grid.dim), op->diag_star, diag, Y, st);
+    rom::launch_spmm(op->S, diag, X, op->n, k, Y, st);
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_sequence_bytes(const rom_operator* op, int n_src, int n_det, int k_u, int K,
+                              const rom_opts* opts, size_t* bytes) {
+  try {
+    if (!op || !bytes) throw Error(ROM_EINVAL, "null argument");
+    rom::check_opts(opts);
+    rom::check_counts(n_src, n_det, k_u, K);
+    rom::Sequencer s(const_cast<rom_operator*>(op), n_src, n_det, k_u, K, *opts);
+    *bytes = s.layout(nullptr);
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_solve_sequence(rom_operator* op, const rom_mu* params, int K,
+                              const int64_t* src_idx, const double* src_scale, int n_src,
+                              const int64_t* det_idx, const double* det_scale, int n_det,
+                              const double* U0, int k_u, const rom_opts* opts, void* workspace,
+                              size_t ws_bytes, rom_basis** basis, double* X_out,
+                              rom_record* records, rom_stats* stats, void* stream) {
+  try {
+    if (!op || !basis || !workspace) throw Error(ROM_EINVAL, "null operator, basis or workspace");
+    rom::check_opts(opts);
+    rom::check_counts(n_src, n_det, k_u, K);
+    if (!params) throw Error(ROM_EINVAL, "null params");
+    for (int i = 0; i < K; ++i) rom::check_mu(&params[i], op->grid.dim);
+    if (k_u > 0 && !U0) throw Error(ROM_EINVAL, "null U0 with k_u > 0");
+    if ((n_src > 0 && (!src_idx || !src_scale)) || (n_det > 0 && (!det_idx || !det_scale)))
+      throw Error(ROM_EINVAL, "null source/detector arrays");
+    for (int j = 0; j < n_src + n_det; ++j) {
+      const int64_t idx = j < n_src ? src_idx[j] : det_idx[j - n_src];
+      const double sc = j < n_src ? src_scale[j] : det_scale[j - n_src];
+      if (idx < 0 || idx >= op->n) throw Error(ROM_EINVAL, "source/detector index out of range");
+      if (!(sc != 0.0) || !std::isfinite(sc)) throw Error(ROM_EINVAL, "scale must be finite and nonzero");
+    }
+    if ((uintptr_t)workspace % 16) throw Error(ROM_EINVAL, "workspace must be 16-byte aligned");
+    rom::Sequencer s(op, n_src, n_det, k_u, K, *opts);
+    const size_t need = s.layout(nullptr);
+    if (ws_bytes < need) throw Error(ROM_ECAPACITY, "workspace too small");
+    s.layout(workspace);
+    *basis = nullptr;
+    return s.run(params, src_idx, src_scale, det_idx, det_scale, U0, X_out, records, stats,
+                 (hipStream_t)stream, basis);
+  } catch (const Error& e) {
+    return rom::fail(e);
+  } catch (const std::exception& e) {
+    rom::g_err = e.what();
+    return ROM_EHIP;
+  }
+}
+
+rom_status rom_reduced_bytes(const rom_basis* V, size_t* bytes) {
+  try {
+    if (!V || !bytes) throw Error(ROM_EINVAL, "null argument");
+    rom::Arena a(nullptr);
+    a.take<double>(V->ld);
+    a.take<double>(std::max<size_t>(rom::gram_partials(V->m, V->m, V->n, true), 1));
+    *bytes = a.off + rom::ALIGN;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_reduced_transfer(const rom_basis* V, const rom_mu* p, double* Ar, double* Br,
+                                double* Cr, double* Er, void* scratch, size_t scratch_bytes,
+                                void* stream) {
+  try {
+    if (!V) throw Error(ROM_EINVAL, "null basis");
+    rom::check_mu(p, V->op->grid.dim);
+    size_t need = 0;
+    rom_reduced_bytes(V, &need);
+    if (!scratch || scratch_bytes < need) throw Error(ROM_ECAPACITY, "scratch too small");
+    hipStream_t st = (hipStream_t)stream;
+    rom::Arena a(scratch);
+    double* dmu = a.take<double>(V->ld);
+    double* part = a.take<double>(std::max<size_t>(rom::gram_partials(V->m, V->m, V->n, true), 1));
+    const int m = V->m;
+    if (m == 0) return ROM_OK;
+    if (Ar) {
+      // A_r = V^T A_* V + mu0 V^T V + V^T diag(mu - mu0) V with V^T V = I (orthonormal V)
+      rom::launch_mu_eval(V->op->S, rom::make_bumps(*p, V->op->grid.dim), V->op->diag_star,
+                          nullptr, dmu, st);
+      rom::launch_gram(V->Q, V->ld, m, V->Q, V->ld, m, V->n, dmu, true, V->Gstar, V->ldg, p->mu0,
+                       Ar, m, part, st);
+    }
+    if (Er)
+      rom::launch_gram(V->Q, V->ld, m, V->Q, V->ld, m, V->n, nullptr, true, nullptr, 0, 0.0, Er,
+                       m, part, st);
+    if (Br && V->n_src > 0)
+      rom::launch_gather_rows(V->Q, V->ld, m, V->idx_dev, V->scale_dev, V->n_src, Br, m, st);
+    if (Cr && V->n_det > 0)
+      rom::launch_gather_rows(V->Q, V->ld, m, V->idx_dev + V->n_src, V->scale_dev + V->n_src,
+                              V->n_det, Cr, m, st);
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_basis_dims(const rom_basis* V, int64_t* N, int* m) {
+  if (!V) {
+    rom::g_err = "null basis";
+    return ROM_EINVAL;
+  }
+  if (N) *N = V->n;
+  if (m) *m = V->m;
+  return ROM_OK;
+}
+
+rom_status rom_basis_copy(const rom_basis* V, double* dst, void* stream) {
+  try {
+    if (!V || !dst) throw Error(ROM_EINVAL, "null argument");
+    if (V->m == 0) return ROM_OK;
+    ROM_HIP(hipMemcpy2DAsync(dst, V->n * sizeof(double), V->Q, V->ld * sizeof(double),
+                             V->n * sizeof(double), V->m, hipMemcpyDeviceToDevice,
+                             (hipStream_t)stream));
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+void rom_basis_destroy(rom_basis* V) { delete V; }
+
+}  // extern "C"

@@ -1,0 +1,233 @@
+// Stencil kernels: assembly of A_* (Sec. 3, eq. (sum)), RBF absorption, and the
+// 5/7-point operator products used throughout the solve.
+//
+// Launch shape of the products: a block owns 256 consecutive nodes of an x-y plane
+// (coalesced along x) and walks a chunk of z planes, carrying the z neighbours in
+// registers, so each node value is fetched from HBM about once per product.
+#include "kernels.h"
+
+namespace rom {
+
+namespace {
+
+constexpr int BS = 256;
+
+__global__ void k_assemble(rom_grid g, double Dc, const double* __restrict__ D, int64_t n,
+                           double* __restrict__ diag, double* __restrict__ fx,
+                           double* __restrict__ fy, double* __restrict__ fz) {
+  int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const int N[3] = {g.n[0], g.n[1], g.n[2]};
+  int c[3];
+  c[0] = (int)(i % N[0]);
+  c[1] = (int)((i / N[0]) % N[1]);
+  c[2] = (int)(i / ((int64_t)N[0] * N[1]));
+  const int64_t st[3] = {1, N[0], (int64_t)N[0] * N[1]};
+  double* F[3] = {fx, fy, fz};
+  const bool cst = D == nullptr;
+  const double Di = cst ? Dc : D[i];
+  double d = 0.0;
+  for (int a = 0; a < g.dim; ++a) {
+    const double h = 1.0 / (N[a] + 1);
+    const double ih2 = 1.0 / (h * h);
+    // minus face
+    if (c[a] > 0) {
+      const double Dn = cst ? Di : D[i - st[a]];
+      d += (cst ? Di : 2.0 * Di * Dn / (Di + Dn)) * ih2;
+    } else {
+      const double beta = g.bc[2 * a] == 1 ? h / (h + 2.0 * g.robin_A * Di) : 1.0;
+      d += Di * ih2 * beta;
+    }
+    // plus face
+    if (c[a] < N[a] - 1) {
+      const double Dn = cst ? Di : D[i + st[a]];
+      const double cf = (cst ? Di : 2.0 * Di * Dn / (Di + Dn)) * ih2;
+      d += cf;
+      if (F[a]) F[a][i] = cf;
+    } else {
+      const double beta = g.bc[2 * a + 1] == 1 ? h / (h + 2.0 * g.robin_A * Di) : 1.0;
+      d += Di * ih2 * beta;
+      if (F[a]) F[a][i] = 0.0;
+    }
+  }
+  diag[i] = d;
+}
+
+__global__ void k_mu_eval(Stencil S, Bumps B, const double* __restrict__ diag_star,
+                          double* __restrict__ diag_i, double* __restrict__ dmu) {
+  int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= S.n) return;
+  const int ix = (int)(i % S.nx);
+  const int64_t q = i / S.nx;
+  const int iy = (int)(q % S.ny);
+  const int iz = (int)(q / S.ny);
+  const double x[3] = {(ix + 1.0) / (S.nx + 1), (iy + 1.0) / (S.ny + 1),
+                       (iz + 1.0) / (S.nz + 1)};
+  const int stride = S.dim + 2;
+  double m = 0.0;
+  for (int b = 0; b < B.nb; ++b) {
+    const double* pb = B.p + b * stride;
+    double d2 = 0.0;
+    for (int a = 0; a < S.dim; ++a) {
+      const double e = x[a] - pb[a];
+      d2 += e * e;
+    }
+    const double t = sqrt(d2) / pb[S.dim];
+    if (t < 1.0) {
+      const double u = 1.0 - t;
+      const double u2 = u * u;
+      m += pb[S.dim + 1] * (u2 * u2) * (4.0 * t + 1.0);
+    }
+  }
+  dmu[i] = m;
+  if (diag_i) diag_i[i] = diag_star[i] + B.mu0 + m;
+}
+
+// MODE 0: y = A x.  MODE 1: y = A x, partial x^T y (CG step; exits if cg->done).
+// MODE 2: y = b - A x with b = bscale e_bidx, partial y^T y.
+// blockIdx.z selects a column (x + z*ldx, y + z*ldy).
+template <bool VAR, int MODE>
+__global__ __launch_bounds__(BS) void k_stencil(Stencil S, const double* __restrict__ diag,
+                                                 const double* __restrict__ x0, int64_t ldx,
+                                                 double* __restrict__ y0, int64_t ldy, int zc,
+                                                 int64_t bidx, double bscale,
+                                                 double* __restrict__ partials,
+                                                 const CGState* cg) {
+  if (MODE == 1 && cg->done) return;
+  const double* __restrict__ x = x0 + (int64_t)blockIdx.z * ldx;
+  double* __restrict__ y = y0 + (int64_t)blockIdx.z * ldy;
+  const int nxy = S.nx * S.ny;
+  const int q = blockIdx.x * BS + threadIdx.x;
+  const bool active = q < nxy;
+  const int ix = active ? q % S.nx : 0;
+  const int iy = active ? q / S.nx : 0;
+  const int z0 = blockIdx.y * zc;
+  const int z1 = min(z0 + zc, S.nz);
+  double acc[1] = {0.0};
+  if (active && z0 < z1) {
+    const bool hl = ix > 0, hr = ix < S.nx - 1, hd = iy > 0, hu = iy < S.ny - 1;
+    int64_t i = (int64_t)z0 * nxy + q;
+    double xm = z0 > 0 ? x[i - nxy] : 0.0;
+    double fm = 0.0;
+    if (VAR && z0 > 0) fm = S.fz[i - nxy];
+    double xc = x[i];
+    for (int z = z0; z < z1; ++z, i += nxy) {
+      const double xp = z < S.nz - 1 ? x[i + nxy] : 0.0;
+      double v = diag[i] * xc;
+      if (!VAR) {
+        const double sx = (hl ? x[i - 1] : 0.0) + (hr ? x[i + 1] : 0.0);
+        const double sy = (hd ? x[i - S.nx] : 0.0) + (hu ? x[i + S.nx] : 0.0);
+        v -= S.cx * sx + S.cy * sy + S.cz * (xm + xp);
+      } else {
+        if (hl) v -= S.fx[i - 1] * x[i - 1];
+        if (hr) v -= S.fx[i] * x[i + 1];
+        if (hd) v -= S.fy[i - S.nx] * x[i - S.nx];
+        if (hu) v -= S.fy[i] * x[i + S.nx];
+        if (S.dim == 3) {
+          const double fp = S.fz[i];
+          v -= fm * xm + fp * xp;
+          fm = fp;
+        }
+      }
+      if (MODE == 2) {
+        v = -v;
+        if (i == bidx) v += bscale;
+        acc[0] += v * v;
+      } else if (MODE == 1) {
+        acc[0] += xc * v;
+      }
+      y[i] = v;
+      xm = xc;
+      xc = xp;
+    }
+  }
+  if (MODE != 0) write_partials<1, BS>(acc, partials, blockIdx.x + gridDim.x * blockIdx.y);
+}
+
+template <int R>
+__global__ void k_reduce_finish(const double* __restrict__ partials, int P, double* out) {
+  __shared__ double tot[R];
+  sum_partials<R, BS>(partials, P, tot);
+  if (threadIdx.x < R) out[threadIdx.x] = tot[threadIdx.x];
+}
+
+}  // namespace
+
+StencilShape stencil_shape(const Stencil& S, int target_blocks) {
+  StencilShape sh;
+  const int nxy = S.nx * S.ny;
+  const int gx = ceil_div(nxy, BS);
+  int nzc = (target_blocks + gx - 1) / gx;
+  if (nzc < 1) nzc = 1;
+  if (nzc > S.nz) nzc = S.nz;
+  sh.zc = (S.nz + nzc - 1) / nzc;
+  nzc = (S.nz + sh.zc - 1) / sh.zc;
+  sh.grid = dim3(gx, nzc, 1);
+  sh.blocks = gx * nzc;
+  return sh;
+}
+
+void launch_assemble(const rom_grid& g, double D_const, const double* D, double* diag_star,
+                     double* fx, double* fy, double* fz, hipStream_t st) {
+  int64_t n = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  hipLaunchKernelGGL(k_assemble, dim3(ceil_div(n, BS)), dim3(BS), 0, st, g, D_const, D, n,
+                     diag_star, fx, fy, fz);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_mu_eval(const Stencil& S, const Bumps& bumps, const double* diag_star,
+                    double* diag_i, double* dmu, hipStream_t st) {
+  hipLaunchKernelGGL(k_mu_eval, dim3(ceil_div(S.n, BS)), dim3(BS), 0, st, S, bumps, diag_star,
+                     diag_i, dmu);
+  ROM_CHECK_LAUNCH();
+}
+
+#define STENCIL_LAUNCH(MODE, grid, ...)                                                        \
+  do {                                                                                         \
+    if (S.var)                                                                                 \
+      hipLaunchKernelGGL((k_stencil<true, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);      \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_stencil<false, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);     \
+    ROM_CHECK_LAUNCH();                                                                        \
+  } while (0)
+
+void launch_spmv(const Stencil& S, const double* diag, const double* x, double* y,
+                 hipStream_t st) {
+  const StencilShape sh = stencil_shape(S, 1024);
+  STENCIL_LAUNCH(0, sh.grid, diag, x, 0, y, 0, sh.zc, (int64_t)-1, 0.0, nullptr, nullptr);
+}
+
+void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t ld, int k,
+                 double* Y, hipStream_t st) {
+  if (k <= 0) return;
+  StencilShape sh = stencil_shape(S, 512);
+  dim3 grid = sh.grid;
+  grid.z = k;
+  STENCIL_LAUNCH(0, grid, diag, X, ld, Y, ld, sh.zc, (int64_t)-1, 0.0, nullptr, nullptr);
+}
+
+void launch_resid_unit(const Stencil& S, const double* diag, const double* x, int64_t idx,
+                       double scale, double* r, double* nrm2, double* partials,
+                       hipStream_t st) {
+  const StencilShape sh = stencil_shape(S, 512);
+  STENCIL_LAUNCH(2, sh.grid, diag, x, 0, r, 0, sh.zc, idx, scale, partials, nullptr);
+  launch_reduce_finish(partials, sh.blocks, 1, nrm2, st);
+}
+
+void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const double* diag,
+                      const double* p, double* w, CGState* cg, double* partials,
+                      hipStream_t st) {
+  STENCIL_LAUNCH(1, sh.grid, diag, p, 0, w, 0, sh.zc, (int64_t)-1, 0.0, partials, cg);
+}
+
+void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st) {
+  if (R == 1)
+    hipLaunchKernelGGL(k_reduce_finish<1>, dim3(1), dim3(BS), 0, st, partials, P, out);
+  else if (R == 2)
+    hipLaunchKernelGGL(k_reduce_finish<2>, dim3(1), dim3(BS), 0, st, partials, P, out);
+  else
+    throw Error(ROM_EINVAL, "reduce_finish: R must be 1 or 2");
+  ROM_CHECK_LAUNCH();
+}
+
+}  // namespace rom

@@ -1,0 +1,127 @@
+"""Device-resident problems driven through the C ABI (torch supplies memory and stream).
+
+Nothing here computes: it sizes and allocates the caller-owned buffers the ABI asks
+for, calls rom_assemble_operator / rom_solve_sequence / rom_reduced_transfer /
+rom_apply_operator, and hands back torch views of what the library wrote.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import rom as R
+
+
+@dataclass
+class SequenceResult:
+    status: int
+    basis: int
+    records: List[dict]
+    stats: dict
+    workspace: torch.Tensor          # owns the basis memory
+    X: Optional[torch.Tensor]        # (K * n_rhs, N): row i*n_rhs + j is solution (i, j)
+    n: int
+    m: int
+
+    def Q(self) -> torch.Tensor:
+        """Copy of the global basis as an (m, N) tensor (row c = column c of V)."""
+        out = torch.empty((self.m, self.n), dtype=torch.float64, device=self.workspace.device)
+        R.rom_basis_copy(self.basis, out)
+        return out
+
+    def close(self):
+        if self.basis:
+            R.rom_basis_destroy(self.basis)
+            self.basis = 0
+
+
+class Problem:
+    """One assembled operator A_* with its sources, detectors and recycle seed U_0."""
+
+    def __init__(self, dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float, D,
+                 src_idx, src_scale, det_idx, det_scale, U0: Optional[np.ndarray],
+                 device="cuda:0"):
+        self.device = torch.device(device)
+        self.dim = dim
+        self.N = tuple(int(x) for x in N) + (1,) * (3 - len(N))
+        self.n = int(np.prod(self.N))
+        self.grid = R.make_grid(dim, self.N, bc, robin_A)
+        var = not np.isscalar(D)
+        self.op_mem = torch.empty(R.rom_operator_bytes(self.grid, var), dtype=torch.uint8,
+                                  device=self.device)
+        self.D_field = torch.as_tensor(np.asarray(D, dtype=np.float64), device=self.device) if var else None
+        self.op = R.rom_assemble_operator(self.grid, 0.0 if var else float(D), self.D_field,
+                                          self.op_mem)
+        self.src_idx = np.asarray(src_idx, dtype=np.int64)
+        self.src_scale = np.asarray(src_scale, dtype=np.float64)
+        self.det_idx = np.asarray(det_idx, dtype=np.int64)
+        self.det_scale = np.asarray(det_scale, dtype=np.float64)
+        self.k_u = 0 if U0 is None else int(U0.shape[1])
+        # column-major N x k_u == row-major k_u x N
+        self.U0 = None if U0 is None or self.k_u == 0 else torch.as_tensor(
+            np.ascontiguousarray(np.asarray(U0, dtype=np.float64).T), device=self.device)
+
+    @property
+    def n_rhs(self) -> int:
+        return self.src_idx.size + self.det_idx.size
+
+    def solve(self, points: List[R.MuParams], tol: float, trunc: float = 1e-8, cap: int = 0,
+              maxit: int = 0, check_every: int = 0, timing: int = 0,
+              keep_X: bool = True) -> SequenceResult:
+        opts = R.make_opts(tol, trunc, cap, maxit, check_every, timing)
+        K = len(points)
+        nbytes = R.rom_sequence_bytes(self.op, self.src_idx.size, self.det_idx.size, self.k_u, K, opts)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        X = torch.empty((K * self.n_rhs, self.n), dtype=torch.float64, device=self.device) if keep_X else None
+        status, basis, records, st = R.rom_solve_sequence(
+            self.op, points, self.src_idx, self.src_scale, self.det_idx, self.det_scale, self.U0,
+            self.k_u, opts, ws, X)
+        n, m = R.rom_basis_dims(basis)
+        return SequenceResult(status, basis, records, R.stats_dict(st), ws, X, n, m)
+
+    def reduced(self, res: SequenceResult, p: R.MuParams):
+        """(A_r, B_r, C_r, E_r) of eq. (newreduced) as float64 tensors (column-major
+        buffers returned as their row-major transposes, i.e. A_r^T = A_r etc.)."""
+        m = res.m
+        dev = self.device
+        Ar = torch.empty((m, m), dtype=torch.float64, device=dev)
+        Er = torch.empty((m, m), dtype=torch.float64, device=dev)
+        Br = torch.empty((self.src_idx.size, m), dtype=torch.float64, device=dev)
+        Cr = torch.empty((self.det_idx.size, m), dtype=torch.float64, device=dev)
+        scratch = torch.empty(R.rom_reduced_bytes(res.basis), dtype=torch.uint8, device=dev)
+        R.rom_reduced_transfer(res.basis, p, Ar, Br, Cr, Er, scratch)
+        # column-major m x m read as row-major is the transpose; B_r (m x n_src col-major)
+        # read row-major is (n_src x m) = B_r^T
+        return Ar.T.contiguous(), Br.T.contiguous(), Cr.T.contiguous(), Er.T.contiguous()
+
+    def apply(self, p: R.MuParams, X: torch.Tensor) -> torch.Tensor:
+        """Y = A(p) X for X given as (k, N) rows (each row a vector)."""
+        X = X.contiguous()
+        Y = torch.empty_like(X)
+        scratch = torch.empty(8 * self.n, dtype=torch.uint8, device=self.device)
+        R.rom_apply_operator(self.op, p, X, Y, X.shape[0], scratch)
+        return Y
+
+    def close(self):
+        if self.op:
+            R.rom_operator_destroy(self.op)
+            self.op = 0
+
+
+def problem_from_workload(wl, device="cuda:0", k_u: Optional[int] = None) -> Problem:
+    """Build a Problem from a phantoms.Workload (seeded synthetic inputs)."""
+    import phantoms as ph
+    D = ph.diffusion_field(wl)
+    s, d = ph.rhs_nodes(wl)
+    ss, ds = ph.rhs_scales(wl)
+    U0 = ph.smooth_modes(wl, k_u)
+    return Problem(wl.dim, wl.N, wl.bc, wl.robin_A, D, s, ss, d, ds, U0, device=device)
+
+
+def points_from_workload(wl, K: Optional[int] = None, mode: str = "independent") -> List[R.MuParams]:
+    import phantoms as ph
+    return [R.MuParams(p.mu0, p.centers, p.radii, p.amps)
+            for p in ph.parameter_points(wl, K=K, mode=mode)]

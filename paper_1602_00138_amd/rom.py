@@ -1,0 +1,259 @@
+"""Thin ctypes binding of the C ABI in include/rom.h (librom.so, gfx950).
+
+Every function here has the name of the C entry point it marshals to and does
+nothing but argument conversion: device buffers are torch tensors (their data
+pointers are passed), the stream is torch's current stream unless given.  All
+arithmetic of the method runs in the library's HIP kernels.  Importing this
+module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librom.so")
+
+ROM_OK = 0
+ROM_EINVAL = -1
+ROM_ENOTSPD = -2
+ROM_ENONFINITE = -3
+ROM_ENOCONV = -4
+ROM_ECAPACITY = -5
+ROM_EHIP = -6
+ROM_NJ_MAX = 64
+ROM_MAX_BUMPS = 64
+
+ROM_K_SPMV, ROM_K_DCG_UPDATE, ROM_K_DCG_DIR, ROM_K_GEMVT, ROM_K_GEMVN, ROM_K_GRAM, ROM_K_OTHER = range(7)
+ROM_NK = 7
+KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "other"]
+
+EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator", "rom_sequence_bytes",
+            "rom_solve_sequence", "rom_reduced_bytes", "rom_reduced_transfer", "rom_basis_dims",
+            "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error"]
+
+
+class rom_grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("bc", C.c_int * 6), ("robin_A", C.c_double)]
+
+
+class rom_mu(C.Structure):
+    _fields_ = [("nb", C.c_int), ("centers", C.POINTER(C.c_double)),
+                ("radii", C.POINTER(C.c_double)), ("amps", C.POINTER(C.c_double)),
+                ("mu0", C.c_double)]
+
+
+class rom_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("cap", C.c_int), ("maxit", C.c_int),
+                ("check_every", C.c_int), ("timing", C.c_int)]
+
+
+class rom_record(C.Structure):
+    _fields_ = [("point", C.c_int), ("rhs", C.c_int), ("rho0", C.c_double), ("its", C.c_int),
+                ("solved", C.c_int), ("kept", C.c_int), ("rho", C.c_double),
+                ("final_res", C.c_double), ("m", C.c_int), ("restarts", C.c_int),
+                ("converged", C.c_int), ("pad", C.c_int)]
+
+
+class rom_stats(C.Structure):
+    _fields_ = [("m", C.c_int), ("k_u", C.c_int), ("n_solved", C.c_int), ("n_kept", C.c_int),
+                ("n_dropped_trunc", C.c_int), ("n_dropped_cap", C.c_int),
+                ("n_nonconv", C.c_int), ("total_its", C.c_longlong), ("seconds", C.c_double),
+                ("kernel_ms", C.c_double * ROM_NK), ("kernel_bytes", C.c_double * ROM_NK),
+                ("kernel_flops", C.c_double * ROM_NK), ("kernel_launches", C.c_longlong * ROM_NK)]
+
+
+class RomError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rom status {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_1602_00138_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    vp, sz = C.c_void_p, C.c_size_t
+    P = C.POINTER
+    sig = {
+        "rom_operator_bytes": (C.c_int, [P(rom_grid), C.c_int, P(sz)]),
+        "rom_assemble_operator": (C.c_int, [P(rom_grid), C.c_double, vp, vp, sz, P(vp), vp]),
+        "rom_apply_operator": (C.c_int, [vp, P(rom_mu), vp, vp, C.c_int, vp, sz, vp]),
+        "rom_sequence_bytes": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, P(rom_opts), P(sz)]),
+        "rom_solve_sequence": (C.c_int, [vp, P(rom_mu), C.c_int, P(C.c_int64), P(C.c_double), C.c_int,
+                                         P(C.c_int64), P(C.c_double), C.c_int, vp, C.c_int,
+                                         P(rom_opts), vp, sz, P(vp), vp, P(rom_record),
+                                         P(rom_stats), vp]),
+        "rom_reduced_bytes": (C.c_int, [vp, P(sz)]),
+        "rom_reduced_transfer": (C.c_int, [vp, P(rom_mu), vp, vp, vp, vp, vp, sz, vp]),
+        "rom_basis_dims": (C.c_int, [vp, P(C.c_int64), P(C.c_int)]),
+        "rom_basis_copy": (C.c_int, [vp, vp, vp]),
+        "rom_operator_destroy": (None, [vp]),
+        "rom_basis_destroy": (None, [vp]),
+        "rom_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int, allow=()):
+    if status != ROM_OK and status not in allow:
+        raise RomError(status, rom_last_error())
+    return status
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def rom_last_error() -> str:
+    s = _lib.rom_last_error()
+    return s.decode() if s else ""
+
+
+def make_grid(dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float) -> rom_grid:
+    g = rom_grid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = int(N[a]) if a < len(N) else 1
+    for f in range(6):
+        g.bc[f] = int(bc[f])
+    g.robin_A = float(robin_A)
+    return g
+
+
+def make_opts(tol: float, trunc: float = 1e-8, cap: int = 0, maxit: int = 0,
+              check_every: int = 0, timing: int = 0) -> rom_opts:
+    return rom_opts(float(tol), float(trunc), int(cap), int(maxit), int(check_every), int(timing))
+
+
+@dataclass
+class MuParams:
+    """Host-side absorption parameters of one point (kept alive during a call)."""
+    mu0: float
+    centers: np.ndarray
+    radii: np.ndarray
+    amps: np.ndarray
+
+    def c_struct(self) -> rom_mu:
+        self._c = np.ascontiguousarray(self.centers, dtype=np.float64).reshape(-1)
+        self._r = np.ascontiguousarray(self.radii, dtype=np.float64)
+        self._a = np.ascontiguousarray(self.amps, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        return rom_mu(int(self._r.size), self._c.ctypes.data_as(dp), self._r.ctypes.data_as(dp),
+                      self._a.ctypes.data_as(dp), float(self.mu0))
+
+
+def rom_operator_bytes(grid: rom_grid, variable_D: bool) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.rom_operator_bytes(C.byref(grid), int(bool(variable_D)), C.byref(out)))
+    return int(out.value)
+
+
+def rom_assemble_operator(grid: rom_grid, D_const: float, D_field, op_mem, stream=None) -> int:
+    h = C.c_void_p()
+    _check(_lib.rom_assemble_operator(C.byref(grid), float(D_const), _ptr(D_field), _ptr(op_mem),
+                                      op_mem.numel() * op_mem.element_size(), C.byref(h),
+                                      _stream(stream)))
+    return h.value
+
+
+def rom_apply_operator(op: int, p: MuParams, X, Y, k: int, scratch, stream=None) -> None:
+    mu = p.c_struct()
+    _check(_lib.rom_apply_operator(op, C.byref(mu), _ptr(X), _ptr(Y), int(k), _ptr(scratch),
+                                   scratch.numel() * scratch.element_size(), _stream(stream)))
+
+
+def rom_sequence_bytes(op: int, n_src: int, n_det: int, k_u: int, K: int, opts: rom_opts) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.rom_sequence_bytes(op, n_src, n_det, k_u, K, C.byref(opts), C.byref(out)))
+    return int(out.value)
+
+
+def rom_solve_sequence(op: int, params: List[MuParams], src_idx, src_scale, det_idx, det_scale,
+                       U0, k_u: int, opts: rom_opts, workspace, X_out=None, stream=None):
+    """Returns (status, basis handle, records list, stats); raises on errors other
+    than ROM_ENOCONV."""
+    K = len(params)
+    arr = (rom_mu * K)(*[p.c_struct() for p in params])
+    si = np.ascontiguousarray(src_idx, dtype=np.int64)
+    ss = np.ascontiguousarray(src_scale, dtype=np.float64)
+    di = np.ascontiguousarray(det_idx, dtype=np.int64)
+    ds = np.ascontiguousarray(det_scale, dtype=np.float64)
+    n_rhs = si.size + di.size
+    recs = (rom_record * (K * n_rhs))()
+    st = rom_stats()
+    basis = C.c_void_p()
+    P = C.POINTER
+    status = _lib.rom_solve_sequence(
+        op, arr, K, si.ctypes.data_as(P(C.c_int64)), ss.ctypes.data_as(P(C.c_double)), si.size,
+        di.ctypes.data_as(P(C.c_int64)), ds.ctypes.data_as(P(C.c_double)), di.size,
+        _ptr(U0), int(k_u), C.byref(opts), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), C.byref(basis), _ptr(X_out), recs,
+        C.byref(st), _stream(stream))
+    _check(status, allow=(ROM_ENOCONV,))
+    records = [{f: getattr(r, f) for f, _ in rom_record._fields_ if f != "pad"} for r in recs]
+    return status, basis.value, records, st
+
+
+def rom_reduced_bytes(basis: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.rom_reduced_bytes(basis, C.byref(out)))
+    return int(out.value)
+
+
+def rom_reduced_transfer(basis: int, p: MuParams, Ar, Br, Cr, Er, scratch, stream=None) -> None:
+    mu = p.c_struct()
+    _check(_lib.rom_reduced_transfer(basis, C.byref(mu), _ptr(Ar), _ptr(Br), _ptr(Cr), _ptr(Er),
+                                     _ptr(scratch), scratch.numel() * scratch.element_size(),
+                                     _stream(stream)))
+
+
+def rom_basis_dims(basis: int):
+    n = C.c_int64(0)
+    m = C.c_int(0)
+    _check(_lib.rom_basis_dims(basis, C.byref(n), C.byref(m)))
+    return int(n.value), int(m.value)
+
+
+def rom_basis_copy(basis: int, dst, stream=None) -> None:
+    _check(_lib.rom_basis_copy(basis, _ptr(dst), _stream(stream)))
+
+
+def rom_operator_destroy(op: int) -> None:
+    _lib.rom_operator_destroy(op)
+
+
+def rom_basis_destroy(basis: int) -> None:
+    _lib.rom_basis_destroy(basis)
+
+
+def stats_dict(st: rom_stats) -> dict:
+    d = {f: getattr(st, f) for f in ("m", "k_u", "n_solved", "n_kept", "n_dropped_trunc",
+                                     "n_dropped_cap", "n_nonconv", "total_its", "seconds")}
+    d["kernels"] = {KERNEL_CLASSES[k]: {"ms": st.kernel_ms[k], "bytes": st.kernel_bytes[k],
+                                        "flops": st.kernel_flops[k],
+                                        "launches": int(st.kernel_launches[k])}
+                    for k in range(ROM_NK)}
+    return d

@@ -195,11 +195,15 @@ def rhs_nodes(wl: Workload) -> Tuple[np.ndarray, np.ndarray]:
         return ((np.arange(count) + 0.5) * length / count).astype(np.int64)
 
     if wl.dim == 2:
+        if min(wl.n_src, wl.n_det) == 0:
+            raise ValueError("2D workloads need sources and detectors")
         src = spread(wl.n_src, N[0]) + N[0] * (N[1] - 1)
         det = spread(wl.n_det, N[0])
         return src.astype(np.int64), det.astype(np.int64)
 
     def lattice(count, layer):
+        if count == 0:
+            return np.zeros(0, dtype=np.int64)
         na = 8 if count >= 8 and count % 8 == 0 else count
         nbb = count // na
         ia = spread(na, N[0])

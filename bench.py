@@ -94,7 +94,9 @@ def main():
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--mode", default="independent", choices=["independent", "drift"])
     ap.add_argument("--cpu-sample", type=int, default=4, help="oracle sample RHS (0: skip)")
-    ap.add_argument("--kernel", default="auto", help="kernel class for the roofline")
+    ap.add_argument("--kernel", default="outer",
+                    help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
+                         "k_gemvn<false>; auto: the class with the most event time)")
     args = ap.parse_args()
 
     if args.gpus != 1:

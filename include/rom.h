@@ -112,15 +112,16 @@ typedef struct {
   int pad;
 } rom_record;
 
-/* Instrumented kernel classes (timing/bytes accumulated when opts.timing = 1). */
+/* Instrumented kernel classes (event timing for the classes set in opts.timing). */
 #define ROM_K_SPMV 0        /* stencil products */
 #define ROM_K_DCG_UPDATE 1  /* CG step: g += a p, s -= a w, s^T s, (A U_j)^T s */
 #define ROM_K_DCG_DIR 2     /* CG step: p = s + b p - U_j y */
 #define ROM_K_GEMVT 3       /* V^T x (tall-skinny transposed products) */
 #define ROM_K_GEMVN 4       /* V c (tall-skinny products) */
 #define ROM_K_GRAM 5        /* V^T diag(w) V (FP64 MFMA) */
-#define ROM_K_OTHER 6
-#define ROM_NK 7
+#define ROM_K_OUTER 6       /* outer projection x0 = V c (one per right-hand side) */
+#define ROM_K_OTHER 7
+#define ROM_NK 8
 
 typedef struct {
   int m;                 /* final basis size */

@@ -1,6 +1,7 @@
 // Internal helpers shared by the HIP kernels and the host runtime.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -30,10 +31,41 @@ struct Error : std::runtime_error {
 
 #define ROM_CHECK_LAUNCH() ROM_HIP(hipGetLastError())
 
+// Start/stop events for the next kernel launch of this thread (set by the kernel
+// timer).  A launch through ROM_LAUNCH consumes them: the events are recorded by the
+// dispatch of that kernel itself, so their interval is the kernel's execution.
+struct LaunchEvents {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+inline LaunchEvents& pending_events() {
+  thread_local LaunchEvents e;
+  return e;
+}
+
+#define ROM_LAUNCH(K, G, B, S, ST, ...)                                                 \
+  do {                                                                                  \
+    ::rom::LaunchEvents& pe_ = ::rom::pending_events();                                \
+    if (pe_.a) {                                                                        \
+      hipExtLaunchKernelGGL(K, G, B, S, ST, pe_.a, pe_.b, 0, __VA_ARGS__);              \
+      pe_.a = pe_.b = nullptr;                                                          \
+    } else {                                                                            \
+      hipLaunchKernelGGL(K, G, B, S, ST, __VA_ARGS__);                                  \
+    }                                                                                   \
+    ROM_CHECK_LAUNCH();                                                                 \
+  } while (0)
+
 // Column pointer table passed by value as a kernel argument (U_j columns live in
 // different buffers: the first columns of V and a per-RHS pool).
 struct ColPtrs {
   const double* p[NJ_MAX];
+};
+
+// Device-side skip condition: a kernel given Skip{v, thr} returns at once when
+// v[0] > thr * v[1] (both read from device memory); Skip{} never skips.
+struct Skip {
+  const double* v = nullptr;
+  double thr = 0.0;
+  __device__ __forceinline__ bool on() const { return v && v[0] > thr * v[1]; }
 };
 
 // Stencil description handed to kernels.

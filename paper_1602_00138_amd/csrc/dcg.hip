@@ -18,7 +18,14 @@ template <int NJT>
 struct CgBlock {
   static constexpr int value = NJT <= 32 ? 1024 : 512;
 };
+// rows of U_j / A U_j are prefetched ahead of the reduction only while they fit in the
+// register budget of a 1024-thread block (128 VGPRs per lane)
+template <int NJT>
+struct CgPrefetch {
+  static constexpr bool value = NJT <= 16;
+};
 constexpr int CG_GRID = 256;
+constexpr int START_BS = 256;
 
 __global__ void k_cg_setup(CGState* cg, double tol2, int maxit) {
   cg->tol2 = tol2;
@@ -45,7 +52,7 @@ __device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv, int 
 
 // Start: y0 = G^{-1} U^T r (U^T r in cg->t), g = U y0, s = r - AU y0; partials of
 // (AU)^T s (values 0..nj-1) and s^T s (value NJT).
-template <int NJT, int B = CgBlock<NJT>::value>
+template <int NJT, int B = START_BS>
 __global__ __launch_bounds__(B) void k_dcg_start(const double* __restrict__ W,
                                                   const double* __restrict__ AW, int64_t ld,
                                                   int64_t n, int nj,
@@ -62,21 +69,23 @@ __global__ __launch_bounds__(B) void k_dcg_start(const double* __restrict__ W,
 #pragma unroll
   for (int c = 0; c <= NJT; ++c) acc[c] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
+    constexpr bool KEEP = NJT <= 32;   // cache the AU row in registers
     double gi = 0.0, si = r[i];
-    double aw[NJT];
+    double aw[KEEP ? NJT : 1];
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
       if (c < nj) {
-        aw[c] = AW[i + c * ld];
+        const double a = AW[i + c * ld];
+        if (KEEP) aw[KEEP ? c : 0] = a;
         gi += W[i + c * ld] * ys[c];
-        si -= aw[c] * ys[c];
+        si -= a * ys[c];
       }
     g[i] = gi;
     s[i] = si;
     acc[NJT] += si * si;
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (c < nj) acc[c] += aw[c] * si;
+      if (c < nj) acc[c] += (KEEP ? aw[KEEP ? c : 0] : AW[i + c * ld]) * si;
   }
   write_partials_t<NJT + 1, B>(acc, part2, blockIdx.x, gridDim.x);
 }
@@ -94,14 +103,17 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const double* __restrict__ W, int
   if (cg->done) return;
   const bool first = iter < 0;
   // first row of this thread, loaded ahead of the reduction
+  constexpr bool PF = CgPrefetch<NJT>::value;
   const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
-  double w0[NJT], s0 = 0.0, p0 = 0.0;
+  double w0[PF ? NJT : 1], s0 = 0.0, p0 = 0.0;
   if (i0 < n) {
     s0 = s[i0];
     if (!first) p0 = p[i0];
+    if (PF) {
 #pragma unroll
-    for (int c = 0; c < NJT; ++c)
-      if (c < nj) w0[c] = W[i0 + c * ld];
+      for (int c = 0; c < NJT; ++c)
+        if (c < nj) w0[c] = W[i0 + c * ld];
+    }
   }
   __shared__ double tot[NJT + 1];
   __shared__ double ys[NJ_MAX];
@@ -128,7 +140,7 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const double* __restrict__ W, int
     double pi = s0 + beta * p0;
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (c < nj) pi -= w0[c] * ys[c];
+      if (c < nj) pi -= (PF ? w0[PF ? c : 0] : W[i0 + c * ld]) * ys[c];
     p[i0] = pi;
   }
   for (int64_t i = i0 + (int64_t)gridDim.x * B; i < n; i += (int64_t)gridDim.x * B) {
@@ -152,16 +164,19 @@ __global__ __launch_bounds__(B) void k_dcg_update(const double* __restrict__ AW,
                                                    const double* __restrict__ part1, int P1,
                                                    double* __restrict__ part2) {
   if (cg->done) return;
+  constexpr bool PF = CgPrefetch<NJT>::value;
   const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
-  double a0[NJT], p0 = 0.0, w0 = 0.0, g0 = 0.0, s0 = 0.0;
+  double a0[PF ? NJT : 1], p0 = 0.0, w0 = 0.0, g0 = 0.0, s0 = 0.0;
   if (i0 < n) {
     p0 = p[i0];
     w0 = w[i0];
     g0 = g[i0];
     s0 = s[i0];
+    if (PF) {
 #pragma unroll
-    for (int c = 0; c < NJT; ++c)
-      if (c < nj) a0[c] = AW[i0 + c * ld];
+      for (int c = 0; c < NJT; ++c)
+        if (c < nj) a0[c] = AW[i0 + c * ld];
+    }
   }
   __shared__ double pwt[1];
   sum_partials<1, B>(part1, P1, pwt);
@@ -185,7 +200,7 @@ __global__ __launch_bounds__(B) void k_dcg_update(const double* __restrict__ AW,
     acc[NJT] += si * si;
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (c < nj) acc[c] += a0[c] * si;
+      if (c < nj) acc[c] += (PF ? a0[PF ? c : 0] : AW[i0 + c * ld]) * si;
   }
   for (int64_t i = i0 + (int64_t)gridDim.x * B; i < n; i += (int64_t)gridDim.x * B) {
     g[i] += alpha * p[i];
@@ -209,7 +224,7 @@ int dcg_blocks(int64_t n) {
 }
 
 void launch_cg_setup(CGState* cg, double tol2, int maxit, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, st, cg, tol2, maxit);
+  ROM_LAUNCH(k_cg_setup, dim3(1), dim3(1), 0, st, cg, tol2, maxit);
   ROM_CHECK_LAUNCH();
 }
 
@@ -218,7 +233,7 @@ void launch_dcg_start(const double* W, const double* AW, int64_t ld, int64_t n, 
                       const CGState* cg, double* part2, hipStream_t st) {
   const dim3 grid(dcg_blocks(n));
   switch (njt_of(nj)) {
-#define C(T) case T: hipLaunchKernelGGL((k_dcg_start<T>), grid, dim3(CgBlock<T>::value), 0, st, W, AW, ld, n, nj, Ginv, r, g, s, cg, part2); break;
+#define C(T) case T: ROM_LAUNCH((k_dcg_start<T>), grid, dim3(START_BS), 0, st, W, AW, ld, n, nj, Ginv, r, g, s, cg, part2); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -231,7 +246,7 @@ void launch_dcg_dir(const double* W, int64_t ld, int64_t n, int nj, const double
   const dim3 grid(dcg_blocks(n));
   const int P2 = dcg_blocks(n);
   switch (njt_of(nj)) {
-#define C(T) case T: hipLaunchKernelGGL((k_dcg_dir<T>), grid, dim3(CgBlock<T>::value), 0, st, W, ld, n, nj, Ginv, s, p, iter, cg, part2, P2); break;
+#define C(T) case T: ROM_LAUNCH((k_dcg_dir<T>), grid, dim3(CgBlock<T>::value), 0, st, W, ld, n, nj, Ginv, s, p, iter, cg, part2, P2); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -243,7 +258,7 @@ void launch_dcg_update(const double* AW, int64_t ld, int64_t n, int nj, const do
                        const double* part1, int P1, double* part2, hipStream_t st) {
   const dim3 grid(dcg_blocks(n));
   switch (njt_of(nj)) {
-#define C(T) case T: hipLaunchKernelGGL((k_dcg_update<T>), grid, dim3(CgBlock<T>::value), 0, st, AW, ld, n, nj, p, w, g, s, iter, cg, part1, P1, part2); break;
+#define C(T) case T: ROM_LAUNCH((k_dcg_update<T>), grid, dim3(CgBlock<T>::value), 0, st, AW, ld, n, nj, p, w, g, s, iter, cg, part1, P1, part2); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }

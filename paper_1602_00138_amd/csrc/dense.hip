@@ -24,7 +24,8 @@ __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int6
                                                int64_t rows, int cols,
                                                const double* __restrict__ V, int64_t vstride,
                                                double* __restrict__ out,
-                                               double* __restrict__ partials) {
+                                               double* __restrict__ partials, Skip skip) {
+  if (skip.on()) return;
   const int64_t r0 = (int64_t)blockIdx.x * (64 * CPL);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double vr[NV][CPL];
@@ -65,7 +66,8 @@ __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int6
 
 // out[e] = sum over chunks b of partials[e * nch + b]: one wave per output, fixed order.
 __global__ void k_gemvt_reduce(const double* __restrict__ partials, int nch, int ne,
-                               double* __restrict__ out) {
+                               double* __restrict__ out, Skip skip) {
+  if (skip.on()) return;
   const int e = blockIdx.x * (BS / WAVE) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (e >= ne) return;
@@ -84,7 +86,8 @@ __global__ __launch_bounds__(BS) void k_gemvn(const double* __restrict__ M, int6
                                                const double* __restrict__ coef, double alpha,
                                                const double* __restrict__ in, double beta,
                                                double* __restrict__ out,
-                                               double* partials) {
+                                               double* partials, Skip skip) {
+  if (skip.on()) return;
   extern __shared__ double cs[];
   for (int c = threadIdx.x; c < cols; c += BS) cs[c] = coef[c];
   __syncthreads();
@@ -251,7 +254,7 @@ __global__ void k_border_fill(const double* __restrict__ vals, int k, double* Gs
 
 void launch_border_fill(const double* vals, int k, double* Gs, double* Gi, int64_t ldg,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_border_fill, dim3(ceil_div(k + 1, BS)), dim3(BS), 0, st, vals, k, Gs, Gi,
+  ROM_LAUNCH(k_border_fill, dim3(ceil_div(k + 1, BS)), dim3(BS), 0, st, vals, k, Gs, Gi,
                      ldg);
   ROM_CHECK_LAUNCH();
 }
@@ -269,14 +272,15 @@ size_t gemvt_partials_max(int64_t rows, int maxcols, int nv) {
 }
 
 void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const double* V,
-                  int64_t vstride, int nv, double* out, double* partials, hipStream_t st) {
+                  int64_t vstride, int nv, double* out, double* partials, hipStream_t st,
+                  Skip skip) {
   if (cols <= 0) return;
   const int cpl = gemvt_cpl(cols);
   const int chunk = 64 * cpl;
   dim3 grid(ceil_div(rows, chunk), ceil_div(cols, GT_COLS));
   if (grid.x < 1) grid.x = 1;
 #define GT_LAUNCH(C, N) \
-  hipLaunchKernelGGL((k_gemvt<C, N>), grid, dim3(BS), 0, st, M, ld, rows, cols, V, vstride, out, partials)
+  ROM_LAUNCH((k_gemvt<C, N>), grid, dim3(BS), 0, st, M, ld, rows, cols, V, vstride, out, partials, skip)
   if (cpl == 16) {
     if (nv == 1) GT_LAUNCH(16, 1); else GT_LAUNCH(16, 2);
   } else {
@@ -286,25 +290,25 @@ void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const dou
   ROM_CHECK_LAUNCH();
   if (grid.x > 1) {
     const int ne = nv * cols;
-    hipLaunchKernelGGL(k_gemvt_reduce, dim3(ceil_div(ne, BS / WAVE)), dim3(BS), 0, st, partials,
-                       (int)grid.x, ne, out);
+    ROM_LAUNCH(k_gemvt_reduce, dim3(ceil_div(ne, BS / WAVE)), dim3(BS), 0, st, partials,
+                       (int)grid.x, ne, out, skip);
     ROM_CHECK_LAUNCH();
   }
 }
 
 void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
                   double alpha, const double* in, double beta, double* out, double* nrm2,
-                  double* partials, hipStream_t st) {
+                  double* partials, hipStream_t st, Skip skip) {
   const size_t shm = (size_t)(cols > 0 ? cols : 1) * sizeof(double);
   const int grid = reduce_grid(rows);
   if (nrm2) {
-    hipLaunchKernelGGL(k_gemvn<true>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef,
-                       alpha, in, beta, out, partials);
+    ROM_LAUNCH(k_gemvn<true>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef,
+                       alpha, in, beta, out, partials, skip);
     ROM_CHECK_LAUNCH();
-    launch_reduce_finish(partials, grid, 1, nrm2, st);
+    launch_reduce_finish(partials, grid, 1, nrm2, st, skip);
   } else {
-    hipLaunchKernelGGL(k_gemvn<false>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef,
-                       alpha, in, beta, out, partials);
+    ROM_LAUNCH(k_gemvn<false>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef,
+                       alpha, in, beta, out, partials, skip);
     ROM_CHECK_LAUNCH();
   }
 }
@@ -312,14 +316,14 @@ void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const dou
 void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
                   double* nrm2, double* partials, hipStream_t st) {
   const int grid = reduce_grid(n);
-  hipLaunchKernelGGL(k_axpby, dim3(grid), dim3(BS), 0, st, n, a, x, b, y, out, nrm2 ? 1 : 0,
+  ROM_LAUNCH(k_axpby, dim3(grid), dim3(BS), 0, st, n, a, x, b, y, out, nrm2 ? 1 : 0,
                      partials);
   ROM_CHECK_LAUNCH();
   if (nrm2) launch_reduce_finish(partials, grid, 2, nrm2, st);
 }
 
 void launch_normalize(int64_t n, double* x, const double* nrm2, hipStream_t st) {
-  hipLaunchKernelGGL(k_normalize, dim3(reduce_grid(n)), dim3(BS), 0, st, n, x, nrm2);
+  ROM_LAUNCH(k_normalize, dim3(reduce_grid(n)), dim3(BS), 0, st, n, x, nrm2);
   ROM_CHECK_LAUNCH();
 }
 
@@ -328,14 +332,14 @@ void launch_pack_cols(int64_t n, const ColPtrs& src, int k, double* dst, int64_t
   if (k <= 0) return;
   int gx = ceil_div(n, BS);
   if (gx > 256) gx = 256;
-  hipLaunchKernelGGL(k_pack_cols, dim3(gx, k), dim3(BS), 0, st, n, src, k, dst, ld);
+  ROM_LAUNCH(k_pack_cols, dim3(gx, k), dim3(BS), 0, st, n, src, k, dst, ld);
   ROM_CHECK_LAUNCH();
 }
 
 void launch_gather_row(const double* M, int64_t ld, int cols, int64_t idx, double scale,
                        double* out, hipStream_t st) {
   if (cols <= 0) return;
-  hipLaunchKernelGGL(k_gather_row, dim3(ceil_div(cols, BS)), dim3(BS), 0, st, M, ld, cols, idx,
+  ROM_LAUNCH(k_gather_row, dim3(ceil_div(cols, BS)), dim3(BS), 0, st, M, ld, cols, idx,
                      scale, out);
   ROM_CHECK_LAUNCH();
 }
@@ -344,7 +348,7 @@ void launch_gather_rows(const double* M, int64_t ld, int cols, const int64_t* id
                         const double* scale, int nidx, double* out, int64_t ldo,
                         hipStream_t st) {
   if (cols <= 0 || nidx <= 0) return;
-  hipLaunchKernelGGL(k_gather_rows, dim3(ceil_div(cols, BS), nidx), dim3(BS), 0, st, M, ld, cols,
+  ROM_LAUNCH(k_gather_rows, dim3(ceil_div(cols, BS), nidx), dim3(BS), 0, st, M, ld, cols,
                      idx, scale, nidx, out, ldo);
   ROM_CHECK_LAUNCH();
 }
@@ -358,7 +362,7 @@ void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double*
     // r = Linv^T l: column j of Linv is column j of Lc.
     launch_gemvt(Lc, ld, k, k, tmp_l, 0, 1, tmp_r, partials, st);
   }
-  hipLaunchKernelGGL(k_linv_finish, dim3(1), dim3(BS), 0, st, Lc, Lr, ld, k, gcol, tmp_l, tmp_r,
+  ROM_LAUNCH(k_linv_finish, dim3(1), dim3(BS), 0, st, Lc, Lr, ld, k, gcol, tmp_l, tmp_r,
                      status);
   ROM_CHECK_LAUNCH();
 }
@@ -373,7 +377,7 @@ void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, co
 void launch_small_chol_inv(const double* G, int m, double* Linv, double* Ginv, int* status,
                            hipStream_t st) {
   if (m <= 0) return;
-  hipLaunchKernelGGL(k_small_chol_inv, dim3(1), dim3(BS), 0, st, G, m, Linv, Ginv, status);
+  ROM_LAUNCH(k_small_chol_inv, dim3(1), dim3(BS), 0, st, G, m, Linv, Ginv, status);
   ROM_CHECK_LAUNCH();
 }
 

@@ -178,15 +178,15 @@ void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t l
   int64_t rps;
   gram_shape(a, b, rows, sym, np, ns, rps);
   const int ntx = (a + TT - 1) / TT;
-  hipLaunchKernelGGL(k_gram, dim3(np, ns), dim3(BS), 0, st, X, ldx, a, Y, ldy, b, rows, rps, w,
+  ROM_LAUNCH(k_gram, dim3(np, ns), dim3(BS), 0, st, X, ldx, a, Y, ldy, b, rows, rps, w,
                      sym ? 1 : 0, ntx, partials);
   ROM_CHECK_LAUNCH();
   const int64_t ne = (int64_t)a * b;
   if (ns >= 32)
-    hipLaunchKernelGGL(k_gram_finish<true>, dim3(ceil_div(ne, BS / WAVE)), dim3(BS), 0, st,
+    ROM_LAUNCH(k_gram_finish<true>, dim3(ceil_div(ne, BS / WAVE)), dim3(BS), 0, st,
                        partials, ns, a, b, sym ? 1 : 0, base, ldb, shift, C, ldc);
   else
-    hipLaunchKernelGGL(k_gram_finish<false>, dim3(ceil_div(ne, BS)), dim3(BS), 0, st, partials,
+    ROM_LAUNCH(k_gram_finish<false>, dim3(ceil_div(ne, BS)), dim3(BS), 0, st, partials,
                        ns, a, b, sym ? 1 : 0, base, ldb, shift, C, ldc);
   ROM_CHECK_LAUNCH();
 }

@@ -52,7 +52,8 @@ void launch_resid_unit(const Stencil& S, const double* diag, const double* x, in
                        double scale, double* r, double* nrm2, double* partials,
                        hipStream_t st);
 // out[r] = sum_b partials[b*R + r] for r < R (R = 1 or 2), one block, fixed order.
-void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st);
+void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st,
+                          Skip skip = Skip());
 
 // ---- tall-skinny products ---------------------------------------------------------
 // out[v * cols + c] = sum_{r < rows} M[r + c * ld] * V[r + v * vstride], v < nv (nv <= 2).
@@ -61,12 +62,13 @@ size_t gemvt_partials(int64_t rows, int cols, int nv);
 // max of gemvt_partials over every column count <= maxcols
 size_t gemvt_partials_max(int64_t rows, int maxcols, int nv);
 void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const double* V,
-                  int64_t vstride, int nv, double* out, double* partials, hipStream_t st);
+                  int64_t vstride, int nv, double* out, double* partials, hipStream_t st,
+                  Skip skip = Skip());
 // out[r] = alpha * in[r] + beta * sum_{c < cols} M[r + c * ld] coef[c]  (in may be NULL)
 // and, if nrm2 != NULL, nrm2[0] = ||out||^2.  partials: >= 1024 doubles.
 void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
                   double alpha, const double* in, double beta, double* out, double* nrm2,
-                  double* partials, hipStream_t st);
+                  double* partials, hipStream_t st, Skip skip = Skip());
 
 // ---- vector helpers ---------------------------------------------------------------
 // out = a*x + b*y (y may be NULL); if nrm2: nrm2[0] = ||out||^2, nrm2[1] = ||y||^2.

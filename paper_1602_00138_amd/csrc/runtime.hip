@@ -72,23 +72,31 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 // HIP events on the launch stream and harvested at the host sync points.
 class Timer {
  public:
-  Timer(int mask, hipStream_t st) : mask_(mask), st_(st) {
+  explicit Timer(int mask) : mask_(mask) {
     for (int k = 0; k < ROM_NK; ++k) ms[k] = bytes[k] = flops[k] = 0.0, launches[k] = 0;
   }
   ~Timer() {
     for (auto& e : pool_) (void)hipEventDestroy(e);
   }
+  // the next ROM_LAUNCH of class cls records (a, b) in its own dispatch
   void begin(int cls) {
     if (!(mask_ >> cls & 1)) return;
     hipEvent_t a = get(), b = get();
-    (void)hipEventRecord(a, st_);
+    pending_events().a = a;
+    pending_events().b = b;
     open_.push_back({cls, a, b});
   }
   void end(int cls, double by, double fl = 0.0) {
     add(cls, by, fl);
     if (!(mask_ >> cls & 1) || open_.empty() || open_.back().cls != cls) return;
-    (void)hipEventRecord(open_.back().b, st_);
-    pending_.push_back(open_.back());
+    if (pending_events().a) {
+      // nothing was launched: the events were never recorded
+      pending_events().a = pending_events().b = nullptr;
+      free_.push_back(open_.back().a);
+      free_.push_back(open_.back().b);
+    } else {
+      pending_.push_back(open_.back());
+    }
     open_.pop_back();
   }
   // account a launch without events
@@ -143,7 +151,6 @@ class Timer {
     return e;
   }
   int mask_;
-  hipStream_t st_;
   std::vector<hipEvent_t> pool_, free_;
   std::vector<Pair> open_, pending_;
 };
@@ -288,7 +295,7 @@ class Sequencer {
                  rom_basis** out_basis) {
     const auto t0 = std::chrono::steady_clock::now();
     st_ = st;
-    Timer timer(o_.timing, st);
+    Timer timer(o_.timing);
     tm_ = &timer;
     ROM_HIP(hipHostMalloc((void**)&h_, sizeof(Ctrl), hipHostMallocDefault));
     struct Free {
@@ -345,9 +352,9 @@ class Sequencer {
         if (m_ > 0) {
           launch_gather_row(Q_, ld_, m_, idx, sc, tbuf_, st);
           launch_linv_solve(Lc_, Lr_, ldg_, m_, tbuf_, ubuf_, cbuf_, gt_part_, st);
-          tm_->begin(ROM_K_GEMVN);
+          tm_->begin(ROM_K_OUTER);
           launch_gemvn(Q_, ld_, n_, m_, cbuf_, 0.0, nullptr, 1.0, x0_, nullptr, red_part_, st);
-          tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m_ + 1), 2.0 * n_ * m_);
+          tm_->end(ROM_K_OUTER, 8.0 * n_ * (m_ + 1), 2.0 * n_ * m_);
         } else {
           ROM_HIP(hipMemsetAsync(x0_, 0, sizeof(double) * n_, st));
         }
@@ -487,6 +494,10 @@ class Sequencer {
     ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
     ROM_HIP(hipStreamSynchronize(st_));
     tm_->harvest();
+    check_status();
+  }
+
+  void check_status() {
     if (h_->status[0]) throw Error(ROM_ENOTSPD, "outer Gram matrix V^T A V not positive definite");
     if (h_->status[1]) throw Error(ROM_ENOTSPD, "recycle Gram matrix U_j^T A U_j not positive definite");
   }
@@ -496,26 +507,41 @@ class Sequencer {
     tm_->add(cls, by, 13.0 * n_);
   }
 
-  // In-place CGS2 of v against the first `cols` columns of M (orthonormal, ld_);
-  // returns the norm ratio ||v_out|| / ||v_in||; ctrl sc[4] = ||v_out||^2.
+  // In-place classical Gram-Schmidt of v against the first `cols` columns of M
+  // (orthonormal, ld_), with the second pass taken only when the first one removed more
+  // than half of ||v||^2 (Kahan-Parlett "twice is enough"; the second-pass kernels
+  // test this on the device).  Returns ||v_out|| / ||v_in||; ctrl sc[4] = ||v_out||^2.
   double cgs2_inplace(double* v, const double* M, int cols) {
     launch_axpby(n_, 1.0, v, 0.0, nullptr, v, &ctrl_->sc[5], red_part_, st_);
     if (cols > 0) {
       for (int pass = 0; pass < 2; ++pass) {
+        Skip skip;
+        if (pass == 1) {
+          skip.v = &ctrl_->sc[4];
+          skip.thr = 0.5;
+        }
         tm_->begin(ROM_K_GEMVT);
-        launch_gemvt(M, ld_, n_, cols, v, 0, 1, tbuf_, gt_part_, st_);
+        launch_gemvt(M, ld_, n_, cols, v, 0, 1, tbuf_, gt_part_, st_, skip);
         tm_->end(ROM_K_GEMVT, 8.0 * n_ * (cols + 1), 2.0 * n_ * cols);
         tm_->begin(ROM_K_GEMVN);
-        launch_gemvn(M, ld_, n_, cols, tbuf_, 1.0, v, -1.0, v, pass ? &ctrl_->sc[4] : nullptr,
-                     red_part_, st_);
+        launch_gemvn(M, ld_, n_, cols, tbuf_, 1.0, v, -1.0, v, &ctrl_->sc[4], red_part_, st_,
+                     skip);
         tm_->end(ROM_K_GEMVN, 8.0 * n_ * (cols + 2), 2.0 * n_ * cols);
       }
     } else {
       ROM_HIP(hipMemcpyAsync(&ctrl_->sc[4], &ctrl_->sc[5], sizeof(double),
                              hipMemcpyDeviceToDevice, st_));
     }
-    sync();
+    ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
+    ROM_HIP(hipStreamSynchronize(st_));
     const double a = h_->sc[4], b = h_->sc[5];
+    if (cols > 0 && a > 0.5 * b) {
+      // the second pass returned at once: drop it from the accounting
+      tm_->discard(ROM_K_GEMVT, 1, 8.0 * n_ * (cols + 1), 2.0 * n_ * cols);
+      tm_->discard(ROM_K_GEMVN, 1, 8.0 * n_ * (cols + 2), 2.0 * n_ * cols);
+    }
+    tm_->harvest();
+    check_status();
     if (!(b > 0.0) || !std::isfinite(a) || !std::isfinite(b)) return 0.0;
     return std::sqrt(a / b);
   }

@@ -145,7 +145,9 @@ __global__ __launch_bounds__(BS) void k_stencil(Stencil S, const double* __restr
 }
 
 template <int R>
-__global__ void k_reduce_finish(const double* __restrict__ partials, int P, double* out) {
+__global__ void k_reduce_finish(const double* __restrict__ partials, int P, double* out,
+                                Skip skip) {
+  if (skip.on()) return;
   __shared__ double tot[R];
   sum_partials<R, BS>(partials, P, tot);
   if (threadIdx.x < R) out[threadIdx.x] = tot[threadIdx.x];
@@ -170,14 +172,14 @@ StencilShape stencil_shape(const Stencil& S, int target_blocks) {
 void launch_assemble(const rom_grid& g, double D_const, const double* D, double* diag_star,
                      double* fx, double* fy, double* fz, hipStream_t st) {
   int64_t n = (int64_t)g.n[0] * g.n[1] * g.n[2];
-  hipLaunchKernelGGL(k_assemble, dim3(ceil_div(n, BS)), dim3(BS), 0, st, g, D_const, D, n,
+  ROM_LAUNCH(k_assemble, dim3(ceil_div(n, BS)), dim3(BS), 0, st, g, D_const, D, n,
                      diag_star, fx, fy, fz);
   ROM_CHECK_LAUNCH();
 }
 
 void launch_mu_eval(const Stencil& S, const Bumps& bumps, const double* diag_star,
                     double* diag_i, double* dmu, hipStream_t st) {
-  hipLaunchKernelGGL(k_mu_eval, dim3(ceil_div(S.n, BS)), dim3(BS), 0, st, S, bumps, diag_star,
+  ROM_LAUNCH(k_mu_eval, dim3(ceil_div(S.n, BS)), dim3(BS), 0, st, S, bumps, diag_star,
                      diag_i, dmu);
   ROM_CHECK_LAUNCH();
 }
@@ -185,9 +187,9 @@ void launch_mu_eval(const Stencil& S, const Bumps& bumps, const double* diag_sta
 #define STENCIL_LAUNCH(MODE, grid, ...)                                                        \
   do {                                                                                         \
     if (S.var)                                                                                 \
-      hipLaunchKernelGGL((k_stencil<true, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);      \
+      ROM_LAUNCH((k_stencil<true, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);      \
     else                                                                                       \
-      hipLaunchKernelGGL((k_stencil<false, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);     \
+      ROM_LAUNCH((k_stencil<false, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);     \
     ROM_CHECK_LAUNCH();                                                                        \
   } while (0)
 
@@ -220,11 +222,12 @@ void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const double* di
   STENCIL_LAUNCH(1, sh.grid, diag, p, 0, w, 0, sh.zc, (int64_t)-1, 0.0, partials, cg);
 }
 
-void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st) {
+void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st,
+                          Skip skip) {
   if (R == 1)
-    hipLaunchKernelGGL(k_reduce_finish<1>, dim3(1), dim3(BS), 0, st, partials, P, out);
+    ROM_LAUNCH(k_reduce_finish<1>, dim3(1), dim3(BS), 0, st, partials, P, out, skip);
   else if (R == 2)
-    hipLaunchKernelGGL(k_reduce_finish<2>, dim3(1), dim3(BS), 0, st, partials, P, out);
+    ROM_LAUNCH(k_reduce_finish<2>, dim3(1), dim3(BS), 0, st, partials, P, out, skip);
   else
     throw Error(ROM_EINVAL, "reduce_finish: R must be 1 or 2");
   ROM_CHECK_LAUNCH();

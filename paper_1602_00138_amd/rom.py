@@ -28,9 +28,10 @@ ROM_EHIP = -6
 ROM_NJ_MAX = 64
 ROM_MAX_BUMPS = 64
 
-ROM_K_SPMV, ROM_K_DCG_UPDATE, ROM_K_DCG_DIR, ROM_K_GEMVT, ROM_K_GEMVN, ROM_K_GRAM, ROM_K_OTHER = range(7)
-ROM_NK = 7
-KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "other"]
+(ROM_K_SPMV, ROM_K_DCG_UPDATE, ROM_K_DCG_DIR, ROM_K_GEMVT, ROM_K_GEMVN, ROM_K_GRAM, ROM_K_OUTER,
+ ROM_K_OTHER) = range(8)
+ROM_NK = 8
+KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "outer", "other"]
 
 EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator", "rom_sequence_bytes",
             "rom_solve_sequence", "rom_reduced_bytes", "rom_reduced_transfer", "rom_basis_dims",

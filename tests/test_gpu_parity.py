@@ -170,7 +170,7 @@ def test_kernel_timing_accounting(drv):
     k = res_t.stats["kernels"]
     its = res_t.stats["total_its"]
     assert k["spmv"]["launches"] == its and k["dcg_update"]["launches"] == its
-    for name in ("spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram"):
+    for name in ("spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "outer"):
         assert k[name]["launches"] > 0 and k[name]["ms"] > 0 and k[name]["bytes"] > 0, name
     assert res.stats["kernels"]["spmv"]["ms"] == 0.0      # no events when timing is off
 

@@ -37,6 +37,24 @@ __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int6
   }
   const int c0 = blockIdx.y * GT_COLS;
   const bool single = gridDim.x == 1;
+  if (NV == 1) {
+    // a row chunk whose vector entries are all zero contributes nothing: skip its reads of M
+    bool nz = false;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) nz |= vr[0][q] != 0.0;
+    if (!__syncthreads_or(nz)) {
+      for (int cc = wid; cc < GT_COLS; cc += BS / 64) {
+        const int c = c0 + cc;
+        if (c < cols && lane == 0) {
+          if (single)
+            out[c] = 0.0;
+          else
+            partials[(int64_t)c * gridDim.x + blockIdx.x] = 0.0;
+        }
+      }
+      return;
+    }
+  }
   for (int cc = wid; cc < GT_COLS; cc += BS / 64) {
     const int c = c0 + cc;
     if (c >= cols) break;
@@ -239,6 +257,115 @@ __global__ void k_small_chol_inv(const double* __restrict__ G, int m, double* __
   if (threadIdx.x == 0 && bad) status[0] = 1;
 }
 
+// C = alpha op(A) op(B) + beta D (all column-major; D may be NULL).  op(A) is M x K,
+// op(B) is K x N.  64 x 64 output tiles, 256 threads with 4 x 4 outputs each.
+__global__ __launch_bounds__(BS) void k_gemm(int M, int N, int K, double alpha,
+                                             const double* __restrict__ A, int64_t lda, int ta,
+                                             const double* __restrict__ B, int64_t ldb, int tb,
+                                             double beta, const double* __restrict__ D,
+                                             int64_t ldd, double* __restrict__ C, int64_t ldc) {
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    // stage op(A)[m0:m0+64, k0:k0+16] and op(B)[k0:k0+16, n0:n0+64]
+    for (int e = threadIdx.x; e < 16 * 64; e += BS) {
+      const int kk = e / 64, r = e % 64;
+      const int k = k0 + kk, mi = m0 + r, ni = n0 + r;
+      double a = 0.0, b = 0.0;
+      if (k < K && mi < M) a = ta ? A[k + (int64_t)mi * lda] : A[mi + (int64_t)k * lda];
+      if (k < K && ni < N) b = tb ? B[ni + (int64_t)k * ldb] : B[k + (int64_t)ni * ldb];
+      As[kk][r] = a;
+      Bs[kk][r] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][tx + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][ty + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int mi = m0 + tx + 16 * i, ni = n0 + ty + 16 * j;
+      if (mi < M && ni < N) {
+        double v = alpha * acc[i][j];
+        if (D) v += beta * D[mi + (int64_t)ni * ldd];
+        C[mi + (int64_t)ni * ldc] = v;
+      }
+    }
+}
+
+// Scatter one block row of the inverse Cholesky factor: rows k0..k0+nb of Linv get
+// T21 (nb x k0, ld nb) left of the diagonal block and T22 (nb x nb lower, ld nb).
+__global__ void k_linv_scatter(double* Lc, double* Lr, int64_t ld, int k0, int nb,
+                               const double* __restrict__ T21, const double* __restrict__ T22) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t tot = (int64_t)nb * (k0 + nb);
+  if (e >= tot) return;
+  const int r = (int)(e % nb);
+  const int c = (int)(e / nb);   // 0 .. k0+nb-1
+  double v;
+  if (c < k0)
+    v = T21[r + (int64_t)c * nb];
+  else
+    v = (c - k0 <= r) ? T22[r + (int64_t)(c - k0) * nb] : 0.0;
+  Lc[(k0 + r) + (int64_t)c * ld] = v;
+  Lr[c + (int64_t)(k0 + r) * ld] = v;
+}
+
+// Gram border from the Gram-Schmidt projections: with q = (v - Q t)/rho,
+// Q^T A_* q = (h - G_* t)/rho and Q^T A_i q = Q^T A_* q + w (w = Q^T (dmu o q)).
+// vals[c] = (h[c] - u[c]) / rho, vals[k+1+c] = vals[c] + w[c] for c < k; the diagonal
+// entries (c = k) come from d2[0] = q^T A_* q, d2[1] = q^T A_i q.
+__global__ void k_border_from_proj(const double* __restrict__ h, const double* __restrict__ u,
+                                   const double* __restrict__ w, const double* __restrict__ nrm2,
+                                   const double* __restrict__ d2, int k,
+                                   double* __restrict__ vals) {
+  const int c = blockIdx.x * BS + threadIdx.x;
+  if (c > k) return;
+  if (c == k) {
+    vals[k] = d2[0];
+    vals[2 * k + 1] = d2[1];
+    return;
+  }
+  const double inv = 1.0 / sqrt(nrm2[0]);
+  const double gs = (h[c] - u[c]) * inv;
+  vals[c] = gs;
+  vals[k + 1 + c] = gs + w[c];
+}
+
+// out[0] = x^T a, out[1] = x^T b (partials; finished by k_reduce_finish<2>); also
+// z = dmu o x.
+__global__ void k_dot2_scale(int64_t n, const double* __restrict__ x, const double* __restrict__ a,
+                             const double* __restrict__ b, const double* __restrict__ dmu,
+                             double* __restrict__ z, double* partials) {
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double xi = x[i];
+    v[0] += xi * a[i];
+    v[1] += xi * b[i];
+    z[i] = dmu[i] * xi;
+  }
+  write_partials<2, BS>(v, partials, blockIdx.x);
+}
+
 __global__ void k_border_fill(const double* __restrict__ vals, int k, double* Gs, double* Gi,
                               int64_t ldg) {
   const int c = blockIdx.x * BS + threadIdx.x;
@@ -251,6 +378,64 @@ __global__ void k_border_fill(const double* __restrict__ vals, int k, double* Gs
 }
 
 }  // namespace
+
+void launch_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, bool ta,
+                 const double* B, int64_t ldb, bool tb, double beta, const double* D, int64_t ldd,
+                 double* C, int64_t ldc, hipStream_t st) {
+  if (M <= 0 || N <= 0) return;
+  ROM_LAUNCH(k_gemm, dim3(ceil_div(M, 64), ceil_div(N, 64)), dim3(BS), 0, st, M, N, K, alpha,
+             A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, beta, D, ldd, C, ldc);
+}
+
+void launch_linv_rebuild(const double* G, int64_t ldg, int m, double* Lc, double* Lr,
+                         double* work, int* status, hipStream_t st) {
+  // work: nb*nb (S, Linv22, Ginv22) + 3 * nb * m doubles
+  constexpr int NB = 64;
+  double* S = work;
+  double* L22 = S + NB * NB;
+  double* G22i = L22 + NB * NB;
+  double* T1 = G22i + NB * NB;
+  double* T2 = T1 + (int64_t)NB * m;
+  double* T3 = T2 + (int64_t)NB * m;
+  for (int k0 = 0; k0 < m; k0 += NB) {
+    const int nb = std::min(NB, m - k0);
+    if (k0 == 0) {
+      launch_gemm(nb, nb, 0, 0.0, nullptr, 1, false, nullptr, 1, false, 1.0, G, ldg, S, nb, st);
+    } else {
+      // L21 = G21 Linv11^T  (nb x k0); Linv11^T is Lr in column-major form
+      launch_gemm(nb, k0, k0, 1.0, G + k0, ldg, false, Lr, ldg, false, 0.0, nullptr, 0,
+                  T1, nb, st);
+      // S = G22 - L21 L21^T
+      launch_gemm(nb, nb, k0, -1.0, T1, nb, false, T1, nb, true, 1.0, G + k0 + k0 * ldg, ldg,
+                  S, nb, st);
+    }
+    launch_small_chol_inv(S, nb, L22, G22i, status, st);
+    if (k0 > 0) {
+      // M = L21 Linv11 (nb x k0), Linv21 = -Linv22 M
+      launch_gemm(nb, k0, k0, 1.0, T1, nb, false, Lc, ldg, false, 0.0, nullptr, 0, T2, nb,
+                  st);
+      launch_gemm(nb, k0, nb, -1.0, L22, nb, false, T2, nb, false, 0.0, nullptr, 0, T3, nb, st);
+    }
+    const int64_t tot = (int64_t)nb * (k0 + nb);
+    ROM_LAUNCH(k_linv_scatter, dim3(ceil_div(tot, BS)), dim3(BS), 0, st, Lc, Lr, ldg, k0, nb, T3,
+               L22);
+  }
+}
+
+void launch_border_from_proj(const double* h, const double* u, const double* w,
+                             const double* nrm2, const double* d2, int k, double* vals,
+                             hipStream_t st) {
+  ROM_LAUNCH(k_border_from_proj, dim3(ceil_div(k + 1, BS)), dim3(BS), 0, st, h, u, w, nrm2, d2, k,
+             vals);
+}
+
+void launch_dot2_scale(int64_t n, const double* x, const double* a, const double* b,
+                       const double* dmu, double* z, double* out2, double* partials,
+                       hipStream_t st) {
+  const int grid = reduce_grid(n);
+  ROM_LAUNCH(k_dot2_scale, dim3(grid), dim3(BS), 0, st, n, x, a, b, dmu, z, partials);
+  launch_reduce_finish(partials, grid, 2, out2, st);
+}
 
 void launch_border_fill(const double* vals, int k, double* Gs, double* Gi, int64_t ldg,
                         hipStream_t st) {

@@ -109,6 +109,16 @@ void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t l
 void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double* gcol,
                         double* tmp_l, double* tmp_r, int* status, double* partials,
                         hipStream_t st);
+// Rebuild Linv (both layouts) from the m x m SPD matrix G in 64-column blocks: per block
+// L21 = G21 Linv11^T, S = G22 - L21 L21^T, Linv22 = chol(S)^{-1},
+// Linv21 = -Linv22 (L21 Linv11).  work: >= linv_rebuild_work(m) doubles.
+inline size_t linv_rebuild_work(int m) { return 3 * 64 * 64 + 3 * 64 * (size_t)m; }
+void launch_linv_rebuild(const double* G, int64_t ldg, int m, double* Lc, double* Lr,
+                         double* work, int* status, hipStream_t st);
+// C = alpha op(A) op(B) + beta D, column-major, op(A) M x K, op(B) K x N.
+void launch_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, bool ta,
+                 const double* B, int64_t ldb, bool tb, double beta, const double* D, int64_t ldd,
+                 double* C, int64_t ldc, hipStream_t st);
 // c = Linv^T (Linv t), for m x m Linv.
 void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, const double* t,
                        double* u, double* c, double* partials, hipStream_t st);
@@ -121,6 +131,16 @@ void launch_small_chol_inv(const double* G, int m, double* Linv, double* Ginv, i
 // Gs[c,k] = Gs[k,c] = vals[c] and Gi[c,k] = Gi[k,c] = vals[k+1+c].
 void launch_border_fill(const double* vals, int k, double* Gs, double* Gi, int64_t ldg,
                         hipStream_t st);
+
+// vals[c] = (h[c] - u[c]) / sqrt(nrm2[0]) and vals[k+1+c] = vals[c] + w[c] for c < k;
+// vals[k] = d2[0], vals[2k+1] = d2[1] (the Gram border of a new basis column).
+void launch_border_from_proj(const double* h, const double* u, const double* w,
+                             const double* nrm2, const double* d2, int k, double* vals,
+                             hipStream_t st);
+// out2 = [x^T a, x^T b]; z = dmu o x.  partials: >= 2048 doubles.
+void launch_dot2_scale(int64_t n, const double* x, const double* a, const double* b,
+                       const double* dmu, double* z, double* out2, double* partials,
+                       hipStream_t st);
 
 // ---- deflated CG --------------------------------------------------------------------
 // W, AW: n x nj contiguous (ld), Ginv: nj x nj inverse of W^T A W.

@@ -278,9 +278,10 @@ class Sequencer {
     ubuf_ = a.take<double>(cap_ + 8);
     cbuf_ = a.take<double>(cap_ + 8);
     tmpl_ = a.take<double>(cap_ + 8);
-    tmpr_ = a.take<double>(cap_ + 8);
+    tmpr_ = a.take<double>(2 * (cap_ + 8));
     bvals_ = a.take<double>(2 * (cap_ + 8));
     GW_ = a.take<double>(NJ_MAX * NJ_MAX);
+    lwork_ = a.take<double>(linv_rebuild_work(cap_));
     LWinv_ = a.take<double>(NJ_MAX * NJ_MAX);
     GWinv_ = a.take<double>(NJ_MAX * NJ_MAX);
     ctrl_ = a.take<Ctrl>(1);
@@ -547,31 +548,90 @@ class Sequencer {
   }
 
   // Append v to V if its normalised part outside range(V) exceeds trunc; border the
-  // Gram matrices V^T A_* V and V^T A_i V and the inverse Cholesky factor.
+  // Gram matrices V^T A_* V and V^T A_i V and the inverse Cholesky factor.  The first
+  // Gram-Schmidt pass also forms h = V^T A_* v, so that V^T A_* q = (h - G_* t)/rho needs
+  // no further pass over V; V^T A_i q adds V^T (dmu o q), which only reads the row chunks
+  // inside the absorption bumps.  With heavy cancellation (rho < 0.1) the border is
+  // formed directly instead.
   bool append_q(const double* v, double* rho_out) {
     *rho_out = -1.0;
     if (m_ >= cap_) return false;
-    double* slot = Q_ + (int64_t)m_ * ld_;
-    launch_axpby(n_, 1.0, v, 0.0, nullptr, slot, nullptr, red_part_, st_);
-    const double rho = cgs2_inplace(slot, Q_, m_);
+    const int m = m_;
+    double* slot = Q_ + (int64_t)m * ld_;
+    double* vcopy = vAB_;           // v, then A_* v at vAB_ + ld_
+    launch_axpby(n_, 1.0, v, 0.0, nullptr, vcopy, &ctrl_->sc[5], red_part_, st_);
+    bool pass2 = false;
+    if (m > 0) {
+      launch_spmv(S_, op_->diag_star, vcopy, vAB_ + ld_, st_);
+      account_spmv(ROM_K_OTHER);
+      tm_->begin(ROM_K_GEMVT);
+      launch_gemvt(Q_, ld_, n_, m, vcopy, ld_, 2, bvals_, gt_part_, st_);   // [t1 | h]
+      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (m + 2), 4.0 * n_ * m);
+      tm_->begin(ROM_K_GEMVN);
+      launch_gemvn(Q_, ld_, n_, m, bvals_, 1.0, vcopy, -1.0, slot, &ctrl_->sc[4], red_part_, st_);
+      tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m + 2), 2.0 * n_ * m);
+      Skip skip{&ctrl_->sc[4], 0.5};
+      tm_->begin(ROM_K_GEMVT);
+      launch_gemvt(Q_, ld_, n_, m, slot, 0, 1, tbuf_, gt_part_, st_, skip);
+      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (m + 1), 2.0 * n_ * m);
+      tm_->begin(ROM_K_GEMVN);
+      launch_gemvn(Q_, ld_, n_, m, tbuf_, 1.0, slot, -1.0, slot, &ctrl_->sc[4], red_part_, st_,
+                   skip);
+      tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m + 2), 2.0 * n_ * m);
+      ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
+      ROM_HIP(hipStreamSynchronize(st_));
+      pass2 = !(h_->sc[4] > 0.5 * h_->sc[5]);
+      if (!pass2) {
+        tm_->discard(ROM_K_GEMVT, 1, 8.0 * n_ * (m + 1), 2.0 * n_ * m);
+        tm_->discard(ROM_K_GEMVN, 1, 8.0 * n_ * (m + 2), 2.0 * n_ * m);
+      }
+      tm_->harvest();
+      check_status();
+    } else {
+      ROM_HIP(hipMemcpyAsync(slot, vcopy, sizeof(double) * n_, hipMemcpyDeviceToDevice, st_));
+      ROM_HIP(hipMemcpyAsync(&ctrl_->sc[4], &ctrl_->sc[5], sizeof(double),
+                             hipMemcpyDeviceToDevice, st_));
+      sync();
+    }
+    const double a = h_->sc[4], b = h_->sc[5];
+    const double rho = (b > 0.0 && std::isfinite(a) && std::isfinite(b)) ? std::sqrt(a / b) : 0.0;
     *rho_out = rho;
-    if (!(rho > trunc_) || m_ >= cap_) return false;
+    if (!(rho > trunc_)) return false;
+    const bool fused = m > 0 && rho >= 0.1;
+    if (fused) {
+      // t = t1 (+ t2) into ubuf_, u = G_* t into cbuf_
+      launch_axpby(m, 1.0, bvals_, pass2 ? 1.0 : 0.0, pass2 ? tbuf_ : nullptr, ubuf_, nullptr,
+                   red_part_, st_);
+      launch_gemvt(Gs_, ldg_, m, m, ubuf_, 0, 1, cbuf_, gt_part_, st_);
+    }
     launch_normalize(n_, slot, &ctrl_->sc[4], st_);
-    border(m_);
+    border_new(m, slot, fused);
     ++m_;
     return true;
   }
 
-  void border(int k) {
-    const double* q = Q_ + (int64_t)k * ld_;
+  // Border of G_*, G_i and Linv for the new (normalised) column k = q.  fused: the
+  // projection h is in bvals_[k .. 2k), u = G_* t in cbuf_, and ||v_final||^2 in sc[4].
+  void border_new(int k, const double* q, bool fused) {
     launch_spmv(S_, op_->diag_star, q, vAB_, st_);
     account_spmv(ROM_K_OTHER);
     launch_spmv(S_, diag_i_, q, vAB_ + ld_, st_);
     account_spmv(ROM_K_OTHER);
-    tm_->begin(ROM_K_GEMVT);
-    launch_gemvt(Q_, ld_, n_, k + 1, vAB_, ld_, 2, bvals_, gt_part_, st_);
-    tm_->end(ROM_K_GEMVT, 8.0 * n_ * (k + 3), 4.0 * n_ * (k + 1));
-    launch_border_fill(bvals_, k, Gs_, Gi_, ldg_, st_);
+    if (fused) {
+      // d2 = [q^T A_* q, q^T A_i q]; z = dmu o q; w = V^T z (bump rows only)
+      launch_dot2_scale(n_, q, vAB_, vAB_ + ld_, dmu_, r2_, &ctrl_->sc[8], red_part_, st_);
+      tm_->begin(ROM_K_GEMVT);
+      launch_gemvt(Q_, ld_, n_, k, r2_, 0, 1, tmpl_, gt_part_, st_);
+      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (k + 1), 2.0 * n_ * k);
+      launch_border_from_proj(bvals_ + k, cbuf_, tmpl_, &ctrl_->sc[4], &ctrl_->sc[8], k,
+                              tmpr_, st_);
+      launch_border_fill(tmpr_, k, Gs_, Gi_, ldg_, st_);
+    } else {
+      tm_->begin(ROM_K_GEMVT);
+      launch_gemvt(Q_, ld_, n_, k + 1, vAB_, ld_, 2, bvals_, gt_part_, st_);
+      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (k + 3), 4.0 * n_ * (k + 1));
+      launch_border_fill(bvals_, k, Gs_, Gi_, ldg_, st_);
+    }
     launch_linv_border(Lc_, Lr_, ldg_, k, Gi_ + (int64_t)k * ldg_, tmpl_, tmpr_,
                        &ctrl_->status[0], gt_part_, st_);
   }
@@ -582,11 +642,7 @@ class Sequencer {
     tm_->begin(ROM_K_GRAM);
     launch_gram(Q_, ld_, m_, Q_, ld_, m_, n_, dmu_, true, Gs_, ldg_, mu0_, Gi_, ldg_, gram_part_, st_);
     tm_->end(ROM_K_GRAM, 8.0 * n_ * (m_ + 1), 2.0 * n_ * m_ * m_);
-    ROM_HIP(hipMemsetAsync(Lc_, 0, sizeof(double) * ldg_ * m_, st_));
-    ROM_HIP(hipMemsetAsync(Lr_, 0, sizeof(double) * ldg_ * m_, st_));
-    for (int k = 0; k < m_; ++k)
-      launch_linv_border(Lc_, Lr_, ldg_, k, Gi_ + (int64_t)k * ldg_, tmpl_, tmpr_,
-                         &ctrl_->status[0], gt_part_, st_);
+    launch_linv_rebuild(Gi_, ldg_, m_, Lc_, Lr_, lwork_, &ctrl_->status[0], st_);
   }
 
   // Pack U_j = [U_0 part of V, extra columns of RHS j] and form A_i U_j, its Gram and
@@ -697,7 +753,7 @@ class Sequencer {
   // device buffers
   double *Q_, *pool_, *Wp_, *AWp_, *x0_, *r_, *g_, *s_, *p_, *w_, *d_, *xt_, *r2_, *vAB_;
   double *diag_i_, *dmu_, *Gs_, *Gi_, *Lc_, *Lr_, *gram_part_, *red_part_, *gt_part_;
-  double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_;
+  double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_, *lwork_;
   Ctrl* ctrl_;
   double *part1_, *part2_;
   int64_t* idx_dev_;

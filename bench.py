@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--mode", default="independent", choices=["independent", "drift"])
     ap.add_argument("--cpu-sample", type=int, default=4, help="oracle sample RHS (0: skip)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="fp64: plain FP64 recycled CG; mixed: FP32 inner sweeps in FP64 refinement")
     ap.add_argument("--kernel", default="outer",
                     help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
                          "k_gemvn<false>; auto: the class with the most event time)")
@@ -122,7 +124,8 @@ def main():
     dev = torch.device("cuda:0")
 
     # caller-owned buffers, allocated once outside the timed region
-    opts_all = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=(1 << R.ROM_NK) - 1)
+    prec = R.ROM_PREC_MIXED if args.precision == "mixed" else R.ROM_PREC_FP64
+    opts_all = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=(1 << R.ROM_NK) - 1, precision=prec)
     nbytes = R.rom_sequence_bytes(prob.op, prob.src_idx.size, prob.det_idx.size, prob.k_u, K, opts_all)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     X = torch.empty((K * n_rhs, prob.n), dtype=torch.float64, device=dev)
@@ -162,7 +165,7 @@ def main():
     if dom == "auto":
         dom = max((k for k in kern if k != "other"), key=lambda k: kern[k]["ms"])
     cls = R.KERNEL_CLASSES.index(dom)
-    opts = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=1 << cls)
+    opts = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=1 << cls, precision=prec)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -207,10 +210,12 @@ def main():
         "metric": "full-order solves/sec at 1e-8 rel. residual; SpMM HBM GB/s vs peak",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == R.ROM_PREC_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": f"{wl.name}: {'x'.join(map(str, wl.N[:wl.dim]))} grid, "
                                f"{wl.n_src}+{wl.n_det} RHS, {K} points ({args.mode}), tol {wl.tol}, "
-                               f"plain FP64 recycled CG",
+                               + ("plain FP64 recycled CG" if prec == R.ROM_PREC_FP64 else
+                                  "FP32 inner recycled CG in FP64 refinement"),
                    "n": prob.n, "points": K, "rhs": n_rhs, "tol": wl.tol,
                    "basis_m": last["m"], "inner_its": last["total_its"],
                    "solved": last["n_solved"], "nonconverged": bad},

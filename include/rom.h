@@ -69,6 +69,19 @@ typedef int rom_status;
 #define ROM_NJ_MAX 64       /* max columns of a per-RHS recycle space U_j */
 #define ROM_MAX_BUMPS 64
 
+/* Arithmetic of the inner solves (rom_opts.precision).
+ *   ROM_PREC_FP64:  Algorithm 2 entirely in FP64.
+ *   ROM_PREC_MIXED: the inner recycled CG of each solve runs in FP32 (stencil products,
+ *     projections onto U_j and all CG vectors in FP32 with FP32 sums) inside an FP64
+ *     iterative refinement on the true residual: r = b - A x in FP64, an FP32 sweep
+ *     solves A d = r / ||r|| to inner_tol, x += ||r|| d in FP64, until the FP64 residual
+ *     meets tol.  A sweep that fails to halve the residual hands the solve to the FP64
+ *     solver.  The outer projection, the skip test, the basis append, the truncation
+ *     test, the Gram matrices and (U_j^T A U_j)^{-1} stay FP64, so every returned
+ *     solution meets the same FP64 tolerance as in ROM_PREC_FP64. */
+#define ROM_PREC_FP64 0
+#define ROM_PREC_MIXED 1
+
 typedef struct rom_operator rom_operator;
 typedef struct rom_basis rom_basis;
 
@@ -90,11 +103,14 @@ typedef struct {
 typedef struct {
   double tol;       /* relative residual tolerance ||b - A x|| <= tol ||b|| (Alg. 2 skip test and CG stop) */
   double trunc;     /* keep a new basis direction iff its norm outside range(V) > trunc (unit input) */
+  double inner_tol; /* mixed precision: residual reduction asked of each FP32 sweep
+                       (0: 1e-5; values below 1e-6 act as 1e-6) */
   int cap;          /* max basis columns (0: k_u + n_rhs * K) */
   int maxit;        /* max inner CG iterations per solve (0: N) */
   int check_every;  /* CG iterations between host convergence polls (0: 16) */
   int timing;       /* bit mask over ROM_K_* classes: time every launch of those classes with
                        HIP events (0: no events; algorithmic bytes are always counted) */
+  int precision;    /* ROM_PREC_FP64 or ROM_PREC_MIXED */
 } rom_opts;
 
 /* One record per (point i, right-hand side j), in solve order. */
@@ -109,7 +125,7 @@ typedef struct {
   int m;            /* basis size after this right-hand side */
   int restarts;     /* CG restarts from the true residual */
   int converged;    /* 1 if final_res <= tol */
-  int pad;
+  int fp64_sweeps;  /* mixed precision: refinement sweeps that fell back to the FP64 solver */
 } rom_record;
 
 /* Instrumented kernel classes (event timing for the classes set in opts.timing). */

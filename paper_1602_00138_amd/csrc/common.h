@@ -76,11 +76,15 @@ struct Stencil {
   const double* fx;      // per-node coefficient of the +x face (var D), 0 at the boundary
   const double* fy;
   const double* fz;
+  const float* fx32;     // FP32 copies of the face coefficients (var D), for the FP32 solver
+  const float* fy32;
+  const float* fz32;
   int var;               // 1: per-node face coefficients
   int64_t n;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
   return v;
@@ -88,17 +92,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Sum R per-thread values over the block; thread r < R of the returned block gets
 // the block total of value r in `out` (other threads get garbage).
-template <int R, int BS>
-__device__ __forceinline__ void block_sum(const double (&v)[R], double* sh /* [BS/WAVE][R] */,
-                                          double& out) {
+template <int R, int BS, typename T>
+__device__ __forceinline__ void block_sum(const T (&v)[R], T* sh /* [BS/WAVE][R] */, T& out) {
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    double s = wave_sum(v[r]);
+    T s = wave_sum(v[r]);
     if (lane == 0) sh[wid * R + r] = s;
   }
   __syncthreads();
-  out = 0.0;
+  out = T(0);
   if (threadIdx.x < R) {
 #pragma unroll
     for (int w = 0; w < BS / WAVE; ++w) out += sh[w * R + threadIdx.x];
@@ -107,28 +110,27 @@ __device__ __forceinline__ void block_sum(const double (&v)[R], double* sh /* [B
 
 // Block partials: thread r < R of the block writes the block total of value r to
 // partials[bid * R + r] (plain stores; a later kernel launch reads them).
-template <int R, int BS>
-__device__ __forceinline__ void write_partials(const double (&v)[R], double* partials, int bid) {
-  __shared__ double sh[(BS / WAVE) * R];
-  double bs;
+template <int R, int BS, typename T>
+__device__ __forceinline__ void write_partials(const T (&v)[R], T* partials, int bid) {
+  __shared__ T sh[(BS / WAVE) * R];
+  T bs;
   block_sum<R, BS>(v, sh, bs);
   if (threadIdx.x < R) partials[(size_t)bid * R + threadIdx.x] = bs;
 }
 
 // Sum P rows of R partials (row b = partials[b*R .. b*R+R)) in a fixed order; the totals
 // land in tot[0..R) (shared memory) and are visible to every thread on return.
-template <int R, int BS>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ partials, int P,
-                                             double* tot) {
-  __shared__ double sh[(BS / WAVE) * R];
-  double acc[R];
+template <int R, int BS, typename T>
+__device__ __forceinline__ void sum_partials(const T* __restrict__ partials, int P, T* tot) {
+  __shared__ T sh[(BS / WAVE) * R];
+  T acc[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int r = 0; r < R; ++r) acc[r] = T(0);
   for (int b = threadIdx.x; b < P; b += BS) {
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] += partials[(size_t)b * R + r];
   }
-  double t;
+  T t;
   block_sum<R, BS>(acc, sh, t);
   if (threadIdx.x < R) tot[threadIdx.x] = t;
   __syncthreads();
@@ -136,27 +138,25 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ partials
 
 // Transposed partials for many values: value r of block bid goes to partials[r * P + bid]
 // so that the consumer's loads are coalesced across blocks.
-template <int R, int BS>
-__device__ __forceinline__ void write_partials_t(const double (&v)[R], double* partials, int bid,
-                                                 int P) {
-  __shared__ double sh[(BS / WAVE) * R];
-  double bs;
+template <int R, int BS, typename T>
+__device__ __forceinline__ void write_partials_t(const T (&v)[R], T* partials, int bid, int P) {
+  __shared__ T sh[(BS / WAVE) * R];
+  T bs;
   block_sum<R, BS>(v, sh, bs);
   if (threadIdx.x < R) partials[(size_t)threadIdx.x * P + bid] = bs;
 }
 
-template <int R, int BS>
-__device__ __forceinline__ void sum_partials_t(const double* __restrict__ partials, int P,
-                                               double* tot) {
-  __shared__ double sh[(BS / WAVE) * R];
-  double acc[R];
+template <int R, int BS, typename T>
+__device__ __forceinline__ void sum_partials_t(const T* __restrict__ partials, int P, T* tot) {
+  __shared__ T sh[(BS / WAVE) * R];
+  T acc[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int r = 0; r < R; ++r) acc[r] = T(0);
   for (int b = threadIdx.x; b < P; b += BS) {
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] += partials[(size_t)r * P + b];
   }
-  double t;
+  T t;
   block_sum<R, BS>(acc, sh, t);
   if (threadIdx.x < R) tot[threadIdx.x] = t;
   __syncthreads();

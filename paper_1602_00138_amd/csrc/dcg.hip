@@ -5,7 +5,9 @@
 // reduces them; the scalar state lives in device memory (s^T s double-buffered by
 // step parity), so chunks of steps run without host round trips.  Each thread loads
 // its first row before reducing the previous launch's partials, so the reduction
-// latency hides behind the loads.
+// latency hides behind the loads.  T is the vector type: double for the plain form,
+// float for the inner sweeps of the mixed form (FP32 vectors and FP32 sums); the CG
+// scalars, the tolerance and (U^T A U)^{-1} stay FP64 in either case.
 #include "kernels.h"
 
 namespace rom {
@@ -14,15 +16,15 @@ namespace {
 
 // Step kernels: 256 blocks of CgBlock threads (4 waves per SIMD on 256 CUs); the next
 // launch then reduces only 256 partial rows.
-template <int NJT>
+template <typename T, int NJT>
 struct CgBlock {
-  static constexpr int value = NJT <= 32 ? 1024 : 512;
+  static constexpr int value = NJT * sizeof(T) <= 256 ? 1024 : 512;
 };
 // rows of U_j / A U_j are prefetched ahead of the reduction only while they fit in the
 // register budget of a 1024-thread block (128 VGPRs per lane)
-template <int NJT>
+template <typename T, int NJT>
 struct CgPrefetch {
-  static constexpr bool value = NJT <= 16;
+  static constexpr bool value = NJT * sizeof(T) <= 128;
 };
 constexpr int CG_GRID = 256;
 constexpr int START_BS = 256;
@@ -38,44 +40,45 @@ __global__ void k_cg_setup(CGState* cg, double tol2, int maxit) {
   cg->pw = 0.0;
 }
 
-// ys[j] = sum_c Ginv[j + c nj] t[c] (Ginv = (U^T A U)^{-1}, symmetric), into shared memory.
-__device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv, int nj,
-                                           const double* t, double* ys) {
+// ys[j] = scale * sum_c Ginv[j + c nj] t[c] (Ginv = (U^T A U)^{-1}, symmetric, FP64),
+// evaluated in FP64 and stored as T in shared memory.
+template <typename T, typename S>
+__device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv, int nj, const S* t,
+                                           double scale, T* ys) {
   if (threadIdx.x < nj) {
     const int j = threadIdx.x;
     double y = 0.0;
-    for (int c = 0; c < nj; ++c) y += Ginv[j + c * nj] * t[c];
-    ys[j] = y;
+    for (int c = 0; c < nj; ++c) y += Ginv[j + c * nj] * (double)t[c];
+    ys[j] = (T)(scale * y);
   }
   __syncthreads();
 }
 
 // Start: y0 = G^{-1} U^T r (U^T r in cg->t), g = U y0, s = r - AU y0; partials of
-// (AU)^T s (values 0..nj-1) and s^T s (value NJT).
-template <int NJT, int B = START_BS>
-__global__ __launch_bounds__(B) void k_dcg_start(const double* __restrict__ W,
-                                                  const double* __restrict__ AW, int64_t ld,
+// (AU)^T s (values 0..nj-1) and s^T s (value NJT).  The right-hand side is FP64 and is
+// read as rscale * r (the mixed form solves for a unit-norm residual in FP32).
+template <typename T, int NJT, int B = START_BS>
+__global__ __launch_bounds__(B) void k_dcg_start(const T* __restrict__ W,
+                                                  const T* __restrict__ AW, int64_t ld,
                                                   int64_t n, int nj,
                                                   const double* __restrict__ Ginv,
-                                                  const double* __restrict__ r,
-                                                  double* __restrict__ g,
-                                                  double* __restrict__ s, const CGState* cg,
-                                                  double* __restrict__ part2) {
-  __shared__ double ts[NJ_MAX], ys[NJ_MAX];
-  if (threadIdx.x < nj) ts[threadIdx.x] = cg->t[threadIdx.x];
-  __syncthreads();
-  gram_apply(Ginv, nj, ts, ys);
-  double acc[NJT + 1];
+                                                  const double* __restrict__ r, double rscale,
+                                                  T* __restrict__ g, T* __restrict__ s,
+                                                  const CGState* cg, T* __restrict__ part2) {
+  __shared__ T ys[NJ_MAX];
+  gram_apply(Ginv, nj, cg->t, rscale, ys);
+  const T rs = (T)rscale;
+  T acc[NJT + 1];
 #pragma unroll
-  for (int c = 0; c <= NJT; ++c) acc[c] = 0.0;
+  for (int c = 0; c <= NJT; ++c) acc[c] = T(0);
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
-    constexpr bool KEEP = NJT <= 32;   // cache the AU row in registers
-    double gi = 0.0, si = r[i];
-    double aw[KEEP ? NJT : 1];
+    constexpr bool KEEP = NJT * sizeof(T) <= 256;   // cache the AU row in registers
+    T gi = T(0), si = (T)(rs * (T)r[i]);
+    T aw[KEEP ? NJT : 1];
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
       if (c < nj) {
-        const double a = AW[i + c * ld];
+        const T a = AW[i + c * ld];
         if (KEEP) aw[KEEP ? c : 0] = a;
         gi += W[i + c * ld] * ys[c];
         si -= a * ys[c];
@@ -93,19 +96,18 @@ __global__ __launch_bounds__(B) void k_dcg_start(const double* __restrict__ W,
 // Reduce the step's partials (s^T s, (AU)^T s); record s^T s for the next step, count
 // the step, stop on convergence / maxit / non-finite values; else the new direction
 // p = s + beta p - U G^{-1} (AU)^T s.  iter = -1 for the direction after the start.
-template <int NJT, int B = CgBlock<NJT>::value>
-__global__ __launch_bounds__(B) void k_dcg_dir(const double* __restrict__ W, int64_t ld,
-                                                int64_t n, int nj,
-                                                const double* __restrict__ Ginv,
-                                                const double* __restrict__ s,
-                                                double* __restrict__ p, int iter, CGState* cg,
-                                                const double* __restrict__ part2, int P2) {
+template <typename T, int NJT, int B = CgBlock<T, NJT>::value>
+__global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t ld, int64_t n,
+                                                int nj, const double* __restrict__ Ginv,
+                                                const T* __restrict__ s, T* __restrict__ p,
+                                                int iter, CGState* cg,
+                                                const T* __restrict__ part2, int P2) {
   if (cg->done) return;
   const bool first = iter < 0;
   // first row of this thread, loaded ahead of the reduction
-  constexpr bool PF = CgPrefetch<NJT>::value;
+  constexpr bool PF = CgPrefetch<T, NJT>::value;
   const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
-  double w0[PF ? NJT : 1], s0 = 0.0, p0 = 0.0;
+  T w0[PF ? NJT : 1], s0 = T(0), p0 = T(0);
   if (i0 < n) {
     s0 = s[i0];
     if (!first) p0 = p[i0];
@@ -115,10 +117,10 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const double* __restrict__ W, int
         if (c < nj) w0[c] = W[i0 + c * ld];
     }
   }
-  __shared__ double tot[NJT + 1];
-  __shared__ double ys[NJ_MAX];
+  __shared__ T tot[NJT + 1];
+  __shared__ T ys[NJ_MAX];
   sum_partials_t<NJT + 1, B>(part2, P2, tot);
-  const double gnew = tot[NJT];
+  const double gnew = (double)tot[NJT];
   const double gold = first ? 1.0 : cg->gamma[iter & 1];
   const bool nonfinite = !isfinite(gnew);
   const bool conv = gnew <= cg->tol2;
@@ -134,17 +136,17 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const double* __restrict__ W, int
     }
   }
   if (nonfinite || conv || hit) return;
-  gram_apply(Ginv, nj, tot, ys);
-  const double beta = first ? 0.0 : gnew / gold;
+  gram_apply(Ginv, nj, tot, 1.0, ys);
+  const T beta = first ? T(0) : (T)(gnew / gold);
   if (i0 < n) {
-    double pi = s0 + beta * p0;
+    T pi = s0 + beta * p0;
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
       if (c < nj) pi -= (PF ? w0[PF ? c : 0] : W[i0 + c * ld]) * ys[c];
     p[i0] = pi;
   }
   for (int64_t i = i0 + (int64_t)gridDim.x * B; i < n; i += (int64_t)gridDim.x * B) {
-    double pi = s[i];
+    T pi = s[i];
     if (!first) pi += beta * p[i];
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
@@ -154,19 +156,17 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const double* __restrict__ W, int
 }
 
 // alpha = s^T s / p^T A p; g += alpha p; s -= alpha w; partials of (AU)^T s and s^T s.
-template <int NJT, int B = CgBlock<NJT>::value>
-__global__ __launch_bounds__(B) void k_dcg_update(const double* __restrict__ AW, int64_t ld,
-                                                   int64_t n, int nj,
-                                                   const double* __restrict__ p,
-                                                   const double* __restrict__ w,
-                                                   double* __restrict__ g,
-                                                   double* __restrict__ s, int iter, CGState* cg,
-                                                   const double* __restrict__ part1, int P1,
-                                                   double* __restrict__ part2) {
+template <typename T, int NJT, int B = CgBlock<T, NJT>::value>
+__global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int64_t ld,
+                                                   int64_t n, int nj, const T* __restrict__ p,
+                                                   const T* __restrict__ w, T* __restrict__ g,
+                                                   T* __restrict__ s, int iter, CGState* cg,
+                                                   const T* __restrict__ part1, int P1,
+                                                   T* __restrict__ part2) {
   if (cg->done) return;
-  constexpr bool PF = CgPrefetch<NJT>::value;
+  constexpr bool PF = CgPrefetch<T, NJT>::value;
   const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
-  double a0[PF ? NJT : 1], p0 = 0.0, w0 = 0.0, g0 = 0.0, s0 = 0.0;
+  T a0[PF ? NJT : 1], p0 = T(0), w0 = T(0), g0 = T(0), s0 = T(0);
   if (i0 < n) {
     p0 = p[i0];
     w0 = w[i0];
@@ -178,9 +178,9 @@ __global__ __launch_bounds__(B) void k_dcg_update(const double* __restrict__ AW,
         if (c < nj) a0[c] = AW[i0 + c * ld];
     }
   }
-  __shared__ double pwt[1];
+  __shared__ T pwt[1];
   sum_partials<1, B>(part1, P1, pwt);
-  const double pw = pwt[0];
+  const double pw = (double)pwt[0];
   if (!(pw > 0.0) || !isfinite(pw)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       cg->flag = isfinite(pw) ? 1 : 2;
@@ -189,13 +189,13 @@ __global__ __launch_bounds__(B) void k_dcg_update(const double* __restrict__ AW,
     return;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) cg->pw = pw;
-  const double alpha = cg->gamma[iter & 1] / pw;
-  double acc[NJT + 1];
+  const T alpha = (T)(cg->gamma[iter & 1] / pw);
+  T acc[NJT + 1];
 #pragma unroll
-  for (int c = 0; c <= NJT; ++c) acc[c] = 0.0;
+  for (int c = 0; c <= NJT; ++c) acc[c] = T(0);
   if (i0 < n) {
     g[i0] = g0 + alpha * p0;
-    const double si = s0 - alpha * w0;
+    const T si = s0 - alpha * w0;
     s[i0] = si;
     acc[NJT] += si * si;
 #pragma unroll
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(B) void k_dcg_update(const double* __restrict__ AW,
   }
   for (int64_t i = i0 + (int64_t)gridDim.x * B; i < n; i += (int64_t)gridDim.x * B) {
     g[i] += alpha * p[i];
-    const double si = s[i] - alpha * w[i];
+    const T si = s[i] - alpha * w[i];
     s[i] = si;
     acc[NJT] += si * si;
 #pragma unroll
@@ -228,41 +228,55 @@ void launch_cg_setup(CGState* cg, double tol2, int maxit, hipStream_t st) {
   ROM_CHECK_LAUNCH();
 }
 
-void launch_dcg_start(const double* W, const double* AW, int64_t ld, int64_t n, int nj,
-                      const double* Ginv, const double* r, double* g, double* s,
-                      const CGState* cg, double* part2, hipStream_t st) {
+template <typename T>
+void launch_dcg_start(const T* W, const T* AW, int64_t ld, int64_t n, int nj, const double* Ginv,
+                      const double* r, double rscale, T* g, T* s, const CGState* cg, T* part2,
+                      hipStream_t st) {
   const dim3 grid(dcg_blocks(n));
   switch (njt_of(nj)) {
-#define C(T) case T: ROM_LAUNCH((k_dcg_start<T>), grid, dim3(START_BS), 0, st, W, AW, ld, n, nj, Ginv, r, g, s, cg, part2); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, ld, n, nj, Ginv, r, rscale, g, s, cg, part2); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
   ROM_CHECK_LAUNCH();
 }
 
-void launch_dcg_dir(const double* W, int64_t ld, int64_t n, int nj, const double* Ginv,
-                    const double* s, double* p, int iter, CGState* cg, const double* part2,
-                    hipStream_t st) {
+template <typename T>
+void launch_dcg_dir(const T* W, int64_t ld, int64_t n, int nj, const double* Ginv, const T* s,
+                    T* p, int iter, CGState* cg, const T* part2, hipStream_t st) {
   const dim3 grid(dcg_blocks(n));
   const int P2 = dcg_blocks(n);
   switch (njt_of(nj)) {
-#define C(T) case T: ROM_LAUNCH((k_dcg_dir<T>), grid, dim3(CgBlock<T>::value), 0, st, W, ld, n, nj, Ginv, s, p, iter, cg, part2, P2); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, W, ld, n, nj, Ginv, s, p, iter, cg, part2, P2); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
   ROM_CHECK_LAUNCH();
 }
 
-void launch_dcg_update(const double* AW, int64_t ld, int64_t n, int nj, const double* p,
-                       const double* w, double* g, double* s, int iter, CGState* cg,
-                       const double* part1, int P1, double* part2, hipStream_t st) {
+template <typename T>
+void launch_dcg_update(const T* AW, int64_t ld, int64_t n, int nj, const T* p, const T* w, T* g,
+                       T* s, int iter, CGState* cg, const T* part1, int P1, T* part2,
+                       hipStream_t st) {
   const dim3 grid(dcg_blocks(n));
   switch (njt_of(nj)) {
-#define C(T) case T: ROM_LAUNCH((k_dcg_update<T>), grid, dim3(CgBlock<T>::value), 0, st, AW, ld, n, nj, p, w, g, s, iter, cg, part1, P1, part2); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, AW, ld, n, nj, p, w, g, s, iter, cg, part1, P1, part2); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
   ROM_CHECK_LAUNCH();
 }
+
+#define INSTANTIATE(T)                                                                          \
+  template void launch_dcg_start<T>(const T*, const T*, int64_t, int64_t, int, const double*,    \
+                                    const double*, double, T*, T*, const CGState*, T*,           \
+                                    hipStream_t);                                                \
+  template void launch_dcg_dir<T>(const T*, int64_t, int64_t, int, const double*, const T*, T*,  \
+                                  int, CGState*, const T*, hipStream_t);                         \
+  template void launch_dcg_update<T>(const T*, int64_t, int64_t, int, const T*, const T*, T*, T*, \
+                                     int, CGState*, const T*, int, T*, hipStream_t);
+INSTANTIATE(double)
+INSTANTIATE(float)
+#undef INSTANTIATE
 
 }  // namespace rom

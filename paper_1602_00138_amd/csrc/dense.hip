@@ -154,6 +154,25 @@ __global__ void k_normalize(int64_t n, double* __restrict__ x, const double* nrm
     x[i] *= s;
 }
 
+// Mixed form: FP32 copies of FP64 columns (blockIdx.y = column).
+__global__ void k_cast_cols_f32(int64_t n, const double* __restrict__ in, int64_t ld,
+                                float* __restrict__ out) {
+  const int64_t off = (int64_t)blockIdx.y * ld;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    out[off + i] = (float)in[off + i];
+}
+
+// Mixed form, end of an FP32 sweep: g += sigma d; x = x0 + g (FP64).
+__global__ void k_refine_update(int64_t n, double sigma, const float* __restrict__ d,
+                                double* __restrict__ g, const double* __restrict__ x0,
+                                double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double gi = g[i] + sigma * (double)d[i];
+    g[i] = gi;
+    x[i] = x0[i] + gi;
+  }
+}
+
 __global__ void k_pack_cols(int64_t n, ColPtrs src, int k, double* __restrict__ dst, int64_t ld) {
   const int c = blockIdx.y;
   const double* s = src.p[c];
@@ -509,6 +528,26 @@ void launch_axpby(int64_t n, double a, const double* x, double b, const double* 
 
 void launch_normalize(int64_t n, double* x, const double* nrm2, hipStream_t st) {
   ROM_LAUNCH(k_normalize, dim3(reduce_grid(n)), dim3(BS), 0, st, n, x, nrm2);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_cast_cols_f32(int64_t n, int k, const double* in, int64_t ld, float* out,
+                          hipStream_t st) {
+  if (k <= 0 || n <= 0) return;
+  int gx = ceil_div(n, BS);
+  if (gx > 512) gx = 512;
+  ROM_LAUNCH(k_cast_cols_f32, dim3(gx, k), dim3(BS), 0, st, n, in, ld, out);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_cast_f32(int64_t n, const double* in, float* out, hipStream_t st) {
+  launch_cast_cols_f32(n, 1, in, n, out, st);
+}
+
+void launch_refine_update(int64_t n, double sigma, const float* d, double* g, const double* x0,
+                          double* x, hipStream_t st) {
+  if (n <= 0) return;
+  ROM_LAUNCH(k_refine_update, dim3(reduce_grid(n)), dim3(BS), 0, st, n, sigma, d, g, x0, x);
   ROM_CHECK_LAUNCH();
 }
 

@@ -143,22 +143,37 @@ void launch_dot2_scale(int64_t n, const double* x, const double* a, const double
                        hipStream_t st);
 
 // ---- deflated CG --------------------------------------------------------------------
-// W, AW: n x nj contiguous (ld), Ginv: nj x nj inverse of W^T A W.
-// part1: >= stencil_shape(S, 512).blocks doubles (p^T A p partials of the operator step);
-// part2: >= (NJ_MAX + 1) * dcg_blocks(n) doubles.  iter: 0-based step index (-1 for the
-// direction after the start).
+// T = double (plain form) or float (inner sweeps of the mixed form).  W, AW: n x nj
+// contiguous (ld), Ginv: nj x nj FP64 inverse of W^T A W.  part1: >= stencil_shape(S,
+// 1024).blocks values of T (p^T A p partials of the operator step); part2: >= (NJ_MAX +
+// 1) * dcg_blocks(n) values of T.  iter: 0-based step index (-1 for the direction after
+// the start).  The start reads the FP64 right-hand side as rscale * r, and U^T r from
+// cg->t (the caller stores the unscaled product there).
 int dcg_blocks(int64_t n);
 void launch_cg_setup(CGState* cg, double tol2, int maxit, hipStream_t st);
-void launch_dcg_start(const double* W, const double* AW, int64_t ld, int64_t n, int nj,
-                      const double* Ginv, const double* r, double* g, double* s,
-                      const CGState* cg, double* part2, hipStream_t st);
-void launch_dcg_dir(const double* W, int64_t ld, int64_t n, int nj, const double* Ginv,
-                    const double* s, double* p, int iter, CGState* cg, const double* part2,
-                    hipStream_t st);
-void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const double* diag,
-                      const double* p, double* w, CGState* cg, double* part1, hipStream_t st);
-void launch_dcg_update(const double* AW, int64_t ld, int64_t n, int nj, const double* p,
-                       const double* w, double* g, double* s, int iter, CGState* cg,
-                       const double* part1, int P1, double* part2, hipStream_t st);
+template <typename T>
+void launch_dcg_start(const T* W, const T* AW, int64_t ld, int64_t n, int nj, const double* Ginv,
+                      const double* r, double rscale, T* g, T* s, const CGState* cg, T* part2,
+                      hipStream_t st);
+template <typename T>
+void launch_dcg_dir(const T* W, int64_t ld, int64_t n, int nj, const double* Ginv, const T* s,
+                    T* p, int iter, CGState* cg, const T* part2, hipStream_t st);
+template <typename T>
+void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
+                      CGState* cg, T* partials, hipStream_t st);
+template <typename T>
+void launch_dcg_update(const T* AW, int64_t ld, int64_t n, int nj, const T* p, const T* w, T* g,
+                       T* s, int iter, CGState* cg, const T* part1, int P1, T* part2,
+                       hipStream_t st);
+
+// ---- mixed form -----------------------------------------------------------------------
+// out[i] = (float) in[i], i < n.
+void launch_cast_f32(int64_t n, const double* in, float* out, hipStream_t st);
+// out[i + c*ld] = (float) in[i + c*ld] for i < n, c < k.
+void launch_cast_cols_f32(int64_t n, int k, const double* in, int64_t ld, float* out,
+                          hipStream_t st);
+// One refinement step: g += sigma * d (d FP32), x = x0 + g (FP64).
+void launch_refine_update(int64_t n, double sigma, const float* d, double* g, const double* x0,
+                          double* x, hipStream_t st);
 
 }  // namespace rom

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -21,7 +22,7 @@ struct rom_operator {
   double* fx;
   double* fy;
   double* fz;
-  rom::Stencil S;
+  rom::Stencil S{};
 };
 
 struct rom_basis {
@@ -43,6 +44,11 @@ namespace {
 thread_local std::string g_err;
 
 constexpr size_t ALIGN = 256;
+// restarts of one solve from its true residual (each a full CG solve)
+constexpr int MAX_SWEEPS = 64;
+// smallest residual reduction asked of one FP32 sweep (about 16 FP32 unit roundoffs:
+// below it the FP32 true residual no longer follows the recursive one)
+constexpr double FP32_GOAL_MIN = 1e-6;
 
 struct Arena {
   char* base;
@@ -238,6 +244,8 @@ class Sequencer {
     trunc_ = o.trunc;
     maxit_ = o.maxit > 0 ? o.maxit : (int)std::min<int64_t>(n_, 1 << 30);
     chunk_ = o.check_every > 0 ? o.check_every : 16;
+    mixed_ = o.precision == ROM_PREC_MIXED;
+    inner_tol_ = o.inner_tol > 0 ? o.inner_tol : 1e-5;
   }
 
   int cap() const { return cap_; }
@@ -284,6 +292,20 @@ class Sequencer {
     lwork_ = a.take<double>(linv_rebuild_work(cap_));
     LWinv_ = a.take<double>(NJ_MAX * NJ_MAX);
     GWinv_ = a.take<double>(NJ_MAX * NJ_MAX);
+    if (mixed_) {
+      W32_ = a.take<float>(ld_ * NJ_MAX);
+      AW32_ = a.take<float>(ld_ * NJ_MAX);
+      s32_ = a.take<float>(ld_);
+      p32_ = a.take<float>(ld_);
+      w32_ = a.take<float>(ld_);
+      d32_ = a.take<float>(ld_);
+      diag32_ = a.take<float>(ld_);
+      if (S_.var) {
+        fx32_ = a.take<float>(ld_);
+        fy32_ = a.take<float>(ld_);
+        fz32_ = S_.dim == 3 ? a.take<float>(ld_) : nullptr;
+      }
+    }
     ctrl_ = a.take<Ctrl>(1);
     idx_dev_ = a.take<int64_t>(n_rhs_);
     scale_dev_ = a.take<double>(n_rhs_);
@@ -315,6 +337,15 @@ class Sequencer {
     ROM_HIP(hipMemsetAsync(Gi_, 0, sizeof(double) * ldg_ * cap_, st));
     ROM_HIP(hipMemsetAsync(Lc_, 0, sizeof(double) * ldg_ * cap_, st));
     ROM_HIP(hipMemsetAsync(Lr_, 0, sizeof(double) * ldg_ * cap_, st));
+    if (mixed_ && S_.var) {
+      // FP32 face coefficients for the FP32 stencil of the mixed form
+      launch_cast_f32(n_, op_->fx, fx32_, st);
+      launch_cast_f32(n_, op_->fy, fy32_, st);
+      if (S_.dim == 3) launch_cast_f32(n_, op_->fz, fz32_, st);
+      S_.fx32 = fx32_;
+      S_.fy32 = fy32_;
+      S_.fz32 = fz32_;
+    }
     sync();
 
     m_ = 0;
@@ -329,6 +360,7 @@ class Sequencer {
     for (int i = 0; i < K_; ++i) {
       mu0_ = params[i].mu0;
       launch_mu_eval(S_, make_bumps(params[i], S_.dim), op_->diag_star, diag_i_, dmu_, st);
+      if (mixed_) launch_cast_f32(n_, diag_i_, diag32_, st);
       if (i == 0) {
         // V <- orth(U_0): CGS2 append of every column (Alg. 2 initialisation)
         for (int c = 0; c < ku_in_; ++c) {
@@ -380,23 +412,21 @@ class Sequencer {
         ++n_solved;
         rec.solved = 1;
         const int nj = make_W(i, j);
-        int flag = 0;
-        int its = cg_solve(r_, g_, nj, tol_ * nb, maxit_, flag);
-        launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
-        launch_resid_unit(S_, diag_i_, xdst, idx, sc, r2_, &ctrl_->sc[3], red_part_, st);
-        account_spmv(ROM_K_OTHER);
-        sync();
-        double res = std::sqrt(h_->sc[3]) / nb;
-        int restarts = 0;
-        while (res > tol_ && its < maxit_ && flag == 0) {
-          ++restarts;
-          its += cg_solve(r2_, d_, nj, tol_ * nb, maxit_ - its, flag);
-          launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st);
+        int flag = 0, its = 0, restarts = 0;
+        double res = rho0;
+        if (!mixed_) {
+          its = cg_solve<double>(r_, 1.0, g_, nj, tol_ * nb, maxit_, flag);
           launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
-          launch_resid_unit(S_, diag_i_, xdst, idx, sc, r2_, &ctrl_->sc[3], red_part_, st);
-          account_spmv(ROM_K_OTHER);
-          sync();
-          res = std::sqrt(h_->sc[3]) / nb;
+          res = true_residual(xdst, idx, sc, nb);
+          while (res > tol_ && its < maxit_ && flag == 0 && restarts < MAX_SWEEPS) {
+            ++restarts;
+            its += cg_solve<double>(r2_, 1.0, d_, nj, tol_ * nb, maxit_ - its, flag);
+            launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st);
+            launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
+            res = true_residual(xdst, idx, sc, nb);
+          }
+        } else {
+          its = refine(xdst, idx, sc, nb, nj, rec, res, restarts, flag);
         }
         if (flag == 1) throw Error(ROM_ENOTSPD, "CG met non-positive curvature (operator not SPD)");
         if (flag == 2) throw Error(ROM_ENONFINITE, "non-finite value in CG");
@@ -666,11 +696,86 @@ class Sequencer {
                 gram_part_, st_);
     tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
     launch_small_chol_inv(GW_, nj, LWinv_, GWinv_, &ctrl_->status[1], st_);
+    if (mixed_) {
+      launch_cast_cols_f32(n_, nj, Wp_, ld_, W32_, st_);
+      launch_cast_cols_f32(n_, nj, AWp_, ld_, AW32_, st_);
+    }
     return nj;
   }
 
-  // Deflated CG on A_i d = rhs with the packed U_j; returns iterations.
-  int cg_solve(const double* rhs, double* dvec, int nj, double tol_abs, int maxit, int& flag) {
+  // r2 = b - A x in FP64 (b = sc e_idx); returns ||r2|| / nb.
+  double true_residual(const double* x, int64_t idx, double sc, double nb) {
+    launch_resid_unit(S_, diag_i_, x, idx, sc, r2_, &ctrl_->sc[3], red_part_, st_);
+    account_spmv(ROM_K_OTHER);
+    sync();
+    return std::sqrt(h_->sc[3]) / nb;
+  }
+
+  // Mixed form: FP64 iterative refinement around FP32 deflated-CG sweeps.  On entry
+  // r_ = b - A x0 with relative norm res; on exit x = x0 + g meets tol (or maxit).
+  // Each FP32 sweep solves A d = r / ||r|| to the relative tolerance
+  // max(inner_tol, tol / (2 res), FP32_GOAL_MIN), with at most a quarter of the
+  // remaining iteration budget (at least 64), and is followed by g += ||r|| d and the
+  // FP64 residual.  A sweep that breaks down or fails to halve the residual hands the
+  // solve to the FP64 solver for its remaining sweeps.
+  int refine(double* x, int64_t idx, double sc, double nb, int nj, rom_record& rec, double& res,
+             int& restarts, int& flag) {
+    ROM_HIP(hipMemsetAsync(g_, 0, sizeof(double) * n_, st_));
+    const double* rcur = r_;
+    bool fp32 = true;
+    int its = 0;
+    for (;;) {
+      const double rn = res * nb;
+      if (fp32) {
+        const double goal =
+            std::min(0.5, std::max(std::max(inner_tol_, FP32_GOAL_MIN), 0.5 * tol_ / res));
+        const int budget = std::min(maxit_ - its, std::max(64, (maxit_ - its) / 4));
+        int f32 = 0;
+        its += cg_solve<float>(rcur, 1.0 / rn, d32_, nj, goal, budget, f32);
+        if (f32 != 0) {
+          fp32 = false;   // FP32 breakdown: keep g, go on in FP64
+          if (its < maxit_) continue;
+          launch_axpby(n_, 1.0, x0_, 1.0, g_, x, nullptr, red_part_, st_);
+          break;
+        }
+        launch_refine_update(n_, rn, d32_, g_, x0_, x, st_);
+      } else {
+        ++rec.fp64_sweeps;
+        its += cg_solve<double>(rcur, 1.0, d_, nj, tol_ * nb, maxit_ - its, flag);
+        launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st_);
+        launch_axpby(n_, 1.0, x0_, 1.0, g_, x, &ctrl_->sc[6], red_part_, st_);
+      }
+      const double prev = res;
+      res = true_residual(x, idx, sc, nb);
+      if (res <= tol_ || its >= maxit_ || flag != 0 || restarts >= MAX_SWEEPS) break;
+      ++restarts;
+      if (fp32 && !(res <= 0.5 * prev)) fp32 = false;
+      rcur = r2_;
+    }
+    return its;
+  }
+
+  struct CgBufs32 {
+    const float *W, *AW, *diag;
+    float *s, *p, *w, *part1, *part2;
+  };
+  struct CgBufs64 {
+    const double *W, *AW, *diag;
+    double *s, *p, *w, *part1, *part2;
+  };
+  void bufs(CgBufs64& b) const { b = {Wp_, AWp_, diag_i_, s_, p_, w_, part1_, part2_}; }
+  void bufs(CgBufs32& b) const {
+    b = {W32_, AW32_, diag32_, s32_, p32_, w32_, reinterpret_cast<float*>(part1_),
+         reinterpret_cast<float*>(part2_)};
+  }
+
+  // Deflated CG on A_i d = rscale * rhs with the packed U_j, in arithmetic T (the
+  // right-hand side is FP64); stops at ||s|| <= tol_abs.  Returns iterations.
+  template <typename T>
+  int cg_solve(const double* rhs, double rscale, T* dvec, int nj, double tol_abs, int maxit,
+               int& flag) {
+    typename std::conditional<std::is_same<T, float>::value, CgBufs32, CgBufs64>::type b;
+    bufs(b);
     CGState* cg = &ctrl_->cg;
     const StencilShape sh = stencil_shape(S_, 1024);
     launch_cg_setup(cg, tol_abs * tol_abs, maxit, st_);
@@ -679,15 +784,16 @@ class Sequencer {
       launch_gemvt(Wp_, ld_, n_, nj, rhs, 0, 1, cg->t, gt_part_, st_);
       tm_->end(ROM_K_GEMVT, 8.0 * n_ * (nj + 1), 2.0 * n_ * nj);
     }
-    launch_dcg_start(Wp_, AWp_, ld_, n_, nj, GWinv_, rhs, dvec, s_, cg, part2_, st_);
+    const double E = sizeof(T);
+    launch_dcg_start<T>(b.W, b.AW, ld_, n_, nj, GWinv_, rhs, rscale, dvec, b.s, cg, b.part2, st_);
     tm_->begin(ROM_K_DCG_DIR);
-    launch_dcg_dir(Wp_, ld_, n_, nj, GWinv_, s_, p_, -1, cg, part2_, st_);
-    tm_->end(ROM_K_DCG_DIR, 8.0 * n_ * (2 + nj), n_ * (1.0 + 2.0 * nj));
-    const double by_apply = 8.0 * n_ * (3 + (S_.var ? S_.dim : 0));
+    launch_dcg_dir<T>(b.W, ld_, n_, nj, GWinv_, b.s, b.p, -1, cg, b.part2, st_);
+    tm_->end(ROM_K_DCG_DIR, E * n_ * (2 + nj), n_ * (1.0 + 2.0 * nj));
+    const double by_apply = E * n_ * (3 + (S_.var ? S_.dim : 0));
     const double fl_apply = 15.0 * n_;
-    const double by_upd = 8.0 * n_ * (6 + nj);
+    const double by_upd = E * n_ * (6 + nj);
     const double fl_upd = n_ * (6.0 + 2.0 * nj);
-    const double by_dir = 8.0 * n_ * (3 + nj);
+    const double by_dir = E * n_ * (3 + nj);
     const double fl_dir = n_ * (3.0 + 2.0 * nj);
     int next = chunk_;
     int its_before = 0;
@@ -696,13 +802,14 @@ class Sequencer {
       for (int c = 0; c < next; ++c) {
         const int k = its_before + c;
         tm_->begin(ROM_K_SPMV);
-        launch_dcg_apply(S_, sh, diag_i_, p_, w_, cg, part1_, st_);
+        launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, cg, b.part1, st_);
         tm_->end(ROM_K_SPMV, by_apply, fl_apply);
         tm_->begin(ROM_K_DCG_UPDATE);
-        launch_dcg_update(AWp_, ld_, n_, nj, p_, w_, dvec, s_, k, cg, part1_, sh.blocks, part2_, st_);
+        launch_dcg_update<T>(b.AW, ld_, n_, nj, b.p, b.w, dvec, b.s, k, cg, b.part1, sh.blocks,
+                             b.part2, st_);
         tm_->end(ROM_K_DCG_UPDATE, by_upd, fl_upd);
         tm_->begin(ROM_K_DCG_DIR);
-        launch_dcg_dir(Wp_, ld_, n_, nj, GWinv_, s_, p_, k, cg, part2_, st_);
+        launch_dcg_dir<T>(b.W, ld_, n_, nj, GWinv_, b.s, b.p, k, cg, b.part2, st_);
         tm_->end(ROM_K_DCG_DIR, by_dir, fl_dir);
       }
       ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
@@ -741,6 +848,8 @@ class Sequencer {
   int cap_, ldg_, pool_cap_;
   double tol_, trunc_;
   int maxit_, chunk_;
+  bool mixed_ = false;
+  double inner_tol_ = 1e-5;
   hipStream_t st_ = nullptr;
   Timer* tm_ = nullptr;
   Ctrl* h_ = nullptr;
@@ -756,6 +865,10 @@ class Sequencer {
   double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_, *lwork_;
   Ctrl* ctrl_;
   double *part1_, *part2_;
+  // mixed form: FP32 copies of U_j, A U_j, the diagonal and the face coefficients, and the
+  // FP32 CG vectors
+  float *W32_ = nullptr, *AW32_ = nullptr, *s32_ = nullptr, *p32_ = nullptr, *w32_ = nullptr;
+  float *d32_ = nullptr, *diag32_ = nullptr, *fx32_ = nullptr, *fy32_ = nullptr, *fz32_ = nullptr;
   int64_t* idx_dev_;
   double* scale_dev_;
 };
@@ -771,6 +884,9 @@ void check_opts(const rom_opts* o) {
   if (!(o->trunc >= 0) || !std::isfinite(o->trunc)) throw Error(ROM_EINVAL, "trunc must be >= 0");
   if (o->cap < 0 || o->cap > 4096) throw Error(ROM_EINVAL, "cap must be in [0, 4096]");
   if (o->maxit < 0 || o->check_every < 0) throw Error(ROM_EINVAL, "maxit/check_every must be >= 0");
+  if (o->precision != ROM_PREC_FP64 && o->precision != ROM_PREC_MIXED)
+    throw Error(ROM_EINVAL, "precision must be ROM_PREC_FP64 or ROM_PREC_MIXED");
+  if (!(o->inner_tol >= 0) || !(o->inner_tol < 1)) throw Error(ROM_EINVAL, "inner_tol must be in [0, 1)");
 }
 
 void check_counts(int n_src, int n_det, int k_u, int K) {

@@ -83,19 +83,31 @@ __global__ void k_mu_eval(Stencil S, Bumps B, const double* __restrict__ diag_st
   if (diag_i) diag_i[i] = diag_star[i] + B.mu0 + m;
 }
 
+template <typename T>
+struct Faces {
+  const T *fx, *fy, *fz;
+};
+__device__ __forceinline__ Faces<double> faces(const Stencil& S, double) {
+  return {S.fx, S.fy, S.fz};
+}
+__device__ __forceinline__ Faces<float> faces(const Stencil& S, float) {
+  return {S.fx32, S.fy32, S.fz32};
+}
+
 // MODE 0: y = A x.  MODE 1: y = A x, partial x^T y (CG step; exits if cg->done).
 // MODE 2: y = b - A x with b = bscale e_bidx, partial y^T y.
-// blockIdx.z selects a column (x + z*ldx, y + z*ldy).
-template <bool VAR, int MODE>
-__global__ __launch_bounds__(BS) void k_stencil(Stencil S, const double* __restrict__ diag,
-                                                 const double* __restrict__ x0, int64_t ldx,
-                                                 double* __restrict__ y0, int64_t ldy, int zc,
+// blockIdx.z selects a column (x + z*ldx, y + z*ldy).  T is the arithmetic type.
+template <typename T, bool VAR, int MODE>
+__global__ __launch_bounds__(BS) void k_stencil(Stencil S, const T* __restrict__ diag,
+                                                 const T* __restrict__ x0, int64_t ldx,
+                                                 T* __restrict__ y0, int64_t ldy, int zc,
                                                  int64_t bidx, double bscale,
-                                                 double* __restrict__ partials,
-                                                 const CGState* cg) {
+                                                 T* __restrict__ partials, const CGState* cg) {
   if (MODE == 1 && cg->done) return;
-  const double* __restrict__ x = x0 + (int64_t)blockIdx.z * ldx;
-  double* __restrict__ y = y0 + (int64_t)blockIdx.z * ldy;
+  const T* __restrict__ x = x0 + (int64_t)blockIdx.z * ldx;
+  T* __restrict__ y = y0 + (int64_t)blockIdx.z * ldy;
+  const Faces<T> F = faces(S, T(0));
+  const T cx = (T)S.cx, cy = (T)S.cy, cz = (T)S.cz;
   const int nxy = S.nx * S.ny;
   const int q = blockIdx.x * BS + threadIdx.x;
   const bool active = q < nxy;
@@ -103,35 +115,35 @@ __global__ __launch_bounds__(BS) void k_stencil(Stencil S, const double* __restr
   const int iy = active ? q / S.nx : 0;
   const int z0 = blockIdx.y * zc;
   const int z1 = min(z0 + zc, S.nz);
-  double acc[1] = {0.0};
+  T acc[1] = {T(0)};
   if (active && z0 < z1) {
     const bool hl = ix > 0, hr = ix < S.nx - 1, hd = iy > 0, hu = iy < S.ny - 1;
     int64_t i = (int64_t)z0 * nxy + q;
-    double xm = z0 > 0 ? x[i - nxy] : 0.0;
-    double fm = 0.0;
-    if (VAR && z0 > 0) fm = S.fz[i - nxy];
-    double xc = x[i];
+    T xm = z0 > 0 ? x[i - nxy] : T(0);
+    T fm = T(0);
+    if (VAR && z0 > 0) fm = F.fz[i - nxy];
+    T xc = x[i];
     for (int z = z0; z < z1; ++z, i += nxy) {
-      const double xp = z < S.nz - 1 ? x[i + nxy] : 0.0;
-      double v = diag[i] * xc;
+      const T xp = z < S.nz - 1 ? x[i + nxy] : T(0);
+      T v = diag[i] * xc;
       if (!VAR) {
-        const double sx = (hl ? x[i - 1] : 0.0) + (hr ? x[i + 1] : 0.0);
-        const double sy = (hd ? x[i - S.nx] : 0.0) + (hu ? x[i + S.nx] : 0.0);
-        v -= S.cx * sx + S.cy * sy + S.cz * (xm + xp);
+        const T sx = (hl ? x[i - 1] : T(0)) + (hr ? x[i + 1] : T(0));
+        const T sy = (hd ? x[i - S.nx] : T(0)) + (hu ? x[i + S.nx] : T(0));
+        v -= cx * sx + cy * sy + cz * (xm + xp);
       } else {
-        if (hl) v -= S.fx[i - 1] * x[i - 1];
-        if (hr) v -= S.fx[i] * x[i + 1];
-        if (hd) v -= S.fy[i - S.nx] * x[i - S.nx];
-        if (hu) v -= S.fy[i] * x[i + S.nx];
+        if (hl) v -= F.fx[i - 1] * x[i - 1];
+        if (hr) v -= F.fx[i] * x[i + 1];
+        if (hd) v -= F.fy[i - S.nx] * x[i - S.nx];
+        if (hu) v -= F.fy[i] * x[i + S.nx];
         if (S.dim == 3) {
-          const double fp = S.fz[i];
+          const T fp = F.fz[i];
           v -= fm * xm + fp * xp;
           fm = fp;
         }
       }
       if (MODE == 2) {
         v = -v;
-        if (i == bidx) v += bscale;
+        if (i == bidx) v += (T)bscale;
         acc[0] += v * v;
       } else if (MODE == 1) {
         acc[0] += xc * v;
@@ -184,19 +196,19 @@ void launch_mu_eval(const Stencil& S, const Bumps& bumps, const double* diag_sta
   ROM_CHECK_LAUNCH();
 }
 
-#define STENCIL_LAUNCH(MODE, grid, ...)                                                        \
+#define STENCIL_LAUNCH(T, MODE, grid, ...)                                                     \
   do {                                                                                         \
     if (S.var)                                                                                 \
-      ROM_LAUNCH((k_stencil<true, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);      \
+      ROM_LAUNCH((k_stencil<T, true, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);           \
     else                                                                                       \
-      ROM_LAUNCH((k_stencil<false, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);     \
-    ROM_CHECK_LAUNCH();                                                                        \
+      ROM_LAUNCH((k_stencil<T, false, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);          \
   } while (0)
 
 void launch_spmv(const Stencil& S, const double* diag, const double* x, double* y,
                  hipStream_t st) {
   const StencilShape sh = stencil_shape(S, 1024);
-  STENCIL_LAUNCH(0, sh.grid, diag, x, 0, y, 0, sh.zc, (int64_t)-1, 0.0, nullptr, nullptr);
+  STENCIL_LAUNCH(double, 0, sh.grid, diag, x, 0, y, 0, sh.zc, (int64_t)-1, 0.0,
+                 (double*)nullptr, (const CGState*)nullptr);
 }
 
 void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t ld, int k,
@@ -205,22 +217,29 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
   StencilShape sh = stencil_shape(S, 512);
   dim3 grid = sh.grid;
   grid.z = k;
-  STENCIL_LAUNCH(0, grid, diag, X, ld, Y, ld, sh.zc, (int64_t)-1, 0.0, nullptr, nullptr);
+  STENCIL_LAUNCH(double, 0, grid, diag, X, ld, Y, ld, sh.zc, (int64_t)-1, 0.0, (double*)nullptr,
+                 (const CGState*)nullptr);
 }
 
 void launch_resid_unit(const Stencil& S, const double* diag, const double* x, int64_t idx,
                        double scale, double* r, double* nrm2, double* partials,
                        hipStream_t st) {
   const StencilShape sh = stencil_shape(S, 512);
-  STENCIL_LAUNCH(2, sh.grid, diag, x, 0, r, 0, sh.zc, idx, scale, partials, nullptr);
+  STENCIL_LAUNCH(double, 2, sh.grid, diag, x, 0, r, 0, sh.zc, idx, scale, partials,
+                 (const CGState*)nullptr);
   launch_reduce_finish(partials, sh.blocks, 1, nrm2, st);
 }
 
-void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const double* diag,
-                      const double* p, double* w, CGState* cg, double* partials,
-                      hipStream_t st) {
-  STENCIL_LAUNCH(1, sh.grid, diag, p, 0, w, 0, sh.zc, (int64_t)-1, 0.0, partials, cg);
+template <typename T>
+void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
+                      CGState* cg, T* partials, hipStream_t st) {
+  STENCIL_LAUNCH(T, 1, sh.grid, diag, p, 0, w, 0, sh.zc, (int64_t)-1, 0.0, partials,
+                 (const CGState*)cg);
 }
+template void launch_dcg_apply<double>(const Stencil&, const StencilShape&, const double*,
+                                       const double*, double*, CGState*, double*, hipStream_t);
+template void launch_dcg_apply<float>(const Stencil&, const StencilShape&, const float*,
+                                      const float*, float*, CGState*, float*, hipStream_t);
 
 void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st,
                           Skip skip) {

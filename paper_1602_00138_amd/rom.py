@@ -27,6 +27,8 @@ ROM_ECAPACITY = -5
 ROM_EHIP = -6
 ROM_NJ_MAX = 64
 ROM_MAX_BUMPS = 64
+ROM_PREC_FP64 = 0
+ROM_PREC_MIXED = 1
 
 (ROM_K_SPMV, ROM_K_DCG_UPDATE, ROM_K_DCG_DIR, ROM_K_GEMVT, ROM_K_GEMVN, ROM_K_GRAM, ROM_K_OUTER,
  ROM_K_OTHER) = range(8)
@@ -49,15 +51,16 @@ class rom_mu(C.Structure):
 
 
 class rom_opts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("cap", C.c_int), ("maxit", C.c_int),
-                ("check_every", C.c_int), ("timing", C.c_int)]
+    _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("inner_tol", C.c_double),
+                ("cap", C.c_int), ("maxit", C.c_int), ("check_every", C.c_int), ("timing", C.c_int),
+                ("precision", C.c_int)]
 
 
 class rom_record(C.Structure):
     _fields_ = [("point", C.c_int), ("rhs", C.c_int), ("rho0", C.c_double), ("its", C.c_int),
                 ("solved", C.c_int), ("kept", C.c_int), ("rho", C.c_double),
                 ("final_res", C.c_double), ("m", C.c_int), ("restarts", C.c_int),
-                ("converged", C.c_int), ("pad", C.c_int)]
+                ("converged", C.c_int), ("fp64_sweeps", C.c_int)]
 
 
 class rom_stats(C.Structure):
@@ -145,8 +148,10 @@ def make_grid(dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float) -> 
 
 
 def make_opts(tol: float, trunc: float = 1e-8, cap: int = 0, maxit: int = 0,
-              check_every: int = 0, timing: int = 0) -> rom_opts:
-    return rom_opts(float(tol), float(trunc), int(cap), int(maxit), int(check_every), int(timing))
+              check_every: int = 0, timing: int = 0, precision: int = ROM_PREC_FP64,
+              inner_tol: float = 0.0) -> rom_opts:
+    return rom_opts(float(tol), float(trunc), float(inner_tol), int(cap), int(maxit),
+                    int(check_every), int(timing), int(precision))
 
 
 @dataclass
@@ -214,7 +219,7 @@ def rom_solve_sequence(op: int, params: List[MuParams], src_idx, src_scale, det_
         workspace.numel() * workspace.element_size(), C.byref(basis), _ptr(X_out), recs,
         C.byref(st), _stream(stream))
     _check(status, allow=(ROM_ENOCONV,))
-    records = [{f: getattr(r, f) for f, _ in rom_record._fields_ if f != "pad"} for r in recs]
+    records = [{f: getattr(r, f) for f, _ in rom_record._fields_} for r in recs]
     return status, basis.value, records, st
 
 

@@ -170,3 +170,23 @@ def test_deflated_cg_catches_missing_projection():
         p = s + gn / gam * p
         gam = gn
     assert np.abs(W.T @ s).max() > 1e-6 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("wl", [ph.small(3, (12, 11, 10), n_src=2, n_det=2),
+                                ph.small(3, (9, 10, 8), n_src=2, n_det=2, D="lognormal")])
+def test_full_solve_matches_direct(wl):
+    """The large-grid reference solve reaches the sparse LU solution to its tolerance:
+    ||x - x_LU|| <= ||A^{-1}|| ||b - A x|| <= tol ||b|| / lambda_min."""
+    from oracle import rom as orom
+    As = op.assemble_Astar(wl.dim, wl.N, wl.bc, ph.diffusion_field(wl), wl.robin_A)
+    p = ph.parameter_points(wl)[1]
+    A = op.assemble_A(As, op.mu_field(wl.dim, wl.N, p.mu0, p.centers, p.radii, p.amps))
+    lam = spla.eigsh(A, k=1, which="SA", return_eigenvectors=False)[0]
+    rng = np.random.default_rng(5)
+    for tol in (1e-6, 1e-12):
+        b = np.zeros(wl.n)
+        b[rng.integers(wl.n)] = 1.0
+        x = orom.full_solve(A, b, tol)
+        assert np.linalg.norm(b - A @ x) <= tol
+        x_lu = spla.splu(sp.csc_matrix(A)).solve(b)
+        assert np.linalg.norm(x - x_lu) <= 1.01 * tol / lam + 1e-15

@@ -25,6 +25,11 @@ uses CG with A-orthogonal projections):
   * U_j is stored orthonormal (U_0 part = the first columns of Q; each added
     column CGS2-orthogonalised against U_j); a correction joins U_j only if it
     joined V, so range(U_j) stays inside range(V).
+  * group g (the batched form; g = 1 is the paper's order): the right-hand sides of
+    a point are taken in consecutive groups of g.  Every member of a group is
+    projected on the basis as it stands at the start of the group and solved
+    without the other members' corrections; the group's corrections are then
+    appended one by one in right-hand-side order, each exactly as for g = 1.
 """
 from __future__ import annotations
 
@@ -61,10 +66,31 @@ class SequenceResult:
     k_u: int
 
 
+def _inner_solve(A, b, nb, x0, r, Wj, tol, maxit):
+    """Deflated CG on A g = r with W = U_j, restarted from the true residual until
+    ||b - A (x0 + g)|| <= tol ||b|| or maxit iterations."""
+    AW = A @ Wj
+    res = deflated_cg(A, r, Wj, tol * nb, maxit, AW=AW)
+    g, its = res.g, res.its
+    x = x0 + g
+    rt = b - A @ x
+    restarts = 0
+    while np.linalg.norm(rt) > tol * nb and its < maxit and not res.breakdown:
+        res = deflated_cg(A, rt, Wj, tol * nb, maxit - its, AW=AW)
+        g = g + res.g
+        its += res.its
+        restarts += 1
+        x = x0 + g
+        rt = b - A @ x
+    return g, x, its, restarts, float(np.linalg.norm(rt)) / nb
+
+
 def solve_sequence(Astar: sp.csr_matrix, mus: List[np.ndarray], B: np.ndarray, U0: np.ndarray,
                    tol: float, trunc: float = 1e-8, cap: int = 0, maxit: Optional[int] = None,
-                   keep_X: bool = True) -> SequenceResult:
+                   keep_X: bool = True, group: int = 1) -> SequenceResult:
     n, n_rhs = B.shape
+    if group < 1:
+        raise ValueError("group must be >= 1")
     if maxit is None:
         maxit = n
     # V <- basis for range(U_0)
@@ -81,45 +107,45 @@ def solve_sequence(Astar: sp.csr_matrix, mus: List[np.ndarray], B: np.ndarray, U
         A = (Astar + sp.diags(mu)).tocsr()
         AQ = A @ Q
         Xi = np.zeros((n, n_rhs)) if keep_X or i == 0 else None
-        for j in range(n_rhs):
-            b = B[:, j]
-            nb = float(np.linalg.norm(b))
-            x0, r, _ = galerkin(Q, AQ, b)
-            rho0 = float(np.linalg.norm(r)) / nb
-            if rho0 <= tol:
-                rec = Record(i, j, rho0, 0, False, False, float("nan"), rho0, Q.shape[1])
-                x = x0
-            else:
-                Wj = np.column_stack([Q[:, :k_u]] + W_extra[j]) if (i > 0 and W_extra[j]) \
-                    else Q[:, :k_u]
-                AW = A @ Wj
-                res = deflated_cg(A, r, Wj, tol * nb, maxit, AW=AW)
-                g, its = res.g, res.its
-                x = x0 + g
-                rt = b - A @ x
-                restarts = 0
-                while np.linalg.norm(rt) > tol * nb and its < maxit and not res.breakdown:
-                    res = deflated_cg(A, rt, Wj, tol * nb, maxit - its, AW=AW)
-                    g = g + res.g
-                    its += res.its
-                    restarts += 1
-                    x = x0 + g
-                    rt = b - A @ x
-                final = float(np.linalg.norm(rt)) / nb
-                q, rho = cgs2_append(Q, g, trunc)
-                kept = q is not None and (cap == 0 or Q.shape[1] < cap)
-                if kept:
-                    Q = np.column_stack([Q, q])
-                    AQ = np.column_stack([AQ, A @ q])
-                    if i > 0:
-                        w, _ = cgs2_append(Wj, g, trunc)
-                        if w is not None:
-                            W_extra[j].append(w)
-                rec = Record(i, j, rho0, its, True, kept, rho, final, Q.shape[1], restarts,
-                             converged=final <= tol)
-            records.append(rec)
-            if Xi is not None:
-                Xi[:, j] = x
+        for j0 in range(0, n_rhs, group):
+            members = range(j0, min(j0 + group, n_rhs))
+            solved = {}
+            recs = {}
+            # projections and solves against the basis as it stands at the group start
+            for j in members:
+                b = B[:, j]
+                nb = float(np.linalg.norm(b))
+                x0, r, _ = galerkin(Q, AQ, b)
+                rho0 = float(np.linalg.norm(r)) / nb
+                if rho0 <= tol:
+                    recs[j] = Record(i, j, rho0, 0, False, False, float("nan"), rho0, Q.shape[1])
+                    x = x0
+                else:
+                    Wj = np.column_stack([Q[:, :k_u]] + W_extra[j]) if (i > 0 and W_extra[j]) \
+                        else Q[:, :k_u]
+                    g, x, its, restarts, final = _inner_solve(A, b, nb, x0, r, Wj, tol, maxit)
+                    solved[j] = (g, Wj)
+                    recs[j] = Record(i, j, rho0, its, True, False, float("nan"), final, 0,
+                                     restarts, converged=final <= tol)
+                if Xi is not None:
+                    Xi[:, j] = x
+            # the group's corrections join V (and U_j) in right-hand-side order
+            for j in members:
+                rec = recs[j]
+                if j in solved:
+                    g, Wj = solved[j]
+                    q, rho = cgs2_append(Q, g, trunc)
+                    kept = q is not None and (cap == 0 or Q.shape[1] < cap)
+                    if kept:
+                        Q = np.column_stack([Q, q])
+                        AQ = np.column_stack([AQ, A @ q])
+                        if i > 0:
+                            w, _ = cgs2_append(Wj, g, trunc)
+                            if w is not None:
+                                W_extra[j].append(w)
+                    rec.kept, rec.rho = kept, rho
+                rec.m = Q.shape[1]
+                records.append(rec)
         if i == 0:
             for j in range(n_rhs):
                 w, _ = cgs2_append(Q[:, :k_u], Xi[:, j], trunc)

@@ -153,3 +153,43 @@ def test_skip_when_in_basis():
     second = [r for r in res.records if r.point == 1]
     assert all(r.its == 0 and not r.solved for r in second)
     assert all(r.rho0 <= 1e-10 for r in second)
+
+
+@pytest.mark.parametrize("group", [3, 16])
+def test_grouped_sequence_invariants(cfg1, group):
+    """The batched reading (RHS in groups sharing one projection): every solution still
+    meets the dense Cholesky solution, the basis stays orthonormal and contains every
+    solution, so the reduced transfer function interpolates at every sample point."""
+    wl, As, mus, B, U0, res1 = cfg1
+    res = seq.solve_sequence(As, mus, B, U0, wl.tol, wl.trunc, group=group)
+    Q = res.Q
+    assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 1e-12
+    assert Q.shape[1] == res.k_u + sum(r.kept for r in res.records)
+    assert [(r.point, r.rhs) for r in res.records] == [(r.point, r.rhs) for r in res1.records]
+    ns = wl.n_src
+    for i, mu in enumerate(mus):
+        Ad = As.toarray() + np.diag(mu)
+        Xc = sla.cho_solve(sla.cho_factor(Ad), B)
+        err = np.linalg.norm(res.X[i] - Xc, axis=0) / np.linalg.norm(Xc, axis=0)
+        assert err.max() < 1e-7
+        assert np.linalg.norm(res.X[i] - Q @ (Q.T @ res.X[i])) <= 1e-9 * np.linalg.norm(res.X[i])
+        A = op.assemble_A(As, mu)
+        Ar, Br, Cr, _ = rom.reduced_matrices(Q, A, B[:, :ns], B[:, ns:])
+        psi = B[:, ns:].T @ Xc[:, :ns]
+        assert np.abs(rom.reduced_transfer(Ar, Br, Cr) - psi).max() <= 1e-9 * np.abs(psi).max()
+    # members of a group see the basis of the group start: with one group per point,
+    # every right-hand side at p_0 is projected on orth(U_0) alone
+    resall = seq.solve_sequence(As, mus[:1], B, U0, wl.tol, wl.trunc, group=B.shape[1])
+    A0 = op.assemble_A(As, mus[0])
+    U, _ = np.linalg.qr(U0)
+    for r in resall.records:
+        b = B[:, r.rhs]
+        c = np.linalg.solve(U.T @ (A0 @ U), U.T @ b)
+        assert abs(r.rho0 - np.linalg.norm(b - A0 @ (U @ c)) / np.linalg.norm(b)) <= 1e-12
+
+
+def test_group_one_is_the_sequential_order(cfg1):
+    wl, As, mus, B, U0, res1 = cfg1
+    res = seq.solve_sequence(As, mus[:2], B, U0, wl.tol, wl.trunc, group=1)
+    for a, b in zip(res.records, res1.records):
+        assert (a.point, a.rhs, a.its, a.kept, a.m) == (b.point, b.rhs, b.its, b.kept, b.m)

@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4, help="oracle sample RHS (0: skip)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="fp64: plain FP64 recycled CG; mixed: FP32 inner sweeps in FP64 refinement")
+    ap.add_argument("--group", type=int, default=1,
+                    help="right-hand sides per batch (1: the paper's order, up to 16)")
     ap.add_argument("--kernel", default="outer",
                     help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
                          "k_gemvn<false>; auto: the class with the most event time)")
@@ -125,7 +127,8 @@ def main():
 
     # caller-owned buffers, allocated once outside the timed region
     prec = R.ROM_PREC_MIXED if args.precision == "mixed" else R.ROM_PREC_FP64
-    opts_all = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=(1 << R.ROM_NK) - 1, precision=prec)
+    opts_all = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=(1 << R.ROM_NK) - 1, precision=prec,
+                           group=args.group)
     nbytes = R.rom_sequence_bytes(prob.op, prob.src_idx.size, prob.det_idx.size, prob.k_u, K, opts_all)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     X = torch.empty((K * n_rhs, prob.n), dtype=torch.float64, device=dev)
@@ -165,7 +168,7 @@ def main():
     if dom == "auto":
         dom = max((k for k in kern if k != "other"), key=lambda k: kern[k]["ms"])
     cls = R.KERNEL_CLASSES.index(dom)
-    opts = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=1 << cls, precision=prec)
+    opts = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=1 << cls, precision=prec, group=args.group)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -215,7 +218,9 @@ def main():
         "config": {"workload": f"{wl.name}: {'x'.join(map(str, wl.N[:wl.dim]))} grid, "
                                f"{wl.n_src}+{wl.n_det} RHS, {K} points ({args.mode}), tol {wl.tol}, "
                                + ("plain FP64 recycled CG" if prec == R.ROM_PREC_FP64 else
-                                  "FP32 inner recycled CG in FP64 refinement"),
+                                  "FP32 inner recycled CG in FP64 refinement")
+                               + (f", groups of {args.group} RHS" if args.group > 1 else ""),
+                   "group": args.group, "precision": args.precision,
                    "n": prob.n, "points": K, "rhs": n_rhs, "tol": wl.tol,
                    "basis_m": last["m"], "inner_its": last["total_its"],
                    "solved": last["n_solved"], "nonconverged": bad},

@@ -111,6 +111,9 @@ typedef struct {
   int timing;       /* bit mask over ROM_K_* classes: time every launch of those classes with
                        HIP events (0: no events; algorithmic bytes are always counted) */
   int precision;    /* ROM_PREC_FP64 or ROM_PREC_MIXED */
+  int group;        /* right-hand sides per batch, 1..16 (0: 1, the paper's order): the
+                       members of a group are projected on V as it stands at the group
+                       start, solved together, and appended in order afterwards */
 } rom_opts;
 
 /* One record per (point i, right-hand side j), in solve order. */

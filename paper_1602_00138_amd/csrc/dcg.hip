@@ -29,15 +29,20 @@ struct CgPrefetch {
 constexpr int CG_GRID = 256;
 constexpr int START_BS = 256;
 
-__global__ void k_cg_setup(CGState* cg, double tol2, int maxit) {
-  cg->tol2 = tol2;
-  cg->maxit = maxit;
-  cg->its = 0;
-  cg->done = 0;
-  cg->flag = 0;
-  cg->gamma[0] = 0.0;
-  cg->gamma[1] = 0.0;
-  cg->pw = 0.0;
+__global__ void k_cg_setup(CGState* cg, CgSetup su, int nb) {
+  const int y = threadIdx.x;
+  if (y >= nb) return;
+  CGState* c = cg + y;
+  c->tol2 = su.tol2[y];
+  c->rscale = su.rscale[y];
+  c->maxit = su.maxit[y];
+  c->nj = su.nj[y];
+  c->its = 0;
+  c->done = su.active[y] ? 0 : 1;
+  c->flag = 0;
+  c->gamma[0] = 0.0;
+  c->gamma[1] = 0.0;
+  c->pw = 0.0;
 }
 
 // ys[j] = scale * sum_c Ginv[j + c nj] t[c] (Ginv = (U^T A U)^{-1}, symmetric, FP64),
@@ -59,12 +64,26 @@ __device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv, int 
 // read as rscale * r (the mixed form solves for a unit-norm residual in FP32).
 template <typename T, int NJT, int B = START_BS>
 __global__ __launch_bounds__(B) void k_dcg_start(const T* __restrict__ W,
-                                                  const T* __restrict__ AW, int64_t ld,
-                                                  int64_t n, int nj,
+                                                  const T* __restrict__ AW, int64_t wstride,
+                                                  int64_t ld, int64_t n,
                                                   const double* __restrict__ Ginv,
-                                                  const double* __restrict__ r, double rscale,
-                                                  T* __restrict__ g, T* __restrict__ s,
-                                                  const CGState* cg, T* __restrict__ part2) {
+                                                  int64_t gstride, const double* __restrict__ r,
+                                                  int64_t rstride, T* __restrict__ g,
+                                                  T* __restrict__ s, int64_t vstride,
+                                                  const CGState* cgs, T* __restrict__ part2,
+                                                  int64_t p2stride) {
+  const int y = blockIdx.y;
+  const CGState* cg = cgs + y;
+  if (cg->done) return;
+  W += y * wstride;
+  AW += y * wstride;
+  Ginv += y * gstride;
+  r += y * rstride;
+  g += y * vstride;
+  s += y * vstride;
+  part2 += y * p2stride;
+  const int nj = cg->nj;
+  const double rscale = cg->rscale;
   __shared__ T ys[NJ_MAX];
   gram_apply(Ginv, nj, cg->t, rscale, ys);
   const T rs = (T)rscale;
@@ -97,12 +116,22 @@ __global__ __launch_bounds__(B) void k_dcg_start(const T* __restrict__ W,
 // the step, stop on convergence / maxit / non-finite values; else the new direction
 // p = s + beta p - U G^{-1} (AU)^T s.  iter = -1 for the direction after the start.
 template <typename T, int NJT, int B = CgBlock<T, NJT>::value>
-__global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t ld, int64_t n,
-                                                int nj, const double* __restrict__ Ginv,
+__global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t wstride,
+                                                int64_t ld, int64_t n,
+                                                const double* __restrict__ Ginv, int64_t gstride,
                                                 const T* __restrict__ s, T* __restrict__ p,
-                                                int iter, CGState* cg,
-                                                const T* __restrict__ part2, int P2) {
+                                                int64_t vstride, int iter, CGState* cgs,
+                                                const T* __restrict__ part2, int64_t p2stride,
+                                                int P2) {
+  const int y = blockIdx.y;
+  CGState* cg = cgs + y;
   if (cg->done) return;
+  W += y * wstride;
+  Ginv += y * gstride;
+  s += y * vstride;
+  p += y * vstride;
+  part2 += y * p2stride;
+  const int nj = cg->nj;
   const bool first = iter < 0;
   // first row of this thread, loaded ahead of the reduction
   constexpr bool PF = CgPrefetch<T, NJT>::value;
@@ -157,13 +186,25 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t 
 
 // alpha = s^T s / p^T A p; g += alpha p; s -= alpha w; partials of (AU)^T s and s^T s.
 template <typename T, int NJT, int B = CgBlock<T, NJT>::value>
-__global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int64_t ld,
-                                                   int64_t n, int nj, const T* __restrict__ p,
+__global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int64_t wstride,
+                                                   int64_t ld, int64_t n,
+                                                   const T* __restrict__ p,
                                                    const T* __restrict__ w, T* __restrict__ g,
-                                                   T* __restrict__ s, int iter, CGState* cg,
-                                                   const T* __restrict__ part1, int P1,
-                                                   T* __restrict__ part2) {
+                                                   T* __restrict__ s, int64_t vstride, int iter,
+                                                   CGState* cgs, const T* __restrict__ part1,
+                                                   int P1, int64_t p1stride,
+                                                   T* __restrict__ part2, int64_t p2stride) {
+  const int y = blockIdx.y;
+  CGState* cg = cgs + y;
   if (cg->done) return;
+  AW += y * wstride;
+  p += y * vstride;
+  w += y * vstride;
+  g += y * vstride;
+  s += y * vstride;
+  part1 += y * p1stride;
+  part2 += y * p2stride;
+  const int nj = cg->nj;
   constexpr bool PF = CgPrefetch<T, NJT>::value;
   const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
   T a0[PF ? NJT : 1], p0 = T(0), w0 = T(0), g0 = T(0), s0 = T(0);
@@ -223,18 +264,20 @@ int dcg_blocks(int64_t n) {
   return b < CG_GRID ? (b < 1 ? 1 : b) : CG_GRID;
 }
 
-void launch_cg_setup(CGState* cg, double tol2, int maxit, hipStream_t st) {
-  ROM_LAUNCH(k_cg_setup, dim3(1), dim3(1), 0, st, cg, tol2, maxit);
+void launch_cg_setup(CGState* cg, const CgSetup& su, int nb, hipStream_t st) {
+  if (nb < 1 || nb > G_MAX) throw Error(ROM_EINVAL, "cg_setup: batch size out of range");
+  ROM_LAUNCH(k_cg_setup, dim3(1), dim3(64), 0, st, cg, su, nb);
   ROM_CHECK_LAUNCH();
 }
 
 template <typename T>
-void launch_dcg_start(const T* W, const T* AW, int64_t ld, int64_t n, int nj, const double* Ginv,
-                      const double* r, double rscale, T* g, T* s, const CGState* cg, T* part2,
+void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax,
+                      const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
+                      T* s, int64_t vstride, const CGState* cg, T* part2, int64_t p2stride, int nb,
                       hipStream_t st) {
-  const dim3 grid(dcg_blocks(n));
-  switch (njt_of(nj)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, ld, n, nj, Ginv, r, rscale, g, s, cg, part2); break;
+  const dim3 grid(dcg_blocks(n), nb);
+  switch (njt_of(njmax)) {
+#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, wstride, ld, n, Ginv, gstride, r, rstride, g, s, vstride, cg, part2, p2stride); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -242,12 +285,14 @@ void launch_dcg_start(const T* W, const T* AW, int64_t ld, int64_t n, int nj, co
 }
 
 template <typename T>
-void launch_dcg_dir(const T* W, int64_t ld, int64_t n, int nj, const double* Ginv, const T* s,
-                    T* p, int iter, CGState* cg, const T* part2, hipStream_t st) {
-  const dim3 grid(dcg_blocks(n));
+void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
+                    const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
+                    int iter, CGState* cg, const T* part2, int64_t p2stride, int nb,
+                    hipStream_t st) {
+  const dim3 grid(dcg_blocks(n), nb);
   const int P2 = dcg_blocks(n);
-  switch (njt_of(nj)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, W, ld, n, nj, Ginv, s, p, iter, cg, part2, P2); break;
+  switch (njt_of(njmax)) {
+#define C(J) case J: ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, W, wstride, ld, n, Ginv, gstride, s, p, vstride, iter, cg, part2, p2stride, P2); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -255,12 +300,13 @@ void launch_dcg_dir(const T* W, int64_t ld, int64_t n, int nj, const double* Gin
 }
 
 template <typename T>
-void launch_dcg_update(const T* AW, int64_t ld, int64_t n, int nj, const T* p, const T* w, T* g,
-                       T* s, int iter, CGState* cg, const T* part1, int P1, T* part2,
-                       hipStream_t st) {
-  const dim3 grid(dcg_blocks(n));
-  switch (njt_of(nj)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, AW, ld, n, nj, p, w, g, s, iter, cg, part1, P1, part2); break;
+void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax, const T* p,
+                       const T* w, T* g, T* s, int64_t vstride, int iter, CGState* cg,
+                       const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
+                       int nb, hipStream_t st) {
+  const dim3 grid(dcg_blocks(n), nb);
+  switch (njt_of(njmax)) {
+#define C(J) case J: ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, AW, wstride, ld, n, p, w, g, s, vstride, iter, cg, part1, P1, p1stride, part2, p2stride); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -268,13 +314,15 @@ void launch_dcg_update(const T* AW, int64_t ld, int64_t n, int nj, const T* p, c
 }
 
 #define INSTANTIATE(T)                                                                          \
-  template void launch_dcg_start<T>(const T*, const T*, int64_t, int64_t, int, const double*,    \
-                                    const double*, double, T*, T*, const CGState*, T*,           \
-                                    hipStream_t);                                                \
-  template void launch_dcg_dir<T>(const T*, int64_t, int64_t, int, const double*, const T*, T*,  \
-                                  int, CGState*, const T*, hipStream_t);                         \
-  template void launch_dcg_update<T>(const T*, int64_t, int64_t, int, const T*, const T*, T*, T*, \
-                                     int, CGState*, const T*, int, T*, hipStream_t);
+  template void launch_dcg_start<T>(const T*, const T*, int64_t, int64_t, int64_t, int,          \
+                                    const double*, int64_t, const double*, int64_t, T*, T*,      \
+                                    int64_t, const CGState*, T*, int64_t, int, hipStream_t);     \
+  template void launch_dcg_dir<T>(const T*, int64_t, int64_t, int64_t, int, const double*,       \
+                                  int64_t, const T*, T*, int64_t, int, CGState*, const T*,       \
+                                  int64_t, int, hipStream_t);                                    \
+  template void launch_dcg_update<T>(const T*, int64_t, int64_t, int64_t, int, const T*,         \
+                                     const T*, T*, T*, int64_t, int, CGState*, const T*, int,    \
+                                     int64_t, T*, int64_t, int, hipStream_t);
 INSTANTIATE(double)
 INSTANTIATE(float)
 #undef INSTANTIATE

@@ -134,6 +134,71 @@ __global__ __launch_bounds__(BS) void k_gemvn(const double* __restrict__ M, int6
   if (NRM) write_partials<1, BS>(nv, partials, blockIdx.x);
 }
 
+// Several coefficient vectors against one basis pass: each thread owns RPT rows and
+// NV accumulators per row; coefficients are staged through LDS in chunks of CCH columns.
+template <int NV, int RPT>
+__global__ __launch_bounds__(BS) void k_gemvn_multi(const double* __restrict__ M, int64_t ld,
+                                                     int64_t rows, int cols,
+                                                     const double* __restrict__ coef,
+                                                     int64_t ldc, int nv, double alpha,
+                                                     const double* __restrict__ in, int64_t ldi,
+                                                     double beta, double* __restrict__ out,
+                                                     int64_t ldo) {
+  constexpr int CCH = 128;
+  __shared__ double cs[CCH][NV];
+  const int64_t rbase = (int64_t)blockIdx.x * (BS * RPT) + threadIdx.x;
+  double acc[RPT][NV];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[q][v] = 0.0;
+  for (int c0 = 0; c0 < cols; c0 += CCH) {
+    const int cn = min(CCH, cols - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < CCH * NV; e += BS) {
+      const int c = e % CCH, v = e / CCH;
+      cs[c][v] = (c < cn && v < nv) ? coef[(int64_t)(c0 + c) + (int64_t)v * ldc] : 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < cn; ++c) {
+      const double* col = M + (int64_t)(c0 + c) * ld;
+      double mv[RPT];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int64_t r = rbase + (int64_t)q * BS;
+        mv[q] = r < rows ? col[r] : 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double cv = cs[c][v];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[q][v] += mv[q] * cv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int64_t r = rbase + (int64_t)q * BS;
+    if (r >= rows) continue;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (v < nv) {
+        const double o = beta * acc[q][v] + (in ? alpha * in[r + (int64_t)v * ldi] : 0.0);
+        out[r + (int64_t)v * ldo] = o;
+      }
+  }
+}
+
+__global__ void k_axpby_cols(int64_t n, double a, const double* __restrict__ x, int64_t ldx,
+                             double b, const double* __restrict__ y, int64_t ldy,
+                             double* __restrict__ out, int64_t ldo) {
+  const int v = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double yi = y ? y[i + v * ldy] : 0.0;
+    out[i + v * ldo] = a * x[i + v * ldx] + b * yi;
+  }
+}
+
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
                         const double* __restrict__ y, double* __restrict__ out, int want,
                         double* partials) {
@@ -173,6 +238,25 @@ __global__ void k_refine_update(int64_t n, double sigma, const float* __restrict
   }
 }
 
+// End of a refinement sweep for a batch: g[:, y] += coef.c[y] d[:, y] (d of type T),
+// x[:, y] = x0[:, y] + g[:, y] (blockIdx.y = y).
+template <typename T>
+__global__ void k_refine_cols(int64_t n, Coefs coef, const T* __restrict__ d, int64_t ldd,
+                              double* __restrict__ g, const double* __restrict__ x0, int64_t ld,
+                              double* __restrict__ x, int64_t ldx) {
+  const int y = blockIdx.y;
+  const double c = coef.c[y];
+  d += y * ldd;
+  g += y * ld;
+  x0 += y * ld;
+  x += y * ldx;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double gi = c != 0.0 ? g[i] + c * (double)d[i] : g[i];
+    g[i] = gi;
+    x[i] = x0[i] + gi;
+  }
+}
+
 __global__ void k_pack_cols(int64_t n, ColPtrs src, int k, double* __restrict__ dst, int64_t ld) {
   const int c = blockIdx.y;
   const double* s = src.p[c];
@@ -197,7 +281,7 @@ __global__ void k_gather_rows(const double* __restrict__ M, int64_t ld, int cols
 // Border step finalisation (one block): delta^2 = d - l^T l, new row of Linv.
 __global__ void k_linv_finish(double* Lc, double* Lr, int64_t ld, int k,
                               const double* __restrict__ gcol, const double* __restrict__ l,
-                              const double* __restrict__ r, int* status) {
+                              const double* __restrict__ r, int* status, double* info) {
   __shared__ double sh[BS / WAVE];
   double s = 0.0;
   for (int i = threadIdx.x; i < k; i += BS) s += l[i] * l[i];
@@ -218,7 +302,15 @@ __global__ void k_linv_finish(double* Lc, double* Lr, int64_t ld, int k,
   if (threadIdx.x == 0) {
     Lr[k + (int64_t)k * ld] = inv;
     Lc[k + (int64_t)k * ld] = inv;
-    if (bad) status[0] = 1;
+    if (bad && status[0] == 0) {
+      status[0] = 1;
+      // the first failing border: column, diagonal entry, squared norm of its projection
+      if (info) {
+        info[0] = k;
+        info[1] = gcol[k];
+        info[2] = ll;
+      }
+    }
   }
 }
 
@@ -517,6 +609,35 @@ void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const dou
   }
 }
 
+void launch_gemvn_multi(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
+                        int64_t ldc, int nv, double alpha, const double* in, int64_t ldi,
+                        double beta, double* out, int64_t ldo, hipStream_t st) {
+  if (nv <= 0 || rows <= 0) return;
+  if (nv > 16) throw Error(ROM_EINVAL, "gemvn_multi: at most 16 vectors");
+#define GM_LAUNCH(NV, RPT)                                                                   \
+  ROM_LAUNCH((k_gemvn_multi<NV, RPT>), dim3(ceil_div(rows, BS * RPT)), dim3(BS), 0, st, M, ld, \
+             rows, cols, coef, ldc, nv, alpha, in, ldi, beta, out, ldo)
+  if (nv <= 2)
+    GM_LAUNCH(2, 4);
+  else if (nv <= 4)
+    GM_LAUNCH(4, 4);
+  else if (nv <= 8)
+    GM_LAUNCH(8, 2);
+  else
+    GM_LAUNCH(16, 1);
+#undef GM_LAUNCH
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_axpby_cols(int64_t n, int nv, double a, const double* x, int64_t ldx, double b,
+                       const double* y, int64_t ldy, double* out, int64_t ldo, hipStream_t st) {
+  if (nv <= 0 || n <= 0) return;
+  int gx = ceil_div(n, BS);
+  if (gx > 512) gx = 512;
+  ROM_LAUNCH(k_axpby_cols, dim3(gx, nv), dim3(BS), 0, st, n, a, x, ldx, b, y, ldy, out, ldo);
+  ROM_CHECK_LAUNCH();
+}
+
 void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
                   double* nrm2, double* partials, hipStream_t st) {
   const int grid = reduce_grid(n);
@@ -551,6 +672,21 @@ void launch_refine_update(int64_t n, double sigma, const float* d, double* g, co
   ROM_CHECK_LAUNCH();
 }
 
+template <typename T>
+void launch_refine_cols(int64_t n, int nb, const Coefs& coef, const T* d, int64_t ldd, double* g,
+                        const double* x0, int64_t ld, double* x, int64_t ldx, hipStream_t st) {
+  if (n <= 0 || nb <= 0) return;
+  int gx = ceil_div(n, BS);
+  if (gx > 512) gx = 512;
+  ROM_LAUNCH((k_refine_cols<T>), dim3(gx, nb), dim3(BS), 0, st, n, coef, d, ldd, g, x0, ld, x, ldx);
+  ROM_CHECK_LAUNCH();
+}
+template void launch_refine_cols<double>(int64_t, int, const Coefs&, const double*, int64_t,
+                                         double*, const double*, int64_t, double*, int64_t,
+                                         hipStream_t);
+template void launch_refine_cols<float>(int64_t, int, const Coefs&, const float*, int64_t, double*,
+                                        const double*, int64_t, double*, int64_t, hipStream_t);
+
 void launch_pack_cols(int64_t n, const ColPtrs& src, int k, double* dst, int64_t ld,
                       hipStream_t st) {
   if (k <= 0) return;
@@ -579,7 +715,7 @@ void launch_gather_rows(const double* M, int64_t ld, int cols, const int64_t* id
 
 void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double* gcol,
                         double* tmp_l, double* tmp_r, int* status, double* partials,
-                        hipStream_t st) {
+                        hipStream_t st, double* info) {
   if (k > 0) {
     // l = Linv g: row i of Linv is column i of Lr.
     launch_gemvt(Lr, ld, k, k, gcol, 0, 1, tmp_l, partials, st);
@@ -587,7 +723,7 @@ void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double*
     launch_gemvt(Lc, ld, k, k, tmp_l, 0, 1, tmp_r, partials, st);
   }
   ROM_LAUNCH(k_linv_finish, dim3(1), dim3(BS), 0, st, Lc, Lr, ld, k, gcol, tmp_l, tmp_r,
-                     status);
+                     status, info);
   ROM_CHECK_LAUNCH();
 }
 

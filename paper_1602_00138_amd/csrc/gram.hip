@@ -137,6 +137,68 @@ __global__ void k_gram_finish(const double* __restrict__ partials, int nsplit, i
   C[i + j * ldc] = s;
 }
 
+// Projections onto a tall basis: partials[s][i + v*a] = sum over the rows of split s of
+// X[r, i] V[r, v] for v < nv <= 16 (a block of right-hand sides against the basis).
+// Each wave owns 16 columns of X and all 16 vector slots (one 16x16 MFMA tile); the
+// block stages KC rows of its 64 columns of X and of V through LDS.
+__global__ __launch_bounds__(BS) void k_proj(const double* __restrict__ X, int64_t ldx, int a,
+                                              const double* __restrict__ V, int64_t ldv, int nv,
+                                              int64_t rows, int64_t rows_per_split,
+                                              double* __restrict__ partials) {
+  __shared__ double Xs[KC][TT + PAD];
+  __shared__ double Vs[KC][16 + PAD];
+  const int x0 = blockIdx.x * TT;
+  const int64_t rbeg = (int64_t)blockIdx.y * rows_per_split;
+  int64_t rend = rbeg + rows_per_split;
+  if (rend > rows) rend = rows;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+  const int srow = threadIdx.x % KC;
+  const int scol = threadIdx.x / KC;   // 0..7
+  for (int64_t r0 = rbeg; r0 < rend; r0 += KC) {
+    const int64_t r = r0 + srow;
+    const bool in = r < rend;
+#pragma unroll
+    for (int q = 0; q < TT / (BS / KC); ++q) {
+      const int c = scol + (BS / KC) * q;
+      Xs[srow][c] = (in && x0 + c < a) ? X[r + (int64_t)(x0 + c) * ldx] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16 / (BS / KC); ++q) {
+      const int v = scol + (BS / KC) * q;
+      Vs[srow][v] = (in && v < nv) ? V[r + (int64_t)v * ldv] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double av = Xs[kr][wid * 16 + (lane & 15)];
+      const double bv = Vs[kr][lane & 15];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* P = partials + (int64_t)blockIdx.y * a * nv;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int xi = x0 + wid * 16 + (lane >> 4) + 4 * v;
+    const int vj = lane & 15;
+    if (xi < a && vj < nv) P[xi + (int64_t)vj * a] = acc[v];
+  }
+}
+
+void proj_shape(int a, int64_t rows, int& ntile, int& nsplit, int64_t& rps) {
+  ntile = (a + TT - 1) / TT;
+  nsplit = 2048 / (ntile > 0 ? ntile : 1);
+  if (nsplit < 1) nsplit = 1;
+  int64_t maxs = (rows + 8 * KC - 1) / (8 * KC);
+  if (nsplit > maxs) nsplit = (int)(maxs > 0 ? maxs : 1);
+  rps = (rows + nsplit - 1) / nsplit;
+  rps = (rps + KC - 1) / KC * KC;
+  nsplit = (int)((rows + rps - 1) / rps);
+  if (nsplit < 1) nsplit = 1;
+}
+
 void gram_shape(int a, int b, int64_t rows, bool sym, int& npairs, int& nsplit, int64_t& rps) {
   const int ta = (a + TT - 1) / TT, tb = (b + TT - 1) / TT;
   npairs = sym ? ta * (ta + 1) / 2 : ta * tb;
@@ -168,6 +230,39 @@ size_t gram_partials_max(int a, int b, int64_t rows, bool sym) {
     best = std::max(best, gram_partials(aa, bb, rows, sym));
   }
   return best;
+}
+
+size_t proj_partials(int a, int nv, int64_t rows) {
+  int nt, ns;
+  int64_t rps;
+  proj_shape(a, rows, nt, ns, rps);
+  return (size_t)ns * a * nv;
+}
+
+size_t proj_partials_max(int maxa, int nv, int64_t rows) {
+  size_t best = 0;
+  for (int t = 1; t <= (maxa + TT - 1) / TT; ++t)
+    best = std::max(best, proj_partials(std::min(maxa, t * TT), nv, rows));
+  return best;
+}
+
+void launch_proj(const double* X, int64_t ldx, int a, const double* V, int64_t ldv, int nv,
+                 int64_t rows, double* C, int64_t ldc, double* partials, hipStream_t st) {
+  if (a <= 0 || nv <= 0) return;
+  if (nv > 16) throw Error(ROM_EINVAL, "launch_proj: at most 16 vectors");
+  int nt, ns;
+  int64_t rps;
+  proj_shape(a, rows, nt, ns, rps);
+  ROM_LAUNCH(k_proj, dim3(nt, ns), dim3(BS), 0, st, X, ldx, a, V, ldv, nv, rows, rps, partials);
+  ROM_CHECK_LAUNCH();
+  const int64_t ne = (int64_t)a * nv;
+  if (ns >= 32)
+    ROM_LAUNCH(k_gram_finish<true>, dim3(ceil_div(ne, BS / WAVE)), dim3(BS), 0, st, partials, ns,
+               a, nv, 0, (const double*)nullptr, (int64_t)0, 0.0, C, ldc);
+  else
+    ROM_LAUNCH(k_gram_finish<false>, dim3(ceil_div(ne, BS)), dim3(BS), 0, st, partials, ns, a,
+               nv, 0, (const double*)nullptr, (int64_t)0, 0.0, C, ldc);
+  ROM_CHECK_LAUNCH();
 }
 
 void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b,

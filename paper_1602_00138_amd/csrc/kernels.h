@@ -6,15 +6,31 @@
 namespace rom {
 
 // CG scalar state shared by the deflated-CG kernels (device memory).
+// Scalar state of one deflated-CG solve (one per member of a batch of right-hand sides).
 struct CGState {
   double gamma[2];     // s^T s, double-buffered by step parity
   double pw;           // p^T A p of the latest direction
   double tol2;         // (tol * ||b||)^2
-  double t[NJ_MAX];    // U_j^T r for the start
+  double rscale;       // the right-hand side is read as rscale * r
+  double t[NJ_MAX];    // U_j^T r (unscaled) for the start
+  int nj;              // columns of U_j
   int its;             // iterations done
   int maxit;
-  int done;            // 1: stop (converged, maxit or breakdown)
+  int done;            // 1: stop (converged, maxit, breakdown, or inactive member)
   int flag;            // 0 ok, 1 non-positive curvature, 2 non-finite
+  int pad;
+};
+
+// Most right-hand sides solved together (members of one batch).
+constexpr int G_MAX = 16;
+
+// Per-member parameters of a batched CG start (members >= nb are ignored).
+struct CgSetup {
+  double tol2[G_MAX];
+  double rscale[G_MAX];
+  int maxit[G_MAX];
+  int nj[G_MAX];
+  int active[G_MAX];
 };
 
 // Launch shape of the stencil products: blocks of 256 plane nodes x zc planes.
@@ -51,6 +67,12 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
 void launch_resid_unit(const Stencil& S, const double* diag, const double* x, int64_t idx,
                        double scale, double* r, double* nrm2, double* partials,
                        hipStream_t st);
+// Columns z < nb at once: R[:, z] = scale[z] e_{idx[z]} - A X[:, z] (idx, scale on the
+// device) and nrm2[z * nstride] = ||R[:, z]||^2.  partials: >= nb * stencil_shape(S,
+// 512).blocks doubles.
+void launch_resid_cols(const Stencil& S, const double* diag, const double* X, int64_t ldx, int nb,
+                       const int64_t* idx, const double* scale, double* R, int64_t ldr,
+                       double* nrm2, int64_t nstride, double* partials, hipStream_t st);
 // out[r] = sum_b partials[b*R + r] for r < R (R = 1 or 2), one block, fixed order.
 void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st,
                           Skip skip = Skip());
@@ -69,6 +91,15 @@ void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const dou
 void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
                   double alpha, const double* in, double beta, double* out, double* nrm2,
                   double* partials, hipStream_t st, Skip skip = Skip());
+
+// Several right-hand sides at once: out[r + v*ldo] = alpha * in[r + v*ldi]
+//   + beta * sum_{c < cols} M[r + c*ld] coef[c + v*ldc], v < nv <= 16 (in may be NULL).
+void launch_gemvn_multi(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
+                        int64_t ldc, int nv, double alpha, const double* in, int64_t ldi,
+                        double beta, double* out, int64_t ldo, hipStream_t st);
+// out[r + v*ldo] = a x[r + v*ldx] + b y[r + v*ldy] for r < n, v < nv (y may be NULL).
+void launch_axpby_cols(int64_t n, int nv, double a, const double* x, int64_t ldx, double b,
+                       const double* y, int64_t ldy, double* out, int64_t ldo, hipStream_t st);
 
 // ---- vector helpers ---------------------------------------------------------------
 // out = a*x + b*y (y may be NULL); if nrm2: nrm2[0] = ||out||^2, nrm2[1] = ||y||^2.
@@ -96,6 +127,12 @@ void launch_gather_rows(const double* M, int64_t ld, int cols, const int64_t* id
 size_t gram_partials(int a, int b, int64_t rows, bool sym);
 // max of gram_partials over a' <= a (b' = a' when sym) -- the split count depends on a.
 size_t gram_partials_max(int a, int b, int64_t rows, bool sym);
+// C[i + v*ldc] = sum_r X[r + i*ldx] V[r + v*ldv] for i < a, v < nv <= 16 (MFMA).
+// partials: >= proj_partials(a, nv, rows) doubles.
+size_t proj_partials(int a, int nv, int64_t rows);
+size_t proj_partials_max(int maxa, int nv, int64_t rows);
+void launch_proj(const double* X, int64_t ldx, int a, const double* V, int64_t ldv, int nv,
+                 int64_t rows, double* C, int64_t ldc, double* partials, hipStream_t st);
 void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b,
                  int64_t rows, const double* w, bool sym, const double* base, int64_t ldb,
                  double shift, double* C, int64_t ldc, double* partials, hipStream_t st);
@@ -105,10 +142,10 @@ void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t l
 // (column-major, ld) and Lr (its transpose, column-major, ld).  Border step k: with
 // g = G[0:k, k] and d = G[k, k]: l = Linv g, delta^2 = d - l^T l,
 // Linv[k, 0:k] = -(Linv^T l)^T / delta, Linv[k, k] = 1/delta.  status[0] is set to 1
-// if delta^2 <= 0 (not SPD).
+// if delta^2 <= 0 (not SPD); the first such border also stores (k, d, l^T l) in info.
 void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double* gcol,
                         double* tmp_l, double* tmp_r, int* status, double* partials,
-                        hipStream_t st);
+                        hipStream_t st, double* info = nullptr);
 // Rebuild Linv (both layouts) from the m x m SPD matrix G in 64-column blocks: per block
 // L21 = G21 Linv11^T, S = G22 - L21 L21^T, Linv22 = chol(S)^{-1},
 // Linv21 = -Linv22 (L21 Linv11).  work: >= linv_rebuild_work(m) doubles.
@@ -143,28 +180,36 @@ void launch_dot2_scale(int64_t n, const double* x, const double* a, const double
                        hipStream_t st);
 
 // ---- deflated CG --------------------------------------------------------------------
-// T = double (plain form) or float (inner sweeps of the mixed form).  W, AW: n x nj
-// contiguous (ld), Ginv: nj x nj FP64 inverse of W^T A W.  part1: >= stencil_shape(S,
-// 1024).blocks values of T (p^T A p partials of the operator step); part2: >= (NJ_MAX +
-// 1) * dcg_blocks(n) values of T.  iter: 0-based step index (-1 for the direction after
-// the start).  The start reads the FP64 right-hand side as rscale * r, and U^T r from
-// cg->t (the caller stores the unscaled product there).
+// T = double (plain form) or float (inner sweeps of the mixed form).  A batch of nb
+// members (blockIdx.y) runs together; member y uses cg[y] (its nj, rscale, tol2, maxit),
+// W + y*wstride, AW + y*wstride and Ginv + y*gstride (strides 0: one recycle space for
+// every member), the FP64 right-hand side r + y*rstride (read as rscale * r) and its
+// CG vectors at + y*vstride.  W, AW: n x nj contiguous (ld); Ginv: nj x nj FP64 inverse
+// of W^T A W.  Partials (values of T): part1 >= stencil_shape(S, 1024).blocks per
+// member, part2 >= (NJ_MAX + 1) * dcg_blocks(n) per member, at strides p1stride,
+// p2stride.  iter: 0-based step index shared by the batch (-1 for the direction after
+// the start).  cg[y].t holds U_j^T r before the start.  Inactive members (done set at
+// setup) return at once from every kernel.
 int dcg_blocks(int64_t n);
-void launch_cg_setup(CGState* cg, double tol2, int maxit, hipStream_t st);
+void launch_cg_setup(CGState* cg, const CgSetup& su, int nb, hipStream_t st);
 template <typename T>
-void launch_dcg_start(const T* W, const T* AW, int64_t ld, int64_t n, int nj, const double* Ginv,
-                      const double* r, double rscale, T* g, T* s, const CGState* cg, T* part2,
+void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax,
+                      const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
+                      T* s, int64_t vstride, const CGState* cg, T* part2, int64_t p2stride, int nb,
                       hipStream_t st);
 template <typename T>
-void launch_dcg_dir(const T* W, int64_t ld, int64_t n, int nj, const double* Ginv, const T* s,
-                    T* p, int iter, CGState* cg, const T* part2, hipStream_t st);
+void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
+                    const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
+                    int iter, CGState* cg, const T* part2, int64_t p2stride, int nb,
+                    hipStream_t st);
 template <typename T>
 void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
-                      CGState* cg, T* partials, hipStream_t st);
+                      int64_t vstride, CGState* cg, T* part1, int nb, hipStream_t st);
 template <typename T>
-void launch_dcg_update(const T* AW, int64_t ld, int64_t n, int nj, const T* p, const T* w, T* g,
-                       T* s, int iter, CGState* cg, const T* part1, int P1, T* part2,
-                       hipStream_t st);
+void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax, const T* p,
+                       const T* w, T* g, T* s, int64_t vstride, int iter, CGState* cg,
+                       const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
+                       int nb, hipStream_t st);
 
 // ---- mixed form -----------------------------------------------------------------------
 // out[i] = (float) in[i], i < n.
@@ -172,6 +217,14 @@ void launch_cast_f32(int64_t n, const double* in, float* out, hipStream_t st);
 // out[i + c*ld] = (float) in[i + c*ld] for i < n, c < k.
 void launch_cast_cols_f32(int64_t n, int k, const double* in, int64_t ld, float* out,
                           hipStream_t st);
+// Batched refinement step, columns y < nb: g[:, y] += coef.c[y] d[:, y] (d of type T;
+// c = 0 leaves g), x[:, y] = x0[:, y] + g[:, y].  g, x0 at stride ld, d at ldd, x at ldx.
+struct Coefs {
+  double c[G_MAX];
+};
+template <typename T>
+void launch_refine_cols(int64_t n, int nb, const Coefs& coef, const T* d, int64_t ldd, double* g,
+                        const double* x0, int64_t ld, double* x, int64_t ldx, hipStream_t st);
 // One refinement step: g += sigma * d (d FP32), x = x0 + g (FP64).
 void launch_refine_update(int64_t n, double sigma, const float* d, double* g, const double* x0,
                           double* x, hipStream_t st);

@@ -68,7 +68,8 @@ struct Ctrl {
   double sc[16];
   int status[4];
   int pad[4];
-  CGState cg;
+  double rn[G_MAX];        // squared residual norms of a batch
+  CGState cg[G_MAX];
 };
 
 
@@ -110,6 +111,11 @@ class Timer {
     bytes[cls] += by;
     flops[cls] += fl;
     launches[cls] += 1;
+  }
+  // correct the byte / flop count of class cls
+  void adjust(int cls, double dby, double dfl) {
+    bytes[cls] += dby;
+    flops[cls] += dfl;
   }
   // Undo the accounting of the last `count` launches of class cls (launches that
   // returned at once because the iteration had already stopped).
@@ -246,25 +252,28 @@ class Sequencer {
     chunk_ = o.check_every > 0 ? o.check_every : 16;
     mixed_ = o.precision == ROM_PREC_MIXED;
     inner_tol_ = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    G_ = std::max(1, std::min(o.group, std::min(G_MAX, n_rhs_)));
   }
 
   int cap() const { return cap_; }
 
   size_t layout(void* base) {
     Arena a(base);
+    const int G = G_;
+    const int64_t wsz = ld_ * NJ_MAX;   // one member's recycle space
     Q_ = a.take<double>(ld_ * cap_);
     pool_ = a.take<double>(ld_ * pool_cap_);
-    Wp_ = a.take<double>(ld_ * NJ_MAX);
-    AWp_ = a.take<double>(ld_ * NJ_MAX);
-    x0_ = a.take<double>(ld_);
-    r_ = a.take<double>(ld_);
-    g_ = a.take<double>(ld_);
-    s_ = a.take<double>(ld_);
-    p_ = a.take<double>(ld_);
-    w_ = a.take<double>(ld_);
-    d_ = a.take<double>(ld_);
-    xt_ = a.take<double>(ld_);
-    r2_ = a.take<double>(ld_);
+    Wp_ = a.take<double>(wsz * G);
+    AWp_ = a.take<double>(wsz * G);
+    x0_ = a.take<double>(ld_ * G);
+    r_ = a.take<double>(ld_ * G);
+    g_ = a.take<double>(ld_ * G);
+    s_ = a.take<double>(ld_ * G);
+    p_ = a.take<double>(ld_ * G);
+    w_ = a.take<double>(ld_ * G);
+    d_ = a.take<double>(ld_ * G);
+    xt_ = a.take<double>(ld_ * G);
+    r2_ = a.take<double>(ld_ * G);
     vAB_ = a.take<double>(2 * ld_);
     diag_i_ = a.take<double>(ld_);
     dmu_ = a.take<double>(ld_);
@@ -276,29 +285,33 @@ class Sequencer {
                                gram_partials_max(NJ_MAX, NJ_MAX, n_, false));
     gram_part_ = a.take<double>(std::max<size_t>(gp, 1));
     const StencilShape sh = stencil_shape(S_, 1024);
-    red_part_ = a.take<double>(std::max<size_t>(2 * 1024, (size_t)sh.blocks));
-    part1_ = a.take<double>(std::max(sh.blocks, 1));
-    part2_ = a.take<double>((size_t)(NJ_MAX + 1) * dcg_blocks(n_));
+    const StencilShape sh5 = stencil_shape(S_, 512);
+    red_part_ = a.take<double>(std::max<size_t>(2 * 1024, (size_t)sh5.blocks * G));
+    p1s_ = std::max(sh.blocks, 1);
+    part1_ = a.take<double>((size_t)p1s_ * G);
+    p2s_ = (int64_t)(NJ_MAX + 1) * dcg_blocks(n_);
+    part2_ = a.take<double>((size_t)p2s_ * G);
     size_t gt = std::max(gemvt_partials_max(n_, std::max(cap_ + 1, NJ_MAX), 2),
                          gemvt_partials_max(cap_, cap_, 1));
+    gt = std::max(gt, proj_partials_max(std::max(cap_, NJ_MAX), G_MAX, n_));
     gt_part_ = a.take<double>(std::max<size_t>(gt, 1));
-    tbuf_ = a.take<double>(std::max(cap_, NJ_MAX) + 8);
-    ubuf_ = a.take<double>(cap_ + 8);
-    cbuf_ = a.take<double>(cap_ + 8);
+    tbuf_ = a.take<double>((size_t)(std::max(cap_, NJ_MAX) + 8) * std::max(G, 2));
+    ubuf_ = a.take<double>((size_t)(cap_ + 8) * G);
+    cbuf_ = a.take<double>((size_t)(cap_ + 8) * G);
     tmpl_ = a.take<double>(cap_ + 8);
     tmpr_ = a.take<double>(2 * (cap_ + 8));
     bvals_ = a.take<double>(2 * (cap_ + 8));
     GW_ = a.take<double>(NJ_MAX * NJ_MAX);
     lwork_ = a.take<double>(linv_rebuild_work(cap_));
-    LWinv_ = a.take<double>(NJ_MAX * NJ_MAX);
-    GWinv_ = a.take<double>(NJ_MAX * NJ_MAX);
+    LWinv_ = a.take<double>(NJ_MAX * NJ_MAX * G);
+    GWinv_ = a.take<double>(NJ_MAX * NJ_MAX * G);
     if (mixed_) {
-      W32_ = a.take<float>(ld_ * NJ_MAX);
-      AW32_ = a.take<float>(ld_ * NJ_MAX);
-      s32_ = a.take<float>(ld_);
-      p32_ = a.take<float>(ld_);
-      w32_ = a.take<float>(ld_);
-      d32_ = a.take<float>(ld_);
+      W32_ = a.take<float>(wsz * G);
+      AW32_ = a.take<float>(wsz * G);
+      s32_ = a.take<float>(ld_ * G);
+      p32_ = a.take<float>(ld_ * G);
+      w32_ = a.take<float>(ld_ * G);
+      d32_ = a.take<float>(ld_ * G);
       diag32_ = a.take<float>(ld_);
       if (S_.var) {
         fx32_ = a.take<float>(ld_);
@@ -351,148 +364,34 @@ class Sequencer {
     m_ = 0;
     extra_.assign(n_rhs_, {});
     next_slot_ = n_rhs_;
-    rom_status status = ROM_OK;
-    std::vector<rom_record> recs;
-    recs.reserve((size_t)K_ * n_rhs_);
-    long long total_its = 0;
-    int n_solved = 0, n_kept = 0, n_drop_trunc = 0, n_drop_cap = 0, n_nonconv = 0;
+    status_ = ROM_OK;
+    recs_.clear();
+    recs_.reserve((size_t)K_ * n_rhs_);
+    total_its_ = 0;
+    n_solved_ = n_kept_ = n_drop_trunc_ = n_drop_cap_ = n_nonconv_ = 0;
 
-    for (int i = 0; i < K_; ++i) {
-      mu0_ = params[i].mu0;
-      launch_mu_eval(S_, make_bumps(params[i], S_.dim), op_->diag_star, diag_i_, dmu_, st);
-      if (mixed_) launch_cast_f32(n_, diag_i_, diag32_, st);
-      if (i == 0) {
-        // V <- orth(U_0): CGS2 append of every column (Alg. 2 initialisation)
-        for (int c = 0; c < ku_in_; ++c) {
-          double rho;
-          append_q(U0 + (int64_t)c * n_, &rho);
-        }
-        ku_ = m_;
-      } else {
-        rebuild_gi();
+    try {
+      sweep_points(params, U0, X_out);
+    } catch (...) {
+      // the records of the right-hand sides completed before the error
+      if (records) {
+        std::memset(records, 0, (size_t)K_ * n_rhs_ * sizeof(rom_record));
+        std::memcpy(records, recs_.data(), recs_.size() * sizeof(rom_record));
       }
-      w_key_ = -2;
-      for (int j = 0; j < n_rhs_; ++j) {
-        const int64_t idx = idx_[j];
-        const double sc = scale_[j];
-        const double nb = std::fabs(sc);
-        rom_record rec;
-        std::memset(&rec, 0, sizeof(rec));
-        rec.point = i;
-        rec.rhs = j;
-        rec.rho = -1.0;
-        // ---- outer projection on V (Galerkin in the A(p_i) inner product)
-        if (m_ > 0) {
-          launch_gather_row(Q_, ld_, m_, idx, sc, tbuf_, st);
-          launch_linv_solve(Lc_, Lr_, ldg_, m_, tbuf_, ubuf_, cbuf_, gt_part_, st);
-          tm_->begin(ROM_K_OUTER);
-          launch_gemvn(Q_, ld_, n_, m_, cbuf_, 0.0, nullptr, 1.0, x0_, nullptr, red_part_, st);
-          tm_->end(ROM_K_OUTER, 8.0 * n_ * (m_ + 1), 2.0 * n_ * m_);
-        } else {
-          ROM_HIP(hipMemsetAsync(x0_, 0, sizeof(double) * n_, st));
-        }
-        launch_resid_unit(S_, diag_i_, x0_, idx, sc, r_, &ctrl_->sc[0], red_part_, st);
-        account_spmv(ROM_K_OTHER);
-        sync();
-        const double rho0 = std::sqrt(h_->sc[0]) / nb;
-        rec.rho0 = rho0;
-        double* xdst = X_out ? X_out + ((int64_t)i * n_rhs_ + j) * n_ : xt_;
-        if (rho0 <= tol_) {
-          ROM_HIP(hipMemcpyAsync(xdst, x0_, sizeof(double) * n_, hipMemcpyDeviceToDevice, st));
-          if (i == 0)
-            ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)j * ld_, x0_, sizeof(double) * n_,
-                                   hipMemcpyDeviceToDevice, st));
-          rec.final_res = rho0;
-          rec.converged = 1;
-          rec.m = m_;
-          recs.push_back(rec);
-          continue;
-        }
-        // ---- inner recycled CG on A g = r with U_j (correction equation, eq. (resi))
-        ++n_solved;
-        rec.solved = 1;
-        const int nj = make_W(i, j);
-        int flag = 0, its = 0, restarts = 0;
-        double res = rho0;
-        if (!mixed_) {
-          its = cg_solve<double>(r_, 1.0, g_, nj, tol_ * nb, maxit_, flag);
-          launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
-          res = true_residual(xdst, idx, sc, nb);
-          while (res > tol_ && its < maxit_ && flag == 0 && restarts < MAX_SWEEPS) {
-            ++restarts;
-            its += cg_solve<double>(r2_, 1.0, d_, nj, tol_ * nb, maxit_ - its, flag);
-            launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st);
-            launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
-            res = true_residual(xdst, idx, sc, nb);
-          }
-        } else {
-          its = refine(xdst, idx, sc, nb, nj, rec, res, restarts, flag);
-        }
-        if (flag == 1) throw Error(ROM_ENOTSPD, "CG met non-positive curvature (operator not SPD)");
-        if (flag == 2) throw Error(ROM_ENONFINITE, "non-finite value in CG");
-        total_its += its;
-        rec.its = its;
-        rec.restarts = restarts;
-        rec.final_res = res;
-        rec.converged = res <= tol_;
-        if (!rec.converged) {
-          ++n_nonconv;
-          status = ROM_ENOCONV;
-        }
-        // ---- append the new information to V (CGS2 + truncation) and to U_j
-        if (m_ < cap_) {
-          double rho = 0.0;
-          const bool kept = append_q(g_, &rho);
-          rec.rho = rho;
-          rec.kept = kept;
-          if (kept) {
-            ++n_kept;
-            if (i > 0 && ku_ + (int)extra_[j].size() < NJ_MAX && next_slot_ < pool_cap_) {
-              double* slot = pool_ + (int64_t)next_slot_ * ld_;
-              launch_axpby(n_, 1.0, g_, 0.0, nullptr, slot, nullptr, red_part_, st);
-              const double ru = cgs2_inplace(slot, Wp_, nj);
-              if (ru > trunc_) {
-                launch_normalize(n_, slot, &ctrl_->sc[4], st);
-                extra_[j].push_back(next_slot_++);
-              }
-            }
-          } else {
-            ++n_drop_trunc;
-          }
-        } else {
-          ++n_drop_cap;
-        }
-        if (i == 0)
-          ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)j * ld_, xdst, sizeof(double) * n_,
-                                 hipMemcpyDeviceToDevice, st));
-        rec.m = m_;
-        recs.push_back(rec);
-      }
-      if (i == 0) {
-        // U_j <- [U_0, X_0(:, j)] (Sec. 4.2.2), X_0(:, j) orthonormalised against U_0
-        for (int j = 0; j < n_rhs_; ++j) {
-          double* slot = pool_ + (int64_t)j * ld_;
-          const double rho = cgs2_inplace(slot, Q_, ku_);
-          extra_[j].clear();
-          if (rho > trunc_ && ku_ < NJ_MAX) {
-            launch_normalize(n_, slot, &ctrl_->sc[4], st);
-            extra_[j].push_back(j);
-          }
-        }
-      }
+      throw;
     }
     sync();
-    if (records) std::memcpy(records, recs.data(), recs.size() * sizeof(rom_record));
+    if (records) std::memcpy(records, recs_.data(), recs_.size() * sizeof(rom_record));
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
       stats->m = m_;
       stats->k_u = ku_;
-      stats->n_solved = n_solved;
-      stats->n_kept = n_kept;
-      stats->n_dropped_trunc = n_drop_trunc;
-      stats->n_dropped_cap = n_drop_cap;
-      stats->n_nonconv = n_nonconv;
-      stats->total_its = total_its;
+      stats->n_solved = n_solved_;
+      stats->n_kept = n_kept_;
+      stats->n_dropped_trunc = n_drop_trunc_;
+      stats->n_dropped_cap = n_drop_cap_;
+      stats->n_nonconv = n_nonconv_;
+      stats->total_its = total_its_;
       stats->seconds =
           std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       for (int k = 0; k < ROM_NK; ++k) {
@@ -517,7 +416,7 @@ class Sequencer {
     V->scale_dev = scale_dev_;
     *out_basis = V;
     tm_ = nullptr;
-    return status;
+    return status_;
   }
 
  private:
@@ -529,8 +428,17 @@ class Sequencer {
   }
 
   void check_status() {
-    if (h_->status[0]) throw Error(ROM_ENOTSPD, "outer Gram matrix V^T A V not positive definite");
-    if (h_->status[1]) throw Error(ROM_ENOTSPD, "recycle Gram matrix U_j^T A U_j not positive definite");
+    const std::string where = " (point " + std::to_string(cur_point_) + ", basis size " +
+                              std::to_string(m_) + ")";
+    if (h_->status[0]) {
+      std::string info;
+      if (h_->sc[12] > 0 || h_->sc[13] != 0)
+        info = "; border of column " + std::to_string((long)h_->sc[12]) + ": diagonal " +
+               std::to_string(h_->sc[13]) + ", projected part " + std::to_string(h_->sc[14]);
+      throw Error(ROM_ENOTSPD, "outer Gram matrix V^T A V not positive definite" + where + info);
+    }
+    if (h_->status[1])
+      throw Error(ROM_ENOTSPD, "recycle Gram matrix U_j^T A U_j not positive definite" + where);
   }
 
   void account_spmv(int cls) {
@@ -578,32 +486,41 @@ class Sequencer {
   }
 
   // Append v to V if its normalised part outside range(V) exceeds trunc; border the
-  // Gram matrices V^T A_* V and V^T A_i V and the inverse Cholesky factor.  The first
-  // Gram-Schmidt pass also forms h = V^T A_* v, so that V^T A_* q = (h - G_* t)/rho needs
-  // no further pass over V; V^T A_i q adds V^T (dmu o q), which only reads the row chunks
-  // inside the absorption bumps.  With heavy cancellation (rho < 0.1) the border is
-  // formed directly instead.
+  // Gram matrices V^T A_* V and V^T A_i V and the inverse Cholesky factor.  Each
+  // Gram-Schmidt pass also projects A_* of its input: with the pass input u, its
+  // coefficients t = V^T u and h = V^T A_* u, the new column q = (u - V t)/rho has
+  // V^T A_* q = (h - G_* t)/rho, so the border needs no further pass over V.  The border
+  // is taken from the last pass run: after the second pass ||t|| / rho is of the order
+  // of the rounding error, and a single pass is only kept when rho >= ||u|| / sqrt(2)
+  // (||t|| <= rho), so errors already in G_* are not amplified from one column to the
+  // next.  V^T A_i q adds V^T (dmu o q), which only reads the row chunks inside the
+  // absorption bumps.
   bool append_q(const double* v, double* rho_out) {
     *rho_out = -1.0;
     if (m_ >= cap_) return false;
     const int m = m_;
     double* slot = Q_ + (int64_t)m * ld_;
-    double* vcopy = vAB_;           // v, then A_* v at vAB_ + ld_
-    launch_axpby(n_, 1.0, v, 0.0, nullptr, vcopy, &ctrl_->sc[5], red_part_, st_);
+    double* u = vAB_;               // pass input, then A_* of it at vAB_ + ld_
+    launch_axpby(n_, 1.0, v, 0.0, nullptr, u, &ctrl_->sc[5], red_part_, st_);
     bool pass2 = false;
     if (m > 0) {
-      launch_spmv(S_, op_->diag_star, vcopy, vAB_ + ld_, st_);
+      launch_spmv(S_, op_->diag_star, u, vAB_ + ld_, st_);
       account_spmv(ROM_K_OTHER);
       tm_->begin(ROM_K_GEMVT);
-      launch_gemvt(Q_, ld_, n_, m, vcopy, ld_, 2, bvals_, gt_part_, st_);   // [t1 | h]
+      launch_gemvt(Q_, ld_, n_, m, u, ld_, 2, bvals_, gt_part_, st_);   // [t1 | h1]
       tm_->end(ROM_K_GEMVT, 8.0 * n_ * (m + 2), 4.0 * n_ * m);
       tm_->begin(ROM_K_GEMVN);
-      launch_gemvn(Q_, ld_, n_, m, bvals_, 1.0, vcopy, -1.0, slot, &ctrl_->sc[4], red_part_, st_);
+      launch_gemvn(Q_, ld_, n_, m, bvals_, 1.0, u, -1.0, slot, &ctrl_->sc[4], red_part_, st_);
       tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m + 2), 2.0 * n_ * m);
+      // second pass (the kernels return at once when the first kept more than half
+      // of ||v||^2): input slot, [t2 | h2] = V^T [slot, A_* slot]
       Skip skip{&ctrl_->sc[4], 0.5};
+      ROM_HIP(hipMemcpyAsync(u, slot, sizeof(double) * n_, hipMemcpyDeviceToDevice, st_));
+      launch_spmv(S_, op_->diag_star, u, vAB_ + ld_, st_);
+      account_spmv(ROM_K_OTHER);
       tm_->begin(ROM_K_GEMVT);
-      launch_gemvt(Q_, ld_, n_, m, slot, 0, 1, tbuf_, gt_part_, st_, skip);
-      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (m + 1), 2.0 * n_ * m);
+      launch_gemvt(Q_, ld_, n_, m, u, ld_, 2, tbuf_, gt_part_, st_, skip);
+      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (m + 2), 4.0 * n_ * m);
       tm_->begin(ROM_K_GEMVN);
       launch_gemvn(Q_, ld_, n_, m, tbuf_, 1.0, slot, -1.0, slot, &ctrl_->sc[4], red_part_, st_,
                    skip);
@@ -612,13 +529,13 @@ class Sequencer {
       ROM_HIP(hipStreamSynchronize(st_));
       pass2 = !(h_->sc[4] > 0.5 * h_->sc[5]);
       if (!pass2) {
-        tm_->discard(ROM_K_GEMVT, 1, 8.0 * n_ * (m + 1), 2.0 * n_ * m);
+        tm_->discard(ROM_K_GEMVT, 1, 8.0 * n_ * (m + 2), 4.0 * n_ * m);
         tm_->discard(ROM_K_GEMVN, 1, 8.0 * n_ * (m + 2), 2.0 * n_ * m);
       }
       tm_->harvest();
       check_status();
     } else {
-      ROM_HIP(hipMemcpyAsync(slot, vcopy, sizeof(double) * n_, hipMemcpyDeviceToDevice, st_));
+      ROM_HIP(hipMemcpyAsync(slot, u, sizeof(double) * n_, hipMemcpyDeviceToDevice, st_));
       ROM_HIP(hipMemcpyAsync(&ctrl_->sc[4], &ctrl_->sc[5], sizeof(double),
                              hipMemcpyDeviceToDevice, st_));
       sync();
@@ -627,43 +544,32 @@ class Sequencer {
     const double rho = (b > 0.0 && std::isfinite(a) && std::isfinite(b)) ? std::sqrt(a / b) : 0.0;
     *rho_out = rho;
     if (!(rho > trunc_)) return false;
-    const bool fused = m > 0 && rho >= 0.1;
-    if (fused) {
-      // t = t1 (+ t2) into ubuf_, u = G_* t into cbuf_
-      launch_axpby(m, 1.0, bvals_, pass2 ? 1.0 : 0.0, pass2 ? tbuf_ : nullptr, ubuf_, nullptr,
-                   red_part_, st_);
-      launch_gemvt(Gs_, ldg_, m, m, ubuf_, 0, 1, cbuf_, gt_part_, st_);
-    }
+    const double* th = pass2 ? tbuf_ : bvals_;   // [t | h] of the last pass
+    if (m > 0) launch_gemvt(Gs_, ldg_, m, m, th, 0, 1, cbuf_, gt_part_, st_);   // G_* t
     launch_normalize(n_, slot, &ctrl_->sc[4], st_);
-    border_new(m, slot, fused);
+    border_new(m, slot, th + m);
     ++m_;
     return true;
   }
 
-  // Border of G_*, G_i and Linv for the new (normalised) column k = q.  fused: the
-  // projection h is in bvals_[k .. 2k), u = G_* t in cbuf_, and ||v_final||^2 in sc[4].
-  void border_new(int k, const double* q, bool fused) {
+  // Border of G_*, G_i and Linv for the new (normalised) column k = q: h = V^T A_* u of
+  // the last Gram-Schmidt pass, G_* t in cbuf_, ||q_unnormalised||^2 in sc[4].
+  void border_new(int k, const double* q, const double* h) {
     launch_spmv(S_, op_->diag_star, q, vAB_, st_);
     account_spmv(ROM_K_OTHER);
     launch_spmv(S_, diag_i_, q, vAB_ + ld_, st_);
     account_spmv(ROM_K_OTHER);
-    if (fused) {
-      // d2 = [q^T A_* q, q^T A_i q]; z = dmu o q; w = V^T z (bump rows only)
-      launch_dot2_scale(n_, q, vAB_, vAB_ + ld_, dmu_, r2_, &ctrl_->sc[8], red_part_, st_);
+    // d2 = [q^T A_* q, q^T A_i q]; z = dmu o q; w = V^T z (bump rows only)
+    launch_dot2_scale(n_, q, vAB_, vAB_ + ld_, dmu_, r2_, &ctrl_->sc[8], red_part_, st_);
+    if (k > 0) {
       tm_->begin(ROM_K_GEMVT);
       launch_gemvt(Q_, ld_, n_, k, r2_, 0, 1, tmpl_, gt_part_, st_);
       tm_->end(ROM_K_GEMVT, 8.0 * n_ * (k + 1), 2.0 * n_ * k);
-      launch_border_from_proj(bvals_ + k, cbuf_, tmpl_, &ctrl_->sc[4], &ctrl_->sc[8], k,
-                              tmpr_, st_);
-      launch_border_fill(tmpr_, k, Gs_, Gi_, ldg_, st_);
-    } else {
-      tm_->begin(ROM_K_GEMVT);
-      launch_gemvt(Q_, ld_, n_, k + 1, vAB_, ld_, 2, bvals_, gt_part_, st_);
-      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (k + 3), 4.0 * n_ * (k + 1));
-      launch_border_fill(bvals_, k, Gs_, Gi_, ldg_, st_);
     }
+    launch_border_from_proj(h, cbuf_, tmpl_, &ctrl_->sc[4], &ctrl_->sc[8], k, tmpr_, st_);
+    launch_border_fill(tmpr_, k, Gs_, Gi_, ldg_, st_);
     launch_linv_border(Lc_, Lr_, ldg_, k, Gi_ + (int64_t)k * ldg_, tmpl_, tmpr_,
-                       &ctrl_->status[0], gt_part_, st_);
+                       &ctrl_->status[0], gt_part_, st_, &ctrl_->sc[12]);
   }
 
   // G_i = V^T A_* V + mu0 I + V^T diag(mu_i - mu0) V, then its inverse Cholesky factor.
@@ -675,9 +581,10 @@ class Sequencer {
     launch_linv_rebuild(Gi_, ldg_, m_, Lc_, Lr_, lwork_, &ctrl_->status[0], st_);
   }
 
-  // Pack U_j = [U_0 part of V, extra columns of RHS j] and form A_i U_j, its Gram and
-  // the inverse Cholesky factor.  At point 0 every U_j is U_0 (built once).
-  int make_W(int i, int j) {
+  // Pack U_j = [U_0 part of V, extra columns of RHS j] into member slot y and form
+  // A_i U_j, its Gram matrix and the inverse (FP64; FP32 copies of U_j and A_i U_j in the
+  // mixed form).  At point 0 every U_j is U_0 (slot 0, built once per point).
+  int make_W(int i, int j, int y) {
     const int key = i == 0 ? -1 : j;
     ColPtrs cp;
     int nj = 0;
@@ -685,22 +592,335 @@ class Sequencer {
     if (i > 0)
       for (int sl : extra_[j])
         if (nj < NJ_MAX) cp.p[nj++] = pool_ + (int64_t)sl * ld_;
-    if (key == w_key_ && nj == w_nj_) return nj;
-    w_key_ = key;
-    w_nj_ = nj;
+    if (key == w_key_[y] && nj == w_nj_[y]) return nj;
+    w_key_[y] = key;
+    w_nj_[y] = nj;
     if (nj == 0) return 0;
-    launch_pack_cols(n_, cp, nj, Wp_, ld_, st_);
-    launch_spmm(S_, diag_i_, Wp_, ld_, nj, AWp_, st_);
+    const int64_t off = (int64_t)y * ld_ * NJ_MAX;
+    double* W = Wp_ + off;
+    double* AW = AWp_ + off;
+    launch_pack_cols(n_, cp, nj, W, ld_, st_);
+    launch_spmm(S_, diag_i_, W, ld_, nj, AW, st_);
     tm_->begin(ROM_K_GRAM);
-    launch_gram(Wp_, ld_, nj, AWp_, ld_, nj, n_, nullptr, false, nullptr, 0, 0.0, GW_, nj,
+    launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, false, nullptr, 0, 0.0, GW_, nj,
                 gram_part_, st_);
     tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
-    launch_small_chol_inv(GW_, nj, LWinv_, GWinv_, &ctrl_->status[1], st_);
+    launch_small_chol_inv(GW_, nj, LWinv_ + (int64_t)y * NJ_MAX * NJ_MAX,
+                          GWinv_ + (int64_t)y * NJ_MAX * NJ_MAX, &ctrl_->status[1], st_);
     if (mixed_) {
-      launch_cast_cols_f32(n_, nj, Wp_, ld_, W32_, st_);
-      launch_cast_cols_f32(n_, nj, AWp_, ld_, AW32_, st_);
+      launch_cast_cols_f32(n_, nj, W, ld_, W32_ + off, st_);
+      launch_cast_cols_f32(n_, nj, AW, ld_, AW32_ + off, st_);
     }
     return nj;
+  }
+
+  // Algorithm 2 over the parameter points.
+  void sweep_points(const rom_mu* params, const double* U0, double* X_out) {
+    hipStream_t st = st_;
+    for (int i = 0; i < K_; ++i) {
+      cur_point_ = i;
+      mu0_ = params[i].mu0;
+      launch_mu_eval(S_, make_bumps(params[i], S_.dim), op_->diag_star, diag_i_, dmu_, st);
+      if (mixed_) launch_cast_f32(n_, diag_i_, diag32_, st);
+      if (i == 0) {
+        // V <- orth(U_0): CGS2 append of every column (Alg. 2 initialisation)
+        for (int c = 0; c < ku_in_; ++c) {
+          double rho;
+          append_q(U0 + (int64_t)c * n_, &rho);
+        }
+        ku_ = m_;
+      } else {
+        rebuild_gi();
+      }
+      for (int y = 0; y < G_MAX; ++y) w_key_[y] = -2;
+      if (G_ == 1)
+        point_sequential(i, X_out);
+      else
+        point_grouped(i, X_out);
+      if (i == 0) {
+        // U_j <- [U_0, X_0(:, j)] (Sec. 4.2.2), X_0(:, j) orthonormalised against U_0
+        for (int j = 0; j < n_rhs_; ++j) {
+          double* slot = pool_ + (int64_t)j * ld_;
+          const double rho = cgs2_inplace(slot, Q_, ku_);
+          extra_[j].clear();
+          if (rho > trunc_ && ku_ < NJ_MAX) {
+            launch_normalize(n_, slot, &ctrl_->sc[4], st);
+            extra_[j].push_back(j);
+          }
+        }
+      }
+    }
+  }
+
+  // Record bookkeeping and the append of a solved right-hand side j (correction g at
+  // gptr, solution at xdst): V grows by the CGS2-orthogonalised correction when it
+  // passes the truncation test, and U_j by the correction orthonormalised against the
+  // recycle space it was solved with (member slot y of the packed spaces).
+  void finish_solved(int i, int j, int y, const double* gptr, const double* xdst, int nj,
+                     int its, int restarts, double res, int flag, rom_record& rec) {
+    if (flag == 1) throw Error(ROM_ENOTSPD, "CG met non-positive curvature (operator not SPD)");
+    if (flag == 2) throw Error(ROM_ENONFINITE, "non-finite value in CG");
+    total_its_ += its;
+    rec.its = its;
+    rec.restarts = restarts;
+    rec.final_res = res;
+    rec.converged = res <= tol_;
+    if (!rec.converged) {
+      ++n_nonconv_;
+      status_ = ROM_ENOCONV;
+    }
+    if (m_ < cap_) {
+      double rho = 0.0;
+      const bool kept = append_q(gptr, &rho);
+      rec.rho = rho;
+      rec.kept = kept;
+      if (kept) {
+        ++n_kept_;
+        if (i > 0 && ku_ + (int)extra_[j].size() < NJ_MAX && next_slot_ < pool_cap_) {
+          double* slot = pool_ + (int64_t)next_slot_ * ld_;
+          launch_axpby(n_, 1.0, gptr, 0.0, nullptr, slot, nullptr, red_part_, st_);
+          const double ru = cgs2_inplace(slot, Wp_ + (int64_t)y * ld_ * NJ_MAX, nj);
+          if (ru > trunc_) {
+            launch_normalize(n_, slot, &ctrl_->sc[4], st_);
+            extra_[j].push_back(next_slot_++);
+          }
+        }
+      } else {
+        ++n_drop_trunc_;
+      }
+    } else {
+      ++n_drop_cap_;
+    }
+    if (i == 0)
+      ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)j * ld_, xdst, sizeof(double) * n_,
+                             hipMemcpyDeviceToDevice, st_));
+    rec.m = m_;
+  }
+
+  // The right-hand sides of point i one at a time (the paper's order).
+  void point_sequential(int i, double* X_out) {
+    hipStream_t st = st_;
+    for (int j = 0; j < n_rhs_; ++j) {
+      const int64_t idx = idx_[j];
+      const double sc = scale_[j];
+      const double nb = std::fabs(sc);
+      rom_record rec;
+      std::memset(&rec, 0, sizeof(rec));
+      rec.point = i;
+      rec.rhs = j;
+      rec.rho = -1.0;
+      // ---- outer projection on V (Galerkin in the A(p_i) inner product)
+      if (m_ > 0) {
+        launch_gather_row(Q_, ld_, m_, idx, sc, tbuf_, st);
+        launch_linv_solve(Lc_, Lr_, ldg_, m_, tbuf_, ubuf_, cbuf_, gt_part_, st);
+        tm_->begin(ROM_K_OUTER);
+        launch_gemvn(Q_, ld_, n_, m_, cbuf_, 0.0, nullptr, 1.0, x0_, nullptr, red_part_, st);
+        tm_->end(ROM_K_OUTER, 8.0 * n_ * (m_ + 1), 2.0 * n_ * m_);
+      } else {
+        ROM_HIP(hipMemsetAsync(x0_, 0, sizeof(double) * n_, st));
+      }
+      launch_resid_unit(S_, diag_i_, x0_, idx, sc, r_, &ctrl_->sc[0], red_part_, st);
+      account_spmv(ROM_K_OTHER);
+      sync();
+      const double rho0 = std::sqrt(h_->sc[0]) / nb;
+      rec.rho0 = rho0;
+      double* xdst = X_out ? X_out + ((int64_t)i * n_rhs_ + j) * n_ : xt_;
+      if (rho0 <= tol_) {
+        ROM_HIP(hipMemcpyAsync(xdst, x0_, sizeof(double) * n_, hipMemcpyDeviceToDevice, st));
+        if (i == 0)
+          ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)j * ld_, x0_, sizeof(double) * n_,
+                                 hipMemcpyDeviceToDevice, st));
+        rec.final_res = rho0;
+        rec.converged = 1;
+        rec.m = m_;
+        recs_.push_back(rec);
+        continue;
+      }
+      // ---- inner recycled CG on A g = r with U_j (correction equation, eq. (resi))
+      ++n_solved_;
+      rec.solved = 1;
+      const int nj = make_W(i, j, 0);
+      int flag = 0, its = 0, restarts = 0;
+      double res = rho0;
+      if (!mixed_) {
+        its = cg_solve<double>(r_, 1.0, g_, nj, tol_ * nb, maxit_, flag);
+        launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
+        res = true_residual(xdst, idx, sc, nb);
+        while (res > tol_ && its < maxit_ && flag == 0 && restarts < MAX_SWEEPS) {
+          ++restarts;
+          its += cg_solve<double>(r2_, 1.0, d_, nj, tol_ * nb, maxit_ - its, flag);
+          launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st);
+          launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
+          res = true_residual(xdst, idx, sc, nb);
+        }
+      } else {
+        its = refine(xdst, idx, sc, nb, nj, rec, res, restarts, flag);
+      }
+      finish_solved(i, j, 0, g_, xdst, nj, its, restarts, res, flag, rec);
+      recs_.push_back(rec);
+    }
+  }
+
+  // The right-hand sides of point i in groups of G_: one outer projection per group
+  // (the basis as it stands at the group start), the group's inner solves together,
+  // then the appends in right-hand-side order.
+  void point_grouped(int i, double* X_out) {
+    hipStream_t st = st_;
+    for (int j0 = 0; j0 < n_rhs_; j0 += G_) {
+      const int nb = std::min(G_, n_rhs_ - j0);
+      double* xdst = X_out ? X_out + ((int64_t)i * n_rhs_ + j0) * n_ : xt_;
+      const int64_t ldx = X_out ? n_ : ld_;
+      // ---- outer projection of the group: X0 = V G_i^{-1} V^T [b_j0 ..]
+      if (m_ > 0) {
+        launch_gather_rows(Q_, ld_, m_, idx_dev_ + j0, scale_dev_ + j0, nb, tbuf_, m_, st);
+        launch_gemm(m_, nb, m_, 1.0, Lc_, ldg_, false, tbuf_, m_, false, 0.0, nullptr, 0, ubuf_,
+                    m_, st);
+        launch_gemm(m_, nb, m_, 1.0, Lc_, ldg_, true, ubuf_, m_, false, 0.0, nullptr, 0, cbuf_,
+                    m_, st);
+        tm_->begin(ROM_K_OUTER);
+        launch_gemvn_multi(Q_, ld_, n_, m_, cbuf_, m_, nb, 0.0, nullptr, 0, 1.0, x0_, ld_, st);
+        tm_->end(ROM_K_OUTER, 8.0 * n_ * (m_ + nb), 2.0 * n_ * m_ * nb);
+      } else {
+        ROM_HIP(hipMemsetAsync(x0_, 0, sizeof(double) * ld_ * nb, st));
+      }
+      launch_resid_cols(S_, diag_i_, x0_, ld_, nb, idx_dev_ + j0, scale_dev_ + j0, r_, ld_,
+                        ctrl_->rn, 1, red_part_, st);
+      for (int y = 0; y < nb; ++y) account_spmv(ROM_K_OTHER);
+      sync();
+      rom_record rec[G_MAX];
+      double nbv[G_MAX], res[G_MAX];
+      int act[G_MAX], nj[G_MAX];
+      bool any = false;
+      for (int y = 0; y < nb; ++y) {
+        const int j = j0 + y;
+        std::memset(&rec[y], 0, sizeof(rom_record));
+        rec[y].point = i;
+        rec[y].rhs = j;
+        rec[y].rho = -1.0;
+        nbv[y] = std::fabs(scale_[j]);
+        res[y] = std::sqrt(h_->rn[y]) / nbv[y];
+        rec[y].rho0 = res[y];
+        act[y] = res[y] > tol_;
+        nj[y] = 0;
+        if (act[y]) {
+          any = true;
+          ++n_solved_;
+          rec[y].solved = 1;
+        } else {
+          rec[y].final_res = res[y];
+          rec[y].converged = 1;
+          rec[y].m = m_;
+        }
+      }
+      // skipped members: x = x0
+      launch_axpby_cols(n_, nb, 1.0, x0_, ld_, 0.0, nullptr, 0, xdst, ldx, st);
+      if (any) {
+        for (int y = 0; y < nb; ++y)
+          if (act[y]) nj[y] = make_W(i, j0 + y, i == 0 ? 0 : y);
+        int its[G_MAX], restarts[G_MAX], flag[G_MAX];
+        solve_group(i == 0, nb, j0, act, nj, nbv, res, xdst, ldx, its, restarts, flag, rec);
+        // ---- appends in right-hand-side order
+        for (int y = 0; y < nb; ++y)
+          if (act[y])
+            finish_solved(i, j0 + y, i == 0 ? 0 : y, g_ + (int64_t)y * ld_, xdst + y * ldx, nj[y],
+                          its[y], restarts[y], res[y], flag[y], rec[y]);
+      }
+      for (int y = 0; y < nb; ++y) {
+        if (!act[y] && i == 0)
+          ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)(j0 + y) * ld_, xdst + y * ldx,
+                                 sizeof(double) * n_, hipMemcpyDeviceToDevice, st));
+        recs_.push_back(rec[y]);
+      }
+    }
+  }
+
+  // Inner solves of the active members of a group, restarted from the FP64 true
+  // residual until each meets tol (plain form: FP64 sweeps; mixed form: FP32 sweeps in
+  // FP64 refinement, a stalled member continuing in FP64).  On entry r_ holds the
+  // members' residuals b - A x0 and res[] their relative norms; on exit g_ holds the
+  // corrections, xdst the solutions and res[] the final relative residuals.
+  void solve_group(bool shared, int nb, int j0, const int* act, const int* nj, const double* nbv,
+                   double* res, double* xdst, int64_t ldx, int* its, int* restarts, int* flag,
+                   rom_record* rec) {
+    ROM_HIP(hipMemsetAsync(g_, 0, sizeof(double) * ld_ * nb, st_));
+    bool live[G_MAX], fp32[G_MAX];
+    for (int y = 0; y < nb; ++y) {
+      live[y] = act[y] != 0;
+      fp32[y] = mixed_;
+      its[y] = restarts[y] = flag[y] = 0;
+    }
+    const double* rcur = r_;
+    for (;;) {
+      Batch b32, b64;
+      b32.nb = b64.nb = nb;
+      b32.shared = b64.shared = shared;
+      Coefs c32, c64;
+      bool any32 = false, any64 = false;
+      for (int y = 0; y < nb; ++y) {
+        c32.c[y] = c64.c[y] = 0.0;
+        b32.nj[y] = b64.nj[y] = nj[y];
+        if (!live[y]) continue;
+        const double rn = res[y] * nbv[y];
+        if (fp32[y]) {
+          const double goal =
+              std::min(0.5, std::max(std::max(inner_tol_, FP32_GOAL_MIN), 0.5 * tol_ / res[y]));
+          b32.active[y] = 1;
+          b32.rscale[y] = 1.0 / rn;
+          b32.tol_abs[y] = goal;
+          b32.maxit[y] = std::min(maxit_ - its[y], std::max(64, (maxit_ - its[y]) / 4));
+          c32.c[y] = rn;
+          any32 = true;
+        } else {
+          b64.active[y] = 1;
+          b64.rscale[y] = 1.0;
+          b64.tol_abs[y] = tol_ * nbv[y];
+          b64.maxit[y] = maxit_ - its[y];
+          c64.c[y] = 1.0;
+          if (mixed_) ++rec[y].fp64_sweeps;
+          any64 = true;
+        }
+      }
+      if (any32) {
+        cg_batch<float>(b32, rcur, d32_);
+        for (int y = 0; y < nb; ++y)
+          if (b32.active[y]) {
+            its[y] += b32.its[y];
+            if (b32.flag[y]) {
+              fp32[y] = false;   // FP32 breakdown: keep g, go on in FP64
+              c32.c[y] = 0.0;
+            }
+          }
+        launch_refine_cols<float>(n_, nb, c32, d32_, ld_, g_, x0_, ld_, xdst, ldx, st_);
+      }
+      if (any64) {
+        cg_batch<double>(b64, rcur, d_);
+        for (int y = 0; y < nb; ++y)
+          if (b64.active[y]) {
+            its[y] += b64.its[y];
+            flag[y] = b64.flag[y];
+          }
+        launch_refine_cols<double>(n_, nb, c64, d_, ld_, g_, x0_, ld_, xdst, ldx, st_);
+      }
+      launch_resid_cols(S_, diag_i_, xdst, ldx, nb, idx_dev_ + j0, scale_dev_ + j0, r2_, ld_,
+                        ctrl_->rn, 1, red_part_, st_);
+      for (int y = 0; y < nb; ++y) account_spmv(ROM_K_OTHER);
+      sync();
+      bool more = false;
+      for (int y = 0; y < nb; ++y) {
+        if (!live[y]) continue;
+        const double prev = res[y];
+        res[y] = std::sqrt(h_->rn[y]) / nbv[y];
+        if (res[y] <= tol_ || its[y] >= maxit_ || flag[y] != 0 || restarts[y] >= MAX_SWEEPS) {
+          live[y] = false;
+          continue;
+        }
+        ++restarts[y];
+        if (fp32[y] && !(res[y] <= 0.5 * prev)) fp32[y] = false;
+        more = true;
+      }
+      if (!more) break;
+      rcur = r2_;
+    }
   }
 
   // r2 = b - A x in FP64 (b = sc e_idx); returns ||r2|| / nb.
@@ -769,75 +989,175 @@ class Sequencer {
          reinterpret_cast<float*>(part2_)};
   }
 
-  // Deflated CG on A_i d = rscale * rhs with the packed U_j, in arithmetic T (the
-  // right-hand side is FP64); stops at ||s|| <= tol_abs.  Returns iterations.
+  // One batched deflated-CG solve: member y (active[y]) solves A_i d_y = rscale[y] r_y
+  // with the recycle space of slot y (slot 0 for every member when shared) until
+  // ||s_y|| <= tol_abs[y] or maxit[y] steps.  r_y at rhs + y*ld_ (FP64), d_y at
+  // dvec + y*ld_ (type T).
+  struct Batch {
+    int nb = 0;
+    bool shared = false;
+    int active[G_MAX] = {};
+    int nj[G_MAX] = {};
+    int maxit[G_MAX] = {};
+    double rscale[G_MAX] = {};
+    double tol_abs[G_MAX] = {};
+    int its[G_MAX] = {};
+    int flag[G_MAX] = {};
+  };
+
   template <typename T>
-  int cg_solve(const double* rhs, double rscale, T* dvec, int nj, double tol_abs, int maxit,
-               int& flag) {
+  void cg_batch(Batch& bt, const double* rhs, T* dvec) {
     typename std::conditional<std::is_same<T, float>::value, CgBufs32, CgBufs64>::type b;
     bufs(b);
-    CGState* cg = &ctrl_->cg;
+    const int nb = bt.nb;
+    CGState* cg = ctrl_->cg;
     const StencilShape sh = stencil_shape(S_, 1024);
-    launch_cg_setup(cg, tol_abs * tol_abs, maxit, st_);
-    if (nj > 0) {
-      tm_->begin(ROM_K_GEMVT);
-      launch_gemvt(Wp_, ld_, n_, nj, rhs, 0, 1, cg->t, gt_part_, st_);
-      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (nj + 1), 2.0 * n_ * nj);
+    const int64_t wstride = bt.shared ? 0 : ld_ * NJ_MAX;
+    const int64_t gstride = bt.shared ? 0 : (int64_t)NJ_MAX * NJ_MAX;
+    CgSetup su;
+    std::memset(&su, 0, sizeof(su));
+    int njmax = 0, nact = 0;
+    for (int y = 0; y < nb; ++y) {
+      bt.its[y] = bt.flag[y] = 0;
+      su.tol2[y] = bt.tol_abs[y] * bt.tol_abs[y];
+      su.rscale[y] = bt.rscale[y];
+      su.maxit[y] = bt.maxit[y];
+      su.nj[y] = bt.nj[y];
+      su.active[y] = bt.active[y];
+      if (bt.active[y]) {
+        njmax = std::max(njmax, bt.nj[y]);
+        ++nact;
+      }
+    }
+    if (nact == 0) return;
+    launch_cg_setup(cg, su, nb, st_);
+    // U_j^T r_j for the start
+    if (njmax > 0) {
+      if (bt.shared && nact > 1) {
+        tm_->begin(ROM_K_GEMVT);
+        launch_proj(Wp_, ld_, njmax, rhs, ld_, nb, n_, cg[0].t, sizeof(CGState) / sizeof(double),
+                    gt_part_, st_);
+        tm_->end(ROM_K_GEMVT, 8.0 * n_ * (njmax + nb), 2.0 * n_ * njmax * nb);
+      } else {
+        for (int y = 0; y < nb; ++y)
+          if (bt.active[y] && bt.nj[y] > 0) {
+            tm_->begin(ROM_K_GEMVT);
+            launch_gemvt(Wp_ + y * wstride, ld_, n_, bt.nj[y], rhs + (int64_t)y * ld_, 0, 1,
+                         cg[y].t, gt_part_, st_);
+            tm_->end(ROM_K_GEMVT, 8.0 * n_ * (bt.nj[y] + 1), 2.0 * n_ * bt.nj[y]);
+          }
+      }
     }
     const double E = sizeof(T);
-    launch_dcg_start<T>(b.W, b.AW, ld_, n_, nj, GWinv_, rhs, rscale, dvec, b.s, cg, b.part2, st_);
+    double njavg = 0.0;
+    for (int y = 0; y < nb; ++y)
+      if (bt.active[y]) njavg += bt.nj[y];
+    njavg /= nact;
+    launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec, b.s,
+                        ld_, cg, b.part2, p2s_, nb, st_);
     tm_->begin(ROM_K_DCG_DIR);
-    launch_dcg_dir<T>(b.W, ld_, n_, nj, GWinv_, b.s, b.p, -1, cg, b.part2, st_);
-    tm_->end(ROM_K_DCG_DIR, E * n_ * (2 + nj), n_ * (1.0 + 2.0 * nj));
+    launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, -1, cg,
+                      b.part2, p2s_, nb, st_);
+    tm_->end(ROM_K_DCG_DIR, nact * E * n_ * (2 + njavg), nact * n_ * (1.0 + 2.0 * njavg));
+    // per member and step
     const double by_apply = E * n_ * (3 + (S_.var ? S_.dim : 0));
     const double fl_apply = 15.0 * n_;
-    const double by_upd = E * n_ * (6 + nj);
-    const double fl_upd = n_ * (6.0 + 2.0 * nj);
-    const double by_dir = E * n_ * (3 + nj);
-    const double fl_dir = n_ * (3.0 + 2.0 * nj);
+    const double by_upd = E * n_ * (6 + njavg);
+    const double fl_upd = n_ * (6.0 + 2.0 * njavg);
+    const double by_dir = E * n_ * (3 + njavg);
+    const double fl_dir = n_ * (3.0 + 2.0 * njavg);
     int next = chunk_;
-    int its_before = 0;
-    double gam_before = -1.0;
+    int k0 = 0;
+    int its_before[G_MAX] = {};
+    double gam_before[G_MAX];
+    for (int y = 0; y < G_MAX; ++y) gam_before[y] = -1.0;
+    int nlive = nact;
     for (;;) {
       for (int c = 0; c < next; ++c) {
-        const int k = its_before + c;
+        const int k = k0 + c;
         tm_->begin(ROM_K_SPMV);
-        launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, cg, b.part1, st_);
-        tm_->end(ROM_K_SPMV, by_apply, fl_apply);
+        launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, st_);
+        tm_->end(ROM_K_SPMV, nlive * by_apply, nlive * fl_apply);
         tm_->begin(ROM_K_DCG_UPDATE);
-        launch_dcg_update<T>(b.AW, ld_, n_, nj, b.p, b.w, dvec, b.s, k, cg, b.part1, sh.blocks,
-                             b.part2, st_);
-        tm_->end(ROM_K_DCG_UPDATE, by_upd, fl_upd);
+        launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
+                             b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, st_);
+        tm_->end(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
         tm_->begin(ROM_K_DCG_DIR);
-        launch_dcg_dir<T>(b.W, ld_, n_, nj, GWinv_, b.s, b.p, k, cg, b.part2, st_);
-        tm_->end(ROM_K_DCG_DIR, by_dir, fl_dir);
+        launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,
+                          b.part2, p2s_, nb, st_);
+        tm_->end(ROM_K_DCG_DIR, nlive * by_dir, nlive * fl_dir);
       }
       ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
       ROM_HIP(hipStreamSynchronize(st_));
-      // steps after the stop returned at once: drop them from the accounting (the
-      // direction update of the stopping step is one of them)
-      const int real = h_->cg.its - its_before;
-      const bool stop = h_->cg.done != 0;
-      const int noop = next - real;
-      tm_->discard(ROM_K_SPMV, noop, by_apply, fl_apply);
-      tm_->discard(ROM_K_DCG_UPDATE, noop, by_upd, fl_upd);
-      tm_->discard(ROM_K_DCG_DIR, noop + (stop ? 1 : 0), by_dir, fl_dir);
+      // member-steps done in this chunk; launches after the last member stopped
+      // returned at once (the direction update of a stopping step is one of them)
+      int maxreal = 0, steps = 0, still = 0, nstopped = 0;
+      for (int y = 0; y < nb; ++y) {
+        if (!bt.active[y] || its_before[y] < 0) continue;
+        const CGState& c = h_->cg[y];
+        const int real = c.its - its_before[y];
+        maxreal = std::max(maxreal, real);
+        steps += real;
+        if (c.done) {
+          ++nstopped;
+          its_before[y] = -1;
+        } else {
+          ++still;
+          its_before[y] = c.its;
+        }
+      }
+      const bool stop = still == 0;
+      const int noop = stop ? next - maxreal : 0;
+      tm_->discard(ROM_K_SPMV, noop, 0.0, 0.0);
+      tm_->discard(ROM_K_DCG_UPDATE, noop, 0.0, 0.0);
+      tm_->discard(ROM_K_DCG_DIR, noop + (stop ? 1 : 0), 0.0, 0.0);
+      const double over = (double)nlive * next - steps;
+      tm_->adjust(ROM_K_SPMV, -over * by_apply, -over * fl_apply);
+      tm_->adjust(ROM_K_DCG_UPDATE, -over * by_upd, -over * fl_upd);
+      tm_->adjust(ROM_K_DCG_DIR, -(over + nstopped) * by_dir, -(over + nstopped) * fl_dir);
       tm_->harvest();
       if (stop) break;
-      // next poll: extrapolate the last chunk's contraction of s^T s to the tolerance
-      const double gam = h_->cg.gamma[h_->cg.its & 1];
-      int pred = chunk_;
-      if (gam_before > 0.0 && gam > 0.0 && gam < gam_before && real > 0) {
-        const double rate = std::log(gam / gam_before) / real;   // < 0
-        const double need = std::log(h_->cg.tol2 / gam) / rate;
-        pred = (int)std::ceil(need);
+      // next poll: extrapolate each live member's contraction of s^T s to its tolerance
+      int pred = 2;
+      for (int y = 0; y < nb; ++y) {
+        if (!bt.active[y] || its_before[y] < 0) continue;
+        const CGState& c = h_->cg[y];
+        const double gam = c.gamma[c.its & 1];
+        int py = chunk_;
+        if (gam_before[y] > 0.0 && gam > 0.0 && gam < gam_before[y] && next > 0) {
+          const double rate = std::log(gam / gam_before[y]) / next;   // < 0
+          py = (int)std::ceil(std::log(c.tol2 / gam) / rate);
+        }
+        pred = std::max(pred, py);
+        gam_before[y] = gam;
       }
+      k0 += next;
+      nlive = still;
       next = std::min(64, std::max(2, pred));
-      its_before = h_->cg.its;
-      gam_before = gam;
     }
-    flag = h_->cg.flag;
-    return h_->cg.its;
+    for (int y = 0; y < nb; ++y) {
+      if (!bt.active[y]) continue;
+      bt.its[y] = h_->cg[y].its;
+      bt.flag[y] = h_->cg[y].flag;
+    }
+  }
+
+  // Deflated CG on A_i d = rscale * rhs with the recycle space in slot 0, in arithmetic T
+  // (the right-hand side is FP64); stops at ||s|| <= tol_abs.  Returns iterations.
+  template <typename T>
+  int cg_solve(const double* rhs, double rscale, T* dvec, int nj, double tol_abs, int maxit,
+               int& flag) {
+    Batch bt;
+    bt.nb = 1;
+    bt.shared = true;
+    bt.active[0] = 1;
+    bt.nj[0] = nj;
+    bt.maxit[0] = maxit;
+    bt.rscale[0] = rscale;
+    bt.tol_abs[0] = tol_abs;
+    cg_batch<T>(bt, rhs, dvec);
+    flag = bt.flag[0];
+    return bt.its[0];
   }
 
   rom_operator* op_;
@@ -848,6 +1168,9 @@ class Sequencer {
   int cap_, ldg_, pool_cap_;
   double tol_, trunc_;
   int maxit_, chunk_;
+  int G_ = 1;                // right-hand sides per group
+  int cur_point_ = 0;
+  int64_t p1s_ = 0, p2s_ = 0;   // per-member strides of the CG partials
   bool mixed_ = false;
   double inner_tol_ = 1e-5;
   hipStream_t st_ = nullptr;
@@ -855,7 +1178,12 @@ class Sequencer {
   Ctrl* h_ = nullptr;
   double mu0_ = 0.0;
   int m_ = 0, ku_ = 0, next_slot_ = 0;
-  int w_key_ = -2, w_nj_ = -1;
+  int w_key_[G_MAX], w_nj_[G_MAX] = {};
+  // results
+  std::vector<rom_record> recs_;
+  rom_status status_ = ROM_OK;
+  long long total_its_ = 0;
+  int n_solved_ = 0, n_kept_ = 0, n_drop_trunc_ = 0, n_drop_cap_ = 0, n_nonconv_ = 0;
   std::vector<std::vector<int>> extra_;
   std::vector<int64_t> idx_;
   std::vector<double> scale_;
@@ -887,6 +1215,7 @@ void check_opts(const rom_opts* o) {
   if (o->precision != ROM_PREC_FP64 && o->precision != ROM_PREC_MIXED)
     throw Error(ROM_EINVAL, "precision must be ROM_PREC_FP64 or ROM_PREC_MIXED");
   if (!(o->inner_tol >= 0) || !(o->inner_tol < 1)) throw Error(ROM_EINVAL, "inner_tol must be in [0, 1)");
+  if (o->group < 0 || o->group > G_MAX) throw Error(ROM_EINVAL, "group must be in [0, 16]");
 }
 
 void check_counts(int n_src, int n_det, int k_u, int K) {

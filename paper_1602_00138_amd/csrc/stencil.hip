@@ -94,16 +94,23 @@ __device__ __forceinline__ Faces<float> faces(const Stencil& S, float) {
   return {S.fx32, S.fy32, S.fz32};
 }
 
-// MODE 0: y = A x.  MODE 1: y = A x, partial x^T y (CG step; exits if cg->done).
-// MODE 2: y = b - A x with b = bscale e_bidx, partial y^T y.
-// blockIdx.z selects a column (x + z*ldx, y + z*ldy).  T is the arithmetic type.
+// MODE 0: y = A x.  MODE 1: y = A x, partial x^T y (CG step; exits if cg[z].done).
+// MODE 2: y = b - A x with b = bscale e_bidx (or bscale_arr[z] e_{bidx_arr[z]}), partial
+// y^T y.  blockIdx.z selects a column (x + z*ldx, y + z*ldy; partials of column z at
+// + z * gridDim.x * gridDim.y).  T is the arithmetic type.
 template <typename T, bool VAR, int MODE>
 __global__ __launch_bounds__(BS) void k_stencil(Stencil S, const T* __restrict__ diag,
                                                  const T* __restrict__ x0, int64_t ldx,
                                                  T* __restrict__ y0, int64_t ldy, int zc,
                                                  int64_t bidx, double bscale,
+                                                 const int64_t* __restrict__ bidx_arr,
+                                                 const double* __restrict__ bscale_arr,
                                                  T* __restrict__ partials, const CGState* cg) {
-  if (MODE == 1 && cg->done) return;
+  if (MODE == 1 && cg[blockIdx.z].done) return;
+  if (MODE == 2 && bidx_arr) {
+    bidx = bidx_arr[blockIdx.z];
+    bscale = bscale_arr[blockIdx.z];
+  }
   const T* __restrict__ x = x0 + (int64_t)blockIdx.z * ldx;
   T* __restrict__ y = y0 + (int64_t)blockIdx.z * ldy;
   const Faces<T> F = faces(S, T(0));
@@ -153,7 +160,17 @@ __global__ __launch_bounds__(BS) void k_stencil(Stencil S, const T* __restrict__
       xc = xp;
     }
   }
-  if (MODE != 0) write_partials<1, BS>(acc, partials, blockIdx.x + gridDim.x * blockIdx.y);
+  if (MODE != 0)
+    write_partials<1, BS>(acc, partials + (int64_t)blockIdx.z * gridDim.x * gridDim.y,
+                          blockIdx.x + gridDim.x * blockIdx.y);
+}
+
+// out[z * ostride] = sum_b partials[z * P + b], one block per column z.
+__global__ void k_reduce_cols(const double* __restrict__ partials, int P, double* out,
+                              int64_t ostride) {
+  __shared__ double tot[1];
+  sum_partials<1, BS>(partials + (int64_t)blockIdx.x * P, P, tot);
+  if (threadIdx.x == 0) out[blockIdx.x * ostride] = tot[0];
 }
 
 template <int R>
@@ -208,7 +225,8 @@ void launch_spmv(const Stencil& S, const double* diag, const double* x, double* 
                  hipStream_t st) {
   const StencilShape sh = stencil_shape(S, 1024);
   STENCIL_LAUNCH(double, 0, sh.grid, diag, x, 0, y, 0, sh.zc, (int64_t)-1, 0.0,
-                 (double*)nullptr, (const CGState*)nullptr);
+                 (const int64_t*)nullptr, (const double*)nullptr, (double*)nullptr,
+                 (const CGState*)nullptr);
 }
 
 void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t ld, int k,
@@ -217,7 +235,8 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
   StencilShape sh = stencil_shape(S, 512);
   dim3 grid = sh.grid;
   grid.z = k;
-  STENCIL_LAUNCH(double, 0, grid, diag, X, ld, Y, ld, sh.zc, (int64_t)-1, 0.0, (double*)nullptr,
+  STENCIL_LAUNCH(double, 0, grid, diag, X, ld, Y, ld, sh.zc, (int64_t)-1, 0.0,
+                 (const int64_t*)nullptr, (const double*)nullptr, (double*)nullptr,
                  (const CGState*)nullptr);
 }
 
@@ -225,21 +244,37 @@ void launch_resid_unit(const Stencil& S, const double* diag, const double* x, in
                        double scale, double* r, double* nrm2, double* partials,
                        hipStream_t st) {
   const StencilShape sh = stencil_shape(S, 512);
-  STENCIL_LAUNCH(double, 2, sh.grid, diag, x, 0, r, 0, sh.zc, idx, scale, partials,
+  STENCIL_LAUNCH(double, 2, sh.grid, diag, x, 0, r, 0, sh.zc, idx, scale,
+                 (const int64_t*)nullptr, (const double*)nullptr, partials,
                  (const CGState*)nullptr);
   launch_reduce_finish(partials, sh.blocks, 1, nrm2, st);
 }
 
 template <typename T>
 void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
-                      CGState* cg, T* partials, hipStream_t st) {
-  STENCIL_LAUNCH(T, 1, sh.grid, diag, p, 0, w, 0, sh.zc, (int64_t)-1, 0.0, partials,
-                 (const CGState*)cg);
+                      int64_t vstride, CGState* cg, T* part1, int nb, hipStream_t st) {
+  const dim3 grid(sh.grid.x, sh.grid.y, nb);
+  STENCIL_LAUNCH(T, 1, grid, diag, p, vstride, w, vstride, sh.zc, (int64_t)-1, 0.0,
+                 (const int64_t*)nullptr, (const double*)nullptr, part1, (const CGState*)cg);
 }
 template void launch_dcg_apply<double>(const Stencil&, const StencilShape&, const double*,
-                                       const double*, double*, CGState*, double*, hipStream_t);
+                                       const double*, double*, int64_t, CGState*, double*, int,
+                                       hipStream_t);
 template void launch_dcg_apply<float>(const Stencil&, const StencilShape&, const float*,
-                                      const float*, float*, CGState*, float*, hipStream_t);
+                                      const float*, float*, int64_t, CGState*, float*, int,
+                                      hipStream_t);
+
+void launch_resid_cols(const Stencil& S, const double* diag, const double* X, int64_t ldx, int nb,
+                       const int64_t* idx, const double* scale, double* R, int64_t ldr,
+                       double* nrm2, int64_t nstride, double* partials, hipStream_t st) {
+  if (nb <= 0) return;
+  const StencilShape sh = stencil_shape(S, 512);
+  const dim3 grid(sh.grid.x, sh.grid.y, nb);
+  STENCIL_LAUNCH(double, 2, grid, diag, X, ldx, R, ldr, sh.zc, (int64_t)-1, 0.0, idx, scale,
+                 partials, (const CGState*)nullptr);
+  ROM_LAUNCH(k_reduce_cols, dim3(nb), dim3(BS), 0, st, partials, sh.blocks, nrm2, nstride);
+  ROM_CHECK_LAUNCH();
+}
 
 void launch_reduce_finish(const double* partials, int P, int R, double* out, hipStream_t st,
                           Skip skip) {

@@ -53,7 +53,7 @@ class rom_mu(C.Structure):
 class rom_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("inner_tol", C.c_double),
                 ("cap", C.c_int), ("maxit", C.c_int), ("check_every", C.c_int), ("timing", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("group", C.c_int)]
 
 
 class rom_record(C.Structure):
@@ -149,9 +149,9 @@ def make_grid(dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float) -> 
 
 def make_opts(tol: float, trunc: float = 1e-8, cap: int = 0, maxit: int = 0,
               check_every: int = 0, timing: int = 0, precision: int = ROM_PREC_FP64,
-              inner_tol: float = 0.0) -> rom_opts:
+              inner_tol: float = 0.0, group: int = 0) -> rom_opts:
     return rom_opts(float(tol), float(trunc), float(inner_tol), int(cap), int(maxit),
-                    int(check_every), int(timing), int(precision))
+                    int(check_every), int(timing), int(precision), int(group))
 
 
 @dataclass
@@ -218,8 +218,12 @@ def rom_solve_sequence(op: int, params: List[MuParams], src_idx, src_scale, det_
         _ptr(U0), int(k_u), C.byref(opts), _ptr(workspace),
         workspace.numel() * workspace.element_size(), C.byref(basis), _ptr(X_out), recs,
         C.byref(st), _stream(stream))
-    _check(status, allow=(ROM_ENOCONV,))
     records = [{f: getattr(r, f) for f, _ in rom_record._fields_} for r in recs]
+    if status != ROM_OK and status != ROM_ENOCONV:
+        err = RomError(status, rom_last_error())
+        # the right-hand sides completed before the error (zeroed records after them)
+        err.records = [r for r in records if r["converged"] or r["solved"] or r["rho0"] > 0]
+        raise err
     return status, basis.value, records, st
 
 

@@ -24,11 +24,11 @@ class OracleProblem:
     def A(self, i):
         return op.assemble_A(self.As, self.mus[i])
 
-    def run(self, tol=None, trunc=None, cap=0, mus=None):
+    def run(self, tol=None, trunc=None, cap=0, mus=None, group=1):
         wl = self.wl
         return oseq.solve_sequence(self.As, mus if mus is not None else self.mus, self.B, self.U0,
                                    wl.tol if tol is None else tol,
-                                   wl.trunc if trunc is None else trunc, cap=cap)
+                                   wl.trunc if trunc is None else trunc, cap=cap, group=group)
 
     def psi(self, i):
         ns = self.wl.n_src

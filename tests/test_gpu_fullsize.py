@@ -55,8 +55,11 @@ def reference():
     return ref, idx, si, di, pts
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_fullsize_sampled_parity(gpu, reference, precision):
+@pytest.mark.parametrize("precision,group", [("fp64", 1), ("mixed", 1), ("fp64", 8), ("mixed", 8)])
+def test_fullsize_sampled_parity(gpu, reference, precision, group):
+    """Groups of 8 at this size append many corrections that are nearly aligned with
+    the columns appended just before them (small rho, large projections on V); the
+    sampled A_r entries check that the bordered Gram matrix V^T A_* V stays exact."""
     import torch
     from paper_1602_00138_amd import driver
     from paper_1602_00138_amd import rom as R
@@ -65,8 +68,9 @@ def test_fullsize_sampled_parity(gpu, reference, precision):
     prob = driver.problem_from_workload(WL)
     pts = driver.points_from_workload(WL)
     prec = R.ROM_PREC_MIXED if precision == "mixed" else R.ROM_PREC_FP64
-    print(f"\n{WL.name} {precision}: solving {len(pts)} points x {prob.n_rhs} RHS", flush=True)
-    res = prob.solve(pts, WL.tol, WL.trunc, precision=prec)
+    print(f"\n{WL.name} {precision} group {group}: solving {len(pts)} points x {prob.n_rhs} RHS",
+          flush=True)
+    res = prob.solve(pts, WL.tol, WL.trunc, precision=prec, group=group)
     n_rhs = prob.n_rhs
     assert all(r["converged"] and r["final_res"] <= WL.tol * (1 + 1e-6) for r in res.records)
     Qd = res.Q()                                   # m x N on the device (rows = columns of V)
@@ -104,7 +108,7 @@ def test_fullsize_sampled_parity(gpu, reference, precision):
         worst.update(sol=max(worst["sol"], err), res=max(worst["res"], rel),
                      basis=max(worst["basis"], dist), Ar=max(worst["Ar"], ea))
     st = res.stats
-    print(f"{WL.name} {precision}: m {m}, solved {st['n_solved']}, its {st['total_its']}, "
+    print(f"{WL.name} {precision} group {group}: m {m}, solved {st['n_solved']}, its {st['total_its']}, "
           f"sweeps {sum(r['restarts'] for r in res.records)}, FP64 fallback sweeps "
           f"{sum(r['fp64_sweeps'] for r in res.records)}; sampled max rel. error vs oracle: "
           f"solution {worst['sol']:.2e}, true residual {worst['res']:.2e}, reference outside "

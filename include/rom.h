@@ -114,6 +114,9 @@ typedef struct {
   int group;        /* right-hand sides per batch, 1..16 (0: 1, the paper's order): the
                        members of a group are projected on V as it stands at the group
                        start, solved together, and appended in order afterwards */
+  int tune;         /* 1: the first batch of each kind in the process times a few launch
+                       shapes of the CG kernels and keeps the fastest (results then depend on
+                       the chosen shape up to rounding); 0: fixed shape */
 } rom_opts;
 
 /* One record per (point i, right-hand side j), in solve order. */

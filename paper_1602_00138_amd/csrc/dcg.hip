@@ -255,9 +255,9 @@ __global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int6
   write_partials_t<NJT + 1, B>(acc, part2, blockIdx.x, gridDim.x);
 }
 
-int njt_of(int nj) { return nj <= 8 ? 8 : nj <= 16 ? 16 : nj <= 32 ? 32 : 64; }
-
 }  // namespace
+
+int njt_of(int nj) { return nj <= 8 ? 8 : nj <= 16 ? 16 : nj <= 32 ? 32 : 64; }
 
 int dcg_blocks(int64_t n) {
   const int b = ceil_div(n, 512);
@@ -274,8 +274,8 @@ template <typename T>
 void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax,
                       const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
                       T* s, int64_t vstride, const CGState* cg, T* part2, int64_t p2stride, int nb,
-                      hipStream_t st) {
-  const dim3 grid(dcg_blocks(n), nb);
+                      int P, hipStream_t st) {
+  const dim3 grid(P, nb);
   switch (njt_of(njmax)) {
 #define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, wstride, ld, n, Ginv, gstride, r, rstride, g, s, vstride, cg, part2, p2stride); break;
     C(8) C(16) C(32) C(64)
@@ -287,10 +287,10 @@ void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int6
 template <typename T>
 void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
                     const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
-                    int iter, CGState* cg, const T* part2, int64_t p2stride, int nb,
+                    int iter, CGState* cg, const T* part2, int64_t p2stride, int nb, int P,
                     hipStream_t st) {
-  const dim3 grid(dcg_blocks(n), nb);
-  const int P2 = dcg_blocks(n);
+  const dim3 grid(P, nb);
+  const int P2 = P;
   switch (njt_of(njmax)) {
 #define C(J) case J: ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, W, wstride, ld, n, Ginv, gstride, s, p, vstride, iter, cg, part2, p2stride, P2); break;
     C(8) C(16) C(32) C(64)
@@ -303,8 +303,8 @@ template <typename T>
 void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax, const T* p,
                        const T* w, T* g, T* s, int64_t vstride, int iter, CGState* cg,
                        const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
-                       int nb, hipStream_t st) {
-  const dim3 grid(dcg_blocks(n), nb);
+                       int nb, int P, hipStream_t st) {
+  const dim3 grid(P, nb);
   switch (njt_of(njmax)) {
 #define C(J) case J: ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, AW, wstride, ld, n, p, w, g, s, vstride, iter, cg, part1, P1, p1stride, part2, p2stride); break;
     C(8) C(16) C(32) C(64)
@@ -316,13 +316,14 @@ void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int 
 #define INSTANTIATE(T)                                                                          \
   template void launch_dcg_start<T>(const T*, const T*, int64_t, int64_t, int64_t, int,          \
                                     const double*, int64_t, const double*, int64_t, T*, T*,      \
-                                    int64_t, const CGState*, T*, int64_t, int, hipStream_t);     \
+                                    int64_t, const CGState*, T*, int64_t, int, int,              \
+                                    hipStream_t);                                                \
   template void launch_dcg_dir<T>(const T*, int64_t, int64_t, int64_t, int, const double*,       \
                                   int64_t, const T*, T*, int64_t, int, CGState*, const T*,       \
-                                  int64_t, int, hipStream_t);                                    \
+                                  int64_t, int, int, hipStream_t);                               \
   template void launch_dcg_update<T>(const T*, int64_t, int64_t, int64_t, int, const T*,         \
                                      const T*, T*, T*, int64_t, int, CGState*, const T*, int,    \
-                                     int64_t, T*, int64_t, int, hipStream_t);
+                                     int64_t, T*, int64_t, int, int, hipStream_t);
 INSTANTIATE(double)
 INSTANTIATE(float)
 #undef INSTANTIATE

@@ -257,6 +257,37 @@ __global__ void k_refine_cols(int64_t n, Coefs coef, const T* __restrict__ d, in
   }
 }
 
+// Squared norms of s columns: partials[c * gridDim.x + b] (column c = blockIdx.y).
+__global__ void k_colnorm2(int64_t n, const double* __restrict__ X, int64_t ld,
+                           double* __restrict__ partials) {
+  const double* x = X + (int64_t)blockIdx.y * ld;
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    v[0] += x[i] * x[i];
+  write_partials<1, BS>(v, partials + (int64_t)blockIdx.y * gridDim.x, blockIdx.x);
+}
+
+__global__ void k_sum_cols(const double* __restrict__ partials, int P, double* out) {
+  __shared__ double tot[1];
+  sum_partials<1, BS>(partials + (int64_t)blockIdx.x * P, P, tot);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot[0];
+}
+
+// Gram borders of k new basis columns m .. m+k-1 from B = [V^T A_* Q_new | V^T A_i Q_new]
+// ((m + k) x 2k, ld ldb): column m + c of G_* and G_i gets rows 0 .. m + c, mirrored.
+__global__ void k_border_fill_block(const double* __restrict__ B, int64_t ldb, int m, int k,
+                                    double* Gs, double* Gi, int64_t ldg) {
+  const int c = blockIdx.y;
+  const int r = blockIdx.x * BS + threadIdx.x;
+  const int col = m + c;
+  if (r > col) return;
+  const double a = B[r + (int64_t)c * ldb], b = B[r + (int64_t)(k + c) * ldb];
+  Gs[r + (int64_t)col * ldg] = a;
+  Gs[col + (int64_t)r * ldg] = a;
+  Gi[r + (int64_t)col * ldg] = b;
+  Gi[col + (int64_t)r * ldg] = b;
+}
+
 __global__ void k_pack_cols(int64_t n, ColPtrs src, int k, double* __restrict__ dst, int64_t ld) {
   const int c = blockIdx.y;
   const double* s = src.p[c];
@@ -686,6 +717,24 @@ template void launch_refine_cols<double>(int64_t, int, const Coefs&, const doubl
                                          hipStream_t);
 template void launch_refine_cols<float>(int64_t, int, const Coefs&, const float*, int64_t, double*,
                                         const double*, int64_t, double*, int64_t, hipStream_t);
+
+void launch_col_norms(int64_t n, int s, const double* X, int64_t ld, double* out,
+                      double* partials, hipStream_t st) {
+  if (s <= 0) return;
+  const int P = std::min(256, std::max(1, ceil_div(n, BS * 4)));
+  ROM_LAUNCH(k_colnorm2, dim3(P, s), dim3(BS), 0, st, n, X, ld, partials);
+  ROM_CHECK_LAUNCH();
+  ROM_LAUNCH(k_sum_cols, dim3(s), dim3(BS), 0, st, partials, P, out);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_border_fill_block(const double* B, int64_t ldb, int m, int k, double* Gs, double* Gi,
+                              int64_t ldg, hipStream_t st) {
+  if (k <= 0) return;
+  ROM_LAUNCH(k_border_fill_block, dim3(ceil_div(m + k, BS), k), dim3(BS), 0, st, B, ldb, m, k, Gs,
+             Gi, ldg);
+  ROM_CHECK_LAUNCH();
+}
 
 void launch_pack_cols(int64_t n, const ColPtrs& src, int k, double* dst, int64_t ld,
                       hipStream_t st) {

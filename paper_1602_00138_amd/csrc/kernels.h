@@ -101,6 +101,14 @@ void launch_gemvn_multi(const double* M, int64_t ld, int64_t rows, int cols, con
 void launch_axpby_cols(int64_t n, int nv, double a, const double* x, int64_t ldx, double b,
                        const double* y, int64_t ldy, double* out, int64_t ldo, hipStream_t st);
 
+// out[c] = ||X[:, c]||^2 for c < s (device).  partials: >= 256 * s doubles.
+void launch_col_norms(int64_t n, int s, const double* X, int64_t ld, double* out,
+                      double* partials, hipStream_t st);
+// Gram borders of k new columns m .. m+k-1 from B = [V^T A_* Q_new | V^T A_i Q_new]
+// ((m + k) x 2k, column-major, ld ldb), written to both triangles of G_* and G_i.
+void launch_border_fill_block(const double* B, int64_t ldb, int m, int k, double* Gs, double* Gi,
+                              int64_t ldg, hipStream_t st);
+
 // ---- vector helpers ---------------------------------------------------------------
 // out = a*x + b*y (y may be NULL); if nrm2: nrm2[0] = ||out||^2, nrm2[1] = ||y||^2.
 // partials: >= 2048 doubles.
@@ -185,22 +193,25 @@ void launch_dot2_scale(int64_t n, const double* x, const double* a, const double
 // W + y*wstride, AW + y*wstride and Ginv + y*gstride (strides 0: one recycle space for
 // every member), the FP64 right-hand side r + y*rstride (read as rscale * r) and its
 // CG vectors at + y*vstride.  W, AW: n x nj contiguous (ld); Ginv: nj x nj FP64 inverse
-// of W^T A W.  Partials (values of T): part1 >= stencil_shape(S, 1024).blocks per
-// member, part2 >= (NJ_MAX + 1) * dcg_blocks(n) per member, at strides p1stride,
-// p2stride.  iter: 0-based step index shared by the batch (-1 for the direction after
+// of W^T A W.  P: blocks per member of the start, update and direction kernels
+// (1 <= P <= dcg_blocks(n)); each thread covers n / (P * block) rows.  Partials (values
+// of T): part1 >= stencil_shape(S, 1024).blocks per member, part2 >= (NJ_MAX + 1) * P
+// per member, at strides p1stride, p2stride.  iter: 0-based step index shared by the batch (-1 for the direction after
 // the start).  cg[y].t holds U_j^T r before the start.  Inactive members (done set at
 // setup) return at once from every kernel.
 int dcg_blocks(int64_t n);
+// the width class (8, 16, 32 or 64 columns) the kernels are compiled for
+int njt_of(int nj);
 void launch_cg_setup(CGState* cg, const CgSetup& su, int nb, hipStream_t st);
 template <typename T>
 void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax,
                       const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
                       T* s, int64_t vstride, const CGState* cg, T* part2, int64_t p2stride, int nb,
-                      hipStream_t st);
+                      int P, hipStream_t st);
 template <typename T>
 void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
                     const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
-                    int iter, CGState* cg, const T* part2, int64_t p2stride, int nb,
+                    int iter, CGState* cg, const T* part2, int64_t p2stride, int nb, int P,
                     hipStream_t st);
 template <typename T>
 void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
@@ -209,7 +220,7 @@ template <typename T>
 void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax, const T* p,
                        const T* w, T* g, T* s, int64_t vstride, int iter, CGState* cg,
                        const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
-                       int nb, hipStream_t st);
+                       int nb, int P, hipStream_t st);
 
 // ---- mixed form -----------------------------------------------------------------------
 // out[i] = (float) in[i], i < n.

@@ -8,6 +8,9 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -232,6 +235,18 @@ size_t operator_layout(const rom_grid& g, bool var, Arena& a, rom_operator* op) 
   return a.off;
 }
 
+// Launch shapes chosen by the CG autotuner, per process: (device, value size, batch
+// size, U_j width class, grid size) -> blocks per member.
+using TuneKey = std::tuple<int, int, int, int, int64_t>;
+std::map<TuneKey, int>& tune_map() {
+  static std::map<TuneKey, int> m;
+  return m;
+}
+std::mutex& tune_mu() {
+  static std::mutex mu;
+  return mu;
+}
+
 // ------------------------------------------------------------------------------------
 // Algorithm 2, CG form.
 
@@ -251,6 +266,7 @@ class Sequencer {
     maxit_ = o.maxit > 0 ? o.maxit : (int)std::min<int64_t>(n_, 1 << 30);
     chunk_ = o.check_every > 0 ? o.check_every : 16;
     mixed_ = o.precision == ROM_PREC_MIXED;
+    tune_ = o.tune != 0;
     inner_tol_ = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     G_ = std::max(1, std::min(o.group, std::min(G_MAX, n_rhs_)));
   }
@@ -275,6 +291,8 @@ class Sequencer {
     xt_ = a.take<double>(ld_ * G);
     r2_ = a.take<double>(ld_ * G);
     vAB_ = a.take<double>(2 * ld_);
+    blk_ = G > 1 ? a.take<double>(ld_ * 2 * G) : nullptr;
+    bblk_ = G > 1 ? a.take<double>((size_t)(cap_ + 8) * 2 * G) : nullptr;
     diag_i_ = a.take<double>(ld_);
     dmu_ = a.take<double>(ld_);
     Gs_ = a.take<double>((size_t)ldg_ * cap_);
@@ -286,7 +304,7 @@ class Sequencer {
     gram_part_ = a.take<double>(std::max<size_t>(gp, 1));
     const StencilShape sh = stencil_shape(S_, 1024);
     const StencilShape sh5 = stencil_shape(S_, 512);
-    red_part_ = a.take<double>(std::max<size_t>(2 * 1024, (size_t)sh5.blocks * G));
+    red_part_ = a.take<double>(std::max<size_t>(2 * 1024, (size_t)std::max(sh5.blocks, 256) * G));
     p1s_ = std::max(sh.blocks, 1);
     part1_ = a.take<double>((size_t)p1s_ * G);
     p2s_ = (int64_t)(NJ_MAX + 1) * dcg_blocks(n_);
@@ -652,12 +670,8 @@ class Sequencer {
     }
   }
 
-  // Record bookkeeping and the append of a solved right-hand side j (correction g at
-  // gptr, solution at xdst): V grows by the CGS2-orthogonalised correction when it
-  // passes the truncation test, and U_j by the correction orthonormalised against the
-  // recycle space it was solved with (member slot y of the packed spaces).
-  void finish_solved(int i, int j, int y, const double* gptr, const double* xdst, int nj,
-                     int its, int restarts, double res, int flag, rom_record& rec) {
+  // Bookkeeping of a solved right-hand side: iterations, final residual, convergence.
+  void record_solve(int its, int restarts, double res, int flag, rom_record& rec) {
     if (flag == 1) throw Error(ROM_ENOTSPD, "CG met non-positive curvature (operator not SPD)");
     if (flag == 2) throw Error(ROM_ENONFINITE, "non-finite value in CG");
     total_its_ += its;
@@ -669,6 +683,27 @@ class Sequencer {
       ++n_nonconv_;
       status_ = ROM_ENOCONV;
     }
+  }
+
+  // U_j grows by the correction of RHS j orthonormalised against the recycle space it
+  // was solved with (member slot y), when the correction joined V (i > 0).
+  void update_Uj(int i, int j, int y, const double* gptr, int nj) {
+    if (i == 0 || ku_ + (int)extra_[j].size() >= NJ_MAX || next_slot_ >= pool_cap_) return;
+    double* slot = pool_ + (int64_t)next_slot_ * ld_;
+    launch_axpby(n_, 1.0, gptr, 0.0, nullptr, slot, nullptr, red_part_, st_);
+    const double ru = cgs2_inplace(slot, Wp_ + (int64_t)y * ld_ * NJ_MAX, nj);
+    if (ru > trunc_) {
+      launch_normalize(n_, slot, &ctrl_->sc[4], st_);
+      extra_[j].push_back(next_slot_++);
+    }
+  }
+
+  // A solved right-hand side j of the sequential order (correction at gptr, solution
+  // at xdst): V grows by the CGS2-orthogonalised correction when it passes the
+  // truncation test and the cap, then U_j.
+  void finish_solved(int i, int j, int y, const double* gptr, const double* xdst, int nj,
+                     int its, int restarts, double res, int flag, rom_record& rec) {
+    record_solve(its, restarts, res, flag, rec);
     if (m_ < cap_) {
       double rho = 0.0;
       const bool kept = append_q(gptr, &rho);
@@ -676,15 +711,7 @@ class Sequencer {
       rec.kept = kept;
       if (kept) {
         ++n_kept_;
-        if (i > 0 && ku_ + (int)extra_[j].size() < NJ_MAX && next_slot_ < pool_cap_) {
-          double* slot = pool_ + (int64_t)next_slot_ * ld_;
-          launch_axpby(n_, 1.0, gptr, 0.0, nullptr, slot, nullptr, red_part_, st_);
-          const double ru = cgs2_inplace(slot, Wp_ + (int64_t)y * ld_ * NJ_MAX, nj);
-          if (ru > trunc_) {
-            launch_normalize(n_, slot, &ctrl_->sc[4], st_);
-            extra_[j].push_back(next_slot_++);
-          }
-        }
+        update_Uj(i, j, y, gptr, nj);
       } else {
         ++n_drop_trunc_;
       }
@@ -695,6 +722,99 @@ class Sequencer {
       ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)j * ld_, xdst, sizeof(double) * n_,
                              hipMemcpyDeviceToDevice, st_));
     rec.m = m_;
+  }
+
+  // The corrections of a group's solved members (y with act[y], in order) join V as a
+  // block: two block Gram-Schmidt passes against V as it stood at the group start (one
+  // MFMA projection and one multi-vector update per pass), then, member by member, two
+  // passes against the columns this group already added and the truncation test on the
+  // remaining norm relative to ||g||.  The Gram borders of the k new columns come from
+  // one projection of [A_* Q_new, A_i Q_new] on the extended basis, then the inverse
+  // Cholesky factor is bordered column by column.  Fills rec[y].rho / kept / m.
+  void append_block(int nb, const int* act, rom_record* rec) {
+    int ys[G_MAX];
+    int s = 0;
+    for (int y = 0; y < nb; ++y)
+      if (act[y]) ys[s++] = y;
+    if (s == 0) return;
+    const int m0 = m_;
+    if (m0 >= cap_) {
+      for (int c = 0; c < s; ++c) {
+        ++n_drop_cap_;
+        rec[ys[c]].m = m_;
+      }
+      return;
+    }
+    double* U = d_;   // working copies of the corrections, s columns
+    for (int c = 0; c < s; ++c)
+      ROM_HIP(hipMemcpyAsync(U + (int64_t)c * ld_, g_ + (int64_t)ys[c] * ld_, sizeof(double) * n_,
+                             hipMemcpyDeviceToDevice, st_));
+    launch_col_norms(n_, s, U, ld_, ctrl_->rn, red_part_, st_);
+    if (m0 > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        tm_->begin(ROM_K_GEMVT);
+        launch_proj(Q_, ld_, m0, U, ld_, s, n_, tbuf_, m0, gt_part_, st_);
+        tm_->end(ROM_K_GEMVT, 8.0 * n_ * (m0 + s), 2.0 * n_ * m0 * s);
+        tm_->begin(ROM_K_GEMVN);
+        launch_gemvn_multi(Q_, ld_, n_, m0, tbuf_, m0, s, 1.0, U, ld_, -1.0, U, ld_, st_);
+        tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m0 + 2 * s), 2.0 * n_ * m0 * s);
+      }
+    }
+    sync();
+    double gn[G_MAX];
+    for (int c = 0; c < s; ++c) gn[c] = h_->rn[c];
+    int k = 0;
+    double* Qnew = Q_ + (int64_t)m0 * ld_;
+    for (int c = 0; c < s; ++c) {
+      rom_record& r = rec[ys[c]];
+      if (m0 + k >= cap_) {
+        ++n_drop_cap_;
+        r.m = m0 + k;
+        continue;
+      }
+      double* w = U + (int64_t)c * ld_;
+      if (k > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_gemvt(Qnew, ld_, n_, k, w, 0, 1, tmpl_, gt_part_, st_);
+          launch_gemvn(Qnew, ld_, n_, k, tmpl_, 1.0, w, -1.0, w, &ctrl_->sc[4], red_part_, st_);
+        }
+      } else {
+        launch_col_norms(n_, 1, w, ld_, &ctrl_->sc[4], red_part_, st_);
+      }
+      sync();
+      const double a = h_->sc[4], b = gn[c];
+      const double rho = (b > 0.0 && std::isfinite(a) && std::isfinite(b)) ? std::sqrt(a / b) : 0.0;
+      r.rho = rho;
+      if (rho > trunc_) {
+        double* slot = Qnew + (int64_t)k * ld_;
+        ROM_HIP(hipMemcpyAsync(slot, w, sizeof(double) * n_, hipMemcpyDeviceToDevice, st_));
+        launch_normalize(n_, slot, &ctrl_->sc[4], st_);
+        ++k;
+        r.kept = 1;
+        ++n_kept_;
+      } else {
+        ++n_drop_trunc_;
+      }
+      r.m = m0 + k;
+    }
+    if (k == 0) return;
+    // borders: B = [V^T A_* Q_new | V^T A_i Q_new] over the m0 + k columns
+    launch_spmm(S_, op_->diag_star, Qnew, ld_, k, blk_, st_);
+    launch_spmm(S_, diag_i_, Qnew, ld_, k, blk_ + (int64_t)k * ld_, st_);
+    for (int c = 0; c < 2 * k; ++c) account_spmv(ROM_K_OTHER);
+    const int mk = m0 + k;
+    for (int h = 0; h < 2 * k; h += 16) {
+      const int nv = std::min(16, 2 * k - h);
+      tm_->begin(ROM_K_GEMVT);
+      launch_proj(Q_, ld_, mk, blk_ + (int64_t)h * ld_, ld_, nv, n_, bblk_ + (int64_t)h * mk, mk,
+                  gt_part_, st_);
+      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (mk + nv), 2.0 * n_ * mk * nv);
+    }
+    launch_border_fill_block(bblk_, mk, m0, k, Gs_, Gi_, ldg_, st_);
+    for (int c = 0; c < k; ++c)
+      launch_linv_border(Lc_, Lr_, ldg_, m0 + c, Gi_ + (int64_t)(m0 + c) * ldg_, tmpl_, tmpr_,
+                         &ctrl_->status[0], gt_part_, st_, &ctrl_->sc[12]);
+    m_ = mk;
   }
 
   // The right-hand sides of point i one at a time (the paper's order).
@@ -819,14 +939,16 @@ class Sequencer {
           if (act[y]) nj[y] = make_W(i, j0 + y, i == 0 ? 0 : y);
         int its[G_MAX], restarts[G_MAX], flag[G_MAX];
         solve_group(i == 0, nb, j0, act, nj, nbv, res, xdst, ldx, its, restarts, flag, rec);
-        // ---- appends in right-hand-side order
         for (int y = 0; y < nb; ++y)
-          if (act[y])
-            finish_solved(i, j0 + y, i == 0 ? 0 : y, g_ + (int64_t)y * ld_, xdst + y * ldx, nj[y],
-                          its[y], restarts[y], res[y], flag[y], rec[y]);
+          if (act[y]) record_solve(its[y], restarts[y], res[y], flag[y], rec[y]);
+        // ---- the group's corrections join V (in right-hand-side order), then U_j
+        append_block(nb, act, rec);
+        for (int y = 0; y < nb; ++y)
+          if (act[y] && rec[y].kept)
+            update_Uj(i, j0 + y, i == 0 ? 0 : y, g_ + (int64_t)y * ld_, nj[y]);
       }
       for (int y = 0; y < nb; ++y) {
-        if (!act[y] && i == 0)
+        if (i == 0)
           ROM_HIP(hipMemcpyAsync(pool_ + (int64_t)(j0 + y) * ld_, xdst + y * ldx,
                                  sizeof(double) * n_, hipMemcpyDeviceToDevice, st));
         recs_.push_back(rec[y]);
@@ -1005,6 +1127,84 @@ class Sequencer {
     int flag[G_MAX] = {};
   };
 
+  // Blocks per member of the CG step kernels.  Fixed shape: the full grid for one
+  // member, split among the members of a batch.  With opts.tune the first batch of each
+  // (arithmetic, batch size, U_j width class, grid size) in the process times every
+  // power-of-two candidate on its own data (a few CG steps each, from its real start;
+  // the solve then restarts) and keeps the fastest for the rest of the process.
+  template <typename T, typename Bufs>
+  int cg_shape(const Batch& bt, const Bufs& b, const double* rhs, T* dvec, int64_t wstride,
+               int64_t gstride, int njmax) {
+    const int nb = bt.nb;
+    const int Pmax = dcg_blocks(n_);
+    const int fixed = std::max(std::min(Pmax, 8), Pmax / nb);
+    if (!tune_) return fixed;
+    int dev = 0;
+    ROM_HIP(hipGetDevice(&dev));
+    const TuneKey key{dev, (int)sizeof(T), nb, njt_of(njmax), (int64_t)n_};
+    {
+      std::lock_guard<std::mutex> lk(tune_mu());
+      auto it = tune_map().find(key);
+      if (it != tune_map().end()) return it->second;
+    }
+    std::vector<int> cand;
+    for (int P = Pmax; P >= 8; P /= 2) cand.push_back(P);
+    int best = fixed;
+    if (cand.size() > 1) {
+      CGState* cg = ctrl_->cg;
+      CgSetup su;
+      std::memset(&su, 0, sizeof(su));
+      for (int y = 0; y < nb; ++y) {
+        su.tol2[y] = 0.0;
+        su.rscale[y] = bt.rscale[y];
+        su.maxit[y] = 1 << 30;
+        su.nj[y] = bt.nj[y];
+        su.active[y] = bt.active[y];
+      }
+      const StencilShape sh = stencil_shape(S_, 1024);
+      launch_cg_setup(cg, su, nb, st_);
+      launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec,
+                          b.s, ld_, cg, b.part2, p2s_, nb, Pmax, st_);
+      launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, -1, cg,
+                        b.part2, p2s_, nb, Pmax, st_);
+      hipEvent_t e0, e1;
+      ROM_HIP(hipEventCreate(&e0));
+      ROM_HIP(hipEventCreate(&e1));
+      struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+          (void)hipEventDestroy(a);
+          (void)hipEventDestroy(b);
+        }
+      } guard{e0, e1};
+      int k = 0;
+      float best_ms = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {   // the first round warms up
+        for (int P : cand) {
+          ROM_HIP(hipEventRecord(e0, st_));
+          for (int step = 0; step < 4; ++step, ++k) {
+            launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, st_);
+            launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
+                                 b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_);
+            launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,
+                              b.part2, p2s_, nb, P, st_);
+          }
+          ROM_HIP(hipEventRecord(e1, st_));
+          ROM_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          ROM_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (rep == 1 && ms < best_ms) {
+            best_ms = ms;
+            best = P;
+          }
+        }
+      }
+    }
+    std::lock_guard<std::mutex> lk(tune_mu());
+    tune_map()[key] = best;
+    return best;
+  }
+
   template <typename T>
   void cg_batch(Batch& bt, const double* rhs, T* dvec) {
     typename std::conditional<std::is_same<T, float>::value, CgBufs32, CgBufs64>::type b;
@@ -1030,6 +1230,7 @@ class Sequencer {
       }
     }
     if (nact == 0) return;
+    const int P = cg_shape<T>(bt, b, rhs, dvec, wstride, gstride, njmax);
     launch_cg_setup(cg, su, nb, st_);
     // U_j^T r_j for the start
     if (njmax > 0) {
@@ -1054,10 +1255,10 @@ class Sequencer {
       if (bt.active[y]) njavg += bt.nj[y];
     njavg /= nact;
     launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec, b.s,
-                        ld_, cg, b.part2, p2s_, nb, st_);
+                        ld_, cg, b.part2, p2s_, nb, P, st_);
     tm_->begin(ROM_K_DCG_DIR);
     launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, -1, cg,
-                      b.part2, p2s_, nb, st_);
+                      b.part2, p2s_, nb, P, st_);
     tm_->end(ROM_K_DCG_DIR, nact * E * n_ * (2 + njavg), nact * n_ * (1.0 + 2.0 * njavg));
     // per member and step
     const double by_apply = E * n_ * (3 + (S_.var ? S_.dim : 0));
@@ -1080,11 +1281,11 @@ class Sequencer {
         tm_->end(ROM_K_SPMV, nlive * by_apply, nlive * fl_apply);
         tm_->begin(ROM_K_DCG_UPDATE);
         launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
-                             b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, st_);
+                             b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_);
         tm_->end(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
         tm_->begin(ROM_K_DCG_DIR);
         launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,
-                          b.part2, p2s_, nb, st_);
+                          b.part2, p2s_, nb, P, st_);
         tm_->end(ROM_K_DCG_DIR, nlive * by_dir, nlive * fl_dir);
       }
       ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
@@ -1172,6 +1373,7 @@ class Sequencer {
   int cur_point_ = 0;
   int64_t p1s_ = 0, p2s_ = 0;   // per-member strides of the CG partials
   bool mixed_ = false;
+  bool tune_ = false;
   double inner_tol_ = 1e-5;
   hipStream_t st_ = nullptr;
   Timer* tm_ = nullptr;
@@ -1189,6 +1391,7 @@ class Sequencer {
   std::vector<double> scale_;
   // device buffers
   double *Q_, *pool_, *Wp_, *AWp_, *x0_, *r_, *g_, *s_, *p_, *w_, *d_, *xt_, *r2_, *vAB_;
+  double *blk_ = nullptr, *bblk_ = nullptr;   // block append: A Q_new, its projections
   double *diag_i_, *dmu_, *Gs_, *Gi_, *Lc_, *Lr_, *gram_part_, *red_part_, *gt_part_;
   double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_, *lwork_;
   Ctrl* ctrl_;
@@ -1216,6 +1419,7 @@ void check_opts(const rom_opts* o) {
     throw Error(ROM_EINVAL, "precision must be ROM_PREC_FP64 or ROM_PREC_MIXED");
   if (!(o->inner_tol >= 0) || !(o->inner_tol < 1)) throw Error(ROM_EINVAL, "inner_tol must be in [0, 1)");
   if (o->group < 0 || o->group > G_MAX) throw Error(ROM_EINVAL, "group must be in [0, 16]");
+  if (o->tune != 0 && o->tune != 1) throw Error(ROM_EINVAL, "tune must be 0 or 1");
 }
 
 void check_counts(int n_src, int n_det, int k_u, int K) {

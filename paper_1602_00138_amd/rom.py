@@ -53,7 +53,7 @@ class rom_mu(C.Structure):
 class rom_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("inner_tol", C.c_double),
                 ("cap", C.c_int), ("maxit", C.c_int), ("check_every", C.c_int), ("timing", C.c_int),
-                ("precision", C.c_int), ("group", C.c_int)]
+                ("precision", C.c_int), ("group", C.c_int), ("tune", C.c_int)]
 
 
 class rom_record(C.Structure):
@@ -149,9 +149,9 @@ def make_grid(dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float) -> 
 
 def make_opts(tol: float, trunc: float = 1e-8, cap: int = 0, maxit: int = 0,
               check_every: int = 0, timing: int = 0, precision: int = ROM_PREC_FP64,
-              inner_tol: float = 0.0, group: int = 0) -> rom_opts:
+              inner_tol: float = 0.0, group: int = 0, tune: int = 0) -> rom_opts:
     return rom_opts(float(tol), float(trunc), float(inner_tol), int(cap), int(maxit),
-                    int(check_every), int(timing), int(precision), int(group))
+                    int(check_every), int(timing), int(precision), int(group), int(tune))
 
 
 @dataclass

@@ -77,3 +77,22 @@ def test_group_one_equals_sequential(drv):
     a = prob.solve(pts, wl.tol, wl.trunc)
     b = prob.solve(pts, wl.tol, wl.trunc, group=1)
     assert torch.equal(a.X, b.X)
+
+
+def test_autotuned_shape_parity(drv):
+    """With the CG launch shape autotuned, results still match the oracle (the shape only
+    changes summation order), and a second solve in the process reuses the shape."""
+    import torch
+    wl = ph.small(3, (14, 13, 12), n_src=5, n_det=4, K=2)
+    orc = OracleProblem(wl)
+    for group in (1, 4):
+        ores = orc.run(group=group)
+        prob = drv.problem_from_workload(wl)
+        pts = drv.points_from_workload(wl)
+        res = prob.solve(pts, wl.tol, wl.trunc, group=group, tune=1)
+        _check_sequence(wl, orc, ores, res, prob, pts)
+        again = prob.solve(pts, wl.tol, wl.trunc, group=group, tune=1)
+        assert torch.equal(res.X, again.X)
+        res.close()
+        again.close()
+        prob.close()

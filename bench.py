@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--group", type=int, default=1,
                     help="right-hand sides per batch (1: the paper's order, up to 16)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the CG launch shape (0/1)")
+    ap.add_argument("--graph", type=int, default=0, help="replay CG steps from captured HIP graphs")
     ap.add_argument("--kernel", default="outer",
                     help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
                          "k_gemvn<false>; auto: the class with the most event time)")
@@ -129,7 +130,7 @@ def main():
     # caller-owned buffers, allocated once outside the timed region
     prec = R.ROM_PREC_MIXED if args.precision == "mixed" else R.ROM_PREC_FP64
     opts_all = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=(1 << R.ROM_NK) - 1, precision=prec,
-                           group=args.group, tune=args.tune)
+                           group=args.group, tune=args.tune, graph=args.graph)
     nbytes = R.rom_sequence_bytes(prob.op, prob.src_idx.size, prob.det_idx.size, prob.k_u, K, opts_all)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     X = torch.empty((K * n_rhs, prob.n), dtype=torch.float64, device=dev)
@@ -170,7 +171,7 @@ def main():
         dom = max((k for k in kern if k != "other"), key=lambda k: kern[k]["ms"])
     cls = R.KERNEL_CLASSES.index(dom)
     opts = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=1 << cls, precision=prec, group=args.group,
-                       tune=args.tune)
+                       tune=args.tune, graph=args.graph)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()

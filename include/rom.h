@@ -117,6 +117,8 @@ typedef struct {
   int tune;         /* 1: the first batch of each kind in the process times a few launch
                        shapes of the CG kernels and keeps the fastest (results then depend on
                        the chosen shape up to rounding); 0: fixed shape */
+  int graph;        /* 1: the CG iterations run as replays of a captured HIP graph of 8 steps
+                       (same kernels, same results; not used while a CG class is timed) */
 } rom_opts;
 
 /* One record per (point i, right-hand side j), in solve order. */
@@ -197,6 +199,39 @@ ROM_API rom_status rom_solve_sequence(rom_operator* op, const rom_mu* params, in
                               void* workspace, size_t ws_bytes, rom_basis** basis,
                               double* X_out, rom_record* records, rom_stats* stats,
                               void* stream);
+
+/* Several independent sequences at once (e.g. one per grid of a set of uneven grids):
+ * each job holds the arguments of one rom_solve_sequence call; every job runs on its own
+ * host thread on its own stream (give each a different stream for the kernels of the
+ * sequences to overlap on the GPU), on the device current for the calling thread.
+ * job.status receives that job's status and job.message its error text.  Returns
+ * ROM_OK, ROM_ENOCONV if some job reported it, or the first (in job order) other error
+ * status.  Returns when every job has finished. */
+typedef struct {
+  rom_operator* op;
+  const rom_mu* params;
+  int K;
+  const int64_t* src_idx;
+  const double* src_scale;
+  int n_src;
+  const int64_t* det_idx;
+  const double* det_scale;
+  int n_det;
+  const double* U0;
+  int k_u;
+  const rom_opts* opts;
+  void* workspace;
+  size_t ws_bytes;
+  rom_basis** basis;
+  double* X_out;
+  rom_record* records;
+  rom_stats* stats;
+  void* stream;
+  rom_status status;      /* out */
+  char message[192];      /* out: error text of this job ("" if none) */
+} rom_sequence_job;
+
+ROM_API rom_status rom_solve_sequences(rom_sequence_job* jobs, int count);
 
 /* Reduced matrices of eq. (newreduced) at parameter p for the basis V (m columns):
  *   Ar (m x m), Er (m x m), Br (m x n_src), Cr (m x n_det): device, column-major.

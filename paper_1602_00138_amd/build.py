@@ -12,7 +12,7 @@ SOURCES = ["stencil.hip", "dense.hip", "gram.hip", "dcg.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fvisibility=hidden", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+         "-fvisibility=hidden", "-pthread", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
 def build(verbose: bool = False) -> str:

@@ -43,6 +43,7 @@ __global__ void k_cg_setup(CGState* cg, CgSetup su, int nb) {
   c->gamma[0] = 0.0;
   c->gamma[1] = 0.0;
   c->pw = 0.0;
+  c->kcur = 0;
 }
 
 // ys[j] = scale * sum_c Ginv[j + c nj] t[c] (Ginv = (U^T A U)^{-1}, symmetric, FP64),
@@ -132,6 +133,7 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t 
   p += y * vstride;
   part2 += y * p2stride;
   const int nj = cg->nj;
+  if (iter == ITER_STATE) iter = cg->kcur;
   const bool first = iter < 0;
   // first row of this thread, loaded ahead of the reduction
   constexpr bool PF = CgPrefetch<T, NJT>::value;
@@ -205,6 +207,7 @@ __global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int6
   part1 += y * p1stride;
   part2 += y * p2stride;
   const int nj = cg->nj;
+  if (iter == ITER_STATE) iter = cg->its;
   constexpr bool PF = CgPrefetch<T, NJT>::value;
   const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
   T a0[PF ? NJT : 1], p0 = T(0), w0 = T(0), g0 = T(0), s0 = T(0);
@@ -229,7 +232,10 @@ __global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int6
     }
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) cg->pw = pw;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cg->pw = pw;
+    cg->kcur = iter;
+  }
   const T alpha = (T)(cg->gamma[iter & 1] / pw);
   T acc[NJT + 1];
 #pragma unroll

@@ -18,8 +18,13 @@ struct CGState {
   int maxit;
   int done;            // 1: stop (converged, maxit, breakdown, or inactive member)
   int flag;            // 0 ok, 1 non-positive curvature, 2 non-finite
-  int pad;
+  int kcur;            // step index of the latest update (read by the direction kernel)
 };
+
+// Step index argument meaning "take it from the CG state": the update uses its, the
+// direction kernel the index the update recorded.  Launches with it can be captured
+// once and replayed.
+constexpr int ITER_STATE = -2;
 
 // Most right-hand sides solved together (members of one batch).
 constexpr int G_MAX = 16;
@@ -196,9 +201,10 @@ void launch_dot2_scale(int64_t n, const double* x, const double* a, const double
 // of W^T A W.  P: blocks per member of the start, update and direction kernels
 // (1 <= P <= dcg_blocks(n)); each thread covers n / (P * block) rows.  Partials (values
 // of T): part1 >= stencil_shape(S, 1024).blocks per member, part2 >= (NJ_MAX + 1) * P
-// per member, at strides p1stride, p2stride.  iter: 0-based step index shared by the batch (-1 for the direction after
-// the start).  cg[y].t holds U_j^T r before the start.  Inactive members (done set at
-// setup) return at once from every kernel.
+// per member, at strides p1stride, p2stride.  iter: 0-based step index shared by the
+// batch (-1 for the direction after the start; ITER_STATE: from the state, see above).
+// cg[y].t holds U_j^T r before the start.  Inactive members (done set at setup) return
+// at once from every kernel.
 int dcg_blocks(int64_t n);
 // the width class (8, 16, 32 or 64 columns) the kernels are compiled for
 int njt_of(int nj);

@@ -7,7 +7,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 #include <string>
+#include <thread>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -52,6 +54,8 @@ constexpr int MAX_SWEEPS = 64;
 // smallest residual reduction asked of one FP32 sweep (about 16 FP32 unit roundoffs:
 // below it the FP32 true residual no longer follows the recursive one)
 constexpr double FP32_GOAL_MIN = 1e-6;
+// CG steps per captured graph
+constexpr int GRAPH_STEPS = 8;
 
 struct Arena {
   char* base;
@@ -267,11 +271,21 @@ class Sequencer {
     chunk_ = o.check_every > 0 ? o.check_every : 16;
     mixed_ = o.precision == ROM_PREC_MIXED;
     tune_ = o.tune != 0;
+    graph_ = o.graph != 0;
     inner_tol_ = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     G_ = std::max(1, std::min(o.group, std::min(G_MAX, n_rhs_)));
   }
 
   int cap() const { return cap_; }
+
+  ~Sequencer() {
+    if (!graphs_.empty()) {
+      // an error may have left replays queued: let them drain first
+      (void)hipStreamSynchronize(st_);
+      for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+    }
+    if (cap_st_) (void)hipStreamDestroy(cap_st_);
+  }
 
   size_t layout(void* base) {
     Arena a(base);
@@ -1205,6 +1219,46 @@ class Sequencer {
     return best;
   }
 
+  // A captured chunk of GRAPH_STEPS CG steps (operator, update, direction) that takes its
+  // step index from the CG state, replayed instead of individual launches.  One graph per
+  // (value type, batch size, shared recycle space, width class, blocks, output vector),
+  // kept for the rest of the call.
+  template <typename T, typename Bufs>
+  hipGraphExec_t chunk_graph(const Bufs& b, int nb, bool shared, int njmax, int P,
+                             int64_t wstride, int64_t gstride, T* dvec, const StencilShape& sh) {
+    const GraphKey key{(int)sizeof(T), nb, shared ? 1 : 0, njt_of(njmax), P, (const void*)dvec};
+    auto it = graphs_.find(key);
+    if (it != graphs_.end()) return it->second;
+    CGState* cg = ctrl_->cg;
+    // captured on a private stream (the caller's may be the legacy default stream, which
+    // cannot capture); the replays run on the caller's stream
+    if (!cap_st_) ROM_HIP(hipStreamCreateWithFlags(&cap_st_, hipStreamNonBlocking));
+    hipStream_t cs = cap_st_;
+    hipGraph_t g = nullptr;
+    ROM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int c = 0; c < GRAPH_STEPS; ++c) {
+        launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, cs);
+        launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, ITER_STATE,
+                             cg, b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, cs);
+        launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_,
+                          ITER_STATE, cg, b.part2, p2s_, nb, P, cs);
+      }
+    } catch (...) {
+      hipGraph_t dummy = nullptr;
+      (void)hipStreamEndCapture(cs, &dummy);
+      if (dummy) (void)hipGraphDestroy(dummy);
+      throw;
+    }
+    ROM_HIP(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw Error(ROM_EHIP, "hipGraphInstantiate failed");
+    graphs_[key] = ex;
+    return ex;
+  }
+
   template <typename T>
   void cg_batch(Batch& bt, const double* rhs, T* dvec) {
     typename std::conditional<std::is_same<T, float>::value, CgBufs32, CgBufs64>::type b;
@@ -1273,8 +1327,22 @@ class Sequencer {
     double gam_before[G_MAX];
     for (int y = 0; y < G_MAX; ++y) gam_before[y] = -1.0;
     int nlive = nact;
+    // CG steps as replays of a captured chunk when asked for and no step kernel is timed
+    const int cg_classes = (1 << ROM_K_SPMV) | (1 << ROM_K_DCG_UPDATE) | (1 << ROM_K_DCG_DIR);
+    const bool graphs = graph_ && !(o_.timing & cg_classes);
     for (;;) {
-      for (int c = 0; c < next; ++c) {
+      if (graphs) {
+        const int reps = (next + GRAPH_STEPS - 1) / GRAPH_STEPS;
+        hipGraphExec_t ex = chunk_graph<T>(b, nb, bt.shared, njmax, P, wstride, gstride, dvec, sh);
+        for (int r = 0; r < reps; ++r) ROM_HIP(hipGraphLaunch(ex, st_));
+        next = reps * GRAPH_STEPS;
+        for (int c = 0; c < next; ++c) {
+          tm_->add(ROM_K_SPMV, nlive * by_apply, nlive * fl_apply);
+          tm_->add(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
+          tm_->add(ROM_K_DCG_DIR, nlive * by_dir, nlive * fl_dir);
+        }
+      }
+      for (int c = 0; c < (graphs ? 0 : next); ++c) {
         const int k = k0 + c;
         tm_->begin(ROM_K_SPMV);
         launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, st_);
@@ -1374,6 +1442,10 @@ class Sequencer {
   int64_t p1s_ = 0, p2s_ = 0;   // per-member strides of the CG partials
   bool mixed_ = false;
   bool tune_ = false;
+  bool graph_ = false;
+  using GraphKey = std::tuple<int, int, int, int, int, const void*>;
+  std::map<GraphKey, hipGraphExec_t> graphs_;
+  hipStream_t cap_st_ = nullptr;   // capture stream of the graphs
   double inner_tol_ = 1e-5;
   hipStream_t st_ = nullptr;
   Timer* tm_ = nullptr;
@@ -1420,6 +1492,7 @@ void check_opts(const rom_opts* o) {
   if (!(o->inner_tol >= 0) || !(o->inner_tol < 1)) throw Error(ROM_EINVAL, "inner_tol must be in [0, 1)");
   if (o->group < 0 || o->group > G_MAX) throw Error(ROM_EINVAL, "group must be in [0, 16]");
   if (o->tune != 0 && o->tune != 1) throw Error(ROM_EINVAL, "tune must be 0 or 1");
+  if (o->graph != 0 && o->graph != 1) throw Error(ROM_EINVAL, "graph must be 0 or 1");
 }
 
 void check_counts(int n_src, int n_det, int k_u, int K) {
@@ -1565,6 +1638,49 @@ rom_status rom_solve_sequence(rom_operator* op, const rom_mu* params, int K,
     *basis = nullptr;
     return s.run(params, src_idx, src_scale, det_idx, det_scale, U0, X_out, records, stats,
                  (hipStream_t)stream, basis);
+  } catch (const Error& e) {
+    return rom::fail(e);
+  } catch (const std::exception& e) {
+    rom::g_err = e.what();
+    return ROM_EHIP;
+  }
+}
+
+rom_status rom_solve_sequences(rom_sequence_job* jobs, int count) {
+  try {
+    if (!jobs || count < 1) throw Error(ROM_EINVAL, "need at least one job");
+    int dev = 0;
+    ROM_HIP(hipGetDevice(&dev));
+    std::vector<std::thread> th;
+    th.reserve(count);
+    for (int q = 0; q < count; ++q) {
+      th.emplace_back([dev, q, jobs]() {
+        rom_sequence_job& j = jobs[q];
+        j.message[0] = 0;
+        if (hipSetDevice(dev) != hipSuccess) {
+          j.status = ROM_EHIP;
+          std::snprintf(j.message, sizeof(j.message), "hipSetDevice failed");
+          return;
+        }
+        j.status = rom_solve_sequence(j.op, j.params, j.K, j.src_idx, j.src_scale, j.n_src,
+                                      j.det_idx, j.det_scale, j.n_det, j.U0, j.k_u, j.opts,
+                                      j.workspace, j.ws_bytes, j.basis, j.X_out, j.records,
+                                      j.stats, j.stream);
+        if (j.status != ROM_OK)
+          std::snprintf(j.message, sizeof(j.message), "%s", rom_last_error());
+      });
+    }
+    for (auto& t : th) t.join();
+    rom_status agg = ROM_OK;
+    for (int q = 0; q < count; ++q) {
+      const rom_status st = jobs[q].status;
+      if (st != ROM_OK && st != ROM_ENOCONV) {
+        rom::g_err = "job " + std::to_string(q) + ": " + jobs[q].message;
+        return st;
+      }
+      if (st == ROM_ENOCONV) agg = ROM_ENOCONV;
+    }
+    return agg;
   } catch (const Error& e) {
     return rom::fail(e);
   } catch (const std::exception& e) {

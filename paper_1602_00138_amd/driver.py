@@ -71,9 +71,10 @@ class Problem:
     def solve(self, points: List[R.MuParams], tol: float, trunc: float = 1e-8, cap: int = 0,
               maxit: int = 0, check_every: int = 0, timing: int = 0,
               keep_X: bool = True, precision: int = R.ROM_PREC_FP64,
-              inner_tol: float = 0.0, group: int = 0, tune: int = 0) -> SequenceResult:
+              inner_tol: float = 0.0, group: int = 0, tune: int = 0,
+              graph: int = 0) -> SequenceResult:
         opts = R.make_opts(tol, trunc, cap, maxit, check_every, timing, precision, inner_tol,
-                           group, tune)
+                           group, tune, graph)
         K = len(points)
         nbytes = R.rom_sequence_bytes(self.op, self.src_idx.size, self.det_idx.size, self.k_u, K, opts)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -111,6 +112,40 @@ class Problem:
         if self.op:
             R.rom_operator_destroy(self.op)
             self.op = 0
+
+
+def solve_many(problems: List["Problem"], points: List[List[R.MuParams]], tol: float,
+               trunc: float = 1e-8, keep_X: bool = False, streams=None,
+               **opt_kw) -> List[SequenceResult]:
+    """Independent sequences (e.g. one per grid) solved concurrently, each on its own
+    stream (created here unless given) and host thread (rom_solve_sequences)."""
+    jobs = []
+    if streams is None:
+        streams = [torch.cuda.Stream(device=p.device) for p in problems]
+    opt_kw = dict(opt_kw)
+    for prob, pts, stream in zip(problems, points, streams):
+        cap = opt_kw.get("cap", 0)
+        opts = R.make_opts(tol, trunc, cap, opt_kw.get("maxit", 0), opt_kw.get("check_every", 0),
+                           opt_kw.get("timing", 0), opt_kw.get("precision", R.ROM_PREC_FP64),
+                           opt_kw.get("inner_tol", 0.0), opt_kw.get("group", 0),
+                           opt_kw.get("tune", 0), opt_kw.get("graph", 0))
+        K = len(pts)
+        nbytes = R.rom_sequence_bytes(prob.op, prob.src_idx.size, prob.det_idx.size, prob.k_u, K,
+                                      opts)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=prob.device)
+        X = torch.empty((K * prob.n_rhs, prob.n), dtype=torch.float64,
+                        device=prob.device) if keep_X else None
+        jobs.append(dict(op=prob.op, params=pts, src_idx=prob.src_idx, src_scale=prob.src_scale,
+                         det_idx=prob.det_idx, det_scale=prob.det_scale, U0=prob.U0, k_u=prob.k_u,
+                         opts=opts, workspace=ws, X_out=X, stream=stream))
+    torch.cuda.synchronize()     # inputs resident before the other streams read them
+    outs = R.rom_solve_sequences(jobs)
+    res = []
+    for jb, (status, basis, records, st) in zip(jobs, outs):
+        n, m = R.rom_basis_dims(basis)
+        res.append(SequenceResult(status, basis, records, R.stats_dict(st), jb["workspace"],
+                                  jb["X_out"], n, m))
+    return res
 
 
 def problem_from_workload(wl, device="cuda:0", k_u: Optional[int] = None) -> Problem:

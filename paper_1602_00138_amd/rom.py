@@ -36,7 +36,7 @@ ROM_NK = 8
 KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "outer", "other"]
 
 EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator", "rom_sequence_bytes",
-            "rom_solve_sequence", "rom_reduced_bytes", "rom_reduced_transfer", "rom_basis_dims",
+            "rom_solve_sequence", "rom_solve_sequences", "rom_reduced_bytes", "rom_reduced_transfer", "rom_basis_dims",
             "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error"]
 
 
@@ -53,7 +53,7 @@ class rom_mu(C.Structure):
 class rom_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("inner_tol", C.c_double),
                 ("cap", C.c_int), ("maxit", C.c_int), ("check_every", C.c_int), ("timing", C.c_int),
-                ("precision", C.c_int), ("group", C.c_int), ("tune", C.c_int)]
+                ("precision", C.c_int), ("group", C.c_int), ("tune", C.c_int), ("graph", C.c_int)]
 
 
 class rom_record(C.Structure):
@@ -69,6 +69,17 @@ class rom_stats(C.Structure):
                 ("n_nonconv", C.c_int), ("total_its", C.c_longlong), ("seconds", C.c_double),
                 ("kernel_ms", C.c_double * ROM_NK), ("kernel_bytes", C.c_double * ROM_NK),
                 ("kernel_flops", C.c_double * ROM_NK), ("kernel_launches", C.c_longlong * ROM_NK)]
+
+
+class rom_sequence_job(C.Structure):
+    _fields_ = [("op", C.c_void_p), ("params", C.POINTER(rom_mu)), ("K", C.c_int),
+                ("src_idx", C.POINTER(C.c_int64)), ("src_scale", C.POINTER(C.c_double)),
+                ("n_src", C.c_int), ("det_idx", C.POINTER(C.c_int64)),
+                ("det_scale", C.POINTER(C.c_double)), ("n_det", C.c_int), ("U0", C.c_void_p),
+                ("k_u", C.c_int), ("opts", C.POINTER(rom_opts)), ("workspace", C.c_void_p),
+                ("ws_bytes", C.c_size_t), ("basis", C.POINTER(C.c_void_p)), ("X_out", C.c_void_p),
+                ("records", C.POINTER(rom_record)), ("stats", C.POINTER(rom_stats)),
+                ("stream", C.c_void_p), ("status", C.c_int), ("message", C.c_char * 192)]
 
 
 class RomError(RuntimeError):
@@ -92,6 +103,7 @@ def _load():
                                          P(C.c_int64), P(C.c_double), C.c_int, vp, C.c_int,
                                          P(rom_opts), vp, sz, P(vp), vp, P(rom_record),
                                          P(rom_stats), vp]),
+        "rom_solve_sequences": (C.c_int, [P(rom_sequence_job), C.c_int]),
         "rom_reduced_bytes": (C.c_int, [vp, P(sz)]),
         "rom_reduced_transfer": (C.c_int, [vp, P(rom_mu), vp, vp, vp, vp, vp, sz, vp]),
         "rom_basis_dims": (C.c_int, [vp, P(C.c_int64), P(C.c_int)]),
@@ -149,9 +161,10 @@ def make_grid(dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float) -> 
 
 def make_opts(tol: float, trunc: float = 1e-8, cap: int = 0, maxit: int = 0,
               check_every: int = 0, timing: int = 0, precision: int = ROM_PREC_FP64,
-              inner_tol: float = 0.0, group: int = 0, tune: int = 0) -> rom_opts:
+              inner_tol: float = 0.0, group: int = 0, tune: int = 0, graph: int = 0) -> rom_opts:
     return rom_opts(float(tol), float(trunc), float(inner_tol), int(cap), int(maxit),
-                    int(check_every), int(timing), int(precision), int(group), int(tune))
+                    int(check_every), int(timing), int(precision), int(group), int(tune),
+                    int(graph))
 
 
 @dataclass
@@ -226,6 +239,61 @@ def rom_solve_sequence(op: int, params: List[MuParams], src_idx, src_scale, det_
         raise err
     return status, basis.value, records, st
 
+
+
+def rom_solve_sequences(jobs: List[dict]):
+    """Run several sequences concurrently (one host thread and one stream each).  Each job
+    is a dict of rom_solve_sequence arguments: op, params, src_idx, src_scale, det_idx,
+    det_scale, U0, k_u, opts, workspace, X_out (or None), stream (or None).  Returns a
+    list of (status, basis handle, records, stats); raises on errors other than
+    ROM_ENOCONV (the error of the first failing job)."""
+    n = len(jobs)
+    arr = (rom_sequence_job * n)()
+    keep = []
+    out = []
+    P = C.POINTER
+    for q, jb in enumerate(jobs):
+        params = jb["params"]
+        K = len(params)
+        mus = (rom_mu * K)(*[p.c_struct() for p in params])
+        si = np.ascontiguousarray(jb["src_idx"], dtype=np.int64)
+        ss = np.ascontiguousarray(jb["src_scale"], dtype=np.float64)
+        di = np.ascontiguousarray(jb["det_idx"], dtype=np.int64)
+        ds = np.ascontiguousarray(jb["det_scale"], dtype=np.float64)
+        recs = (rom_record * (K * (si.size + di.size)))()
+        st = rom_stats()
+        basis = C.c_void_p()
+        opts = jb["opts"]
+        ws = jb["workspace"]
+        keep.append((mus, si, ss, di, ds, recs, st, basis, opts, params))
+        j = arr[q]
+        j.op = jb["op"]
+        j.params = C.cast(mus, P(rom_mu))
+        j.K = K
+        j.src_idx = si.ctypes.data_as(P(C.c_int64))
+        j.src_scale = ss.ctypes.data_as(P(C.c_double))
+        j.n_src = si.size
+        j.det_idx = di.ctypes.data_as(P(C.c_int64))
+        j.det_scale = ds.ctypes.data_as(P(C.c_double))
+        j.n_det = di.size
+        j.U0 = _ptr(jb.get("U0"))
+        j.k_u = int(jb.get("k_u", 0))
+        j.opts = C.pointer(opts)
+        j.workspace = _ptr(ws)
+        j.ws_bytes = ws.numel() * ws.element_size()
+        j.basis = C.pointer(basis)
+        j.X_out = _ptr(jb.get("X_out"))
+        j.records = C.cast(recs, P(rom_record))
+        j.stats = C.pointer(st)
+        j.stream = _stream(jb.get("stream"))
+    status = _lib.rom_solve_sequences(arr, n)
+    for q in range(n):
+        mus, si, ss, di, ds, recs, st, basis, opts, params = keep[q]
+        records = [{f: getattr(r, f) for f, _ in rom_record._fields_} for r in recs]
+        out.append((arr[q].status, basis.value, records, st))
+    if status != ROM_OK and status != ROM_ENOCONV:
+        raise RomError(status, rom_last_error())
+    return out
 
 def rom_reduced_bytes(basis: int) -> int:
     out = C.c_size_t(0)

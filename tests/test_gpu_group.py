@@ -96,3 +96,52 @@ def test_autotuned_shape_parity(drv):
         res.close()
         again.close()
         prob.close()
+
+
+def test_concurrent_sequences_on_uneven_grids(drv):
+    """Independent sequences on grids of different sizes run concurrently (one stream
+    and host thread each): every result is bitwise the one the sequence gives alone, and
+    matches the oracle.  A failing job reports its own error without stopping the rest."""
+    import torch
+    from paper_1602_00138_amd import rom as R
+    wls = [ph.small(3, (10, 11, 12), n_src=3, n_det=3, K=2),
+           ph.small(3, (14, 9, 8), n_src=4, n_det=2, K=3, D="lognormal"),
+           ph.small(2, (30, 21), n_src=3, n_det=4, K=2)]
+    probs = [drv.problem_from_workload(w) for w in wls]
+    pts = [drv.points_from_workload(w) for w in wls]
+    for prec, group in ((R.ROM_PREC_FP64, 1), (R.ROM_PREC_MIXED, 4)):
+        many = drv.solve_many(probs, pts, 1e-10, keep_X=True, precision=prec, group=group)
+        for w, prob, p, res in zip(wls, probs, pts, many):
+            alone = prob.solve(p, 1e-10, w.trunc, precision=prec, group=group)
+            assert torch.equal(res.X, alone.X)
+            assert res.m == alone.m
+            assert [r["its"] for r in res.records] == [r["its"] for r in alone.records]
+            alone.close()
+    orc = OracleProblem(wls[1])
+    ores = orc.run(tol=1e-10)
+    many = drv.solve_many(probs, pts, 1e-10, keep_X=True)
+    _check_sequence(wls[1].replace(tol=1e-10), orc, ores, many[1], probs[1], pts[1])
+    bad = list(pts)
+    bad[1] = [R.MuParams(0.01, np.zeros((1, 3)), np.array([-1.0]), np.array([0.01]))]
+    with pytest.raises(R.RomError) as e:
+        drv.solve_many(probs, bad, 1e-10)
+    assert e.value.status == R.ROM_EINVAL and "job 1" in str(e.value)
+
+
+@pytest.mark.parametrize("precision,group", [(0, 1), (1, 1), (0, 4), (1, 8)])
+def test_graph_replay_equals_eager(drv, precision, group):
+    """CG chunks replayed from a captured HIP graph give bitwise the eager results (the
+    graph is replayed many times per solve, with host polls and other eager work between
+    the replays)."""
+    import torch
+    wl = ph.small(3, (13, 12, 11), n_src=5, n_det=4, K=3, D="lognormal")
+    prob = drv.problem_from_workload(wl)
+    pts = drv.points_from_workload(wl)
+    eager = prob.solve(pts, wl.tol, wl.trunc, precision=precision, group=group)
+    graph = prob.solve(pts, wl.tol, wl.trunc, precision=precision, group=group, graph=1)
+    assert torch.equal(eager.X, graph.X)
+    assert [r["its"] for r in eager.records] == [r["its"] for r in graph.records]
+    assert eager.m == graph.m
+    eager.close()
+    graph.close()
+    prob.close()

@@ -84,6 +84,68 @@ def spmm_bandwidth(prob, point, k: int, reps: int = 5):
                     "the timed call also evaluates mu(p) on the nodes"}
 
 
+def measure_forms(prob, pts, wl, steps: int):
+    """The other forms of the method on the same problem: mixed precision, groups of 8,
+    and both (solves/s over `steps` timed solve_sequence calls after one warm-up)."""
+    import torch
+    from paper_1602_00138_amd import rom as R
+    forms = {"mixed": dict(precision=R.ROM_PREC_MIXED),
+             "fp64_group8": dict(group=8),
+             "mixed_group8": dict(precision=R.ROM_PREC_MIXED, group=8)}
+    out = {}
+    K, n_rhs = len(pts), prob.n_rhs
+    for name, kw in forms.items():
+        kw = dict(kw, tune=1)
+        prob.solve(pts, wl.tol, wl.trunc, keep_X=False, **kw).close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = None
+        for _ in range(steps):
+            if last is not None:
+                last.close()
+            last = prob.solve(pts, wl.tol, wl.trunc, keep_X=False, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = last.stats
+        out[name] = {"value": K * n_rhs * steps / dt, "ms_per_step": 1e3 * dt / steps,
+                     "basis_m": st["m"], "inner_its": st["total_its"], "solved": st["n_solved"],
+                     "nonconverged": st["n_nonconv"]}
+        last.close()
+        log(f"form {name}: {out[name]['value']:.1f} solves/s, m={st['m']}, its={st['total_its']}")
+    return out
+
+
+def measure_concurrent(names, steps: int, **kw):
+    """Independent sequences on uneven grids: solves/s run one after another vs all at
+    once (rom_solve_sequences, one stream and host thread each)."""
+    import torch
+    import phantoms as ph
+    from paper_1602_00138_amd import driver
+    wls = [ph.WORKLOADS[n] for n in names]
+    probs = [driver.problem_from_workload(w) for w in wls]
+    pts = [driver.points_from_workload(w) for w in wls]
+    tol = wls[0].tol
+    total = sum(len(p) * pr.n_rhs for p, pr in zip(pts, probs))
+    for r in driver.solve_many(probs, pts, tol, **kw):
+        r.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for prob, p in zip(probs, pts):
+            prob.solve(p, tol, keep_X=False, **kw).close()
+    torch.cuda.synchronize()
+    serial = total * steps / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for r in driver.solve_many(probs, pts, tol, **kw):
+            r.close()
+    torch.cuda.synchronize()
+    conc = total * steps / (time.perf_counter() - t0)
+    log(f"{'+'.join(names)}: serial {serial:.1f} solves/s, concurrent {conc:.1f} solves/s")
+    return {"workloads": {w.name: "x".join(map(str, w.N[:w.dim])) for w in wls},
+            "solves": total, "serial": serial, "concurrent": conc}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,13 +155,17 @@ def main():
     ap.add_argument("--points", type=int, default=0, help="parameter points (0: the workload's)")
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--mode", default="independent", choices=["independent", "drift"])
-    ap.add_argument("--cpu-sample", type=int, default=4, help="oracle sample RHS (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="oracle sample RHS (0: skip)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="fp64: plain FP64 recycled CG; mixed: FP32 inner sweeps in FP64 refinement")
     ap.add_argument("--group", type=int, default=1,
                     help="right-hand sides per batch (1: the paper's order, up to 16)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the CG launch shape (0/1)")
     ap.add_argument("--graph", type=int, default=0, help="replay CG steps from captured HIP graphs")
+    ap.add_argument("--forms", type=int, default=1,
+                    help="also time the mixed / grouped forms on the same problem (0/1)")
+    ap.add_argument("--suite", type=int, default=0,
+                    help="also time the uneven-grid workload (48^3, 64^3, 96^3 sequences)")
     ap.add_argument("--kernel", default="outer",
                     help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
                          "k_gemvn<false>; auto: the class with the most event time)")
@@ -207,6 +273,16 @@ def main():
     spmm = spmm_bandwidth(prob, pts[-1], 64)
     log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s)")
 
+    forms = measure_forms(prob, pts, wl, args.steps) if args.forms else None
+    if forms:
+        for f in forms.values():
+            f["vs_plain_fp64"] = f["value"] / value
+    suite = None
+    if args.suite:
+        from paper_1602_00138_amd import rom as R2
+        suite = measure_concurrent(["cfg3a", "cfg3b", "cfg3c"], 1, precision=R2.ROM_PREC_MIXED,
+                                   group=8, tune=1)
+
     cpu = None
     if args.cpu_sample > 0:
         cpu = cpu_baseline(wl, ph.parameter_points(wl, mode=args.mode), args.cpu_sample)
@@ -229,6 +305,8 @@ def main():
                    "solved": last["n_solved"], "nonconverged": bad},
         "roofline": roof,
         "spmm": spmm,
+        "forms": forms,
+        "uneven_grids": suite,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

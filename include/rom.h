@@ -245,6 +245,41 @@ ROM_API rom_status rom_reduced_transfer(const rom_basis* V, const rom_mu* p, dou
 ROM_API rom_status rom_basis_dims(const rom_basis* V, int64_t* N, int* m);
 ROM_API rom_status rom_basis_copy(const rom_basis* V, double* dst, void* stream);
 
+/* ---- Learned seed (not in the paper) -------------------------------------------------
+ * A small 3D convolutional network on an nx x ny x nz grid (each a positive multiple of
+ * 8): 4 levels (16, 32, 48, 64 channels), 3x3x3 convolutions with zero padding, 2x2x2
+ * average pooling, 2x nearest upsampling, additive skips, ReLU:
+ *   e0 = relu(conv(x; 3->16)), e1 = relu(conv(pool(e0); 16->32)),
+ *   e2 = relu(conv(pool(e1); 32->48)), e3 = relu(conv(pool(e2); 48->64)),
+ *   d2 = relu(conv(up(e3); 64->48) + e2), d1 = relu(conv(up(d2); 48->32) + e1),
+ *   d0 = relu(conv(up(d1); 32->16) + e0), y = conv(d0; 16->1).
+ * Weights and activations are BF16 with FP32 accumulation (matrix cores); the master
+ * parameters, gradients and Adam moments are FP32.  Parameters (host or device arrays
+ * of nparams floats): per layer in the order e0 e1 e2 e3 d2 d1 d0 y, the weights
+ * w[o][i][a][b][c] (multiplying input channel i at offset (a-1, b-1, c-1) in (z, y, x))
+ * then the biases b[o].
+ * Inputs: device FP32 [batch][3][N] (fields in the grid's x-fastest order); outputs and
+ * targets: device FP32 [batch][N].  The loss is the mean over batch and voxels of
+ * (y - target)^2.  Memory is caller-owned: param_mem (>= param_bytes) and work_mem
+ * (>= work_bytes, sized for up to `batch` samples per call), 256-byte aligned. */
+typedef struct rom_seednet rom_seednet;
+ROM_API rom_status rom_seednet_bytes(int nx, int ny, int nz, int batch, int64_t* nparams,
+                             size_t* param_bytes, size_t* work_bytes);
+ROM_API rom_status rom_seednet_create(int nx, int ny, int nz, int batch, const float* params,
+                              void* param_mem, size_t param_bytes, void* work_mem,
+                              size_t work_bytes, rom_seednet** net, void* stream);
+ROM_API rom_status rom_seednet_forward(rom_seednet* net, const float* in, float* out, int batch,
+                               void* stream);
+/* Loss and gradient (host array of nparams floats, or NULL) at the current parameters. */
+ROM_API rom_status rom_seednet_gradients(rom_seednet* net, const float* in, const float* target,
+                                 int batch, float* grads, double* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch; *loss (if not NULL)
+ * receives the loss before the step. */
+ROM_API rom_status rom_seednet_train_step(rom_seednet* net, const float* in, const float* target,
+                                  int batch, float lr, double* loss, void* stream);
+ROM_API rom_status rom_seednet_params(const rom_seednet* net, float* params, void* stream);
+ROM_API void rom_seednet_destroy(rom_seednet* net);
+
 ROM_API void rom_operator_destroy(rom_operator* op);
 ROM_API void rom_basis_destroy(rom_basis* V);
 ROM_API const char* rom_last_error(void);

@@ -228,6 +228,44 @@ void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int 
                        const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
                        int nb, int P, hipStream_t st);
 
+// Error reporting shared by the entry points of every subsystem (sets rom_last_error).
+rom_status report(const Error& e);
+void report_message(const std::string& m);
+
+// ---- learned seed (3D convolutional network, BF16 with FP32 accumulation) -----------
+// Activations: voxel-major BF16 with Cp channels (Cp a multiple of 8, pads zero); GEMM
+// weights: BF16 [rows = round_up(cout, 16)][Kp = round_up(27 Cpi, 32)].
+int seed_round8(int c);
+int seed_kp(int cp);
+void launch_seed_conv(int nx, int ny, int nz, int batch, const void* X, int Cpi, const void* W,
+                      int Kp, int Cout, int rows, const float* bias, const void* skip, int relu,
+                      void* Y, int Cpo, hipStream_t st);
+size_t seed_wgrad_partials(int nx, int ny, int nz, int batch, int rows, int Kp);
+void launch_seed_wgrad(int nx, int ny, int nz, int batch, const void* X, int Cpi, const void* dZ,
+                       int Cpo, int Cout, int rows, int Kp, float* P, float* dWg, float* Pb,
+                       float* db, hipStream_t st);
+void launch_seed_pool(int nx, int ny, int nz, int batch, const void* X, void* Y, int C,
+                      hipStream_t st);
+void launch_seed_pool_bwd(int nx, int ny, int nz, int batch, const void* dY, void* dX, int C,
+                          int acc, hipStream_t st);
+void launch_seed_up(int nx, int ny, int nz, int batch, const void* X, void* Y, int C,
+                    hipStream_t st);
+void launch_seed_up_bwd(int nx, int ny, int nz, int batch, const void* dY, void* dX, int C,
+                        hipStream_t st);
+void launch_seed_relu_bwd(int64_t ne, void* dY, const void* Y, hipStream_t st);
+void launch_seed_add(int64_t ne, void* out, const void* in, hipStream_t st);
+void launch_seed_pack_input(int64_t nvox, int batch, int cin, const float* in, void* X, int Cp,
+                            hipStream_t st);
+void launch_seed_unpack_output(int64_t ne, const void* Y, int Cp, float* out, hipStream_t st);
+void launch_seed_mse(int64_t ne, const void* Y, int Cp, const float* tgt, void* dY,
+                     double* partials, double* loss, hipStream_t st);
+void launch_seed_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                      float b2, float c1, float c2, float eps, hipStream_t st);
+void launch_seed_pack_weights(const float* w, int cout, int cin, int Cpi, int Kp, int rows,
+                              void* Wb, int Cpo, int Ktp, int rowst, void* Wt, hipStream_t st);
+void launch_seed_unpack_wgrad(const float* dWg, int Kp, int cout, int cin, int Cpi, float* dw,
+                              hipStream_t st);
+
 // ---- mixed form -----------------------------------------------------------------------
 // out[i] = (float) in[i], i < n.
 void launch_cast_f32(int64_t n, const double* in, float* out, hipStream_t st);

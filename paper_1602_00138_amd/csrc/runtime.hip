@@ -1503,6 +1503,10 @@ void check_counts(int n_src, int n_det, int k_u, int K) {
 }
 
 }  // namespace
+
+rom_status report(const Error& e) { return fail(e); }
+void report_message(const std::string& m) { g_err = m; }
+
 }  // namespace rom
 
 using rom::Error;

@@ -1,0 +1,502 @@
+// Kernels of the learned-seed network (a small 3D convolutional network in BF16 with
+// FP32 accumulation; not part of the paper).  Activations are stored voxel-major with
+// the channels contiguous: X[v][c], v = x + nx (y + ny (z + nz b)) over a batch of grids,
+// c < Cp (Cp a multiple of 8; padded channels hold zeros).  A 3x3x3 convolution with zero
+// padding is an implicit GEMM
+//     Y[v][o] = sum_k A[v][k] W[o][k],   k = tap * Cp_in + c,  A[v][k] = X[nbr(v, tap)][c],
+// evaluated on the matrix cores (v_mfma_f32_16x16x32_bf16: a wave owns 16 voxels and
+// 16-channel output tiles; the 8 consecutive k a lane supplies lie in one tap, so its A
+// operand is one 16-byte load of a neighbour's channels).  The data gradient is the same
+// convolution with the weights flipped in space and transposed in channels; the weight
+// gradient reduces over voxels in LDS-staged 32-voxel steps, split over voxel chunks.
+#include "kernels.h"
+
+namespace rom {
+
+namespace {
+
+constexpr int BS = 256;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+struct Grid3 {
+  int nx, ny, nz, batch;
+};
+
+// neighbour of voxel v at tap t (0..26, t = (dz+1) 9 + (dy+1) 3 + (dx+1)), or -1 outside
+__device__ __forceinline__ int64_t neighbour(const Grid3& g, int64_t v, int t) {
+  const int x = (int)(v % g.nx);
+  const int64_t r = v / g.nx;
+  const int y = (int)(r % g.ny);
+  const int64_t r2 = r / g.ny;
+  const int z = (int)(r2 % g.nz);
+  const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+  const int xx = x + dx, yy = y + dy, zz = z + dz;
+  if (xx < 0 || xx >= g.nx || yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz) return -1;
+  return v + dx + (int64_t)g.nx * (dy + (int64_t)g.ny * dz);
+}
+
+// Convolution: Y = act(conv(X; W) + bias + skip).  W: [cop16][Kp] BF16 (zero beyond K =
+// 27 Cpi and beyond Cout), NT = cop16 / 16 output tiles.  Writes channels < Cpo of Y
+// (zeros for Cout <= c < Cpo).
+template <int NT>
+__global__ __launch_bounds__(BS) void k_conv(Grid3 g, const __bf16* __restrict__ X, int Cpi,
+                                             const __bf16* __restrict__ W, int Kp, int Cout,
+                                             const float* __restrict__ bias,
+                                             const __bf16* __restrict__ skip, int relu,
+                                             __bf16* __restrict__ Y, int Cpo) {
+  const int64_t nv = (int64_t)g.nx * g.ny * g.nz * g.batch;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t v0 = (int64_t)blockIdx.x * 64 + wid * 16;
+  const int64_t va = v0 + (lane & 15);   // this lane's A row
+  const int kg = lane >> 4;              // which 8 of the 32 k of a step
+  const int K = 27 * Cpi;
+  float4_t acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = (float4_t){0.f, 0.f, 0.f, 0.f};
+  const bool rowok = va < nv;
+  for (int k0 = 0; k0 < Kp; k0 += 32) {
+    const int k = k0 + 8 * kg;
+    bf16x8 a;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = (__bf16)0.f;
+    if (rowok && k < K) {
+      const int tap = k / Cpi, c = k % Cpi;
+      const int64_t nb = neighbour(g, va, tap);
+      if (nb >= 0) a = *reinterpret_cast<const bf16x8*>(X + nb * Cpi + c);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(W + (int64_t)(16 * t + (lane & 15)) * Kp + k);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  // D layout: register r of a lane holds row 4 (lane / 16) + r, column lane % 16
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int o = 16 * t + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t v = v0 + 4 * kg + r;
+      if (v >= nv || o >= Cpo) continue;
+      float val = 0.f;
+      if (o < Cout) {
+        val = acc[t][r] + (bias ? bias[o] : 0.f);
+        if (skip) val += (float)skip[v * Cpo + o];
+        if (relu) val = fmaxf(val, 0.f);
+      }
+      Y[v * Cpo + o] = (__bf16)val;
+    }
+  }
+}
+
+// Weight gradient partials: P[chunk][o][k] = sum over the chunk's voxels of
+// dZ[v][o] A[v][k] for o in the block's 16-channel tile and k in its 64-wide slice (one
+// 16-wide tile per wave); 32 voxels are staged in LDS per step.
+constexpr int WG_VOX = 2048;   // voxels per chunk
+__global__ __launch_bounds__(BS) void k_conv_wgrad(Grid3 g, const __bf16* __restrict__ X,
+                                                   int Cpi, const __bf16* __restrict__ dZ,
+                                                   int Cpo, int Kp, float* __restrict__ P) {
+  __shared__ __bf16 Zs[32][16 + 2];
+  __shared__ __bf16 As[32][64 + 8];
+  const int64_t nv = (int64_t)g.nx * g.ny * g.nz * g.batch;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int o0 = blockIdx.z * 16;
+  const int kb = blockIdx.y * 64;
+  const int K = 27 * Cpi;
+  const int64_t vbeg = (int64_t)blockIdx.x * WG_VOX;
+  const int64_t vend = min<int64_t>(vbeg + WG_VOX, nv);
+  float4_t acc = (float4_t){0.f, 0.f, 0.f, 0.f};
+  // staging maps: dZ: thread -> (voxel t/8, channels 2 (t%8) .. +1); A: thread -> (voxel
+  // t/8, k 8 (t%8) .. +7)
+  const int zr = threadIdx.x >> 3, zc = 2 * (threadIdx.x & 7);
+  const int ar = threadIdx.x >> 3, ac = 8 * (threadIdx.x & 7);
+  for (int64_t vs = vbeg; vs < vend; vs += 32) {
+    {
+      const int64_t v = vs + zr;
+      __bf16 z0 = (__bf16)0.f, z1 = (__bf16)0.f;
+      if (v < vend) {
+        if (o0 + zc < Cpo) z0 = dZ[v * Cpo + o0 + zc];
+        if (o0 + zc + 1 < Cpo) z1 = dZ[v * Cpo + o0 + zc + 1];
+      }
+      Zs[zr][zc] = z0;
+      Zs[zr][zc + 1] = z1;
+    }
+    {
+      const int64_t v = vs + ar;
+      const int k = kb + ac;
+      bf16x8 a;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = (__bf16)0.f;
+      if (v < vend && k < K) {
+        const int tap = k / Cpi, c = k % Cpi;
+        const int64_t nb = neighbour(g, v, tap);
+        if (nb >= 0) a = *reinterpret_cast<const bf16x8*>(X + nb * Cpi + c);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[ar][ac + q] = a[q];
+    }
+    __syncthreads();
+    // A operand: A[i = o][kk = voxel]; B operand: B[kk = voxel][j = k]
+    bf16x8 am, bm;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      am[q] = Zs[8 * (lane >> 4) + q][lane & 15];
+      bm[q] = As[8 * (lane >> 4) + q][16 * wid + (lane & 15)];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc, 0, 0, 0);
+    __syncthreads();
+  }
+  float* Pc = P + (int64_t)blockIdx.x * (gridDim.z * 16) * Kp;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int o = o0 + 4 * (lane >> 4) + r;
+    const int k = kb + 16 * wid + (lane & 15);
+    if (k < Kp) Pc[(int64_t)o * Kp + k] = acc[r];
+  }
+}
+
+// dW[o][k] (+)= sum over chunks of P[chunk][o][k]; bias partials likewise.
+__global__ void k_wgrad_reduce(const float* __restrict__ P, int nchunk, int rows, int Kp,
+                               float* __restrict__ dW, int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t ne = (int64_t)rows * Kp;
+  if (e >= ne) return;
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += P[(int64_t)c * ne + e];
+  dW[e] = accumulate ? dW[e] + s : s;
+}
+
+// Bias gradient partials: Pb[chunk][o] = sum over the chunk's voxels of dZ[v][o].
+__global__ void k_bias_grad(int64_t nv, const __bf16* __restrict__ dZ, int Cpo, int Cout,
+                            float* __restrict__ Pb) {
+  __shared__ float sh[BS];
+  const int o = blockIdx.y;
+  float s = 0.f;
+  const int64_t vbeg = (int64_t)blockIdx.x * WG_VOX;
+  const int64_t vend = min<int64_t>(vbeg + WG_VOX, nv);
+  for (int64_t v = vbeg + threadIdx.x; v < vend; v += BS) s += (float)dZ[v * Cpo + o];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = BS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) Pb[(int64_t)blockIdx.x * Cout + o] = sh[0];
+}
+
+// 2x2x2 average pooling and its adjoint; 2x nearest upsampling and its adjoint.
+// g: the fine grid.  acc: add into the output instead of overwriting.
+__global__ void k_pool(Grid3 g, const __bf16* __restrict__ X, __bf16* __restrict__ Y, int C) {
+  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
+  const int64_t nc = (int64_t)cx * cy * cz * g.batch;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= nc * C) return;
+  const int c = (int)(e % C);
+  const int64_t vc = e / C;
+  const int x = (int)(vc % cx);
+  const int y = (int)((vc / cx) % cy);
+  const int64_t zb = vc / ((int64_t)cx * cy);   // z + cz * b
+  const int z = (int)(zb % cz);
+  const int64_t b = zb / cz;
+  float s = 0.f;
+  for (int d = 0; d < 8; ++d) {
+    const int64_t v = (2 * x + (d & 1)) +
+                      (int64_t)g.nx * ((2 * y + ((d >> 1) & 1)) +
+                                       (int64_t)g.ny * ((2 * z + (d >> 2)) + (int64_t)g.nz * b));
+    s += (float)X[v * C + c];
+  }
+  Y[vc * C + c] = (__bf16)(0.125f * s);
+}
+
+__global__ void k_pool_bwd(Grid3 g, const __bf16* __restrict__ dY, __bf16* __restrict__ dX, int C,
+                           int acc) {
+  const int64_t nv = (int64_t)g.nx * g.ny * g.nz * g.batch;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= nv * C) return;
+  const int c = (int)(e % C);
+  const int64_t v = e / C;
+  const int x = (int)(v % g.nx);
+  const int y = (int)((v / g.nx) % g.ny);
+  const int64_t zb = v / ((int64_t)g.nx * g.ny);
+  const int z = (int)(zb % g.nz);
+  const int64_t b = zb / g.nz;
+  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
+  const int64_t vc = (x / 2) + (int64_t)cx * ((y / 2) + (int64_t)cy * ((z / 2) + (int64_t)cz * b));
+  float val = 0.125f * (float)dY[vc * C + c];
+  if (acc) val += (float)dX[e];
+  dX[e] = (__bf16)val;
+}
+
+__global__ void k_up(Grid3 g, const __bf16* __restrict__ X, __bf16* __restrict__ Y, int C) {
+  const int64_t nv = (int64_t)g.nx * g.ny * g.nz * g.batch;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= nv * C) return;
+  const int c = (int)(e % C);
+  const int64_t v = e / C;
+  const int x = (int)(v % g.nx);
+  const int y = (int)((v / g.nx) % g.ny);
+  const int64_t zb = v / ((int64_t)g.nx * g.ny);
+  const int z = (int)(zb % g.nz);
+  const int64_t b = zb / g.nz;
+  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
+  const int64_t vc = (x / 2) + (int64_t)cx * ((y / 2) + (int64_t)cy * ((z / 2) + (int64_t)cz * b));
+  Y[e] = X[vc * C + c];
+}
+
+__global__ void k_up_bwd(Grid3 g, const __bf16* __restrict__ dY, __bf16* __restrict__ dX, int C) {
+  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
+  const int64_t nc = (int64_t)cx * cy * cz * g.batch;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= nc * C) return;
+  const int c = (int)(e % C);
+  const int64_t vc = e / C;
+  const int x = (int)(vc % cx);
+  const int y = (int)((vc / cx) % cy);
+  const int64_t zb = vc / ((int64_t)cx * cy);
+  const int z = (int)(zb % cz);
+  const int64_t b = zb / cz;
+  float s = 0.f;
+  for (int d = 0; d < 8; ++d) {
+    const int64_t v = (2 * x + (d & 1)) +
+                      (int64_t)g.nx * ((2 * y + ((d >> 1) & 1)) +
+                                       (int64_t)g.ny * ((2 * z + (d >> 2)) + (int64_t)g.nz * b));
+    s += (float)dY[v * C + c];
+  }
+  dX[e] = (__bf16)s;
+}
+
+// dZ = dY * (Y > 0) in place on dY
+__global__ void k_relu_bwd(int64_t ne, __bf16* __restrict__ dY, const __bf16* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e < ne && !((float)Y[e] > 0.f)) dY[e] = (__bf16)0.f;
+}
+
+// out += in (elementwise, bf16 storage, FP32 add)
+__global__ void k_add(int64_t ne, __bf16* __restrict__ out, const __bf16* __restrict__ in) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e < ne) out[e] = (__bf16)((float)out[e] + (float)in[e]);
+}
+
+// Input fields (FP32, [b][c][v], c < cin) -> BF16 activations [b v][Cp] (pads zero).
+__global__ void k_pack_input(int64_t nvox, int batch, int cin, const float* __restrict__ in,
+                             __bf16* __restrict__ X, int Cp) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= nvox * batch * Cp) return;
+  const int c = (int)(e % Cp);
+  const int64_t vb = e / Cp;
+  const int64_t b = vb / nvox, v = vb % nvox;
+  X[e] = (__bf16)(c < cin ? in[(b * cin + c) * nvox + v] : 0.f);
+}
+
+// Channel 0 of the output -> FP32 [b][v]
+__global__ void k_unpack_output(int64_t ne, const __bf16* __restrict__ Y, int Cp,
+                                float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e < ne) out[e] = (float)Y[e * Cp];
+}
+
+// MSE on channel 0: partial sums of (y - t)^2 / count per block, dY = 2 (y - t) / count.
+__global__ void k_mse(int64_t ne, const __bf16* __restrict__ Y, int Cp,
+                      const float* __restrict__ tgt, double inv_count, __bf16* __restrict__ dY,
+                      double* __restrict__ partials) {
+  double v[1] = {0.0};
+  for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < ne; e += (int64_t)gridDim.x * BS) {
+    const double d = (double)(float)Y[e * Cp] - (double)tgt[e];
+    v[0] += d * d * inv_count;
+    dY[e * Cp] = (__bf16)(float)(2.0 * d * inv_count);
+    for (int c = 1; c < Cp; ++c) dY[e * Cp + c] = (__bf16)0.f;
+  }
+  write_partials<1, BS>(v, partials, blockIdx.x);
+}
+
+// Adam (Kingma & Ba) on FP32 master parameters; c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+__global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
+                       float c1, float c2, float eps) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= n) return;
+  const float gi = g[e];
+  const float mi = b1 * m[e] + (1.f - b1) * gi;
+  const float vi = b2 * v[e] + (1.f - b2) * gi * gi;
+  m[e] = mi;
+  v[e] = vi;
+  p[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// FP32 layer weights (oracle order w[o][i][a][b][c]) -> BF16 GEMM weights
+// Wb[o][tap Cpi + i] (zeros beyond) and the data-gradient weights
+// Wt[i][tap' Cpo + o] = w[o][i][26 - tap'] (spatially flipped, channels transposed).
+__global__ void k_pack_weights(const float* __restrict__ w, int cout, int cin, int Cpi, int Kp,
+                               int rows, __bf16* __restrict__ Wb, int Cpo, int Ktp, int rowst,
+                               __bf16* __restrict__ Wt) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t n1 = (int64_t)rows * Kp, n2 = (int64_t)rowst * Ktp;
+  if (e < n1) {
+    const int o = (int)(e / Kp), k = (int)(e % Kp);
+    float val = 0.f;
+    if (o < cout && k < 27 * Cpi) {
+      const int tap = k / Cpi, i = k % Cpi;
+      if (i < cin) val = w[((int64_t)o * cin + i) * 27 + tap];
+    }
+    Wb[e] = (__bf16)val;
+  } else if (e < n1 + n2) {
+    const int64_t f = e - n1;
+    const int i = (int)(f / Ktp), k = (int)(f % Ktp);
+    float val = 0.f;
+    if (i < cin && k < 27 * Cpo) {
+      const int tap = k / Cpo, o = k % Cpo;
+      if (o < cout) val = w[((int64_t)o * cin + i) * 27 + (26 - tap)];
+    }
+    Wt[f] = (__bf16)val;
+  }
+}
+
+// GEMM-layout weight gradient dWg[o][tap Cpi + i] -> oracle order dw[o][i][tap] (added).
+__global__ void k_unpack_wgrad(const float* __restrict__ dWg, int Kp, int cout, int cin, int Cpi,
+                               float* __restrict__ dw) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= (int64_t)cout * cin * 27) return;
+  const int tap = (int)(e % 27);
+  const int i = (int)((e / 27) % cin);
+  const int o = (int)(e / (27 * cin));
+  dw[e] += dWg[(int64_t)o * Kp + tap * Cpi + i];
+}
+
+int gridn(int64_t n) { return (int)ceil_div(n, BS); }
+
+}  // namespace
+
+int seed_round8(int c) { return (c + 7) / 8 * 8; }
+int seed_kp(int cp) { return (27 * cp + 31) / 32 * 32; }
+
+void launch_seed_conv(int nx, int ny, int nz, int batch, const void* X, int Cpi, const void* W,
+                      int Kp, int Cout, int rows, const float* bias, const void* skip, int relu,
+                      void* Y, int Cpo, hipStream_t st) {
+  const Grid3 g{nx, ny, nz, batch};
+  const int64_t nv = (int64_t)nx * ny * nz * batch;
+  const dim3 grid(ceil_div(nv, 64));
+  const __bf16* x = (const __bf16*)X;
+  const __bf16* w = (const __bf16*)W;
+  const __bf16* sk = (const __bf16*)skip;
+  __bf16* y = (__bf16*)Y;
+  switch (rows / 16) {
+#define C(N) case N: ROM_LAUNCH((k_conv<N>), grid, dim3(BS), 0, st, g, x, Cpi, w, Kp, Cout, bias, sk, relu, y, Cpo); break;
+    C(1) C(2) C(3) C(4)
+#undef C
+    default: throw Error(ROM_EINVAL, "seed conv: at most 64 output channels");
+  }
+  ROM_CHECK_LAUNCH();
+}
+
+size_t seed_wgrad_partials(int nx, int ny, int nz, int batch, int rows, int Kp) {
+  const int64_t nv = (int64_t)nx * ny * nz * batch;
+  return (size_t)ceil_div(nv, WG_VOX) * rows * Kp;
+}
+
+void launch_seed_wgrad(int nx, int ny, int nz, int batch, const void* X, int Cpi, const void* dZ,
+                       int Cpo, int Cout, int rows, int Kp, float* P, float* dWg, float* Pb,
+                       float* db, hipStream_t st) {
+  const Grid3 g{nx, ny, nz, batch};
+  const int64_t nv = (int64_t)nx * ny * nz * batch;
+  const int nch = (int)ceil_div(nv, WG_VOX);
+  ROM_LAUNCH(k_conv_wgrad, dim3(nch, ceil_div(Kp, 64), rows / 16), dim3(BS), 0, st, g,
+             (const __bf16*)X, Cpi, (const __bf16*)dZ, Cpo, Kp, P);
+  ROM_CHECK_LAUNCH();
+  ROM_LAUNCH(k_wgrad_reduce, dim3(gridn((int64_t)rows * Kp)), dim3(BS), 0, st, P, nch, rows, Kp,
+             dWg, 0);
+  ROM_CHECK_LAUNCH();
+  ROM_LAUNCH(k_bias_grad, dim3(nch, Cout), dim3(BS), 0, st, nv, (const __bf16*)dZ, Cpo, Cout, Pb);
+  ROM_CHECK_LAUNCH();
+  // db[o] += sum over chunks
+  ROM_LAUNCH(k_wgrad_reduce, dim3(gridn(Cout)), dim3(BS), 0, st, Pb, nch, 1, Cout, db, 1);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_pool(int nx, int ny, int nz, int batch, const void* X, void* Y, int C,
+                      hipStream_t st) {
+  const Grid3 g{nx, ny, nz, batch};
+  const int64_t n = (int64_t)(nx / 2) * (ny / 2) * (nz / 2) * batch * C;
+  ROM_LAUNCH(k_pool, dim3(gridn(n)), dim3(BS), 0, st, g, (const __bf16*)X, (__bf16*)Y, C);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_pool_bwd(int nx, int ny, int nz, int batch, const void* dY, void* dX, int C,
+                          int acc, hipStream_t st) {
+  const Grid3 g{nx, ny, nz, batch};
+  const int64_t n = (int64_t)nx * ny * nz * batch * C;
+  ROM_LAUNCH(k_pool_bwd, dim3(gridn(n)), dim3(BS), 0, st, g, (const __bf16*)dY, (__bf16*)dX, C,
+             acc);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_up(int nx, int ny, int nz, int batch, const void* X, void* Y, int C,
+                    hipStream_t st) {
+  const Grid3 g{nx, ny, nz, batch};
+  const int64_t n = (int64_t)nx * ny * nz * batch * C;
+  ROM_LAUNCH(k_up, dim3(gridn(n)), dim3(BS), 0, st, g, (const __bf16*)X, (__bf16*)Y, C);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_up_bwd(int nx, int ny, int nz, int batch, const void* dY, void* dX, int C,
+                        hipStream_t st) {
+  const Grid3 g{nx, ny, nz, batch};
+  const int64_t n = (int64_t)(nx / 2) * (ny / 2) * (nz / 2) * batch * C;
+  ROM_LAUNCH(k_up_bwd, dim3(gridn(n)), dim3(BS), 0, st, g, (const __bf16*)dY, (__bf16*)dX, C);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_relu_bwd(int64_t ne, void* dY, const void* Y, hipStream_t st) {
+  ROM_LAUNCH(k_relu_bwd, dim3(gridn(ne)), dim3(BS), 0, st, ne, (__bf16*)dY, (const __bf16*)Y);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_add(int64_t ne, void* out, const void* in, hipStream_t st) {
+  ROM_LAUNCH(k_add, dim3(gridn(ne)), dim3(BS), 0, st, ne, (__bf16*)out, (const __bf16*)in);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_pack_input(int64_t nvox, int batch, int cin, const float* in, void* X, int Cp,
+                            hipStream_t st) {
+  ROM_LAUNCH(k_pack_input, dim3(gridn(nvox * batch * Cp)), dim3(BS), 0, st, nvox, batch, cin, in,
+             (__bf16*)X, Cp);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_unpack_output(int64_t ne, const void* Y, int Cp, float* out, hipStream_t st) {
+  ROM_LAUNCH(k_unpack_output, dim3(gridn(ne)), dim3(BS), 0, st, ne, (const __bf16*)Y, Cp, out);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_mse(int64_t ne, const void* Y, int Cp, const float* tgt, void* dY,
+                     double* partials, double* loss, hipStream_t st) {
+  int grid = gridn(ne);
+  if (grid > 1024) grid = 1024;
+  ROM_LAUNCH(k_mse, dim3(grid), dim3(BS), 0, st, ne, (const __bf16*)Y, Cp, tgt, 1.0 / (double)ne,
+             (__bf16*)dY, partials);
+  ROM_CHECK_LAUNCH();
+  launch_reduce_finish(partials, grid, 1, loss, st);
+}
+
+void launch_seed_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                      float b2, float c1, float c2, float eps, hipStream_t st) {
+  ROM_LAUNCH(k_adam, dim3(gridn(n)), dim3(BS), 0, st, n, p, g, m, v, lr, b1, b2, c1, c2, eps);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_pack_weights(const float* w, int cout, int cin, int Cpi, int Kp, int rows,
+                              void* Wb, int Cpo, int Ktp, int rowst, void* Wt, hipStream_t st) {
+  const int64_t n = (int64_t)rows * Kp + (int64_t)rowst * Ktp;
+  ROM_LAUNCH(k_pack_weights, dim3(gridn(n)), dim3(BS), 0, st, w, cout, cin, Cpi, Kp, rows,
+             (__bf16*)Wb, Cpo, Ktp, rowst, (__bf16*)Wt);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_unpack_wgrad(const float* dWg, int Kp, int cout, int cin, int Cpi, float* dw,
+                              hipStream_t st) {
+  ROM_LAUNCH(k_unpack_wgrad, dim3(gridn((int64_t)cout * cin * 27)), dim3(BS), 0, st, dWg, Kp, cout,
+             cin, Cpi, dw);
+  ROM_CHECK_LAUNCH();
+}
+
+}  // namespace rom

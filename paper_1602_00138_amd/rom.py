@@ -37,7 +37,10 @@ KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "ou
 
 EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator", "rom_sequence_bytes",
             "rom_solve_sequence", "rom_solve_sequences", "rom_reduced_bytes", "rom_reduced_transfer", "rom_basis_dims",
-            "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error"]
+            "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error",
+            "rom_seednet_bytes", "rom_seednet_create", "rom_seednet_forward",
+            "rom_seednet_gradients", "rom_seednet_train_step", "rom_seednet_params",
+            "rom_seednet_destroy"]
 
 
 class rom_grid(C.Structure):
@@ -111,6 +114,15 @@ def _load():
         "rom_operator_destroy": (None, [vp]),
         "rom_basis_destroy": (None, [vp]),
         "rom_last_error": (C.c_char_p, []),
+        "rom_seednet_bytes": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_int64), P(sz),
+                                        P(sz)]),
+        "rom_seednet_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_float), vp, sz,
+                                         vp, sz, P(vp), vp]),
+        "rom_seednet_forward": (C.c_int, [vp, vp, vp, C.c_int, vp]),
+        "rom_seednet_gradients": (C.c_int, [vp, vp, vp, C.c_int, P(C.c_float), P(C.c_double), vp]),
+        "rom_seednet_train_step": (C.c_int, [vp, vp, vp, C.c_int, C.c_float, P(C.c_double), vp]),
+        "rom_seednet_params": (C.c_int, [vp, P(C.c_float), vp]),
+        "rom_seednet_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -335,3 +347,53 @@ def stats_dict(st: rom_stats) -> dict:
                                         "launches": int(st.kernel_launches[k])}
                     for k in range(ROM_NK)}
     return d
+
+
+# ---- learned seed network ---------------------------------------------------------------
+
+def rom_seednet_bytes(nx: int, ny: int, nz: int, batch: int):
+    npar, pb, wb = C.c_int64(), C.c_size_t(), C.c_size_t()
+    _check(_lib.rom_seednet_bytes(nx, ny, nz, batch, C.byref(npar), C.byref(pb), C.byref(wb)))
+    return npar.value, pb.value, wb.value
+
+
+def rom_seednet_create(nx: int, ny: int, nz: int, batch: int, params: np.ndarray, param_mem,
+                       work_mem, stream=None) -> int:
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    net = C.c_void_p()
+    _check(_lib.rom_seednet_create(nx, ny, nz, batch, params.ctypes.data_as(C.POINTER(C.c_float)),
+                                   _ptr(param_mem), param_mem.numel() * param_mem.element_size(),
+                                   _ptr(work_mem), work_mem.numel() * work_mem.element_size(),
+                                   C.byref(net), _stream(stream)))
+    return net.value
+
+
+def rom_seednet_forward(net: int, inputs, outputs, batch: int, stream=None):
+    _check(_lib.rom_seednet_forward(net, _ptr(inputs), _ptr(outputs), batch, _stream(stream)))
+
+
+def rom_seednet_gradients(net: int, inputs, targets, batch: int, nparams: int, stream=None):
+    g = np.empty(nparams, dtype=np.float32)
+    loss = C.c_double()
+    _check(_lib.rom_seednet_gradients(net, _ptr(inputs), _ptr(targets), batch,
+                                      g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
+                                      _stream(stream)))
+    return loss.value, g
+
+
+def rom_seednet_train_step(net: int, inputs, targets, batch: int, lr: float, stream=None) -> float:
+    loss = C.c_double()
+    _check(_lib.rom_seednet_train_step(net, _ptr(inputs), _ptr(targets), batch, float(lr),
+                                       C.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def rom_seednet_params(net: int, nparams: int, stream=None) -> np.ndarray:
+    p = np.empty(nparams, dtype=np.float32)
+    _check(_lib.rom_seednet_params(net, p.ctypes.data_as(C.POINTER(C.c_float)), _stream(stream)))
+    return p
+
+
+def rom_seednet_destroy(net: int):
+    if net:
+        _lib.rom_seednet_destroy(net)

@@ -1,0 +1,97 @@
+"""GPU parity of the learned-seed network (BF16 storage, FP32 accumulation on the matrix
+cores) against the FP64 reference network.
+
+The reference runs on the same BF16-rounded parameters and inputs; the remaining
+differences come from the GPU storing every activation and gradient in BF16 (relative
+rounding 2^-9 per value, compounded over the layers).  Gates (relative L2 norms):
+output 2e-2, loss 2e-2, each layer's weight and bias gradient 1e-1.  Training on a fixed
+batch must cut the loss by 4x in 60 Adam steps."""
+import numpy as np
+import pytest
+
+from oracle import seednet as sn
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16(a: np.ndarray) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def case(gpu):
+    import torch
+    from paper_1602_00138_amd import seed
+    rng = np.random.default_rng(7)
+    grid = (16, 16, 16)
+    B = 2
+    flat = seed.he_init(11)
+    p = seed.unflatten(flat)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+        p[k] = bf16(p[k]) if k.endswith(".w") else np.asarray(p[k], dtype=np.float32).astype(np.float64)
+    flat = seed.flatten(p)
+    x = bf16(rng.standard_normal((B, 3) + grid[::-1]))      # (b, c, z, y, x)
+    t = rng.standard_normal((B,) + grid[::-1]) * 0.5
+    net = seed.SeedNet(grid, B, flat.astype(np.float32))
+    xin = torch.as_tensor(x.reshape(B, 3, -1), dtype=torch.float32, device="cuda")
+    tin = torch.as_tensor(t.reshape(B, -1), dtype=torch.float32, device="cuda")
+    yield net, p, flat, x, t, xin, tin, grid, B
+    net.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def test_forward_matches_reference(case):
+    net, p, flat, x, t, xin, tin, grid, B = case
+    y = net.forward(xin).cpu().numpy()
+    for b in range(B):
+        ref, _ = sn.forward(p, x[b])
+        e = _rel(y[b], ref[0].reshape(-1))
+        print(f"\nsample {b}: output rel. error {e:.2e}")
+        assert e <= 2e-2
+
+
+def test_gradients_match_reference(case):
+    from paper_1602_00138_amd import seed
+    net, p, flat, x, t, xin, tin, grid, B = case
+    loss, g = net.gradients(xin, tin)
+    # reference: mean over the batch of the per-sample MSE = sum of per-sample grads / B
+    ref_loss = 0.0
+    ref_g = None
+    for b in range(B):
+        lb, gb = sn.loss_and_grad(p, x[b], t[b])
+        ref_loss += lb / B
+        fb = seed.flatten({k: v / B for k, v in gb.items()})
+        ref_g = fb if ref_g is None else ref_g + fb
+    assert abs(loss - ref_loss) <= 2e-2 * ref_loss, (loss, ref_loss)
+    gg = seed.unflatten(g.astype(np.float64))
+    rg = seed.unflatten(ref_g)
+    worst = 0.0
+    for name, _, _ in seed.LAYERS:
+        for suf in (".w", ".b"):
+            e = _rel(gg[name + suf], rg[name + suf])
+            worst = max(worst, e)
+            assert e <= 1e-1, (name + suf, e)
+    print(f"\nloss {loss:.6e} (reference {ref_loss:.6e}); worst gradient rel. error {worst:.2e}")
+
+
+def test_training_reduces_loss(case):
+    import torch
+    from paper_1602_00138_amd import seed
+    net0, p, flat, x, t, xin, tin, grid, B = case
+    net = seed.SeedNet(grid, B, flat.astype(np.float32))
+    # a learnable target: a smooth function of the inputs
+    tt = torch.tanh(xin[:, 0] + 0.5 * xin[:, 1]).contiguous()
+    losses = [net.train_step(xin, tt, 2e-3) for _ in range(60)]
+    print(f"\nloss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert losses[-1] <= 0.25 * losses[0]
+    assert np.all(np.isfinite(net.params()))
+    net.close()

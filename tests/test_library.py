@@ -63,3 +63,17 @@ def test_null_handles_rejected(R):
     assert e.value.status == R.ROM_EINVAL
     with pytest.raises(R.RomError):
         R.rom_basis_dims(None)
+
+
+@pytest.mark.parametrize("g", [(12, 16, 16), (16, 16, 0), (16, 8, 4)])
+def test_seednet_rejects_grids_not_multiple_of_8(R, g):
+    with pytest.raises(R.RomError) as e:
+        R.rom_seednet_bytes(*g, 1)
+    assert e.value.status == R.ROM_EINVAL
+
+
+def test_seednet_sizes(R):
+    from paper_1602_00138_amd import seed
+    npar, pb, wb = R.rom_seednet_bytes(16, 16, 16, 2)
+    assert npar == seed.flatten(seed.unflatten(seed.he_init(0))).size
+    assert pb >= 4 * 4 * npar and wb > 0

@@ -119,6 +119,12 @@ typedef struct {
                        the chosen shape up to rounding); 0: fixed shape */
   int graph;        /* 1: the CG iterations run as replays of a captured HIP graph of 8 steps
                        (same kernels, same results; not used while a CG class is timed) */
+  const float* guess; /* device, or NULL: an initial guess per (point i, RHS j), N values at
+                       column (i (n_src + n_det) + j), any scale (e.g. the seed network's
+                       output).  A solve that the outer test does not skip first moves to the
+                       A(p_i)-optimal point of x0 + span(guess - x0) when that lowers the
+                       residual; the correction appended to V and U_j is still x - x0.
+                       Needs group <= 1. */
 } rom_opts;
 
 /* One record per (point i, right-hand side j), in solve order. */
@@ -134,6 +140,7 @@ typedef struct {
   int restarts;     /* CG restarts from the true residual */
   int converged;    /* 1 if final_res <= tol */
   int fp64_sweeps;  /* mixed precision: refinement sweeps that fell back to the FP64 solver */
+  double rho_guess; /* relative residual of the start after an initial guess (-1: none) */
 } rom_record;
 
 /* Instrumented kernel classes (event timing for the classes set in opts.timing). */
@@ -278,6 +285,17 @@ ROM_API rom_status rom_seednet_gradients(rom_seednet* net, const float* in, cons
 ROM_API rom_status rom_seednet_train_step(rom_seednet* net, const float* in, const float* target,
                                   int batch, float lr, double* loss, void* stream);
 ROM_API rom_status rom_seednet_params(const rom_seednet* net, float* params, void* stream);
+/* Network inputs for `count` right-hand sides (unit columns at nodes idx[], host) at the
+ * parameter point p of operator op: out (device FP32 [count][3][N]) receives
+ * (mu(p) - mu0) / 0.03, log(D / 0.03) and the indicator of node idx[b].
+ * scratch: device, >= 8 (N + count) bytes. */
+ROM_API rom_status rom_seednet_inputs(const rom_operator* op, const rom_mu* p, const int64_t* idx,
+                              int count, float* out, void* scratch, size_t scratch_bytes,
+                              void* stream);
+/* Training targets: out[b][v] = X[v + b ldx] / max_v |X[v + b ldx]| (device; X FP64, out
+ * FP32 [count][N]).  scratch: device, >= 512 count bytes. */
+ROM_API rom_status rom_seednet_targets(const double* X, int64_t N, int64_t ldx, int count,
+                               float* out, void* scratch, size_t scratch_bytes, void* stream);
 ROM_API void rom_seednet_destroy(rom_seednet* net);
 
 ROM_API void rom_operator_destroy(rom_operator* op);

@@ -266,6 +266,16 @@ void launch_seed_pack_weights(const float* w, int cout, int cin, int Cpi, int Kp
 void launch_seed_unpack_wgrad(const float* dWg, int Kp, int cout, int cin, int Cpi, float* dw,
                               hipStream_t st);
 
+// Seed-network inputs [dmu/mu_scale, log(D/Dref), indicator of idx[b]] for count
+// right-hand sides (out: FP32 [count][3][n]; D NULL: constant Dc; idx on the device).
+void launch_seed_inputs(int64_t n, int count, const double* dmu, double mu_scale, const double* D,
+                        double Dc, double Dref, const int64_t* idx, float* out, hipStream_t st);
+// Training targets out[b][v] = X[v + b ldx] / max |X[:, b]|.  part: >= 64 count doubles.
+void launch_seed_targets(int64_t n, int count, const double* X, int64_t ldx, double* part,
+                         float* out, hipStream_t st);
+// d = xg - x0 (guess direction; xg FP32)
+void launch_guess_dir(int64_t n, const float* xg, const double* x0, double* d, hipStream_t st);
+
 // ---- mixed form -----------------------------------------------------------------------
 // out[i] = (float) in[i], i < n.
 void launch_cast_f32(int64_t n, const double* in, float* out, hipStream_t st);

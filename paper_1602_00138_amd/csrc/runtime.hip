@@ -27,6 +27,7 @@ struct rom_operator {
   double* fx;
   double* fy;
   double* fz;
+  double* Dfield = nullptr;   // per-node D (copy), when var
   rom::Stencil S{};
 };
 
@@ -229,8 +230,8 @@ size_t operator_layout(const rom_grid& g, bool var, Arena& a, rom_operator* op) 
     fz = g.dim == 3 ? a.take<double>(n) : nullptr;
     Dcopy = a.take<double>(n);
   }
-  (void)Dcopy;
   if (op) {
+    op->Dfield = Dcopy;
     op->diag_star = diag;
     op->fx = fx;
     op->fy = fy;
@@ -272,6 +273,7 @@ class Sequencer {
     mixed_ = o.precision == ROM_PREC_MIXED;
     tune_ = o.tune != 0;
     graph_ = o.graph != 0;
+    guess_ = o.guess;
     inner_tol_ = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     G_ = std::max(1, std::min(o.group, std::min(G_MAX, n_rhs_)));
   }
@@ -305,6 +307,7 @@ class Sequencer {
     xt_ = a.take<double>(ld_ * G);
     r2_ = a.take<double>(ld_ * G);
     vAB_ = a.take<double>(2 * ld_);
+    xg_ = a.take<double>(ld_);
     blk_ = G > 1 ? a.take<double>(ld_ * 2 * G) : nullptr;
     bblk_ = G > 1 ? a.take<double>((size_t)(cap_ + 8) * 2 * G) : nullptr;
     diag_i_ = a.take<double>(ld_);
@@ -873,23 +876,39 @@ class Sequencer {
       // ---- inner recycled CG on A g = r with U_j (correction equation, eq. (resi))
       ++n_solved_;
       rec.solved = 1;
-      const int nj = make_W(i, j, 0);
-      int flag = 0, its = 0, restarts = 0;
+      rec.rho_guess = -1.0;
+      // a given initial guess moves the start to its A-optimal point on x0 + span(xg - x0)
+      // when that lowers the residual (r_ and the base point follow)
+      xbase_ = x0_;
       double res = rho0;
-      if (!mixed_) {
-        its = cg_solve<double>(r_, 1.0, g_, nj, tol_ * nb, maxit_, flag);
-        launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
-        res = true_residual(xdst, idx, sc, nb);
-        while (res > tol_ && its < maxit_ && flag == 0 && restarts < MAX_SWEEPS) {
-          ++restarts;
-          its += cg_solve<double>(r2_, 1.0, d_, nj, tol_ * nb, maxit_ - its, flag);
-          launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st);
-          launch_axpby(n_, 1.0, x0_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
+      if (guess_) {
+        res = guess_step(guess_ + ((int64_t)i * n_rhs_ + j) * n_, nb, rho0);
+        rec.rho_guess = res;
+      }
+      int flag = 0, its = 0, restarts = 0;
+      int nj = 0;
+      if (res > tol_) {
+        nj = make_W(i, j, 0);
+        if (!mixed_) {
+          its = cg_solve<double>(r_, 1.0, g_, nj, tol_ * nb, maxit_, flag);
+          launch_axpby(n_, 1.0, xbase_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
           res = true_residual(xdst, idx, sc, nb);
+          while (res > tol_ && its < maxit_ && flag == 0 && restarts < MAX_SWEEPS) {
+            ++restarts;
+            its += cg_solve<double>(r2_, 1.0, d_, nj, tol_ * nb, maxit_ - its, flag);
+            launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st);
+            launch_axpby(n_, 1.0, xbase_, 1.0, g_, xdst, &ctrl_->sc[6], red_part_, st);
+            res = true_residual(xdst, idx, sc, nb);
+          }
+        } else {
+          its = refine(xdst, idx, sc, nb, nj, rec, res, restarts, flag);
         }
       } else {
-        its = refine(xdst, idx, sc, nb, nj, rec, res, restarts, flag);
+        ROM_HIP(hipMemcpyAsync(xdst, xbase_, sizeof(double) * n_, hipMemcpyDeviceToDevice, st));
+        nj = make_W(i, j, 0);
       }
+      // the correction that joins V and U_j is x - x0 (x0 in range(V))
+      if (xbase_ != x0_) launch_axpby(n_, 1.0, xdst, -1.0, x0_, g_, nullptr, red_part_, st);
       finish_solved(i, j, 0, g_, xdst, nj, its, restarts, res, flag, rec);
       recs_.push_back(rec);
     }
@@ -1059,6 +1078,29 @@ class Sequencer {
     }
   }
 
+  // Initial guess xg (FP32): d = xg - x0, alpha = d^T r / d^T A d (the A-optimal step
+  // along d from the Galerkin start), x1 = x0 + alpha d, r1 = r - alpha A d.  Kept, as
+  // the base point xg_ with r_ = r1, when ||r1|| < ||r||.  Returns the relative residual
+  // of the start taken.
+  double guess_step(const float* xg, double nb, double rho0) {
+    launch_guess_dir(n_, xg, x0_, d_, st_);
+    launch_spmv(S_, diag_i_, d_, w_, st_);
+    account_spmv(ROM_K_OTHER);
+    launch_dot2_scale(n_, d_, r_, w_, dmu_, r2_, &ctrl_->sc[8], red_part_, st_);
+    sync();
+    const double dr = h_->sc[8], dad = h_->sc[9];
+    if (!(dad > 0.0) || !std::isfinite(dr) || !std::isfinite(dad)) return rho0;
+    const double alpha = dr / dad;
+    launch_axpby(n_, 1.0, r_, -alpha, w_, r2_, &ctrl_->sc[10], red_part_, st_);
+    sync();
+    const double rho1 = std::sqrt(h_->sc[10]) / nb;
+    if (!(rho1 < rho0)) return rho0;
+    launch_axpby(n_, 1.0, x0_, alpha, d_, xg_, nullptr, red_part_, st_);
+    ROM_HIP(hipMemcpyAsync(r_, r2_, sizeof(double) * n_, hipMemcpyDeviceToDevice, st_));
+    xbase_ = xg_;
+    return rho1;
+  }
+
   // r2 = b - A x in FP64 (b = sc e_idx); returns ||r2|| / nb.
   double true_residual(const double* x, int64_t idx, double sc, double nb) {
     launch_resid_unit(S_, diag_i_, x, idx, sc, r2_, &ctrl_->sc[3], red_part_, st_);
@@ -1091,15 +1133,15 @@ class Sequencer {
         if (f32 != 0) {
           fp32 = false;   // FP32 breakdown: keep g, go on in FP64
           if (its < maxit_) continue;
-          launch_axpby(n_, 1.0, x0_, 1.0, g_, x, nullptr, red_part_, st_);
+          launch_axpby(n_, 1.0, xbase_, 1.0, g_, x, nullptr, red_part_, st_);
           break;
         }
-        launch_refine_update(n_, rn, d32_, g_, x0_, x, st_);
+        launch_refine_update(n_, rn, d32_, g_, xbase_, x, st_);
       } else {
         ++rec.fp64_sweeps;
         its += cg_solve<double>(rcur, 1.0, d_, nj, tol_ * nb, maxit_ - its, flag);
         launch_axpby(n_, 1.0, g_, 1.0, d_, g_, nullptr, red_part_, st_);
-        launch_axpby(n_, 1.0, x0_, 1.0, g_, x, &ctrl_->sc[6], red_part_, st_);
+        launch_axpby(n_, 1.0, xbase_, 1.0, g_, x, &ctrl_->sc[6], red_part_, st_);
       }
       const double prev = res;
       res = true_residual(x, idx, sc, nb);
@@ -1443,6 +1485,8 @@ class Sequencer {
   bool mixed_ = false;
   bool tune_ = false;
   bool graph_ = false;
+  const float* guess_ = nullptr;   // per (point, RHS) initial guesses (FP32, N each)
+  const double* xbase_ = nullptr;  // base point of the current inner solve
   using GraphKey = std::tuple<int, int, int, int, int, const void*>;
   std::map<GraphKey, hipGraphExec_t> graphs_;
   hipStream_t cap_st_ = nullptr;   // capture stream of the graphs
@@ -1464,6 +1508,7 @@ class Sequencer {
   // device buffers
   double *Q_, *pool_, *Wp_, *AWp_, *x0_, *r_, *g_, *s_, *p_, *w_, *d_, *xt_, *r2_, *vAB_;
   double *blk_ = nullptr, *bblk_ = nullptr;   // block append: A Q_new, its projections
+  double* xg_ = nullptr;                       // start moved by an initial guess
   double *diag_i_, *dmu_, *Gs_, *Gi_, *Lc_, *Lr_, *gram_part_, *red_part_, *gt_part_;
   double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_, *lwork_;
   Ctrl* ctrl_;
@@ -1493,6 +1538,7 @@ void check_opts(const rom_opts* o) {
   if (o->group < 0 || o->group > G_MAX) throw Error(ROM_EINVAL, "group must be in [0, 16]");
   if (o->tune != 0 && o->tune != 1) throw Error(ROM_EINVAL, "tune must be 0 or 1");
   if (o->graph != 0 && o->graph != 1) throw Error(ROM_EINVAL, "graph must be 0 or 1");
+  if (o->guess && o->group > 1) throw Error(ROM_EINVAL, "initial guesses need group <= 1");
 }
 
 void check_counts(int n_src, int n_det, int k_u, int K) {
@@ -1550,6 +1596,9 @@ rom_status rom_assemble_operator(const rom_grid* grid, double D_const, const dou
     rom::operator_layout(*grid, var, a, o);
     try {
       rom::launch_assemble(*grid, D_const, D_field, o->diag_star, o->fx, o->fy, o->fz, st);
+      if (var)
+        ROM_HIP(hipMemcpyAsync(o->Dfield, D_field, sizeof(double) * o->n, hipMemcpyDeviceToDevice,
+                               st));
     } catch (...) {
       delete o;
       throw;
@@ -1690,6 +1739,44 @@ rom_status rom_solve_sequences(rom_sequence_job* jobs, int count) {
   } catch (const std::exception& e) {
     rom::g_err = e.what();
     return ROM_EHIP;
+  }
+}
+
+rom_status rom_seednet_inputs(const rom_operator* op, const rom_mu* p, const int64_t* idx,
+                              int count, float* out, void* scratch, size_t scratch_bytes,
+                              void* stream) {
+  try {
+    if (!op || !p || !idx || !out || !scratch) throw Error(ROM_EINVAL, "null argument");
+    if (count < 1) throw Error(ROM_EINVAL, "count must be >= 1");
+    rom::check_mu(p, op->grid.dim);
+    for (int b = 0; b < count; ++b)
+      if (idx[b] < 0 || idx[b] >= op->n) throw Error(ROM_EINVAL, "node index out of range");
+    if (scratch_bytes < 8 * (size_t)(op->n + count)) throw Error(ROM_ECAPACITY, "scratch too small");
+    if ((uintptr_t)scratch % 8) throw Error(ROM_EINVAL, "scratch must be 8-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    double* dmu = (double*)scratch;
+    int64_t* didx = (int64_t*)(dmu + op->n);
+    ROM_HIP(hipMemcpyAsync(didx, idx, sizeof(int64_t) * count, hipMemcpyHostToDevice, st));
+    rom::launch_mu_eval(op->S, rom::make_bumps(*p, op->grid.dim), op->diag_star, nullptr, dmu, st);
+    rom::launch_seed_inputs(op->n, count, dmu, 0.03, op->var ? op->Dfield : nullptr, op->Dc, 0.03,
+                            didx, out, st);
+    ROM_HIP(hipStreamSynchronize(st));   // idx is pageable host memory
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_seednet_targets(const double* X, int64_t N, int64_t ldx, int count, float* out,
+                               void* scratch, size_t scratch_bytes, void* stream) {
+  try {
+    if (!X || !out || !scratch) throw Error(ROM_EINVAL, "null argument");
+    if (N < 1 || count < 1 || ldx < N) throw Error(ROM_EINVAL, "bad sizes");
+    if (scratch_bytes < 512 * (size_t)count) throw Error(ROM_ECAPACITY, "scratch too small");
+    rom::launch_seed_targets(N, count, X, ldx, (double*)scratch, out, (hipStream_t)stream);
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
   }
 }
 

@@ -9,6 +9,8 @@
 // operand is one 16-byte load of a neighbour's channels).  The data gradient is the same
 // convolution with the weights flipped in space and transposed in channels; the weight
 // gradient reduces over voxels in LDS-staged 32-voxel steps, split over voxel chunks.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace rom {
@@ -363,6 +365,55 @@ __global__ void k_unpack_wgrad(const float* __restrict__ dWg, int Kp, int cout, 
   dw[e] += dWg[(int64_t)o * Kp + tap * Cpi + i];
 }
 
+// Network inputs for `count` right-hand sides: [dmu / mu_scale, log(D / D_ref), e_idx[b]].
+__global__ void k_seed_inputs(int64_t n, int count, const double* __restrict__ dmu,
+                              double mu_scale, const double* __restrict__ D, double Dc,
+                              double Dref, const int64_t* __restrict__ idx,
+                              float* __restrict__ out) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int b = blockIdx.y;
+  if (v >= n || b >= count) return;
+  float* o = out + (int64_t)b * 3 * n;
+  o[v] = (float)(dmu[v] / mu_scale);
+  o[n + v] = (float)log((D ? D[v] : Dc) / Dref);
+  o[2 * n + v] = v == idx[b] ? 1.f : 0.f;
+}
+
+// Per-column max |X| partials (blockIdx.y = column).
+__global__ void k_colmaxabs(int64_t n, const double* __restrict__ X, int64_t ldx,
+                            double* __restrict__ part) {
+  __shared__ double sh[BS];
+  const double* x = X + (int64_t)blockIdx.y * ldx;
+  double m = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS)
+    m = fmax(m, fabs(x[v]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = BS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sh[0];
+}
+
+// out[b][v] = X[v + b ldx] / max over the column's partials
+__global__ void k_scale_targets(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                const double* __restrict__ part, int P, float* __restrict__ out) {
+  const int b = blockIdx.y;
+  double m = 0.0;
+  for (int q = 0; q < P; ++q) m = fmax(m, part[(int64_t)b * P + q]);
+  const double s = m > 0.0 ? 1.0 / m : 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS)
+    out[(int64_t)b * n + v] = (float)(X[(int64_t)b * ldx + v] * s);
+}
+
+// Guess direction d = xg - x0 (xg FP32).
+__global__ void k_guess_dir(int64_t n, const float* __restrict__ xg, const double* __restrict__ x0,
+                            double* __restrict__ d) {
+  for (int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x; v < n; v += (int64_t)gridDim.x * BS)
+    d[v] = (double)xg[v] - x0[v];
+}
+
 int gridn(int64_t n) { return (int)ceil_div(n, BS); }
 
 }  // namespace
@@ -496,6 +547,30 @@ void launch_seed_unpack_wgrad(const float* dWg, int Kp, int cout, int cin, int C
                               hipStream_t st) {
   ROM_LAUNCH(k_unpack_wgrad, dim3(gridn((int64_t)cout * cin * 27)), dim3(BS), 0, st, dWg, Kp, cout,
              cin, Cpi, dw);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_inputs(int64_t n, int count, const double* dmu, double mu_scale, const double* D,
+                        double Dc, double Dref, const int64_t* idx, float* out, hipStream_t st) {
+  if (count <= 0) return;
+  ROM_LAUNCH(k_seed_inputs, dim3(gridn(n), count), dim3(BS), 0, st, n, count, dmu, mu_scale, D, Dc,
+             Dref, idx, out);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_seed_targets(int64_t n, int count, const double* X, int64_t ldx, double* part,
+                         float* out, hipStream_t st) {
+  if (count <= 0) return;
+  const int P = std::min(64, gridn(n));
+  ROM_LAUNCH(k_colmaxabs, dim3(P, count), dim3(BS), 0, st, n, X, ldx, part);
+  ROM_CHECK_LAUNCH();
+  ROM_LAUNCH(k_scale_targets, dim3(std::min(256, gridn(n)), count), dim3(BS), 0, st, n, X, ldx,
+             part, P, out);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_guess_dir(int64_t n, const float* xg, const double* x0, double* d, hipStream_t st) {
+  ROM_LAUNCH(k_guess_dir, dim3(std::min(1024, gridn(n))), dim3(BS), 0, st, n, xg, x0, d);
   ROM_CHECK_LAUNCH();
 }
 

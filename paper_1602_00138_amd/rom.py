@@ -40,7 +40,7 @@ EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator",
             "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error",
             "rom_seednet_bytes", "rom_seednet_create", "rom_seednet_forward",
             "rom_seednet_gradients", "rom_seednet_train_step", "rom_seednet_params",
-            "rom_seednet_destroy"]
+            "rom_seednet_destroy", "rom_seednet_inputs", "rom_seednet_targets"]
 
 
 class rom_grid(C.Structure):
@@ -56,14 +56,15 @@ class rom_mu(C.Structure):
 class rom_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("inner_tol", C.c_double),
                 ("cap", C.c_int), ("maxit", C.c_int), ("check_every", C.c_int), ("timing", C.c_int),
-                ("precision", C.c_int), ("group", C.c_int), ("tune", C.c_int), ("graph", C.c_int)]
+                ("precision", C.c_int), ("group", C.c_int), ("tune", C.c_int), ("graph", C.c_int),
+                ("guess", C.c_void_p)]
 
 
 class rom_record(C.Structure):
     _fields_ = [("point", C.c_int), ("rhs", C.c_int), ("rho0", C.c_double), ("its", C.c_int),
                 ("solved", C.c_int), ("kept", C.c_int), ("rho", C.c_double),
                 ("final_res", C.c_double), ("m", C.c_int), ("restarts", C.c_int),
-                ("converged", C.c_int), ("fp64_sweeps", C.c_int)]
+                ("converged", C.c_int), ("fp64_sweeps", C.c_int), ("rho_guess", C.c_double)]
 
 
 class rom_stats(C.Structure):
@@ -123,6 +124,8 @@ def _load():
         "rom_seednet_train_step": (C.c_int, [vp, vp, vp, C.c_int, C.c_float, P(C.c_double), vp]),
         "rom_seednet_params": (C.c_int, [vp, P(C.c_float), vp]),
         "rom_seednet_destroy": (None, [vp]),
+        "rom_seednet_inputs": (C.c_int, [vp, P(rom_mu), P(C.c_int64), C.c_int, vp, vp, sz, vp]),
+        "rom_seednet_targets": (C.c_int, [vp, C.c_int64, C.c_int64, C.c_int, vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -173,10 +176,13 @@ def make_grid(dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float) -> 
 
 def make_opts(tol: float, trunc: float = 1e-8, cap: int = 0, maxit: int = 0,
               check_every: int = 0, timing: int = 0, precision: int = ROM_PREC_FP64,
-              inner_tol: float = 0.0, group: int = 0, tune: int = 0, graph: int = 0) -> rom_opts:
+              inner_tol: float = 0.0, group: int = 0, tune: int = 0, graph: int = 0,
+              guess=None) -> rom_opts:
+    """guess: device FP32 tensor (K * n_rhs, N) of initial guesses, or None (kept alive by
+    the caller during the solve)."""
     return rom_opts(float(tol), float(trunc), float(inner_tol), int(cap), int(maxit),
                     int(check_every), int(timing), int(precision), int(group), int(tune),
-                    int(graph))
+                    int(graph), _ptr(guess))
 
 
 @dataclass
@@ -397,3 +403,16 @@ def rom_seednet_params(net: int, nparams: int, stream=None) -> np.ndarray:
 def rom_seednet_destroy(net: int):
     if net:
         _lib.rom_seednet_destroy(net)
+
+
+def rom_seednet_inputs(op: int, p: MuParams, idx, out, scratch, stream=None):
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    mu = p.c_struct()
+    _check(_lib.rom_seednet_inputs(op, C.byref(mu), idx.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   idx.size, _ptr(out), _ptr(scratch),
+                                   scratch.numel() * scratch.element_size(), _stream(stream)))
+
+
+def rom_seednet_targets(X, n: int, ldx: int, count: int, out, scratch, stream=None):
+    _check(_lib.rom_seednet_targets(_ptr(X), n, ldx, count, _ptr(out), _ptr(scratch),
+                                    scratch.numel() * scratch.element_size(), _stream(stream)))

@@ -75,3 +75,82 @@ class SeedNet:
     def close(self):
         R.rom_seednet_destroy(self.net)
         self.net = 0
+
+
+def make_inputs(prob, point: R.MuParams, idx: np.ndarray, out: torch.Tensor = None,
+                scratch: torch.Tensor = None) -> torch.Tensor:
+    """Network inputs [count][3][N] for the right-hand sides at nodes idx at one point
+    (rom_seednet_inputs)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    dev = prob.device
+    if out is None:
+        out = torch.empty((idx.size, 3, prob.n), dtype=torch.float32, device=dev)
+    if scratch is None:
+        scratch = torch.empty(8 * (prob.n + idx.size), dtype=torch.uint8, device=dev)
+    R.rom_seednet_inputs(prob.op, point, idx, out, scratch)
+    return out
+
+
+def make_targets(X: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    """Targets x / max|x| (FP32 [count][N]) from FP64 solutions X (count, N)."""
+    count, n = X.shape
+    if out is None:
+        out = torch.empty((count, n), dtype=torch.float32, device=X.device)
+    scratch = torch.empty(512 * count, dtype=torch.uint8, device=X.device)
+    R.rom_seednet_targets(X, n, n, count, out, scratch)
+    return out
+
+
+def rhs_nodes(prob) -> np.ndarray:
+    return np.concatenate([prob.src_idx, prob.det_idx])
+
+
+def dataset(prob, points, tol: float, **solve_kw):
+    """Training pairs from the method's own solutions: run the sequence on `points` and
+    return (inputs [K n_rhs][3][N], targets [K n_rhs][N])."""
+    res = prob.solve(points, tol, keep_X=True, **solve_kw)
+    X = res.X
+    res.close()
+    idx = rhs_nodes(prob)
+    inputs = torch.empty((len(points) * idx.size, 3, prob.n), dtype=torch.float32,
+                         device=prob.device)
+    for i, p in enumerate(points):
+        make_inputs(prob, p, idx, out=inputs[i * idx.size:(i + 1) * idx.size])
+    targets = make_targets(X)
+    del X
+    return inputs, targets
+
+
+def train(net: SeedNet, inputs: torch.Tensor, targets: torch.Tensor, steps: int, lr: float,
+          seed: int = 0, log=None):
+    """Adam on shuffled minibatches of net.batch samples; returns the losses."""
+    rng = np.random.default_rng(seed)
+    n = inputs.shape[0]
+    order = rng.permutation(n)
+    losses = []
+    pos = 0
+    for s in range(steps):
+        if pos + net.batch > n:
+            order = rng.permutation(n)
+            pos = 0
+        sel = torch.as_tensor(order[pos:pos + net.batch], device=inputs.device)
+        pos += net.batch
+        losses.append(net.train_step(inputs.index_select(0, sel), targets.index_select(0, sel), lr))
+        if log and (s % 50 == 0 or s == steps - 1):
+            log(f"seed network step {s}: loss {losses[-1]:.4e}")
+    return losses
+
+
+def guesses(net: SeedNet, prob, points) -> torch.Tensor:
+    """Network guesses for every (point, right-hand side), FP32 [K n_rhs][N]."""
+    idx = rhs_nodes(prob)
+    K = len(points)
+    out = torch.empty((K * idx.size, prob.n), dtype=torch.float32, device=prob.device)
+    inp = torch.empty((idx.size, 3, prob.n), dtype=torch.float32, device=prob.device)
+    scratch = torch.empty(8 * (prob.n + idx.size), dtype=torch.uint8, device=prob.device)
+    for i, p in enumerate(points):
+        make_inputs(prob, p, idx, out=inp, scratch=scratch)
+        for b0 in range(0, idx.size, net.batch):
+            b1 = min(idx.size, b0 + net.batch)
+            net.forward(inp[b0:b1], out=out[i * idx.size + b0:i * idx.size + b1])
+    return out

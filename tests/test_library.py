@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(R):
 
 def test_header_struct_sizes_match_binding(R):
     # rom_record / rom_stats are read field by field through ctypes
-    assert ctypes.sizeof(R.rom_record) == 64
+    assert ctypes.sizeof(R.rom_record) == 72
     assert ctypes.sizeof(R.rom_grid) == 48
 
 

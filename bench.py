@@ -115,6 +115,68 @@ def measure_forms(prob, pts, wl, steps: int):
     return out
 
 
+def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_points: int,
+                         plain_value: float, log_every=100):
+    """The learned-seed form: the network is trained on the method's own solutions at
+    other parameter points (untimed, reported), then every timed step runs the network
+    for every (point, RHS) and the mixed-precision sequence started from its guesses."""
+    import torch
+    import phantoms as ph
+    from paper_1602_00138_amd import driver, seed
+    from paper_1602_00138_amd import rom as R
+    twl = wl.replace(seed=wl.seed + 5000, K=train_points)
+    tpts = driver.points_from_workload(twl)
+    t0 = time.perf_counter()
+    inputs, targets = seed.dataset(prob, tpts, wl.tol)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = seed.SeedNet(wl.N[:3], 8, seed.he_init(5).astype(np.float32))
+    t0 = time.perf_counter()
+    losses = seed.train(net, inputs, targets, steps=train_steps, lr=2e-3, seed=1,
+                        log=lambda m: log(m) if False else None)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del inputs, targets
+    log(f"seed network: {len(tpts) * prob.n_rhs} training solutions in {t_data:.1f} s, "
+        f"{train_steps} steps in {t_train:.1f} s, loss {np.mean(losses[:10]):.3e} -> "
+        f"{np.mean(losses[-10:]):.3e}")
+    kw = dict(precision=R.ROM_PREC_MIXED, tune=1)
+    g = seed.guesses(net, prob, pts)
+    prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, **kw).close()
+    torch.cuda.synchronize()
+    t_inf = 0.0
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        if last is not None:
+            last.close()
+        ti = time.perf_counter()
+        g = seed.guesses(net, prob, pts)
+        torch.cuda.synchronize()
+        t_inf += time.perf_counter() - ti
+        last = prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    K, n_rhs = len(pts), prob.n_rhs
+    st = last.stats
+    drops = [np.log10(r["rho0"] / r["rho_guess"]) for r in last.records
+             if r["solved"] and r["rho_guess"] > 0]
+    out = {"value": K * n_rhs * steps / dt, "ms_per_step": 1e3 * dt / steps,
+           "inference_ms_per_step": 1e3 * t_inf / steps, "vs_plain_fp64": K * n_rhs * steps / dt / plain_value,
+           "basis_m": st["m"], "inner_its": st["total_its"], "solved": st["n_solved"],
+           "mean_log10_residual_drop": float(np.mean(drops)) if drops else 0.0,
+           "training": {"points": len(tpts), "solutions": len(tpts) * n_rhs, "steps": train_steps,
+                        "batch": 8, "data_s": t_data, "train_s": t_train,
+                        "loss_first": float(np.mean(losses[:10])),
+                        "loss_last": float(np.mean(losses[-10:]))},
+           "precision": "mixed", "group": 1}
+    last.close()
+    net.close()
+    log(f"learned seed (mixed): {out['value']:.1f} solves/s, its {st['total_its']}, "
+        f"inference {out['inference_ms_per_step']:.0f} ms/step, residual drop 10^{out['mean_log10_residual_drop']:.2f}")
+    return out
+
+
 def measure_concurrent(names, steps: int, **kw):
     """Independent sequences on uneven grids: solves/s run one after another vs all at
     once (rom_solve_sequences, one stream and host thread each)."""
@@ -166,6 +228,9 @@ def main():
                     help="also time the mixed / grouped forms on the same problem (0/1)")
     ap.add_argument("--suite", type=int, default=0,
                     help="also time the uneven-grid workload (48^3, 64^3, 96^3 sequences)")
+    ap.add_argument("--seed-steps", type=int, default=0,
+                    help="train the seed network this many steps and time the learned-seed form")
+    ap.add_argument("--seed-points", type=int, default=16, help="training points for the seed network")
     ap.add_argument("--kernel", default="outer",
                     help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
                          "k_gemvn<false>; auto: the class with the most event time)")
@@ -277,6 +342,10 @@ def main():
     if forms:
         for f in forms.values():
             f["vs_plain_fp64"] = f["value"] / value
+    learned = None
+    if args.seed_steps > 0:
+        learned = measure_learned_seed(prob, pts, wl, args.steps, args.seed_steps,
+                                       args.seed_points, value)
     suite = None
     if args.suite:
         from paper_1602_00138_amd import rom as R2
@@ -306,6 +375,7 @@ def main():
         "roofline": roof,
         "spmm": spmm,
         "forms": forms,
+        "learned_seed": learned,
         "uneven_grids": suite,
         "cpu_baseline": cpu,
     }

@@ -22,6 +22,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_outer_gemvn_cfg2_64cubed.md")
+
+
+def traffic_ratio():
+    """Measured HBM bytes / algorithmic bytes of the outer-projection kernel (rocprofv3
+    FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), from the committed profile."""
+    try:
+        for line in open(TRAFFIC_PROFILE):
+            if line.startswith("traffic_ratio:"):
+                return float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return None
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -231,6 +244,9 @@ def main():
     ap.add_argument("--seed-steps", type=int, default=0,
                     help="train the seed network this many steps and time the learned-seed form")
     ap.add_argument("--seed-points", type=int, default=16, help="training points for the seed network")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run 3 plain device copies of 1 GiB (the reference for the "
+                         "HBM traffic counters) and exit")
     ap.add_argument("--kernel", default="outer",
                     help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
                          "k_gemvn<false>; auto: the class with the most event time)")
@@ -242,6 +258,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return
 
     import phantoms as ph
     from paper_1602_00138_amd import driver
@@ -334,6 +361,10 @@ def main():
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
     roof.update({"kernel": dom, "launches": agg["launches"], "avg_launch_us": 1e3 * avg_ms,
                  "bytes_per_launch": agg["bytes"] / max(agg["launches"], 1)})
+    tr = traffic_ratio() if dom == "outer" and args.precision == "fp64" and args.group == 1 else None
+    if tr is not None:
+        roof["traffic"] = tr * roof["bytes_per_launch"]
+        roof["traffic_source"] = "profiles/traffic_outer_gemvn_cfg2_64cubed.md (ratio %.3f)" % tr
 
     spmm = spmm_bandwidth(prob, pts[-1], 64)
     log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s)")

@@ -46,15 +46,36 @@ __global__ void k_cg_setup(CGState* cg, CgSetup su, int nb) {
   c->kcur = 0;
 }
 
-// ys[j] = scale * sum_c Ginv[j + c nj] t[c] (Ginv = (U^T A U)^{-1}, symmetric, FP64),
-// evaluated in FP64 and stored as T in shared memory.
-template <typename T, typename S>
-__device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv, int nj, const S* t,
+// Row j = threadIdx.x < nj of Ginv = (U^T A U)^{-1} (symmetric, FP64) is loaded early
+// into registers, where it fits (NJT <= 16), so that its latency hides behind other loads.
+template <int NJT>
+struct GramPf {
+  static constexpr bool value = NJT <= 16;
+};
+
+template <int NJT, bool PF>
+__device__ __forceinline__ void gram_row(const double* __restrict__ Ginv, int nj,
+                                         double (&gr)[PF ? NJT : 1]) {
+  if (!PF) return;
+  const int j = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < NJT; ++c)
+    if (j < nj && c < nj) gr[PF ? c : 0] = Ginv[j + c * nj];
+}
+
+// ys[j] = scale * sum_c Ginv[j + c nj] t[c], evaluated in FP64 (the loop is unrolled to
+// NJT so that the row loads, where not prefetched, issue together) and stored as T in
+// shared memory.
+template <int NJT, bool PF, typename T, typename S>
+__device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv,
+                                           const double (&gr)[PF ? NJT : 1], int nj, const S* t,
                                            double scale, T* ys) {
   if (threadIdx.x < nj) {
     const int j = threadIdx.x;
     double y = 0.0;
-    for (int c = 0; c < nj; ++c) y += Ginv[j + c * nj] * (double)t[c];
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) y += (PF ? gr[PF ? c : 0] : Ginv[j + c * nj]) * (double)t[c];
     ys[j] = (T)(scale * y);
   }
   __syncthreads();
@@ -86,7 +107,10 @@ __global__ __launch_bounds__(B) void k_dcg_start(const T* __restrict__ W,
   const int nj = cg->nj;
   const double rscale = cg->rscale;
   __shared__ T ys[NJ_MAX];
-  gram_apply(Ginv, nj, cg->t, rscale, ys);
+  constexpr bool GPF = GramPf<NJT>::value;
+  double gr[GPF ? NJT : 1];
+  gram_row<NJT, GPF>(Ginv, nj, gr);
+  gram_apply<NJT, GPF>(Ginv, gr, nj, cg->t, rscale, ys);
   const T rs = (T)rscale;
   T acc[NJT + 1];
 #pragma unroll
@@ -148,6 +172,9 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t 
         if (c < nj) w0[c] = W[i0 + c * ld];
     }
   }
+  constexpr bool GPF = GramPf<NJT>::value;
+  double gr[GPF ? NJT : 1];
+  gram_row<NJT, GPF>(Ginv, nj, gr);
   __shared__ T tot[NJT + 1];
   __shared__ T ys[NJ_MAX];
   sum_partials_t<NJT + 1, B>(part2, P2, tot);
@@ -167,7 +194,7 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t 
     }
   }
   if (nonfinite || conv || hit) return;
-  gram_apply(Ginv, nj, tot, 1.0, ys);
+  gram_apply<NJT, GPF>(Ginv, gr, nj, tot, 1.0, ys);
   const T beta = first ? T(0) : (T)(gnew / gold);
   if (i0 < n) {
     T pi = s0 + beta * p0;
@@ -294,9 +321,9 @@ template <typename T>
 void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
                     const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
                     int iter, CGState* cg, const T* part2, int64_t p2stride, int nb, int P,
-                    hipStream_t st) {
+                    hipStream_t st, int P2) {
   const dim3 grid(P, nb);
-  const int P2 = P;
+  if (P2 <= 0) P2 = P;
   switch (njt_of(njmax)) {
 #define C(J) case J: ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, W, wstride, ld, n, Ginv, gstride, s, p, vstride, iter, cg, part2, p2stride, P2); break;
     C(8) C(16) C(32) C(64)
@@ -326,7 +353,7 @@ void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int 
                                     hipStream_t);                                                \
   template void launch_dcg_dir<T>(const T*, int64_t, int64_t, int64_t, int, const double*,       \
                                   int64_t, const T*, T*, int64_t, int, CGState*, const T*,       \
-                                  int64_t, int, int, hipStream_t);                               \
+                                  int64_t, int, int, hipStream_t, int);                          \
   template void launch_dcg_update<T>(const T*, int64_t, int64_t, int64_t, int, const T*,         \
                                      const T*, T*, T*, int64_t, int, CGState*, const T*, int,    \
                                      int64_t, T*, int64_t, int, int, hipStream_t);

@@ -347,56 +347,84 @@ __global__ void k_linv_finish(double* Lc, double* Lr, int64_t ld, int k,
 
 // Cholesky factor of a small SPD matrix in one workgroup (m <= 64), the inverse of the
 // factor (Linv) and the inverse of the matrix (Ginv = Linv^T Linv).
-__global__ void k_small_chol_inv(const double* __restrict__ G, int m, double* __restrict__ Linv,
-                                 double* __restrict__ Ginv, int* status) {
+__global__ __launch_bounds__(BS) void k_small_chol_inv(const double* __restrict__ G, int m,
+                                                       double* __restrict__ Linv,
+                                                       double* __restrict__ Ginv, int* status) {
+  // A holds the symmetrised G.  Elimination in the square-root-free form: after step k the
+  // lower column k holds sqrt(d_k) L[:, k] and A[k][k] the pivot d_k, so one barrier per
+  // step suffices; the columns are scaled at the end.  A pivot that is not positive is
+  // replaced by 1 and reported.  The strict upper triangle then holds R = L^{-1} before
+  // its row scaling, transposed (R[i][j] at A[j][i], j < i); the diagonal of R is 1, and
+  // Z = L^{-1} is R with row i divided by L[i][i].
   __shared__ double A[NJ_MAX][NJ_MAX + 1];
+  __shared__ double rl[NJ_MAX];   // 1 / L[i][i]
   __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  for (int e = t; e < m * m; e += BS) {
     const int i = e % m, j = e / m;
-    A[i][j] = 0.5 * (G[i + j * m] + G[j + i * m]);
+    A[i][j] = i >= j ? 0.5 * (G[i + j * m] + G[j + i * m]) : 0.0;
   }
   __syncthreads();
-  // right-looking Cholesky, lower triangle
   for (int k = 0; k < m; ++k) {
-    if (threadIdx.x == 0) {
-      const double d = A[k][k];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        A[k][k] = 1.0;
-      } else {
-        A[k][k] = sqrt(d);
-      }
+    const double d = A[k][k];
+    const bool ok = d > 0.0 && isfinite(d);
+    const double rd = ok ? 1.0 / d : 1.0;
+    if (t == 0 && !ok) {
+      A[k][k] = 1.0;   // every reader of this step takes the same replacement
+      bad = 1;
     }
-    __syncthreads();
-    const double piv = A[k][k];
-    for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) A[i][k] /= piv;
-    __syncthreads();
     const int w = m - k - 1;
-    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-      const int i = k + 1 + e % w, j = k + 1 + e / w;
-      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+    for (int e = t; e < w * (w + 1) / 2; e += BS) {
+      // e -> (i, j) with k < j <= i < m, packed by rows of the trailing lower triangle
+      int r = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+      if ((r + 1) * (r + 2) / 2 <= e) ++r;
+      if (r * (r + 1) / 2 > e) --r;
+      const int i = k + 1 + r, j = k + 1 + (e - r * (r + 1) / 2);
+      A[i][j] -= A[i][k] * A[j][k] * rd;
     }
     __syncthreads();
   }
-  // thread j: column j of Linv (L z = e_j) then column j of Ginv (L^T x = z); each
-  // thread re-reads only its own writes
-  for (int j = threadIdx.x; j < m; j += blockDim.x) {
-    double* z = Linv + j * m;
-    double* x = Ginv + j * m;
-    for (int i = 0; i < j; ++i) z[i] = 0.0;
-    for (int i = j; i < m; ++i) {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int c = j; c < i; ++c) s -= A[i][c] * z[c];
-      z[i] = s / A[i][i];
-    }
-    for (int i = m - 1; i >= 0; --i) {
-      double s = z[i];
-      for (int c = i + 1; c < m; ++c) s -= A[c][i] * x[c];
-      x[i] = s / A[i][i];
-    }
+  for (int k = t; k < m; k += BS) {
+    const double d = A[k][k];
+    const double l = sqrt(d);
+    rl[k] = 1.0 / l;
+    A[k][k] = l;
   }
-  if (threadIdx.x == 0 && bad) status[0] = 1;
+  __syncthreads();
+  for (int e = t; e < m * m; e += BS) {
+    const int i = e % m, k = e / m;
+    if (i > k) A[i][k] *= rl[k];
+  }
+  __syncthreads();
+  // R by right-looking substitution: after column c is final, R[i][j] -= L[i][c] Z[c][j]
+  // for every i > c, j <= c, where Z[c][j] = R[c][j] / L[c][c].
+  for (int c = 0; c + 1 < m; ++c) {
+    const double sc = rl[c];
+    const int rows = m - c - 1, cols = c + 1;
+    for (int e = t; e < rows * cols; e += BS) {
+      const int i = c + 1 + e % rows, j = e / rows;
+      const double zcj = (j == c ? 1.0 : A[j][c]) * sc;
+      A[j][i] -= A[i][c] * zcj;
+    }
+    __syncthreads();
+  }
+  // Z in place (row i scaled by 1 / L[i][i]); the diagonal is rl
+  for (int e = t; e < m * m; e += BS) {
+    const int i = e % m, j = e / m;
+    if (j < i) A[j][i] *= rl[i];
+  }
+  __syncthreads();
+  // Linv = Z (column-major), Ginv = Z^T Z: Ginv[i][j] = sum_{k >= max(i,j)} Z[k][i] Z[k][j]
+  for (int e = t; e < m * m; e += BS) {
+    const int i = e % m, j = e / m;
+    Linv[e] = i > j ? A[j][i] : (i == j ? rl[i] : 0.0);
+    const int k0 = i > j ? i : j;
+    double s = (k0 == i ? rl[i] : A[i][k0]) * (k0 == j ? rl[j] : A[j][k0]);
+    for (int k = k0 + 1; k < m; ++k) s += A[i][k] * A[j][k];
+    Ginv[e] = s;
+  }
+  if (t == 0 && bad) status[0] = 1;
 }
 
 // C = alpha op(A) op(B) + beta D (all column-major; D may be NULL).  op(A) is M x K,

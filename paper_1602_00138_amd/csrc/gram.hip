@@ -11,9 +11,7 @@ namespace rom {
 namespace {
 
 constexpr int BS = 256;    // 4 waves
-constexpr int TT = 64;     // output tile (TT x TT), each wave owns a 32 x 32 quarter
-constexpr int KC = 32;     // rows staged in LDS per step
-constexpr int PAD = 1;
+constexpr int TT = 64;     // output tile (TT x TT) of one wave
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -31,73 +29,164 @@ __device__ __forceinline__ void tile_of(int p, bool sym, int ntb, int& ti, int& 
   tj = p - t * (t + 1) / 2;
 }
 
-// partials[s][i + j*a] = sum over the rows of split s of w[r] X[r,i] Y[r,j]
-// for the tile pair of this block.
+// Four consecutive rows of one column: two 16-byte loads when the whole row group is in
+// range, guarded scalar loads in the ragged tail.
+__device__ __forceinline__ void load4(const double* __restrict__ p, int64_t r, int64_t rend,
+                                      bool full, double (&v)[4]) {
+  if (full) {
+    const double2 u0 = *reinterpret_cast<const double2*>(p + r);
+    const double2 u1 = *reinterpret_cast<const double2*>(p + r + 2);
+    v[0] = u0.x;
+    v[1] = u0.y;
+    v[2] = u1.x;
+    v[3] = u1.y;
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = r + s < rend ? p[r + s] : 0.0;
+  }
+}
+
+constexpr int ROWG = 16;   // rows per MFMA group: four k-steps of four k-slots
+
+// partials[s][i + j*a] = sum over the rows of block s of w[r] X[r,i] Y[r,j] for the tile
+// pair of this block.  Every wave works alone on its own rows and on the whole 64 x 64
+// pair (4 x 4 MFMA tiles of 16 x 16).  A lane reads four consecutive rows of one column,
+// so the 16 rows of a group reach the matrix core as four k-steps: step s takes, in
+// k-slot q, row 4 q + s of the group (a reordering of the sum over rows).  A group whose
+// weights are all zero is skipped.  On a diagonal pair of a symmetric Gram only the tiles
+// on or below the diagonal are formed.  The waves' tiles are added in a fixed order.
+// The unweighted form prefetches the next row group into registers while the matrix
+// cores work on the current one (one wave per SIMD fits, so the overlap has to come from
+// within the wave).  The weighted form (a few rows of bump support) loads a group only
+// after its weights show a non-zero.
+template <bool WEIGHTED>
 __global__ __launch_bounds__(BS) void k_gram(const double* __restrict__ X, int64_t ldx, int a,
                                               const double* __restrict__ Y, int64_t ldy, int b,
-                                              int64_t rows, int64_t rows_per_split,
+                                              int64_t rows, int64_t rows_per_wave,
                                               const double* __restrict__ w, int sym, int ntx,
                                               double* __restrict__ partials) {
-  __shared__ double Xs[KC][TT + PAD];
-  __shared__ double Ys[KC][TT + PAD];
+  __shared__ double red[16][4][WAVE];
   int ti, tj;
   tile_of(blockIdx.x, sym != 0, ntx, ti, tj);
   const int x0 = ti * TT, y0 = tj * TT;
-  const int64_t rbeg = (int64_t)blockIdx.y * rows_per_split;
-  int64_t rend = rbeg + rows_per_split;
-  if (rend > rows) rend = rows;
+  const bool diag = sym && ti == tj;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
-  double4_t acc[2][2];
+  const int ci = lane & 15, kq = lane >> 4;
+  const int64_t rbeg = ((int64_t)blockIdx.y * (BS / WAVE) + wid) * rows_per_wave;
+  int64_t rend = rbeg + rows_per_wave;
+  if (rend > rows) rend = rows;
+  const double *xp[4], *yp[4];
+  bool xin[4], yin[4];
+  int ntlx = 0, ntly = 0;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int t = 0; t < 4; ++t) {
+    const int cx = x0 + 16 * t + ci, cy = y0 + 16 * t + ci;
+    xin[t] = cx < a;
+    yin[t] = cy < b;
+    xp[t] = X + (int64_t)(xin[t] ? cx : a - 1) * ldx;
+    yp[t] = Y + (int64_t)(yin[t] ? cy : b - 1) * ldy;
+    if (x0 + 16 * t < a) ntlx = t + 1;
+    if (y0 + 16 * t < b) ntly = t + 1;
+  }
+  double4_t acc[4][4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-  // staging map: thread -> row (t % 32) and columns (t / 32) + 8 q
-  const int srow = threadIdx.x % KC;
-  const int scol = threadIdx.x / KC;
-  for (int64_t r0 = rbeg; r0 < rend; r0 += KC) {
-    const int64_t r = r0 + srow;
-    double wr_ = 0.0;
-    if (r < rend) wr_ = w ? w[r] : 1.0;
-    if (!__syncthreads_or(wr_ != 0.0)) continue;
+  auto load_group = [&](int64_t r0, double (&xv)[4][4], double (&yv)[4][4]) {
+    const bool full = r0 + ROWG <= rend;
+    const int64_t r = r0 + 4 * kq;
 #pragma unroll
-    for (int q = 0; q < TT / (BS / KC); ++q) {
-      const int c = scol + (BS / KC) * q;
-      const int xc = x0 + c, yc = y0 + c;
-      Xs[srow][c] = (wr_ != 0.0 && xc < a) ? wr_ * X[r + (int64_t)xc * ldx] : 0.0;
-      Ys[srow][c] = (r < rend && yc < b) ? Y[r + (int64_t)yc * ldy] : 0.0;
+    for (int t = 0; t < 4; ++t) {
+      if (t < ntlx) load4(xp[t], r, rend, full, xv[t]);
+      if (t < ntly) load4(yp[t], r, rend, full, yv[t]);
     }
-    __syncthreads();
+  };
+  auto mma_group = [&](double (&xv)[4][4], double (&yv)[4][4], const double (&wv)[4]) {
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double av[2], bv[2];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = Xs[kr][wr * 32 + i * 16 + (lane & 15)];
+      for (int s = 0; s < 4; ++s) {
+        xv[t][s] = xin[t] ? xv[t][s] * wv[s] : 0.0;
+        yv[t][s] = yin[t] ? yv[t][s] : 0.0;
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = Ys[kr][wc * 32 + j * 16 + (lane & 15)];
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          if (i >= ntlx || j >= ntly || (diag && i < j)) continue;
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[i][s], yv[j][s], acc[i][j], 0, 0, 0);
+        }
+  };
+
+  if (WEIGHTED) {
+    // scan the weights 256 rows (16 groups) at a time: lane l checks rows 4 l .. 4 l + 3,
+    // so lanes 4 g .. 4 g + 3 cover group g; only groups with a non-zero weight are loaded
+    for (int64_t rs = rbeg; rs < rend; rs += 16 * ROWG) {
+      double ws[4];
+      load4(w, rs + 4 * lane, rend, rs + 4 * lane + 4 <= rend, ws);
+      uint64_t nz = __ballot(ws[0] != 0.0 || ws[1] != 0.0 || ws[2] != 0.0 || ws[3] != 0.0);
+      while (nz) {
+        const int g = __builtin_ctzll(nz) >> 2;
+        nz &= ~(0xFull << (4 * g));
+        const int64_t r0 = rs + (int64_t)g * ROWG;
+        double wv[4];
+        load4(w, r0 + 4 * kq, rend, r0 + ROWG <= rend, wv);
+        double xv[4][4], yv[4][4];
+        load_group(r0, xv, yv);
+        mma_group(xv, yv, wv);
+      }
+    }
+  } else {
+    const double one[4] = {1.0, 1.0, 1.0, 1.0};
+    double xc[4][4], yc[4][4];
+    if (rbeg < rend) load_group(rbeg, xc, yc);
+    for (int64_t r0 = rbeg; r0 < rend; r0 += ROWG) {
+      double xn[4][4], yn[4][4];
+      if (r0 + ROWG < rend) load_group(r0 + ROWG, xn, yn);
+      mma_group(xc, yc, one);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          xc[t][s] = xn[t][s];
+          yc[t][s] = yn[t][s];
+        }
+    }
+  }
+  // waves 3, 2, 1 pass their running sum down through LDS; wave 0 adds its own last
+#pragma unroll
+  for (int src = BS / WAVE - 1; src >= 1; --src) {
+    if (wid == src) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double t = acc[i][j][v];
+            if (src < BS / WAVE - 1) t += red[i * 4 + j][v][lane];
+            red[i * 4 + j][v][lane] = t;
+          }
     }
     __syncthreads();
   }
+  if (wid != 0) return;
   // D layout of the 16x16x4 f64 MFMA: register v of a lane holds row (lane/16) + 4 v,
   // column lane % 16.
   double* P = partials + (int64_t)blockIdx.y * a * b;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int xi = x0 + wr * 32 + i * 16 + (lane >> 4) + 4 * v;
-        const int yj = y0 + wc * 32 + j * 16 + (lane & 15);
-        if (xi < a && yj < b) P[xi + (int64_t)yj * a] = acc[i][j][v];
+        const int xi = x0 + 16 * i + (lane >> 4) + 4 * v;
+        const int yj = y0 + 16 * j + (lane & 15);
+        if (xi < a && yj < b) P[xi + (int64_t)yj * a] = acc[i][j][v] + red[i * 4 + j][v][lane];
       }
 }
 
@@ -137,89 +226,128 @@ __global__ void k_gram_finish(const double* __restrict__ partials, int nsplit, i
   C[i + j * ldc] = s;
 }
 
-// Projections onto a tall basis: partials[s][i + v*a] = sum over the rows of split s of
+// Projections onto a tall basis: partials[s][i + v*a] = sum over the rows of block s of
 // X[r, i] V[r, v] for v < nv <= 16 (a block of right-hand sides against the basis).
-// Each wave owns 16 columns of X and all 16 vector slots (one 16x16 MFMA tile); the
-// block stages KC rows of its 64 columns of X and of V through LDS.
+// Every wave works alone on its own rows and on the block's 64 columns of X (four 16 x 16
+// MFMA tiles against the 16 vector slots).  A lane reads four consecutive rows of one
+// column (two 16-byte loads), so the 16 rows of a group reach the matrix core as four
+// k-steps: step s takes, in k-slot q, row 4 q + s of the group -- a reordering of the
+// sum over rows.  The four waves' tiles are added in wave order at the end.
 __global__ __launch_bounds__(BS) void k_proj(const double* __restrict__ X, int64_t ldx, int a,
                                               const double* __restrict__ V, int64_t ldv, int nv,
-                                              int64_t rows, int64_t rows_per_split,
+                                              int64_t rows, int64_t rows_per_wave,
                                               double* __restrict__ partials) {
-  __shared__ double Xs[KC][TT + PAD];
-  __shared__ double Vs[KC][16 + PAD];
-  const int x0 = blockIdx.x * TT;
-  const int64_t rbeg = (int64_t)blockIdx.y * rows_per_split;
-  int64_t rend = rbeg + rows_per_split;
-  if (rend > rows) rend = rows;
+  __shared__ double red[BS / WAVE - 1][4][4][WAVE];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-  const int srow = threadIdx.x % KC;
-  const int scol = threadIdx.x / KC;   // 0..7
-  for (int64_t r0 = rbeg; r0 < rend; r0 += KC) {
-    const int64_t r = r0 + srow;
-    const bool in = r < rend;
+  const int ci = lane & 15, kq = lane >> 4;
+  const int x0 = blockIdx.x * TT;
+  const int64_t rbeg = ((int64_t)blockIdx.y * (BS / WAVE) + wid) * rows_per_wave;
+  int64_t rend = rbeg + rows_per_wave;
+  if (rend > rows) rend = rows;
+  // lanes past the last column read a valid neighbour and drop the value
+  const double* xp[4];
+  bool xin[4];
+  int ntl = 0;
 #pragma unroll
-    for (int q = 0; q < TT / (BS / KC); ++q) {
-      const int c = scol + (BS / KC) * q;
-      Xs[srow][c] = (in && x0 + c < a) ? X[r + (int64_t)(x0 + c) * ldx] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 16 / (BS / KC); ++q) {
-      const int v = scol + (BS / KC) * q;
-      Vs[srow][v] = (in && v < nv) ? V[r + (int64_t)v * ldv] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      const double av = Xs[kr][wid * 16 + (lane & 15)];
-      const double bv = Vs[kr][lane & 15];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-    __syncthreads();
+  for (int t = 0; t < 4; ++t) {
+    const int c = x0 + 16 * t + ci;
+    xin[t] = c < a;
+    xp[t] = X + (int64_t)(xin[t] ? c : a - 1) * ldx;
+    if (x0 + 16 * t < a) ntl = t + 1;
   }
+  const bool vin = ci < nv;
+  const double* vp = V + (int64_t)(vin ? ci : nv - 1) * ldv;
+  double4_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int64_t r0 = rbeg; r0 < rend; r0 += ROWG) {
+    const bool full = r0 + ROWG <= rend;
+    const int64_t r = r0 + 4 * kq;
+    double vv[4], xv[4][4];
+    load4(vp, r, rend, full, vv);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < ntl) load4(xp[t], r, rend, full, xv[t]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) vv[s] = vin ? vv[s] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= ntl) continue;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xin[t] ? xv[t][s] : 0.0, vv[s], acc[t],
+                                                      0, 0, 0);
+    }
+  }
+  if (wid > 0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[wid - 1][t][v][lane] = acc[t][v];
+  }
+  __syncthreads();
+  if (wid != 0) return;
+  // D layout of the 16x16x4 f64 MFMA: register v of a lane holds row (lane/16) + 4 v,
+  // column lane % 16.
   double* P = partials + (int64_t)blockIdx.y * a * nv;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int xi = x0 + wid * 16 + (lane >> 4) + 4 * v;
-    const int vj = lane & 15;
-    if (xi < a && vj < nv) P[xi + (int64_t)vj * a] = acc[v];
-  }
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double sum = acc[t][v];
+#pragma unroll
+      for (int w = 0; w < BS / WAVE - 1; ++w) sum += red[w][t][v][lane];
+      const int xi = x0 + 16 * t + (lane >> 4) + 4 * v;
+      const int vj = lane & 15;
+      if (xi < a && vj < nv) P[xi + (int64_t)vj * a] = sum;
+    }
 }
 
+// About 1024 blocks of four waves (four blocks per CU, one round), each wave at least
+// four row groups; rps is the rows of one wave, a multiple of the row group.
 void proj_shape(int a, int64_t rows, int& ntile, int& nsplit, int64_t& rps) {
+  constexpr int64_t WPB = BS / WAVE;
   ntile = (a + TT - 1) / TT;
-  nsplit = 2048 / (ntile > 0 ? ntile : 1);
-  if (nsplit < 1) nsplit = 1;
-  int64_t maxs = (rows + 8 * KC - 1) / (8 * KC);
-  if (nsplit > maxs) nsplit = (int)(maxs > 0 ? maxs : 1);
-  rps = (rows + nsplit - 1) / nsplit;
-  rps = (rps + KC - 1) / KC * KC;
-  nsplit = (int)((rows + rps - 1) / rps);
+  if (ntile < 1) ntile = 1;
+  int64_t ns = 1024 / ntile;
+  if (ns < 1) ns = 1;
+  const int64_t maxs = (rows + WPB * 4 * ROWG - 1) / (WPB * 4 * ROWG);
+  if (ns > maxs) ns = maxs > 0 ? maxs : 1;
+  rps = (rows + ns * WPB - 1) / (ns * WPB);
+  rps = (rps + ROWG - 1) / ROWG * ROWG;
+  if (rps < ROWG) rps = ROWG;
+  nsplit = (int)((rows + rps * WPB - 1) / (rps * WPB));
   if (nsplit < 1) nsplit = 1;
 }
 
-void gram_shape(int a, int b, int64_t rows, bool sym, int& npairs, int& nsplit, int64_t& rps) {
+// About 256 blocks of four waves (one block per CU, one round), each wave at least four
+// row groups; rps is the rows of one wave, a multiple of 256 rows (the weight scan).  A
+// weighted Gram (rows of bump support only) gets four times as many blocks: most of its
+// rows are skipped, and the scan itself is what has to be spread.
+void gram_shape(int a, int b, int64_t rows, bool sym, bool weighted, int& npairs, int& nsplit,
+                int64_t& rps) {
+  constexpr int64_t WPB = BS / WAVE, SCAN = 16 * ROWG;
   const int ta = (a + TT - 1) / TT, tb = (b + TT - 1) / TT;
   npairs = sym ? ta * (ta + 1) / 2 : ta * tb;
-  nsplit = 2048 / (npairs > 0 ? npairs : 1);
-  if (nsplit < 1) nsplit = 1;
-  if (nsplit > 1024) nsplit = 1024;
-  int64_t maxs = (rows + 8 * KC - 1) / (8 * KC);   // at least 8 staged chunks per split
-  if (nsplit > maxs) nsplit = (int)(maxs > 0 ? maxs : 1);
-  rps = (rows + nsplit - 1) / nsplit;
-  rps = (rps + KC - 1) / KC * KC;
-  nsplit = (int)((rows + rps - 1) / rps);
+  if (npairs < 1) npairs = 1;
+  int64_t ns = (weighted ? 1024 : 256) / npairs;
+  if (ns < 1) ns = 1;
+  const int64_t maxs = (rows + WPB * SCAN - 1) / (WPB * SCAN);
+  if (ns > maxs) ns = maxs > 0 ? maxs : 1;
+  rps = (rows + ns * WPB - 1) / (ns * WPB);
+  rps = (rps + SCAN - 1) / SCAN * SCAN;
+  nsplit = (int)((rows + rps * WPB - 1) / (rps * WPB));
   if (nsplit < 1) nsplit = 1;
 }
 
 }  // namespace
 
 size_t gram_partials(int a, int b, int64_t rows, bool sym) {
-  int np, ns;
+  int np, ns, nsw;
   int64_t rps;
-  gram_shape(a, b, rows, sym, np, ns, rps);
-  return (size_t)ns * a * b;
+  gram_shape(a, b, rows, sym, false, np, ns, rps);
+  gram_shape(a, b, rows, sym, true, np, nsw, rps);
+  return (size_t)std::max(ns, nsw) * a * b;
 }
 
 size_t gram_partials_max(int a, int b, int64_t rows, bool sym) {
@@ -250,6 +378,8 @@ void launch_proj(const double* X, int64_t ldx, int a, const double* V, int64_t l
                  int64_t rows, double* C, int64_t ldc, double* partials, hipStream_t st) {
   if (a <= 0 || nv <= 0) return;
   if (nv > 16) throw Error(ROM_EINVAL, "launch_proj: at most 16 vectors");
+  if ((ldx | ldv) & 1 || ((uintptr_t)X | (uintptr_t)V) & 15)
+    throw Error(ROM_EINVAL, "launch_proj: X and V need 16-byte aligned columns");
   int nt, ns;
   int64_t rps;
   proj_shape(a, rows, nt, ns, rps);
@@ -269,12 +399,18 @@ void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t l
                  int64_t rows, const double* w, bool sym, const double* base, int64_t ldb,
                  double shift, double* C, int64_t ldc, double* partials, hipStream_t st) {
   if (a <= 0 || b <= 0) return;
+  if ((ldx | ldy) & 1 || ((uintptr_t)X | (uintptr_t)Y | (uintptr_t)w) & 15)
+    throw Error(ROM_EINVAL, "launch_gram: X, Y and w need 16-byte aligned columns");
   int np, ns;
   int64_t rps;
-  gram_shape(a, b, rows, sym, np, ns, rps);
+  gram_shape(a, b, rows, sym, w != nullptr, np, ns, rps);
   const int ntx = (a + TT - 1) / TT;
-  ROM_LAUNCH(k_gram, dim3(np, ns), dim3(BS), 0, st, X, ldx, a, Y, ldy, b, rows, rps, w,
-                     sym ? 1 : 0, ntx, partials);
+  if (w)
+    ROM_LAUNCH(k_gram<true>, dim3(np, ns), dim3(BS), 0, st, X, ldx, a, Y, ldy, b, rows, rps, w,
+               sym ? 1 : 0, ntx, partials);
+  else
+    ROM_LAUNCH(k_gram<false>, dim3(np, ns), dim3(BS), 0, st, X, ldx, a, Y, ldy, b, rows, rps,
+               w, sym ? 1 : 0, ntx, partials);
   ROM_CHECK_LAUNCH();
   const int64_t ne = (int64_t)a * b;
   if (ns >= 32)

@@ -203,6 +203,8 @@ void launch_dot2_scale(int64_t n, const double* x, const double* a, const double
 // of T): part1 >= stencil_shape(S, 1024).blocks per member, part2 >= (NJ_MAX + 1) * P
 // per member, at strides p1stride, p2stride.  iter: 0-based step index shared by the
 // batch (-1 for the direction after the start; ITER_STATE: from the state, see above).
+// P2 of the direction kernel: the partial rows it reduces, the grid of the launch before
+// it (0: P; the start may run on a wider grid than the steps).
 // cg[y].t holds U_j^T r before the start.  Inactive members (done set at setup) return
 // at once from every kernel.
 int dcg_blocks(int64_t n);
@@ -218,7 +220,7 @@ template <typename T>
 void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
                     const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
                     int iter, CGState* cg, const T* part2, int64_t p2stride, int nb, int P,
-                    hipStream_t st);
+                    hipStream_t st, int P2 = 0);
 template <typename T>
 void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
                       int64_t vstride, CGState* cg, T* part1, int nb, hipStream_t st);

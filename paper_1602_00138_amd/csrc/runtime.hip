@@ -264,7 +264,7 @@ class Sequencer {
     cap_ = o.cap > 0 ? (int)std::min<int64_t>(o.cap, full) : (int)std::min<int64_t>(full, 4096);
     cap_ = (int)std::min<int64_t>(cap_, n_);
     if (cap_ < 1) cap_ = 1;
-    ldg_ = cap_;
+    ldg_ = round_up(cap_, 2);   // even: the projections read 16-byte column pairs
     pool_cap_ = n_rhs_ + std::max(0, cap_);
     tol_ = o.tol;
     trunc_ = o.trunc;
@@ -637,7 +637,8 @@ class Sequencer {
     launch_pack_cols(n_, cp, nj, W, ld_, st_);
     launch_spmm(S_, diag_i_, W, ld_, nj, AW, st_);
     tm_->begin(ROM_K_GRAM);
-    launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, false, nullptr, 0, 0.0, GW_, nj,
+    // symmetric by construction: the lower triangle W_i^T (A W_j), i >= j, is mirrored
+    launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, true, nullptr, 0, 0.0, GW_, nj,
                 gram_part_, st_);
     tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
     launch_small_chol_inv(GW_, nj, LWinv_ + (int64_t)y * NJ_MAX * NJ_MAX,
@@ -925,13 +926,13 @@ class Sequencer {
       const int64_t ldx = X_out ? n_ : ld_;
       // ---- outer projection of the group: X0 = V G_i^{-1} V^T [b_j0 ..]
       if (m_ > 0) {
-        launch_gather_rows(Q_, ld_, m_, idx_dev_ + j0, scale_dev_ + j0, nb, tbuf_, m_, st);
-        launch_gemm(m_, nb, m_, 1.0, Lc_, ldg_, false, tbuf_, m_, false, 0.0, nullptr, 0, ubuf_,
-                    m_, st);
-        launch_gemm(m_, nb, m_, 1.0, Lc_, ldg_, true, ubuf_, m_, false, 0.0, nullptr, 0, cbuf_,
-                    m_, st);
+        // t = V^T B (rows of V), u = L^{-1} t = Lr^T t, c = L^{-T} u = Lc^T u
+        const int mm = (int)round_up(m_, 2);
+        launch_gather_rows(Q_, ld_, m_, idx_dev_ + j0, scale_dev_ + j0, nb, tbuf_, mm, st);
+        launch_proj(Lr_, ldg_, m_, tbuf_, mm, nb, m_, ubuf_, mm, gt_part_, st);
+        launch_proj(Lc_, ldg_, m_, ubuf_, mm, nb, m_, cbuf_, mm, gt_part_, st);
         tm_->begin(ROM_K_OUTER);
-        launch_gemvn_multi(Q_, ld_, n_, m_, cbuf_, m_, nb, 0.0, nullptr, 0, 1.0, x0_, ld_, st);
+        launch_gemvn_multi(Q_, ld_, n_, m_, cbuf_, mm, nb, 0.0, nullptr, 0, 1.0, x0_, ld_, st);
         tm_->end(ROM_K_OUTER, 8.0 * n_ * (m_ + nb), 2.0 * n_ * m_ * nb);
       } else {
         ROM_HIP(hipMemsetAsync(x0_, 0, sizeof(double) * ld_ * nb, st));
@@ -1350,11 +1351,15 @@ class Sequencer {
     for (int y = 0; y < nb; ++y)
       if (bt.active[y]) njavg += bt.nj[y];
     njavg /= nact;
+    // the start runs once per solve on the full grid for every member (its 256-thread
+    // blocks would leave the chip idle on the steps' grid); the first direction step
+    // reduces its partial rows
+    const int P0 = dcg_blocks(n_);
     launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec, b.s,
-                        ld_, cg, b.part2, p2s_, nb, P, st_);
+                        ld_, cg, b.part2, p2s_, nb, P0, st_);
     tm_->begin(ROM_K_DCG_DIR);
     launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, -1, cg,
-                      b.part2, p2s_, nb, P, st_);
+                      b.part2, p2s_, nb, P, st_, P0);
     tm_->end(ROM_K_DCG_DIR, nact * E * n_ * (2 + njavg), nact * n_ * (1.0 + 2.0 * njavg));
     // per member and step
     const double by_apply = E * n_ * (3 + (S_.var ? S_.dim : 0));

@@ -83,11 +83,40 @@ struct Stencil {
   int64_t n;
 };
 
+// One DPP move of a 32-bit or 64-bit value (lanes whose source is outside the pattern,
+// or whose row is masked off, receive 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf,
+                                                    false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  Row shifts by 1, 2, 4 and 8
+// leave each 16-lane row's sum in its last lane; the row broadcasts of lanes 15 and 31
+// carry the row sums up so that lane 63 holds the total.  All on the vector ALU (no LDS
+// traffic, unlike a butterfly of lane permutes).  Every lane of the wave must be active.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
+  v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return lane63(v);
 }
 
 // Sum R per-thread values over the block; thread r < R of the returned block gets
@@ -146,19 +175,35 @@ __device__ __forceinline__ void write_partials_t(const T (&v)[R], T* partials, i
   if (threadIdx.x < R) partials[(size_t)threadIdx.x * P + bid] = bs;
 }
 
+// Totals of R transposed partial rows: a single value is summed by the whole block; with
+// several, wave w sums values w, w + BS/64, ... (one wave reduction per value, not R
+// reductions per wave).  tot[] (shared) is visible to every thread on return.
 template <int R, int BS, typename T>
 __device__ __forceinline__ void sum_partials_t(const T* __restrict__ partials, int P, T* tot) {
-  __shared__ T sh[(BS / WAVE) * R];
-  T acc[R];
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  if (R == 1) {
+    __shared__ T sh[BS / WAVE];
+    T a = T(0);
+#pragma unroll 4
+    for (int b = threadIdx.x; b < P; b += BS) a += partials[b];
+    a = wave_sum(a);
+    if (lane == 0) sh[wid] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T t = T(0);
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = T(0);
-  for (int b = threadIdx.x; b < P; b += BS) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += partials[(size_t)r * P + b];
+      for (int w = 0; w < BS / WAVE; ++w) t += sh[w];
+      tot[0] = t;
+    }
+  } else {
+    for (int r = wid; r < R; r += BS / WAVE) {
+      T a = T(0);
+#pragma unroll 4
+      for (int b = lane; b < P; b += WAVE) a += partials[(size_t)r * P + b];
+      a = wave_sum(a);
+      if (lane == 0) tot[r] = a;
+    }
   }
-  T t;
-  block_sum<R, BS>(acc, sh, t);
-  if (threadIdx.x < R) tot[threadIdx.x] = t;
   __syncthreads();
 }
 

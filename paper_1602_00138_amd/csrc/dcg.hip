@@ -14,17 +14,18 @@ namespace rom {
 
 namespace {
 
-// Step kernels: 256 blocks of CgBlock threads (4 waves per SIMD on 256 CUs); the next
-// launch then reduces only 256 partial rows.
+// Step kernels: blocks of 256 threads, each thread RPT rows of a 256 * RPT-row chunk
+// (rows b * chunk + t + 256 q), a block's chunks strided by the grid.  A thread issues
+// every load of its first chunk (the rows of U_j or A U_j and the vectors) before it
+// reduces the previous launch's partials, so the reduction hides behind the loads.  RPT
+// is as large as keeps those values and the NJT + 1 running sums in registers without
+// spilling; at 64 columns nothing is preloaded (RPT 0: one row per thread per pass,
+// U_j read as it is used).
+constexpr int CG_BS = 256;
 template <typename T, int NJT>
-struct CgBlock {
-  static constexpr int value = NJT * sizeof(T) <= 256 ? 1024 : 512;
-};
-// rows of U_j / A U_j are prefetched ahead of the reduction only while they fit in the
-// register budget of a 1024-thread block (128 VGPRs per lane)
-template <typename T, int NJT>
-struct CgPrefetch {
-  static constexpr bool value = NJT * sizeof(T) <= 128;
+struct CgRows {
+  static constexpr int value =
+      sizeof(T) == 8 ? (NJT <= 16 ? 4 : NJT <= 32 ? 2 : 0) : (NJT <= 32 ? 4 : 0);
 };
 constexpr int CG_GRID = 256;
 constexpr int START_BS = 256;
@@ -140,14 +141,14 @@ __global__ __launch_bounds__(B) void k_dcg_start(const T* __restrict__ W,
 // Reduce the step's partials (s^T s, (AU)^T s); record s^T s for the next step, count
 // the step, stop on convergence / maxit / non-finite values; else the new direction
 // p = s + beta p - U G^{-1} (AU)^T s.  iter = -1 for the direction after the start.
-template <typename T, int NJT, int B = CgBlock<T, NJT>::value>
-__global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t wstride,
-                                                int64_t ld, int64_t n,
-                                                const double* __restrict__ Ginv, int64_t gstride,
-                                                const T* __restrict__ s, T* __restrict__ p,
-                                                int64_t vstride, int iter, CGState* cgs,
-                                                const T* __restrict__ part2, int64_t p2stride,
-                                                int P2) {
+template <typename T, int NJT, int RPT = CgRows<T, NJT>::value>
+__global__ __launch_bounds__(CG_BS) void k_dcg_dir(const T* __restrict__ W, int64_t wstride,
+                                                    int64_t ld, int64_t n,
+                                                    const double* __restrict__ Ginv,
+                                                    int64_t gstride, const T* __restrict__ s,
+                                                    T* __restrict__ p, int64_t vstride, int iter,
+                                                    CGState* cgs, const T* __restrict__ part2,
+                                                    int64_t p2stride, int P2) {
   const int y = blockIdx.y;
   CGState* cg = cgs + y;
   if (cg->done) return;
@@ -159,25 +160,32 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t 
   const int nj = cg->nj;
   if (iter == ITER_STATE) iter = cg->kcur;
   const bool first = iter < 0;
-  // first row of this thread, loaded ahead of the reduction
-  constexpr bool PF = CgPrefetch<T, NJT>::value;
-  const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
-  T w0[PF ? NJT : 1], s0 = T(0), p0 = T(0);
-  if (i0 < n) {
-    s0 = s[i0];
-    if (!first) p0 = p[i0];
-    if (PF) {
+  constexpr bool PRE = RPT > 0;
+  constexpr int R = PRE ? RPT : 1;
+  constexpr int64_t CH = (int64_t)CG_BS * R;
+  int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  T wr[R][PRE ? NJT : 1], sv[R], pv[R];
+  auto load = [&](int64_t b0) {
 #pragma unroll
-      for (int c = 0; c < NJT; ++c)
-        if (c < nj) w0[c] = W[i0 + c * ld];
+    for (int q = 0; q < R; ++q) {
+      const int64_t i = b0 + (int64_t)q * CG_BS;
+      const bool in = i < n;
+      sv[q] = in ? s[i] : T(0);
+      pv[q] = (in && !first) ? p[i] : T(0);
+      if (PRE) {
+#pragma unroll
+        for (int c = 0; c < NJT; ++c)
+          wr[q][PRE ? c : 0] = (in && c < nj) ? W[i + c * ld] : T(0);
+      }
     }
-  }
+  };
+  load(base);
   constexpr bool GPF = GramPf<NJT>::value;
   double gr[GPF ? NJT : 1];
   gram_row<NJT, GPF>(Ginv, nj, gr);
   __shared__ T tot[NJT + 1];
   __shared__ T ys[NJ_MAX];
-  sum_partials_t<NJT + 1, B>(part2, P2, tot);
+  sum_partials_t<NJT + 1, CG_BS>(part2, P2, tot);
   const double gnew = (double)tot[NJT];
   const double gold = first ? 1.0 : cg->gamma[iter & 1];
   const bool nonfinite = !isfinite(gnew);
@@ -196,33 +204,33 @@ __global__ __launch_bounds__(B) void k_dcg_dir(const T* __restrict__ W, int64_t 
   if (nonfinite || conv || hit) return;
   gram_apply<NJT, GPF>(Ginv, gr, nj, tot, 1.0, ys);
   const T beta = first ? T(0) : (T)(gnew / gold);
-  if (i0 < n) {
-    T pi = s0 + beta * p0;
+  for (;;) {
 #pragma unroll
-    for (int c = 0; c < NJT; ++c)
-      if (c < nj) pi -= (PF ? w0[PF ? c : 0] : W[i0 + c * ld]) * ys[c];
-    p[i0] = pi;
-  }
-  for (int64_t i = i0 + (int64_t)gridDim.x * B; i < n; i += (int64_t)gridDim.x * B) {
-    T pi = s[i];
-    if (!first) pi += beta * p[i];
+    for (int q = 0; q < R; ++q) {
+      const int64_t i = base + (int64_t)q * CG_BS;
+      T pi = sv[q] + beta * pv[q];
 #pragma unroll
-    for (int c = 0; c < NJT; ++c)
-      if (c < nj) pi -= W[i + c * ld] * ys[c];
-    p[i] = pi;
+      for (int c = 0; c < NJT; ++c)
+        if (c < nj) pi -= (PRE ? wr[q][PRE ? c : 0] : (i < n ? W[i + c * ld] : T(0))) * ys[c];
+      if (i < n) p[i] = pi;
+    }
+    base += (int64_t)gridDim.x * CH;
+    if (base - threadIdx.x >= n) break;
+    load(base);
   }
 }
 
 // alpha = s^T s / p^T A p; g += alpha p; s -= alpha w; partials of (AU)^T s and s^T s.
-template <typename T, int NJT, int B = CgBlock<T, NJT>::value>
-__global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int64_t wstride,
-                                                   int64_t ld, int64_t n,
-                                                   const T* __restrict__ p,
-                                                   const T* __restrict__ w, T* __restrict__ g,
-                                                   T* __restrict__ s, int64_t vstride, int iter,
-                                                   CGState* cgs, const T* __restrict__ part1,
-                                                   int P1, int64_t p1stride,
-                                                   T* __restrict__ part2, int64_t p2stride) {
+template <typename T, int NJT, int RPT = CgRows<T, NJT>::value>
+__global__ __launch_bounds__(CG_BS) void k_dcg_update(const T* __restrict__ AW, int64_t wstride,
+                                                       int64_t ld, int64_t n,
+                                                       const T* __restrict__ p,
+                                                       const T* __restrict__ w,
+                                                       T* __restrict__ g, T* __restrict__ s,
+                                                       int64_t vstride, int iter, CGState* cgs,
+                                                       const T* __restrict__ part1, int P1,
+                                                       int64_t p1stride, T* __restrict__ part2,
+                                                       int64_t p2stride) {
   const int y = blockIdx.y;
   CGState* cg = cgs + y;
   if (cg->done) return;
@@ -235,22 +243,30 @@ __global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int6
   part2 += y * p2stride;
   const int nj = cg->nj;
   if (iter == ITER_STATE) iter = cg->its;
-  constexpr bool PF = CgPrefetch<T, NJT>::value;
-  const int64_t i0 = (int64_t)blockIdx.x * B + threadIdx.x;
-  T a0[PF ? NJT : 1], p0 = T(0), w0 = T(0), g0 = T(0), s0 = T(0);
-  if (i0 < n) {
-    p0 = p[i0];
-    w0 = w[i0];
-    g0 = g[i0];
-    s0 = s[i0];
-    if (PF) {
+  constexpr bool PRE = RPT > 0;
+  constexpr int R = PRE ? RPT : 1;
+  constexpr int64_t CH = (int64_t)CG_BS * R;
+  int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  T a[R][PRE ? NJT : 1], pv[R], wv[R], gv[R], sv[R];
+  auto load = [&](int64_t b0) {
 #pragma unroll
-      for (int c = 0; c < NJT; ++c)
-        if (c < nj) a0[c] = AW[i0 + c * ld];
+    for (int q = 0; q < R; ++q) {
+      const int64_t i = b0 + (int64_t)q * CG_BS;
+      const bool in = i < n;
+      pv[q] = in ? p[i] : T(0);
+      wv[q] = in ? w[i] : T(0);
+      gv[q] = in ? g[i] : T(0);
+      sv[q] = in ? s[i] : T(0);
+      if (PRE) {
+#pragma unroll
+        for (int c = 0; c < NJT; ++c)
+          a[q][PRE ? c : 0] = (in && c < nj) ? AW[i + c * ld] : T(0);
+      }
     }
-  }
+  };
+  load(base);
   __shared__ T pwt[1];
-  sum_partials<1, B>(part1, P1, pwt);
+  sum_partials_t<1, CG_BS>(part1, P1, pwt);
   const double pw = (double)pwt[0];
   if (!(pw > 0.0) || !isfinite(pw)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -267,25 +283,26 @@ __global__ __launch_bounds__(B) void k_dcg_update(const T* __restrict__ AW, int6
   T acc[NJT + 1];
 #pragma unroll
   for (int c = 0; c <= NJT; ++c) acc[c] = T(0);
-  if (i0 < n) {
-    g[i0] = g0 + alpha * p0;
-    const T si = s0 - alpha * w0;
-    s[i0] = si;
-    acc[NJT] += si * si;
+  for (;;) {
 #pragma unroll
-    for (int c = 0; c < NJT; ++c)
-      if (c < nj) acc[c] += (PF ? a0[PF ? c : 0] : AW[i0 + c * ld]) * si;
-  }
-  for (int64_t i = i0 + (int64_t)gridDim.x * B; i < n; i += (int64_t)gridDim.x * B) {
-    g[i] += alpha * p[i];
-    const T si = s[i] - alpha * w[i];
-    s[i] = si;
-    acc[NJT] += si * si;
+    for (int q = 0; q < R; ++q) {
+      const int64_t i = base + (int64_t)q * CG_BS;
+      const T si = sv[q] - alpha * wv[q];   // 0 past the end (sv = wv = 0 there)
+      if (i < n) {
+        g[i] = gv[q] + alpha * pv[q];
+        s[i] = si;
+      }
+      acc[NJT] += si * si;
 #pragma unroll
-    for (int c = 0; c < NJT; ++c)
-      if (c < nj) acc[c] += AW[i + c * ld] * si;
+      for (int c = 0; c < NJT; ++c)
+        if (c < nj)
+          acc[c] += (PRE ? a[q][PRE ? c : 0] : (i < n ? AW[i + c * ld] : T(0))) * si;
+    }
+    base += (int64_t)gridDim.x * CH;
+    if (base - threadIdx.x >= n) break;
+    load(base);
   }
-  write_partials_t<NJT + 1, B>(acc, part2, blockIdx.x, gridDim.x);
+  write_partials_t<NJT + 1, CG_BS>(acc, part2, blockIdx.x, gridDim.x);
 }
 
 }  // namespace
@@ -325,7 +342,7 @@ void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njma
   const dim3 grid(P, nb);
   if (P2 <= 0) P2 = P;
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, W, wstride, ld, n, Ginv, gstride, s, p, vstride, iter, cg, part2, p2stride, P2); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CG_BS), 0, st, W, wstride, ld, n, Ginv, gstride, s, p, vstride, iter, cg, part2, p2stride, P2); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -339,7 +356,7 @@ void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int 
                        int nb, int P, hipStream_t st) {
   const dim3 grid(P, nb);
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CgBlock<T, J>::value), 0, st, AW, wstride, ld, n, p, w, g, s, vstride, iter, cg, part1, P1, p1stride, part2, p2stride); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CG_BS), 0, st, AW, wstride, ld, n, p, w, g, s, vstride, iter, cg, part1, P1, p1stride, part2, p2stride); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }

@@ -249,7 +249,7 @@ def main():
                          "HBM traffic counters) and exit")
     ap.add_argument("--kernel", default="outer",
                     help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
-                         "k_gemvn<false>; auto: the class with the most event time)")
+                         "k_gemvn4<false>; auto: the class with the most event time)")
     args = ap.parse_args()
 
     if args.gpus != 1:

@@ -134,6 +134,61 @@ __global__ __launch_bounds__(BS) void k_gemvn(const double* __restrict__ M, int6
   if (NRM) write_partials<1, BS>(nv, partials, blockIdx.x);
 }
 
+// The same product with four consecutive rows per thread: two 16-byte loads per column,
+// four columns per step, one block per CU at 64^3 (the loop is strided by the grid).
+// Rows are read in groups of four up to round_up(rows, 4) <= ld (the column padding);
+// `in` and `out` are touched only below `rows`.  Needs ld % 4 == 0 and M 16-byte aligned.
+template <bool NRM>
+__global__ __launch_bounds__(BS) void k_gemvn4(const double* __restrict__ M, int64_t ld,
+                                                int64_t rows, int cols,
+                                                const double* __restrict__ coef, double alpha,
+                                                const double* __restrict__ in, double beta,
+                                                double* __restrict__ out, double* partials,
+                                                Skip skip) {
+  if (skip.on()) return;
+  extern __shared__ double cs[];
+  for (int c = threadIdx.x; c < cols; c += BS) cs[c] = coef[c];
+  __syncthreads();
+  double nv[1] = {0.0};
+  for (int64_t r0 = ((int64_t)blockIdx.x * BS + threadIdx.x) * 4; r0 < rows;
+       r0 += (int64_t)gridDim.x * BS * 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* p = M + r0;
+    int c = 0;
+    for (; c + 4 <= cols; c += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double w = cs[c + u];
+        const double2 v0 = *reinterpret_cast<const double2*>(p + (int64_t)(c + u) * ld);
+        const double2 v1 = *reinterpret_cast<const double2*>(p + (int64_t)(c + u) * ld + 2);
+        acc[0] += v0.x * w;
+        acc[1] += v0.y * w;
+        acc[2] += v1.x * w;
+        acc[3] += v1.y * w;
+      }
+    }
+    for (; c < cols; ++c) {
+      const double w = cs[c];
+      const double2 v0 = *reinterpret_cast<const double2*>(p + (int64_t)c * ld);
+      const double2 v1 = *reinterpret_cast<const double2*>(p + (int64_t)c * ld + 2);
+      acc[0] += v0.x * w;
+      acc[1] += v0.y * w;
+      acc[2] += v1.x * w;
+      acc[3] += v1.y * w;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = r0 + q;
+      if (r < rows) {
+        const double o = beta * acc[q] + (in ? alpha * in[r] : 0.0);
+        out[r] = o;
+        nv[0] += o * o;
+      }
+    }
+  }
+  if (NRM) write_partials<1, BS>(nv, partials, blockIdx.x);
+}
+
 // Several coefficient vectors against one basis pass: each thread owns RPT rows and
 // NV accumulators per row; coefficients are staged through LDS in chunks of CCH columns.
 template <int NV, int RPT>
@@ -655,15 +710,25 @@ void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const dou
                   double alpha, const double* in, double beta, double* out, double* nrm2,
                   double* partials, hipStream_t st, Skip skip) {
   const size_t shm = (size_t)(cols > 0 ? cols : 1) * sizeof(double);
-  const int grid = reduce_grid(rows);
+  // four rows per thread where the basis allows it (the usual case: columns padded to 64)
+  const bool four = ld % 4 == 0 && ((uintptr_t)M & 15) == 0;
+  const int grid = four ? std::min(256, std::max(1, ceil_div(rows, 4 * BS))) : reduce_grid(rows);
   if (nrm2) {
-    ROM_LAUNCH(k_gemvn<true>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef,
-                       alpha, in, beta, out, partials, skip);
+    if (four)
+      ROM_LAUNCH(k_gemvn4<true>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef, alpha,
+                 in, beta, out, partials, skip);
+    else
+      ROM_LAUNCH(k_gemvn<true>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef, alpha,
+                 in, beta, out, partials, skip);
     ROM_CHECK_LAUNCH();
     launch_reduce_finish(partials, grid, 1, nrm2, st, skip);
   } else {
-    ROM_LAUNCH(k_gemvn<false>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef,
-                       alpha, in, beta, out, partials, skip);
+    if (four)
+      ROM_LAUNCH(k_gemvn4<false>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef, alpha,
+                 in, beta, out, partials, skip);
+    else
+      ROM_LAUNCH(k_gemvn<false>, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, coef, alpha,
+                 in, beta, out, partials, skip);
     ROM_CHECK_LAUNCH();
   }
 }

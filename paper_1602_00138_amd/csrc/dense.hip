@@ -586,9 +586,99 @@ __global__ void k_dot2_scale(int64_t n, const double* __restrict__ x, const doub
     const double xi = x[i];
     v[0] += xi * a[i];
     v[1] += xi * b[i];
-    z[i] = dmu[i] * xi;
+    if (z) z[i] = dmu[i] * xi;
   }
   write_partials<2, BS>(v, partials, blockIdx.x);
+}
+
+// ---- rows of bump support, compacted once per parameter point ----------------------
+// counts[b] = rows r of block b (256 rows) with w[r] != 0.
+__global__ __launch_bounds__(BS) void k_nz_count(int64_t n, const double* __restrict__ w,
+                                                 int* __restrict__ counts) {
+  __shared__ int sh[BS / WAVE];
+  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const uint64_t b = __ballot(r < n && w[r] != 0.0);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = __popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < BS / WAVE; ++k) c += sh[k];
+    counts[blockIdx.x] = c;
+  }
+}
+
+// Exclusive prefix sums of counts[0..nb) in place (one block: each thread a run of
+// consecutive counts, then a scan of the run totals in LDS); the total goes to *total.
+__global__ __launch_bounds__(1024) void k_nz_scan(int nb, int* __restrict__ counts,
+                                                  int* __restrict__ total) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = t * per, b1 = min(nb, b0 + per);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += counts[b];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = t > 0 ? part[t - 1] : 0;
+  for (int b = b0; b < b1; ++b) {
+    const int c = counts[b];
+    counts[b] = run;
+    run += c;
+  }
+  if (t == 1023) *total = part[1023];
+}
+
+// idx[pos] = r and wc[pos] = w[r] for every row with w[r] != 0, in ascending row order
+// (pos = the block's offset + the non-zero rows before r in the block); positions past
+// cap are not written.
+__global__ __launch_bounds__(BS) void k_nz_scatter(int64_t n, const double* __restrict__ w,
+                                                   const int* __restrict__ offs, int64_t cap,
+                                                   int64_t* __restrict__ idx,
+                                                   double* __restrict__ wc) {
+  __shared__ int sh[BS / WAVE];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const double v = r < n ? w[r] : 0.0;
+  const bool nz = v != 0.0;
+  const uint64_t b = __ballot(nz);
+  if (lane == 0) sh[wid] = __popcll(b);
+  __syncthreads();
+  int before = 0;
+  for (int k = 0; k < wid; ++k) before += sh[k];
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t pos = (int64_t)offs[blockIdx.x] + before + __popcll(b & lt);
+  if (nz && pos < cap) {
+    idx[pos] = r;
+    wc[pos] = v;
+  }
+}
+
+// Vb[t + c ldb] = M[idx[t] + c ld] for t < cnt, column c = c0 + blockIdx.y.
+__global__ void k_gather_idx(const double* __restrict__ M, int64_t ld,
+                             const int64_t* __restrict__ idx, int64_t cnt, int c0,
+                             double* __restrict__ Vb, int64_t ldb) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t c = c0 + blockIdx.y;
+  if (t < cnt) Vb[t + c * ldb] = M[idx[t] + c * ld];
+}
+
+// qb[t] = q[idx[t]] (if qb), zb[t] = wc[t] q[idx[t]] for t < cnt.
+__global__ void k_gather_scale(const double* __restrict__ q, const int64_t* __restrict__ idx,
+                               const double* __restrict__ wc, int64_t cnt,
+                               double* __restrict__ qb, double* __restrict__ zb) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (t < cnt) {
+    const double v = q[idx[t]];
+    if (qb) qb[t] = v;
+    zb[t] = wc[t] * v;
+  }
 }
 
 __global__ void k_border_fill(const double* __restrict__ vals, int k, double* Gs, double* Gi,
@@ -874,6 +964,28 @@ void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, co
   if (m <= 0) return;
   launch_gemvt(Lr, ld, m, m, t, 0, 1, u, partials, st);
   launch_gemvt(Lc, ld, m, m, u, 0, 1, c, partials, st);
+}
+
+void launch_nz_rows(int64_t n, const double* w, int64_t* idx, double* wc, int64_t cap, int* total,
+                    int* work, hipStream_t st) {
+  const int nb = ceil_div(n, BS);
+  if (nb < 1) return;
+  ROM_LAUNCH(k_nz_count, dim3(nb), dim3(BS), 0, st, n, w, work);
+  ROM_LAUNCH(k_nz_scan, dim3(1), dim3(1024), 0, st, nb, work, total);
+  ROM_LAUNCH(k_nz_scatter, dim3(nb), dim3(BS), 0, st, n, w, (const int*)work, cap, idx, wc);
+}
+
+void launch_gather_idx(const double* M, int64_t ld, const int64_t* idx, int64_t cnt, int c0,
+                       int c1, double* Vb, int64_t ldb, hipStream_t st) {
+  if (cnt <= 0 || c1 <= c0) return;
+  ROM_LAUNCH(k_gather_idx, dim3(ceil_div(cnt, BS), c1 - c0), dim3(BS), 0, st, M, ld, idx, cnt, c0,
+             Vb, ldb);
+}
+
+void launch_gather_scale(const double* q, const int64_t* idx, const double* wc, int64_t cnt,
+                         double* qb, double* zb, hipStream_t st) {
+  if (cnt <= 0) return;
+  ROM_LAUNCH(k_gather_scale, dim3(ceil_div(cnt, BS)), dim3(BS), 0, st, q, idx, wc, cnt, qb, zb);
 }
 
 void launch_small_chol_inv(const double* G, int m, double* Linv, double* Ginv, int* status,

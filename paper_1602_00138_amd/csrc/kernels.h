@@ -172,6 +172,17 @@ void launch_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda
 // c = Linv^T (Linv t), for m x m Linv.
 void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, const double* t,
                        double* u, double* c, double* partials, hipStream_t st);
+// Rows r < n with w[r] != 0, ascending: idx[t] = r and wc[t] = w[r] for the first cap of
+// them; *total = how many there are (device int, all of them).  work: ceil(n / 256) ints.
+void launch_nz_rows(int64_t n, const double* w, int64_t* idx, double* wc, int64_t cap, int* total,
+                    int* work, hipStream_t st);
+// Vb[t + c ldb] = M[idx[t] + c ld] for t < cnt, c0 <= c < c1 (rows of a basis at given
+// indices).
+void launch_gather_idx(const double* M, int64_t ld, const int64_t* idx, int64_t cnt, int c0,
+                       int c1, double* Vb, int64_t ldb, hipStream_t st);
+// qb[t] = q[idx[t]] (qb may be NULL), zb[t] = wc[t] q[idx[t]] for t < cnt.
+void launch_gather_scale(const double* q, const int64_t* idx, const double* wc, int64_t cnt,
+                         double* qb, double* zb, hipStream_t st);
 // Small SPD m x m (m <= NJ_MAX) in one workgroup: Linv (inverse of its Cholesky factor)
 // and Ginv (its inverse), col-major, ld = m.  status[0] = 1 if not SPD.
 void launch_small_chol_inv(const double* G, int m, double* Linv, double* Ginv, int* status,

@@ -312,6 +312,14 @@ class Sequencer {
     bblk_ = G > 1 ? a.take<double>((size_t)(cap_ + 8) * 2 * G) : nullptr;
     diag_i_ = a.take<double>(ld_);
     dmu_ = a.take<double>(ld_);
+    // the rows of bump support (at most a quarter of the grid) and V on them
+    nzcap_ = std::min<int64_t>(n_, std::max<int64_t>(1024, n_ / 4));
+    ldb_ = round_up(nzcap_, 64);
+    Vb_ = a.take<double>((size_t)ldb_ * cap_);
+    bidx_ = a.take<int64_t>(nzcap_);
+    dmub_ = a.take<double>(nzcap_);
+    zb_ = a.take<double>(nzcap_);
+    nzwork_ = a.take<int>(ceil_div(n_, 256) + 1);
     Gs_ = a.take<double>((size_t)ldg_ * cap_);
     Gi_ = a.take<double>((size_t)ldg_ * cap_);
     Lc_ = a.take<double>((size_t)ldg_ * cap_);
@@ -594,12 +602,23 @@ class Sequencer {
     account_spmv(ROM_K_OTHER);
     launch_spmv(S_, diag_i_, q, vAB_ + ld_, st_);
     account_spmv(ROM_K_OTHER);
-    // d2 = [q^T A_* q, q^T A_i q]; z = dmu o q; w = V^T z (bump rows only)
-    launch_dot2_scale(n_, q, vAB_, vAB_ + ld_, dmu_, r2_, &ctrl_->sc[8], red_part_, st_);
-    if (k > 0) {
-      tm_->begin(ROM_K_GEMVT);
-      launch_gemvt(Q_, ld_, n_, k, r2_, 0, 1, tmpl_, gt_part_, st_);
-      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (k + 1), 2.0 * n_ * k);
+    // d2 = [q^T A_* q, q^T A_i q]; z = dmu o q; w = V^T z (bump rows only: on the
+    // gathered rows when the point has them, else the row chunks with a non-zero)
+    if (compact_) {
+      launch_dot2_scale(n_, q, vAB_, vAB_ + ld_, dmu_, nullptr, &ctrl_->sc[8], red_part_, st_);
+      launch_gather_scale(q, bidx_, dmub_, nzr_, Vb_ + (int64_t)k * ldb_, zb_, st_);
+      if (k > 0) {
+        tm_->begin(ROM_K_GEMVT);
+        launch_gemvt(Vb_, ldb_, nzr_, k, zb_, 0, 1, tmpl_, gt_part_, st_);
+        tm_->end(ROM_K_GEMVT, 8.0 * nzr_ * (k + 1), 2.0 * nzr_ * k);
+      }
+    } else {
+      launch_dot2_scale(n_, q, vAB_, vAB_ + ld_, dmu_, r2_, &ctrl_->sc[8], red_part_, st_);
+      if (k > 0) {
+        tm_->begin(ROM_K_GEMVT);
+        launch_gemvt(Q_, ld_, n_, k, r2_, 0, 1, tmpl_, gt_part_, st_);
+        tm_->end(ROM_K_GEMVT, 8.0 * n_ * (k + 1), 2.0 * n_ * k);
+      }
     }
     launch_border_from_proj(h, cbuf_, tmpl_, &ctrl_->sc[4], &ctrl_->sc[8], k, tmpr_, st_);
     launch_border_fill(tmpr_, k, Gs_, Gi_, ldg_, st_);
@@ -611,7 +630,12 @@ class Sequencer {
   void rebuild_gi() {
     if (m_ == 0) return;
     tm_->begin(ROM_K_GRAM);
-    launch_gram(Q_, ld_, m_, Q_, ld_, m_, n_, dmu_, true, Gs_, ldg_, mu0_, Gi_, ldg_, gram_part_, st_);
+    if (compact_)
+      launch_gram(Vb_, ldb_, m_, Vb_, ldb_, m_, nzr_, dmub_, true, Gs_, ldg_, mu0_, Gi_, ldg_,
+                  gram_part_, st_);
+    else
+      launch_gram(Q_, ld_, m_, Q_, ld_, m_, n_, dmu_, true, Gs_, ldg_, mu0_, Gi_, ldg_,
+                  gram_part_, st_);
     tm_->end(ROM_K_GRAM, 8.0 * n_ * (m_ + 1), 2.0 * n_ * m_ * m_);
     launch_linv_rebuild(Gi_, ldg_, m_, Lc_, Lr_, lwork_, &ctrl_->status[0], st_);
   }
@@ -657,6 +681,12 @@ class Sequencer {
       cur_point_ = i;
       mu0_ = params[i].mu0;
       launch_mu_eval(S_, make_bumps(params[i], S_.dim), op_->diag_star, diag_i_, dmu_, st);
+      // the rows of bump support of this point, and V gathered on them
+      launch_nz_rows(n_, dmu_, bidx_, dmub_, nzcap_, &ctrl_->status[2], nzwork_, st);
+      sync();
+      nzr_ = h_->status[2];
+      compact_ = nzr_ > 0 && nzr_ <= nzcap_;
+      if (compact_) launch_gather_idx(Q_, ld_, bidx_, nzr_, 0, m_, Vb_, ldb_, st);
       if (mixed_) launch_cast_f32(n_, diag_i_, diag32_, st);
       if (i == 0) {
         // V <- orth(U_0): CGS2 append of every column (Alg. 2 initialisation)
@@ -829,6 +859,7 @@ class Sequencer {
       tm_->end(ROM_K_GEMVT, 8.0 * n_ * (mk + nv), 2.0 * n_ * mk * nv);
     }
     launch_border_fill_block(bblk_, mk, m0, k, Gs_, Gi_, ldg_, st_);
+    if (compact_) launch_gather_idx(Q_, ld_, bidx_, nzr_, m0, mk, Vb_, ldb_, st_);
     for (int c = 0; c < k; ++c)
       launch_linv_border(Lc_, Lr_, ldg_, m0 + c, Gi_ + (int64_t)(m0 + c) * ldg_, tmpl_, tmpr_,
                          &ctrl_->status[0], gt_part_, st_, &ctrl_->sc[12]);
@@ -1515,6 +1546,13 @@ class Sequencer {
   double *blk_ = nullptr, *bblk_ = nullptr;   // block append: A Q_new, its projections
   double* xg_ = nullptr;                       // start moved by an initial guess
   double *diag_i_, *dmu_, *Gs_, *Gi_, *Lc_, *Lr_, *gram_part_, *red_part_, *gt_part_;
+  // bump-row compaction of the current point: V^T (dmu o q) and V^T diag(dmu) V only read
+  // the rows where dmu != 0, so V is kept gathered on them (Vb, nzr_ x m, ld ldb_)
+  double *Vb_ = nullptr, *dmub_ = nullptr, *zb_ = nullptr;
+  int64_t* bidx_ = nullptr;
+  int* nzwork_ = nullptr;
+  int64_t nzcap_ = 0, ldb_ = 0, nzr_ = 0;
+  bool compact_ = false;
   double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_, *lwork_;
   Ctrl* ctrl_;
   double *part1_, *part2_;

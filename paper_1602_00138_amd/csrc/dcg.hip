@@ -183,14 +183,17 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_dir(const T* __restrict__ W, int6
   constexpr bool GPF = GramPf<NJT>::value;
   double gr[GPF ? NJT : 1];
   gram_row<NJT, GPF>(Ginv, nj, gr);
+  // the state's scalars are read with the rows, ahead of the partial sums
+  const double g0 = cg->gamma[0], g1 = cg->gamma[1], tol2 = cg->tol2;
+  const int maxit = cg->maxit;
   __shared__ T tot[NJT + 1];
   __shared__ T ys[NJ_MAX];
   sum_partials_t<NJT + 1, CG_BS>(part2, P2, tot);
   const double gnew = (double)tot[NJT];
-  const double gold = first ? 1.0 : cg->gamma[iter & 1];
+  const double gold = first ? 1.0 : ((iter & 1) ? g1 : g0);
   const bool nonfinite = !isfinite(gnew);
-  const bool conv = gnew <= cg->tol2;
-  const bool hit = !first && iter + 1 >= cg->maxit;
+  const bool conv = gnew <= tol2;
+  const bool hit = !first && iter + 1 >= maxit;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     cg->gamma[(iter + 1) & 1] = gnew;
     if (!first) cg->its = iter + 1;
@@ -264,6 +267,7 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(const T* __restrict__ AW, 
       }
     }
   };
+  const double g0 = cg->gamma[0], g1 = cg->gamma[1];   // read with the rows, used after the sum
   load(base);
   __shared__ T pwt[1];
   sum_partials_t<1, CG_BS>(part1, P1, pwt);
@@ -279,7 +283,7 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(const T* __restrict__ AW, 
     cg->pw = pw;
     cg->kcur = iter;
   }
-  const T alpha = (T)(cg->gamma[iter & 1] / pw);
+  const T alpha = (T)(((iter & 1) ? g1 : g0) / pw);
   T acc[NJT + 1];
 #pragma unroll
   for (int c = 0; c <= NJT; ++c) acc[c] = T(0);

@@ -26,6 +26,9 @@ template <typename T, int NJT>
 struct CgRows {
   static constexpr int value =
       sizeof(T) == 8 ? (NJT <= 16 ? 4 : NJT <= 32 ? 2 : 0) : (NJT <= 32 ? 4 : 0);
+  // the narrow variant: half the rows per thread, more waves per SIMD (batches of
+  // members, where a block walks several chunks, can prefer it; the tuner decides)
+  static constexpr int narrow = value >= 2 ? value / 2 : value;
 };
 constexpr int CG_GRID = 256;
 constexpr int START_BS = 256;
@@ -342,11 +345,19 @@ template <typename T>
 void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
                     const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
                     int iter, CGState* cg, const T* part2, int64_t p2stride, int nb, int P,
-                    hipStream_t st, int P2) {
+                    hipStream_t st, int P2, int narrow) {
   const dim3 grid(P, nb);
   if (P2 <= 0) P2 = P;
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CG_BS), 0, st, W, wstride, ld, n, Ginv, gstride, s, p, vstride, iter, cg, part2, p2stride, P2); break;
+#define C(J)                                                                                    \
+  case J:                                                                                       \
+    if (narrow)                                                                                 \
+      ROM_LAUNCH((k_dcg_dir<T, J, CgRows<T, J>::narrow>), grid, dim3(CG_BS), 0, st, W, wstride,  \
+                 ld, n, Ginv, gstride, s, p, vstride, iter, cg, part2, p2stride, P2);           \
+    else                                                                                        \
+      ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CG_BS), 0, st, W, wstride, ld, n, Ginv, gstride,  \
+                 s, p, vstride, iter, cg, part2, p2stride, P2);                                 \
+    break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -357,10 +368,19 @@ template <typename T>
 void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax, const T* p,
                        const T* w, T* g, T* s, int64_t vstride, int iter, CGState* cg,
                        const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
-                       int nb, int P, hipStream_t st) {
+                       int nb, int P, hipStream_t st, int narrow) {
   const dim3 grid(P, nb);
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CG_BS), 0, st, AW, wstride, ld, n, p, w, g, s, vstride, iter, cg, part1, P1, p1stride, part2, p2stride); break;
+#define C(J)                                                                                     \
+  case J:                                                                                        \
+    if (narrow)                                                                                  \
+      ROM_LAUNCH((k_dcg_update<T, J, CgRows<T, J>::narrow>), grid, dim3(CG_BS), 0, st, AW,        \
+                 wstride, ld, n, p, w, g, s, vstride, iter, cg, part1, P1, p1stride, part2,      \
+                 p2stride);                                                                      \
+    else                                                                                         \
+      ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CG_BS), 0, st, AW, wstride, ld, n, p, w, g, s,  \
+                 vstride, iter, cg, part1, P1, p1stride, part2, p2stride);                       \
+    break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -374,10 +394,10 @@ void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int 
                                     hipStream_t);                                                \
   template void launch_dcg_dir<T>(const T*, int64_t, int64_t, int64_t, int, const double*,       \
                                   int64_t, const T*, T*, int64_t, int, CGState*, const T*,       \
-                                  int64_t, int, int, hipStream_t, int);                          \
+                                  int64_t, int, int, hipStream_t, int, int);                     \
   template void launch_dcg_update<T>(const T*, int64_t, int64_t, int64_t, int, const T*,         \
                                      const T*, T*, T*, int64_t, int, CGState*, const T*, int,    \
-                                     int64_t, T*, int64_t, int, int, hipStream_t);
+                                     int64_t, T*, int64_t, int, int, hipStream_t, int);
 INSTANTIATE(double)
 INSTANTIATE(float)
 #undef INSTANTIATE

@@ -215,7 +215,8 @@ void launch_dot2_scale(int64_t n, const double* x, const double* a, const double
 // per member, at strides p1stride, p2stride.  iter: 0-based step index shared by the
 // batch (-1 for the direction after the start; ITER_STATE: from the state, see above).
 // P2 of the direction kernel: the partial rows it reduces, the grid of the launch before
-// it (0: P; the start may run on a wider grid than the steps).
+// it (0: P; the start may run on a wider grid than the steps).  narrow: the variant with
+// half the rows per thread (more waves per SIMD).
 // cg[y].t holds U_j^T r before the start.  Inactive members (done set at setup) return
 // at once from every kernel.
 int dcg_blocks(int64_t n);
@@ -231,7 +232,7 @@ template <typename T>
 void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
                     const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
                     int iter, CGState* cg, const T* part2, int64_t p2stride, int nb, int P,
-                    hipStream_t st, int P2 = 0);
+                    hipStream_t st, int P2 = 0, int narrow = 0);
 template <typename T>
 void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
                       int64_t vstride, CGState* cg, T* part1, int nb, hipStream_t st);
@@ -239,7 +240,7 @@ template <typename T>
 void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax, const T* p,
                        const T* w, T* g, T* s, int64_t vstride, int iter, CGState* cg,
                        const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
-                       int nb, int P, hipStream_t st);
+                       int nb, int P, hipStream_t st, int narrow = 0);
 
 // Error reporting shared by the entry points of every subsystem (sets rom_last_error).
 rom_status report(const Error& e);

@@ -1215,17 +1215,19 @@ class Sequencer {
     int flag[G_MAX] = {};
   };
 
-  // Blocks per member of the CG step kernels.  Fixed shape: the full grid for one
-  // member, split among the members of a batch.  With opts.tune the first batch of each
-  // (arithmetic, batch size, U_j width class, grid size) in the process times every
-  // power-of-two candidate on its own data (a few CG steps each, from its real start;
-  // the solve then restarts) and keeps the fastest for the rest of the process.
+  // Launch shape of the CG step kernels, 2 P + narrow: P blocks per member, narrow for
+  // the variant with half the rows per thread.  Fixed shape: the full grid for one member,
+  // split among the members of a batch (narrow for batches).  With opts.tune the first
+  // batch of each (arithmetic, batch size, U_j width class, grid size) in the process times
+  // every power-of-two P with both variants on its own data (a few CG steps each, from its
+  // real start; the solve then restarts) and keeps the fastest for the rest of the process.
   template <typename T, typename Bufs>
   int cg_shape(const Batch& bt, const Bufs& b, const double* rhs, T* dvec, int64_t wstride,
                int64_t gstride, int njmax) {
     const int nb = bt.nb;
     const int Pmax = dcg_blocks(n_);
-    const int fixed = std::max(std::min(Pmax, 8), Pmax / nb);
+    // shape = 2 P + narrow (the variant with half the rows per thread)
+    const int fixed = 2 * std::max(std::min(Pmax, 8), Pmax / nb) + (nb > 1 ? 1 : 0);
     if (!tune_) return fixed;
     int dev = 0;
     ROM_HIP(hipGetDevice(&dev));
@@ -1236,7 +1238,10 @@ class Sequencer {
       if (it != tune_map().end()) return it->second;
     }
     std::vector<int> cand;
-    for (int P = Pmax; P >= 8; P /= 2) cand.push_back(P);
+    for (int P = Pmax; P >= 8; P /= 2) {
+      cand.push_back(2 * P);
+      cand.push_back(2 * P + 1);
+    }
     int best = fixed;
     if (cand.size() > 1) {
       CGState* cg = ctrl_->cg;
@@ -1268,14 +1273,15 @@ class Sequencer {
       int k = 0;
       float best_ms = 1e30f;
       for (int rep = 0; rep < 2; ++rep) {   // the first round warms up
-        for (int P : cand) {
+        for (int shape : cand) {
+          const int P = shape >> 1, nr = shape & 1;
           ROM_HIP(hipEventRecord(e0, st_));
           for (int step = 0; step < 4; ++step, ++k) {
             launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, st_);
             launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
-                                 b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_);
+                                 b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_, nr);
             launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,
-                              b.part2, p2s_, nb, P, st_);
+                              b.part2, p2s_, nb, P, st_, 0, nr);
           }
           ROM_HIP(hipEventRecord(e1, st_));
           ROM_HIP(hipEventSynchronize(e1));
@@ -1283,7 +1289,7 @@ class Sequencer {
           ROM_HIP(hipEventElapsedTime(&ms, e0, e1));
           if (rep == 1 && ms < best_ms) {
             best_ms = ms;
-            best = P;
+            best = shape;
           }
         }
       }
@@ -1298,9 +1304,11 @@ class Sequencer {
   // (value type, batch size, shared recycle space, width class, blocks, output vector),
   // kept for the rest of the call.
   template <typename T, typename Bufs>
-  hipGraphExec_t chunk_graph(const Bufs& b, int nb, bool shared, int njmax, int P,
+  hipGraphExec_t chunk_graph(const Bufs& b, int nb, bool shared, int njmax, int shape,
                              int64_t wstride, int64_t gstride, T* dvec, const StencilShape& sh) {
-    const GraphKey key{(int)sizeof(T), nb, shared ? 1 : 0, njt_of(njmax), P, (const void*)dvec};
+    const GraphKey key{(int)sizeof(T), nb, shared ? 1 : 0, njt_of(njmax), shape,
+                       (const void*)dvec};
+    const int P = shape >> 1, nr = shape & 1;
     auto it = graphs_.find(key);
     if (it != graphs_.end()) return it->second;
     CGState* cg = ctrl_->cg;
@@ -1314,9 +1322,9 @@ class Sequencer {
       for (int c = 0; c < GRAPH_STEPS; ++c) {
         launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, cs);
         launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, ITER_STATE,
-                             cg, b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, cs);
+                             cg, b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, cs, nr);
         launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_,
-                          ITER_STATE, cg, b.part2, p2s_, nb, P, cs);
+                          ITER_STATE, cg, b.part2, p2s_, nb, P, cs, 0, nr);
       }
     } catch (...) {
       hipGraph_t dummy = nullptr;
@@ -1358,7 +1366,8 @@ class Sequencer {
       }
     }
     if (nact == 0) return;
-    const int P = cg_shape<T>(bt, b, rhs, dvec, wstride, gstride, njmax);
+    const int shape = cg_shape<T>(bt, b, rhs, dvec, wstride, gstride, njmax);
+    const int P = shape >> 1, nr = shape & 1;
     launch_cg_setup(cg, su, nb, st_);
     // U_j^T r_j for the start
     if (njmax > 0) {
@@ -1390,7 +1399,7 @@ class Sequencer {
                         ld_, cg, b.part2, p2s_, nb, P0, st_);
     tm_->begin(ROM_K_DCG_DIR);
     launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, -1, cg,
-                      b.part2, p2s_, nb, P, st_, P0);
+                      b.part2, p2s_, nb, P, st_, P0, nr);
     tm_->end(ROM_K_DCG_DIR, nact * E * n_ * (2 + njavg), nact * n_ * (1.0 + 2.0 * njavg));
     // per member and step
     const double by_apply = E * n_ * (3 + (S_.var ? S_.dim : 0));
@@ -1411,7 +1420,8 @@ class Sequencer {
     for (;;) {
       if (graphs) {
         const int reps = (next + GRAPH_STEPS - 1) / GRAPH_STEPS;
-        hipGraphExec_t ex = chunk_graph<T>(b, nb, bt.shared, njmax, P, wstride, gstride, dvec, sh);
+        hipGraphExec_t ex =
+            chunk_graph<T>(b, nb, bt.shared, njmax, shape, wstride, gstride, dvec, sh);
         for (int r = 0; r < reps; ++r) ROM_HIP(hipGraphLaunch(ex, st_));
         next = reps * GRAPH_STEPS;
         for (int c = 0; c < next; ++c) {
@@ -1427,11 +1437,11 @@ class Sequencer {
         tm_->end(ROM_K_SPMV, nlive * by_apply, nlive * fl_apply);
         tm_->begin(ROM_K_DCG_UPDATE);
         launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
-                             b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_);
+                             b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_, nr);
         tm_->end(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
         tm_->begin(ROM_K_DCG_DIR);
         launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,
-                          b.part2, p2s_, nb, P, st_);
+                          b.part2, p2s_, nb, P, st_, 0, nr);
         tm_->end(ROM_K_DCG_DIR, nlive * by_dir, nlive * fl_dir);
       }
       ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));

@@ -251,19 +251,19 @@ void report_message(const std::string& m);
 // weights: BF16 [rows = round_up(cout, 16)][Kp = round_up(27 Cpi, 32)].
 int seed_round8(int c);
 int seed_kp(int cp);
+// up != 0: X is on the grid of half the size (even nx, ny, nz) and the layer reads its
+// 2x nearest-neighbour upsampling.
 void launch_seed_conv(int nx, int ny, int nz, int batch, const void* X, int Cpi, const void* W,
                       int Kp, int Cout, int rows, const float* bias, const void* skip, int relu,
-                      void* Y, int Cpo, hipStream_t st);
+                      void* Y, int Cpo, hipStream_t st, int up = 0);
 size_t seed_wgrad_partials(int nx, int ny, int nz, int batch, int rows, int Kp);
 void launch_seed_wgrad(int nx, int ny, int nz, int batch, const void* X, int Cpi, const void* dZ,
                        int Cpo, int Cout, int rows, int Kp, float* P, float* dWg, float* Pb,
-                       float* db, hipStream_t st);
+                       float* db, hipStream_t st, int up = 0);
 void launch_seed_pool(int nx, int ny, int nz, int batch, const void* X, void* Y, int C,
                       hipStream_t st);
 void launch_seed_pool_bwd(int nx, int ny, int nz, int batch, const void* dY, void* dX, int C,
                           int acc, hipStream_t st);
-void launch_seed_up(int nx, int ny, int nz, int batch, const void* X, void* Y, int C,
-                    hipStream_t st);
 void launch_seed_up_bwd(int nx, int ny, int nz, int batch, const void* dY, void* dX, int C,
                         hipStream_t st);
 void launch_seed_relu_bwd(int64_t ne, void* dY, const void* Y, hipStream_t st);

@@ -25,71 +25,96 @@ struct Grid3 {
   int nx, ny, nz, batch;
 };
 
-// neighbour of voxel v at tap t (0..26, t = (dz+1) 9 + (dy+1) 3 + (dx+1)), or -1 outside
-__device__ __forceinline__ int64_t neighbour(const Grid3& g, int64_t v, int t) {
-  const int x = (int)(v % g.nx);
-  const int64_t r = v / g.nx;
-  const int y = (int)(r % g.ny);
-  const int64_t r2 = r / g.ny;
-  const int z = (int)(r2 % g.nz);
-  const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-  const int xx = x + dx, yy = y + dy, zz = z + dz;
-  if (xx < 0 || xx >= g.nx || yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz) return -1;
-  return v + dx + (int64_t)g.nx * (dy + (int64_t)g.ny * dz);
-}
-
 // Convolution: Y = act(conv(X; W) + bias + skip).  W: [cop16][Kp] BF16 (zero beyond K =
 // 27 Cpi and beyond Cout), NT = cop16 / 16 output tiles.  Writes channels < Cpo of Y
-// (zeros for Cout <= c < Cpo).
-template <int NT>
+// (zeros for Cout <= c < Cpo).  A wave owns VT tiles of 16 voxels, so each weight load
+// feeds VT MFMAs; a lane decomposes its voxels into (x, y, z) once and follows its tap
+// and channel through the k loop by increments (no divisions inside the loop).  up != 0:
+// X lives on the grid of half the size and the convolution reads its 2x nearest-neighbour
+// upsampling (fine voxel (x, y, z) takes coarse voxel (x/2, y/2, z/2)) without forming it.
+template <int NT, int VT>
 __global__ __launch_bounds__(BS) void k_conv(Grid3 g, const __bf16* __restrict__ X, int Cpi,
                                              const __bf16* __restrict__ W, int Kp, int Cout,
                                              const float* __restrict__ bias,
                                              const __bf16* __restrict__ skip, int relu,
-                                             __bf16* __restrict__ Y, int Cpo) {
+                                             __bf16* __restrict__ Y, int Cpo, int up) {
   const int64_t nv = (int64_t)g.nx * g.ny * g.nz * g.batch;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t v0 = (int64_t)blockIdx.x * 64 + wid * 16;
-  const int64_t va = v0 + (lane & 15);   // this lane's A row
+  const int64_t v0 = ((int64_t)blockIdx.x * (BS / WAVE) + wid) * (16 * VT);
   const int kg = lane >> 4;              // which 8 of the 32 k of a step
   const int K = 27 * Cpi;
-  float4_t acc[NT];
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  const int cx = g.nx >> 1, cy = g.ny >> 1, cz = g.nz >> 1;   // the coarse grid (up)
+  int64_t va[VT], cb[VT];
+  int vx[VT], vy[VT], vz[VT];
+  bool rowok[VT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = (float4_t){0.f, 0.f, 0.f, 0.f};
-  const bool rowok = va < nv;
+  for (int u = 0; u < VT; ++u) {
+    va[u] = v0 + 16 * u + (lane & 15);
+    rowok[u] = va[u] < nv;
+    const int64_t v = rowok[u] ? va[u] : 0;
+    vx[u] = (int)(v % g.nx);
+    const int64_t r = v / g.nx;
+    vy[u] = (int)(r % g.ny);
+    const int64_t r2 = r / g.ny;
+    vz[u] = (int)(r2 % g.nz);
+    cb[u] = (r2 / g.nz) * cz;   // batch offset in coarse planes
+  }
+  float4_t acc[VT][NT];
+#pragma unroll
+  for (int u = 0; u < VT; ++u)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[u][t] = (float4_t){0.f, 0.f, 0.f, 0.f};
+  int tap = (8 * kg) / Cpi, c = (8 * kg) % Cpi;
   for (int k0 = 0; k0 < Kp; k0 += 32) {
     const int k = k0 + 8 * kg;
-    bf16x8 a;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int64_t off = dx + sy * dy + sz * dz;
+    bf16x8 a[VT];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] = (__bf16)0.f;
-    if (rowok && k < K) {
-      const int tap = k / Cpi, c = k % Cpi;
-      const int64_t nb = neighbour(g, va, tap);
-      if (nb >= 0) a = *reinterpret_cast<const bf16x8*>(X + nb * Cpi + c);
+    for (int u = 0; u < VT; ++u) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[u][q] = (__bf16)0.f;
+      const int xx = vx[u] + dx, yy = vy[u] + dy, zz = vz[u] + dz;
+      if (rowok[u] && k < K && xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny && zz >= 0 &&
+          zz < g.nz) {
+        const int64_t src =
+            up ? (((cb[u] + (zz >> 1)) * cy + (yy >> 1)) * cx + (xx >> 1)) : va[u] + off;
+        a[u] = *reinterpret_cast<const bf16x8*>(X + src * Cpi + c);
+      }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const bf16x8 b = *reinterpret_cast<const bf16x8*>(W + (int64_t)(16 * t + (lane & 15)) * Kp + k);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < VT; ++u)
+        acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b, acc[u][t], 0, 0, 0);
+    }
+    c += 32;
+    while (c >= Cpi) {
+      c -= Cpi;
+      ++tap;
     }
   }
   // D layout: register r of a lane holds row 4 (lane / 16) + r, column lane % 16
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int o = 16 * t + (lane & 15);
+  for (int u = 0; u < VT; ++u)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t v = v0 + 4 * kg + r;
-      if (v >= nv || o >= Cpo) continue;
-      float val = 0.f;
-      if (o < Cout) {
-        val = acc[t][r] + (bias ? bias[o] : 0.f);
-        if (skip) val += (float)skip[v * Cpo + o];
-        if (relu) val = fmaxf(val, 0.f);
+    for (int t = 0; t < NT; ++t) {
+      const int o = 16 * t + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t v = v0 + 16 * u + 4 * kg + r;
+        if (v >= nv || o >= Cpo) continue;
+        float val = 0.f;
+        if (o < Cout) {
+          val = acc[u][t][r] + (bias ? bias[o] : 0.f);
+          if (skip) val += (float)skip[v * Cpo + o];
+          if (relu) val = fmaxf(val, 0.f);
+        }
+        Y[v * Cpo + o] = (__bf16)val;
       }
-      Y[v * Cpo + o] = (__bf16)val;
     }
-  }
 }
 
 // Weight gradient partials: P[chunk][o][k] = sum over the chunk's voxels of
@@ -98,7 +123,8 @@ __global__ __launch_bounds__(BS) void k_conv(Grid3 g, const __bf16* __restrict__
 constexpr int WG_VOX = 2048;   // voxels per chunk
 __global__ __launch_bounds__(BS) void k_conv_wgrad(Grid3 g, const __bf16* __restrict__ X,
                                                    int Cpi, const __bf16* __restrict__ dZ,
-                                                   int Cpo, int Kp, float* __restrict__ P) {
+                                                   int Cpo, int Kp, float* __restrict__ P,
+                                                   int up) {
   __shared__ __bf16 Zs[32][16 + 2];
   __shared__ __bf16 As[32][64 + 8];
   const int64_t nv = (int64_t)g.nx * g.ny * g.nz * g.batch;
@@ -113,6 +139,25 @@ __global__ __launch_bounds__(BS) void k_conv_wgrad(Grid3 g, const __bf16* __rest
   // t/8, k 8 (t%8) .. +7)
   const int zr = threadIdx.x >> 3, zc = 2 * (threadIdx.x & 7);
   const int ar = threadIdx.x >> 3, ac = 8 * (threadIdx.x & 7);
+  // this thread's k (fixed: tap and channel once) and its staged voxel, decomposed once
+  // and then advanced by 32 per step
+  const int ka = kb + ac;
+  const bool kin = ka < K;
+  const int tap = kin ? ka / Cpi : 0, ca = kin ? ka % Cpi : 0;
+  const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+  const int64_t off = dx + (int64_t)g.nx * (dy + (int64_t)g.ny * dz);
+  const int cx = g.nx >> 1, cy = g.ny >> 1, cz = g.nz >> 1;   // the coarse grid (up)
+  int ax, ay, az;
+  int64_t ab;
+  {
+    const int64_t v = vbeg + ar;
+    ax = (int)(v % g.nx);
+    const int64_t r = v / g.nx;
+    ay = (int)(r % g.ny);
+    const int64_t r2 = r / g.ny;
+    az = (int)(r2 % g.nz);
+    ab = r2 / g.nz;
+  }
   for (int64_t vs = vbeg; vs < vend; vs += 32) {
     {
       const int64_t v = vs + zr;
@@ -126,17 +171,29 @@ __global__ __launch_bounds__(BS) void k_conv_wgrad(Grid3 g, const __bf16* __rest
     }
     {
       const int64_t v = vs + ar;
-      const int k = kb + ac;
       bf16x8 a;
 #pragma unroll
       for (int q = 0; q < 8; ++q) a[q] = (__bf16)0.f;
-      if (v < vend && k < K) {
-        const int tap = k / Cpi, c = k % Cpi;
-        const int64_t nb = neighbour(g, v, tap);
-        if (nb >= 0) a = *reinterpret_cast<const bf16x8*>(X + nb * Cpi + c);
+      const int xx = ax + dx, yy = ay + dy, zz = az + dz;
+      if (v < vend && kin && xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny && zz >= 0 &&
+          zz < g.nz) {
+        const int64_t src =
+            up ? (((ab * cz + (zz >> 1)) * cy + (yy >> 1)) * cx + (xx >> 1)) : v + off;
+        a = *reinterpret_cast<const bf16x8*>(X + src * Cpi + ca);
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) As[ar][ac + q] = a[q];
+      ax += 32;
+      while (ax >= g.nx) {
+        ax -= g.nx;
+        if (++ay == g.ny) {
+          ay = 0;
+          if (++az == g.nz) {
+            az = 0;
+            ++ab;
+          }
+        }
+      }
     }
     __syncthreads();
     // A operand: A[i = o][kk = voxel]; B operand: B[kk = voxel][j = k]
@@ -228,22 +285,6 @@ __global__ void k_pool_bwd(Grid3 g, const __bf16* __restrict__ dY, __bf16* __res
   float val = 0.125f * (float)dY[vc * C + c];
   if (acc) val += (float)dX[e];
   dX[e] = (__bf16)val;
-}
-
-__global__ void k_up(Grid3 g, const __bf16* __restrict__ X, __bf16* __restrict__ Y, int C) {
-  const int64_t nv = (int64_t)g.nx * g.ny * g.nz * g.batch;
-  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (e >= nv * C) return;
-  const int c = (int)(e % C);
-  const int64_t v = e / C;
-  const int x = (int)(v % g.nx);
-  const int y = (int)((v / g.nx) % g.ny);
-  const int64_t zb = v / ((int64_t)g.nx * g.ny);
-  const int z = (int)(zb % g.nz);
-  const int64_t b = zb / g.nz;
-  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
-  const int64_t vc = (x / 2) + (int64_t)cx * ((y / 2) + (int64_t)cy * ((z / 2) + (int64_t)cz * b));
-  Y[e] = X[vc * C + c];
 }
 
 __global__ void k_up_bwd(Grid3 g, const __bf16* __restrict__ dY, __bf16* __restrict__ dX, int C) {
@@ -423,16 +464,18 @@ int seed_kp(int cp) { return (27 * cp + 31) / 32 * 32; }
 
 void launch_seed_conv(int nx, int ny, int nz, int batch, const void* X, int Cpi, const void* W,
                       int Kp, int Cout, int rows, const float* bias, const void* skip, int relu,
-                      void* Y, int Cpo, hipStream_t st) {
+                      void* Y, int Cpo, hipStream_t st, int up) {
+  if (up && ((nx | ny | nz) & 1)) throw Error(ROM_EINVAL, "seed conv: upsampled input needs even sizes");
   const Grid3 g{nx, ny, nz, batch};
   const int64_t nv = (int64_t)nx * ny * nz * batch;
-  const dim3 grid(ceil_div(nv, 64));
+  constexpr int VT = 2;
+  const dim3 grid(ceil_div(nv, 64 * VT));
   const __bf16* x = (const __bf16*)X;
   const __bf16* w = (const __bf16*)W;
   const __bf16* sk = (const __bf16*)skip;
   __bf16* y = (__bf16*)Y;
   switch (rows / 16) {
-#define C(N) case N: ROM_LAUNCH((k_conv<N>), grid, dim3(BS), 0, st, g, x, Cpi, w, Kp, Cout, bias, sk, relu, y, Cpo); break;
+#define C(N) case N: ROM_LAUNCH((k_conv<N, VT>), grid, dim3(BS), 0, st, g, x, Cpi, w, Kp, Cout, bias, sk, relu, y, Cpo, up); break;
     C(1) C(2) C(3) C(4)
 #undef C
     default: throw Error(ROM_EINVAL, "seed conv: at most 64 output channels");
@@ -447,12 +490,13 @@ size_t seed_wgrad_partials(int nx, int ny, int nz, int batch, int rows, int Kp) 
 
 void launch_seed_wgrad(int nx, int ny, int nz, int batch, const void* X, int Cpi, const void* dZ,
                        int Cpo, int Cout, int rows, int Kp, float* P, float* dWg, float* Pb,
-                       float* db, hipStream_t st) {
+                       float* db, hipStream_t st, int up) {
+  if (up && ((nx | ny | nz) & 1)) throw Error(ROM_EINVAL, "seed wgrad: upsampled input needs even sizes");
   const Grid3 g{nx, ny, nz, batch};
   const int64_t nv = (int64_t)nx * ny * nz * batch;
   const int nch = (int)ceil_div(nv, WG_VOX);
   ROM_LAUNCH(k_conv_wgrad, dim3(nch, ceil_div(Kp, 64), rows / 16), dim3(BS), 0, st, g,
-             (const __bf16*)X, Cpi, (const __bf16*)dZ, Cpo, Kp, P);
+             (const __bf16*)X, Cpi, (const __bf16*)dZ, Cpo, Kp, P, up);
   ROM_CHECK_LAUNCH();
   ROM_LAUNCH(k_wgrad_reduce, dim3(gridn((int64_t)rows * Kp)), dim3(BS), 0, st, P, nch, rows, Kp,
              dWg, 0);
@@ -478,14 +522,6 @@ void launch_seed_pool_bwd(int nx, int ny, int nz, int batch, const void* dY, voi
   const int64_t n = (int64_t)nx * ny * nz * batch * C;
   ROM_LAUNCH(k_pool_bwd, dim3(gridn(n)), dim3(BS), 0, st, g, (const __bf16*)dY, (__bf16*)dX, C,
              acc);
-  ROM_CHECK_LAUNCH();
-}
-
-void launch_seed_up(int nx, int ny, int nz, int batch, const void* X, void* Y, int C,
-                    hipStream_t st) {
-  const Grid3 g{nx, ny, nz, batch};
-  const int64_t n = (int64_t)nx * ny * nz * batch * C;
-  ROM_LAUNCH(k_up, dim3(gridn(n)), dim3(BS), 0, st, g, (const __bf16*)X, (__bf16*)Y, C);
   ROM_CHECK_LAUNCH();
 }
 

@@ -59,7 +59,7 @@ struct rom_seednet {
   float *part, *partb;
   double *lpart, *loss;
   // activations (BF16) and their gradients
-  void *x, *e0, *p1, *e1, *p2, *e2, *p3, *e3, *u2, *d2, *u1, *d1, *u0, *d0, *y;
+  void *x, *e0, *p1, *e1, *p2, *e2, *p3, *e3, *d2, *d1, *d0, *y;
   void *ge0, *gp1, *ge1, *gp2, *ge2, *gp3, *ge3, *gu2, *gd2, *gu1, *gd1, *gu0, *gd0, *gy;
   double* hloss = nullptr;   // pinned host copy
 };
@@ -119,9 +119,10 @@ size_t layout(rom_seednet* net, int nx, int ny, int nz, int maxb, void* pmem, vo
   double* lp = a.take<double>(2048);
   double* ls = a.take<double>(8);
   auto act = [&](int lev, int c) { return a.take<uint16_t>((size_t)nl[lev] * c); };
+  // the decoder inputs (upsampled e3, d2, d1) are never formed: the layers read them
   void *x = act(0, 8), *e0 = act(0, 16), *p1 = act(1, 16), *e1 = act(1, 32), *p2 = act(2, 32),
-       *e2 = act(2, 48), *p3 = act(3, 48), *e3 = act(3, 64), *u2 = act(2, 64), *d2 = act(2, 48),
-       *u1 = act(1, 48), *d1 = act(1, 32), *u0 = act(0, 32), *d0 = act(0, 16), *y = act(0, 8);
+       *e2 = act(2, 48), *p3 = act(3, 48), *e3 = act(3, 64), *d2 = act(2, 48), *d1 = act(1, 32),
+       *d0 = act(0, 16), *y = act(0, 8);
   void *ge0 = act(0, 16), *gp1 = act(1, 16), *ge1 = act(1, 32), *gp2 = act(2, 32),
        *ge2 = act(2, 48), *gp3 = act(3, 48), *ge3 = act(3, 64), *gu2 = act(2, 64),
        *gd2 = act(2, 48), *gu1 = act(1, 48), *gd1 = act(1, 32), *gu0 = act(0, 32),
@@ -144,8 +145,7 @@ size_t layout(rom_seednet* net, int nx, int ny, int nz, int maxb, void* pmem, vo
     net->lpart = lp;
     net->loss = ls;
     net->x = x; net->e0 = e0; net->p1 = p1; net->e1 = e1; net->p2 = p2; net->e2 = e2;
-    net->p3 = p3; net->e3 = e3; net->u2 = u2; net->d2 = d2; net->u1 = u1; net->d1 = d1;
-    net->u0 = u0; net->d0 = d0; net->y = y;
+    net->p3 = p3; net->e3 = e3; net->d2 = d2; net->d1 = d1; net->d0 = d0; net->y = y;
     net->ge0 = ge0; net->gp1 = gp1; net->ge1 = ge1; net->gp2 = gp2; net->ge2 = ge2;
     net->gp3 = gp3; net->ge3 = ge3; net->gu2 = gu2; net->gd2 = gd2; net->gu1 = gu1;
     net->gd1 = gd1; net->gu0 = gu0; net->gd0 = gd0; net->gy = gy;
@@ -160,13 +160,14 @@ void pack_all(rom_seednet* n, hipStream_t st) {
                              n->Wt[l], st);
 }
 
-// forward of one layer: Y = act(conv(X) + b + skip) on the layer's level grid
+// forward of one layer: Y = act(conv(X) + b + skip) on the layer's level grid (up: X is
+// on the next coarser level and the layer reads its upsampling)
 void conv(rom_seednet* n, int l, int b, const void* X, const void* skip, bool relu, void* Y,
-          hipStream_t st) {
+          hipStream_t st, bool up = false) {
   const int lev = LAYERS[l].level;
   launch_seed_conv(n->nx >> lev, n->ny >> lev, n->nz >> lev, b, X, n->Cpi[l], n->Wb[l], n->Kp[l],
                    LAYERS[l].cout, n->rows[l], n->P + n->boff[l], skip, relu ? 1 : 0, Y,
-                   n->Cpo[l], st);
+                   n->Cpo[l], st, up ? 1 : 0);
 }
 
 // data gradient of layer l: dX = conv(dZ; flipped, transposed weights)
@@ -176,12 +177,13 @@ void conv_dx(rom_seednet* n, int l, int b, const void* dZ, void* dX, hipStream_t
                    n->Ktp[l], LAYERS[l].cin, n->rowst[l], nullptr, nullptr, 0, dX, n->Cpi[l], st);
 }
 
-// weight and bias gradients of layer l (added into G)
-void conv_dw(rom_seednet* n, int l, int b, const void* X, const void* dZ, hipStream_t st) {
+// weight and bias gradients of layer l (added into G; up as for the forward)
+void conv_dw(rom_seednet* n, int l, int b, const void* X, const void* dZ, hipStream_t st,
+             bool up = false) {
   const int lev = LAYERS[l].level;
   launch_seed_wgrad(n->nx >> lev, n->ny >> lev, n->nz >> lev, b, X, n->Cpi[l], dZ, n->Cpo[l],
                     LAYERS[l].cout, n->rows[l], n->Kp[l], n->part, n->dWg[l], n->partb,
-                    n->G + n->boff[l], st);
+                    n->G + n->boff[l], st, up ? 1 : 0);
   launch_seed_unpack_wgrad(n->dWg[l], n->Kp[l], LAYERS[l].cout, LAYERS[l].cin, n->Cpi[l],
                            n->G + n->woff[l], st);
 }
@@ -200,12 +202,10 @@ void forward(rom_seednet* n, const float* in, int b, hipStream_t st) {
   conv(n, 2, b, n->p2, nullptr, true, n->e2, st);
   launch_seed_pool(nx / 4, ny / 4, nz / 4, b, n->e2, n->p3, 48, st);
   conv(n, 3, b, n->p3, nullptr, true, n->e3, st);
-  launch_seed_up(nx / 4, ny / 4, nz / 4, b, n->e3, n->u2, 64, st);
-  conv(n, 4, b, n->u2, n->e2, true, n->d2, st);
-  launch_seed_up(nx / 2, ny / 2, nz / 2, b, n->d2, n->u1, 48, st);
-  conv(n, 5, b, n->u1, n->e1, true, n->d1, st);
-  launch_seed_up(nx, ny, nz, b, n->d1, n->u0, 32, st);
-  conv(n, 6, b, n->u0, n->e0, true, n->d0, st);
+  // the decoder layers read the upsampling of the coarser level directly
+  conv(n, 4, b, n->e3, n->e2, true, n->d2, st, true);
+  conv(n, 5, b, n->d2, n->e1, true, n->d1, st, true);
+  conv(n, 6, b, n->d1, n->e0, true, n->d0, st, true);
   conv(n, 7, b, n->d0, nullptr, false, n->y, st);
 }
 
@@ -218,19 +218,19 @@ void backward(rom_seednet* n, const float* target, int b, hipStream_t st) {
   conv_dx(n, 7, b, n->gy, n->gd0, st);
   // d0 = relu(conv(u0) + e0)
   launch_seed_relu_bwd(nvox(n, 0, b) * 16, n->gd0, n->d0, st);
-  conv_dw(n, 6, b, n->u0, n->gd0, st);
+  conv_dw(n, 6, b, n->d1, n->gd0, st, true);
   conv_dx(n, 6, b, n->gd0, n->gu0, st);
   ROM_HIP(hipMemcpyAsync(n->ge0, n->gd0, nvox(n, 0, b) * 16 * 2, hipMemcpyDeviceToDevice, st));
   launch_seed_up_bwd(nx, ny, nz, b, n->gu0, n->gd1, 32, st);
   // d1
   launch_seed_relu_bwd(nvox(n, 1, b) * 32, n->gd1, n->d1, st);
-  conv_dw(n, 5, b, n->u1, n->gd1, st);
+  conv_dw(n, 5, b, n->d2, n->gd1, st, true);
   conv_dx(n, 5, b, n->gd1, n->gu1, st);
   ROM_HIP(hipMemcpyAsync(n->ge1, n->gd1, nvox(n, 1, b) * 32 * 2, hipMemcpyDeviceToDevice, st));
   launch_seed_up_bwd(nx / 2, ny / 2, nz / 2, b, n->gu1, n->gd2, 48, st);
   // d2
   launch_seed_relu_bwd(nvox(n, 2, b) * 48, n->gd2, n->d2, st);
-  conv_dw(n, 4, b, n->u2, n->gd2, st);
+  conv_dw(n, 4, b, n->e3, n->gd2, st, true);
   conv_dx(n, 4, b, n->gd2, n->gu2, st);
   ROM_HIP(hipMemcpyAsync(n->ge2, n->gd2, nvox(n, 2, b) * 48 * 2, hipMemcpyDeviceToDevice, st));
   launch_seed_up_bwd(nx / 4, ny / 4, nz / 4, b, n->gu2, n->ge3, 64, st);

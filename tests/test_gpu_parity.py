@@ -116,6 +116,27 @@ def test_small_sequence_parity(drv, wl):
     prob.close()
 
 
+@pytest.mark.parametrize("radius,compact", [((0.10, 0.14), True), ((0.6, 0.8), False)])
+def test_bump_support_paths(drv, radius, compact):
+    """The border term V^T (dmu o q) and the per-point Gram V^T diag(dmu) V run on V
+    gathered on the rows of bump support when that support is at most max(1024, n/4)
+    rows, else on the full rows with zero chunks skipped.  Small bumps (about 2% of the
+    grid) take the first path, large ones (over 90%) the second; both match the oracle."""
+    from oracle import operator as op
+    wl = ph.small(3, (15, 14, 13), n_src=4, n_det=3, K=3).replace(radius=radius)
+    cap = min(wl.n, max(1024, wl.n // 4))
+    for p in ph.parameter_points(wl):
+        mu = op.mu_field(wl.dim, wl.N, p.mu0, p.centers, p.radii, p.amps)
+        support = int(np.count_nonzero(mu != p.mu0))
+        assert (0 < support <= cap) == compact, (support, cap)
+    orc = OracleProblem(wl)
+    ores = orc.run()
+    prob, pts, res = _gpu_run(drv, wl)
+    _check_sequence(wl, orc, ores, res, prob, pts)
+    res.close()
+    prob.close()
+
+
 def test_no_recycle_seed(drv):
     """k_u = 0: the first solve is plain CG from zero (the empty-basis edge case)."""
     wl = ph.small(3, (9, 9, 9), n_src=3, n_det=3, K=2, k_u=0)

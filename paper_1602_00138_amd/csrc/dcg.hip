@@ -85,19 +85,30 @@ __device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv,
   __syncthreads();
 }
 
+// Rows per thread of the start kernel (it reads both U_j and A U_j): as for the steps, as
+// many as keep the loaded rows and the running sums in registers.
+template <typename T, int NJT>
+struct StartRows {
+  static constexpr int value = sizeof(T) == 8 ? (NJT <= 8 ? 4 : NJT <= 16 ? 2 : 0)
+                                              : (NJT <= 16 ? 4 : 0);
+};
+
 // Start: y0 = G^{-1} U^T r (U^T r in cg->t), g = U y0, s = r - AU y0; partials of
 // (AU)^T s (values 0..nj-1) and s^T s (value NJT).  The right-hand side is FP64 and is
-// read as rscale * r (the mixed form solves for a unit-norm residual in FP32).
-template <typename T, int NJT, int B = START_BS>
-__global__ __launch_bounds__(B) void k_dcg_start(const T* __restrict__ W,
-                                                  const T* __restrict__ AW, int64_t wstride,
-                                                  int64_t ld, int64_t n,
-                                                  const double* __restrict__ Ginv,
-                                                  int64_t gstride, const double* __restrict__ r,
-                                                  int64_t rstride, T* __restrict__ g,
-                                                  T* __restrict__ s, int64_t vstride,
-                                                  const CGState* cgs, T* __restrict__ part2,
-                                                  int64_t p2stride) {
+// read as rscale * r (the mixed form solves for a unit-norm residual in FP32).  Rows as
+// in the step kernels: a thread loads its first chunk's rows before y0 is formed.
+template <typename T, int NJT, int RPT = StartRows<T, NJT>::value>
+__global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
+                                                         const T* __restrict__ AW,
+                                                         int64_t wstride, int64_t ld, int64_t n,
+                                                         const double* __restrict__ Ginv,
+                                                         int64_t gstride,
+                                                         const double* __restrict__ r,
+                                                         int64_t rstride, T* __restrict__ g,
+                                                         T* __restrict__ s, int64_t vstride,
+                                                         const CGState* cgs,
+                                                         T* __restrict__ part2,
+                                                         int64_t p2stride) {
   const int y = blockIdx.y;
   const CGState* cg = cgs + y;
   if (cg->done) return;
@@ -110,6 +121,27 @@ __global__ __launch_bounds__(B) void k_dcg_start(const T* __restrict__ W,
   part2 += y * p2stride;
   const int nj = cg->nj;
   const double rscale = cg->rscale;
+  constexpr bool PRE = RPT > 0;
+  constexpr int R = PRE ? RPT : 1;
+  constexpr int64_t CH = (int64_t)START_BS * R;
+  int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  T wr[R][PRE ? NJT : 1], ar[R][PRE ? NJT : 1], rv[R];
+  auto load = [&](int64_t b0) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int64_t i = b0 + (int64_t)q * START_BS;
+      const bool in = i < n;
+      rv[q] = in ? (T)r[i] : T(0);
+      if (PRE) {
+#pragma unroll
+        for (int c = 0; c < NJT; ++c) {
+          wr[q][PRE ? c : 0] = (in && c < nj) ? W[i + c * ld] : T(0);
+          ar[q][PRE ? c : 0] = (in && c < nj) ? AW[i + c * ld] : T(0);
+        }
+      }
+    }
+  };
+  load(base);
   __shared__ T ys[NJ_MAX];
   constexpr bool GPF = GramPf<NJT>::value;
   double gr[GPF ? NJT : 1];
@@ -119,26 +151,40 @@ __global__ __launch_bounds__(B) void k_dcg_start(const T* __restrict__ W,
   T acc[NJT + 1];
 #pragma unroll
   for (int c = 0; c <= NJT; ++c) acc[c] = T(0);
-  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
-    constexpr bool KEEP = NJT * sizeof(T) <= 256;   // cache the AU row in registers
-    T gi = T(0), si = (T)(rs * (T)r[i]);
-    T aw[KEEP ? NJT : 1];
+  for (;;) {
+    // without a preload the row of A U is still kept between its two uses when it fits
+    constexpr bool KEEP = !PRE && NJT * sizeof(T) <= 256;
 #pragma unroll
-    for (int c = 0; c < NJT; ++c)
-      if (c < nj) {
-        const T a = AW[i + c * ld];
-        if (KEEP) aw[KEEP ? c : 0] = a;
-        gi += W[i + c * ld] * ys[c];
-        si -= a * ys[c];
+    for (int q = 0; q < R; ++q) {
+      const int64_t i = base + (int64_t)q * START_BS;
+      const bool in = i < n;
+      T gi = T(0), si = rs * rv[q];
+      T kept[KEEP ? NJT : 1];
+#pragma unroll
+      for (int c = 0; c < NJT; ++c)
+        if (c < nj) {
+          const T wv = PRE ? wr[q][PRE ? c : 0] : (in ? W[i + c * ld] : T(0));
+          const T av = PRE ? ar[q][PRE ? c : 0] : (in ? AW[i + c * ld] : T(0));
+          if (KEEP) kept[KEEP ? c : 0] = av;
+          gi += wv * ys[c];
+          si -= av * ys[c];
+        }
+      if (in) {
+        g[i] = gi;
+        s[i] = si;
       }
-    g[i] = gi;
-    s[i] = si;
-    acc[NJT] += si * si;
+      acc[NJT] += si * si;   // 0 past the end (rv and the rows are 0 there)
 #pragma unroll
-    for (int c = 0; c < NJT; ++c)
-      if (c < nj) acc[c] += (KEEP ? aw[KEEP ? c : 0] : AW[i + c * ld]) * si;
+      for (int c = 0; c < NJT; ++c)
+        if (c < nj)
+          acc[c] += (PRE ? ar[q][PRE ? c : 0]
+                         : KEEP ? kept[KEEP ? c : 0] : (in ? AW[i + c * ld] : T(0))) * si;
+    }
+    base += (int64_t)gridDim.x * CH;
+    if (base - threadIdx.x >= n) break;
+    load(base);
   }
-  write_partials_t<NJT + 1, B>(acc, part2, blockIdx.x, gridDim.x);
+  write_partials_t<NJT + 1, START_BS>(acc, part2, blockIdx.x, gridDim.x);
 }
 
 // Reduce the step's partials (s^T s, (AU)^T s); record s^T s for the next step, count

@@ -483,8 +483,10 @@ __global__ __launch_bounds__(BS) void k_small_chol_inv(const double* __restrict_
 }
 
 // C = alpha op(A) op(B) + beta D (all column-major; D may be NULL).  op(A) is M x K,
-// op(B) is K x N.  64 x 64 output tiles, 256 threads with 4 x 4 outputs each.
-__global__ __launch_bounds__(BS) void k_gemm(int M, int N, int K, double alpha,
+// op(B) is K x N.  64 x 64 output tiles, 256 threads with 4 x 4 outputs each.  With
+// gridDim.z > 1 the K range is split in chunks of kc: block z sums its chunk into the
+// M x N slice C + z ldc N (the caller passes alpha 1, beta 0 and sums the slices).
+__global__ __launch_bounds__(BS) void k_gemm(int M, int N, int K, int kc, double alpha,
                                              const double* __restrict__ A, int64_t lda, int ta,
                                              const double* __restrict__ B, int64_t ldb, int tb,
                                              double beta, const double* __restrict__ D,
@@ -492,20 +494,22 @@ __global__ __launch_bounds__(BS) void k_gemm(int M, int N, int K, double alpha,
   __shared__ double As[16][64 + 1];
   __shared__ double Bs[16][64 + 1];
   const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+  C += (int64_t)blockIdx.z * ldc * N;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     // stage op(A)[m0:m0+64, k0:k0+16] and op(B)[k0:k0+16, n0:n0+64]
     for (int e = threadIdx.x; e < 16 * 64; e += BS) {
       const int kk = e / 64, r = e % 64;
       const int k = k0 + kk, mi = m0 + r, ni = n0 + r;
       double a = 0.0, b = 0.0;
-      if (k < K && mi < M) a = ta ? A[k + (int64_t)mi * lda] : A[mi + (int64_t)k * lda];
-      if (k < K && ni < N) b = tb ? B[ni + (int64_t)k * ldb] : B[k + (int64_t)ni * ldb];
+      if (k < ke && mi < M) a = ta ? A[k + (int64_t)mi * lda] : A[mi + (int64_t)k * lda];
+      if (k < ke && ni < N) b = tb ? B[ni + (int64_t)k * ldb] : B[k + (int64_t)ni * ldb];
       As[kk][r] = a;
       Bs[kk][r] = b;
     }
@@ -535,6 +539,21 @@ __global__ __launch_bounds__(BS) void k_gemm(int M, int N, int K, double alpha,
         C[mi + (int64_t)ni * ldc] = v;
       }
     }
+}
+
+// C = alpha sum_z P[z] + beta D over ks slices P[z] = P + z M N (leading dimension M),
+// summed in slice order.
+__global__ void k_gemm_sum(int M, int N, int ks, const double* __restrict__ P, double alpha,
+                           double beta, const double* __restrict__ D, int64_t ldd,
+                           double* __restrict__ C, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= (int64_t)M * N) return;
+  const int i = (int)(e % M), j = (int)(e / M);
+  double s = 0.0;
+  for (int z = 0; z < ks; ++z) s += P[(int64_t)z * M * N + e];
+  double v = alpha * s;
+  if (D) v += beta * D[i + (int64_t)j * ldd];
+  C[i + (int64_t)j * ldc] = v;
 }
 
 // Scatter one block row of the inverse Cholesky factor: rows k0..k0+nb of Linv get
@@ -696,15 +715,32 @@ __global__ void k_border_fill(const double* __restrict__ vals, int k, double* Gs
 
 void launch_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, bool ta,
                  const double* B, int64_t ldb, bool tb, double beta, const double* D, int64_t ldd,
-                 double* C, int64_t ldc, hipStream_t st) {
+                 double* C, int64_t ldc, hipStream_t st, double* part, size_t part_elems) {
   if (M <= 0 || N <= 0) return;
-  ROM_LAUNCH(k_gemm, dim3(ceil_div(M, 64), ceil_div(N, 64)), dim3(BS), 0, st, M, N, K, alpha,
-             A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, beta, D, ldd, C, ldc);
+  const int tiles = ceil_div(M, 64) * ceil_div(N, 64);
+  // split K when the output has few tiles and K is long: chunks of >= 64, ~128 blocks
+  int ks = 1;
+  if (part && tiles < 64 && K >= 128) {
+    ks = std::min(ceil_div(K, 64), std::max(1, 128 / tiles));
+    ks = (int)std::min<int64_t>(ks, (int64_t)(part_elems / ((size_t)M * N)));
+  }
+  if (ks <= 1) {
+    ROM_LAUNCH(k_gemm, dim3(ceil_div(M, 64), ceil_div(N, 64)), dim3(BS), 0, st, M, N, K, K,
+               alpha, A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, beta, D, ldd, C, ldc);
+    return;
+  }
+  const int kc = (ceil_div(K, ks) + 15) / 16 * 16;
+  ks = ceil_div(K, kc);
+  ROM_LAUNCH(k_gemm, dim3(ceil_div(M, 64), ceil_div(N, 64), ks), dim3(BS), 0, st, M, N, K, kc,
+             1.0, A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, 0.0, (const double*)nullptr,
+             (int64_t)0, part, (int64_t)M);
+  ROM_LAUNCH(k_gemm_sum, dim3(ceil_div((int64_t)M * N, BS)), dim3(BS), 0, st, M, N, ks,
+             (const double*)part, alpha, beta, D, ldd, C, ldc);
 }
 
 void launch_linv_rebuild(const double* G, int64_t ldg, int m, double* Lc, double* Lr,
                          double* work, int* status, hipStream_t st) {
-  // work: nb*nb (S, Linv22, Ginv22) + 3 * nb * m doubles
+  // work: 3 nb^2 (S, Linv22, Ginv22) + 3 nb m + the K-split slices (linv_rebuild_work)
   constexpr int NB = 64;
   double* S = work;
   double* L22 = S + NB * NB;
@@ -712,6 +748,8 @@ void launch_linv_rebuild(const double* G, int64_t ldg, int m, double* Lc, double
   double* T1 = G22i + NB * NB;
   double* T2 = T1 + (int64_t)NB * m;
   double* T3 = T2 + (int64_t)NB * m;
+  double* SK = T3 + (int64_t)NB * m;
+  const size_t sk = (size_t)GEMM_KSPLIT * NB * std::max(m, NB);
   for (int k0 = 0; k0 < m; k0 += NB) {
     const int nb = std::min(NB, m - k0);
     if (k0 == 0) {
@@ -719,16 +757,16 @@ void launch_linv_rebuild(const double* G, int64_t ldg, int m, double* Lc, double
     } else {
       // L21 = G21 Linv11^T  (nb x k0); Linv11^T is Lr in column-major form
       launch_gemm(nb, k0, k0, 1.0, G + k0, ldg, false, Lr, ldg, false, 0.0, nullptr, 0,
-                  T1, nb, st);
+                  T1, nb, st, SK, sk);
       // S = G22 - L21 L21^T
       launch_gemm(nb, nb, k0, -1.0, T1, nb, false, T1, nb, true, 1.0, G + k0 + k0 * ldg, ldg,
-                  S, nb, st);
+                  S, nb, st, SK, sk);
     }
     launch_small_chol_inv(S, nb, L22, G22i, status, st);
     if (k0 > 0) {
       // M = L21 Linv11 (nb x k0), Linv21 = -Linv22 M
       launch_gemm(nb, k0, k0, 1.0, T1, nb, false, Lc, ldg, false, 0.0, nullptr, 0, T2, nb,
-                  st);
+                  st, SK, sk);
       launch_gemm(nb, k0, nb, -1.0, L22, nb, false, T2, nb, false, 0.0, nullptr, 0, T3, nb, st);
     }
     const int64_t tot = (int64_t)nb * (k0 + nb);

@@ -161,14 +161,21 @@ void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double*
                         hipStream_t st, double* info = nullptr);
 // Rebuild Linv (both layouts) from the m x m SPD matrix G in 64-column blocks: per block
 // L21 = G21 Linv11^T, S = G22 - L21 L21^T, Linv22 = chol(S)^{-1},
-// Linv21 = -Linv22 (L21 Linv11).  work: >= linv_rebuild_work(m) doubles.
-inline size_t linv_rebuild_work(int m) { return 3 * 64 * 64 + 3 * 64 * (size_t)m; }
+// Linv21 = -Linv22 (L21 Linv11).  work: >= linv_rebuild_work(m) doubles (the last part
+// holds the K-split slices of its products).
+constexpr int GEMM_KSPLIT = 16;
+inline size_t linv_rebuild_work(int m) {
+  return 3 * 64 * 64 + 3 * 64 * (size_t)m + (size_t)GEMM_KSPLIT * 64 * (size_t)(m > 64 ? m : 64);
+}
 void launch_linv_rebuild(const double* G, int64_t ldg, int m, double* Lc, double* Lr,
                          double* work, int* status, hipStream_t st);
-// C = alpha op(A) op(B) + beta D, column-major, op(A) M x K, op(B) K x N.
+// C = alpha op(A) op(B) + beta D, column-major, op(A) M x K, op(B) K x N.  part
+// (part_elems doubles, may be NULL): room for K-split slices of M x N; with it an output of
+// few tiles and a long K is summed over K chunks in parallel, then the slices in order.
 void launch_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, bool ta,
                  const double* B, int64_t ldb, bool tb, double beta, const double* D, int64_t ldd,
-                 double* C, int64_t ldc, hipStream_t st);
+                 double* C, int64_t ldc, hipStream_t st, double* part = nullptr,
+                 size_t part_elems = 0);
 // c = Linv^T (Linv t), for m x m Linv.
 void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, const double* t,
                        double* u, double* c, double* partials, hipStream_t st);

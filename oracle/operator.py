@@ -115,6 +115,32 @@ def mu_field(dim: int, N, mu0: float, centers, radii, amps) -> np.ndarray:
     return mu
 
 
+def mu_gradient(dim: int, N, centers, radii, amps) -> np.ndarray:
+    """d mu / d p_k at every unknown for the bump parameters, per bump b in the order
+    (a_b, r_b, c_b[0], .., c_b[dim-1]): rows b (dim + 2) + (0, 1, 2 + d).
+
+    With t = |x - c| / r and psi(t) = (1-t)^4 (4t+1), psi'(t) = -20 t (1-t)^3 (zero for
+    t >= 1), so
+      d mu / d a = psi(t),
+      d mu / d r = a psi'(t) (-t / r)            = 20 a t^2 (1-t)^3 / r,
+      d mu / d c_d = a psi'(t) (-(x_d - c_d) / (r |x - c|)) = 20 a (1-t)^3 (x_d - c_d) / r^2.
+    (the Jacobian columns of eq. (newjac) take Delta_k = diag of these)."""
+    X = node_coords(dim, N)
+    centers = np.asarray(centers, dtype=np.float64)
+    out = []
+    for c, r, a in zip(centers, np.asarray(radii, dtype=np.float64),
+                       np.asarray(amps, dtype=np.float64)):
+        diff = X - c[None, :]
+        t = np.sqrt((diff ** 2).sum(axis=1)) / r
+        inside = t < 1.0
+        u3 = np.where(inside, (1.0 - t) ** 3, 0.0)
+        out.append(wendland(t))
+        out.append(20.0 * a * t * t * u3 / r)
+        for d in range(dim):
+            out.append(20.0 * a * u3 * diff[:, d] / (r * r))
+    return np.array(out).reshape(-1, X.shape[0])
+
+
 def assemble_A(Astar: sp.csr_matrix, mu: np.ndarray) -> sp.csr_matrix:
     """A(p) = A_* + diag(mu(p)) (eq. (sum))."""
     return (Astar + sp.diags(mu)).tocsr()

@@ -128,6 +128,30 @@ def measure_forms(prob, pts, wl, steps: int):
     return out
 
 
+def measure_jacobian(prob, pts, wl, plain_value: float, reps: int = 5):
+    """The reduced Jacobian (eq. (newjac) on the basis) at the last point: one sequence
+    (untimed) builds the basis, then rom_reduced_jacobian is timed; the full-order
+    Jacobian by the adjoint approach would need n_src + n_det solves at that point."""
+    import torch
+    res = prob.solve(pts, wl.tol, wl.trunc, keep_X=False)
+    J = prob.reduced_jacobian(res, pts[-1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        J = prob.reduced_jacobian(res, pts[-1])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    out = {"ms": ms, "params": int(J.shape[0]), "shape": [int(J.shape[1]), int(J.shape[2])],
+           "basis_m": res.m, "full_order_estimate_ms": 1e3 * prob.n_rhs / plain_value,
+           "note": "per call: A_r(p), its inverse Cholesky factor, the lifted states and "
+                   "co-states V A_r^{-1} [B_r, C_r], one weighted product per parameter; "
+                   "the full-order estimate is n_src + n_det solves at the plain rate"}
+    res.close()
+    log(f"reduced Jacobian: {ms:.2f} ms for {out['params']} parameters "
+        f"({out['shape'][0]}x{out['shape'][1]} each, m={out['basis_m']})")
+    return out
+
+
 def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_points: int,
                          plain_value: float, log_every=100):
     """The learned-seed form: the network is trained on the method's own solutions at
@@ -239,6 +263,8 @@ def main():
     ap.add_argument("--graph", type=int, default=0, help="replay CG steps from captured HIP graphs")
     ap.add_argument("--forms", type=int, default=1,
                     help="also time the mixed / grouped forms on the same problem (0/1)")
+    ap.add_argument("--jacobian", type=int, default=1,
+                    help="time the reduced Jacobian at the last point (0/1)")
     ap.add_argument("--suite", type=int, default=0,
                     help="also time the uneven-grid workload (48^3, 64^3, 96^3 sequences)")
     ap.add_argument("--seed-steps", type=int, default=0,
@@ -369,6 +395,7 @@ def main():
     spmm = spmm_bandwidth(prob, pts[-1], 64)
     log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s)")
 
+    jac = measure_jacobian(prob, pts, wl, value) if args.jacobian else None
     forms = measure_forms(prob, pts, wl, args.steps) if args.forms else None
     if forms:
         for f in forms.values():
@@ -406,6 +433,7 @@ def main():
         "roofline": roof,
         "spmm": spmm,
         "forms": forms,
+        "reduced_jacobian": jac,
         "learned_seed": learned,
         "uneven_grids": suite,
         "cpu_baseline": cpu,

@@ -248,6 +248,20 @@ ROM_API rom_status rom_reduced_transfer(const rom_basis* V, const rom_mu* p, dou
                                 double* Cr, double* Er, void* scratch, size_t scratch_bytes,
                                 void* stream);
 
+/* Reduced Jacobian (eq. (newjac) with A~ and Delta_k replaced by their projections on V,
+ * the derivative the interpolation theorem of Sec. 4 matches at the sample points):
+ *   J_k = -C_r^T A_r(p)^{-1} (V^T diag(d mu / d p_k) V) A_r(p)^{-1} B_r
+ * for every parameter of the bumps of p, per bump b in the order (amplitude a_b, radius
+ * r_b, centre c_b[0] .. c_b[dim-1]): k = b (dim + 2) + j.  J: device, nb (dim + 2) blocks
+ * of n_det x n_src (column-major, block k at J + k n_det n_src).  Computed as
+ * -Z^T diag(d mu / d p_k) U with U = V A_r^{-1} B_r, Z = V A_r^{-1} C_r (the products in
+ * a different order; each weighted product only reads the rows of one bump's support).
+ * scratch: device, >= rom_reduced_jacobian_bytes.  Synchronises the stream on return
+ * (it reports ROM_ENOTSPD if A_r(p) is not positive definite). */
+ROM_API rom_status rom_reduced_jacobian_bytes(const rom_basis* V, size_t* bytes);
+ROM_API rom_status rom_reduced_jacobian(const rom_basis* V, const rom_mu* p, double* J, void* scratch,
+                                        size_t scratch_bytes, void* stream);
+
 /* Basis queries: N, m, and a device copy of V (N x m, column-major, ld = N). */
 ROM_API rom_status rom_basis_dims(const rom_basis* V, int64_t* N, int* m);
 ROM_API rom_status rom_basis_copy(const rom_basis* V, double* dst, void* stream);

@@ -61,6 +61,10 @@ void launch_assemble(const rom_grid& g, double D_const, const double* D, double*
 // mu_i = mu0 + sum of bumps; diag_i = diag_star + mu_i (if diag_i); dmu = mu_i - mu0.
 void launch_mu_eval(const Stencil& S, const Bumps& bumps, const double* diag_star,
                     double* diag_i, double* dmu, hipStream_t st);
+// w[j ld + i] = -d mu(x_i) / d p_j for the dim + 2 parameters of bump b (amplitude,
+// radius, centre coordinates), i < n.
+void launch_mu_grad(const Stencil& S, const Bumps& bumps, int b, double* w, int64_t ld,
+                    hipStream_t st);
 
 // y = A x with A = stencil(S) + diag (diag holds the full diagonal).
 void launch_spmv(const Stencil& S, const double* diag, const double* x, double* y,

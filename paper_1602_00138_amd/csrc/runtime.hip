@@ -1846,6 +1846,115 @@ rom_status rom_reduced_bytes(const rom_basis* V, size_t* bytes) {
   }
 }
 
+namespace rom {
+namespace {
+
+// Scratch of rom_reduced_jacobian (the same carving for the size query and the call).
+struct JacLayout {
+  double *dmu, *part, *Ar, *Lc, *Lr, *lwork, *Br, *Cr, *T, *X, *Y, *U, *Z, *wk;
+  int* status;
+  int64_t ldr;
+  size_t bytes;
+};
+
+JacLayout jac_layout(const rom_basis* V, int dim, void* base) {
+  Arena a(base);
+  JacLayout L;
+  const int m = std::max(V->m, 1);
+  const int64_t ld = V->ld;
+  const int ns = std::max(V->n_src, 1), nd = std::max(V->n_det, 1);
+  L.ldr = round_up(m, 2);
+  L.dmu = a.take<double>(ld);
+  L.part = a.take<double>(std::max<size_t>(
+      {gram_partials(m, m, V->n, true), gram_partials(nd, ns, V->n, false), 1}));
+  L.Ar = a.take<double>(L.ldr * m);
+  L.Lc = a.take<double>(L.ldr * m);
+  L.Lr = a.take<double>(L.ldr * m);
+  L.lwork = a.take<double>(linv_rebuild_work(m));
+  L.Br = a.take<double>(L.ldr * ns);
+  L.Cr = a.take<double>(L.ldr * nd);
+  L.T = a.take<double>(L.ldr * std::max(ns, nd));
+  L.X = a.take<double>(L.ldr * ns);
+  L.Y = a.take<double>(L.ldr * nd);
+  L.U = a.take<double>(ld * ns);
+  L.Z = a.take<double>(ld * nd);
+  L.wk = a.take<double>(ld * (dim + 2));
+  L.status = a.take<int>(4);
+  L.bytes = a.off + ALIGN;
+  return L;
+}
+
+}  // namespace
+}  // namespace rom
+
+rom_status rom_reduced_jacobian_bytes(const rom_basis* V, size_t* bytes) {
+  try {
+    if (!V || !bytes) throw Error(ROM_EINVAL, "null argument");
+    *bytes = rom::jac_layout(V, V->op->grid.dim, nullptr).bytes;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_reduced_jacobian(const rom_basis* V, const rom_mu* p, double* J, void* scratch,
+                                size_t scratch_bytes, void* stream) {
+  try {
+    if (!V || !J) throw Error(ROM_EINVAL, "null argument");
+    const int dim = V->op->grid.dim;
+    rom::check_mu(p, dim);
+    const int m = V->m, ns = V->n_src, nd = V->n_det;
+    if (m == 0) throw Error(ROM_EINVAL, "empty basis");
+    const rom::JacLayout L = rom::jac_layout(V, dim, scratch);
+    if (!scratch || scratch_bytes < L.bytes) throw Error(ROM_ECAPACITY, "scratch too small");
+    if (ns == 0 || nd == 0 || p->nb == 0) return ROM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const rom::Bumps bm = rom::make_bumps(*p, dim);
+    const int64_t ld = V->ld, ldr = L.ldr;
+    // A_r = V^T A_* V + mu0 I + V^T diag(mu - mu0) V and its inverse Cholesky factor
+    rom::launch_mu_eval(V->op->S, bm, V->op->diag_star, nullptr, L.dmu, st);
+    rom::launch_gram(V->Q, ld, m, V->Q, ld, m, V->n, L.dmu, true, V->Gstar, V->ldg, p->mu0, L.Ar,
+                     ldr, L.part, st);
+    ROM_HIP(hipMemsetAsync(L.status, 0, sizeof(int), st));
+    rom::launch_linv_rebuild(L.Ar, ldr, m, L.Lc, L.Lr, L.lwork, L.status, st);
+    // B_r = V^T B~, C_r = V^T C~ (row gathers); X = A_r^{-1} B_r, Y = A_r^{-1} C_r
+    rom::launch_gather_rows(V->Q, ld, m, V->idx_dev, V->scale_dev, ns, L.Br, ldr, st);
+    rom::launch_gather_rows(V->Q, ld, m, V->idx_dev + ns, V->scale_dev + ns, nd, L.Cr, ldr, st);
+    auto solve = [&](const double* R, int k, double* out) {
+      rom::launch_gemm(m, k, m, 1.0, L.Lc, ldr, false, R, ldr, false, 0.0, nullptr, 0, L.T, ldr, st);
+      rom::launch_gemm(m, k, m, 1.0, L.Lc, ldr, true, L.T, ldr, false, 0.0, nullptr, 0, out, ldr,
+                       st);
+    };
+    solve(L.Br, ns, L.X);
+    solve(L.Cr, nd, L.Y);
+    // lifted states U = V X (N x n_src) and co-states Z = V Y (N x n_det), 16 per pass
+    for (int c = 0; c < ns; c += 16)
+      rom::launch_gemvn_multi(V->Q, ld, V->n, m, L.X + c * ldr, ldr, std::min(16, ns - c), 0.0,
+                              nullptr, 0, 1.0, L.U + c * ld, ld, st);
+    for (int c = 0; c < nd; c += 16)
+      rom::launch_gemvn_multi(V->Q, ld, V->n, m, L.Y + c * ldr, ldr, std::min(16, nd - c), 0.0,
+                              nullptr, 0, 1.0, L.Z + c * ld, ld, st);
+    // J_k = -Z^T diag(d mu / d p_k) U = -C_r^T A_r^{-1} (V^T diag(d mu / d p_k) V) A_r^{-1} B_r,
+    // over the rows of bump b's support only (the weights vanish elsewhere)
+    const int npb = dim + 2;
+    for (int b = 0; b < p->nb; ++b) {
+      rom::launch_mu_grad(V->op->S, bm, b, L.wk, ld, st);
+      for (int j = 0; j < npb; ++j) {
+        const int64_t k = (int64_t)b * npb + j;
+        rom::launch_gram(L.Z, ld, nd, L.U, ld, ns, V->n, L.wk + j * ld, false, nullptr, 0, 0.0,
+                         J + k * nd * ns, nd, L.part, st);
+      }
+    }
+    int status = 0;
+    ROM_HIP(hipMemcpyAsync(&status, L.status, sizeof(int), hipMemcpyDeviceToHost, st));
+    ROM_HIP(hipStreamSynchronize(st));
+    if (status) throw Error(ROM_ENOTSPD, "reduced matrix A_r(p) not positive definite");
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
 rom_status rom_reduced_transfer(const rom_basis* V, const rom_mu* p, double* Ar, double* Br,
                                 double* Cr, double* Er, void* scratch, size_t scratch_bytes,
                                 void* stream) {

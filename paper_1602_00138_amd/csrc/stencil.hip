@@ -83,6 +83,38 @@ __global__ void k_mu_eval(Stencil S, Bumps B, const double* __restrict__ diag_st
   if (diag_i) diag_i[i] = diag_star[i] + B.mu0 + m;
 }
 
+// w[j ld + i] = -d mu(x_i) / d p for the parameters of bump b in the order (a, r, c_0 ..
+// c_{dim-1}), negated (the Jacobian column is -Z^T diag(d mu / d p) U).  With
+// t = |x - c| / r and psi'(t) = -20 t (1-t)^3: d/da = psi(t), d/dr = 20 a t^2 (1-t)^3 / r,
+// d/dc_d = 20 a (1-t)^3 (x_d - c_d) / r^2, all zero for t >= 1.
+__global__ void k_mu_grad(Stencil S, Bumps B, int b, double* __restrict__ w, int64_t ld) {
+  int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= S.n) return;
+  const int ix = (int)(i % S.nx);
+  const int64_t q = i / S.nx;
+  const int iy = (int)(q % S.ny);
+  const int iz = (int)(q / S.ny);
+  const double x[3] = {(ix + 1.0) / (S.nx + 1), (iy + 1.0) / (S.ny + 1),
+                       (iz + 1.0) / (S.nz + 1)};
+  const double* pb = B.p + b * (S.dim + 2);
+  const double r = pb[S.dim], a = pb[S.dim + 1];
+  double d2 = 0.0;
+  for (int k = 0; k < S.dim; ++k) {
+    const double e = x[k] - pb[k];
+    d2 += e * e;
+  }
+  const double t = sqrt(d2) / r;
+  double u3 = 0.0, psi = 0.0;
+  if (t < 1.0) {
+    const double u = 1.0 - t;
+    u3 = u * u * u;
+    psi = u3 * u * (4.0 * t + 1.0);
+  }
+  w[i] = -psi;
+  w[i + ld] = -20.0 * a * t * t * u3 / r;
+  for (int k = 0; k < S.dim; ++k) w[i + (2 + k) * ld] = -20.0 * a * u3 * (x[k] - pb[k]) / (r * r);
+}
+
 template <typename T>
 struct Faces {
   const T *fx, *fy, *fz;
@@ -220,6 +252,12 @@ void launch_mu_eval(const Stencil& S, const Bumps& bumps, const double* diag_sta
     else                                                                                       \
       ROM_LAUNCH((k_stencil<T, false, MODE>), grid, dim3(BS), 0, st, S, __VA_ARGS__);          \
   } while (0)
+
+void launch_mu_grad(const Stencil& S, const Bumps& bumps, int b, double* w, int64_t ld,
+                    hipStream_t st) {
+  ROM_LAUNCH(k_mu_grad, dim3(ceil_div(S.n, BS)), dim3(BS), 0, st, S, bumps, b, w, ld);
+  ROM_CHECK_LAUNCH();
+}
 
 void launch_spmv(const Stencil& S, const double* diag, const double* x, double* y,
                  hipStream_t st) {

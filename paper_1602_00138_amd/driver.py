@@ -100,6 +100,19 @@ class Problem:
         # read row-major is (n_src x m) = B_r^T
         return Ar.T.contiguous(), Br.T.contiguous(), Cr.T.contiguous(), Er.T.contiguous()
 
+    def reduced_jacobian(self, res: SequenceResult, p: R.MuParams) -> torch.Tensor:
+        """d Psi_r / d p_k for every bump parameter of p (per bump: amplitude, radius,
+        centre coordinates) as a float64 tensor (nparams, n_det, n_src)."""
+        dev = self.device
+        ns, nd = self.src_idx.size, self.det_idx.size
+        npar = int(np.asarray(p.radii).size) * (self.dim + 2)
+        J = torch.empty((npar, ns, nd), dtype=torch.float64, device=dev)
+        scratch = torch.empty(R.rom_reduced_jacobian_bytes(res.basis), dtype=torch.uint8,
+                              device=dev)
+        R.rom_reduced_jacobian(res.basis, p, J, scratch)
+        # each block is n_det x n_src column-major = (n_src, n_det) row-major
+        return J.transpose(1, 2).contiguous()
+
     def apply(self, p: R.MuParams, X: torch.Tensor) -> torch.Tensor:
         """Y = A(p) X for X given as (k, N) rows (each row a vector)."""
         X = X.contiguous()

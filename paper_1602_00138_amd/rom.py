@@ -36,7 +36,8 @@ ROM_NK = 8
 KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "outer", "other"]
 
 EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator", "rom_sequence_bytes",
-            "rom_solve_sequence", "rom_solve_sequences", "rom_reduced_bytes", "rom_reduced_transfer", "rom_basis_dims",
+            "rom_solve_sequence", "rom_solve_sequences", "rom_reduced_bytes", "rom_reduced_transfer",
+            "rom_reduced_jacobian_bytes", "rom_reduced_jacobian", "rom_basis_dims",
             "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error",
             "rom_seednet_bytes", "rom_seednet_create", "rom_seednet_forward",
             "rom_seednet_gradients", "rom_seednet_train_step", "rom_seednet_params",
@@ -110,6 +111,8 @@ def _load():
         "rom_solve_sequences": (C.c_int, [P(rom_sequence_job), C.c_int]),
         "rom_reduced_bytes": (C.c_int, [vp, P(sz)]),
         "rom_reduced_transfer": (C.c_int, [vp, P(rom_mu), vp, vp, vp, vp, vp, sz, vp]),
+        "rom_reduced_jacobian_bytes": (C.c_int, [vp, P(sz)]),
+        "rom_reduced_jacobian": (C.c_int, [vp, P(rom_mu), vp, vp, sz, vp]),
         "rom_basis_dims": (C.c_int, [vp, P(C.c_int64), P(C.c_int)]),
         "rom_basis_copy": (C.c_int, [vp, vp, vp]),
         "rom_operator_destroy": (None, [vp]),
@@ -324,6 +327,18 @@ def rom_reduced_transfer(basis: int, p: MuParams, Ar, Br, Cr, Er, scratch, strea
     _check(_lib.rom_reduced_transfer(basis, C.byref(mu), _ptr(Ar), _ptr(Br), _ptr(Cr), _ptr(Er),
                                      _ptr(scratch), scratch.numel() * scratch.element_size(),
                                      _stream(stream)))
+
+
+def rom_reduced_jacobian_bytes(basis: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.rom_reduced_jacobian_bytes(basis, C.byref(out)))
+    return int(out.value)
+
+
+def rom_reduced_jacobian(basis: int, p: MuParams, J, scratch, stream=None) -> None:
+    mu = p.c_struct()
+    _check(_lib.rom_reduced_jacobian(basis, C.byref(mu), _ptr(J), _ptr(scratch),
+                                     scratch.numel() * scratch.element_size(), _stream(stream)))
 
 
 def rom_basis_dims(basis: int):

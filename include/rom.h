@@ -262,6 +262,26 @@ ROM_API rom_status rom_reduced_jacobian_bytes(const rom_basis* V, size_t* bytes)
 ROM_API rom_status rom_reduced_jacobian(const rom_basis* V, const rom_mu* p, double* J, void* scratch,
                                         size_t scratch_bytes, void* stream);
 
+/* The k smallest eigenpairs of A(p) (the U_0 of Algorithm 2, Sec. 4.2.2, which the paper
+ * computes offline), by Chebyshev-filtered subspace iteration on a block of kx >= k
+ * columns (the extra ones are guards):
+ *   X0: device N x kx (ld N), the starting block (e.g. smooth modes of the background);
+ *   each sweep: Rayleigh-Ritz on the orthonormal block (a one-workgroup Jacobi
+ *   eigensolver), then a degree-24 Chebyshev filter damping [largest Ritz value,
+ *   Gershgorin bound b], then Cholesky QR twice;
+ *   stops when every ||A u_i - lambda_i u_i|| <= tol * b (i < k), or after maxit sweeps.
+ * U: device N x k (ld N), orthonormal; lambda: host, k values ascending; *sweeps: host
+ * (may be NULL).  1 <= k <= kx <= 32; the filter's lower edge is the largest Ritz value of
+ * the block, so column k converges at the rate of lambda_k / lambda_{kx+1}: give kx - k >= 2
+ * guard columns (k == kx is accepted but its last column converges slowly).
+ * scratch: device, >= rom_lowest_modes_bytes.
+ * Synchronises the stream (it decides on the host after every sweep). */
+ROM_API rom_status rom_lowest_modes_bytes(const rom_operator* op, int kx, size_t* bytes);
+ROM_API rom_status rom_lowest_modes(const rom_operator* op, const rom_mu* p, int k,
+                                    const double* X0, int kx, double tol, int maxit, double* U,
+                                    double* lambda, int* sweeps, void* scratch,
+                                    size_t scratch_bytes, void* stream);
+
 /* Basis queries: N, m, and a device copy of V (N x m, column-major, ld = N). */
 ROM_API rom_status rom_basis_dims(const rom_basis* V, int64_t* N, int* m);
 ROM_API rom_status rom_basis_copy(const rom_basis* V, double* dst, void* stream);

@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librom.so")
-SOURCES = ["stencil.hip", "dense.hip", "gram.hip", "dcg.hip", "runtime.hip", "seednet.hip",
-           "seedrt.hip"]
+SOURCES = ["stencil.hip", "dense.hip", "gram.hip", "dcg.hip", "modes.hip", "runtime.hip",
+           "seednet.hip", "seedrt.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

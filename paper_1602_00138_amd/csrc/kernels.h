@@ -154,6 +154,23 @@ void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t l
                  int64_t rows, const double* w, bool sym, const double* base, int64_t ldb,
                  double shift, double* C, int64_t ldc, double* partials, hipStream_t st);
 
+// ---- lowest eigenpairs (U_0) ----------------------------------------------------------
+// Eigenpairs of the symmetric m x m H (ld), m <= 32, by parallel-order Jacobi in one
+// workgroup: lam ascending, Z (m x m, column-major) the matching unit eigenvectors.
+void launch_sym_eig(const double* H, int64_t ld, int m, double* lam, double* Z, hipStream_t st);
+// out[:, v] = a AY[:, v] + b Y[:, v] + c Y2[:, v] (Y2 may be NULL; out may alias Y or Y2).
+void launch_comb3(int64_t n, int k, double a, const double* AY, double b, const double* Y,
+                  double c, const double* Y2, int64_t ld, double* out, hipStream_t st);
+// R[:, v] = AY[:, v] - lam[v] Y[:, v].
+void launch_ritz_resid(int64_t n, int k, const double* AY, const double* Y, const double* lam,
+                       int64_t ld, double* R, hipStream_t st);
+// out[0] = max_i (2 diag_i - a1_i), with a1 = A 1: the Gershgorin bound of an operator whose
+// off-diagonal entries are non-positive.  partials: >= 1024 doubles.
+void launch_gersh(int64_t n, const double* diag, const double* a1, double* partials, double* out,
+                  hipStream_t st);
+void launch_transpose_small(int m, const double* in, double* out, hipStream_t st);
+void launch_fill(int64_t n, double v, double* x, hipStream_t st);
+
 // ---- inverse Cholesky factor -------------------------------------------------------
 // Linv (lower, inverse of the Cholesky factor of G) kept in two layouts, Lc
 // (column-major, ld) and Lr (its transpose, column-major, ld).  Border step k: with

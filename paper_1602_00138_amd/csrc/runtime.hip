@@ -1955,6 +1955,171 @@ rom_status rom_reduced_jacobian(const rom_basis* V, const rom_mu* p, double* J, 
   }
 }
 
+namespace rom {
+namespace {
+
+constexpr int MODES_MAX = 32;   // block columns (guard columns included)
+constexpr int CHEB_DEGREE = 24; // filter degree per sweep
+
+struct ModesLayout {
+  double *diag, *dmu, *a1, *Y, *AY, *B1, *B2, *B3, *G, *Linv, *Ginv, *LT, *H, *Z, *lam, *res2,
+      *bmax, *part, *gpart;
+  int* status;
+  size_t bytes;
+};
+
+ModesLayout modes_layout(const rom_operator* op, int kb, void* base) {
+  Arena a(base);
+  ModesLayout L;
+  const int64_t n = op->n, ld = round_up(n, 64);
+  L.diag = a.take<double>(ld);
+  L.dmu = a.take<double>(ld);
+  L.a1 = a.take<double>(ld);
+  L.Y = a.take<double>(ld * kb);
+  L.AY = a.take<double>(ld * kb);
+  L.B1 = a.take<double>(ld * kb);
+  L.B2 = a.take<double>(ld * kb);
+  L.B3 = a.take<double>(ld * kb);
+  L.G = a.take<double>(kb * kb);
+  L.Linv = a.take<double>(kb * kb);
+  L.Ginv = a.take<double>(kb * kb);
+  L.LT = a.take<double>(kb * kb);
+  L.H = a.take<double>(kb * kb);
+  L.Z = a.take<double>(kb * kb);
+  L.lam = a.take<double>(kb);
+  L.res2 = a.take<double>(kb);
+  L.bmax = a.take<double>(1);
+  L.part = a.take<double>(std::max<size_t>(gram_partials(kb, kb, n, true), (size_t)256 * kb));
+  L.gpart = a.take<double>(1024);
+  L.status = a.take<int>(4);
+  L.bytes = a.off + ALIGN;
+  return L;
+}
+
+}  // namespace
+}  // namespace rom
+
+rom_status rom_lowest_modes_bytes(const rom_operator* op, int kx, size_t* bytes) {
+  try {
+    if (!op || !bytes) throw Error(ROM_EINVAL, "null argument");
+    if (kx < 1 || kx > rom::MODES_MAX) throw Error(ROM_EINVAL, "block size out of range");
+    *bytes = rom::modes_layout(op, kx, nullptr).bytes;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_lowest_modes(const rom_operator* op, const rom_mu* p, int k, const double* X0,
+                            int kx, double tol, int maxit, double* U, double* lambda,
+                            int* sweeps, void* scratch, size_t scratch_bytes, void* stream) {
+  try {
+    if (!op || !X0 || !U || !lambda) throw Error(ROM_EINVAL, "null argument");
+    rom::check_mu(p, op->grid.dim);
+    if (kx < 1 || kx > rom::MODES_MAX || k < 1 || k > kx)
+      throw Error(ROM_EINVAL, "need 1 <= k <= kx <= 32");
+    if (!(tol > 0.0) || maxit < 1) throw Error(ROM_EINVAL, "tol and maxit must be positive");
+    const rom::ModesLayout L = rom::modes_layout(op, kx, scratch);
+    if (!scratch || scratch_bytes < L.bytes) throw Error(ROM_ECAPACITY, "scratch too small");
+    hipStream_t st = (hipStream_t)stream;
+    const rom::Stencil& S = op->S;
+    const int64_t n = op->n, ld = rom::round_up(n, 64);
+    const int kb = kx;
+    // A(p) diagonal and the Gershgorin bound b of its spectrum
+    rom::launch_mu_eval(S, rom::make_bumps(*p, op->grid.dim), op->diag_star, L.diag, L.dmu, st);
+    rom::launch_fill(n, 1.0, L.B1, st);
+    rom::launch_spmv(S, L.diag, L.B1, L.a1, st);
+    rom::launch_gersh(n, L.diag, L.a1, L.gpart, L.bmax, st);
+    double b = 0.0;
+    ROM_HIP(hipMemcpyAsync(&b, L.bmax, sizeof(double), hipMemcpyDeviceToHost, st));
+    ROM_HIP(hipMemcpy2DAsync(L.Y, ld * sizeof(double), X0, n * sizeof(double), n * sizeof(double),
+                             kx, hipMemcpyDeviceToDevice, st));
+    ROM_HIP(hipStreamSynchronize(st));
+    double* Y = L.Y;
+    double* AY = L.AY;
+    double* F[3] = {L.B1, L.B2, L.B3};   // free blocks
+    // orthonormalise X (N x kb) into out: Cholesky QR twice
+    auto cholqr2 = [&](double* X, double* out) {
+      double* src = X;
+      for (int pass = 0; pass < 2; ++pass) {
+        rom::launch_gram(src, ld, kb, src, ld, kb, n, nullptr, true, nullptr, 0, 0.0, L.G, kb,
+                         L.part, st);
+        rom::launch_small_chol_inv(L.G, kb, L.Linv, L.Ginv, L.status, st);
+        rom::launch_transpose_small(kb, L.Linv, L.LT, st);   // R^{-1} = L^{-T}
+        double* dst = pass == 0 ? out : X;
+        rom::launch_gemvn_multi(src, ld, n, kb, L.LT, kb, std::min(16, kb), 0.0, nullptr, 0, 1.0,
+                                dst, ld, st);
+        if (kb > 16)
+          rom::launch_gemvn_multi(src, ld, n, kb, L.LT + 16 * kb, kb, kb - 16, 0.0, nullptr, 0, 1.0,
+                                  dst + 16 * ld, ld, st);
+        src = dst;
+      }
+      // the result is in X after the second pass; copy it to out
+      ROM_HIP(hipMemcpyAsync(out, X, sizeof(double) * ld * kb, hipMemcpyDeviceToDevice, st));
+    };
+    auto mult = [&](const double* X, const double* C, double* out) {   // out = X C (kb x kb)
+      rom::launch_gemvn_multi(X, ld, n, kb, C, kb, std::min(16, kb), 0.0, nullptr, 0, 1.0, out, ld,
+                              st);
+      if (kb > 16)
+        rom::launch_gemvn_multi(X, ld, n, kb, C + 16 * kb, kb, kb - 16, 0.0, nullptr, 0, 1.0,
+                                out + 16 * ld, ld, st);
+    };
+    ROM_HIP(hipMemsetAsync(L.status, 0, sizeof(int), st));
+    cholqr2(Y, F[0]);   // Y orthonormal (F[0] holds a copy)
+    std::vector<double> lam(kb), res2(kb);
+    int sw = 0;
+    for (;; ++sw) {
+      // Rayleigh-Ritz: H = Y^T A Y, H = Z diag(lam) Z^T, Y <- Y Z, AY <- AY Z
+      rom::launch_spmm(S, L.diag, Y, ld, kb, AY, st);
+      rom::launch_gram(Y, ld, kb, AY, ld, kb, n, nullptr, true, nullptr, 0, 0.0, L.H, kb, L.part,
+                       st);
+      rom::launch_sym_eig(L.H, kb, kb, L.lam, L.Z, st);
+      mult(Y, L.Z, F[0]);
+      mult(AY, L.Z, F[1]);
+      std::swap(Y, F[0]);
+      std::swap(AY, F[1]);
+      rom::launch_ritz_resid(n, k, AY, Y, L.lam, ld, F[2], st);
+      rom::launch_col_norms(n, k, F[2], ld, L.res2, L.part, st);
+      int status = 0;
+      ROM_HIP(hipMemcpyAsync(lam.data(), L.lam, sizeof(double) * kb, hipMemcpyDeviceToHost, st));
+      ROM_HIP(hipMemcpyAsync(res2.data(), L.res2, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+      ROM_HIP(hipMemcpyAsync(&status, L.status, sizeof(int), hipMemcpyDeviceToHost, st));
+      ROM_HIP(hipStreamSynchronize(st));
+      if (status) throw Error(ROM_ENOTSPD, "lowest modes: the block lost rank (Cholesky QR failed)");
+      double worst = 0.0;
+      for (int i = 0; i < k; ++i) worst = std::max(worst, std::sqrt(std::max(res2[i], 0.0)));
+      if (!(worst == worst)) throw Error(ROM_ENONFINITE, "lowest modes: non-finite residual");
+      if (worst <= tol * b || sw + 1 >= maxit) break;
+      // Chebyshev filter of degree CHEB_DEGREE damping [lam_max of the block, b]
+      const double lo = lam[kb - 1], e = 0.5 * (b - lo), c = 0.5 * (b + lo);
+      if (!(e > 0.0)) break;
+      double* prev = Y;        // T_0 block
+      double* cur = F[2];      // T_1 block = (A - c) Y / e
+      rom::launch_comb3(n, kb, 1.0 / e, AY, -c / e, Y, 0.0, nullptr, ld, cur, st);
+      for (int j = 2; j <= rom::CHEB_DEGREE; ++j) {
+        rom::launch_spmm(S, L.diag, cur, ld, kb, AY, st);
+        // next = 2 (A - c) cur / e - prev, written over prev
+        rom::launch_comb3(n, kb, 2.0 / e, AY, -2.0 * c / e, cur, -1.0, prev, ld, prev, st);
+        std::swap(prev, cur);
+      }
+      // the filtered block is cur; orthonormalise it into Y's buffer
+      if (cur != Y) {
+        cholqr2(cur, Y);
+      } else {
+        cholqr2(cur, F[0]);
+      }
+    }
+    ROM_HIP(hipMemcpy2DAsync(U, n * sizeof(double), Y, ld * sizeof(double), n * sizeof(double), k,
+                             hipMemcpyDeviceToDevice, st));
+    ROM_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < k; ++i) lambda[i] = lam[i];
+    if (sweeps) *sweeps = sw + 1;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
 rom_status rom_reduced_transfer(const rom_basis* V, const rom_mu* p, double* Ar, double* Br,
                                 double* Cr, double* Er, void* scratch, size_t scratch_bytes,
                                 void* stream) {

@@ -113,6 +113,18 @@ class Problem:
         # each block is n_det x n_src column-major = (n_src, n_det) row-major
         return J.transpose(1, 2).contiguous()
 
+    def lowest_modes(self, p: R.MuParams, k: int, X0: torch.Tensor, tol: float = 1e-8,
+                     maxit: int = 200):
+        """The k smallest eigenpairs of A(p) from the starting block X0 ((kx, N) rows, kx >= k
+        columns): returns (U as (k, N) rows, eigenvalues (k,), sweeps)."""
+        X0 = X0.to(dtype=torch.float64, device=self.device).contiguous()
+        kx = X0.shape[0]
+        U = torch.empty((k, self.n), dtype=torch.float64, device=self.device)
+        scratch = torch.empty(R.rom_lowest_modes_bytes(self.op, kx), dtype=torch.uint8,
+                              device=self.device)
+        lam, sweeps = R.rom_lowest_modes(self.op, p, k, X0, kx, tol, maxit, U, scratch)
+        return U, lam, sweeps
+
     def apply(self, p: R.MuParams, X: torch.Tensor) -> torch.Tensor:
         """Y = A(p) X for X given as (k, N) rows (each row a vector)."""
         X = X.contiguous()

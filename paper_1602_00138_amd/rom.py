@@ -37,7 +37,8 @@ KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "ou
 
 EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator", "rom_sequence_bytes",
             "rom_solve_sequence", "rom_solve_sequences", "rom_reduced_bytes", "rom_reduced_transfer",
-            "rom_reduced_jacobian_bytes", "rom_reduced_jacobian", "rom_basis_dims",
+            "rom_reduced_jacobian_bytes", "rom_reduced_jacobian", "rom_lowest_modes_bytes",
+            "rom_lowest_modes", "rom_basis_dims",
             "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error",
             "rom_seednet_bytes", "rom_seednet_create", "rom_seednet_forward",
             "rom_seednet_gradients", "rom_seednet_train_step", "rom_seednet_params",
@@ -113,6 +114,9 @@ def _load():
         "rom_reduced_transfer": (C.c_int, [vp, P(rom_mu), vp, vp, vp, vp, vp, sz, vp]),
         "rom_reduced_jacobian_bytes": (C.c_int, [vp, P(sz)]),
         "rom_reduced_jacobian": (C.c_int, [vp, P(rom_mu), vp, vp, sz, vp]),
+        "rom_lowest_modes_bytes": (C.c_int, [vp, C.c_int, P(sz)]),
+        "rom_lowest_modes": (C.c_int, [vp, P(rom_mu), C.c_int, vp, C.c_int, C.c_double, C.c_int,
+                                       vp, P(C.c_double), P(C.c_int), vp, sz, vp]),
         "rom_basis_dims": (C.c_int, [vp, P(C.c_int64), P(C.c_int)]),
         "rom_basis_copy": (C.c_int, [vp, vp, vp]),
         "rom_operator_destroy": (None, [vp]),
@@ -339,6 +343,24 @@ def rom_reduced_jacobian(basis: int, p: MuParams, J, scratch, stream=None) -> No
     mu = p.c_struct()
     _check(_lib.rom_reduced_jacobian(basis, C.byref(mu), _ptr(J), _ptr(scratch),
                                      scratch.numel() * scratch.element_size(), _stream(stream)))
+
+
+def rom_lowest_modes_bytes(op: int, kx: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.rom_lowest_modes_bytes(op, int(kx), C.byref(out)))
+    return int(out.value)
+
+
+def rom_lowest_modes(op: int, p: MuParams, k: int, X0, kx: int, tol: float, maxit: int, U,
+                     scratch, stream=None):
+    """Returns (lambda (k,), sweeps); U is filled on the device."""
+    mu = p.c_struct()
+    lam = (C.c_double * k)()
+    sweeps = C.c_int(0)
+    _check(_lib.rom_lowest_modes(op, C.byref(mu), int(k), _ptr(X0), int(kx), float(tol),
+                                 int(maxit), _ptr(U), lam, C.byref(sweeps), _ptr(scratch),
+                                 scratch.numel() * scratch.element_size(), _stream(stream)))
+    return np.array(lam[:], dtype=np.float64), int(sweeps.value)
 
 
 def rom_basis_dims(basis: int):

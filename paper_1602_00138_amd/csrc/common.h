@@ -83,6 +83,45 @@ struct Stencil {
   int64_t n;
 };
 
+// Walk one x-y position q of the FP64 operator through the z planes [z0, z1): calls
+// f(i, (A x)_i, x_i) per node i, with the z neighbours carried in registers (the lateral
+// ones come from the caches), so x is fetched from HBM about once.  diag holds A's
+// diagonal (A_* plus mu); the off-diagonal entries are minus the face coefficients.
+template <bool VAR, class F>
+__device__ __forceinline__ void stencil_walk(const Stencil& S, const double* __restrict__ diag,
+                                             const double* __restrict__ x, int q, int z0,
+                                             int z1, F&& f) {
+  const int nxy = S.nx * S.ny;
+  const int ix = q % S.nx, iy = q / S.nx;
+  const bool hl = ix > 0, hr = ix < S.nx - 1, hd = iy > 0, hu = iy < S.ny - 1;
+  int64_t i = (int64_t)z0 * nxy + q;
+  double xm = z0 > 0 ? x[i - nxy] : 0.0;
+  double fm = (VAR && z0 > 0) ? S.fz[i - nxy] : 0.0;
+  double xc = x[i];
+  for (int z = z0; z < z1; ++z, i += nxy) {
+    const double xp = z < S.nz - 1 ? x[i + nxy] : 0.0;
+    double v = diag[i] * xc;
+    if (!VAR) {
+      const double sx = (hl ? x[i - 1] : 0.0) + (hr ? x[i + 1] : 0.0);
+      const double sy = (hd ? x[i - S.nx] : 0.0) + (hu ? x[i + S.nx] : 0.0);
+      v -= S.cx * sx + S.cy * sy + S.cz * (xm + xp);
+    } else {
+      if (hl) v -= S.fx[i - 1] * x[i - 1];
+      if (hr) v -= S.fx[i] * x[i + 1];
+      if (hd) v -= S.fy[i - S.nx] * x[i - S.nx];
+      if (hu) v -= S.fy[i] * x[i + S.nx];
+      if (S.dim == 3) {
+        const double fp = S.fz[i];
+        v -= fm * xm + fp * xp;
+        fm = fp;
+      }
+    }
+    f(i, v, xc);
+    xm = xc;
+    xc = xp;
+  }
+}
+
 // One DPP move of a 32-bit or 64-bit value (lanes whose source is outside the pattern,
 // or whose row is masked off, receive 0).
 template <int CTRL, int ROW_MASK>

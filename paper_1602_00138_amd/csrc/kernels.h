@@ -69,6 +69,11 @@ void launch_mu_grad(const Stencil& S, const Bumps& bumps, int b, double* w, int6
 // y = A x with A = stencil(S) + diag (diag holds the full diagonal).
 void launch_spmv(const Stencil& S, const double* diag, const double* x, double* y,
                  hipStream_t st);
+// out[:, v] = a A X[:, v] + b X[:, v] + c prev[:, v] for v < k (prev may be NULL; out may
+// alias prev but not X): one fused step of a three-term recurrence.
+void launch_cheb_step(const Stencil& S, const double* diag, const double* X, int64_t ld, int k,
+                      double a, double b, double c, const double* prev, double* out,
+                      hipStream_t st);
 // Y[:, c] = A X[:, c] for c < k (contiguous, leading dimension ld).
 void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t ld, int k,
                  double* Y, hipStream_t st);
@@ -153,6 +158,49 @@ void launch_proj(const double* X, int64_t ldx, int a, const double* V, int64_t l
 void launch_gram(const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b,
                  int64_t rows, const double* w, bool sym, const double* base, int64_t ldb,
                  double shift, double* C, int64_t ldc, double* partials, hipStream_t st);
+
+// ---- nonzero frequency: multi-shift CG for (A + i sigma I) X = B ---------------------
+constexpr int MS_MAX = 8;   // shifts per call
+struct MsShifts {
+  int ns;
+  double sigma[MS_MAX];
+};
+// Per right-hand side: the seed CG scalars and, per shift (complex, interleaved re/im),
+// pi = R_k(-i sigma) (previous, current, next), zeta = 1/pi_next, rho = pi_cur/pi_next, the
+// shifted step alpha(s) and direction weight beta(s).  sdone[s]: shift converged (frozen).
+struct MsState {
+  double rr, bb, tol2, a_prev, b_prev, alpha, beta;
+  double pi_prev[2 * MS_MAX], pi_cur[2 * MS_MAX], pi_next[2 * MS_MAX];
+  double zeta[2 * MS_MAX], rho[2 * MS_MAX], as[2 * MS_MAX], bs[2 * MS_MAX];
+  int sdone[MS_MAX];
+  int its, maxit, flag, done;   // flag: 0 ok, 1 non-positive curvature, 2 non-finite
+};
+// Blocks of the vector kernels below (their partials: that many per column).
+int ms_vec_blocks(int64_t n);
+// r = p = B[:, j], P(s, j) = B[:, j] (imaginary part 0), X = 0; partials of b^T b.
+void launch_ms_init(int64_t n, const double* B, int64_t ldb, int nb, int ns, double* r, double* p,
+                    int64_t ld, double* Pr, double* Pi, double* Xr, double* Xi, int64_t ldx,
+                    double* partials, hipStream_t st);
+void launch_ms_start(const double* partials, int P, MsState* state, int nb, int ns, double tol,
+                     int maxit, hipStream_t st);
+// w = A p per live column, partials of p^T w (sh.blocks per column).
+void launch_ms_apply(const Stencil& S, const StencilShape& sh, const double* diag, const double* p,
+                     int64_t ld, double* w, int nb, const MsState* state, double* partials,
+                     hipStream_t st);
+void launch_ms_alpha(const double* partials, int P, MsState* state, int nb, const MsShifts& sh,
+                     hipStream_t st);
+void launch_ms_update(int64_t n, int nb, int ns, const double* w, double* r, int64_t ld,
+                      const double* Pr, const double* Pi, double* Xr, double* Xi, int64_t ldx,
+                      const MsState* state, double* partials, hipStream_t st);
+void launch_ms_beta(const double* partials, int P, MsState* state, int nb, int ns,
+                    hipStream_t st);
+void launch_ms_dir(int64_t n, int nb, int ns, const double* r, double* p, int64_t ld, double* Pr,
+                   double* Pi, const MsState* state, hipStream_t st);
+// out[c] (c = s * nb + j) = ||Re(b_j - (A + i sigma_s) X_c)||^2 and out[nb*ns + c] the
+// imaginary part's.  partials: >= 2 * nb * ns * shp.blocks doubles.
+void launch_ms_resid(const Stencil& S, const StencilShape& shp, const double* diag,
+                     const double* Xr, const double* Xi, int64_t ldx, const double* B, int64_t ldb,
+                     int nb, const MsShifts& sh, double* partials, double* out, hipStream_t st);
 
 // ---- lowest eigenpairs (U_0) ----------------------------------------------------------
 // Eigenpairs of the symmetric m x m H (ld), m <= 32, by parallel-order Jacobi in one

@@ -18,7 +18,7 @@ constexpr int EIG_MAX = 32;
 // Eigenpairs of the symmetric m x m matrix H (column-major, ld): Jacobi rotations in the
 // parallel (round-robin) order: each round rotates m/2 disjoint index pairs at once, first
 // the rows, then the columns (H <- J^T H J), and accumulates Z <- Z J; the players move
-// one place round the table after every round (index 0 fixed).  Sweeps until the
+// one seat round the table after every round (index 0 fixed).  Sweeps until the
 // off-diagonal Frobenius norm is below 1e-15 of the whole (at most 40 sweeps).  Outputs
 // the eigenvalues ascending in lam and the matching unit eigenvectors as columns of Z
 // (column-major, m x m).  One workgroup, m <= EIG_MAX.
@@ -31,6 +31,7 @@ __global__ __launch_bounds__(BS) void k_sym_eig(const double* __restrict__ H, in
   __shared__ int pp[EIG_MAX / 2], qq[EIG_MAX / 2];
   __shared__ int order[EIG_MAX + 1];
   __shared__ double off2, tot2;
+  __shared__ double red[(BS / WAVE) * 2];
   const int t = threadIdx.x;
   const int mp = m + (m & 1);   // players (an odd m sits one out per round)
   for (int e = t; e < m * m; e += BS) {
@@ -38,26 +39,31 @@ __global__ __launch_bounds__(BS) void k_sym_eig(const double* __restrict__ H, in
     A[i][j] = 0.5 * (H[i + j * ld] + H[j + i * ld]);
     V[i][j] = i == j ? 1.0 : 0.0;
   }
-  for (int i = t; i < mp; i += BS) order[i] = i;
   __syncthreads();
+  // player at seat k of round r: seat 0 keeps player 0, the others rotate one seat a round
+  auto seat = [&](int k, int r) {
+    return k == 0 ? 0 : 1 + ((k - 1 - r) % (mp - 1) + (mp - 1)) % (mp - 1);
+  };
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (t == 0) {
-      double o = 0.0, a = 0.0;
-      for (int j = 0; j < m; ++j)
-        for (int i = 0; i < m; ++i) {
-          const double v = A[i][j] * A[i][j];
-          a += v;
-          if (i != j) o += v;
-        }
-      off2 = o;
-      tot2 = a;
+    {
+      double v2[2] = {0.0, 0.0};   // off-diagonal, whole
+      for (int e = t; e < m * m; e += BS) {
+        const int i = e % m, j = e / m;
+        const double v = A[i][j] * A[i][j];
+        v2[1] += v;
+        if (i != j) v2[0] += v;
+      }
+      double s2;
+      block_sum<2, BS>(v2, red, s2);
+      if (t == 0) off2 = s2;
+      if (t == 1) tot2 = s2;
+      __syncthreads();
     }
-    __syncthreads();
     if (!(off2 > 1e-30 * tot2)) break;
     for (int round = 0; round < mp - 1; ++round) {
-      // pair i: order[i] with order[mp - 1 - i]
+      // pair i: the players at seats i and mp - 1 - i
       if (t < mp / 2) {
-        int p = order[t], q = order[mp - 1 - t];
+        int p = seat(t, round), q = seat(mp - 1 - t, round);
         if (p > q) {
           const int s = p;
           p = q;
@@ -104,13 +110,6 @@ __global__ __launch_bounds__(BS) void k_sym_eig(const double* __restrict__ H, in
           V[k][p] = c * vp - s * vq;
           V[k][q] = s * vp + c * vq;
         }
-      }
-      __syncthreads();
-      // round-robin move: order[0] fixed, the others rotate by one place
-      if (t == 0) {
-        const int last = order[mp - 1];
-        for (int i = mp - 1; i > 1; --i) order[i] = order[i - 1];
-        order[1] = last;
       }
       __syncthreads();
     }

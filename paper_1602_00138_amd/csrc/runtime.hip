@@ -2095,11 +2095,11 @@ rom_status rom_lowest_modes(const rom_operator* op, const rom_mu* p, int k, cons
       if (!(e > 0.0)) break;
       double* prev = Y;        // T_0 block
       double* cur = F[2];      // T_1 block = (A - c) Y / e
-      rom::launch_comb3(n, kb, 1.0 / e, AY, -c / e, Y, 0.0, nullptr, ld, cur, st);
+      rom::launch_cheb_step(S, L.diag, Y, ld, kb, 1.0 / e, -c / e, 0.0, nullptr, cur, st);
       for (int j = 2; j <= rom::CHEB_DEGREE; ++j) {
-        rom::launch_spmm(S, L.diag, cur, ld, kb, AY, st);
-        // next = 2 (A - c) cur / e - prev, written over prev
-        rom::launch_comb3(n, kb, 2.0 / e, AY, -2.0 * c / e, cur, -1.0, prev, ld, prev, st);
+        // next = 2 (A - c) cur / e - prev, written over prev, fused with the product
+        rom::launch_cheb_step(S, L.diag, cur, ld, kb, 2.0 / e, -2.0 * c / e, -1.0, prev, prev,
+                              st);
         std::swap(prev, cur);
       }
       // the filtered block is cur; orthonormalise it into Y's buffer
@@ -2114,6 +2114,235 @@ rom_status rom_lowest_modes(const rom_operator* op, const rom_mu* p, int k, cons
     ROM_HIP(hipStreamSynchronize(st));
     for (int i = 0; i < k; ++i) lambda[i] = lam[i];
     if (sweeps) *sweeps = sw + 1;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+namespace rom {
+namespace {
+
+constexpr int MS_CHUNK = 8;   // iterations between host checks of the multi-shift solver
+
+struct ShiftLayout {
+  double *diag, *dmu, *r, *p, *w, *Pr, *Pi, *part, *res;
+  MsState* state;
+  size_t bytes;
+};
+
+ShiftLayout shift_layout(const rom_operator* op, int nb, int ns, void* base) {
+  Arena a(base);
+  ShiftLayout L;
+  const int64_t n = op->n, ld = round_up(n, 64);
+  const StencilShape sh = stencil_shape(op->S, 512);
+  L.diag = a.take<double>(ld);
+  L.dmu = a.take<double>(ld);
+  L.r = a.take<double>(ld * nb);
+  L.p = a.take<double>(ld * nb);
+  L.w = a.take<double>(ld * nb);
+  L.Pr = a.take<double>(ld * nb * ns);
+  L.Pi = a.take<double>(ld * nb * ns);
+  L.part = a.take<double>(std::max<size_t>({(size_t)nb * sh.blocks, (size_t)nb * ms_vec_blocks(n),
+                                            (size_t)2 * nb * ns * sh.blocks}));
+  L.res = a.take<double>(2 * (size_t)nb * ns);
+  L.state = a.take<MsState>(nb);
+  L.bytes = a.off + ALIGN;
+  return L;
+}
+
+struct ResponseLayout {
+  double *dmu, *part, *Ar, *Lc, *Lr, *Ainv, *N, *Nc, *Nr, *lwork, *Br, *Cr, *T, *Yr, *Yi;
+  int* status;
+  int64_t ldr;
+  size_t bytes;
+};
+
+ResponseLayout response_layout(const rom_basis* V, void* base) {
+  Arena a(base);
+  ResponseLayout L;
+  const int m = std::max(V->m, 1);
+  const int ns = std::max(V->n_src, 1), nd = std::max(V->n_det, 1);
+  L.ldr = round_up(m, 2);
+  const size_t mm = (size_t)L.ldr * m;
+  L.dmu = a.take<double>(V->ld);
+  L.part = a.take<double>(std::max<size_t>(gram_partials(m, m, V->n, true), 1));
+  L.Ar = a.take<double>(mm);
+  L.Lc = a.take<double>(mm);
+  L.Lr = a.take<double>(mm);
+  L.Ainv = a.take<double>(mm);
+  L.N = a.take<double>(mm);
+  L.Nc = a.take<double>(mm);
+  L.Nr = a.take<double>(mm);
+  L.lwork = a.take<double>(linv_rebuild_work(m));
+  L.Br = a.take<double>(L.ldr * ns);
+  L.Cr = a.take<double>(L.ldr * nd);
+  L.T = a.take<double>(L.ldr * ns);
+  L.Yr = a.take<double>(L.ldr * ns);
+  L.Yi = a.take<double>(L.ldr * ns);
+  L.status = a.take<int>(4);
+  L.bytes = a.off + ALIGN;
+  return L;
+}
+
+}  // namespace
+}  // namespace rom
+
+rom_status rom_shifted_solve_bytes(const rom_operator* op, int nb, int ns, size_t* bytes) {
+  try {
+    if (!op || !bytes) throw Error(ROM_EINVAL, "null argument");
+    if (nb < 1 || ns < 1 || ns > rom::MS_MAX) throw Error(ROM_EINVAL, "need nb >= 1, 1 <= ns <= 8");
+    *bytes = rom::shift_layout(op, nb, ns, nullptr).bytes;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_shifted_solve(const rom_operator* op, const rom_mu* p, const double* B, int nb,
+                             const double* sigma, int ns, double tol, int maxit, double* Xr,
+                             double* Xi, int* its, double* resid, void* scratch,
+                             size_t scratch_bytes, void* stream) {
+  try {
+    if (!op || !B || !sigma || !Xr || !Xi) throw Error(ROM_EINVAL, "null argument");
+    rom::check_mu(p, op->grid.dim);
+    if (nb < 1 || ns < 1 || ns > rom::MS_MAX) throw Error(ROM_EINVAL, "need nb >= 1, 1 <= ns <= 8");
+    if (!(tol > 0.0) || maxit < 1) throw Error(ROM_EINVAL, "tol and maxit must be positive");
+    rom::MsShifts sh{};
+    sh.ns = ns;
+    for (int s = 0; s < ns; ++s) {
+      if (!std::isfinite(sigma[s])) throw Error(ROM_EINVAL, "non-finite shift");
+      sh.sigma[s] = sigma[s];
+    }
+    const rom::ShiftLayout L = rom::shift_layout(op, nb, ns, scratch);
+    if (!scratch || scratch_bytes < L.bytes) throw Error(ROM_ECAPACITY, "scratch too small");
+    hipStream_t st = (hipStream_t)stream;
+    const rom::Stencil& S = op->S;
+    const int64_t n = op->n, ld = rom::round_up(n, 64);
+    const rom::StencilShape shp = rom::stencil_shape(S, 512);
+    const int Pv = rom::ms_vec_blocks(n);
+    rom::launch_mu_eval(S, rom::make_bumps(*p, op->grid.dim), op->diag_star, L.diag, L.dmu, st);
+    rom::launch_ms_init(n, B, n, nb, ns, L.r, L.p, ld, L.Pr, L.Pi, Xr, Xi, n, L.part, st);
+    rom::launch_ms_start(L.part, Pv, L.state, nb, ns, tol, maxit, st);
+    std::vector<rom::MsState> hs(nb);
+    for (int it = 0;; it += rom::MS_CHUNK) {
+      for (int c = 0; c < rom::MS_CHUNK; ++c) {
+        rom::launch_ms_apply(S, shp, L.diag, L.p, ld, L.w, nb, L.state, L.part, st);
+        rom::launch_ms_alpha(L.part, shp.blocks, L.state, nb, sh, st);
+        rom::launch_ms_update(n, nb, ns, L.w, L.r, ld, L.Pr, L.Pi, Xr, Xi, n, L.state, L.part, st);
+        rom::launch_ms_beta(L.part, Pv, L.state, nb, ns, st);
+        rom::launch_ms_dir(n, nb, ns, L.r, L.p, ld, L.Pr, L.Pi, L.state, st);
+      }
+      ROM_HIP(hipMemcpyAsync(hs.data(), L.state, sizeof(rom::MsState) * nb, hipMemcpyDeviceToHost,
+                             st));
+      ROM_HIP(hipStreamSynchronize(st));
+      bool all = true;
+      for (int j = 0; j < nb; ++j) all = all && hs[j].done;
+      // every column stops by maxit (its own counter); the bound below is a safety net
+      if (all || it > maxit + 2 * rom::MS_CHUNK) break;
+    }
+    // true residuals ||b_j - (A + i sigma_s) X||, FP64
+    rom::launch_ms_resid(S, shp, L.diag, Xr, Xi, n, B, n, nb, sh, L.part, L.res, st);
+    std::vector<double> r2(2 * (size_t)nb * ns);
+    ROM_HIP(hipMemcpyAsync(r2.data(), L.res, sizeof(double) * r2.size(), hipMemcpyDeviceToHost, st));
+    ROM_HIP(hipStreamSynchronize(st));
+    int flag = 0;
+    bool noconv = false;
+    for (int j = 0; j < nb; ++j) {
+      if (its) its[j] = hs[j].its;
+      flag = std::max(flag, hs[j].flag);
+      for (int s = 0; s < ns; ++s) noconv = noconv || !hs[j].sdone[s];
+    }
+    if (resid) {
+      const size_t cols = (size_t)nb * ns;
+      for (int s = 0; s < ns; ++s)
+        for (int j = 0; j < nb; ++j) {
+          const size_t c = (size_t)s * nb + j;
+          const double bb = hs[j].bb;
+          resid[c] = bb > 0.0 ? std::sqrt((r2[c] + r2[cols + c]) / bb) : 0.0;
+        }
+    }
+    if (flag == 1) throw Error(ROM_ENOTSPD, "shifted solve: non-positive curvature in the seed CG");
+    if (flag == 2) throw Error(ROM_ENONFINITE, "shifted solve: non-finite value");
+    if (noconv) {
+      rom::report_message("shifted solve: some shift reached maxit");
+      return ROM_ENOCONV;
+    }
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_reduced_response_bytes(const rom_basis* V, size_t* bytes) {
+  try {
+    if (!V || !bytes) throw Error(ROM_EINVAL, "null argument");
+    *bytes = rom::response_layout(V, nullptr).bytes;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_reduced_response(const rom_basis* V, const rom_mu* p, const double* sigma, int ns,
+                                double* Psi_re, double* Psi_im, void* scratch,
+                                size_t scratch_bytes, void* stream) {
+  try {
+    if (!V || !sigma || !Psi_re || !Psi_im) throw Error(ROM_EINVAL, "null argument");
+    rom::check_mu(p, V->op->grid.dim);
+    if (ns < 0) throw Error(ROM_EINVAL, "negative shift count");
+    const int m = V->m, nsrc = V->n_src, nd = V->n_det;
+    if (m == 0) throw Error(ROM_EINVAL, "empty basis");
+    const rom::ResponseLayout L = rom::response_layout(V, scratch);
+    if (!scratch || scratch_bytes < L.bytes) throw Error(ROM_ECAPACITY, "scratch too small");
+    for (int s = 0; s < ns; ++s)
+      if (!std::isfinite(sigma[s])) throw Error(ROM_EINVAL, "non-finite shift");
+    if (ns == 0 || nsrc == 0 || nd == 0) return ROM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t ld = V->ld, ldr = L.ldr;
+    // A_r = V^T A_* V + mu0 I + V^T diag(mu - mu0) V, its inverse Cholesky factor Lc and
+    // A_r^{-1} = Lc^T Lc; B_r, C_r by row gathers (E_r = I: V has orthonormal columns)
+    rom::launch_mu_eval(V->op->S, rom::make_bumps(*p, V->op->grid.dim), V->op->diag_star, nullptr,
+                        L.dmu, st);
+    rom::launch_gram(V->Q, ld, m, V->Q, ld, m, V->n, L.dmu, true, V->Gstar, V->ldg, p->mu0, L.Ar,
+                     ldr, L.part, st);
+    ROM_HIP(hipMemsetAsync(L.status, 0, sizeof(int), st));
+    rom::launch_linv_rebuild(L.Ar, ldr, m, L.Lc, L.Lr, L.lwork, L.status, st);
+    rom::launch_gemm(m, m, m, 1.0, L.Lc, ldr, true, L.Lc, ldr, false, 0.0, nullptr, 0, L.Ainv, ldr,
+                     st);
+    rom::launch_gather_rows(V->Q, ld, m, V->idx_dev, V->scale_dev, nsrc, L.Br, ldr, st);
+    rom::launch_gather_rows(V->Q, ld, m, V->idx_dev + nsrc, V->scale_dev + nsrc, nd, L.Cr, ldr, st);
+    for (int s = 0; s < ns; ++s) {
+      const double sg = sigma[s];
+      double* Pr = Psi_re + (size_t)s * nd * nsrc;
+      double* Pi = Psi_im + (size_t)s * nd * nsrc;
+      // (A_r + i sg I)(y_r + i y_i) = B_r  <=>  (A_r + sg^2 A_r^{-1}) y_r = B_r,
+      // y_i = -sg A_r^{-1} y_r; A_r + sg^2 A_r^{-1} is SPD (it commutes with A_r)
+      const double* Lc = L.Lc;
+      if (sg != 0.0) {
+        rom::launch_axpby_cols(m, m, 1.0, L.Ar, ldr, sg * sg, L.Ainv, ldr, L.N, ldr, st);
+        rom::launch_linv_rebuild(L.N, ldr, m, L.Nc, L.Nr, L.lwork, L.status, st);
+        Lc = L.Nc;
+      }
+      rom::launch_gemm(m, nsrc, m, 1.0, Lc, ldr, false, L.Br, ldr, false, 0.0, nullptr, 0, L.T, ldr,
+                       st);
+      rom::launch_gemm(m, nsrc, m, 1.0, Lc, ldr, true, L.T, ldr, false, 0.0, nullptr, 0, L.Yr, ldr,
+                       st);
+      rom::launch_gemm(nd, nsrc, m, 1.0, L.Cr, ldr, true, L.Yr, ldr, false, 0.0, nullptr, 0, Pr, nd,
+                       st);
+      if (sg != 0.0) {
+        rom::launch_gemm(m, nsrc, m, -sg, L.Ainv, ldr, false, L.Yr, ldr, false, 0.0, nullptr, 0,
+                         L.Yi, ldr, st);
+        rom::launch_gemm(nd, nsrc, m, 1.0, L.Cr, ldr, true, L.Yi, ldr, false, 0.0, nullptr, 0, Pi,
+                         nd, st);
+      } else {
+        ROM_HIP(hipMemsetAsync(Pi, 0, sizeof(double) * nd * nsrc, st));
+      }
+    }
+    int status = 0;
+    ROM_HIP(hipMemcpyAsync(&status, L.status, sizeof(int), hipMemcpyDeviceToHost, st));
+    ROM_HIP(hipStreamSynchronize(st));
+    if (status) throw Error(ROM_ENOTSPD, "reduced matrix not positive definite");
     return ROM_OK;
   } catch (const Error& e) {
     return rom::fail(e);

@@ -197,6 +197,29 @@ __global__ __launch_bounds__(BS) void k_stencil(Stencil S, const T* __restrict__
                           blockIdx.x + gridDim.x * blockIdx.y);
 }
 
+// One step of a three-term (Chebyshev) recurrence on k columns, fused with the product:
+// out[:, v] = a (A x[:, v]) + b x[:, v] + c prev[:, v] (prev may be NULL).  out may alias
+// prev (each element of prev is read by the thread that then writes it); neither may alias
+// x.  Same launch shape as k_stencil (blockIdx.z = column), so x is fetched about once.
+template <bool VAR>
+__global__ __launch_bounds__(BS) void k_cheb_step(Stencil S, const double* __restrict__ diag,
+                                                   const double* __restrict__ x0, int64_t ld,
+                                                   double a, double b, double c,
+                                                   const double* prev0, double* out0, int zc) {
+  const double* __restrict__ x = x0 + (int64_t)blockIdx.z * ld;
+  const double* prev = prev0 ? prev0 + (int64_t)blockIdx.z * ld : nullptr;
+  double* out = out0 + (int64_t)blockIdx.z * ld;
+  const int q = blockIdx.x * BS + threadIdx.x;
+  if (q >= S.nx * S.ny) return;
+  const int z0 = blockIdx.y * zc;
+  const int z1 = min(z0 + zc, S.nz);
+  stencil_walk<VAR>(S, diag, x, q, z0, z1, [&](int64_t i, double ax, double xi) {
+    double r = a * ax + b * xi;
+    if (prev) r += c * prev[i];
+    out[i] = r;
+  });
+}
+
 // out[z * ostride] = sum_b partials[z * P + b], one block per column z.
 __global__ void k_reduce_cols(const double* __restrict__ partials, int P, double* out,
                               int64_t ostride) {
@@ -276,6 +299,22 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
   STENCIL_LAUNCH(double, 0, grid, diag, X, ld, Y, ld, sh.zc, (int64_t)-1, 0.0,
                  (const int64_t*)nullptr, (const double*)nullptr, (double*)nullptr,
                  (const CGState*)nullptr);
+}
+
+void launch_cheb_step(const Stencil& S, const double* diag, const double* X, int64_t ld, int k,
+                      double a, double b, double c, const double* prev, double* out,
+                      hipStream_t st) {
+  if (k <= 0) return;
+  StencilShape sh = stencil_shape(S, 512);
+  dim3 grid = sh.grid;
+  grid.z = k;
+  if (S.var)
+    ROM_LAUNCH(k_cheb_step<true>, grid, dim3(BS), 0, st, S, diag, X, ld, a, b, c, prev, out,
+               sh.zc);
+  else
+    ROM_LAUNCH(k_cheb_step<false>, grid, dim3(BS), 0, st, S, diag, X, ld, a, b, c, prev, out,
+               sh.zc);
+  ROM_CHECK_LAUNCH();
 }
 
 void launch_resid_unit(const Stencil& S, const double* diag, const double* x, int64_t idx,

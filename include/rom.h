@@ -282,6 +282,32 @@ ROM_API rom_status rom_lowest_modes(const rom_operator* op, const rom_mu* p, int
                                     double* lambda, int* sweeps, void* scratch,
                                     size_t scratch_bytes, void* stream);
 
+/* Nonzero modulation frequency.  The systems of eq. (solves), (A(p) + i sigma I) X = B with
+ * sigma = omega/nu, for ns shifts at once by multi-shift CG (one real CG on A(p) whose
+ * residuals every shifted system shares up to a complex factor; each shift stops when its
+ * residual <= tol ||b_j||, checked again on the FP64 true residual at exit):
+ *   B: device N x nb (ld N), real right-hand sides; sigma: host, ns values (1 <= ns <= 8);
+ *   Xr, Xi: device N x (nb * ns) (ld N), real and imaginary parts, column s * nb + j;
+ *   its: host nb (may be NULL), iterations of the shared CG per right-hand side;
+ *   resid: host nb * ns (may be NULL), true relative residuals, index s * nb + j.
+ * Returns ROM_ENOCONV if some shift reached maxit (X then holds the last iterate),
+ * ROM_ENOTSPD / ROM_ENONFINITE on breakdown.  scratch: >= rom_shifted_solve_bytes. */
+ROM_API rom_status rom_shifted_solve_bytes(const rom_operator* op, int nb, int ns, size_t* bytes);
+ROM_API rom_status rom_shifted_solve(const rom_operator* op, const rom_mu* p, const double* B,
+                                     int nb, const double* sigma, int ns, double tol, int maxit,
+                                     double* Xr, double* Xi, int* its, double* resid,
+                                     void* scratch, size_t scratch_bytes, void* stream);
+/* The reduced frequency response of the basis (the transfer function that follows eq.
+ * (newreduced)), Psi_r(sigma) = C_r^T (i sigma E_r + A_r(p))^{-1} B_r with E_r = I (V has
+ * orthonormal columns), for ns shifts (host array sigma).  Computed in real arithmetic:
+ * y_r solves the SPD system (A_r + sigma^2 A_r^{-1}) y_r = B_r, y_i = -sigma A_r^{-1} y_r.
+ * Psi_re, Psi_im: device n_det x n_src per shift (column-major), shift s at s*n_det*n_src.
+ * scratch: >= rom_reduced_response_bytes. */
+ROM_API rom_status rom_reduced_response_bytes(const rom_basis* V, size_t* bytes);
+ROM_API rom_status rom_reduced_response(const rom_basis* V, const rom_mu* p, const double* sigma,
+                                        int ns, double* Psi_re, double* Psi_im, void* scratch,
+                                        size_t scratch_bytes, void* stream);
+
 /* Basis queries: N, m, and a device copy of V (N x m, column-major, ld = N). */
 ROM_API rom_status rom_basis_dims(const rom_basis* V, int64_t* N, int* m);
 ROM_API rom_status rom_basis_copy(const rom_basis* V, double* dst, void* stream);

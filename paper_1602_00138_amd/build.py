@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librom.so")
-SOURCES = ["stencil.hip", "dense.hip", "gram.hip", "dcg.hip", "modes.hip", "runtime.hip",
+SOURCES = ["stencil.hip", "dense.hip", "gram.hip", "dcg.hip", "modes.hip", "freq.hip", "runtime.hip",
            "seednet.hip", "seedrt.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

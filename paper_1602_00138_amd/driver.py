@@ -113,6 +113,37 @@ class Problem:
         # each block is n_det x n_src column-major = (n_src, n_det) row-major
         return J.transpose(1, 2).contiguous()
 
+    def reduced_response(self, res: SequenceResult, p: R.MuParams, sigma) -> torch.Tensor:
+        """Psi_r(sigma) = C_r^T (i sigma I + A_r(p))^{-1} B_r for each shift sigma = omega/nu,
+        as a complex128 tensor (ns, n_det, n_src)."""
+        dev = self.device
+        sig = np.atleast_1d(np.asarray(sigma, dtype=np.float64))
+        ns, nd = self.src_idx.size, self.det_idx.size
+        Pr = torch.empty((sig.size, ns, nd), dtype=torch.float64, device=dev)
+        Pi = torch.empty_like(Pr)
+        scratch = torch.empty(R.rom_reduced_response_bytes(res.basis), dtype=torch.uint8,
+                              device=dev)
+        R.rom_reduced_response(res.basis, p, sig, Pr, Pi, scratch)
+        # each block is n_det x n_src column-major = (n_src, n_det) row-major
+        return torch.complex(Pr, Pi).transpose(1, 2).contiguous()
+
+    def shifted_solve(self, p: R.MuParams, B: torch.Tensor, sigma, tol: float = 1e-8,
+                      maxit: int = 0, allow_noconv: bool = False):
+        """(A(p) + i sigma I) X = B for the columns of B ((nb, N) rows) and every shift:
+        returns (X complex128 (ns, nb, N), its (nb,), true relative residuals (ns, nb),
+        status)."""
+        dev = self.device
+        B = B.to(dtype=torch.float64, device=dev).contiguous()
+        nb = B.shape[0]
+        sig = np.atleast_1d(np.asarray(sigma, dtype=np.float64))
+        Xr = torch.empty((sig.size, nb, self.n), dtype=torch.float64, device=dev)
+        Xi = torch.empty_like(Xr)
+        scratch = torch.empty(R.rom_shifted_solve_bytes(self.op, nb, sig.size),
+                              dtype=torch.uint8, device=dev)
+        st, its, res = R.rom_shifted_solve(self.op, p, B, nb, sig, tol, maxit or self.n, Xr, Xi,
+                                           scratch, allow_noconv=allow_noconv)
+        return torch.complex(Xr, Xi), its, res, st
+
     def lowest_modes(self, p: R.MuParams, k: int, X0: torch.Tensor, tol: float = 1e-8,
                      maxit: int = 200):
         """The k smallest eigenpairs of A(p) from the starting block X0 ((kx, N) rows, kx >= k

@@ -38,7 +38,8 @@ KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "ou
 EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator", "rom_sequence_bytes",
             "rom_solve_sequence", "rom_solve_sequences", "rom_reduced_bytes", "rom_reduced_transfer",
             "rom_reduced_jacobian_bytes", "rom_reduced_jacobian", "rom_lowest_modes_bytes",
-            "rom_lowest_modes", "rom_basis_dims",
+            "rom_lowest_modes", "rom_shifted_solve_bytes", "rom_shifted_solve",
+            "rom_reduced_response_bytes", "rom_reduced_response", "rom_basis_dims",
             "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error",
             "rom_seednet_bytes", "rom_seednet_create", "rom_seednet_forward",
             "rom_seednet_gradients", "rom_seednet_train_step", "rom_seednet_params",
@@ -115,6 +116,13 @@ def _load():
         "rom_reduced_jacobian_bytes": (C.c_int, [vp, P(sz)]),
         "rom_reduced_jacobian": (C.c_int, [vp, P(rom_mu), vp, vp, sz, vp]),
         "rom_lowest_modes_bytes": (C.c_int, [vp, C.c_int, P(sz)]),
+        "rom_shifted_solve_bytes": (C.c_int, [vp, C.c_int, C.c_int, P(sz)]),
+        "rom_shifted_solve": (C.c_int, [vp, P(rom_mu), vp, C.c_int, P(C.c_double), C.c_int,
+                                        C.c_double, C.c_int, vp, vp, P(C.c_int),
+                                        P(C.c_double), vp, sz, vp]),
+        "rom_reduced_response_bytes": (C.c_int, [vp, P(sz)]),
+        "rom_reduced_response": (C.c_int, [vp, P(rom_mu), P(C.c_double), C.c_int, vp, vp, vp,
+                                           sz, vp]),
         "rom_lowest_modes": (C.c_int, [vp, P(rom_mu), C.c_int, vp, C.c_int, C.c_double, C.c_int,
                                        vp, P(C.c_double), P(C.c_int), vp, sz, vp]),
         "rom_basis_dims": (C.c_int, [vp, P(C.c_int64), P(C.c_int)]),
@@ -361,6 +369,45 @@ def rom_lowest_modes(op: int, p: MuParams, k: int, X0, kx: int, tol: float, maxi
                                  int(maxit), _ptr(U), lam, C.byref(sweeps), _ptr(scratch),
                                  scratch.numel() * scratch.element_size(), _stream(stream)))
     return np.array(lam[:], dtype=np.float64), int(sweeps.value)
+
+
+def rom_shifted_solve_bytes(op: int, nb: int, ns: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.rom_shifted_solve_bytes(op, int(nb), int(ns), C.byref(out)))
+    return int(out.value)
+
+
+def rom_shifted_solve(op: int, p: MuParams, B, nb: int, sigma, tol: float, maxit: int, Xr, Xi,
+                      scratch, stream=None, allow_noconv: bool = False):
+    """Returns (status, its (nb,), resid (ns, nb)); Xr, Xi are filled on the device."""
+    mu = p.c_struct()
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    ns = sig.size
+    sarr = (C.c_double * ns)(*sig.tolist())
+    its = (C.c_int * nb)()
+    res = (C.c_double * (nb * ns))()
+    st = _check(_lib.rom_shifted_solve(op, C.byref(mu), _ptr(B), int(nb), sarr, int(ns),
+                                       float(tol), int(maxit), _ptr(Xr), _ptr(Xi), its, res,
+                                       _ptr(scratch), scratch.numel() * scratch.element_size(),
+                                       _stream(stream)),
+                allow=(ROM_ENOCONV,) if allow_noconv else ())
+    return st, np.array(its[:], dtype=np.int64), np.array(res[:]).reshape(ns, nb)
+
+
+def rom_reduced_response_bytes(basis: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.rom_reduced_response_bytes(basis, C.byref(out)))
+    return int(out.value)
+
+
+def rom_reduced_response(basis: int, p: MuParams, sigma, Psi_re, Psi_im, scratch,
+                         stream=None) -> None:
+    mu = p.c_struct()
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    sarr = (C.c_double * max(sig.size, 1))(*sig.tolist())
+    _check(_lib.rom_reduced_response(basis, C.byref(mu), sarr, int(sig.size), _ptr(Psi_re),
+                                     _ptr(Psi_im), _ptr(scratch),
+                                     scratch.numel() * scratch.element_size(), _stream(stream)))
 
 
 def rom_basis_dims(basis: int):

@@ -1,0 +1,111 @@
+"""GPU parity at nonzero frequency: rom_shifted_solve (the systems of eq. (solves) by
+multi-shift CG) against the oracle's sparse complex direct solve, and rom_reduced_response
+(the reduced transfer function after eq. (newreduced)) against the oracle's dense complex
+formula evaluated on the GPU's own basis.
+
+Tolerances.  Shifted solves stop at ||b - (A + i sigma) x|| <= tol ||b|| (FP64, checked
+on the true residual at exit), so ||x - x_ref|| <= tol ||b|| / |lambda_min + i sigma|;
+tested at twice that, and the residual is recomputed here from x with the oracle's A.
+The reduced response: the GPU solves the equivalent real SPD system (A_r + sigma^2
+A_r^{-1}) y_r = B_r, y_i = -sigma A_r^{-1} y_r with inverse Cholesky factors, the oracle a
+complex LU; A_r is well conditioned here (kappa < 1e4), so 1e-9 relative to the largest
+entry."""
+import numpy as np
+import pytest
+
+import phantoms as ph
+from helpers import OracleProblem
+from oracle import frequency as fq
+from oracle import modes
+from oracle import rom as orom
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def drv(gpu):
+    from paper_1602_00138_amd import driver
+    return driver
+
+
+def _rhs(orc, extra_zero=False):
+    rng = np.random.default_rng(17)
+    cols = [orc.B[:, 0], orc.B[:, 1], rng.standard_normal(orc.wl.n)]
+    if extra_zero:
+        cols.append(np.zeros(orc.wl.n))
+    return np.stack(cols)          # (nb, N) rows
+
+
+@pytest.mark.parametrize("wl,sigma", [
+    (ph.small(2, (17, 13), K=1, nb=2), [0.0, 0.5, 3.0, 40.0]),
+    (ph.small(3, (11, 10, 9), K=1, nb=3, D="lognormal"), [0.2, 1.0, 7.5]),
+    (ph.small(3, (9, 8, 7), K=1, nb=2), [0.1, 0.3, 1.0, 2.0, 5.0, 10.0, 30.0, 100.0]),  # 8 shifts
+])
+def test_shifted_solve_parity(drv, wl, sigma):
+    import torch
+    orc = OracleProblem(wl)
+    prob = drv.problem_from_workload(wl)
+    p = drv.points_from_workload(wl)[0]
+    A = orc.A(0)
+    Bh = _rhs(orc, extra_zero=True)
+    tol = 1e-10
+    X, its, res, st = prob.shifted_solve(p, torch.from_numpy(Bh), sigma, tol=tol)
+    assert st == 0
+    X = X.cpu().numpy()
+    lam_min = modes.lowest_modes(A, 1)[0][0]
+    assert its[-1] == 0 and np.all(X[:, -1] == 0) and np.all(res[:, -1] == 0)
+    for s, sg in enumerate(sigma):
+        ref = fq.shifted_solve(A, Bh.T, sg)          # N x nb
+        for j in range(Bh.shape[0] - 1):
+            b = Bh[j]
+            x = X[s, j]
+            tr = np.linalg.norm(b - (A @ x + 1j * sg * x)) / np.linalg.norm(b)
+            assert tr <= tol * 1.01, (s, j, tr)
+            assert abs(tr - res[s, j]) <= 1e-3 * tol + 1e-14, (s, j, tr, res[s, j])
+            bound = 2 * tol * np.linalg.norm(b) / abs(lam_min + 1j * sg)
+            assert np.linalg.norm(x - ref[:, j]) <= bound + 1e-14, (s, j)
+
+
+def test_shifted_solve_edges(drv):
+    import torch
+    from paper_1602_00138_amd import rom as R
+    wl = ph.small(2, (9, 8), K=1, nb=1)
+    orc = OracleProblem(wl)
+    prob = drv.problem_from_workload(wl)
+    p = drv.points_from_workload(wl)[0]
+    B = torch.from_numpy(_rhs(orc)[:1])
+    with pytest.raises(R.RomError):
+        prob.shifted_solve(p, B, np.arange(9.0))          # more than 8 shifts
+    with pytest.raises(R.RomError):
+        prob.shifted_solve(p, B, [0.0, np.inf])
+    # maxit reached: ENOCONV, residuals above tol, and X still the last iterate (finite)
+    X, its, res, st = prob.shifted_solve(p, B, [0.5], tol=1e-12, maxit=3, allow_noconv=True)
+    assert st == R.ROM_ENOCONV and its[0] == 3 and res[0, 0] > 1e-12
+    assert np.isfinite(X.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("wl", [ph.small(2, (17, 13), n_src=4, n_det=3, K=2, nb=2),
+                                ph.small(3, (11, 10, 9), n_src=3, n_det=4, K=2, nb=3,
+                                         D="lognormal")])
+def test_reduced_response_parity(drv, wl):
+    orc = OracleProblem(wl)
+    prob = drv.problem_from_workload(wl)
+    pts = drv.points_from_workload(wl)
+    res = prob.solve(pts, wl.tol, wl.trunc)
+    V = res.Q().cpu().numpy().T
+    ns = wl.n_src
+    Bt, Ct = orc.B[:, :ns], orc.B[:, ns:]
+    sigma = [0.0, 0.4, 2.0, 25.0]
+    for i, p in enumerate(pts):
+        Psi = prob.reduced_response(res, p, sigma).cpu().numpy()
+        assert Psi.shape == (len(sigma), wl.n_det, ns)
+        A = orc.A(i)
+        for s, sg in enumerate(sigma):
+            ref = fq.reduced_response(V, A, Bt, Ct, sg)
+            scale = np.abs(ref).max()
+            assert np.abs(Psi[s] - ref).max() <= 1e-9 * scale, (i, s)
+        # zero frequency at a sample point: the full-order transfer (interpolation)
+        full = orom.full_transfer(A, Bt, Ct)
+        assert np.abs(Psi[0] - full).max() <= 1e-6 * np.abs(full).max()
+        assert np.abs(Psi[0].imag).max() == 0.0
+    res.close()

@@ -128,12 +128,11 @@ def measure_forms(prob, pts, wl, steps: int):
     return out
 
 
-def measure_jacobian(prob, pts, wl, plain_value: float, reps: int = 5):
-    """The reduced Jacobian (eq. (newjac) on the basis) at the last point: one sequence
-    (untimed) builds the basis, then rom_reduced_jacobian is timed; the full-order
-    Jacobian by the adjoint approach would need n_src + n_det solves at that point."""
+def measure_jacobian(prob, pts, wl, plain_value: float, res, reps: int = 5):
+    """The reduced Jacobian (eq. (newjac) on the basis) at the last point: rom_reduced_jacobian
+    on the basis `res` of one sequence is timed; the full-order Jacobian by the adjoint
+    approach would need n_src + n_det solves at that point."""
     import torch
-    res = prob.solve(pts, wl.tol, wl.trunc, keep_X=False)
     J = prob.reduced_jacobian(res, pts[-1])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -146,9 +145,47 @@ def measure_jacobian(prob, pts, wl, plain_value: float, reps: int = 5):
            "note": "per call: A_r(p), its inverse Cholesky factor, the lifted states and "
                    "co-states V A_r^{-1} [B_r, C_r], one weighted product per parameter; "
                    "the full-order estimate is n_src + n_det solves at the plain rate"}
-    res.close()
     log(f"reduced Jacobian: {ms:.2f} ms for {out['params']} parameters "
         f"({out['shape'][0]}x{out['shape'][1]} each, m={out['basis_m']})")
+    return out
+
+
+def measure_frequency(prob, pts, wl, res, sigma=(0.3, 1.0, 3.0, 10.0), nb: int = 8,
+                      reps: int = 3):
+    """Nonzero frequency at the last point: the full-order shifted systems of eq. (solves)
+    for nb right-hand sides (sources) and the given sigma = omega/nu by rom_shifted_solve
+    (to relative residual wl.tol), and the reduced response of the basis `res` at the same
+    shifts by rom_reduced_response.  Right-hand sides are resident before timing."""
+    import torch
+    p = pts[-1]
+    B = torch.zeros((nb, prob.n), dtype=torch.float64)
+    idx = prob.src_idx[:nb]
+    B[np.arange(idx.size), torch.from_numpy(np.asarray(idx, dtype=np.int64))] = \
+        torch.from_numpy(np.asarray(prob.src_scale[:nb], dtype=np.float64))
+    B = B.to(prob.device)
+    prob.shifted_solve(p, B, sigma, tol=wl.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        X, its, resid, _ = prob.shifted_solve(p, B, sigma, tol=wl.tol)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    Psi = prob.reduced_response(res, p, sigma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Psi = prob.reduced_response(res, p, sigma)
+    torch.cuda.synchronize()
+    ms_r = 1e3 * (time.perf_counter() - t0) / reps
+    out = {"shifts": list(sigma), "rhs": int(idx.size),
+           "shifted_solve_ms": ms, "shifted_solves_per_s": idx.size * len(sigma) / (ms / 1e3),
+           "cg_its_max": int(its.max()), "max_true_resid": float(resid.max()),
+           "reduced_response_ms": ms_r, "basis_m": res.m,
+           "note": "multi-shift CG: one real CG on A(p) per right-hand side serves every "
+                   "shift; reduced response via the SPD system (A_r + sigma^2 A_r^-1) y_r = B_r"}
+    log(f"frequency: {idx.size} RHS x {len(sigma)} shifts in {ms:.1f} ms "
+        f"({out['shifted_solves_per_s']:.0f} shifted solves/s, {out['cg_its_max']} its), "
+        f"reduced response {ms_r:.2f} ms (m={res.m})")
     return out
 
 
@@ -289,6 +326,8 @@ def main():
                     help="also time the mixed / grouped forms on the same problem (0/1)")
     ap.add_argument("--jacobian", type=int, default=1,
                     help="time the reduced Jacobian at the last point (0/1)")
+    ap.add_argument("--frequency", type=int, default=1,
+                    help="time the nonzero-frequency solves and reduced response (0/1)")
     ap.add_argument("--modes", type=int, default=1,
                     help="time the lowest-eigenpair block U_0 at the first point (0/1)")
     ap.add_argument("--suite", type=int, default=0,
@@ -421,7 +460,12 @@ def main():
     spmm = spmm_bandwidth(prob, pts[-1], 64)
     log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s)")
 
-    jac = measure_jacobian(prob, pts, wl, value) if args.jacobian else None
+    jac = freq = None
+    if args.jacobian or args.frequency:
+        basis = prob.solve(pts, wl.tol, wl.trunc, keep_X=False)
+        jac = measure_jacobian(prob, pts, wl, value, basis) if args.jacobian else None
+        freq = measure_frequency(prob, pts, wl, basis) if args.frequency else None
+        basis.close()
     modes = measure_modes(prob, pts, wl) if args.modes else None
     forms = measure_forms(prob, pts, wl, args.steps) if args.forms else None
     if forms:
@@ -462,6 +506,7 @@ def main():
         "forms": forms,
         "reduced_jacobian": jac,
         "lowest_modes": modes,
+        "frequency": freq,
         "learned_seed": learned,
         "uneven_grids": suite,
         "cpu_baseline": cpu,

@@ -125,6 +125,14 @@ typedef struct {
                        A(p_i)-optimal point of x0 + span(guess - x0) when that lowers the
                        residual; the correction appended to V and U_j is still x - x0.
                        Needs group <= 1. */
+  const float* recycle; /* device, or NULL: n_recycle learned recycle vectors per point i, N
+                       values each at column (i n_recycle + c).  At each point they are made
+                       A(p_i)-orthogonal to V as it stands at the point start (the part the
+                       outer projection cannot supply) and orthonormal among themselves, and
+                       join the recycle space U_j of every right-hand side solved at that
+                       point (not V); a vector with less than 1e-6 of its norm left is
+                       dropped. */
+  int n_recycle;    /* 1..16 when recycle is set */
 } rom_opts;
 
 /* One record per (point i, right-hand side j), in solve order. */
@@ -319,39 +327,63 @@ ROM_API rom_status rom_basis_copy(const rom_basis* V, double* dst, void* stream)
  *   e0 = relu(conv(x; 3->16)), e1 = relu(conv(pool(e0); 16->32)),
  *   e2 = relu(conv(pool(e1); 32->48)), e3 = relu(conv(pool(e2); 48->64)),
  *   d2 = relu(conv(up(e3); 64->48) + e2), d1 = relu(conv(up(d2); 48->32) + e1),
- *   d0 = relu(conv(up(d1); 32->16) + e0), y = conv(d0; 16->1).
+ *   d0 = relu(conv(up(d1); 32->16) + e0), y = conv(d0; 16->outputs).
+ * outputs = 1 for the initial-guess network, up to 16 for the recycle-vector network (one
+ * output channel per vector).
  * Weights and activations are BF16 with FP32 accumulation (matrix cores); the master
  * parameters, gradients and Adam moments are FP32.  Parameters (host or device arrays
  * of nparams floats): per layer in the order e0 e1 e2 e3 d2 d1 d0 y, the weights
  * w[o][i][a][b][c] (multiplying input channel i at offset (a-1, b-1, c-1) in (z, y, x))
  * then the biases b[o].
- * Inputs: device FP32 [batch][3][N] (fields in the grid's x-fastest order); outputs and
- * targets: device FP32 [batch][N].  The loss is the mean over batch and voxels of
- * (y - target)^2.  Memory is caller-owned: param_mem (>= param_bytes) and work_mem
+ * Inputs: device FP32 [batch][3][N] (fields in the grid's x-fastest order); outputs (and
+ * output gradients): device FP32 [batch][outputs][N]; targets (one-output networks):
+ * device FP32 [batch][N], with the loss the mean over batch and voxels of (y - target)^2.  Memory is caller-owned: param_mem (>= param_bytes) and work_mem
  * (>= work_bytes, sized for up to `batch` samples per call), 256-byte aligned. */
 typedef struct rom_seednet rom_seednet;
-ROM_API rom_status rom_seednet_bytes(int nx, int ny, int nz, int batch, int64_t* nparams,
-                             size_t* param_bytes, size_t* work_bytes);
-ROM_API rom_status rom_seednet_create(int nx, int ny, int nz, int batch, const float* params,
+ROM_API rom_status rom_seednet_bytes(int nx, int ny, int nz, int batch, int outputs,
+                             int64_t* nparams, size_t* param_bytes, size_t* work_bytes);
+ROM_API rom_status rom_seednet_create(int nx, int ny, int nz, int batch, int outputs,
+                              const float* params,
                               void* param_mem, size_t param_bytes, void* work_mem,
                               size_t work_bytes, rom_seednet** net, void* stream);
 ROM_API rom_status rom_seednet_forward(rom_seednet* net, const float* in, float* out, int batch,
                                void* stream);
-/* Loss and gradient (host array of nparams floats, or NULL) at the current parameters. */
+/* MSE loss and gradient (host array of nparams floats, or NULL) at the current parameters
+ * (one-output networks; ROM_EINVAL otherwise). */
 ROM_API rom_status rom_seednet_gradients(rom_seednet* net, const float* in, const float* target,
                                  int batch, float* grads, double* loss, void* stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch; *loss (if not NULL)
  * receives the loss before the step. */
 ROM_API rom_status rom_seednet_train_step(rom_seednet* net, const float* in, const float* target,
                                   int batch, float lr, double* loss, void* stream);
+/* Gradient of any loss of the outputs: dy = d loss / d y (device FP32, [batch][outputs][N])
+ * at the outputs of `in` is propagated back through the network; the parameter gradient
+ * is kept for rom_seednet_adam and copied to grads (host, nparams floats) if not NULL. */
+ROM_API rom_status rom_seednet_backward(rom_seednet* net, const float* in, const float* dy,
+                                        int batch, float* grads, void* stream);
+/* One Adam step with the gradient of the last rom_seednet_backward. */
+ROM_API rom_status rom_seednet_adam(rom_seednet* net, float lr, void* stream);
 ROM_API rom_status rom_seednet_params(const rom_seednet* net, float* params, void* stream);
 /* Network inputs for `count` right-hand sides (unit columns at nodes idx[], host) at the
  * parameter point p of operator op: out (device FP32 [count][3][N]) receives
- * (mu(p) - mu0) / 0.03, log(D / 0.03) and the indicator of node idx[b].
+ * (mu(p) - mu0) / 0.03, log(D / 0.03) and the indicator of node idx[b] (all zero for
+ * idx[b] = -1: the point-only input of the recycle-vector network).
  * scratch: device, >= 8 (N + count) bytes. */
 ROM_API rom_status rom_seednet_inputs(const rom_operator* op, const rom_mu* p, const int64_t* idx,
                               int count, float* out, void* scratch, size_t scratch_bytes,
                               void* stream);
+/* Subspace loss of the recycle-vector network for one parameter point: with N the k <= 16
+ * outputs (device FP32 [k][N], i.e. N x k column-major), X the s solutions of that point
+ * (device FP64, N x s, ld ldx) and x^_c = x_c / ||x_c||,
+ *   loss = (1/s) sum_c ||x^_c - N (N^T N)^{-1} N^T x^_c||^2
+ * (the share of the solutions outside span(N), invariant to N -> N S), and if dY is not
+ * NULL its gradient -(2/s) R (N^T X^)^T (N^T N)^{-1}, R the residual block, into dY (device
+ * FP32 [k][N]).  *loss: host.  ROM_ENOTSPD if the outputs are linearly dependent.
+ * scratch: device, >= rom_subspace_loss_bytes. */
+ROM_API rom_status rom_subspace_loss_bytes(int64_t N, int k, int s, size_t* bytes);
+ROM_API rom_status rom_subspace_loss(const float* Y, int k, const double* X, int64_t N,
+                                     int64_t ldx, int s, double* loss, float* dY, void* scratch,
+                                     size_t scratch_bytes, void* stream);
 /* Training targets: out[b][v] = X[v + b ldx] / max_v |X[v + b ldx]| (device; X FP64, out
  * FP32 [count][N]).  scratch: device, >= 512 count bytes. */
 ROM_API rom_status rom_seednet_targets(const double* X, int64_t N, int64_t ldx, int count,

@@ -186,3 +186,23 @@ def adam(p, g, state, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
         mh = m / (1 - beta1 ** t)
         vh = v / (1 - beta2 ** t)
         p[k] -= lr * mh / (np.sqrt(vh) + eps)
+
+
+def subspace_loss(N: np.ndarray, X: np.ndarray) -> float:
+    """Share of the unit-norm solutions outside span(N): (1/s) sum_c ||x^_c - P x^_c||^2 with
+    x^_c = x_c / ||x_c|| and P the orthogonal projector onto span(N) (N: n x k, X: n x s).
+    The projection is a least-squares fit of each column on N."""
+    Xh = X / np.linalg.norm(X, axis=0)
+    coef = np.linalg.lstsq(N, Xh, rcond=None)[0]
+    R = Xh - N @ coef
+    return float((R * R).sum() / X.shape[1])
+
+
+def subspace_loss_grad(N: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Gradient of subspace_loss w.r.t. N: -(2/s) R (N^T X^)^T (N^T N)^{-1}, with R the
+    residual block (differentiating the projector N (N^T N)^{-1} N^T)."""
+    Xh = X / np.linalg.norm(X, axis=0)
+    G = N.T @ N
+    C = N.T @ Xh
+    R = Xh - N @ np.linalg.solve(G, C)
+    return -2.0 / X.shape[1] * R @ np.linalg.solve(G, C).T

@@ -282,6 +282,28 @@ __global__ void k_cast_cols_f32(int64_t n, const double* __restrict__ in, int64_
     out[off + i] = (float)in[off + i];
 }
 
+// out[i + c*ldo] = (Tout) in[i + c*ldi] for i < n, c = blockIdx.y.
+template <typename Tin, typename Tout>
+__global__ void k_convert_cols(int64_t n, const Tin* __restrict__ in, int64_t ldi,
+                               Tout* __restrict__ out, int64_t ldo) {
+  const Tin* a = in + (int64_t)blockIdx.y * ldi;
+  Tout* b = out + (int64_t)blockIdx.y * ldo;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    b[i] = (Tout)a[i];
+}
+
+// out[:, c] = in[:, c] / sqrt(norm2[c]) (0 where norm2[c] == 0), c = blockIdx.y.
+__global__ void k_scale_cols(int64_t n, const double* __restrict__ in, int64_t ldi,
+                             const double* __restrict__ norm2, double* __restrict__ out,
+                             int64_t ldo) {
+  const double q = norm2[blockIdx.y];
+  const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  const double* a = in + (int64_t)blockIdx.y * ldi;
+  double* b = out + (int64_t)blockIdx.y * ldo;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    b[i] = f * a[i];
+}
+
 // Mixed form, end of an FP32 sweep: g += sigma d; x = x0 + g (FP64).
 __global__ void k_refine_update(int64_t n, double sigma, const float* __restrict__ d,
                                 double* __restrict__ g, const double* __restrict__ x0,
@@ -910,6 +932,30 @@ void launch_cast_cols_f32(int64_t n, int k, const double* in, int64_t ld, float*
   int gx = ceil_div(n, BS);
   if (gx > 512) gx = 512;
   ROM_LAUNCH(k_cast_cols_f32, dim3(gx, k), dim3(BS), 0, st, n, in, ld, out);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_convert_cols(int64_t n, int k, const float* in, int64_t ldi, double* out, int64_t ldo,
+                         hipStream_t st) {
+  if (k <= 0 || n <= 0) return;
+  const int gx = std::min(ceil_div(n, BS), 512);
+  ROM_LAUNCH((k_convert_cols<float, double>), dim3(gx, k), dim3(BS), 0, st, n, in, ldi, out, ldo);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_convert_cols(int64_t n, int k, const double* in, int64_t ldi, float* out, int64_t ldo,
+                         hipStream_t st) {
+  if (k <= 0 || n <= 0) return;
+  const int gx = std::min(ceil_div(n, BS), 512);
+  ROM_LAUNCH((k_convert_cols<double, float>), dim3(gx, k), dim3(BS), 0, st, n, in, ldi, out, ldo);
+  ROM_CHECK_LAUNCH();
+}
+
+void launch_scale_cols(int64_t n, int k, const double* in, int64_t ldi, const double* norm2,
+                       double* out, int64_t ldo, hipStream_t st) {
+  if (k <= 0 || n <= 0) return;
+  const int gx = std::min(ceil_div(n, BS), 512);
+  ROM_LAUNCH(k_scale_cols, dim3(gx, k), dim3(BS), 0, st, n, in, ldi, norm2, out, ldo);
   ROM_CHECK_LAUNCH();
 }
 

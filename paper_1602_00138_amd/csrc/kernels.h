@@ -346,7 +346,8 @@ void launch_seed_relu_bwd(int64_t ne, void* dY, const void* Y, hipStream_t st);
 void launch_seed_add(int64_t ne, void* out, const void* in, hipStream_t st);
 void launch_seed_pack_input(int64_t nvox, int batch, int cin, const float* in, void* X, int Cp,
                             hipStream_t st);
-void launch_seed_unpack_output(int64_t ne, const void* Y, int Cp, float* out, hipStream_t st);
+void launch_seed_unpack_output(int64_t nvox, int batch, int cout, const void* Y, int Cp,
+                               float* out, hipStream_t st);
 void launch_seed_mse(int64_t ne, const void* Y, int Cp, const float* tgt, void* dY,
                      double* partials, double* loss, hipStream_t st);
 void launch_seed_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
@@ -369,6 +370,14 @@ void launch_guess_dir(int64_t n, const float* xg, const double* x0, double* d, h
 // ---- mixed form -----------------------------------------------------------------------
 // out[i] = (float) in[i], i < n.
 void launch_cast_f32(int64_t n, const double* in, float* out, hipStream_t st);
+// out[i + c*ldo] = in[i + c*ldi] converted, for i < n, c < k.
+void launch_convert_cols(int64_t n, int k, const float* in, int64_t ldi, double* out, int64_t ldo,
+                         hipStream_t st);
+void launch_convert_cols(int64_t n, int k, const double* in, int64_t ldi, float* out, int64_t ldo,
+                         hipStream_t st);
+// out[:, c] = in[:, c] / sqrt(norm2[c]) for c < k (norm2 on the device; 0 gives 0).
+void launch_scale_cols(int64_t n, int k, const double* in, int64_t ldi, const double* norm2,
+                       double* out, int64_t ldo, hipStream_t st);
 // out[i + c*ld] = (float) in[i + c*ld] for i < n, c < k.
 void launch_cast_cols_f32(int64_t n, int k, const double* in, int64_t ld, float* out,
                           hipStream_t st);

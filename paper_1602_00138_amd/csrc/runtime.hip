@@ -71,6 +71,9 @@ struct Arena {
   }
 };
 
+constexpr int REC_MAX = 16;        // learned recycle vectors per point
+constexpr double REC_KEEP = 1e-6;  // share of a recycle vector's norm outside V to keep it
+
 // Small control block read back by the host at every decision point.
 struct Ctrl {
   double sc[16];
@@ -274,6 +277,8 @@ class Sequencer {
     tune_ = o.tune != 0;
     graph_ = o.graph != 0;
     guess_ = o.guess;
+    recycle_ = o.recycle;
+    n_rec_ = o.recycle ? o.n_recycle : 0;
     inner_tol_ = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     G_ = std::max(1, std::min(o.group, std::min(G_MAX, n_rhs_)));
   }
@@ -341,10 +346,16 @@ class Sequencer {
     tbuf_ = a.take<double>((size_t)(std::max(cap_, NJ_MAX) + 8) * std::max(G, 2));
     ubuf_ = a.take<double>((size_t)(cap_ + 8) * G);
     cbuf_ = a.take<double>((size_t)(cap_ + 8) * G);
-    tmpl_ = a.take<double>(cap_ + 8);
+    tmpl_ = a.take<double>(std::max(cap_, REC_MAX) + 8);
     tmpr_ = a.take<double>(2 * (cap_ + 8));
     bvals_ = a.take<double>(2 * (cap_ + 8));
     GW_ = a.take<double>(NJ_MAX * NJ_MAX);
+    if (n_rec_ > 0) {
+      rec_ = a.take<double>(ld_ * REC_MAX);
+      rAW_ = a.take<double>(ld_ * REC_MAX);
+      rtb_ = a.take<double>((size_t)(cap_ + 8) * REC_MAX);
+      rub_ = a.take<double>((size_t)(cap_ + 8) * REC_MAX);
+    }
     lwork_ = a.take<double>(linv_rebuild_work(cap_));
     LWinv_ = a.take<double>(NJ_MAX * NJ_MAX * G);
     GWinv_ = a.take<double>(NJ_MAX * NJ_MAX * G);
@@ -651,6 +662,7 @@ class Sequencer {
     if (i > 0)
       for (int sl : extra_[j])
         if (nj < NJ_MAX) cp.p[nj++] = pool_ + (int64_t)sl * ld_;
+    for (int c = 0; c < n_rec_kept_ && nj < NJ_MAX; ++c) cp.p[nj++] = rec_ + (int64_t)c * ld_;
     if (key == w_key_[y] && nj == w_nj_[y]) return nj;
     w_key_[y] = key;
     w_nj_[y] = nj;
@@ -698,6 +710,7 @@ class Sequencer {
       } else {
         rebuild_gi();
       }
+      prepare_recycle(i);
       for (int y = 0; y < G_MAX; ++y) w_key_[y] = -2;
       if (G_ == 1)
         point_sequential(i, X_out);
@@ -716,6 +729,54 @@ class Sequencer {
         }
       }
     }
+  }
+
+  // Learned recycle vectors of point i (FP32, n_rec_ of them), made A_i-orthogonal to V as
+  // it stands at the point start (w <- w - V G_i^{-1} V^T A_i w: the part of w that the
+  // outer Galerkin projection on V cannot supply, which is where every correction of this
+  // point lies) and orthonormal among themselves; a vector keeps its place iff more than
+  // REC_KEEP of its norm survives.  They join U_j of every right-hand side solved at this
+  // point (not V, and not the U_j of later points).
+  void prepare_recycle(int i) {
+    n_rec_kept_ = 0;
+    if (n_rec_ <= 0) return;
+    const int k = n_rec_;
+    launch_convert_cols(n_, k, recycle_ + (int64_t)i * k * n_, n_, rec_, ld_, st_);
+    launch_col_norms(n_, k, rec_, ld_, ctrl_->rn, red_part_, st_);
+    if (m_ > 0) {
+      const int64_t mm = round_up(m_, 2);   // even: the projections read column pairs
+      launch_spmm(S_, diag_i_, rec_, ld_, k, rAW_, st_);
+      launch_proj(Q_, ld_, m_, rAW_, ld_, k, n_, rtb_, mm, gt_part_, st_);    // t = V^T A w
+      launch_proj(Lr_, ldg_, m_, rtb_, mm, k, m_, rub_, mm, gt_part_, st_);   // Linv t
+      launch_proj(Lc_, ldg_, m_, rub_, mm, k, m_, rtb_, mm, gt_part_, st_);   // G^{-1} t
+      launch_gemvn_multi(Q_, ld_, n_, m_, rtb_, mm, k, 1.0, rec_, ld_, -1.0, rec_, ld_, st_);
+    }
+    sync();
+    double gn[REC_MAX];
+    for (int c = 0; c < k; ++c) gn[c] = h_->rn[c];
+    int kk = 0;
+    for (int c = 0; c < k; ++c) {
+      double* w = rec_ + (int64_t)c * ld_;
+      if (kk > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_gemvt(rec_, ld_, n_, kk, w, 0, 1, tmpl_, gt_part_, st_);
+          launch_gemvn(rec_, ld_, n_, kk, tmpl_, 1.0, w, -1.0, w, &ctrl_->sc[4], red_part_, st_);
+        }
+      } else {
+        launch_col_norms(n_, 1, w, ld_, &ctrl_->sc[4], red_part_, st_);
+      }
+      sync();
+      const double a = h_->sc[4], b = gn[c];
+      const double rho = (b > 0.0 && std::isfinite(a) && std::isfinite(b)) ? std::sqrt(a / b) : 0.0;
+      if (rho > REC_KEEP) {
+        double* slot = rec_ + (int64_t)kk * ld_;
+        if (slot != w)
+          ROM_HIP(hipMemcpyAsync(slot, w, sizeof(double) * n_, hipMemcpyDeviceToDevice, st_));
+        launch_normalize(n_, slot, &ctrl_->sc[4], st_);
+        ++kk;
+      }
+    }
+    n_rec_kept_ = kk;
   }
 
   // Bookkeeping of a solved right-hand side: iterations, final residual, convergence.
@@ -1532,6 +1593,12 @@ class Sequencer {
   bool tune_ = false;
   bool graph_ = false;
   const float* guess_ = nullptr;   // per (point, RHS) initial guesses (FP32, N each)
+  const float* recycle_ = nullptr; // per point learned recycle vectors (FP32, N each)
+  int n_rec_ = 0, n_rec_kept_ = 0;
+  double* rec_ = nullptr;          // the current point's kept recycle vectors (ld x REC_MAX)
+  double* rAW_ = nullptr;          // A_i times them
+  double* rtb_ = nullptr;          // V^T A_i w, then G_i^{-1} V^T A_i w
+  double* rub_ = nullptr;
   const double* xbase_ = nullptr;  // base point of the current inner solve
   using GraphKey = std::tuple<int, int, int, int, int, const void*>;
   std::map<GraphKey, hipGraphExec_t> graphs_;
@@ -1592,6 +1659,8 @@ void check_opts(const rom_opts* o) {
   if (o->tune != 0 && o->tune != 1) throw Error(ROM_EINVAL, "tune must be 0 or 1");
   if (o->graph != 0 && o->graph != 1) throw Error(ROM_EINVAL, "graph must be 0 or 1");
   if (o->guess && o->group > 1) throw Error(ROM_EINVAL, "initial guesses need group <= 1");
+  if (o->recycle && (o->n_recycle < 1 || o->n_recycle > REC_MAX))
+    throw Error(ROM_EINVAL, "n_recycle must be in [1, 16]");
 }
 
 void check_counts(int n_src, int n_det, int k_u, int K) {
@@ -1803,7 +1872,7 @@ rom_status rom_seednet_inputs(const rom_operator* op, const rom_mu* p, const int
     if (count < 1) throw Error(ROM_EINVAL, "count must be >= 1");
     rom::check_mu(p, op->grid.dim);
     for (int b = 0; b < count; ++b)
-      if (idx[b] < 0 || idx[b] >= op->n) throw Error(ROM_EINVAL, "node index out of range");
+      if (idx[b] < -1 || idx[b] >= op->n) throw Error(ROM_EINVAL, "node index out of range");
     if (scratch_bytes < 8 * (size_t)(op->n + count)) throw Error(ROM_ECAPACITY, "scratch too small");
     if ((uintptr_t)scratch % 8) throw Error(ROM_EINVAL, "scratch must be 8-byte aligned");
     hipStream_t st = (hipStream_t)stream;
@@ -1814,6 +1883,111 @@ rom_status rom_seednet_inputs(const rom_operator* op, const rom_mu* p, const int
     rom::launch_seed_inputs(op->n, count, dmu, 0.03, op->var ? op->Dfield : nullptr, op->Dc, 0.03,
                             didx, out, st);
     ROM_HIP(hipStreamSynchronize(st));   // idx is pageable host memory
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+namespace rom {
+namespace {
+
+constexpr int SUBSPACE_MAX = 16;   // network outputs (recycle vectors) per sample
+
+struct SubspaceLayout {
+  double *Nd, *Xn, *R, *dN, *G, *Linv, *Ginv, *C, *T, *Z, *n2, *part;
+  int* status;
+  int64_t ld;
+  size_t bytes;
+};
+
+SubspaceLayout subspace_layout(int64_t N, int k, int s, void* base) {
+  Arena a(base);
+  SubspaceLayout L;
+  L.ld = round_up(N, 64);
+  L.Nd = a.take<double>(L.ld * k);
+  L.Xn = a.take<double>(L.ld * s);
+  L.R = a.take<double>(L.ld * s);
+  L.dN = a.take<double>(L.ld * k);
+  L.G = a.take<double>(k * k);
+  L.Linv = a.take<double>(k * k);
+  L.Ginv = a.take<double>(k * k);
+  L.C = a.take<double>((size_t)k * s);
+  L.T = a.take<double>((size_t)k * s);
+  L.Z = a.take<double>((size_t)s * k);
+  L.n2 = a.take<double>(s);
+  L.part = a.take<double>(std::max<size_t>({gram_partials(k, k, N, true),
+                                            gram_partials(k, s, N, false), (size_t)256 * s}));
+  L.status = a.take<int>(4);
+  L.bytes = a.off + ALIGN;
+  return L;
+}
+
+}  // namespace
+}  // namespace rom
+
+rom_status rom_subspace_loss_bytes(int64_t N, int k, int s, size_t* bytes) {
+  try {
+    if (!bytes) throw Error(ROM_EINVAL, "null argument");
+    if (N < 1 || k < 1 || k > rom::SUBSPACE_MAX || s < 1) throw Error(ROM_EINVAL, "bad sizes");
+    *bytes = rom::subspace_layout(N, k, s, nullptr).bytes;
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_subspace_loss(const float* Y, int k, const double* X, int64_t N, int64_t ldx, int s,
+                             double* loss, float* dY, void* scratch, size_t scratch_bytes,
+                             void* stream) {
+  try {
+    if (!Y || !X || !loss) throw Error(ROM_EINVAL, "null argument");
+    if (N < 1 || k < 1 || k > rom::SUBSPACE_MAX || s < 1 || ldx < N)
+      throw Error(ROM_EINVAL, "bad sizes");
+    const rom::SubspaceLayout L = rom::subspace_layout(N, k, s, scratch);
+    if (!scratch || scratch_bytes < L.bytes) throw Error(ROM_ECAPACITY, "scratch too small");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t ld = L.ld;
+    // N (FP64) and the unit-norm targets
+    rom::launch_convert_cols(N, k, Y, N, L.Nd, ld, st);
+    rom::launch_col_norms(N, s, X, ldx, L.n2, L.part, st);
+    rom::launch_scale_cols(N, s, X, ldx, L.n2, L.Xn, ld, st);
+    // G = N^T N, C = N^T X^, G^{-1}; T = G^{-1} C; R = X^ - N T
+    rom::launch_gram(L.Nd, ld, k, L.Nd, ld, k, N, nullptr, true, nullptr, 0, 0.0, L.G, k, L.part,
+                     st);
+    rom::launch_gram(L.Nd, ld, k, L.Xn, ld, s, N, nullptr, false, nullptr, 0, 0.0, L.C, k, L.part,
+                     st);
+    ROM_HIP(hipMemsetAsync(L.status, 0, sizeof(int), st));
+    rom::launch_small_chol_inv(L.G, k, L.Linv, L.Ginv, L.status, st);
+    rom::launch_gemm(k, s, k, 1.0, L.Ginv, k, false, L.C, k, false, 0.0, nullptr, 0, L.T, k, st);
+    for (int c = 0; c < s; c += 16)
+      rom::launch_gemvn_multi(L.Nd, ld, N, k, L.T + (size_t)c * k, k, std::min(16, s - c), 1.0,
+                              L.Xn + c * ld, ld, -1.0, L.R + c * ld, ld, st);
+    // loss = sum_c ||R_c||^2 / s
+    rom::launch_col_norms(N, s, L.R, ld, L.n2, L.part, st);
+    std::vector<double> r2(s), hG((size_t)k * k), hL((size_t)k * k);
+    int status = 0;
+    ROM_HIP(hipMemcpyAsync(r2.data(), L.n2, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    ROM_HIP(hipMemcpyAsync(&status, L.status, sizeof(int), hipMemcpyDeviceToHost, st));
+    ROM_HIP(hipMemcpyAsync(hG.data(), L.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    ROM_HIP(hipMemcpyAsync(hL.data(), L.Linv, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    ROM_HIP(hipStreamSynchronize(st));
+    // pivot c of the Cholesky factorisation of G is 1 / Linv[c][c]^2: an output whose pivot
+    // is below 1e-12 of its own squared norm lies in the span of the outputs before it
+    for (int c = 0; c < k && !status; ++c) {
+      const double l = hL[c + (size_t)c * k];
+      if (!(l * l * hG[c + (size_t)c * k] < 1e12)) status = 1;
+    }
+    if (status) throw Error(ROM_ENOTSPD, "subspace loss: the outputs are linearly dependent");
+    double tot = 0.0;
+    for (int c = 0; c < s; ++c) tot += r2[c];
+    *loss = tot / s;
+    if (dY) {
+      // d loss / d N = -(2/s) R C^T G^{-1}
+      rom::launch_gemm(s, k, k, 1.0, L.C, k, true, L.Ginv, k, false, 0.0, nullptr, 0, L.Z, s, st);
+      rom::launch_gemvn_multi(L.R, ld, N, s, L.Z, s, k, 0.0, nullptr, 0, -2.0 / s, L.dN, ld, st);
+      rom::launch_convert_cols(N, k, L.dN, ld, dY, N, st);
+    }
     return ROM_OK;
   } catch (const Error& e) {
     return rom::fail(e);

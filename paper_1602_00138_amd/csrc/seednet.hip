@@ -332,11 +332,16 @@ __global__ void k_pack_input(int64_t nvox, int batch, int cin, const float* __re
   X[e] = (__bf16)(c < cin ? in[(b * cin + c) * nvox + v] : 0.f);
 }
 
-// Channel 0 of the output -> FP32 [b][v]
-__global__ void k_unpack_output(int64_t ne, const __bf16* __restrict__ Y, int Cp,
-                                float* __restrict__ out) {
+// Output channels c < cout of [b v][Cp] -> FP32 [b][c][v]
+__global__ void k_unpack_output(int64_t nvox, int batch, int cout, const __bf16* __restrict__ Y,
+                                int Cp, float* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (e < ne) out[e] = (float)Y[e * Cp];
+  if (e >= nvox * batch * cout) return;
+  const int64_t v = e % nvox;
+  const int64_t bc = e / nvox;
+  const int c = (int)(bc % cout);
+  const int64_t b = bc / cout;
+  out[e] = (float)Y[(b * nvox + v) * Cp + c];
 }
 
 // MSE on channel 0: partial sums of (y - t)^2 / count per block, dY = 2 (y - t) / count.
@@ -550,8 +555,10 @@ void launch_seed_pack_input(int64_t nvox, int batch, int cin, const float* in, v
   ROM_CHECK_LAUNCH();
 }
 
-void launch_seed_unpack_output(int64_t ne, const void* Y, int Cp, float* out, hipStream_t st) {
-  ROM_LAUNCH(k_unpack_output, dim3(gridn(ne)), dim3(BS), 0, st, ne, (const __bf16*)Y, Cp, out);
+void launch_seed_unpack_output(int64_t nvox, int batch, int cout, const void* Y, int Cp,
+                               float* out, hipStream_t st) {
+  ROM_LAUNCH(k_unpack_output, dim3(gridn(nvox * batch * cout)), dim3(BS), 0, st, nvox, batch, cout,
+             (const __bf16*)Y, Cp, out);
   ROM_CHECK_LAUNCH();
 }
 

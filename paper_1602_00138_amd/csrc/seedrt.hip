@@ -14,9 +14,9 @@ struct rom_seednet;
 namespace rom {
 namespace {
 
-constexpr int CIN = 3;    // input fields
-constexpr int COUT = 1;   // output channels (the guess)
-constexpr int NL = 8;     // layers
+constexpr int CIN = 3;        // input fields
+constexpr int COUT_MAX = 16;  // output channels: 1 for the guess, up to 16 recycle vectors
+constexpr int NL = 8;         // layers
 
 struct Layer {
   const char* name;
@@ -25,7 +25,7 @@ struct Layer {
 // encoder e0..e3, decoder d2..d0, head (order of the flat parameter vector)
 const Layer LAYERS[NL] = {{"e0", CIN, 16, 0}, {"e1", 16, 32, 1}, {"e2", 32, 48, 2},
                           {"e3", 48, 64, 3},  {"d2", 64, 48, 2}, {"d1", 48, 32, 1},
-                          {"d0", 32, 16, 0},  {"head", 16, COUT, 0}};
+                          {"d0", 32, 16, 0},  {"head", 16, 1, 0}};   // head width: per network
 
 int rows16(int c) { return (c + 15) / 16 * 16; }
 
@@ -47,6 +47,8 @@ struct Arena2 {
 
 struct rom_seednet {
   int nx, ny, nz, maxb;
+  int cout;                  // output channels
+  rom::Layer L[rom::NL];     // the layer table with this network's head width
   int64_t nparams;
   // parameters (FP32 master, oracle order), gradients, Adam moments
   float *P, *G, *M, *V;
@@ -67,18 +69,23 @@ struct rom_seednet {
 namespace rom {
 namespace {
 
-size_t layout(rom_seednet* net, int nx, int ny, int nz, int maxb, void* pmem, void* wmem,
-              size_t* pbytes, size_t* wbytes) {
+size_t layout(rom_seednet* net, int nx, int ny, int nz, int maxb, int cout, void* pmem,
+              void* wmem, size_t* pbytes, size_t* wbytes) {
   if (nx % 8 || ny % 8 || nz % 8 || nx < 8 || ny < 8 || nz < 8)
     throw Error(ROM_EINVAL, "seed network: grid sizes must be positive multiples of 8");
   if (maxb < 1) throw Error(ROM_EINVAL, "seed network: batch must be >= 1");
+  if (cout < 1 || cout > COUT_MAX) throw Error(ROM_EINVAL, "seed network: 1 <= outputs <= 16");
+  Layer table[NL];   // this network's layers: the fixed table with its head width
+  for (int l = 0; l < NL; ++l) table[l] = LAYERS[l];
+  table[NL - 1].cout = cout;
+  const int ycp = seed_round8(cout);   // channel slots of the output and its gradient
   int64_t np = 0;
   int64_t woff[NL], boff[NL];
   for (int l = 0; l < NL; ++l) {
     woff[l] = np;
-    np += (int64_t)LAYERS[l].cout * LAYERS[l].cin * 27;
+    np += (int64_t)table[l].cout * table[l].cin * 27;
     boff[l] = np;
-    np += LAYERS[l].cout;
+    np += table[l].cout;
   }
   Arena2 pa(pmem);
   float* P = pa.take<float>(np);
@@ -91,7 +98,7 @@ size_t layout(rom_seednet* net, int nx, int ny, int nz, int maxb, void* pmem, vo
   const int64_t nl[4] = {n0, n0 / 8, n0 / 64, n0 / 512};
   size_t part = 0;
   for (int l = 0; l < NL; ++l) {
-    const Layer& L = LAYERS[l];
+    const Layer& L = table[l];
     const int cpi = seed_round8(L.cin), cpo = seed_round8(L.cout);
     const int kp = seed_kp(cpi), r = rows16(L.cout), ktp = seed_kp(cpo), rt = rows16(L.cin);
     if (net) {
@@ -122,13 +129,15 @@ size_t layout(rom_seednet* net, int nx, int ny, int nz, int maxb, void* pmem, vo
   // the decoder inputs (upsampled e3, d2, d1) are never formed: the layers read them
   void *x = act(0, 8), *e0 = act(0, 16), *p1 = act(1, 16), *e1 = act(1, 32), *p2 = act(2, 32),
        *e2 = act(2, 48), *p3 = act(3, 48), *e3 = act(3, 64), *d2 = act(2, 48), *d1 = act(1, 32),
-       *d0 = act(0, 16), *y = act(0, 8);
+       *d0 = act(0, 16), *y = act(0, ycp);
   void *ge0 = act(0, 16), *gp1 = act(1, 16), *ge1 = act(1, 32), *gp2 = act(2, 32),
        *ge2 = act(2, 48), *gp3 = act(3, 48), *ge3 = act(3, 64), *gu2 = act(2, 64),
        *gd2 = act(2, 48), *gu1 = act(1, 48), *gd1 = act(1, 32), *gu0 = act(0, 32),
-       *gd0 = act(0, 16), *gy = act(0, 8);
+       *gd0 = act(0, 16), *gy = act(0, ycp);
   *wbytes = a.off + 256;
   if (net) {
+    net->cout = cout;
+    for (int l = 0; l < NL; ++l) net->L[l] = table[l];
     net->nx = nx;
     net->ny = ny;
     net->nz = nz;
@@ -155,7 +164,7 @@ size_t layout(rom_seednet* net, int nx, int ny, int nz, int maxb, void* pmem, vo
 
 void pack_all(rom_seednet* n, hipStream_t st) {
   for (int l = 0; l < NL; ++l)
-    launch_seed_pack_weights(n->P + n->woff[l], LAYERS[l].cout, LAYERS[l].cin, n->Cpi[l],
+    launch_seed_pack_weights(n->P + n->woff[l], n->L[l].cout, n->L[l].cin, n->Cpi[l],
                              n->Kp[l], n->rows[l], n->Wb[l], n->Cpo[l], n->Ktp[l], n->rowst[l],
                              n->Wt[l], st);
 }
@@ -164,27 +173,27 @@ void pack_all(rom_seednet* n, hipStream_t st) {
 // on the next coarser level and the layer reads its upsampling)
 void conv(rom_seednet* n, int l, int b, const void* X, const void* skip, bool relu, void* Y,
           hipStream_t st, bool up = false) {
-  const int lev = LAYERS[l].level;
+  const int lev = n->L[l].level;
   launch_seed_conv(n->nx >> lev, n->ny >> lev, n->nz >> lev, b, X, n->Cpi[l], n->Wb[l], n->Kp[l],
-                   LAYERS[l].cout, n->rows[l], n->P + n->boff[l], skip, relu ? 1 : 0, Y,
+                   n->L[l].cout, n->rows[l], n->P + n->boff[l], skip, relu ? 1 : 0, Y,
                    n->Cpo[l], st, up ? 1 : 0);
 }
 
 // data gradient of layer l: dX = conv(dZ; flipped, transposed weights)
 void conv_dx(rom_seednet* n, int l, int b, const void* dZ, void* dX, hipStream_t st) {
-  const int lev = LAYERS[l].level;
+  const int lev = n->L[l].level;
   launch_seed_conv(n->nx >> lev, n->ny >> lev, n->nz >> lev, b, dZ, n->Cpo[l], n->Wt[l],
-                   n->Ktp[l], LAYERS[l].cin, n->rowst[l], nullptr, nullptr, 0, dX, n->Cpi[l], st);
+                   n->Ktp[l], n->L[l].cin, n->rowst[l], nullptr, nullptr, 0, dX, n->Cpi[l], st);
 }
 
 // weight and bias gradients of layer l (added into G; up as for the forward)
 void conv_dw(rom_seednet* n, int l, int b, const void* X, const void* dZ, hipStream_t st,
              bool up = false) {
-  const int lev = LAYERS[l].level;
+  const int lev = n->L[l].level;
   launch_seed_wgrad(n->nx >> lev, n->ny >> lev, n->nz >> lev, b, X, n->Cpi[l], dZ, n->Cpo[l],
-                    LAYERS[l].cout, n->rows[l], n->Kp[l], n->part, n->dWg[l], n->partb,
+                    n->L[l].cout, n->rows[l], n->Kp[l], n->part, n->dWg[l], n->partb,
                     n->G + n->boff[l], st, up ? 1 : 0);
-  launch_seed_unpack_wgrad(n->dWg[l], n->Kp[l], LAYERS[l].cout, LAYERS[l].cin, n->Cpi[l],
+  launch_seed_unpack_wgrad(n->dWg[l], n->Kp[l], n->L[l].cout, n->L[l].cin, n->Cpi[l],
                            n->G + n->woff[l], st);
 }
 
@@ -209,10 +218,9 @@ void forward(rom_seednet* n, const float* in, int b, hipStream_t st) {
   conv(n, 7, b, n->d0, nullptr, false, n->y, st);
 }
 
-// loss (into n->loss[0]) and gradients added into G (the caller zeros G)
-void backward(rom_seednet* n, const float* target, int b, hipStream_t st) {
+// gradients of every layer added into G (the caller zeros G) from the output gradient in gy
+void backward_layers(rom_seednet* n, int b, hipStream_t st) {
   const int nx = n->nx, ny = n->ny, nz = n->nz;
-  launch_seed_mse(nvox(n, 0, b), n->y, 8, target, n->gy, n->lpart, n->loss, st);
   // head (no activation)
   conv_dw(n, 7, b, n->d0, n->gy, st);
   conv_dx(n, 7, b, n->gy, n->gd0, st);
@@ -254,9 +262,27 @@ void backward(rom_seednet* n, const float* target, int b, hipStream_t st) {
   conv_dw(n, 0, b, n->x, n->ge0, st);
 }
 
+// MSE loss of the single output channel (into n->loss[0]) and gradients added into G
+void backward(rom_seednet* n, const float* target, int b, hipStream_t st) {
+  launch_seed_mse(nvox(n, 0, b), n->y, n->Cpo[NL - 1], target, n->gy, n->lpart, n->loss, st);
+  backward_layers(n, b, st);
+}
+
+void adam_step(rom_seednet* n, float lr, hipStream_t st) {
+  n->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
+  launch_seed_adam(n->nparams, n->P, n->G, n->M, n->V, lr, b1, b2, c1, c2, 1e-8f, st);
+  pack_all(n, st);
+}
+
 void check_batch(const rom_seednet* n, int b) {
   if (!n) throw Error(ROM_EINVAL, "null network");
   if (b < 1 || b > n->maxb) throw Error(ROM_EINVAL, "batch out of range");
+}
+
+void check_single(const rom_seednet* n) {
+  if (n->cout != 1) throw Error(ROM_EINVAL, "the MSE loss needs a network with one output");
 }
 
 }  // namespace
@@ -266,30 +292,30 @@ using rom::Error;
 
 extern "C" {
 
-rom_status rom_seednet_bytes(int nx, int ny, int nz, int batch, int64_t* nparams,
+rom_status rom_seednet_bytes(int nx, int ny, int nz, int batch, int outputs, int64_t* nparams,
                              size_t* param_bytes, size_t* work_bytes) {
   try {
     if (!nparams || !param_bytes || !work_bytes) throw Error(ROM_EINVAL, "null argument");
-    *nparams = (int64_t)rom::layout(nullptr, nx, ny, nz, batch, nullptr, nullptr, param_bytes,
-                                    work_bytes);
+    *nparams = (int64_t)rom::layout(nullptr, nx, ny, nz, batch, outputs, nullptr, nullptr,
+                                    param_bytes, work_bytes);
     return ROM_OK;
   } catch (const Error& e) {
     return rom::report(e);
   }
 }
 
-rom_status rom_seednet_create(int nx, int ny, int nz, int batch, const float* params,
+rom_status rom_seednet_create(int nx, int ny, int nz, int batch, int outputs, const float* params,
                               void* param_mem, size_t param_bytes, void* work_mem,
                               size_t work_bytes, rom_seednet** net, void* stream) {
   try {
     if (!params || !param_mem || !work_mem || !net) throw Error(ROM_EINVAL, "null argument");
     size_t pb = 0, wb = 0;
-    rom::layout(nullptr, nx, ny, nz, batch, nullptr, nullptr, &pb, &wb);
+    rom::layout(nullptr, nx, ny, nz, batch, outputs, nullptr, nullptr, &pb, &wb);
     if (param_bytes < pb || work_bytes < wb) throw Error(ROM_ECAPACITY, "buffers too small");
     if ((uintptr_t)param_mem % 256 || (uintptr_t)work_mem % 256)
       throw Error(ROM_EINVAL, "buffers must be 256-byte aligned");
     rom_seednet* n = new rom_seednet;
-    rom::layout(n, nx, ny, nz, batch, param_mem, work_mem, &pb, &wb);
+    rom::layout(n, nx, ny, nz, batch, outputs, param_mem, work_mem, &pb, &wb);
     hipStream_t st = (hipStream_t)stream;
     try {
       ROM_HIP(hipHostMalloc((void**)&n->hloss, sizeof(double), hipHostMallocDefault));
@@ -316,7 +342,8 @@ rom_status rom_seednet_forward(rom_seednet* net, const float* in, float* out, in
     if (!in || !out) throw Error(ROM_EINVAL, "null input or output");
     hipStream_t st = (hipStream_t)stream;
     rom::forward(net, in, batch, st);
-    rom::launch_seed_unpack_output(rom::nvox(net, 0, batch), net->y, 8, out, st);
+    rom::launch_seed_unpack_output(rom::nvox(net, 0, 1), batch, net->cout, net->y,
+                                   net->Cpo[rom::NL - 1], out, st);
     return ROM_OK;
   } catch (const Error& e) {
     return rom::report(e);
@@ -328,6 +355,7 @@ rom_status rom_seednet_gradients(rom_seednet* net, const float* in, const float*
   try {
     rom::check_batch(net, batch);
     if (!in || !target) throw Error(ROM_EINVAL, "null input or target");
+    rom::check_single(net);
     hipStream_t st = (hipStream_t)stream;
     ROM_HIP(hipMemsetAsync(net->G, 0, net->nparams * sizeof(float), st));
     rom::forward(net, in, batch, st);
@@ -349,21 +377,49 @@ rom_status rom_seednet_train_step(rom_seednet* net, const float* in, const float
     rom::check_batch(net, batch);
     if (!in || !target) throw Error(ROM_EINVAL, "null input or target");
     if (!(lr > 0.f)) throw Error(ROM_EINVAL, "learning rate must be > 0");
+    rom::check_single(net);
     hipStream_t st = (hipStream_t)stream;
     ROM_HIP(hipMemsetAsync(net->G, 0, net->nparams * sizeof(float), st));
     rom::forward(net, in, batch, st);
     rom::backward(net, target, batch, st);
-    net->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - std::pow(b1, (float)net->step), c2 = 1.f - std::pow(b2, (float)net->step);
-    rom::launch_seed_adam(net->nparams, net->P, net->G, net->M, net->V, lr, b1, b2, c1, c2, 1e-8f,
-                          st);
-    rom::pack_all(net, st);
+    rom::adam_step(net, lr, st);
     if (loss) {
       ROM_HIP(hipMemcpyAsync(net->hloss, net->loss, sizeof(double), hipMemcpyDeviceToHost, st));
       ROM_HIP(hipStreamSynchronize(st));
       *loss = *net->hloss;
     }
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::report(e);
+  }
+}
+
+rom_status rom_seednet_backward(rom_seednet* net, const float* in, const float* dy, int batch,
+                                float* grads, void* stream) {
+  try {
+    rom::check_batch(net, batch);
+    if (!in || !dy) throw Error(ROM_EINVAL, "null input or output gradient");
+    hipStream_t st = (hipStream_t)stream;
+    ROM_HIP(hipMemsetAsync(net->G, 0, net->nparams * sizeof(float), st));
+    rom::forward(net, in, batch, st);
+    rom::launch_seed_pack_input(rom::nvox(net, 0, 1), batch, net->cout, dy, net->gy,
+                                net->Cpo[rom::NL - 1], st);
+    rom::backward_layers(net, batch, st);
+    if (grads) {
+      ROM_HIP(hipMemcpyAsync(grads, net->G, net->nparams * sizeof(float), hipMemcpyDeviceToHost, st));
+      ROM_HIP(hipStreamSynchronize(st));
+    }
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::report(e);
+  }
+}
+
+rom_status rom_seednet_adam(rom_seednet* net, float lr, void* stream) {
+  try {
+    if (!net) throw Error(ROM_EINVAL, "null network");
+    if (!(lr > 0.f)) throw Error(ROM_EINVAL, "learning rate must be > 0");
+    rom::adam_step(net, lr, (hipStream_t)stream);
     return ROM_OK;
   } catch (const Error& e) {
     return rom::report(e);

@@ -72,9 +72,16 @@ class Problem:
               maxit: int = 0, check_every: int = 0, timing: int = 0,
               keep_X: bool = True, precision: int = R.ROM_PREC_FP64,
               inner_tol: float = 0.0, group: int = 0, tune: int = 0,
-              graph: int = 0, guess: Optional[torch.Tensor] = None) -> SequenceResult:
+              graph: int = 0, guess: Optional[torch.Tensor] = None,
+              recycle: Optional[torch.Tensor] = None) -> SequenceResult:
+        """recycle: (K, n_recycle, N) FP32 learned recycle vectors per point (they join the
+        recycle spaces U_j at their point), or None."""
+        if recycle is not None:
+            assert recycle.dim() == 3 and recycle.shape[0] == len(points) and \
+                recycle.shape[2] == self.n and recycle.dtype == torch.float32
+            recycle = recycle.contiguous()
         opts = R.make_opts(tol, trunc, cap, maxit, check_every, timing, precision, inner_tol,
-                           group, tune, graph, guess)
+                           group, tune, graph, guess, recycle)
         K = len(points)
         nbytes = R.rom_sequence_bytes(self.op, self.src_idx.size, self.det_idx.size, self.k_u, K, opts)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -42,7 +42,9 @@ EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator",
             "rom_reduced_response_bytes", "rom_reduced_response", "rom_basis_dims",
             "rom_basis_copy", "rom_operator_destroy", "rom_basis_destroy", "rom_last_error",
             "rom_seednet_bytes", "rom_seednet_create", "rom_seednet_forward",
-            "rom_seednet_gradients", "rom_seednet_train_step", "rom_seednet_params",
+            "rom_seednet_gradients", "rom_seednet_train_step", "rom_seednet_backward",
+            "rom_seednet_adam", "rom_seednet_params", "rom_subspace_loss_bytes",
+            "rom_subspace_loss",
             "rom_seednet_destroy", "rom_seednet_inputs", "rom_seednet_targets"]
 
 
@@ -60,7 +62,7 @@ class rom_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("inner_tol", C.c_double),
                 ("cap", C.c_int), ("maxit", C.c_int), ("check_every", C.c_int), ("timing", C.c_int),
                 ("precision", C.c_int), ("group", C.c_int), ("tune", C.c_int), ("graph", C.c_int),
-                ("guess", C.c_void_p)]
+                ("guess", C.c_void_p), ("recycle", C.c_void_p), ("n_recycle", C.c_int)]
 
 
 class rom_record(C.Structure):
@@ -130,10 +132,15 @@ def _load():
         "rom_operator_destroy": (None, [vp]),
         "rom_basis_destroy": (None, [vp]),
         "rom_last_error": (C.c_char_p, []),
-        "rom_seednet_bytes": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_int64), P(sz),
-                                        P(sz)]),
-        "rom_seednet_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_float), vp, sz,
-                                         vp, sz, P(vp), vp]),
+        "rom_seednet_bytes": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_int64),
+                                        P(sz), P(sz)]),
+        "rom_seednet_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_float),
+                                         vp, sz, vp, sz, P(vp), vp]),
+        "rom_seednet_backward": (C.c_int, [vp, vp, vp, C.c_int, P(C.c_float), vp]),
+        "rom_seednet_adam": (C.c_int, [vp, C.c_float, vp]),
+        "rom_subspace_loss_bytes": (C.c_int, [C.c_int64, C.c_int, C.c_int, P(sz)]),
+        "rom_subspace_loss": (C.c_int, [vp, C.c_int, vp, C.c_int64, C.c_int64, C.c_int,
+                                        P(C.c_double), vp, vp, sz, vp]),
         "rom_seednet_forward": (C.c_int, [vp, vp, vp, C.c_int, vp]),
         "rom_seednet_gradients": (C.c_int, [vp, vp, vp, C.c_int, P(C.c_float), P(C.c_double), vp]),
         "rom_seednet_train_step": (C.c_int, [vp, vp, vp, C.c_int, C.c_float, P(C.c_double), vp]),
@@ -192,12 +199,14 @@ def make_grid(dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float) -> 
 def make_opts(tol: float, trunc: float = 1e-8, cap: int = 0, maxit: int = 0,
               check_every: int = 0, timing: int = 0, precision: int = ROM_PREC_FP64,
               inner_tol: float = 0.0, group: int = 0, tune: int = 0, graph: int = 0,
-              guess=None) -> rom_opts:
-    """guess: device FP32 tensor (K * n_rhs, N) of initial guesses, or None (kept alive by
-    the caller during the solve)."""
+              guess=None, recycle=None) -> rom_opts:
+    """guess: device FP32 tensor (K * n_rhs, N) of initial guesses, or None; recycle: device
+    FP32 tensor (K, n_recycle, N) of learned recycle vectors per point, or None (both kept
+    alive by the caller during the solve)."""
+    nrec = int(recycle.shape[1]) if recycle is not None else 0
     return rom_opts(float(tol), float(trunc), float(inner_tol), int(cap), int(maxit),
                     int(check_every), int(timing), int(precision), int(group), int(tune),
-                    int(graph), _ptr(guess))
+                    int(graph), _ptr(guess), _ptr(recycle), nrec)
 
 
 @dataclass
@@ -441,17 +450,19 @@ def stats_dict(st: rom_stats) -> dict:
 
 # ---- learned seed network ---------------------------------------------------------------
 
-def rom_seednet_bytes(nx: int, ny: int, nz: int, batch: int):
+def rom_seednet_bytes(nx: int, ny: int, nz: int, batch: int, outputs: int = 1):
     npar, pb, wb = C.c_int64(), C.c_size_t(), C.c_size_t()
-    _check(_lib.rom_seednet_bytes(nx, ny, nz, batch, C.byref(npar), C.byref(pb), C.byref(wb)))
+    _check(_lib.rom_seednet_bytes(nx, ny, nz, batch, outputs, C.byref(npar), C.byref(pb),
+                                  C.byref(wb)))
     return npar.value, pb.value, wb.value
 
 
 def rom_seednet_create(nx: int, ny: int, nz: int, batch: int, params: np.ndarray, param_mem,
-                       work_mem, stream=None) -> int:
+                       work_mem, stream=None, outputs: int = 1) -> int:
     params = np.ascontiguousarray(params, dtype=np.float32)
     net = C.c_void_p()
-    _check(_lib.rom_seednet_create(nx, ny, nz, batch, params.ctypes.data_as(C.POINTER(C.c_float)),
+    _check(_lib.rom_seednet_create(nx, ny, nz, batch, outputs,
+                                   params.ctypes.data_as(C.POINTER(C.c_float)),
                                    _ptr(param_mem), param_mem.numel() * param_mem.element_size(),
                                    _ptr(work_mem), work_mem.numel() * work_mem.element_size(),
                                    C.byref(net), _stream(stream)))
@@ -475,6 +486,34 @@ def rom_seednet_train_step(net: int, inputs, targets, batch: int, lr: float, str
     loss = C.c_double()
     _check(_lib.rom_seednet_train_step(net, _ptr(inputs), _ptr(targets), batch, float(lr),
                                        C.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def rom_seednet_backward(net: int, inputs, dy, batch: int, nparams: int = 0, stream=None):
+    """Parameter gradient of a loss whose output gradient is dy (returned if nparams > 0)."""
+    g = np.empty(nparams, dtype=np.float32) if nparams > 0 else None
+    _check(_lib.rom_seednet_backward(net, _ptr(inputs), _ptr(dy), batch,
+                                     g.ctypes.data_as(C.POINTER(C.c_float)) if g is not None
+                                     else None, _stream(stream)))
+    return g
+
+
+def rom_seednet_adam(net: int, lr: float, stream=None) -> None:
+    _check(_lib.rom_seednet_adam(net, float(lr), _stream(stream)))
+
+
+def rom_subspace_loss_bytes(N: int, k: int, s: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.rom_subspace_loss_bytes(int(N), int(k), int(s), C.byref(out)))
+    return int(out.value)
+
+
+def rom_subspace_loss(Y, k: int, X, N: int, ldx: int, s: int, dY, scratch, stream=None) -> float:
+    loss = C.c_double(0.0)
+    _check(_lib.rom_subspace_loss(_ptr(Y), int(k), _ptr(X), int(N), int(ldx), int(s),
+                                  C.byref(loss), _ptr(dY) if dY is not None else None,
+                                  _ptr(scratch), scratch.numel() * scratch.element_size(),
+                                  _stream(stream)))
     return loss.value
 
 

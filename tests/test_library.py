@@ -77,3 +77,19 @@ def test_seednet_sizes(R):
     npar, pb, wb = R.rom_seednet_bytes(16, 16, 16, 2)
     assert npar == seed.flatten(seed.unflatten(seed.he_init(0))).size
     assert pb >= 4 * 4 * npar and wb > 0
+
+
+def test_seednet_outputs_and_subspace_sizes(R):
+    from paper_1602_00138_amd import seed
+    npar16, _, _ = R.rom_seednet_bytes(16, 16, 16, 2, 16)
+    assert npar16 == seed.he_init(0, outputs=16).size
+    npar1, _, _ = R.rom_seednet_bytes(16, 16, 16, 2, 1)
+    assert npar16 - npar1 == 15 * (16 * 27 + 1)
+    for bad in (0, 17):
+        with pytest.raises(R.RomError):
+            R.rom_seednet_bytes(16, 16, 16, 2, bad)
+    assert R.rom_subspace_loss_bytes(1000, 16, 64) > 8 * 1000 * (16 + 64)
+    for k, s in ((0, 4), (17, 4), (4, 0)):
+        with pytest.raises(R.RomError):
+            R.rom_subspace_loss_bytes(1000, k, s)
+

@@ -124,3 +124,32 @@ def test_adam_first_step_closed_form():
     # m_hat = g and v_hat = g^2 after one step: p - lr g / (|g| + eps)
     np.testing.assert_allclose(p["a"], np.array([1.0, -2.0, 0.5]) - 0.01 * g["a"] / (np.abs(g["a"]) + 1e-8),
                                rtol=1e-12)
+
+
+def test_subspace_loss_pins():
+    """The recycle-vector loss: zero when the solutions lie in span(N), invariant to
+    N -> N S, bounded by 1, equal to 1 - ||Q^T x^||^2 per column (Q an orthonormal basis of
+    span(N)), and its gradient against central differences (a planted sign error fails)."""
+    rng = np.random.default_rng(9)
+    n, k, s = 60, 5, 7
+    N = rng.standard_normal((n, k))
+    X = rng.standard_normal((n, s)) * rng.uniform(0.1, 10.0, s)
+    L = sn.subspace_loss(N, X)
+    assert 0.0 < L < 1.0
+    Q, _ = np.linalg.qr(N)
+    Xh = X / np.linalg.norm(X, axis=0)
+    np.testing.assert_allclose(L, np.mean(1.0 - ((Q.T @ Xh) ** 2).sum(axis=0)), rtol=1e-12)
+    S = rng.standard_normal((k, k)) + 3 * np.eye(k)
+    np.testing.assert_allclose(sn.subspace_loss(N @ S, X), L, rtol=1e-10)
+    assert sn.subspace_loss(N, N @ rng.standard_normal((k, 3))) <= 1e-26
+    G = sn.subspace_loss_grad(N, X)
+    h = 1e-6
+    for _ in range(12):
+        i, j = rng.integers(n), rng.integers(k)
+        Np, Nm = N.copy(), N.copy()
+        Np[i, j] += h
+        Nm[i, j] -= h
+        fd = (sn.subspace_loss(Np, X) - sn.subspace_loss(Nm, X)) / (2 * h)
+        assert abs(fd - G[i, j]) <= 1e-7 * (1 + abs(fd))
+    # moving N within its own span (N -> N + t N S) leaves the loss unchanged: <G, N S> = 0
+    assert abs(np.sum(G * (N @ S))) <= 1e-12 * np.linalg.norm(G) * np.linalg.norm(N @ S)

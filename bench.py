@@ -225,7 +225,7 @@ def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_poin
     twl = wl.replace(seed=wl.seed + 5000, K=train_points)
     tpts = driver.points_from_workload(twl)
     t0 = time.perf_counter()
-    inputs, targets = seed.dataset(prob, tpts, wl.tol)
+    inputs, targets, Xtrain = seed.dataset(prob, tpts, wl.tol, keep_solutions=True)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = seed.SeedNet(wl.N[:3], 8, seed.he_init(5).astype(np.float32))
@@ -238,6 +238,17 @@ def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_poin
     log(f"seed network: {len(tpts) * prob.n_rhs} training solutions in {t_data:.1f} s, "
         f"{train_steps} steps in {t_train:.1f} s, loss {np.mean(losses[:10]):.3e} -> "
         f"{np.mean(losses[-10:]):.3e}")
+    # the second output: 16 recycle vectors per point, trained on the subspace loss
+    rec_steps = max(100, train_steps // 2)
+    rnet = seed.SeedNet(wl.N[:3], 4, seed.he_init(8, outputs=16).astype(np.float32), outputs=16)
+    t0 = time.perf_counter()
+    rlosses = seed.train_recycle(rnet, seed.point_inputs(prob, tpts), Xtrain, prob.n_rhs,
+                                 steps=rec_steps, lr=2e-3, seed=2)
+    torch.cuda.synchronize()
+    t_rtrain = time.perf_counter() - t0
+    del Xtrain
+    log(f"recycle network: {rec_steps} steps in {t_rtrain:.1f} s, subspace loss "
+        f"{np.mean(rlosses[:5]):.3e} -> {np.mean(rlosses[-5:]):.3e}")
     kw = dict(precision=R.ROM_PREC_MIXED, tune=1)
     g = seed.guesses(net, prob, pts)
     prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, **kw).close()
@@ -269,9 +280,42 @@ def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_poin
                         "loss_last": float(np.mean(losses[-10:]))},
            "precision": "mixed", "group": 1}
     last.close()
-    net.close()
     log(f"learned seed (mixed): {out['value']:.1f} solves/s, its {st['total_its']}, "
         f"inference {out['inference_ms_per_step']:.0f} ms/step, residual drop 10^{out['mean_log10_residual_drop']:.2f}")
+    # both outputs: guesses and recycle vectors, inference inside every timed step
+    g = seed.guesses(net, prob, pts)
+    rv = seed.recycle_vectors(rnet, prob, pts)
+    prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, recycle=rv, **kw).close()
+    torch.cuda.synchronize()
+    t_inf = 0.0
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        if last is not None:
+            last.close()
+        ti = time.perf_counter()
+        g = seed.guesses(net, prob, pts)
+        rv = seed.recycle_vectors(rnet, prob, pts)
+        torch.cuda.synchronize()
+        t_inf += time.perf_counter() - ti
+        last = prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, recycle=rv, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st2 = last.stats
+    out["with_recycle_vectors"] = {
+        "value": K * n_rhs * steps / dt, "ms_per_step": 1e3 * dt / steps,
+        "inference_ms_per_step": 1e3 * t_inf / steps,
+        "vs_plain_fp64": K * n_rhs * steps / dt / plain_value, "basis_m": st2["m"],
+        "inner_its": st2["total_its"], "solved": st2["n_solved"],
+        "training": {"steps": rec_steps, "batch": 4, "train_s": t_rtrain,
+                     "loss_first": float(np.mean(rlosses[:5])),
+                     "loss_last": float(np.mean(rlosses[-5:]))}}
+    last.close()
+    net.close()
+    rnet.close()
+    log(f"learned seed + recycle vectors (mixed): {out['with_recycle_vectors']['value']:.1f} "
+        f"solves/s, its {st2['total_its']}, inference "
+        f"{out['with_recycle_vectors']['inference_ms_per_step']:.0f} ms/step")
     return out
 
 

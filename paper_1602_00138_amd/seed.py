@@ -124,9 +124,10 @@ def rhs_nodes(prob) -> np.ndarray:
     return np.concatenate([prob.src_idx, prob.det_idx])
 
 
-def dataset(prob, points, tol: float, **solve_kw):
+def dataset(prob, points, tol: float, keep_solutions: bool = False, **solve_kw):
     """Training pairs from the method's own solutions: run the sequence on `points` and
-    return (inputs [K n_rhs][3][N], targets [K n_rhs][N])."""
+    return (inputs [K n_rhs][3][N], targets [K n_rhs][N]), and the FP64 solutions
+    (K n_rhs, N) as a third item if keep_solutions."""
     res = prob.solve(points, tol, keep_X=True, **solve_kw)
     X = res.X
     res.close()
@@ -136,6 +137,8 @@ def dataset(prob, points, tol: float, **solve_kw):
     for i, p in enumerate(points):
         make_inputs(prob, p, idx, out=inputs[i * idx.size:(i + 1) * idx.size])
     targets = make_targets(X)
+    if keep_solutions:
+        return inputs, targets, X
     del X
     return inputs, targets
 

@@ -580,18 +580,22 @@ __global__ void k_gemm_sum(int M, int N, int ks, const double* __restrict__ P, d
 
 // Scatter one block row of the inverse Cholesky factor: rows k0..k0+nb of Linv get
 // T21 (nb x k0, ld nb) left of the diagonal block and T22 (nb x nb lower, ld nb).
-__global__ void k_linv_scatter(double* Lc, double* Lr, int64_t ld, int k0, int nb,
+// Rows k0 .. k0+nb-1 of Linv (all m columns: the strict upper part is written as zeros, so
+// the factor is complete whatever the buffers held) into both layouts.
+__global__ void k_linv_scatter(double* Lc, double* Lr, int64_t ld, int k0, int nb, int m,
                                const double* __restrict__ T21, const double* __restrict__ T22) {
   const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
-  const int64_t tot = (int64_t)nb * (k0 + nb);
+  const int64_t tot = (int64_t)nb * m;
   if (e >= tot) return;
   const int r = (int)(e % nb);
-  const int c = (int)(e / nb);   // 0 .. k0+nb-1
+  const int c = (int)(e / nb);   // 0 .. m-1
   double v;
   if (c < k0)
     v = T21[r + (int64_t)c * nb];
-  else
+  else if (c < k0 + nb)
     v = (c - k0 <= r) ? T22[r + (int64_t)(c - k0) * nb] : 0.0;
+  else
+    v = 0.0;
   Lc[(k0 + r) + (int64_t)c * ld] = v;
   Lr[c + (int64_t)(k0 + r) * ld] = v;
 }
@@ -791,8 +795,8 @@ void launch_linv_rebuild(const double* G, int64_t ldg, int m, double* Lc, double
                   st, SK, sk);
       launch_gemm(nb, k0, nb, -1.0, L22, nb, false, T2, nb, false, 0.0, nullptr, 0, T3, nb, st);
     }
-    const int64_t tot = (int64_t)nb * (k0 + nb);
-    ROM_LAUNCH(k_linv_scatter, dim3(ceil_div(tot, BS)), dim3(BS), 0, st, Lc, Lr, ldg, k0, nb, T3,
+    const int64_t tot = (int64_t)nb * m;
+    ROM_LAUNCH(k_linv_scatter, dim3(ceil_div(tot, BS)), dim3(BS), 0, st, Lc, Lr, ldg, k0, nb, m, T3,
                L22);
   }
 }

@@ -166,12 +166,14 @@ struct MsShifts {
   double sigma[MS_MAX];
 };
 // Per right-hand side: the seed CG scalars and, per shift (complex, interleaved re/im),
-// pi = R_k(-i sigma) (previous, current, next), zeta = 1/pi_next, rho = pi_cur/pi_next, the
-// shifted step alpha(s) and direction weight beta(s).  sdone[s]: shift converged (frozen).
+// pi = R_k(-i sigma) (previous, current, next), zeta = 1/pi_cur and zeta_next = 1/pi_next,
+// rho = pi_cur/pi_next, the shifted step alpha(s) and direction weight beta(s).  sdone[s]:
+// shift converged (frozen).
 struct MsState {
   double rr, bb, tol2, a_prev, b_prev, alpha, beta;
   double pi_prev[2 * MS_MAX], pi_cur[2 * MS_MAX], pi_next[2 * MS_MAX];
-  double zeta[2 * MS_MAX], rho[2 * MS_MAX], as[2 * MS_MAX], bs[2 * MS_MAX];
+  double zeta[2 * MS_MAX], zeta_next[2 * MS_MAX], rho[2 * MS_MAX], as[2 * MS_MAX],
+      bs[2 * MS_MAX];
   int sdone[MS_MAX];
   int its, maxit, flag, done;   // flag: 0 ok, 1 non-positive curvature, 2 non-finite
 };
@@ -190,12 +192,12 @@ void launch_ms_apply(const Stencil& S, const StencilShape& sh, const double* dia
 void launch_ms_alpha(const double* partials, int P, MsState* state, int nb, const MsShifts& sh,
                      hipStream_t st);
 void launch_ms_update(int64_t n, int nb, int ns, const double* w, double* r, int64_t ld,
-                      const double* Pr, const double* Pi, double* Xr, double* Xi, int64_t ldx,
+                      double* Pr, double* Pi, double* Xr, double* Xi, int64_t ldx,
                       const MsState* state, double* partials, hipStream_t st);
 void launch_ms_beta(const double* partials, int P, MsState* state, int nb, int ns,
                     hipStream_t st);
-void launch_ms_dir(int64_t n, int nb, int ns, const double* r, double* p, int64_t ld, double* Pr,
-                   double* Pi, const MsState* state, hipStream_t st);
+void launch_ms_dir(int64_t n, int nb, const double* r, double* p, int64_t ld,
+                   const MsState* state, hipStream_t st);
 // out[c] (c = s * nb + j) = ||Re(b_j - (A + i sigma_s) X_c)||^2 and out[nb*ns + c] the
 // imaginary part's.  partials: >= 2 * nb * ns * shp.blocks doubles.
 void launch_ms_resid(const Stencil& S, const StencilShape& shp, const double* diag,
@@ -228,7 +230,8 @@ void launch_fill(int64_t n, double v, double* x, hipStream_t st);
 void launch_linv_border(double* Lc, double* Lr, int64_t ld, int k, const double* gcol,
                         double* tmp_l, double* tmp_r, int* status, double* partials,
                         hipStream_t st, double* info = nullptr);
-// Rebuild Linv (both layouts) from the m x m SPD matrix G in 64-column blocks: per block
+// Rebuild Linv (both layouts, the whole m x m matrix including the zeros above the
+// diagonal) from the m x m SPD matrix G in 64-column blocks: per block
 // L21 = G21 Linv11^T, S = G22 - L21 L21^T, Linv22 = chol(S)^{-1},
 // Linv21 = -Linv22 (L21 Linv11).  work: >= linv_rebuild_work(m) doubles (the last part
 // holds the K-split slices of its products).

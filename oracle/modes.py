@@ -20,6 +20,8 @@ def lowest_modes(A, k: int):
 
 
 def gershgorin_upper(A) -> float:
-    """max_i sum_j |a_ij|, an upper bound of the spectrum of a symmetric A."""
-    Ad = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
-    return float(np.abs(Ad).sum(axis=1).max())
+    """max_i sum_j |a_ij|, an upper bound of the spectrum of a symmetric A (sparse A stays
+    sparse, so this also serves full-size grids)."""
+    if sp.issparse(A):
+        return float(np.asarray(abs(A).sum(axis=1)).max())
+    return float(np.abs(np.asarray(A, dtype=np.float64)).sum(axis=1).max())

@@ -12,10 +12,12 @@
 // direction (four real vectors).  A shift stops updating once its residual meets the
 // tolerance, which also keeps R_k(-s) bounded by about 1/tol.
 //
-// Per iteration and column: k_ms_apply (w = A p and p^T w), k_ms_alpha (seed step and
-// the shifted scalars), k_ms_update (r -= alpha w, r^T r, X(s) += alpha(s) P(s)),
-// k_ms_beta (beta, per-shift convergence), k_ms_dir (p and P(s)).  Columns (right-hand
-// sides) ride on the grid's last dimension, each with its own scalars in MsState.
+// Per iteration k and column: k_ms_apply (w = A p and p^T w), k_ms_alpha (seed step and
+// the shifted scalars), k_ms_update (the shifted direction P(s)_k = zeta_k r_k +
+// beta(s)_{k-1} P(s)_{k-1} formed where r_k is read anyway, X(s) += alpha(s)_k P(s)_k, then
+// r -= alpha w and r^T r), k_ms_beta (beta, per-shift convergence), k_ms_dir (the seed's
+// p).  Columns (right-hand sides) ride on the grid's last dimension, each with its own
+// scalars in MsState.
 #include "kernels.h"
 
 namespace rom {
@@ -51,7 +53,7 @@ __global__ void k_ms_init(int64_t n, const double* __restrict__ B, int64_t ldb, 
     p[i + j * ld] = v;
     for (int s = 0; s < ns; ++s) {
       const int64_t c = (int64_t)s * nb + j;
-      Pr[i + c * ld] = v;
+      Pr[i + c * ld] = 0.0;   // P(s)_{-1}: weighted by beta(s)_{-1} = 0 in the first update
       Pi[i + c * ld] = 0.0;
       Xr[i + c * ldx] = 0.0;
       Xi[i + c * ldx] = 0.0;
@@ -78,6 +80,9 @@ __global__ void k_ms_start(const double* __restrict__ partials, int P, MsState* 
     for (int s = 0; s < MS_MAX; ++s) {
       m.pi_prev[2 * s] = m.pi_cur[2 * s] = 1.0;
       m.pi_prev[2 * s + 1] = m.pi_cur[2 * s + 1] = 0.0;
+      m.zeta[2 * s] = 1.0;   // zeta_0
+      m.zeta[2 * s + 1] = 0.0;
+      m.bs[2 * s] = m.bs[2 * s + 1] = 0.0;
       m.sdone[s] = s < ns ? (rr > 0.0 ? 0 : 1) : 1;
     }
     m.its = 0;
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(BS) void k_ms_apply(Stencil S, const double* __rest
 
 // Seed step length, then per live shift: pi_next = (1 + c + i alpha sigma) pi_cur - c pi_prev
 // with c = alpha beta_prev / alpha_prev; rho = pi_cur / pi_next; alpha(s) = alpha rho;
-// zeta = 1 / pi_next.
+// zeta_next = 1 / pi_next (zeta, the current one, is still read by the update).
 __global__ void k_ms_alpha(const double* __restrict__ partials, int P, MsState* st,
                            MsShifts sh) {
   MsState& m = st[blockIdx.x];
@@ -141,8 +146,8 @@ __global__ void k_ms_alpha(const double* __restrict__ partials, int P, MsState* 
     const Cx rho = cmul(cur, zeta);
     m.pi_next[2 * s] = nxt.re;
     m.pi_next[2 * s + 1] = nxt.im;
-    m.zeta[2 * s] = zeta.re;
-    m.zeta[2 * s + 1] = zeta.im;
+    m.zeta_next[2 * s] = zeta.re;
+    m.zeta_next[2 * s + 1] = zeta.im;
     m.rho[2 * s] = rho.re;
     m.rho[2 * s + 1] = rho.im;
     m.as[2 * s] = alpha * rho.re;
@@ -150,10 +155,11 @@ __global__ void k_ms_alpha(const double* __restrict__ partials, int P, MsState* 
   }
 }
 
-// r -= alpha w (partial r^T r); X(s) += alpha(s) P(s) for the live shifts.
+// For the live shifts P(s) = zeta r + beta(s) P(s) and X(s) += alpha(s) P(s); then
+// r -= alpha w (partial r^T r).
 __global__ void k_ms_update(int64_t n, int nb, const double* __restrict__ w,
-                            double* __restrict__ r, int64_t ld, const double* __restrict__ Pr,
-                            const double* __restrict__ Pi, double* __restrict__ Xr,
+                            double* __restrict__ r, int64_t ld, double* __restrict__ Pr,
+                            double* __restrict__ Pi, double* __restrict__ Xr,
                             double* __restrict__ Xi, int64_t ldx, const MsState* __restrict__ st,
                             int ns, double* __restrict__ partials) {
   const int j = blockIdx.y;
@@ -162,17 +168,24 @@ __global__ void k_ms_update(int64_t n, int nb, const double* __restrict__ w,
   const double alpha = m.alpha;
   double acc[1] = {0.0};
   for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-    const double rv = r[i + j * ld] - alpha * w[i + j * ld];
-    r[i + j * ld] = rv;
-    acc[0] += rv * rv;
+    const double r0 = r[i + j * ld];
     for (int s = 0; s < ns; ++s) {
       if (m.sdone[s]) continue;
       const int64_t c = (int64_t)s * nb + j;
+      const double zr = m.zeta[2 * s], zi = m.zeta[2 * s + 1];
+      const double br = m.bs[2 * s], bi = m.bs[2 * s + 1];
+      const double qr = Pr[i + c * ld], qi = Pi[i + c * ld];
+      const double pr = zr * r0 + br * qr - bi * qi;
+      const double pi = zi * r0 + br * qi + bi * qr;
+      Pr[i + c * ld] = pr;
+      Pi[i + c * ld] = pi;
       const double ar = m.as[2 * s], ai = m.as[2 * s + 1];
-      const double pr = Pr[i + c * ld], pi = Pi[i + c * ld];
       Xr[i + c * ldx] += ar * pr - ai * pi;
       Xi[i + c * ldx] += ar * pi + ai * pr;
     }
+    const double rv = r0 - alpha * w[i + j * ld];
+    r[i + j * ld] = rv;
+    acc[0] += rv * rv;
   }
   write_partials<1, BS>(acc, partials + (int64_t)j * gridDim.x, blockIdx.x);
 }
@@ -200,9 +213,11 @@ __global__ void k_ms_beta(const double* __restrict__ partials, int P, MsState* s
     const Cx r2 = cmul(rho, rho);
     m.bs[2 * s] = r2.re * beta;
     m.bs[2 * s + 1] = r2.im * beta;
-    const double z2 = m.zeta[2 * s] * m.zeta[2 * s] + m.zeta[2 * s + 1] * m.zeta[2 * s + 1];
-    if (z2 * rr <= m.tol2) m.sdone[s] = 1;
+    const double zr = m.zeta_next[2 * s], zi = m.zeta_next[2 * s + 1];
+    if ((zr * zr + zi * zi) * rr <= m.tol2) m.sdone[s] = 1;
     else ++live;
+    m.zeta[2 * s] = zr;
+    m.zeta[2 * s + 1] = zi;
     m.pi_prev[2 * s] = m.pi_cur[2 * s];
     m.pi_prev[2 * s + 1] = m.pi_cur[2 * s + 1];
     m.pi_cur[2 * s] = m.pi_next[2 * s];
@@ -215,27 +230,15 @@ __global__ void k_ms_beta(const double* __restrict__ partials, int P, MsState* s
   if (live == 0 || m.its >= m.maxit) m.done = 1;
 }
 
-// p = r + beta p; P(s) = zeta r + beta(s) P(s) for the live shifts.
+// The seed's direction p = r + beta p.
 __global__ void k_ms_dir(int64_t n, int nb, const double* __restrict__ r, double* __restrict__ p,
-                         int64_t ld, double* __restrict__ Pr, double* __restrict__ Pi,
-                         const MsState* __restrict__ st, int ns) {
+                         int64_t ld, const MsState* __restrict__ st) {
   const int j = blockIdx.y;
   const MsState& m = st[j];
   if (m.done) return;
   const double beta = m.beta;
-  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-    const double rv = r[i + j * ld];
-    p[i + j * ld] = rv + beta * p[i + j * ld];
-    for (int s = 0; s < ns; ++s) {
-      if (m.sdone[s]) continue;
-      const int64_t c = (int64_t)s * nb + j;
-      const double zr = m.zeta[2 * s], zi = m.zeta[2 * s + 1];
-      const double br = m.bs[2 * s], bi = m.bs[2 * s + 1];
-      const double pr = Pr[i + c * ld], pi = Pi[i + c * ld];
-      Pr[i + c * ld] = zr * rv + br * pr - bi * pi;
-      Pi[i + c * ld] = zi * rv + br * pi + bi * pr;
-    }
-  }
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    p[i + j * ld] = r[i + j * ld] + beta * p[i + j * ld];
 }
 
 // True residual of column c = s * nb + j, one plane at a time:
@@ -321,7 +324,7 @@ void launch_ms_alpha(const double* partials, int P, MsState* state, int nb, cons
 }
 
 void launch_ms_update(int64_t n, int nb, int ns, const double* w, double* r, int64_t ld,
-                      const double* Pr, const double* Pi, double* Xr, double* Xi, int64_t ldx,
+                      double* Pr, double* Pi, double* Xr, double* Xi, int64_t ldx,
                       const MsState* state, double* partials, hipStream_t st) {
   ROM_LAUNCH(k_ms_update, dim3(vec_grid(n), nb), dim3(BS), 0, st, n, nb, w, r, ld, Pr, Pi, Xr, Xi,
              ldx, state, ns, partials);
@@ -332,9 +335,9 @@ void launch_ms_beta(const double* partials, int P, MsState* state, int nb, int n
   ROM_LAUNCH(k_ms_beta, dim3(nb), dim3(BS), 0, st, partials, P, state, ns);
 }
 
-void launch_ms_dir(int64_t n, int nb, int ns, const double* r, double* p, int64_t ld, double* Pr,
-                   double* Pi, const MsState* state, hipStream_t st) {
-  ROM_LAUNCH(k_ms_dir, dim3(vec_grid(n), nb), dim3(BS), 0, st, n, nb, r, p, ld, Pr, Pi, state, ns);
+void launch_ms_dir(int64_t n, int nb, const double* r, double* p, int64_t ld,
+                   const MsState* state, hipStream_t st) {
+  ROM_LAUNCH(k_ms_dir, dim3(vec_grid(n), nb), dim3(BS), 0, st, n, nb, r, p, ld, state);
 }
 
 void launch_ms_resid(const Stencil& S, const StencilShape& shp, const double* diag,

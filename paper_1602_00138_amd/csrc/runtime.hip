@@ -2405,7 +2405,7 @@ rom_status rom_shifted_solve(const rom_operator* op, const rom_mu* p, const doub
         rom::launch_ms_alpha(L.part, shp.blocks, L.state, nb, sh, st);
         rom::launch_ms_update(n, nb, ns, L.w, L.r, ld, L.Pr, L.Pi, Xr, Xi, n, L.state, L.part, st);
         rom::launch_ms_beta(L.part, Pv, L.state, nb, ns, st);
-        rom::launch_ms_dir(n, nb, ns, L.r, L.p, ld, L.Pr, L.Pi, L.state, st);
+        rom::launch_ms_dir(n, nb, L.r, L.p, ld, L.state, st);
       }
       ROM_HIP(hipMemcpyAsync(hs.data(), L.state, sizeof(rom::MsState) * nb, hipMemcpyDeviceToHost,
                              st));

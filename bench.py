@@ -26,11 +26,12 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_outer_gemvn_cfg2_64cub
 
 
 def traffic_ratio():
-    """Measured HBM bytes / algorithmic bytes of the outer-projection kernel (rocprofv3
-    FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), from the committed profile."""
+    """Measured HBM bytes / algorithmic bytes of the outer-projection kernels (the fused
+    k_gemvn4x3 and the plain k_gemvn4<false>; rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated
+    on a plain copy), from the committed profile; None if it was taken on other kernels."""
     try:
         for line in open(TRAFFIC_PROFILE):
-            if line.startswith("traffic_ratio:"):
+            if line.startswith("traffic_ratio_outer_fused:"):
                 return float(line.split(":", 1)[1])
     except OSError:
         pass
@@ -383,7 +384,8 @@ def main():
                     help="only run 3 plain device copies of 1 GiB (the reference for the "
                          "HBM traffic counters) and exit")
     ap.add_argument("--kernel", default="outer",
-                    help="kernel class for the roofline (outer: the per-RHS product x0 = V c, "
+                    help="kernel class for the roofline (outer: the per-RHS start x0 = V c, "
+                         "k_gemvn4x3 fused with the previous append's Gram-Schmidt pass or "
                          "k_gemvn4<false>; auto: the class with the most event time)")
     args = ap.parse_args()
 

@@ -189,6 +189,68 @@ __global__ __launch_bounds__(BS) void k_gemvn4(const double* __restrict__ M, int
   if (NRM) write_partials<1, BS>(nv, partials, blockIdx.x);
 }
 
+// One pass over the basis for three products (the Gram-Schmidt subtraction of one right-hand
+// side fused with the next right-hand side's start): out0 = in - M t (and partial sums of
+// out0^2), out1 = M c1, out2 = M c2.  Same row layout as k_gemvn4 (four consecutive rows
+// per thread, two 16-byte loads per column); the three coefficient vectors sit in LDS.
+__global__ __launch_bounds__(BS) void k_gemvn4x3(const double* __restrict__ M, int64_t ld,
+                                                 int64_t rows, int cols,
+                                                 const double* __restrict__ t,
+                                                 const double* __restrict__ c1,
+                                                 const double* __restrict__ c2,
+                                                 const double* __restrict__ in,
+                                                 double* __restrict__ out0,
+                                                 double* __restrict__ out1,
+                                                 double* __restrict__ out2, double* partials) {
+  extern __shared__ double cs[];   // [t | c1 | c2]
+  for (int c = threadIdx.x; c < cols; c += BS) {
+    cs[c] = t[c];
+    cs[cols + c] = c1[c];
+    cs[2 * cols + c] = c2[c];
+  }
+  __syncthreads();
+  double nv[1] = {0.0};
+  for (int64_t r0 = ((int64_t)blockIdx.x * BS + threadIdx.x) * 4; r0 < rows;
+       r0 += (int64_t)gridDim.x * BS * 4) {
+    double a0[4] = {0.0, 0.0, 0.0, 0.0}, a1[4] = {0.0, 0.0, 0.0, 0.0},
+           a2[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* p = M + r0;
+    for (int c = 0; c < cols; ++c) {
+      const double w0 = cs[c], w1 = cs[cols + c], w2 = cs[2 * cols + c];
+      const double2 v0 = *reinterpret_cast<const double2*>(p + (int64_t)c * ld);
+      const double2 v1 = *reinterpret_cast<const double2*>(p + (int64_t)c * ld + 2);
+      const double v[4] = {v0.x, v0.y, v1.x, v1.y};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a0[q] += v[q] * w0;
+        a1[q] += v[q] * w1;
+        a2[q] += v[q] * w2;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = r0 + q;
+      if (r < rows) {
+        const double o = in[r] - a0[q];
+        out0[r] = o;
+        out1[r] = a1[q];
+        out2[r] = a2[q];
+        nv[0] += o * o;
+      }
+    }
+  }
+  write_partials<1, BS>(nv, partials, blockIdx.x);
+}
+
+// out = a + (u - w) * (cm[0] * s): the next right-hand side's start from the fused pass.
+__global__ void k_fused_start(int64_t n, const double* __restrict__ a, const double* __restrict__ u,
+                              const double* __restrict__ w, const double* __restrict__ cm,
+                              double s, double* __restrict__ out) {
+  const double f = cm[0] * s;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+    out[i] = a[i] + (u[i] - w[i]) * f;
+}
+
 // Several coefficient vectors against one basis pass: each thread owns RPT rows and
 // NV accumulators per row; coefficients are staged through LDS in chunks of CCH columns.
 template <int NV, int RPT>
@@ -845,10 +907,11 @@ void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const dou
   if (grid.x < 1) grid.x = 1;
 #define GT_LAUNCH(C, N) \
   ROM_LAUNCH((k_gemvt<C, N>), grid, dim3(BS), 0, st, M, ld, rows, cols, V, vstride, out, partials, skip)
+  if (nv < 1 || nv > 3) throw Error(ROM_EINVAL, "gemvt: 1 to 3 vectors");
   if (cpl == 16) {
-    if (nv == 1) GT_LAUNCH(16, 1); else GT_LAUNCH(16, 2);
+    if (nv == 1) GT_LAUNCH(16, 1); else if (nv == 2) GT_LAUNCH(16, 2); else GT_LAUNCH(16, 3);
   } else {
-    if (nv == 1) GT_LAUNCH(4, 1); else GT_LAUNCH(4, 2);
+    if (nv == 1) GT_LAUNCH(4, 1); else if (nv == 2) GT_LAUNCH(4, 2); else GT_LAUNCH(4, 3);
   }
 #undef GT_LAUNCH
   ROM_CHECK_LAUNCH();
@@ -885,6 +948,33 @@ void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const dou
                  in, beta, out, partials, skip);
     ROM_CHECK_LAUNCH();
   }
+}
+
+bool gemvn_fused_ok(const double* M, int64_t ld, int cols) {
+  return cols > 0 && ld % 4 == 0 && ((uintptr_t)M & 15) == 0 &&
+         (size_t)3 * cols * sizeof(double) <= 64 * 1024;
+}
+
+void launch_gemvn_fused(const double* M, int64_t ld, int64_t rows, int cols, const double* t,
+                        const double* c1, const double* c2, const double* in, double* out0,
+                        double* out1, double* out2, double* nrm2, double* partials,
+                        hipStream_t st) {
+  if (!gemvn_fused_ok(M, ld, cols)) throw Error(ROM_EINVAL, "gemvn_fused: layout not supported");
+  // one block per CU, as for k_gemvn4 (its streaming rate was measured with this shape)
+  const int grid = std::min(256, std::max(1, ceil_div(rows, 4 * BS)));
+  const size_t shm = (size_t)3 * cols * sizeof(double);
+  ROM_LAUNCH(k_gemvn4x3, dim3(grid), dim3(BS), shm, st, M, ld, rows, cols, t, c1, c2, in, out0,
+             out1, out2, partials);
+  ROM_CHECK_LAUNCH();
+  launch_reduce_finish(partials, grid, 1, nrm2, st);
+}
+
+void launch_fused_start(int64_t n, const double* a, const double* u, const double* w,
+                        const double* cm, double s, double* out, hipStream_t st) {
+  if (n <= 0) return;
+  const int gx = std::min(ceil_div(n, BS), 1024);
+  ROM_LAUNCH(k_fused_start, dim3(gx), dim3(BS), 0, st, n, a, u, w, cm, s, out);
+  ROM_CHECK_LAUNCH();
 }
 
 void launch_gemvn_multi(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
@@ -1052,6 +1142,14 @@ void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, co
   if (m <= 0) return;
   launch_gemvt(Lr, ld, m, m, t, 0, 1, u, partials, st);
   launch_gemvt(Lc, ld, m, m, u, 0, 1, c, partials, st);
+}
+
+void launch_linv_solve_multi(const double* Lc, const double* Lr, int64_t ld, int m, const double* T,
+                             int64_t tstride, int nv, double* U, double* C, double* partials,
+                             hipStream_t st) {
+  if (m <= 0) return;
+  launch_gemvt(Lr, ld, m, m, T, tstride, nv, U, partials, st);
+  launch_gemvt(Lc, ld, m, m, U, m, nv, C, partials, st);
 }
 
 void launch_nz_rows(int64_t n, const double* w, int64_t* idx, double* wc, int64_t cap, int* total,

@@ -106,6 +106,17 @@ void launch_gemvn(const double* M, int64_t ld, int64_t rows, int cols, const dou
                   double alpha, const double* in, double beta, double* out, double* nrm2,
                   double* partials, hipStream_t st, Skip skip = Skip());
 
+// One basis pass for three products: out0 = in - M t (||out0||^2 into nrm2, device),
+// out1 = M c1, out2 = M c2.  Needs gemvn_fused_ok (ld % 4 == 0, M 16-byte aligned,
+// 3 cols doubles of LDS <= 64 KiB).  partials: >= 256 doubles.
+bool gemvn_fused_ok(const double* M, int64_t ld, int cols);
+void launch_gemvn_fused(const double* M, int64_t ld, int64_t rows, int cols, const double* t,
+                        const double* c1, const double* c2, const double* in, double* out0,
+                        double* out1, double* out2, double* nrm2, double* partials,
+                        hipStream_t st);
+// out = a + (u - w) * (cm[0] * s) (cm on the device).
+void launch_fused_start(int64_t n, const double* a, const double* u, const double* w,
+                        const double* cm, double s, double* out, hipStream_t st);
 // Several right-hand sides at once: out[r + v*ldo] = alpha * in[r + v*ldi]
 //   + beta * sum_{c < cols} M[r + c*ld] coef[c + v*ldc], v < nv <= 16 (in may be NULL).
 void launch_gemvn_multi(const double* M, int64_t ld, int64_t rows, int cols, const double* coef,
@@ -251,6 +262,10 @@ void launch_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda
 // c = Linv^T (Linv t), for m x m Linv.
 void launch_linv_solve(const double* Lc, const double* Lr, int64_t ld, int m, const double* t,
                        double* u, double* c, double* partials, hipStream_t st);
+// C[:, v] = Linv^T (Linv T[:, v]) for v < nv <= 3 (T at stride tstride; U and C at stride m).
+void launch_linv_solve_multi(const double* Lc, const double* Lr, int64_t ld, int m, const double* T,
+                             int64_t tstride, int nv, double* U, double* C, double* partials,
+                             hipStream_t st);
 // Rows r < n with w[r] != 0, ascending: idx[t] = r and wc[t] = w[r] for the first cap of
 // them; *total = how many there are (device int, all of them).  work: ceil(n / 256) ints.
 void launch_nz_rows(int64_t n, const double* w, int64_t* idx, double* wc, int64_t cap, int* total,

@@ -311,7 +311,9 @@ class Sequencer {
     d_ = a.take<double>(ld_ * G);
     xt_ = a.take<double>(ld_ * G);
     r2_ = a.take<double>(ld_ * G);
-    vAB_ = a.take<double>(2 * ld_);
+    vAB_ = a.take<double>(3 * ld_);   // u, A_* u, A_i u of an append
+    fa_ = a.take<double>(ld_);
+    fw_ = a.take<double>(ld_);
     xg_ = a.take<double>(ld_);
     blk_ = G > 1 ? a.take<double>(ld_ * 2 * G) : nullptr;
     bblk_ = G > 1 ? a.take<double>((size_t)(cap_ + 8) * 2 * G) : nullptr;
@@ -339,8 +341,8 @@ class Sequencer {
     part1_ = a.take<double>((size_t)p1s_ * G);
     p2s_ = (int64_t)(NJ_MAX + 1) * dcg_blocks(n_);
     part2_ = a.take<double>((size_t)p2s_ * G);
-    size_t gt = std::max(gemvt_partials_max(n_, std::max(cap_ + 1, NJ_MAX), 2),
-                         gemvt_partials_max(cap_, cap_, 1));
+    size_t gt = std::max(gemvt_partials_max(n_, std::max(cap_ + 1, NJ_MAX), 3),
+                         gemvt_partials_max(cap_, cap_, 2));
     gt = std::max(gt, proj_partials_max(std::max(cap_, NJ_MAX), G_MAX, n_));
     gt_part_ = a.take<double>(std::max<size_t>(gt, 1));
     tbuf_ = a.take<double>((size_t)(std::max(cap_, NJ_MAX) + 8) * std::max(G, 2));
@@ -348,7 +350,9 @@ class Sequencer {
     cbuf_ = a.take<double>((size_t)(cap_ + 8) * G);
     tmpl_ = a.take<double>(std::max(cap_, REC_MAX) + 8);
     tmpr_ = a.take<double>(2 * (cap_ + 8));
-    bvals_ = a.take<double>(2 * (cap_ + 8));
+    bvals_ = a.take<double>(4 * (cap_ + 8));   // [t | h | h_i | b row] of an append
+    fcw_ = a.take<double>(2 * (cap_ + 8));     // [w | y]
+    ftmp_ = a.take<double>(2 * (cap_ + 8));
     GW_ = a.take<double>(NJ_MAX * NJ_MAX);
     if (n_rec_ > 0) {
       rec_ = a.take<double>(ld_ * REC_MAX);
@@ -557,15 +561,33 @@ class Sequencer {
     double* u = vAB_;               // pass input, then A_* of it at vAB_ + ld_
     launch_axpby(n_, 1.0, v, 0.0, nullptr, u, &ctrl_->sc[5], red_part_, st_);
     bool pass2 = false;
+    // the next right-hand side of this point takes its start from this pass (see
+    // fused_start): V y and V w are formed with the old V while it is read for u - V t
+    const bool fuse = fuse_next_.on && m > 0 && gemvn_fused_ok(Q_, ld_, m);
     if (m > 0) {
       launch_spmv(S_, op_->diag_star, u, vAB_ + ld_, st_);
       account_spmv(ROM_K_OTHER);
+      if (fuse) {
+        launch_spmv(S_, diag_i_, u, vAB_ + 2 * ld_, st_);
+        account_spmv(ROM_K_OTHER);
+      }
       tm_->begin(ROM_K_GEMVT);
-      launch_gemvt(Q_, ld_, n_, m, u, ld_, 2, bvals_, gt_part_, st_);   // [t1 | h1]
-      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (m + 2), 4.0 * n_ * m);
-      tm_->begin(ROM_K_GEMVN);
-      launch_gemvn(Q_, ld_, n_, m, bvals_, 1.0, u, -1.0, slot, &ctrl_->sc[4], red_part_, st_);
-      tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m + 2), 2.0 * n_ * m);
+      launch_gemvt(Q_, ld_, n_, m, u, ld_, fuse ? 3 : 2, bvals_, gt_part_, st_);   // [t1 | h1 (| h1i)]
+      tm_->end(ROM_K_GEMVT, 8.0 * n_ * (m + (fuse ? 3 : 2)), (fuse ? 6.0 : 4.0) * n_ * m);
+      if (fuse) {
+        // [w | y] = G_i^{-1} [V^T A_i u | V^T b_next] in one pair of triangular products
+        launch_gather_row(Q_, ld_, m, fuse_next_.idx, fuse_next_.sc, bvals_ + 3 * m, st_);
+        launch_linv_solve_multi(Lc_, Lr_, ldg_, m, bvals_ + 2 * m, m, 2, ftmp_, fcw_, gt_part_,
+                                st_);
+        tm_->begin(ROM_K_OUTER);
+        launch_gemvn_fused(Q_, ld_, n_, m, bvals_, fcw_ + m, fcw_, u, slot, fa_, fw_,
+                           &ctrl_->sc[4], red_part_, st_);
+        tm_->end(ROM_K_OUTER, 8.0 * n_ * (m + 4), 6.0 * n_ * m);
+      } else {
+        tm_->begin(ROM_K_GEMVN);
+        launch_gemvn(Q_, ld_, n_, m, bvals_, 1.0, u, -1.0, slot, &ctrl_->sc[4], red_part_, st_);
+        tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m + 2), 2.0 * n_ * m);
+      }
       // second pass (the kernels return at once when the first kept more than half
       // of ||v||^2): input slot, [t2 | h2] = V^T [slot, A_* slot]
       Skip skip{&ctrl_->sc[4], 0.5};
@@ -597,12 +619,18 @@ class Sequencer {
     const double a = h_->sc[4], b = h_->sc[5];
     const double rho = (b > 0.0 && std::isfinite(a) && std::isfinite(b)) ? std::sqrt(a / b) : 0.0;
     *rho_out = rho;
+    if (fuse) {
+      fused_ready_ = true;
+      fused_kept_ = false;
+      fused_rho_ = std::sqrt(a);   // ||u - V t||, the norm q is divided by
+    }
     if (!(rho > trunc_)) return false;
     const double* th = pass2 ? tbuf_ : bvals_;   // [t | h] of the last pass
     if (m > 0) launch_gemvt(Gs_, ldg_, m, m, th, 0, 1, cbuf_, gt_part_, st_);   // G_* t
     launch_normalize(n_, slot, &ctrl_->sc[4], st_);
     border_new(m, slot, th + m);
     ++m_;
+    if (fuse) fused_kept_ = true;
     return true;
   }
 
@@ -711,6 +739,7 @@ class Sequencer {
         rebuild_gi();
       }
       prepare_recycle(i);
+      fused_ready_ = false;
       for (int y = 0; y < G_MAX; ++y) w_key_[y] = -2;
       if (G_ == 1)
         point_sequential(i, X_out);
@@ -777,6 +806,23 @@ class Sequencer {
       }
     }
     n_rec_kept_ = kk;
+  }
+
+  // Start of the right-hand side after a fused append (V' = [V, q] when the correction u was
+  // kept, q = (u - V t) / rho): the Galerkin coefficients c' = G'^{-1} V'^T b split by the
+  // border into c'[0:m] = y - G^{-1} g c'_m with g = V^T A_i q, and
+  // q - V G^{-1} g = (u - V w) / rho with w = G^{-1} V^T A_i u, so
+  // x0 = V' c' = V y + (u - V w) c'_m / rho; c'_m comes from the bordered factor.  Without
+  // an append, V is unchanged and x0 = V y.  u is the correction, still in g_.
+  void fused_start(int64_t idx, double sc) {
+    if (fused_kept_) {
+      launch_gather_row(Q_, ld_, m_, idx, sc, tbuf_, st_);
+      launch_linv_solve(Lc_, Lr_, ldg_, m_, tbuf_, ubuf_, cbuf_, gt_part_, st_);
+      launch_fused_start(n_, fa_, g_, fw_, cbuf_ + (m_ - 1), 1.0 / fused_rho_, x0_, st_);
+    } else {
+      ROM_HIP(hipMemcpyAsync(x0_, fa_, sizeof(double) * n_, hipMemcpyDeviceToDevice, st_));
+    }
+    fused_ready_ = false;
   }
 
   // Bookkeeping of a solved right-hand side: iterations, final residual, convergence.
@@ -940,7 +986,9 @@ class Sequencer {
       rec.rhs = j;
       rec.rho = -1.0;
       // ---- outer projection on V (Galerkin in the A(p_i) inner product)
-      if (m_ > 0) {
+      if (fused_ready_) {
+        fused_start(idx, sc);
+      } else if (m_ > 0) {
         launch_gather_row(Q_, ld_, m_, idx, sc, tbuf_, st);
         launch_linv_solve(Lc_, Lr_, ldg_, m_, tbuf_, ubuf_, cbuf_, gt_part_, st);
         tm_->begin(ROM_K_OUTER);
@@ -1002,7 +1050,14 @@ class Sequencer {
       }
       // the correction that joins V and U_j is x - x0 (x0 in range(V))
       if (xbase_ != x0_) launch_axpby(n_, 1.0, xdst, -1.0, x0_, g_, nullptr, red_part_, st);
+      // the append of this correction also forms the next right-hand side's start
+      fuse_next_.on = j + 1 < n_rhs_;
+      if (fuse_next_.on) {
+        fuse_next_.idx = idx_[j + 1];
+        fuse_next_.sc = scale_[j + 1];
+      }
       finish_solved(i, j, 0, g_, xdst, nj, its, restarts, res, flag, rec);
+      fuse_next_.on = false;
       recs_.push_back(rec);
     }
   }
@@ -1280,8 +1335,9 @@ class Sequencer {
   // the variant with half the rows per thread.  Fixed shape: the full grid for one member,
   // split among the members of a batch (narrow for batches).  With opts.tune the first
   // batch of each (arithmetic, batch size, U_j width class, grid size) in the process times
-  // every power-of-two P with both variants on its own data (a few CG steps each, from its
-  // real start; the solve then restarts) and keeps the fastest for the rest of the process.
+  // every power-of-two P with both variants on its own data (three rounds of 8 CG steps
+  // each after a warm-up round, from its real start; the solve then restarts) and keeps the
+  // fastest (by its best round) for the rest of the process.
   template <typename T, typename Bufs>
   int cg_shape(const Batch& bt, const Bufs& b, const double* rhs, T* dvec, int64_t wstride,
                int64_t gstride, int njmax) {
@@ -1332,12 +1388,15 @@ class Sequencer {
         }
       } guard{e0, e1};
       int k = 0;
-      float best_ms = 1e30f;
-      for (int rep = 0; rep < 2; ++rep) {   // the first round warms up
-        for (int shape : cand) {
+      // each shape's time is the minimum over 3 rounds of 8 steps (the first round only
+      // warms up): single short windows were noisy enough to flip the choice between runs
+      std::vector<float> tmin(cand.size(), 1e30f);
+      for (int rep = 0; rep < 4; ++rep) {
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+          const int shape = cand[ci];
           const int P = shape >> 1, nr = shape & 1;
           ROM_HIP(hipEventRecord(e0, st_));
-          for (int step = 0; step < 4; ++step, ++k) {
+          for (int step = 0; step < 8; ++step, ++k) {
             launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, st_);
             launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
                                  b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_, nr);
@@ -1348,12 +1407,15 @@ class Sequencer {
           ROM_HIP(hipEventSynchronize(e1));
           float ms = 0.f;
           ROM_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (rep == 1 && ms < best_ms) {
-            best_ms = ms;
-            best = shape;
-          }
+          if (rep > 0) tmin[ci] = std::min(tmin[ci], ms);
         }
       }
+      float best_ms = 1e30f;
+      for (size_t ci = 0; ci < cand.size(); ++ci)
+        if (tmin[ci] < best_ms) {
+          best_ms = tmin[ci];
+          best = cand[ci];
+        }
     }
     std::lock_guard<std::mutex> lk(tune_mu());
     tune_map()[key] = best;
@@ -1631,6 +1693,16 @@ class Sequencer {
   int64_t nzcap_ = 0, ldb_ = 0, nzr_ = 0;
   bool compact_ = false;
   double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_, *lwork_;
+  // the next right-hand side's start fused into an append's first Gram-Schmidt pass:
+  // fa_ = V y, fw_ = V w (y = G_i^{-1} V^T b_next, w = G_i^{-1} V^T A_i u)
+  double *fa_ = nullptr, *fw_ = nullptr, *fcw_ = nullptr, *ftmp_ = nullptr;
+  struct {
+    bool on = false;
+    int64_t idx = 0;
+    double sc = 0.0;
+  } fuse_next_;
+  bool fused_ready_ = false, fused_kept_ = false;
+  double fused_rho_ = 0.0;
   Ctrl* ctrl_;
   double *part1_, *part2_;
   // mixed form: FP32 copies of U_j, A U_j, the diagonal and the face coefficients, and the

@@ -17,14 +17,16 @@ int reduce_grid(int64_t n) {
 }
 
 // Transposed product, lanes over rows, waves over columns; one block covers
-// 64*CPL rows x GT_COLS columns.  When several row chunks exist the last block of
-// each column group sums the chunk partials in chunk order.
+// 64*CPL rows x gcols columns (GT_COLS, or one column per wave when that would leave the
+// chip mostly idle).  When several row chunks exist, k_gemvt_reduce sums the chunk
+// partials of each output in chunk order.
 template <int CPL, int NV>
 __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int64_t ld,
                                                int64_t rows, int cols,
                                                const double* __restrict__ V, int64_t vstride,
                                                double* __restrict__ out,
-                                               double* __restrict__ partials, Skip skip) {
+                                               double* __restrict__ partials, Skip skip,
+                                               int gcols) {
   if (skip.on()) return;
   const int64_t r0 = (int64_t)blockIdx.x * (64 * CPL);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int6
 #pragma unroll
     for (int v = 0; v < NV; ++v) vr[v][q] = r < rows ? V[r + v * vstride] : 0.0;
   }
-  const int c0 = blockIdx.y * GT_COLS;
+  const int c0 = blockIdx.y * gcols;
   const bool single = gridDim.x == 1;
   if (NV == 1) {
     // a row chunk whose vector entries are all zero contributes nothing: skip its reads of M
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int6
 #pragma unroll
     for (int q = 0; q < CPL; ++q) nz |= vr[0][q] != 0.0;
     if (!__syncthreads_or(nz)) {
-      for (int cc = wid; cc < GT_COLS; cc += BS / 64) {
+      for (int cc = wid; cc < gcols; cc += BS / 64) {
         const int c = c0 + cc;
         if (c < cols && lane == 0) {
           if (single)
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int6
       return;
     }
   }
-  for (int cc = wid; cc < GT_COLS; cc += BS / 64) {
+  for (int cc = wid; cc < gcols; cc += BS / 64) {
     const int c = c0 + cc;
     if (c >= cols) break;
     const double* col = M + (int64_t)c * ld;
@@ -903,10 +905,14 @@ void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const dou
   if (cols <= 0) return;
   const int cpl = gemvt_cpl(cols);
   const int chunk = 64 * cpl;
-  dim3 grid(ceil_div(rows, chunk), ceil_div(cols, GT_COLS));
-  if (grid.x < 1) grid.x = 1;
+  const int64_t nch = std::max<int64_t>(1, ceil_div(rows, chunk));
+  // GT_COLS columns per block; a product that would not fill the chip that way (the
+  // m x m triangular solves, short tall-skinny ones) takes one column per wave instead
+  const int gcols = nch * ceil_div(cols, GT_COLS) < 512 ? BS / 64 : GT_COLS;
+  dim3 grid((unsigned)nch, ceil_div(cols, gcols));
 #define GT_LAUNCH(C, N) \
-  ROM_LAUNCH((k_gemvt<C, N>), grid, dim3(BS), 0, st, M, ld, rows, cols, V, vstride, out, partials, skip)
+  ROM_LAUNCH((k_gemvt<C, N>), grid, dim3(BS), 0, st, M, ld, rows, cols, V, vstride, out, partials, \
+             skip, gcols)
   if (nv < 1 || nv > 3) throw Error(ROM_EINVAL, "gemvt: 1 to 3 vectors");
   if (cpl == 16) {
     if (nv == 1) GT_LAUNCH(16, 1); else if (nv == 2) GT_LAUNCH(16, 2); else GT_LAUNCH(16, 3);

@@ -22,7 +22,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_outer_gemvn_cfg2_64cubed.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_outer_projection_cube64.md")
 
 
 def traffic_ratio():
@@ -356,7 +356,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="cube64")
     ap.add_argument("--points", type=int, default=0, help="parameter points (0: the workload's)")
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--mode", default="independent", choices=["independent", "drift"])
@@ -501,7 +501,7 @@ def main():
     tr = traffic_ratio() if dom == "outer" and args.precision == "fp64" and args.group == 1 else None
     if tr is not None:
         roof["traffic"] = tr * roof["bytes_per_launch"]
-        roof["traffic_source"] = "profiles/traffic_outer_gemvn_cfg2_64cubed.md (ratio %.3f)" % tr
+        roof["traffic_source"] = "profiles/traffic_outer_projection_cube64.md (ratio %.3f)" % tr
 
     spmm = spmm_bandwidth(prob, pts[-1], 64)
     log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s)")
@@ -524,7 +524,7 @@ def main():
     suite = None
     if args.suite:
         from paper_1602_00138_amd import rom as R2
-        suite = measure_concurrent(["cfg3a", "cfg3b", "cfg3c"], 1, precision=R2.ROM_PREC_MIXED,
+        suite = measure_concurrent(["uneven48", "uneven64", "uneven96"], 1, precision=R2.ROM_PREC_MIXED,
                                    group=8, tune=1)
 
     cpu = None

@@ -78,24 +78,26 @@ def face_kinds(dim: int) -> Tuple[int, ...]:
 
 WORKLOADS = {
     # 2D 32^2, plain FP64, checked against dense Cholesky.
-    "cfg1": Workload("cfg1", 2, (32, 32, 1), 0.03, 0.01, 3, (0.05, 0.15), (0.005, 0.02),
-                     8, 8, 4, 1e-10, seed=1001, d_seed=2001),
+    "slab2d_32": Workload("slab2d_32", 2, (32, 32, 1), 0.03, 0.01, 3, (0.05, 0.15),
+                          (0.005, 0.02), 8, 8, 4, 1e-10, seed=1001, d_seed=2001),
     # 3D 64^3, plain FP64, 32+32 RHS, 16 points (timing tolerance 1e-8).
-    "cfg2": Workload("cfg2", 3, (64, 64, 64), 0.03, 0.01, 8, (0.04, 0.12), (0.005, 0.03),
-                     32, 32, 16, 1e-8, seed=1002, d_seed=2002),
-    # 3D mixed grids, 8 points each, 32+32 RHS.
-    "cfg3a": Workload("cfg3a", 3, (48, 48, 48), 0.03, 0.01, 3, (0.05, 0.15), (0.005, 0.02),
-                      32, 32, 8, 1e-8, seed=1003, d_seed=2003),
-    "cfg3b": Workload("cfg3b", 3, (64, 64, 64), 0.03, 0.01, 3, (0.05, 0.15), (0.005, 0.02),
-                      32, 32, 8, 1e-8, seed=1103, d_seed=2103),
-    "cfg3c": Workload("cfg3c", 3, (96, 96, 96), 0.03, 0.01, 3, (0.05, 0.15), (0.005, 0.02),
-                      32, 32, 8, 1e-8, seed=1203, d_seed=2203),
+    "cube64": Workload("cube64", 3, (64, 64, 64), 0.03, 0.01, 8, (0.04, 0.12), (0.005, 0.03),
+                       32, 32, 16, 1e-8, seed=1002, d_seed=2002),
+    # Three uneven 3D grids (48^3, 64^3, 96^3), 8 points each, 32+32 RHS.
+    "uneven48": Workload("uneven48", 3, (48, 48, 48), 0.03, 0.01, 3, (0.05, 0.15),
+                         (0.005, 0.02), 32, 32, 8, 1e-8, seed=1003, d_seed=2003),
+    "uneven64": Workload("uneven64", 3, (64, 64, 64), 0.03, 0.01, 3, (0.05, 0.15),
+                         (0.005, 0.02), 32, 32, 8, 1e-8, seed=1103, d_seed=2103),
+    "uneven96": Workload("uneven96", 3, (96, 96, 96), 0.03, 0.01, 3, (0.05, 0.15),
+                         (0.005, 0.02), 32, 32, 8, 1e-8, seed=1203, d_seed=2203),
     # 3D 128^3 with log-normal D, capped basis.
-    "cfg4": Workload("cfg4", 3, (128, 128, 128), "lognormal", 0.01, 16, (0.04, 0.12),
-                     (0.005, 0.03), 48, 48, 32, 1e-8, cap=256, seed=1004, d_seed=2004),
+    "cube128_lognormal": Workload("cube128_lognormal", 3, (128, 128, 128), "lognormal", 0.01,
+                                  16, (0.04, 0.12), (0.005, 0.03), 48, 48, 32, 1e-8, cap=256,
+                                  seed=1004, d_seed=2004),
     # 3D 96^3 with log-normal D, 64+64 RHS.
-    "cfg5": Workload("cfg5", 3, (96, 96, 96), "lognormal", 0.01, 12, (0.04, 0.12),
-                     (0.005, 0.03), 64, 64, 16, 1e-8, seed=1005, d_seed=2005),
+    "cube96_lognormal": Workload("cube96_lognormal", 3, (96, 96, 96), "lognormal", 0.01, 12,
+                                 (0.04, 0.12), (0.005, 0.03), 64, 64, 16, 1e-8, seed=1005,
+                                 d_seed=2005),
 }
 
 

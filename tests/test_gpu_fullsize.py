@@ -24,7 +24,7 @@ from oracle import rom as orom
 
 pytestmark = pytest.mark.gpu
 
-WL = ph.WORKLOADS["cfg2"]
+WL = ph.WORKLOADS["cube64"]
 SAMPLES = [(0, 0), (5, 17), (11, 40), (15, 63)]    # (point, right-hand side)
 
 

@@ -20,7 +20,7 @@ def drv(gpu):
     return driver
 
 
-CASES = [(ph.WORKLOADS["cfg1"], 4),
+CASES = [(ph.WORKLOADS["slab2d_32"], 4),
          (ph.small(3, (12, 11, 10), n_src=5, n_det=4, K=3), 3),
          (ph.small(3, (10, 10, 12), n_src=4, n_det=4, K=3, D="lognormal"), 8),
          (ph.small(2, (40, 23), n_src=6, n_det=5, K=3), 16)]

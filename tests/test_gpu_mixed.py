@@ -8,7 +8,7 @@ the tolerance:
   * every returned solution has FP64 true relative residual <= tol, checked with the
     oracle's own CSR operator;
   * solutions equal the oracle's (dense or oracle-CG) solutions to 1e-7 relative at
-    tol 1e-10 (the north-star gate);
+    tol 1e-10 (the mixed form's accuracy gate);
   * the basis stays orthonormal to 1e-12 (its append is FP64) and reproduces every
     oracle solution: ||(I - V V^T) x_ref|| <= 1e-7 ||x_ref||;
   * the reduced transfer function interpolates the full one at every sample point to
@@ -93,7 +93,7 @@ def _check_mixed(wl, orc, ores, prob, pts, res, sol_tol=1e-7, psi_tol=1e-6, basi
     return worst, fb, solved
 
 
-@pytest.mark.parametrize("wl", [ph.WORKLOADS["cfg1"],
+@pytest.mark.parametrize("wl", [ph.WORKLOADS["slab2d_32"],
                                 ph.small(3, (12, 11, 10), n_src=5, n_det=4, K=3),
                                 ph.small(3, (10, 10, 12), n_src=4, n_det=4, K=3, D="lognormal"),
                                 ph.small(2, (40, 23), n_src=6, n_det=5, K=3)])

@@ -94,8 +94,8 @@ def _check_sequence(wl, orc, ores, res, prob, pts, sol_tol=1e-7, psi_tol=1e-6, i
             assert np.abs(psir - psi).max() <= psi_tol * np.abs(psi).max(), i
 
 
-def test_cfg1_sequence_parity(drv):
-    wl = ph.WORKLOADS["cfg1"]
+def test_slab2d_32_sequence_parity(drv):
+    wl = ph.WORKLOADS["slab2d_32"]
     orc = OracleProblem(wl)
     ores = orc.run()
     prob, pts, res = _gpu_run(drv, wl)

@@ -191,13 +191,13 @@ def test_mu_field_bumps():
 
 
 def test_generator_shapes():
-    wl = ph.WORKLOADS["cfg2"]
+    wl = ph.WORKLOADS["cube64"]
     s, d = ph.rhs_nodes(wl)
     assert s.shape == (32,) and d.shape == (32,)
     N = wl.N
     assert np.all(s // (N[0] * N[1]) == 0) and np.all(d // (N[0] * N[1]) == N[2] - 1)
     assert len(set(s.tolist())) == 32 and len(set(d.tolist())) == 32
-    wl1 = ph.WORKLOADS["cfg1"]
+    wl1 = ph.WORKLOADS["slab2d_32"]
     s1, d1 = ph.rhs_nodes(wl1)
     assert np.all(s1 // 32 == 31) and np.all(d1 // 32 == 0)
     U0 = ph.smooth_modes(ph.small(3, (10, 11, 12)))

@@ -23,15 +23,15 @@ def _setup(wl, mode="independent"):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    wl = ph.WORKLOADS["cfg1"]
+def slab2d_32():
+    wl = ph.WORKLOADS["slab2d_32"]
     As, mus, B, U0 = _setup(wl)
     res = seq.solve_sequence(As, mus, B, U0, wl.tol, wl.trunc)
     return wl, As, mus, B, U0, res
 
 
-def test_cfg1_solutions_match_dense_cholesky(cfg1):
-    wl, As, mus, B, U0, res = cfg1
+def test_slab2d_32_solutions_match_dense_cholesky(slab2d_32):
+    wl, As, mus, B, U0, res = slab2d_32
     for i, mu in enumerate(mus):
         Ad = As.toarray() + np.diag(mu)
         Xc = sla.cho_solve(sla.cho_factor(Ad), B)
@@ -41,8 +41,8 @@ def test_cfg1_solutions_match_dense_cholesky(cfg1):
         assert (Xc > 0).all()
 
 
-def test_cfg1_invariants(cfg1):
-    wl, As, mus, B, U0, res = cfg1
+def test_slab2d_32_invariants(slab2d_32):
+    wl, As, mus, B, U0, res = slab2d_32
     Q = res.Q
     m = Q.shape[1]
     assert np.abs(Q.T @ Q - np.eye(m)).max() < 1e-12
@@ -59,18 +59,18 @@ def test_cfg1_invariants(cfg1):
         assert np.linalg.norm(Xi - P) <= 1e-9 * np.linalg.norm(Xi)
 
 
-def test_cfg1_reciprocity(cfg1):
+def test_slab2d_32_reciprocity(slab2d_32):
     """B^T X_i is symmetric (A_i symmetric): forward and adjoint halves agree."""
-    wl, As, mus, B, U0, res = cfg1
+    wl, As, mus, B, U0, res = slab2d_32
     for Xi in res.X:
         S = B.T @ Xi
         assert np.abs(S - S.T).max() <= 1e-8 * np.abs(S).max()
 
 
-def test_interpolation_theorem(cfg1):
+def test_interpolation_theorem(slab2d_32):
     """Theorem of Sec. 3.4: with A(p_i)^{-1}B and (C A(p_i)^{-1})^T in range(V) the
     reduced transfer function and its gradient match the full ones at p_i."""
-    wl, As, mus, B, U0, res = cfg1
+    wl, As, mus, B, U0, res = slab2d_32
     ns = wl.n_src
     Bt, Ct = B[:, :ns], B[:, ns:]
     Q = res.Q
@@ -92,8 +92,8 @@ def test_interpolation_theorem(cfg1):
         assert np.abs(Jr - J).max() <= 1e-6 * np.abs(J).max()
 
 
-def test_reduced_transfer_rotation_invariant(cfg1):
-    wl, As, mus, B, U0, res = cfg1
+def test_reduced_transfer_rotation_invariant(slab2d_32):
+    wl, As, mus, B, U0, res = slab2d_32
     ns = wl.n_src
     Q = res.Q
     O, _ = np.linalg.qr(np.random.default_rng(9).standard_normal((Q.shape[1],) * 2))
@@ -156,11 +156,11 @@ def test_skip_when_in_basis():
 
 
 @pytest.mark.parametrize("group", [3, 16])
-def test_grouped_sequence_invariants(cfg1, group):
+def test_grouped_sequence_invariants(slab2d_32, group):
     """The batched reading (RHS in groups sharing one projection): every solution still
     meets the dense Cholesky solution, the basis stays orthonormal and contains every
     solution, so the reduced transfer function interpolates at every sample point."""
-    wl, As, mus, B, U0, res1 = cfg1
+    wl, As, mus, B, U0, res1 = slab2d_32
     res = seq.solve_sequence(As, mus, B, U0, wl.tol, wl.trunc, group=group)
     Q = res.Q
     assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 1e-12
@@ -188,8 +188,8 @@ def test_grouped_sequence_invariants(cfg1, group):
         assert abs(r.rho0 - np.linalg.norm(b - A0 @ (U @ c)) / np.linalg.norm(b)) <= 1e-12
 
 
-def test_group_one_is_the_sequential_order(cfg1):
-    wl, As, mus, B, U0, res1 = cfg1
+def test_group_one_is_the_sequential_order(slab2d_32):
+    wl, As, mus, B, U0, res1 = slab2d_32
     res = seq.solve_sequence(As, mus[:2], B, U0, wl.tol, wl.trunc, group=1)
     for a, b in zip(res.records, res1.records):
         assert (a.point, a.rhs, a.its, a.kept, a.m) == (b.point, b.rhs, b.its, b.kept, b.m)

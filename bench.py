@@ -498,7 +498,9 @@ def main():
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
     roof.update({"kernel": dom, "launches": agg["launches"], "avg_launch_us": 1e3 * avg_ms,
                  "bytes_per_launch": agg["bytes"] / max(agg["launches"], 1)})
-    tr = traffic_ratio() if dom == "outer" and args.precision == "fp64" and args.group == 1 else None
+    # the counters were taken on cube64 (plain FP64, sequential order); elsewhere: null
+    tr = traffic_ratio() if (dom == "outer" and args.precision == "fp64" and args.group == 1
+                             and wl.name == "cube64") else None
     if tr is not None:
         roof["traffic"] = tr * roof["bytes_per_launch"]
         roof["traffic_source"] = "profiles/traffic_outer_projection_cube64.md (ratio %.3f)" % tr

@@ -44,10 +44,14 @@ def test_apply_operator_matches_oracle(drv, wl):
     prob.close()
 
 
-def _check_sequence(wl, orc, ores, res, prob, pts, sol_tol=1e-7, psi_tol=1e-6, interpolates=True):
+def _check_sequence(wl, orc, ores, res, prob, pts, sol_tol=1e-7, psi_tol=1e-6, interpolates=True,
+                    trunc=None):
     """interpolates: every solution lies in range(V) (no cap), so the reduced transfer
-    function equals the full one at the sample points (Theorem of Sec. 3.4)."""
+    function equals the full one at the sample points (Theorem of Sec. 3.4).  A skip
+    decision within 1% of tol, or a keep decision within rounding (1e-6) of trunc, may
+    differ."""
     n_rhs = wl.n_rhs
+    trunc = wl.trunc if trunc is None else trunc
     # decisions and counts
     assert len(res.records) == len(ores.records)
     for g, o in zip(res.records, ores.records):
@@ -57,7 +61,8 @@ def _check_sequence(wl, orc, ores, res, prob, pts, sol_tol=1e-7, psi_tol=1e-6, i
         assert abs(g["rho0"] - o.rho0) <= 1e-3 * o.rho0 + 1e-12, (g, o)
         if g["solved"] and o.solved and not near:
             assert abs(g["its"] - o.its) <= 2, (g, o)
-            assert bool(g["kept"]) == o.kept, (g, o)
+            if not abs(g["rho"] - trunc) < 1e-6 * trunc:
+                assert bool(g["kept"]) == o.kept, (g, o)
         assert g["converged"] and g["final_res"] <= wl.tol * (1 + 1e-6)
     assert res.m == ores.Q.shape[1]
     # solutions against direct solves
@@ -145,6 +150,27 @@ def test_no_recycle_seed(drv):
     prob, pts, res = _gpu_run(drv, wl, k_u=0)
     assert res.stats["k_u"] == 0
     _check_sequence(wl, orc, ores, res, prob, pts)
+
+
+def test_truncated_corrections(drv):
+    """A large truncation threshold drops many corrections; the right-hand side after a
+    dropped one starts from V y (V unchanged) instead of the bordered start.  Decisions,
+    solutions and the basis against the oracle run with the same threshold."""
+    # rho (the share of a unit correction outside V) is 0.97-1.0 here, as a correction is
+    # A-orthogonal to V; trunc = 0.982 drops 5 of the 18 corrections and sits at least 0.28%
+    # from every rho of this sequence (oracle), far beyond the FP64 differences of the sides
+    wl = ph.small(3, (10, 9, 8), n_src=3, n_det=3, K=3, tol=1e-10, D="lognormal")
+    trunc = 0.982
+    orc = OracleProblem(wl)
+    ores = orc.run(trunc=trunc)
+    prob, pts, res = _gpu_run(drv, wl, trunc=trunc)
+    recs = res.records
+    dropped_then_solved = [
+        (a["point"], a["rhs"]) for a, b in zip(recs, recs[1:])
+        if a["solved"] and not a["kept"] and b["solved"] and b["point"] == a["point"]]
+    assert dropped_then_solved, "the pattern this test is for did not occur"
+    assert any(r["solved"] and r["kept"] for r in recs)
+    _check_sequence(wl, orc, ores, res, prob, pts, interpolates=False, trunc=trunc)
 
 
 def test_cap_and_repeated_point(drv):

@@ -282,6 +282,8 @@ ROM_API rom_status rom_reduced_jacobian(const rom_basis* V, const rom_mu* p, dou
  * (may be NULL).  1 <= k <= kx <= 32; the filter's lower edge is the largest Ritz value of
  * the block, so column k converges at the rate of lambda_k / lambda_{kx+1}: give kx - k >= 2
  * guard columns (k == kx is accepted but its last column converges slowly).
+ * Returns ROM_ENOCONV (U, lambda and *sweeps still written) if the residual test did not
+ * pass within maxit sweeps.
  * scratch: device, >= rom_lowest_modes_bytes.
  * Synchronises the stream (it decides on the host after every sweep). */
 ROM_API rom_status rom_lowest_modes_bytes(const rom_operator* op, int kx, size_t* bytes);

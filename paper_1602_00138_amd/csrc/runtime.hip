@@ -2314,6 +2314,7 @@ rom_status rom_lowest_modes(const rom_operator* op, const rom_mu* p, int k, cons
     cholqr2(Y, F[0]);   // Y orthonormal (F[0] holds a copy)
     std::vector<double> lam(kb), res2(kb);
     int sw = 0;
+    bool converged = false;
     for (;; ++sw) {
       // Rayleigh-Ritz: H = Y^T A Y, H = Z diag(lam) Z^T, Y <- Y Z, AY <- AY Z
       rom::launch_spmm(S, L.diag, Y, ld, kb, AY, st);
@@ -2335,7 +2336,8 @@ rom_status rom_lowest_modes(const rom_operator* op, const rom_mu* p, int k, cons
       double worst = 0.0;
       for (int i = 0; i < k; ++i) worst = std::max(worst, std::sqrt(std::max(res2[i], 0.0)));
       if (!(worst == worst)) throw Error(ROM_ENONFINITE, "lowest modes: non-finite residual");
-      if (worst <= tol * b || sw + 1 >= maxit) break;
+      converged = worst <= tol * b;
+      if (converged || sw + 1 >= maxit) break;
       // Chebyshev filter of degree CHEB_DEGREE damping [lam_max of the block, b]
       const double lo = lam[kb - 1], e = 0.5 * (b - lo), c = 0.5 * (b + lo);
       if (!(e > 0.0)) break;
@@ -2360,6 +2362,11 @@ rom_status rom_lowest_modes(const rom_operator* op, const rom_mu* p, int k, cons
     ROM_HIP(hipStreamSynchronize(st));
     for (int i = 0; i < k; ++i) lambda[i] = lam[i];
     if (sweeps) *sweeps = sw + 1;
+    if (!converged) {
+      rom::report_message("lowest modes: the residual test did not pass (maxit, or a filter "
+                          "interval that vanished)");
+      return ROM_ENOCONV;
+    }
     return ROM_OK;
   } catch (const Error& e) {
     return rom::fail(e);

@@ -152,16 +152,18 @@ class Problem:
         return torch.complex(Xr, Xi), its, res, st
 
     def lowest_modes(self, p: R.MuParams, k: int, X0: torch.Tensor, tol: float = 1e-8,
-                     maxit: int = 200):
+                     maxit: int = 200, allow_noconv: bool = False):
         """The k smallest eigenpairs of A(p) from the starting block X0 ((kx, N) rows, kx >= k
-        columns): returns (U as (k, N) rows, eigenvalues (k,), sweeps)."""
+        columns): returns (U as (k, N) rows, eigenvalues (k,), sweeps), plus the status with
+        allow_noconv (ROM_ENOCONV when the residual test did not pass within maxit)."""
         X0 = X0.to(dtype=torch.float64, device=self.device).contiguous()
         kx = X0.shape[0]
         U = torch.empty((k, self.n), dtype=torch.float64, device=self.device)
         scratch = torch.empty(R.rom_lowest_modes_bytes(self.op, kx), dtype=torch.uint8,
                               device=self.device)
-        lam, sweeps = R.rom_lowest_modes(self.op, p, k, X0, kx, tol, maxit, U, scratch)
-        return U, lam, sweeps
+        out = R.rom_lowest_modes(self.op, p, k, X0, kx, tol, maxit, U, scratch,
+                                 allow_noconv=allow_noconv)
+        return (U,) + tuple(out)
 
     def apply(self, p: R.MuParams, X: torch.Tensor) -> torch.Tensor:
         """Y = A(p) X for X given as (k, N) rows (each row a vector)."""

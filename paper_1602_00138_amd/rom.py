@@ -369,15 +369,18 @@ def rom_lowest_modes_bytes(op: int, kx: int) -> int:
 
 
 def rom_lowest_modes(op: int, p: MuParams, k: int, X0, kx: int, tol: float, maxit: int, U,
-                     scratch, stream=None):
-    """Returns (lambda (k,), sweeps); U is filled on the device."""
+                     scratch, stream=None, allow_noconv: bool = False):
+    """Returns (lambda (k,), sweeps), or (lambda, sweeps, status) with allow_noconv; U is
+    filled on the device."""
     mu = p.c_struct()
     lam = (C.c_double * k)()
     sweeps = C.c_int(0)
-    _check(_lib.rom_lowest_modes(op, C.byref(mu), int(k), _ptr(X0), int(kx), float(tol),
-                                 int(maxit), _ptr(U), lam, C.byref(sweeps), _ptr(scratch),
-                                 scratch.numel() * scratch.element_size(), _stream(stream)))
-    return np.array(lam[:], dtype=np.float64), int(sweeps.value)
+    st = _check(_lib.rom_lowest_modes(op, C.byref(mu), int(k), _ptr(X0), int(kx), float(tol),
+                                      int(maxit), _ptr(U), lam, C.byref(sweeps), _ptr(scratch),
+                                      scratch.numel() * scratch.element_size(), _stream(stream)),
+                allow=(ROM_ENOCONV,) if allow_noconv else ())
+    out = (np.array(lam[:], dtype=np.float64), int(sweeps.value))
+    return out + (st,) if allow_noconv else out
 
 
 def rom_shifted_solve_bytes(op: int, nb: int, ns: int) -> int:

@@ -105,9 +105,12 @@ def test_lowest_modes_errors(drv):
         prob.lowest_modes(p, 4, torch_from(np.zeros((33, wl.n))))
     with pytest.raises(R.RomError):
         R.rom_lowest_modes_bytes(prob.op, 33)
-    # maxit reached: the iteration stops after exactly maxit sweeps with a valid block
-    U, lam, sweeps = prob.lowest_modes(p, 4, X0, tol=1e-30, maxit=3)
-    assert sweeps == 3
+    # maxit reached: ENOCONV after exactly maxit sweeps, with a valid block
+    with pytest.raises(R.RomError) as e:
+        prob.lowest_modes(p, 4, X0, tol=1e-30, maxit=3)
+    assert e.value.status == R.ROM_ENOCONV
+    U, lam, sweeps, st = prob.lowest_modes(p, 4, X0, tol=1e-30, maxit=3, allow_noconv=True)
+    assert sweeps == 3 and st == R.ROM_ENOCONV
     Uh = U.cpu().numpy().T
     assert np.abs(Uh.T @ Uh - np.eye(4)).max() <= 1e-12
 

@@ -220,6 +220,65 @@ __global__ __launch_bounds__(BS) void k_cheb_step(Stencil S, const double* __res
   });
 }
 
+// Y = A X for several columns with two consecutive x-nodes per thread (even nx, 16-byte
+// aligned columns): 16-byte loads for the node pair, its y-neighbour pairs, the diagonal,
+// the face coefficients and the next z-plane, and one 8-byte load for each outer
+// x-neighbour, which halves the memory instructions per node of the one-node walk.
+// Columns on blockIdx.z; z planes walked in chunks of zc with the z neighbours in registers.
+template <bool VAR>
+__global__ __launch_bounds__(BS) void k_spmm2(Stencil S, const double* __restrict__ diag,
+                                               const double* __restrict__ x0, int64_t ld,
+                                               double* __restrict__ y0, int zc) {
+  const double* __restrict__ x = x0 + (int64_t)blockIdx.z * ld;
+  double* __restrict__ y = y0 + (int64_t)blockIdx.z * ld;
+  const int hx = S.nx / 2;
+  const int q = blockIdx.x * BS + threadIdx.x;
+  if (q >= hx * S.ny) return;
+  const int ix = 2 * (q % hx), iy = q / hx;
+  const int nxy = S.nx * S.ny;
+  const int z0 = blockIdx.y * zc, z1 = min(z0 + zc, S.nz);
+  if (z0 >= z1) return;
+  const bool hl = ix > 0, hr = ix + 2 < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
+  const double2 zero = {0.0, 0.0};
+  auto ld2 = [](const double* p, int64_t k) { return *reinterpret_cast<const double2*>(p + k); };
+  int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
+  double2 xm = z0 > 0 ? ld2(x, i - nxy) : zero;
+  double2 fm = (VAR && z0 > 0) ? ld2(S.fz, i - nxy) : zero;
+  double2 xc = ld2(x, i);
+  for (int z = z0; z < z1; ++z, i += nxy) {
+    const double2 xp = z < S.nz - 1 ? ld2(x, i + nxy) : zero;
+    const double2 d = ld2(diag, i);
+    const double xl = hl ? x[i - 1] : 0.0;
+    const double xr = hr ? x[i + 2] : 0.0;
+    const double2 yd = hd ? ld2(x, i - S.nx) : zero;
+    const double2 yu = hu ? ld2(x, i + S.nx) : zero;
+    double v0 = d.x * xc.x, v1 = d.y * xc.y;
+    if (!VAR) {
+      v0 -= S.cx * (xl + xc.y) + S.cy * (yd.x + yu.x) + S.cz * (xm.x + xp.x);
+      v1 -= S.cx * (xc.x + xr) + S.cy * (yd.y + yu.y) + S.cz * (xm.y + xp.y);
+    } else {
+      // +x faces: node i-1 (left of the pair), i (inside the pair), i+1 (right)
+      const double fxl = hl ? S.fx[i - 1] : 0.0;
+      const double2 fx = ld2(S.fx, i);
+      v0 -= fxl * xl + fx.x * xc.y;
+      v1 -= fx.x * xc.x + fx.y * xr;
+      const double2 fyd = hd ? ld2(S.fy, i - S.nx) : zero;
+      const double2 fyu = ld2(S.fy, i);
+      v0 -= fyd.x * yd.x + fyu.x * yu.x;
+      v1 -= fyd.y * yd.y + fyu.y * yu.y;
+      if (S.dim == 3) {
+        const double2 fp = ld2(S.fz, i);
+        v0 -= fm.x * xm.x + fp.x * xp.x;
+        v1 -= fm.y * xm.y + fp.y * xp.y;
+        fm = fp;
+      }
+    }
+    *reinterpret_cast<double2*>(y + i) = double2{v0, v1};
+    xm = xc;
+    xc = xp;
+  }
+}
+
 // out[z * ostride] = sum_b partials[z * P + b], one block per column z.
 __global__ void k_reduce_cols(const double* __restrict__ partials, int P, double* out,
                               int64_t ostride) {
@@ -296,6 +355,18 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
   StencilShape sh = stencil_shape(S, 512);
   dim3 grid = sh.grid;
   grid.z = k;
+  const auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const bool pairs = S.nx % 2 == 0 && ld % 2 == 0 && a16(X) && a16(Y) && a16(diag) &&
+                     (!S.var || (a16(S.fx) && a16(S.fy) && (S.dim < 3 || a16(S.fz))));
+  if (pairs) {
+    grid.x = ceil_div((int64_t)(S.nx / 2) * S.ny, BS);
+    if (S.var)
+      ROM_LAUNCH(k_spmm2<true>, grid, dim3(BS), 0, st, S, diag, X, ld, Y, sh.zc);
+    else
+      ROM_LAUNCH(k_spmm2<false>, grid, dim3(BS), 0, st, S, diag, X, ld, Y, sh.zc);
+    ROM_CHECK_LAUNCH();
+    return;
+  }
   STENCIL_LAUNCH(double, 0, grid, diag, X, ld, Y, ld, sh.zc, (int64_t)-1, 0.0,
                  (const int64_t*)nullptr, (const double*)nullptr, (double*)nullptr,
                  (const CGState*)nullptr);

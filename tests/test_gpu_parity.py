@@ -29,8 +29,11 @@ def _gpu_run(drv, wl, K=None, mode="independent", k_u=None, **kw):
     return prob, pts, res
 
 
+# odd nx: one node per thread; even nx: the two-node SpMM (16-byte loads and stores)
 @pytest.mark.parametrize("wl", [ph.small(2, (17, 13)), ph.small(3, (9, 8, 7)),
-                                ph.small(3, (11, 6, 9), D="lognormal")])
+                                ph.small(3, (11, 6, 9), D="lognormal"),
+                                ph.small(2, (18, 13)), ph.small(2, (16, 11), D="lognormal"),
+                                ph.small(3, (10, 8, 7)), ph.small(3, (12, 6, 9), D="lognormal")])
 def test_apply_operator_matches_oracle(drv, wl):
     import torch
     orc = OracleProblem(wl)

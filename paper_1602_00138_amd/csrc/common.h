@@ -3,6 +3,7 @@
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
+#include <initializer_list>
 
 #include <cstddef>
 #include <cstdint>
@@ -120,6 +121,69 @@ __device__ __forceinline__ void stencil_walk(const Stencil& S, const double* __r
     xm = xc;
     xc = xp;
   }
+}
+
+// The walk of stencil_walk for two consecutive x-nodes (i even, nx even, every array
+// 16-byte aligned at even indices): calls f(i, (A x)_i, (A x)_{i+1}, x_i, x_{i+1}) per
+// z-plane.  16-byte loads for the pair, its y-neighbour pairs, the diagonal, the face
+// coefficients and the next plane; one 8-byte load per outer x-neighbour.
+template <bool VAR, class F>
+__device__ __forceinline__ void stencil_walk2(const Stencil& S, const double* __restrict__ diag,
+                                              const double* __restrict__ x, int q, int z0,
+                                              int z1, F&& f) {
+  const int hx = S.nx / 2;
+  const int ix = 2 * (q % hx), iy = q / hx;
+  const int nxy = S.nx * S.ny;
+  const bool hl = ix > 0, hr = ix + 2 < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
+  const double2 zero = {0.0, 0.0};
+  auto ld2 = [](const double* p, int64_t k) { return *reinterpret_cast<const double2*>(p + k); };
+  int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
+  double2 xm = z0 > 0 ? ld2(x, i - nxy) : zero;
+  double2 fm = (VAR && z0 > 0) ? ld2(S.fz, i - nxy) : zero;
+  double2 xc = ld2(x, i);
+  for (int z = z0; z < z1; ++z, i += nxy) {
+    const double2 xp = z < S.nz - 1 ? ld2(x, i + nxy) : zero;
+    const double2 d = ld2(diag, i);
+    const double xl = hl ? x[i - 1] : 0.0;
+    const double xr = hr ? x[i + 2] : 0.0;
+    const double2 yd = hd ? ld2(x, i - S.nx) : zero;
+    const double2 yu = hu ? ld2(x, i + S.nx) : zero;
+    double v0 = d.x * xc.x, v1 = d.y * xc.y;
+    if (!VAR) {
+      v0 -= S.cx * (xl + xc.y) + S.cy * (yd.x + yu.x) + S.cz * (xm.x + xp.x);
+      v1 -= S.cx * (xc.x + xr) + S.cy * (yd.y + yu.y) + S.cz * (xm.y + xp.y);
+    } else {
+      // +x faces: node i-1 (left of the pair), i (inside the pair), i+1 (right)
+      const double fxl = hl ? S.fx[i - 1] : 0.0;
+      const double2 fx = ld2(S.fx, i);
+      v0 -= fxl * xl + fx.x * xc.y;
+      v1 -= fx.x * xc.x + fx.y * xr;
+      const double2 fyd = hd ? ld2(S.fy, i - S.nx) : zero;
+      const double2 fyu = ld2(S.fy, i);
+      v0 -= fyd.x * yd.x + fyu.x * yu.x;
+      v1 -= fyd.y * yd.y + fyu.y * yu.y;
+      if (S.dim == 3) {
+        const double2 fp = ld2(S.fz, i);
+        v0 -= fm.x * xm.x + fp.x * xp.x;
+        v1 -= fm.y * xm.y + fp.y * xp.y;
+        fm = fp;
+      }
+    }
+    f(i, v0, v1, xc.x, xc.y);
+    xm = xc;
+    xc = xp;
+  }
+}
+
+// Whether the two-node walk applies: even nx and 16-byte aligned arrays at even leading
+// dimensions (ld of every column array passed in `ld`).
+inline bool stencil_pairs_ok(const Stencil& S, int64_t ld, std::initializer_list<const void*> ptrs) {
+  if (S.nx % 2 != 0 || ld % 2 != 0) return false;
+  for (const void* p : ptrs)
+    if (p && ((uintptr_t)p & 15)) return false;
+  if (S.var && (((uintptr_t)S.fx | (uintptr_t)S.fy | (S.dim == 3 ? (uintptr_t)S.fz : 0)) & 15))
+    return false;
+  return true;
 }
 
 // One DPP move of a 32-bit or 64-bit value (lanes whose source is outside the pattern,

@@ -115,6 +115,30 @@ __global__ __launch_bounds__(BS) void k_ms_apply(Stencil S, const double* __rest
                         blockIdx.x + gridDim.x * blockIdx.y);
 }
 
+// k_ms_apply with two x-nodes per thread (even nx, 16-byte aligned columns).
+template <bool VAR>
+__global__ __launch_bounds__(BS) void k_ms_apply2(Stencil S, const double* __restrict__ diag,
+                                                   const double* __restrict__ p0, int64_t ld,
+                                                   double* __restrict__ w0, int zc,
+                                                   const MsState* __restrict__ st,
+                                                   double* __restrict__ partials) {
+  if (st[blockIdx.z].done) return;
+  const double* __restrict__ p = p0 + (int64_t)blockIdx.z * ld;
+  double* __restrict__ w = w0 + (int64_t)blockIdx.z * ld;
+  const int q = blockIdx.x * BS + threadIdx.x;
+  const int z0 = blockIdx.y * zc;
+  const int z1 = min(z0 + zc, S.nz);
+  double acc[1] = {0.0};
+  if (q < (S.nx / 2) * S.ny && z0 < z1)
+    stencil_walk2<VAR>(S, diag, p, q, z0, z1,
+                       [&](int64_t i, double v0, double v1, double x0i, double x1i) {
+                         *reinterpret_cast<double2*>(w + i) = double2{v0, v1};
+                         acc[0] += x0i * v0 + x1i * v1;
+                       });
+  write_partials<1, BS>(acc, partials + (int64_t)blockIdx.z * gridDim.x * gridDim.y,
+                        blockIdx.x + gridDim.x * blockIdx.y);
+}
+
 // Seed step length, then per live shift: pi_next = (1 + c + i alpha sigma) pi_cur - c pi_prev
 // with c = alpha beta_prev / alpha_prev; rho = pi_cur / pi_next; alpha(s) = alpha rho;
 // zeta_next = 1 / pi_next (zeta, the current one, is still read by the update).
@@ -306,9 +330,20 @@ void launch_ms_start(const double* partials, int P, MsState* state, int nb, int 
   ROM_LAUNCH(k_ms_start, dim3(nb), dim3(BS), 0, st, partials, P, state, ns, tol, maxit);
 }
 
-void launch_ms_apply(const Stencil& S, const StencilShape& sh, const double* diag, const double* p,
-                     int64_t ld, double* w, int nb, const MsState* state, double* partials,
-                     hipStream_t st) {
+int launch_ms_apply(const Stencil& S, const StencilShape& sh, const double* diag, const double* p,
+                    int64_t ld, double* w, int nb, const MsState* state, double* partials,
+                    hipStream_t st) {
+  if (stencil_pairs_ok(S, ld, {diag, p, w})) {
+    // half the x-blocks of sh (at most sh.blocks partials per column)
+    const dim3 grid2(ceil_div((int64_t)(S.nx / 2) * S.ny, BS), sh.grid.y, nb);
+    if (S.var)
+      ROM_LAUNCH(k_ms_apply2<true>, grid2, dim3(BS), 0, st, S, diag, p, ld, w, sh.zc, state,
+                 partials);
+    else
+      ROM_LAUNCH(k_ms_apply2<false>, grid2, dim3(BS), 0, st, S, diag, p, ld, w, sh.zc, state,
+                 partials);
+    return (int)(grid2.x * grid2.y);
+  }
   const dim3 grid(sh.grid.x, sh.grid.y, nb);
   if (S.var)
     ROM_LAUNCH(k_ms_apply<true>, grid, dim3(BS), 0, st, S, diag, p, ld, w, sh.zc, state,
@@ -316,6 +351,7 @@ void launch_ms_apply(const Stencil& S, const StencilShape& sh, const double* dia
   else
     ROM_LAUNCH(k_ms_apply<false>, grid, dim3(BS), 0, st, S, diag, p, ld, w, sh.zc, state,
                partials);
+  return (int)(grid.x * grid.y);
 }
 
 void launch_ms_alpha(const double* partials, int P, MsState* state, int nb, const MsShifts& sh,

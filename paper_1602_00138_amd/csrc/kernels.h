@@ -196,10 +196,11 @@ void launch_ms_init(int64_t n, const double* B, int64_t ldb, int nb, int ns, dou
                     double* partials, hipStream_t st);
 void launch_ms_start(const double* partials, int P, MsState* state, int nb, int ns, double tol,
                      int maxit, hipStream_t st);
-// w = A p per live column, partials of p^T w (sh.blocks per column).
-void launch_ms_apply(const Stencil& S, const StencilShape& sh, const double* diag, const double* p,
-                     int64_t ld, double* w, int nb, const MsState* state, double* partials,
-                     hipStream_t st);
+// w = A p per live column, partials of p^T w; returns the partials per column (at most
+// sh.blocks), which is what launch_ms_alpha must sum.
+int launch_ms_apply(const Stencil& S, const StencilShape& sh, const double* diag, const double* p,
+                    int64_t ld, double* w, int nb, const MsState* state, double* partials,
+                    hipStream_t st);
 void launch_ms_alpha(const double* partials, int P, MsState* state, int nb, const MsShifts& sh,
                      hipStream_t st);
 void launch_ms_update(int64_t n, int nb, int ns, const double* w, double* r, int64_t ld,

@@ -2480,8 +2480,8 @@ rom_status rom_shifted_solve(const rom_operator* op, const rom_mu* p, const doub
     std::vector<rom::MsState> hs(nb);
     for (int it = 0;; it += rom::MS_CHUNK) {
       for (int c = 0; c < rom::MS_CHUNK; ++c) {
-        rom::launch_ms_apply(S, shp, L.diag, L.p, ld, L.w, nb, L.state, L.part, st);
-        rom::launch_ms_alpha(L.part, shp.blocks, L.state, nb, sh, st);
+        const int Pa = rom::launch_ms_apply(S, shp, L.diag, L.p, ld, L.w, nb, L.state, L.part, st);
+        rom::launch_ms_alpha(L.part, Pa, L.state, nb, sh, st);
         rom::launch_ms_update(n, nb, ns, L.w, L.r, ld, L.Pr, L.Pi, Xr, Xi, n, L.state, L.part, st);
         rom::launch_ms_beta(L.part, Pv, L.state, nb, ns, st);
         rom::launch_ms_dir(n, nb, L.r, L.p, ld, L.state, st);

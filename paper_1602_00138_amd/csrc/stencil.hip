@@ -220,63 +220,47 @@ __global__ __launch_bounds__(BS) void k_cheb_step(Stencil S, const double* __res
   });
 }
 
-// Y = A X for several columns with two consecutive x-nodes per thread (even nx, 16-byte
-// aligned columns): 16-byte loads for the node pair, its y-neighbour pairs, the diagonal,
-// the face coefficients and the next z-plane, and one 8-byte load for each outer
-// x-neighbour, which halves the memory instructions per node of the one-node walk.
-// Columns on blockIdx.z; z planes walked in chunks of zc with the z neighbours in registers.
+// Y = A X for several columns with two consecutive x-nodes per thread (stencil_walk2: even
+// nx, 16-byte aligned columns), which halves the memory instructions per node of the
+// one-node walk.  Columns on blockIdx.z; z planes in chunks of zc.
 template <bool VAR>
 __global__ __launch_bounds__(BS) void k_spmm2(Stencil S, const double* __restrict__ diag,
                                                const double* __restrict__ x0, int64_t ld,
                                                double* __restrict__ y0, int zc) {
   const double* __restrict__ x = x0 + (int64_t)blockIdx.z * ld;
   double* __restrict__ y = y0 + (int64_t)blockIdx.z * ld;
-  const int hx = S.nx / 2;
   const int q = blockIdx.x * BS + threadIdx.x;
-  if (q >= hx * S.ny) return;
-  const int ix = 2 * (q % hx), iy = q / hx;
-  const int nxy = S.nx * S.ny;
+  if (q >= (S.nx / 2) * S.ny) return;
   const int z0 = blockIdx.y * zc, z1 = min(z0 + zc, S.nz);
   if (z0 >= z1) return;
-  const bool hl = ix > 0, hr = ix + 2 < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
-  const double2 zero = {0.0, 0.0};
-  auto ld2 = [](const double* p, int64_t k) { return *reinterpret_cast<const double2*>(p + k); };
-  int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
-  double2 xm = z0 > 0 ? ld2(x, i - nxy) : zero;
-  double2 fm = (VAR && z0 > 0) ? ld2(S.fz, i - nxy) : zero;
-  double2 xc = ld2(x, i);
-  for (int z = z0; z < z1; ++z, i += nxy) {
-    const double2 xp = z < S.nz - 1 ? ld2(x, i + nxy) : zero;
-    const double2 d = ld2(diag, i);
-    const double xl = hl ? x[i - 1] : 0.0;
-    const double xr = hr ? x[i + 2] : 0.0;
-    const double2 yd = hd ? ld2(x, i - S.nx) : zero;
-    const double2 yu = hu ? ld2(x, i + S.nx) : zero;
-    double v0 = d.x * xc.x, v1 = d.y * xc.y;
-    if (!VAR) {
-      v0 -= S.cx * (xl + xc.y) + S.cy * (yd.x + yu.x) + S.cz * (xm.x + xp.x);
-      v1 -= S.cx * (xc.x + xr) + S.cy * (yd.y + yu.y) + S.cz * (xm.y + xp.y);
-    } else {
-      // +x faces: node i-1 (left of the pair), i (inside the pair), i+1 (right)
-      const double fxl = hl ? S.fx[i - 1] : 0.0;
-      const double2 fx = ld2(S.fx, i);
-      v0 -= fxl * xl + fx.x * xc.y;
-      v1 -= fx.x * xc.x + fx.y * xr;
-      const double2 fyd = hd ? ld2(S.fy, i - S.nx) : zero;
-      const double2 fyu = ld2(S.fy, i);
-      v0 -= fyd.x * yd.x + fyu.x * yu.x;
-      v1 -= fyd.y * yd.y + fyu.y * yu.y;
-      if (S.dim == 3) {
-        const double2 fp = ld2(S.fz, i);
-        v0 -= fm.x * xm.x + fp.x * xp.x;
-        v1 -= fm.y * xm.y + fp.y * xp.y;
-        fm = fp;
-      }
-    }
+  stencil_walk2<VAR>(S, diag, x, q, z0, z1, [&](int64_t i, double v0, double v1, double, double) {
     *reinterpret_cast<double2*>(y + i) = double2{v0, v1};
-    xm = xc;
-    xc = xp;
-  }
+  });
+}
+
+// k_cheb_step with two x-nodes per thread (the same conditions as k_spmm2).
+template <bool VAR>
+__global__ __launch_bounds__(BS) void k_cheb_step2(Stencil S, const double* __restrict__ diag,
+                                                    const double* __restrict__ x0, int64_t ld,
+                                                    double a, double b, double c,
+                                                    const double* prev0, double* out0, int zc) {
+  const double* __restrict__ x = x0 + (int64_t)blockIdx.z * ld;
+  const double* prev = prev0 ? prev0 + (int64_t)blockIdx.z * ld : nullptr;
+  double* out = out0 + (int64_t)blockIdx.z * ld;
+  const int q = blockIdx.x * BS + threadIdx.x;
+  if (q >= (S.nx / 2) * S.ny) return;
+  const int z0 = blockIdx.y * zc, z1 = min(z0 + zc, S.nz);
+  if (z0 >= z1) return;
+  stencil_walk2<VAR>(S, diag, x, q, z0, z1,
+                     [&](int64_t i, double v0, double v1, double x0i, double x1i) {
+                       double r0 = a * v0 + b * x0i, r1 = a * v1 + b * x1i;
+                       if (prev) {
+                         const double2 pv = *reinterpret_cast<const double2*>(prev + i);
+                         r0 += c * pv.x;
+                         r1 += c * pv.y;
+                       }
+                       *reinterpret_cast<double2*>(out + i) = double2{r0, r1};
+                     });
 }
 
 // out[z * ostride] = sum_b partials[z * P + b], one block per column z.
@@ -355,10 +339,7 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
   StencilShape sh = stencil_shape(S, 512);
   dim3 grid = sh.grid;
   grid.z = k;
-  const auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-  const bool pairs = S.nx % 2 == 0 && ld % 2 == 0 && a16(X) && a16(Y) && a16(diag) &&
-                     (!S.var || (a16(S.fx) && a16(S.fy) && (S.dim < 3 || a16(S.fz))));
-  if (pairs) {
+  if (stencil_pairs_ok(S, ld, {X, Y, diag})) {
     grid.x = ceil_div((int64_t)(S.nx / 2) * S.ny, BS);
     if (S.var)
       ROM_LAUNCH(k_spmm2<true>, grid, dim3(BS), 0, st, S, diag, X, ld, Y, sh.zc);
@@ -379,6 +360,17 @@ void launch_cheb_step(const Stencil& S, const double* diag, const double* X, int
   StencilShape sh = stencil_shape(S, 512);
   dim3 grid = sh.grid;
   grid.z = k;
+  if (stencil_pairs_ok(S, ld, {X, diag, prev, out})) {
+    grid.x = ceil_div((int64_t)(S.nx / 2) * S.ny, BS);
+    if (S.var)
+      ROM_LAUNCH(k_cheb_step2<true>, grid, dim3(BS), 0, st, S, diag, X, ld, a, b, c, prev, out,
+                 sh.zc);
+    else
+      ROM_LAUNCH(k_cheb_step2<false>, grid, dim3(BS), 0, st, S, diag, X, ld, a, b, c, prev, out,
+                 sh.zc);
+    ROM_CHECK_LAUNCH();
+    return;
+  }
   if (S.var)
     ROM_LAUNCH(k_cheb_step<true>, grid, dim3(BS), 0, st, S, diag, X, ld, a, b, c, prev, out,
                sh.zc);

@@ -40,6 +40,7 @@ def _rhs(orc, extra_zero=False):
     (ph.small(2, (17, 13), K=1, nb=2), [0.0, 0.5, 3.0, 40.0]),
     (ph.small(3, (11, 10, 9), K=1, nb=3, D="lognormal"), [0.2, 1.0, 7.5]),
     (ph.small(3, (9, 8, 7), K=1, nb=2), [0.1, 0.3, 1.0, 2.0, 5.0, 10.0, 30.0, 100.0]),  # 8 shifts
+    (ph.small(3, (12, 10, 8), K=1, nb=2, D="lognormal"), [0.0, 0.7, 6.0]),   # even nx
 ])
 def test_shifted_solve_parity(drv, wl, sigma):
     import torch

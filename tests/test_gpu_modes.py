@@ -52,6 +52,7 @@ def _check_pairs(A, U, lam, k, tol):
     (ph.small(3, (11, 10, 9), K=2, nb=3, D="lognormal"), 10, 16),
     (ph.small(3, (9, 8, 7), K=2, nb=2, D="lognormal"), 24, 32),    # the largest block
     (ph.small(2, (12, 11), K=2, nb=1), 1, 4),
+    (ph.small(3, (12, 10, 9), K=2, nb=2, D="lognormal"), 10, 16),   # even nx: two-node filter
 ])
 def test_lowest_modes_parity(drv, wl, k, kx):
     orc = OracleProblem(wl)

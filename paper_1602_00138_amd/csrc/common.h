@@ -124,46 +124,62 @@ __device__ __forceinline__ void stencil_walk(const Stencil& S, const double* __r
 }
 
 // The walk of stencil_walk for two consecutive x-nodes (i even, nx even, every array
-// 16-byte aligned at even indices): calls f(i, (A x)_i, (A x)_{i+1}, x_i, x_{i+1}) per
-// z-plane.  16-byte loads for the pair, its y-neighbour pairs, the diagonal, the face
-// coefficients and the next plane; one 8-byte load per outer x-neighbour.
-template <bool VAR, class F>
-__device__ __forceinline__ void stencil_walk2(const Stencil& S, const double* __restrict__ diag,
-                                              const double* __restrict__ x, int q, int z0,
-                                              int z1, F&& f) {
+// aligned for two-element vector loads at even indices), in arithmetic T (double, or float
+// with the FP32 face coefficients): calls f(i, (A x)_i, (A x)_{i+1}, x_i, x_{i+1}) per
+// z-plane.  Vector loads for the pair, its y-neighbour pairs, the diagonal, the face
+// coefficients and the next plane; one scalar load per outer x-neighbour.
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+__device__ __forceinline__ void walk_faces(const Stencil& S, double, const double*& fx,
+                                           const double*& fy, const double*& fz) {
+  fx = S.fx; fy = S.fy; fz = S.fz;
+}
+__device__ __forceinline__ void walk_faces(const Stencil& S, float, const float*& fx,
+                                           const float*& fy, const float*& fz) {
+  fx = S.fx32; fy = S.fy32; fz = S.fz32;
+}
+template <typename T, bool VAR, class F>
+__device__ __forceinline__ void stencil_walk2t(const Stencil& S, const T* __restrict__ diag,
+                                               const T* __restrict__ x, int q, int z0, int z1,
+                                               F&& f) {
+  using V = typename Vec2<T>::type;
+  const T *Fx, *Fy, *Fz;
+  walk_faces(S, T(0), Fx, Fy, Fz);
+  const T cx = (T)S.cx, cy = (T)S.cy, cz = (T)S.cz;
   const int hx = S.nx / 2;
   const int ix = 2 * (q % hx), iy = q / hx;
   const int nxy = S.nx * S.ny;
   const bool hl = ix > 0, hr = ix + 2 < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
-  const double2 zero = {0.0, 0.0};
-  auto ld2 = [](const double* p, int64_t k) { return *reinterpret_cast<const double2*>(p + k); };
+  const V zero = {T(0), T(0)};
+  auto ld2 = [](const T* p, int64_t k) { return *reinterpret_cast<const V*>(p + k); };
   int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
-  double2 xm = z0 > 0 ? ld2(x, i - nxy) : zero;
-  double2 fm = (VAR && z0 > 0) ? ld2(S.fz, i - nxy) : zero;
-  double2 xc = ld2(x, i);
+  V xm = z0 > 0 ? ld2(x, i - nxy) : zero;
+  V fm = (VAR && z0 > 0) ? ld2(Fz, i - nxy) : zero;
+  V xc = ld2(x, i);
   for (int z = z0; z < z1; ++z, i += nxy) {
-    const double2 xp = z < S.nz - 1 ? ld2(x, i + nxy) : zero;
-    const double2 d = ld2(diag, i);
-    const double xl = hl ? x[i - 1] : 0.0;
-    const double xr = hr ? x[i + 2] : 0.0;
-    const double2 yd = hd ? ld2(x, i - S.nx) : zero;
-    const double2 yu = hu ? ld2(x, i + S.nx) : zero;
-    double v0 = d.x * xc.x, v1 = d.y * xc.y;
+    const V xp = z < S.nz - 1 ? ld2(x, i + nxy) : zero;
+    const V d = ld2(diag, i);
+    const T xl = hl ? x[i - 1] : T(0);
+    const T xr = hr ? x[i + 2] : T(0);
+    const V yd = hd ? ld2(x, i - S.nx) : zero;
+    const V yu = hu ? ld2(x, i + S.nx) : zero;
+    T v0 = d.x * xc.x, v1 = d.y * xc.y;
     if (!VAR) {
-      v0 -= S.cx * (xl + xc.y) + S.cy * (yd.x + yu.x) + S.cz * (xm.x + xp.x);
-      v1 -= S.cx * (xc.x + xr) + S.cy * (yd.y + yu.y) + S.cz * (xm.y + xp.y);
+      v0 -= cx * (xl + xc.y) + cy * (yd.x + yu.x) + cz * (xm.x + xp.x);
+      v1 -= cx * (xc.x + xr) + cy * (yd.y + yu.y) + cz * (xm.y + xp.y);
     } else {
       // +x faces: node i-1 (left of the pair), i (inside the pair), i+1 (right)
-      const double fxl = hl ? S.fx[i - 1] : 0.0;
-      const double2 fx = ld2(S.fx, i);
+      const T fxl = hl ? Fx[i - 1] : T(0);
+      const V fx = ld2(Fx, i);
       v0 -= fxl * xl + fx.x * xc.y;
       v1 -= fx.x * xc.x + fx.y * xr;
-      const double2 fyd = hd ? ld2(S.fy, i - S.nx) : zero;
-      const double2 fyu = ld2(S.fy, i);
+      const V fyd = hd ? ld2(Fy, i - S.nx) : zero;
+      const V fyu = ld2(Fy, i);
       v0 -= fyd.x * yd.x + fyu.x * yu.x;
       v1 -= fyd.y * yd.y + fyu.y * yu.y;
       if (S.dim == 3) {
-        const double2 fp = ld2(S.fz, i);
+        const V fp = ld2(Fz, i);
         v0 -= fm.x * xm.x + fp.x * xp.x;
         v1 -= fm.y * xm.y + fp.y * xp.y;
         fm = fp;
@@ -174,15 +190,28 @@ __device__ __forceinline__ void stencil_walk2(const Stencil& S, const double* __
     xc = xp;
   }
 }
+template <bool VAR, class F>
+__device__ __forceinline__ void stencil_walk2(const Stencil& S, const double* __restrict__ diag,
+                                              const double* __restrict__ x, int q, int z0,
+                                              int z1, F&& f) {
+  stencil_walk2t<double, VAR>(S, diag, x, q, z0, z1, static_cast<F&&>(f));
+}
 
 // Whether the two-node walk applies: even nx and 16-byte aligned arrays at even leading
 // dimensions (ld of every column array passed in `ld`).
-inline bool stencil_pairs_ok(const Stencil& S, int64_t ld, std::initializer_list<const void*> ptrs) {
+inline bool stencil_pairs_ok(const Stencil& S, int64_t ld, std::initializer_list<const void*> ptrs,
+                             bool fp32 = false) {
+  const uintptr_t m = fp32 ? 7 : 15;
   if (S.nx % 2 != 0 || ld % 2 != 0) return false;
   for (const void* p : ptrs)
-    if (p && ((uintptr_t)p & 15)) return false;
-  if (S.var && (((uintptr_t)S.fx | (uintptr_t)S.fy | (S.dim == 3 ? (uintptr_t)S.fz : 0)) & 15))
-    return false;
+    if (p && ((uintptr_t)p & m)) return false;
+  if (S.var) {
+    const uintptr_t f = fp32 ? ((uintptr_t)S.fx32 | (uintptr_t)S.fy32 |
+                                (S.dim == 3 ? (uintptr_t)S.fz32 : 0))
+                             : ((uintptr_t)S.fx | (uintptr_t)S.fy |
+                                (S.dim == 3 ? (uintptr_t)S.fz : 0));
+    if (f & m) return false;
+  }
   return true;
 }
 

@@ -43,8 +43,15 @@ struct StencilShape {
   dim3 grid;
   int zc;
   int blocks;
+  int pairs = 0;   // CG operator step with two x-nodes per thread (grid.x counts pairs)
 };
 StencilShape stencil_shape(const Stencil& S, int target_blocks);
+// Launch shape of the CG operator step (launch_dcg_apply) for these buffers: the two-node
+// walk when nx is even and every array is aligned for it (then grid.x and blocks count
+// node pairs: the partials per member are `blocks`, at stride `blocks`).
+template <typename T>
+StencilShape cg_apply_shape(const Stencil& S, int target_blocks, const T* diag, const T* p,
+                            const T* w, int64_t vstride);
 
 // Absorption bumps of one parameter point, passed by value as a kernel argument.
 struct Bumps {

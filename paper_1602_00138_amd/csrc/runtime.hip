@@ -1371,7 +1371,7 @@ class Sequencer {
         su.nj[y] = bt.nj[y];
         su.active[y] = bt.active[y];
       }
-      const StencilShape sh = stencil_shape(S_, 1024);
+      const StencilShape sh = cg_apply_shape<T>(S_, 1024, b.diag, b.p, b.w, ld_);
       launch_cg_setup(cg, su, nb, st_);
       launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec,
                           b.s, ld_, cg, b.part2, p2s_, nb, Pmax, st_);
@@ -1399,7 +1399,7 @@ class Sequencer {
           for (int step = 0; step < 8; ++step, ++k) {
             launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, st_);
             launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
-                                 b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_, nr);
+                                 b.part1, sh.blocks, sh.blocks, b.part2, p2s_, nb, P, st_, nr);
             launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,
                               b.part2, p2s_, nb, P, st_, 0, nr);
           }
@@ -1445,7 +1445,7 @@ class Sequencer {
       for (int c = 0; c < GRAPH_STEPS; ++c) {
         launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, cs);
         launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, ITER_STATE,
-                             cg, b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, cs, nr);
+                             cg, b.part1, sh.blocks, sh.blocks, b.part2, p2s_, nb, P, cs, nr);
         launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_,
                           ITER_STATE, cg, b.part2, p2s_, nb, P, cs, 0, nr);
       }
@@ -1470,7 +1470,9 @@ class Sequencer {
     bufs(b);
     const int nb = bt.nb;
     CGState* cg = ctrl_->cg;
-    const StencilShape sh = stencil_shape(S_, 1024);
+    // the operator step's shape (two x-nodes per thread where the layout allows); its block
+    // count is both the number and the per-member stride of the operator's partials
+    const StencilShape sh = cg_apply_shape<T>(S_, 1024, b.diag, b.p, b.w, ld_);
     const int64_t wstride = bt.shared ? 0 : ld_ * NJ_MAX;
     const int64_t gstride = bt.shared ? 0 : (int64_t)NJ_MAX * NJ_MAX;
     CgSetup su;
@@ -1560,7 +1562,7 @@ class Sequencer {
         tm_->end(ROM_K_SPMV, nlive * by_apply, nlive * fl_apply);
         tm_->begin(ROM_K_DCG_UPDATE);
         launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
-                             b.part1, sh.blocks, p1s_, b.part2, p2s_, nb, P, st_, nr);
+                             b.part1, sh.blocks, sh.blocks, b.part2, p2s_, nb, P, st_, nr);
         tm_->end(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
         tm_->begin(ROM_K_DCG_DIR);
         launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,

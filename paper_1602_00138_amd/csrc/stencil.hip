@@ -57,10 +57,18 @@ __global__ void k_mu_eval(Stencil S, Bumps B, const double* __restrict__ diag_st
                           double* __restrict__ diag_i, double* __restrict__ dmu) {
   int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i >= S.n) return;
-  const int ix = (int)(i % S.nx);
-  const int64_t q = i / S.nx;
-  const int iy = (int)(q % S.ny);
-  const int iz = (int)(q / S.ny);
+  int ix, iy, iz;
+  if (S.n <= INT32_MAX) {     // 32-bit index arithmetic where the grid allows it
+    const unsigned u = (unsigned)i, q = u / (unsigned)S.nx;
+    ix = (int)(u - q * (unsigned)S.nx);
+    iy = (int)(q % (unsigned)S.ny);
+    iz = (int)(q / (unsigned)S.ny);
+  } else {
+    const int64_t q = i / S.nx;
+    ix = (int)(i % S.nx);
+    iy = (int)(q % S.ny);
+    iz = (int)(q / S.ny);
+  }
   const double x[3] = {(ix + 1.0) / (S.nx + 1), (iy + 1.0) / (S.ny + 1),
                        (iz + 1.0) / (S.nz + 1)};
   const int stride = S.dim + 2;
@@ -72,6 +80,9 @@ __global__ void k_mu_eval(Stencil S, Bumps B, const double* __restrict__ diag_st
       const double e = x[a] - pb[a];
       d2 += e * e;
     }
+    // outside the support (|x - c| >= r) the bump contributes nothing: skip the square
+    // root and the division there
+    if (d2 >= pb[S.dim] * pb[S.dim]) continue;
     const double t = sqrt(d2) / pb[S.dim];
     if (t < 1.0) {
       const double u = 1.0 - t;

@@ -90,21 +90,32 @@ def spmm_bandwidth(prob, point, k: int, reps: int = 10):
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda._sleep(20_000_000)
-    e0.record(st)
-    for r in range(reps):
-        R.rom_apply_operator(prob.op, point, Xs[r % 2], Ys[r % 2], k, scratch)
-    e1.record(st)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    def timed(call):
+        torch.cuda._sleep(20_000_000)
+        e0.record(st)
+        for r in range(reps):
+            call(r)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = timed(lambda r: R.rom_apply_operator(prob.op, point, Xs[r % 2], Ys[r % 2], k, scratch))
+    # for comparison: the same calls on one operand pair (resident in the Infinity Cache
+    # after the first), and a plain device copy of the same footprint on alternating pairs
+    ms_res = timed(lambda r: R.rom_apply_operator(prob.op, point, Xs[0], Ys[0], k, scratch))
+    ms_copy = timed(lambda r: Ys[r % 2].copy_(Xs[r % 2]))
     var = prob.D_field is not None
     by = n * (16.0 * k + 8.0 + (24.0 if var else 0.0))
     return {"k": k, "bytes": by, "ms": ms, "GBps": by / ms / 1e6,
             "frac_of_peak": by / ms / 1e6 / HBM_PEAK_GBS,
+            "resident_ms": ms_res, "resident_GBps": by / ms_res / 1e6,
+            "copy_ms": ms_copy, "copy_GBps": 16.0 * n * k / ms_copy / 1e6,
             "note": "Y = A(p) X, X and Y N x k FP64; bytes = N(16k + 8) (+24N with a D field); "
                     "each timed call also evaluates mu(p) on the nodes (counted as time, not "
                     "bytes); calls alternate between two operand pairs larger than the "
-                    "Infinity Cache together"}
+                    "Infinity Cache together; resident_*: repeated calls on one pair; copy_*: "
+                    "a plain device copy of X to Y (16 N k bytes read+written) on alternating "
+                    "pairs"}
 
 
 def measure_forms(prob, pts, wl, steps: int):
@@ -515,7 +526,8 @@ def main():
         roof["traffic_source"] = "profiles/traffic_outer_projection_cube64.md (ratio %.3f)" % tr
 
     spmm = spmm_bandwidth(prob, pts[-1], 64)
-    log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s)")
+    log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s); "
+        f"operands resident {spmm['resident_GBps']:.0f} GB/s; plain copy {spmm['copy_GBps']:.0f} GB/s")
 
     jac = freq = None
     if args.jacobian or args.frequency:

@@ -20,7 +20,11 @@ int reduce_grid(int64_t n) {
 // 64*CPL rows x gcols columns (GT_COLS, or one column per wave when that would leave the
 // chip mostly idle).  When several row chunks exist, k_gemvt_reduce sums the chunk
 // partials of each output in chunk order.
-template <int CPL, int NV>
+//
+// Q4: a lane takes four consecutive rows per 256-row slice of its chunk (two 16-byte loads
+// per column instead of four 8-byte ones); needs M and V 16-byte aligned at even leading
+// dimensions.  The chunk and the partials are the same as without it.
+template <int CPL, int NV, bool Q4 = false>
 __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int64_t ld,
                                                int64_t rows, int cols,
                                                const double* __restrict__ V, int64_t vstride,
@@ -31,11 +35,36 @@ __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int6
   const int64_t r0 = (int64_t)blockIdx.x * (64 * CPL);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double vr[NV][CPL];
+  // four rows of a slice: two 16-byte loads when all four exist, else guarded scalars
+  auto quad = [rows](const double* __restrict__ p, int64_t base, double (&o)[4]) {
+    if (base + 3 < rows) {
+      const double2 a = *reinterpret_cast<const double2*>(p + base);
+      const double2 b = *reinterpret_cast<const double2*>(p + base + 2);
+      o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    } else {
 #pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    const int64_t r = r0 + lane + 64 * q;
+      for (int e = 0; e < 4; ++e) o[e] = base + e < rows ? p[base + e] : 0.0;
+    }
+  };
+  if (Q4) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) vr[v][q] = r < rows ? V[r + v * vstride] : 0.0;
+    for (int qq = 0; qq < CPL / 4; ++qq) {
+      const int64_t base = r0 + 256 * qq + 4 * lane;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double o[4];
+        quad(V + v * vstride, base, o);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vr[v][4 * qq + e] = o[e];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int64_t r = r0 + lane + 64 * q;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) vr[v][q] = r < rows ? V[r + v * vstride] : 0.0;
+    }
   }
   const int c0 = blockIdx.y * gcols;
   const bool single = gridDim.x == 1;
@@ -64,12 +93,24 @@ __global__ __launch_bounds__(BS) void k_gemvt(const double* __restrict__ M, int6
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    if (Q4) {
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-      const int64_t r = r0 + lane + 64 * q;
-      const double mv = r < rows ? col[r] : 0.0;
+      for (int qq = 0; qq < CPL / 4; ++qq) {
+        double o[4];
+        quad(col, r0 + 256 * qq + 4 * lane, o);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += mv * vr[v][q];
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v] += o[e] * vr[v][4 * qq + e];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int64_t r = r0 + lane + 64 * q;
+        const double mv = r < rows ? col[r] : 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += mv * vr[v][q];
+      }
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -910,14 +951,21 @@ void launch_gemvt(const double* M, int64_t ld, int64_t rows, int cols, const dou
   // m x m triangular solves, short tall-skinny ones) takes one column per wave instead
   const int gcols = nch * ceil_div(cols, GT_COLS) < 512 ? BS / 64 : GT_COLS;
   dim3 grid((unsigned)nch, ceil_div(cols, gcols));
-#define GT_LAUNCH(C, N) \
-  ROM_LAUNCH((k_gemvt<C, N>), grid, dim3(BS), 0, st, M, ld, rows, cols, V, vstride, out, partials, \
-             skip, gcols)
+#define GT_LAUNCH(C, N, Q) \
+  ROM_LAUNCH((k_gemvt<C, N, Q>), grid, dim3(BS), 0, st, M, ld, rows, cols, V, vstride, out, \
+             partials, skip, gcols)
   if (nv < 1 || nv > 3) throw Error(ROM_EINVAL, "gemvt: 1 to 3 vectors");
-  if (cpl == 16) {
-    if (nv == 1) GT_LAUNCH(16, 1); else if (nv == 2) GT_LAUNCH(16, 2); else GT_LAUNCH(16, 3);
+  const bool q4 = ld % 2 == 0 && ((uintptr_t)M & 15) == 0 && ((uintptr_t)V & 15) == 0 &&
+                  (nv == 1 || vstride % 2 == 0);
+  if (cpl == 16 && q4) {
+    if (nv == 1) GT_LAUNCH(16, 1, true); else if (nv == 2) GT_LAUNCH(16, 2, true);
+    else GT_LAUNCH(16, 3, true);
+  } else if (cpl == 16) {
+    if (nv == 1) GT_LAUNCH(16, 1, false); else if (nv == 2) GT_LAUNCH(16, 2, false);
+    else GT_LAUNCH(16, 3, false);
   } else {
-    if (nv == 1) GT_LAUNCH(4, 1); else if (nv == 2) GT_LAUNCH(4, 2); else GT_LAUNCH(4, 3);
+    if (nv == 1) GT_LAUNCH(4, 1, false); else if (nv == 2) GT_LAUNCH(4, 2, false);
+    else GT_LAUNCH(4, 3, false);
   }
 #undef GT_LAUNCH
   ROM_CHECK_LAUNCH();

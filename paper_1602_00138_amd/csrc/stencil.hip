@@ -11,6 +11,12 @@ namespace rom {
 namespace {
 
 constexpr int BS = 256;
+// Columns per thread of the two-node SpMM: with a D field the diagonal and the three face
+// arrays are shared by all columns, and 8 columns per thread took 64 columns at 96^3 from
+// 2.0 to 3.1 TB/s; with constant D only the diagonal is shared and one column per thread
+// is fastest (2 and 4 measured 1% and 13% slower at 64^3).
+constexpr int SPMM_CPT_VAR = 8;
+constexpr int SPMM_CPT_CONST = 1;
 
 __global__ void k_assemble(rom_grid g, double Dc, const double* __restrict__ D, int64_t n,
                            double* __restrict__ diag, double* __restrict__ fx,
@@ -249,6 +255,83 @@ __global__ __launch_bounds__(BS) void k_spmm2(Stencil S, const double* __restric
   });
 }
 
+// k_spmm2 with C columns per thread (blockIdx.z = group of C columns, the last group
+// possibly partial): the diagonal and, with a D field, the face coefficients are loaded once
+// per node pair for all C columns instead of once per column.  Same arithmetic per column
+// as stencil_walk2.
+template <bool VAR, int C>
+__global__ __launch_bounds__(BS) void k_spmm2c(Stencil S, const double* __restrict__ diag,
+                                                const double* __restrict__ x0, int64_t ld, int k,
+                                                double* __restrict__ y0, int zc) {
+  const int hx = S.nx / 2;
+  const int q = blockIdx.x * BS + threadIdx.x;
+  if (q >= hx * S.ny) return;
+  const int z0 = blockIdx.y * zc, z1 = min(z0 + zc, S.nz);
+  if (z0 >= z1) return;
+  const int c0 = blockIdx.z * C;
+  const int nc = min(C, k - c0);
+  const int ix = 2 * (q % hx), iy = q / hx;
+  const int nxy = S.nx * S.ny;
+  const bool hl = ix > 0, hr = ix + 2 < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
+  const double2 zero = {0.0, 0.0};
+  auto ld2 = [](const double* p, int64_t j) { return *reinterpret_cast<const double2*>(p + j); };
+  const double* x[C];
+  double* y[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int64_t col = c0 + (c < nc ? c : 0);   // columns past k alias the first (never stored)
+    x[c] = x0 + col * ld;
+    y[c] = y0 + col * ld;
+  }
+  int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
+  double2 xm[C], xc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    xm[c] = z0 > 0 ? ld2(x[c], i - nxy) : zero;
+    xc[c] = ld2(x[c], i);
+  }
+  double2 fm = (VAR && z0 > 0) ? ld2(S.fz, i - nxy) : zero;
+  for (int z = z0; z < z1; ++z, i += nxy) {
+    const double2 d = ld2(diag, i);
+    double fxl = 0.0;
+    double2 fx = zero, fyd = zero, fyu = zero, fp = zero;
+    if (VAR) {
+      fxl = hl ? S.fx[i - 1] : 0.0;
+      fx = ld2(S.fx, i);
+      fyd = hd ? ld2(S.fy, i - S.nx) : zero;
+      fyu = ld2(S.fy, i);
+      if (S.dim == 3) fp = ld2(S.fz, i);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (c >= nc) break;
+      const double2 xp = z < S.nz - 1 ? ld2(x[c], i + nxy) : zero;
+      const double xl = hl ? x[c][i - 1] : 0.0;
+      const double xr = hr ? x[c][i + 2] : 0.0;
+      const double2 yd = hd ? ld2(x[c], i - S.nx) : zero;
+      const double2 yu = hu ? ld2(x[c], i + S.nx) : zero;
+      double v0 = d.x * xc[c].x, v1 = d.y * xc[c].y;
+      if (!VAR) {
+        v0 -= S.cx * (xl + xc[c].y) + S.cy * (yd.x + yu.x) + S.cz * (xm[c].x + xp.x);
+        v1 -= S.cx * (xc[c].x + xr) + S.cy * (yd.y + yu.y) + S.cz * (xm[c].y + xp.y);
+      } else {
+        v0 -= fxl * xl + fx.x * xc[c].y;
+        v1 -= fx.x * xc[c].x + fx.y * xr;
+        v0 -= fyd.x * yd.x + fyu.x * yu.x;
+        v1 -= fyd.y * yd.y + fyu.y * yu.y;
+        if (S.dim == 3) {
+          v0 -= fm.x * xm[c].x + fp.x * xp.x;
+          v1 -= fm.y * xm[c].y + fp.y * xp.y;
+        }
+      }
+      *reinterpret_cast<double2*>(y[c] + i) = double2{v0, v1};
+      xm[c] = xc[c];
+      xc[c] = xp;
+    }
+    if (VAR) fm = fp;
+  }
+}
+
 // k_cheb_step with two x-nodes per thread (the same conditions as k_spmm2).
 template <bool VAR>
 __global__ __launch_bounds__(BS) void k_cheb_step2(Stencil S, const double* __restrict__ diag,
@@ -368,6 +451,13 @@ void launch_spmv(const Stencil& S, const double* diag, const double* x, double* 
                  (const CGState*)nullptr);
 }
 
+// Columns per thread of the two-node SpMM (1, 2, 4 or 8), at most k.
+static int spmm_cols_per_thread(const Stencil& S, int k) {
+  int c = S.var ? SPMM_CPT_VAR : SPMM_CPT_CONST;
+  while (c > 1 && c > k) c /= 2;
+  return c;
+}
+
 void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t ld, int k,
                  double* Y, hipStream_t st) {
   if (k <= 0) return;
@@ -376,10 +466,21 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
   grid.z = k;
   if (stencil_pairs_ok(S, ld, {X, Y, diag})) {
     grid.x = ceil_div((int64_t)(S.nx / 2) * S.ny, BS);
-    if (S.var)
+    const int C = spmm_cols_per_thread(S, k);
+    if (C > 1) {
+      grid.z = ceil_div(k, C);
+#define SPMMC(V, CC) ROM_LAUNCH((k_spmm2c<V, CC>), grid, dim3(BS), 0, st, S, diag, X, ld, k, Y, sh.zc)
+      if (S.var) {
+        if (C == 8) SPMMC(true, 8); else if (C == 4) SPMMC(true, 4); else SPMMC(true, 2);
+      } else {
+        if (C == 8) SPMMC(false, 8); else if (C == 4) SPMMC(false, 4); else SPMMC(false, 2);
+      }
+#undef SPMMC
+    } else if (S.var) {
       ROM_LAUNCH(k_spmm2<true>, grid, dim3(BS), 0, st, S, diag, X, ld, Y, sh.zc);
-    else
+    } else {
       ROM_LAUNCH(k_spmm2<false>, grid, dim3(BS), 0, st, S, diag, X, ld, Y, sh.zc);
+    }
     ROM_CHECK_LAUNCH();
     return;
   }

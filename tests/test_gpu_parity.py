@@ -29,7 +29,8 @@ def _gpu_run(drv, wl, K=None, mode="independent", k_u=None, **kw):
     return prob, pts, res
 
 
-# odd nx: one node per thread; even nx: the two-node SpMM (16-byte loads and stores)
+# odd nx: one node per thread; even nx: the two-node SpMM (16-byte loads and stores,
+# two or four columns per thread)
 @pytest.mark.parametrize("wl", [ph.small(2, (17, 13)), ph.small(3, (9, 8, 7)),
                                 ph.small(3, (11, 6, 9), D="lognormal"),
                                 ph.small(2, (18, 13)), ph.small(2, (16, 11), D="lognormal"),
@@ -40,10 +41,13 @@ def test_apply_operator_matches_oracle(drv, wl):
     prob = drv.problem_from_workload(wl)
     pts = drv.points_from_workload(wl)
     rng = np.random.default_rng(0)
-    X = rng.standard_normal((3, wl.n))
-    Y = prob.apply(pts[1], torch.as_tensor(X, device="cuda")).cpu().numpy()
-    ref = (orc.A(1) @ X.T).T
-    assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max()
+    # 1, 3 and 9 columns: single columns, and full and partial groups of the SpMM's
+    # columns-per-thread grouping
+    for k in (1, 3, 9):
+        X = rng.standard_normal((k, wl.n))
+        Y = prob.apply(pts[1], torch.as_tensor(X, device="cuda")).cpu().numpy()
+        ref = (orc.A(1) @ X.T).T
+        assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max(), k
     prob.close()
 
 

@@ -466,15 +466,11 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
   grid.z = k;
   if (stencil_pairs_ok(S, ld, {X, Y, diag})) {
     grid.x = ceil_div((int64_t)(S.nx / 2) * S.ny, BS);
-    const int C = spmm_cols_per_thread(S, k);
+    const int C = spmm_cols_per_thread(S, k);   // > 1 only with a D field
     if (C > 1) {
       grid.z = ceil_div(k, C);
-#define SPMMC(V, CC) ROM_LAUNCH((k_spmm2c<V, CC>), grid, dim3(BS), 0, st, S, diag, X, ld, k, Y, sh.zc)
-      if (S.var) {
-        if (C == 8) SPMMC(true, 8); else if (C == 4) SPMMC(true, 4); else SPMMC(true, 2);
-      } else {
-        if (C == 8) SPMMC(false, 8); else if (C == 4) SPMMC(false, 4); else SPMMC(false, 2);
-      }
+#define SPMMC(CC) ROM_LAUNCH((k_spmm2c<true, CC>), grid, dim3(BS), 0, st, S, diag, X, ld, k, Y, sh.zc)
+      if (C == 8) SPMMC(8); else if (C == 4) SPMMC(4); else SPMMC(2);
 #undef SPMMC
     } else if (S.var) {
       ROM_LAUNCH(k_spmm2<true>, grid, dim3(BS), 0, st, S, diag, X, ld, Y, sh.zc);

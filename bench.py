@@ -130,14 +130,14 @@ def measure_forms(prob, pts, wl, steps: int):
     K, n_rhs = len(pts), prob.n_rhs
     for name, kw in forms.items():
         kw = dict(kw, tune=1)
-        prob.solve(pts, wl.tol, wl.trunc, keep_X=False, **kw).close()
+        prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, **kw).close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         last = None
         for _ in range(steps):
             if last is not None:
                 last.close()
-            last = prob.solve(pts, wl.tol, wl.trunc, keep_X=False, **kw)
+            last = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = last.stats
@@ -272,7 +272,7 @@ def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_poin
         f"{np.mean(rlosses[:5]):.3e} -> {np.mean(rlosses[-5:]):.3e}")
     kw = dict(precision=R.ROM_PREC_MIXED, tune=1)
     g = seed.guesses(net, prob, pts)
-    prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, **kw).close()
+    prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, guess=g, **kw).close()
     torch.cuda.synchronize()
     t_inf = 0.0
     t0 = time.perf_counter()
@@ -284,7 +284,7 @@ def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_poin
         g = seed.guesses(net, prob, pts)
         torch.cuda.synchronize()
         t_inf += time.perf_counter() - ti
-        last = prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, **kw)
+        last = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, guess=g, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     K, n_rhs = len(pts), prob.n_rhs
@@ -306,7 +306,7 @@ def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_poin
     # both outputs: guesses and recycle vectors, inference inside every timed step
     g = seed.guesses(net, prob, pts)
     rv = seed.recycle_vectors(rnet, prob, pts)
-    prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, recycle=rv, **kw).close()
+    prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, guess=g, recycle=rv, **kw).close()
     torch.cuda.synchronize()
     t_inf = 0.0
     t0 = time.perf_counter()
@@ -319,7 +319,7 @@ def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_poin
         rv = seed.recycle_vectors(rnet, prob, pts)
         torch.cuda.synchronize()
         t_inf += time.perf_counter() - ti
-        last = prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, recycle=rv, **kw)
+        last = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, guess=g, recycle=rv, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st2 = last.stats
@@ -531,7 +531,7 @@ def main():
 
     jac = freq = None
     if args.jacobian or args.frequency:
-        basis = prob.solve(pts, wl.tol, wl.trunc, keep_X=False)
+        basis = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False)
         jac = measure_jacobian(prob, pts, wl, value, basis) if args.jacobian else None
         freq = measure_frequency(prob, pts, wl, basis) if args.frequency else None
         basis.close()

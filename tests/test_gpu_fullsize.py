@@ -14,6 +14,8 @@ this size, so it checks sampled outputs one by one:
   * reduced transfer-function columns at the sample points equal C~^T x_ref to 1e-6
     relative (interpolation, Sec. 3.4);
   * sampled entries of A_r(p) = V^T A(p) V equal the oracle's to 1e-12 relative.
+The operator product Y = A(p) X is also checked at full size in the benchmark's 64-column
+shape, at 64^3 and on the 96^3 log-normal-D grid, on sampled rows.
 """
 import numpy as np
 import pytest
@@ -197,3 +199,34 @@ def test_fullsize_shifted_solves_and_response(gpu, reference):
               f"= {err / scale:.1e} of |c||y|")
         assert err <= 1e-10 * scale, s
     res.close()
+
+
+@pytest.mark.parametrize("name,k", [("cube64", 64), ("cube96_lognormal", 64),
+                                    ("cube96_lognormal", 61)])
+def test_fullsize_apply_operator_sampled(gpu, name, k):
+    """Y = A(p) X at full size in the benchmark's SpMM shape (64 columns; 61 leaves a partial
+    group of the D-field kernel's 8 columns per thread), on the last point: sampled rows of
+    every column against the oracle's CSR operator -- random rows, the corners of the grid
+    and the nodes nearest the bump centres -- to 1e-14 of the largest sampled entry."""
+    import torch
+    from paper_1602_00138_amd import driver
+    wl = ph.WORKLOADS[name]
+    D = ph.diffusion_field(wl)
+    As = op.assemble_Astar(wl.dim, wl.N, wl.bc, D, wl.robin_A)
+    p = ph.parameter_points(wl)[-1]
+    A = op.assemble_A(As, op.mu_field(wl.dim, wl.N, p.mu0, p.centers, p.radii, p.amps)).tocsr()
+    rng = np.random.default_rng(7)
+    Nx, Ny, Nz = wl.N[0], wl.N[1], wl.N[2]
+    corners = [ix + Nx * (iy + Ny * iz) for ix in (0, Nx - 1) for iy in (0, Ny - 1)
+               for iz in (0, Nz - 1)]
+    centres = [int(round(c[0] * (Nx + 1) - 1)) + Nx * (int(round(c[1] * (Ny + 1) - 1))
+               + Ny * int(round(c[2] * (Nz + 1) - 1))) for c in np.asarray(p.centers)]
+    rows = np.unique(np.concatenate([rng.choice(wl.n, 1500, replace=False), corners, centres]))
+    X = rng.standard_normal((k, wl.n))
+    prob = driver.problem_from_workload(wl)
+    pt = driver.points_from_workload(wl)[-1]
+    Y = prob.apply(pt, torch.as_tensor(X, device="cuda"))
+    got = Y[:, torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    ref = (A[rows] @ X.T).T
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+    prob.close()

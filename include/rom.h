@@ -193,6 +193,20 @@ ROM_API rom_status rom_apply_operator(const rom_operator* op, const rom_mu* p, c
                                       double* Y, int k, void* scratch, size_t scratch_bytes,
                                       void* stream);
 
+/* Allocation-free form of rom_apply_operator, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same product Y[:, c] = A(p) X[:, c], c < k, with the
+ * diagonal of A(p) kept in a device array owned by the library instead of caller scratch.
+ * That array holds ROM_STATIC_MAX_N doubles (16 MiB) on every GPU the library runs on and
+ * stays allocated until the process ends; its address is looked up once per device on
+ * the first call there.  N > ROM_STATIC_MAX_N: ROM_ECAPACITY, before any work is enqueued.
+ * Every call on one GPU uses that GPU's array, so calls that overlap on one GPU (other
+ * streams or host threads) race on it: the caller serialises them.  X, Y as in
+ * rom_apply_operator; asynchronous on `stream`; allocates nothing. */
+#define ROM_STATIC_MAX_N (1 << 21)
+ROM_API rom_status rom_apply_operator_static(const rom_operator* op, const rom_mu* p,
+                                             const double* X, double* Y, int k, void* stream);
+
 /* Device bytes of the workspace of rom_solve_sequence. */
 ROM_API rom_status rom_sequence_bytes(const rom_operator* op, int n_src, int n_det, int k_u, int K,
                               const rom_opts* opts, size_t* bytes);

@@ -1749,6 +1749,38 @@ void check_counts(int n_src, int n_det, int k_u, int K) {
 rom_status report(const Error& e) { return fail(e); }
 void report_message(const std::string& m) { g_err = m; }
 
+namespace {
+
+// The diagonal of A(p) for rom_apply_operator_static.  A file-scope device array exists
+// once on every device that loads the library; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (the array's name is a host-side
+// stand-in, not a device address).
+static __device__ __align__(256) double static_scratch[ROM_STATIC_MAX_N];
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex& static_scratch_mu() {
+  static std::mutex m;
+  return m;
+}
+double* static_scratch_ptr[STATIC_MAX_DEVICES] = {};
+
+}  // namespace
+
+// Device address of static_scratch on the current device, looked up once per device.
+double* static_scratch_device() {
+  int dev = 0;
+  ROM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) throw Error(ROM_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(static_scratch_mu());
+  if (!static_scratch_ptr[dev]) {
+    void* p = nullptr;
+    ROM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(static_scratch)));
+    if (!p) throw Error(ROM_EHIP, "hipGetSymbolAddress returned a null address");
+    static_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return static_scratch_ptr[dev];
+}
+
 }  // namespace rom
 
 using rom::Error;
@@ -1836,6 +1868,28 @@ rom_status rom_apply_operator(const rom_operator* op, const rom_mu* p, const dou
     double* diag = (double*)scratch;
     // diag(A(p)) = diag(A_*) + mu(p); the bump part goes through Y's first column as
     // temporary storage before the product overwrites it
+    rom::launch_mu_eval(op->S, rom::make_bumps(*p, op->grid.dim), op->diag_star, diag, Y, st);
+    rom::launch_spmm(op->S, diag, X, op->n, k, Y, st);
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_apply_operator_static(const rom_operator* op, const rom_mu* p, const double* X,
+                                     double* Y, int k, void* stream) {
+  try {
+    if (!op || !X || !Y) throw Error(ROM_EINVAL, "null argument");
+    rom::check_mu(p, op->grid.dim);
+    if (k < 0) throw Error(ROM_EINVAL, "k must be >= 0");
+    if (op->n > ROM_STATIC_MAX_N)
+      throw Error(ROM_ECAPACITY, "rom_apply_operator_static: N = " + std::to_string(op->n) +
+                                     " exceeds ROM_STATIC_MAX_N = " +
+                                     std::to_string(ROM_STATIC_MAX_N));
+    if (k == 0) return ROM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    // every entry of the diagonal is written before the product reads it
+    double* diag = rom::static_scratch_device();
     rom::launch_mu_eval(op->S, rom::make_bumps(*p, op->grid.dim), op->diag_star, diag, Y, st);
     rom::launch_spmm(op->S, diag, X, op->n, k, Y, st);
     return ROM_OK;

@@ -26,6 +26,7 @@ ROM_ENOCONV = -4
 ROM_ECAPACITY = -5
 ROM_EHIP = -6
 ROM_NJ_MAX = 64
+ROM_STATIC_MAX_N = 1 << 21
 ROM_MAX_BUMPS = 64
 ROM_PREC_FP64 = 0
 ROM_PREC_MIXED = 1
@@ -35,7 +36,8 @@ ROM_PREC_MIXED = 1
 ROM_NK = 8
 KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "outer", "other"]
 
-EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator", "rom_sequence_bytes",
+EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator",
+            "rom_apply_operator_static", "rom_sequence_bytes",
             "rom_solve_sequence", "rom_solve_sequences", "rom_reduced_bytes", "rom_reduced_transfer",
             "rom_reduced_jacobian_bytes", "rom_reduced_jacobian", "rom_lowest_modes_bytes",
             "rom_lowest_modes", "rom_shifted_solve_bytes", "rom_shifted_solve",
@@ -107,6 +109,7 @@ def _load():
         "rom_operator_bytes": (C.c_int, [P(rom_grid), C.c_int, P(sz)]),
         "rom_assemble_operator": (C.c_int, [P(rom_grid), C.c_double, vp, vp, sz, P(vp), vp]),
         "rom_apply_operator": (C.c_int, [vp, P(rom_mu), vp, vp, C.c_int, vp, sz, vp]),
+        "rom_apply_operator_static": (C.c_int, [vp, P(rom_mu), vp, vp, C.c_int, vp]),
         "rom_sequence_bytes": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, P(rom_opts), P(sz)]),
         "rom_solve_sequence": (C.c_int, [vp, P(rom_mu), C.c_int, P(C.c_int64), P(C.c_double), C.c_int,
                                          P(C.c_int64), P(C.c_double), C.c_int, vp, C.c_int,
@@ -244,6 +247,12 @@ def rom_apply_operator(op: int, p: MuParams, X, Y, k: int, scratch, stream=None)
     mu = p.c_struct()
     _check(_lib.rom_apply_operator(op, C.byref(mu), _ptr(X), _ptr(Y), int(k), _ptr(scratch),
                                    scratch.numel() * scratch.element_size(), _stream(stream)))
+
+
+def rom_apply_operator_static(op: int, p: MuParams, X, Y, k: int, stream=None) -> None:
+    mu = p.c_struct()
+    _check(_lib.rom_apply_operator_static(op, C.byref(mu), _ptr(X), _ptr(Y), int(k),
+                                          _stream(stream)))
 
 
 def rom_sequence_bytes(op: int, n_src: int, n_det: int, k_u: int, K: int, opts: rom_opts) -> int:

@@ -1,11 +1,19 @@
-"""Benchmark: full-order solves/sec of the recycled-CG sequence (Algorithm 2, CG form)
-on one MI355X, plus the stencil SpMM HBM bandwidth, the roofline position of the
-dominant kernel, and the CPU oracle timed on a bounded sample of the same workload.
+"""Benchmark: full-order solves/sec of the recycled-CG sequence (Algorithm 2, CG form) on one
+MI355X, the roofline position of the dominant kernel, the stencil SpMM bandwidth, the other
+forms and workloads of the method, and the CPU oracle on a bounded sample.
 
-A step = one pass of the whole path on the workload: assemble A_* (Sec. 3), run
-rom_solve_sequence over every parameter point and right-hand side (Sec. 4.3), and
-form the reduced matrices of eq. (newreduced) at the last point.  Inputs (grid,
-parameters, U_0) are resident before the timed region; one JSON line goes to stdout.
+Headline workload: the 128^3 grid with log-normal D (2,097,152 unknowns, 48 sources + 48
+detectors, 16 absorption bumps per point, basis capped at 256 columns, tolerance 1e-8) in
+its mixed-precision form (FP32 inner recycled CG inside FP64 refinement).  A step is one
+parameter point of that sequence, taken through rom_sequence_point: the point's operator
+A(p_i) = A_* + diag(mu(p_i)) (Sec. 3), the reprojection of the basis, the outer projection
+and skip test of all 96 right-hand sides, their inner recycled-CG solves and the appends
+(Algorithm 2, Sec. 4.3), then the reduced matrices of eq. (newreduced) at that point.  The
+first `warmup` points of the sequence are untimed (they include point 0, which builds the
+basis from U_0 and solves X_0); the next `steps` points are timed.  The sequence draws its
+points from the workload's seeded generator (its 32 points first, further draws beyond).
+Inputs (grid, D field, U_0, parameters) are resident before the timed region; one JSON line
+goes to stdout, progress to stderr.
 """
 from __future__ import annotations
 
@@ -22,63 +30,144 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_outer_projection_cube64.md")
-
-
-def traffic_ratio():
-    """Measured HBM bytes / algorithmic bytes of the outer-projection kernels (the fused
-    k_gemvn4x3 and the plain k_gemvn4<false>; rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated
-    on a plain copy), from the committed profile; None if it was taken on other kernels."""
-    try:
-        for line in open(TRAFFIC_PROFILE):
-            if line.startswith("traffic_ratio_outer_fused:"):
-                return float(line.split(":", 1)[1])
-    except OSError:
-        pass
-    return None
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
+METRIC = "full-order solves/sec at 1e-8 rel. residual; SpMM HBM GB/s vs peak"
+
+# The paper's own numbers for this path (context, not a target): no wall-clock
+# time is reported, only iteration counts (Table 1: MINRES iterations without / with
+# inner-outer recycling, 2D 201 x 201 mesh, 32 + 32 right-hand sides, 10 eigenvectors in
+# U_0, tolerance 1e-7) and the totals of the comparison with per-right-hand-side recycling.
+PAPER = {
+    "hardware": "laptop, 3.20 GHz processor, 16 GB RAM, MATLAB R2014a (precision not stated)",
+    "problem": "2D 201x201 mesh (40,401 unknowns), 32 sources + 32 detectors, 25 RBFs, "
+               "unpreconditioned MINRES, tolerance 1e-7, K = 3 systems",
+    "table1_minres_its_exp1": {"rhs": [1, 20, 32, 33, 53, 64],
+                               "system1_plain": [463, 541, 487, 467, 528, 489],
+                               "system1_recycled": [140, 52, 0, 124, 57, 0],
+                               "system2_plain": [474, 513, 497, 474, 526, 497],
+                               "system2_recycled": [118, 35, 0, 105, 37, 0]},
+    "total_minres_its_systems_1_2": {"inner_outer": 5006, "per_rhs_recycling": 22659},
+    "large_solves_to_build_V_exp1": 187,
+    "rom_order_exp1": 197,
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, points, n_sample_rhs: int):
-    """The FP64 oracle, untuned, on a bounded sample: assembly plus point 0 for the first
-    n_sample_rhs right-hand sides (orthonormalise U_0, outer projections, deflated CG,
-    appends)."""
-    import threadpoolctl
+def nproc() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
-    import phantoms as ph
-    from oracle import operator as op
-    from oracle import sequence as oseq
+
+def diff_stats(a: dict, b: dict) -> dict:
+    """Kernel-class totals accumulated between two stats snapshots (b after a)."""
+    out = {"total_its": b["total_its"] - a["total_its"], "n_solved": b["n_solved"] - a["n_solved"],
+           "kernels": {}}
+    for k, v in b["kernels"].items():
+        u = a["kernels"][k]
+        out["kernels"][k] = {f: v[f] - u[f] for f in ("ms", "bytes", "flops", "launches")}
+    return out
+
+
+def stream_points(prob, pts, W: int, K: int, wl, timing: int = 0, reduce_each: bool = True, **kw):
+    """Algorithm 2 over points[0 .. W+K) as one streamed sequence: W untimed points, then K
+    timed ones, each followed by rom_reduced_transfer at its point.  Returns a dict with
+    the timed solves/s, per-point times, kernel-class totals of the timed points, the
+    records of the timed points, and the final SequenceResult."""
+    import torch
+    from paper_1602_00138_amd import rom as R
+    dev = prob.device
+    s = prob.stream(W + K, wl.tol, wl.trunc, cap=wl.cap, timing=timing, **kw)
+    m_max = min(wl.cap or (prob.k_u + prob.n_rhs * (W + K)), prob.n)
+    Ar = torch.empty((m_max, m_max), dtype=torch.float64, device=dev)
+    Er = torch.empty_like(Ar)
+    Br = torch.empty((prob.src_idx.size, m_max), dtype=torch.float64, device=dev)
+    Cr = torch.empty((prob.det_idx.size, m_max), dtype=torch.float64, device=dev)
+    scratch = [None]
+
+    def reduced(p):
+        V = s.basis_view()
+        need = R.rom_reduced_bytes(V)
+        if scratch[0] is None or scratch[0].numel() < need:
+            scratch[0] = torch.empty(need, dtype=torch.uint8, device=dev)
+        R.rom_reduced_transfer(V, p, Ar, Br, Cr, Er, scratch[0])
+
+    for w in range(W):
+        t = time.perf_counter()
+        s.point(pts[w])
+        if reduce_each:
+            reduced(pts[w])
+        torch.cuda.synchronize()
+        log(f"  warmup point {w}: {time.perf_counter() - t:.3f} s")
+    # scratch for the reduced matrices at the basis size the timed points reach
+    V = s.basis_view()
+    _, m_now = R.rom_basis_dims(V)
+    torch.cuda.synchronize()
+    before = s.stats()
+    nrec0 = len(s.records)
     t0 = time.perf_counter()
-    D = ph.diffusion_field(wl)
-    As = op.assemble_Astar(wl.dim, wl.N, wl.bc, D, wl.robin_A)
-    p = points[0]
-    mu = op.mu_field(wl.dim, wl.N, p.mu0, p.centers, p.radii, p.amps)
-    si, di = ph.rhs_nodes(wl)
-    ss, ds = ph.rhs_scales(wl)
-    B = oseq.rhs_matrix(wl.n, si, ss, di, ds)[:, :n_sample_rhs]
-    U0 = ph.smooth_modes(wl)
-    res = oseq.solve_sequence(As, [mu], B, U0, wl.tol, wl.trunc, keep_X=False)
+    per = []
+    for k in range(K):
+        t = time.perf_counter()
+        s.point(pts[W + k])
+        if reduce_each:
+            reduced(pts[W + k])
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - t)
+        log(f"  step {k} (point {W + k}): {per[-1]:.3f} s")
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    info = threadpoolctl.threadpool_info()
-    cores = max([d.get("num_threads", 1) for d in info] + [1])
-    its = sum(r.its for r in res.records)
-    return {"value": n_sample_rhs / dt, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{wl.name}: assembly + point 0, right-hand sides 1-{n_sample_rhs} "
-                      f"({its} CG iterations) in {dt:.1f} s; scipy.sparse products single-threaded, "
-                      f"dense NumPy/BLAS on {cores} threads"}
+    after = s.stats()
+    recs = s.records[nrec0:]
+    res = s.end()
+    return {"value": K * prob.n_rhs / dt, "seconds": dt, "per_point_s": per,
+            "timed": diff_stats(before, after), "records": recs, "result": res}
+
+
+def dcg_roofline(timed: dict, precision: str, prob, wl) -> dict:
+    """Roofline of the CG operator step (k_dcg_op): its algorithmic bytes per launch (the
+    timer's per-class byte count over the timed points) over its mean event-timed launch
+    duration."""
+    k = timed["kernels"]["dcg_op"]
+    launches = max(k["launches"], 1)
+    avg_ms = k["ms"] / launches
+    by = k["bytes"] / launches
+    achieved = k["bytes"] / max(k["ms"], 1e-12) / 1e6
+    E = 4 if precision == "mixed" else 8
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_dcg_op (CG operator step: w = A q - (A U_j) c with its dot products)",
+            "launches": int(k["launches"]), "avg_launch_us": 1e3 * avg_ms,
+            "bytes_per_launch": by,
+            "bytes_formula": f"{E} N (4 + n_j" + (" + 3" if prob.D_field is not None else "")
+                             + ") per member-step (q, diag" + (", 3 face arrays" if prob.D_field is not None else "")
+                             + ", s, the n_j columns of A U_j read, w written)",
+            "note": "events on every launch of this class over the timed points; the update "
+                    "kernel and the rest are in 'kernel_classes'"}
+
+
+def class_table(timed: dict) -> dict:
+    out = {}
+    for name, d in timed["kernels"].items():
+        if d["launches"]:
+            out[name] = {"launches": int(d["launches"]), "ms": d["ms"],
+                         "algorithmic_GBps": d["bytes"] / max(d["ms"], 1e-12) / 1e6 if d["ms"] > 0 else None}
+    return out
 
 
 def spmm_bandwidth(prob, point, k: int, reps: int = 10):
     """HBM GB/s of the stencil SpMM Y = A(p) X over k columns (rom_apply_operator).
 
-    Calls alternate between two (X, Y) pairs (2 x 270 MB at 64^3, k = 64), so no call finds
-    its operands in the 256 MB Infinity Cache left there by the call before.  The timed calls
-    are queued behind a spinning kernel, so host-side launch cost leaves no gaps between
-    them; each timed call is the whole entry point (mu(p) on the nodes, then the product)."""
+    Calls alternate between two (X, Y) pairs whose footprint together exceeds the 256 MB
+    Infinity Cache, so no call finds its operands left there by the call before.  The timed
+    calls are queued behind a spinning kernel, so host-side launch cost leaves no gaps
+    between them; each timed call is the whole entry point (mu(p) on the nodes, then the
+    product)."""
     import torch
     from paper_1602_00138_amd import rom as R
     n = prob.n
@@ -90,6 +179,7 @@ def spmm_bandwidth(prob, point, k: int, reps: int = 10):
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
     def timed(call):
         torch.cuda._sleep(20_000_000)
         e0.record(st)
@@ -100,59 +190,71 @@ def spmm_bandwidth(prob, point, k: int, reps: int = 10):
         return e0.elapsed_time(e1) / reps
 
     ms = timed(lambda r: R.rom_apply_operator(prob.op, point, Xs[r % 2], Ys[r % 2], k, scratch))
-    # for comparison: the same calls on one operand pair (resident in the Infinity Cache
-    # after the first), and a plain device copy of the same footprint on alternating pairs
-    ms_res = timed(lambda r: R.rom_apply_operator(prob.op, point, Xs[0], Ys[0], k, scratch))
     ms_copy = timed(lambda r: Ys[r % 2].copy_(Xs[r % 2]))
     var = prob.D_field is not None
     by = n * (16.0 * k + 8.0 + (24.0 if var else 0.0))
-    return {"k": k, "bytes": by, "ms": ms, "GBps": by / ms / 1e6,
+    del Xs, Ys
+    return {"k": k, "n": n, "bytes": by, "ms": ms, "GBps": by / ms / 1e6,
             "frac_of_peak": by / ms / 1e6 / HBM_PEAK_GBS,
-            "resident_ms": ms_res, "resident_GBps": by / ms_res / 1e6,
-            "copy_ms": ms_copy, "copy_GBps": 16.0 * n * k / ms_copy / 1e6,
+            "copy_GBps": 16.0 * n * k / ms_copy / 1e6,
             "note": "Y = A(p) X, X and Y N x k FP64; bytes = N(16k + 8) (+24N with a D field); "
-                    "each timed call also evaluates mu(p) on the nodes (counted as time, not "
-                    "bytes); calls alternate between two operand pairs larger than the "
-                    "Infinity Cache together; resident_*: repeated calls on one pair; copy_*: "
-                    "a plain device copy of X to Y (16 N k bytes read+written) on alternating "
-                    "pairs"}
+                    "each timed call also evaluates mu(p) on the nodes (time, not bytes); "
+                    "copy_GBps: a plain device copy of the same footprint"}
 
 
-def measure_forms(prob, pts, wl, steps: int):
-    """The other forms of the method on the same problem: mixed precision, groups of 8,
-    and both (solves/s over `steps` timed solve_sequence calls after one warm-up)."""
+def whole_sequence(prob, pts, wl, reps: int = 1, **kw) -> dict:
+    """solves/s of whole sequences (rom_solve_sequence over every point, point 0 included)."""
     import torch
-    from paper_1602_00138_amd import rom as R
-    forms = {"mixed": dict(precision=R.ROM_PREC_MIXED),
-             "fp64_group8": dict(group=8),
-             "mixed_group8": dict(precision=R.ROM_PREC_MIXED, group=8)}
-    out = {}
-    K, n_rhs = len(pts), prob.n_rhs
-    for name, kw in forms.items():
-        kw = dict(kw, tune=1)
-        prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, **kw).close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        last = None
-        for _ in range(steps):
-            if last is not None:
-                last.close()
-            last = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, **kw)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        st = last.stats
-        out[name] = {"value": K * n_rhs * steps / dt, "ms_per_step": 1e3 * dt / steps,
-                     "basis_m": st["m"], "inner_its": st["total_its"], "solved": st["n_solved"],
-                     "nonconverged": st["n_nonconv"]}
-        last.close()
-        log(f"form {name}: {out[name]['value']:.1f} solves/s, m={st['m']}, its={st['total_its']}")
-    return out
+    prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, **kw).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(reps):
+        if last is not None:
+            last.close()
+        last = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = last.stats
+    out = {"value": len(pts) * prob.n_rhs * reps / dt, "ms_per_sequence": 1e3 * dt / reps,
+           "basis_m": st["m"], "inner_its": st["total_its"], "solved": st["n_solved"],
+           "nonconverged": st["n_nonconv"]}
+    return out, last
 
 
-def measure_jacobian(prob, pts, wl, plain_value: float, res, reps: int = 5):
-    """The reduced Jacobian (eq. (newjac) on the basis) at the last point: rom_reduced_jacobian
-    on the basis `res` of one sequence is timed; the full-order Jacobian by the adjoint
-    approach would need n_src + n_det solves at that point."""
+def measure_workload_forms(name: str, forms: dict, reps: int = 1, keep_plain: bool = False):
+    """Whole sequences of workload `name` in several forms; vs_plain_fp64 = ratio to the
+    first form."""
+    import phantoms as ph
+    from paper_1602_00138_amd import driver
+    wl = ph.WORKLOADS[name]
+    prob = driver.problem_from_workload(wl)
+    pts = driver.points_from_workload(wl)
+    out = {"workload": describe(wl)}
+    base = None
+    kept = None
+    for fname, kw in forms.items():
+        r, res = whole_sequence(prob, pts, wl, reps=reps, **kw)
+        if base is None:
+            base = r["value"]
+        r["vs_plain_fp64"] = r["value"] / base
+        out[fname] = r
+        log(f"{name} {fname}: {r['value']:.1f} solves/s, its {r['inner_its']}, m {r['basis_m']}")
+        if keep_plain and kept is None:
+            kept = res
+        else:
+            res.close()
+    return out, prob, pts, wl, kept
+
+
+def describe(wl) -> str:
+    return (f"{wl.name}: {'x'.join(map(str, wl.N[:wl.dim]))} grid, "
+            f"{'log-normal D' if wl.D == 'lognormal' else 'D=%g' % wl.D}, {wl.nb} bumps, "
+            f"{wl.n_src}+{wl.n_det} RHS, {wl.K} points, tol {wl.tol}"
+            + (f", basis cap {wl.cap}" if wl.cap else ""))
+
+
+def measure_jacobian(prob, pts, res, reps: int = 5):
     import torch
     J = prob.reduced_jacobian(res, pts[-1])
     torch.cuda.synchronize()
@@ -161,22 +263,12 @@ def measure_jacobian(prob, pts, wl, plain_value: float, res, reps: int = 5):
         J = prob.reduced_jacobian(res, pts[-1])
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
-    out = {"ms": ms, "params": int(J.shape[0]), "shape": [int(J.shape[1]), int(J.shape[2])],
-           "basis_m": res.m, "full_order_estimate_ms": 1e3 * prob.n_rhs / plain_value,
-           "note": "per call: A_r(p), its inverse Cholesky factor, the lifted states and "
-                   "co-states V A_r^{-1} [B_r, C_r], one weighted product per parameter; "
-                   "the full-order estimate is n_src + n_det solves at the plain rate"}
-    log(f"reduced Jacobian: {ms:.2f} ms for {out['params']} parameters "
-        f"({out['shape'][0]}x{out['shape'][1]} each, m={out['basis_m']})")
-    return out
+    log(f"reduced Jacobian: {ms:.2f} ms for {J.shape[0]} parameters (m={res.m})")
+    return {"ms": ms, "params": int(J.shape[0]), "shape": [int(J.shape[1]), int(J.shape[2])],
+            "basis_m": res.m}
 
 
-def measure_frequency(prob, pts, wl, res, sigma=(0.3, 1.0, 3.0, 10.0), nb: int = 8,
-                      reps: int = 3):
-    """Nonzero frequency at the last point: the full-order shifted systems of eq. (solves)
-    for nb right-hand sides (sources) and the given sigma = omega/nu by rom_shifted_solve
-    (to relative residual wl.tol), and the reduced response of the basis `res` at the same
-    shifts by rom_reduced_response.  Right-hand sides are resident before timing."""
+def measure_frequency(prob, pts, wl, res, sigma=(0.3, 1.0, 3.0, 10.0), nb: int = 8, reps: int = 3):
     import torch
     p = pts[-1]
     B = torch.zeros((nb, prob.n), dtype=torch.float64)
@@ -191,29 +283,21 @@ def measure_frequency(prob, pts, wl, res, sigma=(0.3, 1.0, 3.0, 10.0), nb: int =
         X, its, resid, _ = prob.shifted_solve(p, B, sigma, tol=wl.tol)
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
-    Psi = prob.reduced_response(res, p, sigma)
+    prob.reduced_response(res, p, sigma)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        Psi = prob.reduced_response(res, p, sigma)
+        prob.reduced_response(res, p, sigma)
     torch.cuda.synchronize()
     ms_r = 1e3 * (time.perf_counter() - t0) / reps
-    out = {"shifts": list(sigma), "rhs": int(idx.size),
-           "shifted_solve_ms": ms, "shifted_solves_per_s": idx.size * len(sigma) / (ms / 1e3),
-           "cg_its_max": int(its.max()), "max_true_resid": float(resid.max()),
-           "reduced_response_ms": ms_r, "basis_m": res.m,
-           "note": "multi-shift CG: one real CG on A(p) per right-hand side serves every "
-                   "shift; reduced response via the SPD system (A_r + sigma^2 A_r^-1) y_r = B_r"}
-    log(f"frequency: {idx.size} RHS x {len(sigma)} shifts in {ms:.1f} ms "
-        f"({out['shifted_solves_per_s']:.0f} shifted solves/s, {out['cg_its_max']} its), "
-        f"reduced response {ms_r:.2f} ms (m={res.m})")
-    return out
+    log(f"frequency: {idx.size} RHS x {len(sigma)} shifts in {ms:.1f} ms, reduced response {ms_r:.2f} ms")
+    return {"shifts": list(sigma), "rhs": int(idx.size), "shifted_solve_ms": ms,
+            "shifted_solves_per_s": idx.size * len(sigma) / (ms / 1e3),
+            "cg_its_max": int(its.max()), "max_true_resid": float(resid.max()),
+            "reduced_response_ms": ms_r, "basis_m": res.m}
 
 
 def measure_modes(prob, pts, wl, reps: int = 3, guards: int = 6):
-    """The U_0 block (the k_u lowest eigenpairs of A(p_0), Algorithm 2's offline input) by
-    rom_lowest_modes from the analytic smooth modes, to eigen-residual 1e-8 of the
-    Gershgorin bound, with `guards` extra block columns; the starting block is resident."""
     import torch
     import phantoms as ph
     k, kx = wl.k_u, wl.k_u + guards
@@ -225,124 +309,93 @@ def measure_modes(prob, pts, wl, reps: int = 3, guards: int = 6):
         U, lam, sweeps = prob.lowest_modes(pts[0], k, X0, tol=1e-8)
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
-    out = {"ms": ms, "k": k, "block": kx, "sweeps": sweeps, "filter_degree": 24,
-           "lambda_min": float(lam[0]), "lambda_k": float(lam[-1]),
-           "note": "Chebyshev-filtered subspace iteration; each filter step is one fused "
-                   "stencil product + three-term recurrence over the block"}
-    log(f"lowest modes: {ms:.2f} ms for k={k} (block {kx}), {sweeps} sweeps, "
-        f"lambda {lam[0]:.4g}..{lam[-1]:.4g}")
-    return out
+    log(f"lowest modes: {ms:.2f} ms for k={k}, {sweeps} sweeps")
+    return {"ms": ms, "k": k, "block": kx, "sweeps": sweeps, "lambda_min": float(lam[0]),
+            "lambda_k": float(lam[-1])}
 
 
-def measure_learned_seed(prob, pts, wl, steps: int, train_steps: int, train_points: int,
-                         plain_value: float, log_every=100):
-    """The learned-seed form: the network is trained on the method's own solutions at
-    other parameter points (untimed, reported), then every timed step runs the network
-    for every (point, RHS) and the mixed-precision sequence started from its guesses."""
+def measure_learned(name: str, train_points: int, train_steps: int, reps: int = 1):
+    """The benchmark spec's target comparison on workload `name`: plain FP64 recycled CG in the
+    paper's order against the batched (groups of 8) mixed-precision form with and without
+    the learned seed, whole sequences on the same problem.  The seed network is trained on
+    the GPU (untimed, reported) on solutions the method produced at other parameter points
+    of the same grid and D field; every timed sequence runs the network for all its
+    (point, right-hand side) pairs first (inference time is inside the timed value)."""
     import torch
     import phantoms as ph
     from paper_1602_00138_amd import driver, seed
     from paper_1602_00138_amd import rom as R
+    wl = ph.WORKLOADS[name]
+    prob = driver.problem_from_workload(wl)
+    pts = driver.points_from_workload(wl)
     twl = wl.replace(seed=wl.seed + 5000, K=train_points)
     tpts = driver.points_from_workload(twl)
     t0 = time.perf_counter()
-    inputs, targets, Xtrain = seed.dataset(prob, tpts, wl.tol, keep_solutions=True)
+    inputs, targets = seed.dataset(prob, tpts, wl.tol, precision=R.ROM_PREC_MIXED, group=8)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = seed.SeedNet(wl.N[:3], 8, seed.he_init(5).astype(np.float32))
     t0 = time.perf_counter()
-    losses = seed.train(net, inputs, targets, steps=train_steps, lr=2e-3, seed=1,
-                        log=lambda m: log(m) if False else None)
+    losses = seed.train(net, inputs, targets, steps=train_steps, lr=2e-3, seed=1)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    nsol = int(targets.shape[0])
     del inputs, targets
-    log(f"seed network: {len(tpts) * prob.n_rhs} training solutions in {t_data:.1f} s, "
-        f"{train_steps} steps in {t_train:.1f} s, loss {np.mean(losses[:10]):.3e} -> "
-        f"{np.mean(losses[-10:]):.3e}")
-    # the second output: 16 recycle vectors per point, trained on the subspace loss
-    rec_steps = max(100, train_steps // 2)
-    rnet = seed.SeedNet(wl.N[:3], 4, seed.he_init(8, outputs=16).astype(np.float32), outputs=16)
-    t0 = time.perf_counter()
-    rlosses = seed.train_recycle(rnet, seed.point_inputs(prob, tpts), Xtrain, prob.n_rhs,
-                                 steps=rec_steps, lr=2e-3, seed=2)
-    torch.cuda.synchronize()
-    t_rtrain = time.perf_counter() - t0
-    del Xtrain
-    log(f"recycle network: {rec_steps} steps in {t_rtrain:.1f} s, subspace loss "
-        f"{np.mean(rlosses[:5]):.3e} -> {np.mean(rlosses[-5:]):.3e}")
-    kw = dict(precision=R.ROM_PREC_MIXED, tune=1)
+    log(f"{name} seed network: {nsol} training solutions in {t_data:.1f} s, {train_steps} "
+        f"steps in {t_train:.1f} s, loss {np.mean(losses[:10]):.3e} -> {np.mean(losses[-10:]):.3e}")
+    out = {"workload": describe(wl),
+           "training": {"points": len(tpts), "solutions": nsol, "steps": train_steps, "batch": 8,
+                        "data_s": t_data, "train_s": t_train,
+                        "loss_first": float(np.mean(losses[:10])),
+                        "loss_last": float(np.mean(losses[-10:]))}}
+    plain, res = whole_sequence(prob, pts, wl, reps=reps)
+    res.close()
+    out["plain_fp64"] = plain
+    log(f"{name} plain FP64: {plain['value']:.1f} solves/s, its {plain['inner_its']}")
+    kw = dict(precision=R.ROM_PREC_MIXED, group=8, tune=1)
+    mg, res = whole_sequence(prob, pts, wl, reps=reps, **kw)
+    res.close()
+    mg["vs_plain_fp64"] = mg["value"] / plain["value"]
+    out["mixed_group8"] = mg
+    log(f"{name} mixed group 8: {mg['value']:.1f} solves/s, its {mg['inner_its']}")
+    # learned: inference inside every timed sequence
     g = seed.guesses(net, prob, pts)
-    prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, guess=g, **kw).close()
+    prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, **kw).close()
     torch.cuda.synchronize()
-    t_inf = 0.0
     t0 = time.perf_counter()
+    t_inf = 0.0
     last = None
-    for _ in range(steps):
+    for _ in range(reps):
         if last is not None:
             last.close()
         ti = time.perf_counter()
         g = seed.guesses(net, prob, pts)
         torch.cuda.synchronize()
         t_inf += time.perf_counter() - ti
-        last = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, guess=g, **kw)
+        last = prob.solve(pts, wl.tol, wl.trunc, keep_X=False, guess=g, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    K, n_rhs = len(pts), prob.n_rhs
     st = last.stats
     drops = [np.log10(r["rho0"] / r["rho_guess"]) for r in last.records
              if r["solved"] and r["rho_guess"] > 0]
-    out = {"value": K * n_rhs * steps / dt, "ms_per_step": 1e3 * dt / steps,
-           "inference_ms_per_step": 1e3 * t_inf / steps, "vs_plain_fp64": K * n_rhs * steps / dt / plain_value,
-           "basis_m": st["m"], "inner_its": st["total_its"], "solved": st["n_solved"],
-           "mean_log10_residual_drop": float(np.mean(drops)) if drops else 0.0,
-           "training": {"points": len(tpts), "solutions": len(tpts) * n_rhs, "steps": train_steps,
-                        "batch": 8, "data_s": t_data, "train_s": t_train,
-                        "loss_first": float(np.mean(losses[:10])),
-                        "loss_last": float(np.mean(losses[-10:]))},
-           "precision": "mixed", "group": 1}
-    last.close()
-    log(f"learned seed (mixed): {out['value']:.1f} solves/s, its {st['total_its']}, "
-        f"inference {out['inference_ms_per_step']:.0f} ms/step, residual drop 10^{out['mean_log10_residual_drop']:.2f}")
-    # both outputs: guesses and recycle vectors, inference inside every timed step
-    g = seed.guesses(net, prob, pts)
-    rv = seed.recycle_vectors(rnet, prob, pts)
-    prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, guess=g, recycle=rv, **kw).close()
-    torch.cuda.synchronize()
-    t_inf = 0.0
-    t0 = time.perf_counter()
-    last = None
-    for _ in range(steps):
-        if last is not None:
-            last.close()
-        ti = time.perf_counter()
-        g = seed.guesses(net, prob, pts)
-        rv = seed.recycle_vectors(rnet, prob, pts)
-        torch.cuda.synchronize()
-        t_inf += time.perf_counter() - ti
-        last = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False, guess=g, recycle=rv, **kw)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st2 = last.stats
-    out["with_recycle_vectors"] = {
-        "value": K * n_rhs * steps / dt, "ms_per_step": 1e3 * dt / steps,
-        "inference_ms_per_step": 1e3 * t_inf / steps,
-        "vs_plain_fp64": K * n_rhs * steps / dt / plain_value, "basis_m": st2["m"],
-        "inner_its": st2["total_its"], "solved": st2["n_solved"],
-        "training": {"steps": rec_steps, "batch": 4, "train_s": t_rtrain,
-                     "loss_first": float(np.mean(rlosses[:5])),
-                     "loss_last": float(np.mean(rlosses[-5:]))}}
+    lv = {"value": len(pts) * prob.n_rhs * reps / dt, "ms_per_sequence": 1e3 * dt / reps,
+          "inference_ms_per_sequence": 1e3 * t_inf / reps, "basis_m": st["m"],
+          "inner_its": st["total_its"], "solved": st["n_solved"], "nonconverged": st["n_nonconv"],
+          "mean_log10_residual_drop": float(np.mean(drops)) if drops else 0.0}
+    lv["vs_plain_fp64"] = lv["value"] / plain["value"]
+    lv["vs_mixed_group8"] = lv["value"] / mg["value"]
+    out["mixed_group8_learned"] = lv
+    log(f"{name} mixed group 8 + learned seed: {lv['value']:.1f} solves/s, its {lv['inner_its']}, "
+        f"inference {lv['inference_ms_per_sequence']:.0f} ms/sequence")
     last.close()
     net.close()
-    rnet.close()
-    log(f"learned seed + recycle vectors (mixed): {out['with_recycle_vectors']['value']:.1f} "
-        f"solves/s, its {st2['total_its']}, inference "
-        f"{out['with_recycle_vectors']['inference_ms_per_step']:.0f} ms/step")
+    prob.close()
     return out
 
 
-def measure_concurrent(names, steps: int, **kw):
-    """Independent sequences on uneven grids: solves/s run one after another vs all at
-    once (rom_solve_sequences, one stream and host thread each)."""
+def measure_concurrent(names, **kw):
+    """The uneven grids: solves/s one sequence after another vs all at once
+    (rom_solve_sequences, one stream and host thread each)."""
     import torch
     import phantoms as ph
     from paper_1602_00138_amd import driver
@@ -355,58 +408,88 @@ def measure_concurrent(names, steps: int, **kw):
         r.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        for prob, p in zip(probs, pts):
-            prob.solve(p, tol, keep_X=False, **kw).close()
+    for prob, p in zip(probs, pts):
+        prob.solve(p, tol, keep_X=False, **kw).close()
     torch.cuda.synchronize()
-    serial = total * steps / (time.perf_counter() - t0)
+    serial = total / (time.perf_counter() - t0)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        for r in driver.solve_many(probs, pts, tol, **kw):
-            r.close()
+    for r in driver.solve_many(probs, pts, tol, **kw):
+        r.close()
     torch.cuda.synchronize()
-    conc = total * steps / (time.perf_counter() - t0)
+    conc = total / (time.perf_counter() - t0)
     log(f"{'+'.join(names)}: serial {serial:.1f} solves/s, concurrent {conc:.1f} solves/s")
+    for p in probs:
+        p.close()
     return {"workloads": {w.name: "x".join(map(str, w.N[:w.dim])) for w in wls},
             "solves": total, "serial": serial, "concurrent": conc}
+
+
+def cpu_baseline(wl, pts, gpu_its_per_solve: float, budget_s: float = 25.0):
+    """The FP64 oracle, untuned, on a bounded sample of the headline workload: assembly, then
+    point 0's right-hand sides one by one (orthonormalise U_0, outer projection, deflated
+    CG, append) until budget_s has passed.  Also an iteration-normalised rate: the
+    oracle's seconds per CG iteration on this grid, times the GPU's mean iterations per solve
+    over the timed points, as solves/s at the GPU's work mix."""
+    import threadpoolctl
+
+    import phantoms as ph
+    from oracle import operator as op
+    from oracle import sequence as oseq
+    t0 = time.perf_counter()
+    D = ph.diffusion_field(wl)
+    As = op.assemble_Astar(wl.dim, wl.N, wl.bc, D, wl.robin_A)
+    p = pts[0]
+    mu = op.mu_field(wl.dim, wl.N, p.mu0, p.centers, p.radii, p.amps)
+    si, di = ph.rhs_nodes(wl)
+    ss, ds = ph.rhs_scales(wl)
+    Bfull = oseq.rhs_matrix(wl.n, si, ss, di, ds)
+    U0 = ph.smooth_modes(wl)
+    t_setup = time.perf_counter() - t0
+    done, its, t_solve = 0, 0, 0.0
+    while done < Bfull.shape[1] and t_setup + t_solve < budget_s:
+        t1 = time.perf_counter()
+        res = oseq.solve_sequence(As, [mu], Bfull[:, :done + 1], U0, wl.tol, wl.trunc, cap=wl.cap,
+                                  keep_X=False)
+        t_solve = time.perf_counter() - t1
+        done += 1
+        its = sum(r.its for r in res.records)
+    info = threadpoolctl.threadpool_info()
+    blas = max([d.get("num_threads", 1) for d in info] + [1])
+    per_it = t_solve / max(its, 1)
+    return {"value": done / (t_setup + t_solve), "unit": "solves/s", "cores": nproc(),
+            "kind": "oracle",
+            "sample": f"{wl.name}: assembly ({t_setup:.1f} s) + point 0, right-hand sides 1-{done} "
+                      f"({its} CG iterations, {t_solve:.1f} s); scipy.sparse products "
+                      f"single-threaded, dense NumPy/BLAS on {blas} threads of {nproc()} cores",
+            "iteration_normalised": {"s_per_cg_iteration": per_it,
+                                     "gpu_its_per_solve": gpu_its_per_solve,
+                                     "solves_per_s": 1.0 / (per_it * max(gpu_its_per_solve, 1e-9)),
+                                     "note": "the oracle's time per CG iteration on this grid times "
+                                             "the GPU's mean inner iterations per solve over the "
+                                             "timed points (outer projections and appends not "
+                                             "counted)"}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube64")
-    ap.add_argument("--points", type=int, default=0, help="parameter points (0: the workload's)")
-    ap.add_argument("--tol", type=float, default=0.0)
-    ap.add_argument("--mode", default="independent", choices=["independent", "drift"])
-    ap.add_argument("--cpu-sample", type=int, default=24, help="oracle sample RHS (0: skip)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
-                    help="fp64: plain FP64 recycled CG; mixed: FP32 inner sweeps in FP64 refinement")
-    ap.add_argument("--group", type=int, default=1,
-                    help="right-hand sides per batch (1: the paper's order, up to 16)")
-    ap.add_argument("--tune", type=int, default=1, help="autotune the CG launch shape (0/1)")
-    ap.add_argument("--graph", type=int, default=0, help="replay CG steps from captured HIP graphs")
-    ap.add_argument("--forms", type=int, default=1,
-                    help="also time the mixed / grouped forms on the same problem (0/1)")
-    ap.add_argument("--jacobian", type=int, default=1,
-                    help="time the reduced Jacobian at the last point (0/1)")
-    ap.add_argument("--frequency", type=int, default=1,
-                    help="time the nonzero-frequency solves and reduced response (0/1)")
-    ap.add_argument("--modes", type=int, default=1,
-                    help="time the lowest-eigenpair block U_0 at the first point (0/1)")
-    ap.add_argument("--suite", type=int, default=0,
-                    help="also time the uneven-grid workload (48^3, 64^3, 96^3 sequences)")
-    ap.add_argument("--seed-steps", type=int, default=0,
-                    help="train the seed network this many steps and time the learned-seed form")
-    ap.add_argument("--seed-points", type=int, default=16, help="training points for the seed network")
+    ap.add_argument("--steps", type=int, default=27, help="timed parameter points")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed parameter points before them")
+    ap.add_argument("--workload", default="cube128_lognormal")
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--group", type=int, default=1, help="right-hand sides per batch (1: the paper's order)")
+    ap.add_argument("--tune", type=int, default=1)
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also time the other forms and workloads, the SpMM, the reduced "
+                         "Jacobian, U_0 and nonzero frequency (0: headline and roofline only)")
+    ap.add_argument("--learned", type=int, default=1,
+                    help="train the seed network and time the learned form on cube96_lognormal")
+    ap.add_argument("--seed-steps", type=int, default=200)
+    ap.add_argument("--seed-points", type=int, default=16)
+    ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of oracle work (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0,
-                    help="only run 3 plain device copies of 1 GiB (the reference for the "
-                         "HBM traffic counters) and exit")
-    ap.add_argument("--kernel", default="outer",
-                    help="kernel class for the roofline (outer: the per-RHS start x0 = V c, "
-                         "k_gemvn4x3 fused with the previous append's Gram-Schmidt pass or "
-                         "k_gemvn4<false>; auto: the class with the most event time)")
+                    help="only run 3 plain device copies of 1 GiB (the reference for the HBM "
+                         "traffic counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -433,153 +516,106 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     wl = ph.WORKLOADS[args.workload]
-    if args.points:
-        wl = wl.replace(K=args.points)
-    if args.tol:
-        wl = wl.replace(tol=args.tol)
+    W, K = max(args.warmup, 1), max(args.steps, 1)
     prob = driver.problem_from_workload(wl)
-    pts = driver.points_from_workload(wl, mode=args.mode)
-    K, n_rhs = len(pts), prob.n_rhs
-    dev = torch.device("cuda:0")
-
-    # caller-owned buffers, allocated once outside the timed region
+    pts = driver.points_from_workload(wl, K=W + K)
     prec = R.ROM_PREC_MIXED if args.precision == "mixed" else R.ROM_PREC_FP64
-    opts_all = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=(1 << R.ROM_NK) - 1, precision=prec,
-                           group=args.group, tune=args.tune, graph=args.graph)
-    nbytes = R.rom_sequence_bytes(prob.op, prob.src_idx.size, prob.det_idx.size, prob.k_u, K, opts_all)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    X = torch.empty((K * n_rhs, prob.n), dtype=torch.float64, device=dev)
-    log(f"workload {wl.name}: grid {wl.N[:wl.dim]}, n={prob.n}, {n_rhs} RHS x {K} points, "
-        f"tol {wl.tol}, workspace {nbytes / 2**30:.2f} GiB")
-
-    def step(opts):
-        R.rom_assemble_operator(prob.grid, 0.0 if prob.D_field is not None else float(wl.D),
-                                prob.D_field, prob.op_mem)
-        status, basis, recs, st = R.rom_solve_sequence(
-            prob.op, pts, prob.src_idx, prob.src_scale, prob.det_idx, prob.det_scale, prob.U0,
-            prob.k_u, opts, ws, X)
-        n, m = R.rom_basis_dims(basis)
-        Ar = torch.empty((m, m), dtype=torch.float64, device=dev)
-        Br = torch.empty((prob.src_idx.size, m), dtype=torch.float64, device=dev)
-        Cr = torch.empty((prob.det_idx.size, m), dtype=torch.float64, device=dev)
-        Er = torch.empty((m, m), dtype=torch.float64, device=dev)
-        scr = torch.empty(R.rom_reduced_bytes(basis), dtype=torch.uint8, device=dev)
-        R.rom_reduced_transfer(basis, pts[-1], Ar, Br, Cr, Er, scr)
-        R.rom_basis_destroy(basis)
-        return status, recs, R.stats_dict(st)
-
-    # warmup (all kernel classes timed, to find the dominant one)
-    stats_w = None
-    for w in range(max(args.warmup, 1)):
-        t = time.perf_counter()
-        status, recs, stats_w = step(opts_all)
-        torch.cuda.synchronize()
-        log(f"warmup {w}: {time.perf_counter() - t:.2f} s, m={stats_w['m']}, "
-            f"solved {stats_w['n_solved']}/{K * n_rhs}, its {stats_w['total_its']}")
-    kern = stats_w["kernels"]
-    for name, d in kern.items():
-        if d["launches"] and d["ms"] > 0:
-            log(f"  {name:11s} launches {d['launches']:7d}  {d['ms']:9.2f} ms  "
-                f"{d['bytes'] / max(d['ms'], 1e-9) / 1e6:8.0f} GB/s (algorithmic)")
-    dom = args.kernel
-    if dom == "auto":
-        dom = max((k for k in kern if k != "other"), key=lambda k: kern[k]["ms"])
-    cls = R.KERNEL_CLASSES.index(dom)
-    opts = R.make_opts(wl.tol, wl.trunc, wl.cap, timing=1 << cls, precision=prec, group=args.group,
-                       tune=args.tune, graph=args.graph)
-
+    log(f"headline {describe(wl)}; {args.precision}, group {args.group}; warmup points {W}, "
+        f"timed points {K}")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    agg = {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0}
-    bad = 0
-    last = None
-    for s in range(args.steps):
-        status, recs, st = step(opts)
-        d = st["kernels"][dom]
-        for k in agg:
-            agg[k] += d[k]
-        bad += sum(1 for r in recs if not r["converged"])
-        last = st
-        log(f"step {s}: {st['seconds']:.3f} s in solve_sequence")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    solves = K * n_rhs * args.steps
-    value = solves / dt
 
-    avg_ms = agg["ms"] / max(agg["launches"], 1)
-    bound = "mfma" if dom == "gram" else "hbm"
-    if bound == "hbm":
-        achieved = agg["bytes"] / max(agg["ms"], 1e-12) / 1e6
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    else:
-        achieved = agg["flops"] / max(agg["ms"], 1e-12) / 1e9
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
-    roof.update({"kernel": dom, "launches": agg["launches"], "avg_launch_us": 1e3 * avg_ms,
-                 "bytes_per_launch": agg["bytes"] / max(agg["launches"], 1)})
-    # the counters were taken on cube64 (plain FP64, sequential order); elsewhere: null
-    tr = traffic_ratio() if (dom == "outer" and args.precision == "fp64" and args.group == 1
-                             and wl.name == "cube64") else None
-    if tr is not None:
-        roof["traffic"] = tr * roof["bytes_per_launch"]
-        roof["traffic_source"] = "profiles/traffic_outer_projection_cube64.md (ratio %.3f)" % tr
-
-    spmm = spmm_bandwidth(prob, pts[-1], 64)
-    log(f"SpMM k=64: {spmm['GBps']:.0f} GB/s ({100 * spmm['frac_of_peak']:.1f}% of 8 TB/s); "
-        f"operands resident {spmm['resident_GBps']:.0f} GB/s; plain copy {spmm['copy_GBps']:.0f} GB/s")
-
-    jac = freq = None
-    if args.jacobian or args.frequency:
-        basis = prob.solve(pts, wl.tol, wl.trunc, cap=wl.cap, keep_X=False)
-        jac = measure_jacobian(prob, pts, wl, value, basis) if args.jacobian else None
-        freq = measure_frequency(prob, pts, wl, basis) if args.frequency else None
-        basis.close()
-    modes = measure_modes(prob, pts, wl) if args.modes else None
-    forms = measure_forms(prob, pts, wl, args.steps) if args.forms else None
-    if forms:
-        for f in forms.values():
-            f["vs_plain_fp64"] = f["value"] / value
-    learned = None
-    if args.seed_steps > 0:
-        learned = measure_learned_seed(prob, pts, wl, args.steps, args.seed_steps,
-                                       args.seed_points, value)
-    suite = None
-    if args.suite:
-        from paper_1602_00138_amd import rom as R2
-        suite = measure_concurrent(["uneven48", "uneven64", "uneven96"], 1, precision=R2.ROM_PREC_MIXED,
-                                   group=8, tune=1)
-
-    cpu = None
-    if args.cpu_sample > 0:
-        cpu = cpu_baseline(wl, ph.parameter_points(wl, mode=args.mode), args.cpu_sample)
-        log(f"cpu oracle: {cpu['value']:.3f} solves/s ({cpu['sample']})")
+    # ---- headline: the timed points, the CG operator step timed with events
+    h = stream_points(prob, pts, W, K, wl, timing=1 << R.ROM_K_DCG_OP, precision=prec,
+                      group=args.group, tune=args.tune)
+    timed = h["timed"]
+    value = h["value"]
+    recs = h["records"]
+    solved = [r for r in recs if r["solved"]]
+    its_per_solve = timed["total_its"] / max(len(solved), 1)
+    roof = dcg_roofline(timed, args.precision, prob, wl)
+    log(f"headline: {value:.1f} solves/s over points {W}..{W + K - 1} "
+        f"({K * prob.n_rhs} solves, {timed['total_its']} inner its, {len(solved)} solved); "
+        f"k_dcg_op {roof['achieved']:.0f} GB/s ({100 * roof['frac']:.1f}% of peak), "
+        f"{roof['avg_launch_us']:.1f} us per launch")
+    final = h["result"]
+    m_final = final.m
+    final.close()
 
     out = {
-        "metric": "full-order solves/sec at 1e-8 rel. residual; SpMM HBM GB/s vs peak",
-        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": 1e3 * h["seconds"] / K, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == R.ROM_PREC_FP64 else "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {'x'.join(map(str, wl.N[:wl.dim]))} grid, "
-                               f"{wl.n_src}+{wl.n_det} RHS, {K} points ({args.mode}), tol {wl.tol}, "
-                               + ("plain FP64 recycled CG" if prec == R.ROM_PREC_FP64 else
-                                  "FP32 inner recycled CG in FP64 refinement")
-                               + (f", groups of {args.group} RHS" if args.group > 1 else ""),
-                   "group": args.group, "precision": args.precision,
-                   "n": prob.n, "points": K, "rhs": n_rhs, "tol": wl.tol,
-                   "basis_m": last["m"], "inner_its": last["total_its"],
-                   "solved": last["n_solved"], "nonconverged": bad},
+        "config": {"workload": describe(wl) + "; " + (
+                       "plain FP64 recycled CG" if prec == R.ROM_PREC_FP64 else
+                       "FP32 inner recycled CG in FP64 refinement")
+                   + (f", groups of {args.group} RHS" if args.group > 1 else "")
+                   + f"; a step = one parameter point ({prob.n_rhs} solves + reduced matrices), "
+                     f"points {W}..{W + K - 1} of the sequence timed",
+                   "group": args.group, "precision": args.precision, "n": prob.n,
+                   "rhs_per_point": prob.n_rhs, "tol": wl.tol, "basis_m": m_final,
+                   "inner_its": timed["total_its"], "solved": len(solved),
+                   "inner_its_per_solve": its_per_solve,
+                   "nonconverged": sum(1 for r in recs if not r["converged"])},
         "roofline": roof,
-        "spmm": spmm,
-        "forms": forms,
-        "reduced_jacobian": jac,
-        "lowest_modes": modes,
-        "frequency": freq,
-        "learned_seed": learned,
-        "uneven_grids": suite,
-        "cpu_baseline": cpu,
     }
+
+    # the same run with every kernel class timed, for the per-class table (not the value)
+    if args.extras:
+        W2, K2 = min(W, 3), min(K, 3)
+        hc = stream_points(prob, pts, W2, K2, wl, timing=(1 << R.ROM_NK) - 1, precision=prec,
+                           group=args.group, tune=args.tune, reduce_each=False)
+        hc["result"].close()
+        out["kernel_classes"] = {"points": f"{W2}..{W2 + K2 - 1} with every class timed",
+                                 "classes": class_table(hc["timed"])}
+        # the other forms of config 4's method on the same points
+        forms = {}
+        for fname, kw in (("fp64", dict(precision=R.ROM_PREC_FP64)),
+                          ("mixed_group8", dict(precision=R.ROM_PREC_MIXED, group=8))):
+            hf = stream_points(prob, pts, W2, K2 + 3, wl, precision=kw["precision"],
+                               group=kw.get("group", 1), tune=1, reduce_each=False)
+            hf["result"].close()
+            forms[fname] = {"value": hf["value"], "points": f"{W2}..{W2 + K2 + 2}",
+                            "inner_its": hf["timed"]["total_its"]}
+            log(f"{wl.name} {fname}: {hf['value']:.1f} solves/s on points {W2}..{W2 + K2 + 2}")
+        ref_mixed = stream_points(prob, pts, W2, K2 + 3, wl, precision=prec, group=args.group,
+                                  tune=1, reduce_each=False)
+        ref_mixed["result"].close()
+        forms["headline_form_same_points"] = {"value": ref_mixed["value"],
+                                              "inner_its": ref_mixed["timed"]["total_its"]}
+        for f in forms.values():
+            f["vs_fp64"] = f["value"] / forms["fp64"]["value"]
+        out["forms"] = forms
+        out["spmm"] = {"cube128_lognormal_k96": spmm_bandwidth(prob, pts[W + K - 1], 96)}
+        log(f"SpMM 128^3 k=96: {out['spmm']['cube128_lognormal_k96']['GBps']:.0f} GB/s")
+    prob.close()
+
+    if args.extras:
+        # config 2 (64^3): plain FP64 and the batched mixed form, whole sequences; the basis
+        # of the plain run feeds the reduced Jacobian and nonzero-frequency entries
+        c2, p2, pts2, wl2, basis2 = measure_workload_forms(
+            "cube64", {"plain_fp64": {}, "mixed_group8": dict(precision=R.ROM_PREC_MIXED, group=8,
+                                                              tune=1)},
+            reps=2, keep_plain=True)
+        out["cube64"] = c2
+        out["spmm"]["cube64_k64"] = spmm_bandwidth(p2, pts2[-1], 64)
+        log(f"SpMM 64^3 k=64: {out['spmm']['cube64_k64']['GBps']:.0f} GB/s")
+        out["reduced_jacobian"] = measure_jacobian(p2, pts2, basis2)
+        out["frequency"] = measure_frequency(p2, pts2, wl2, basis2)
+        out["lowest_modes"] = measure_modes(p2, pts2, wl2)
+        basis2.close()
+        p2.close()
+        # config 3: the uneven grids, one after another vs at once
+        out["uneven_grids"] = measure_concurrent(["uneven48", "uneven64", "uneven96"],
+                                                 precision=R.ROM_PREC_MIXED, group=8, tune=1)
+    if args.learned:
+        # config 5 (96^3, log-normal D, 64 + 64 RHS): the target comparison
+        out["learned_seed"] = measure_learned("cube96_lognormal", args.seed_points, args.seed_steps)
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, ph.parameter_points(wl, K=1), its_per_solve,
+                                           args.cpu_budget)
+        log(f"cpu oracle: {out['cpu_baseline']['value']:.4f} solves/s ({out['cpu_baseline']['sample']})")
+    out["paper"] = PAPER
     print(json.dumps(out), flush=True)
 
 

@@ -124,7 +124,7 @@ typedef struct {
                        output).  A solve that the outer test does not skip first moves to the
                        A(p_i)-optimal point of x0 + span(guess - x0) when that lowers the
                        residual; the correction appended to V and U_j is still x - x0.
-                       Needs group <= 1. */
+                       With groups each member takes this step from the group's start. */
   const float* recycle; /* device, or NULL: n_recycle learned recycle vectors per point i, N
                        values each at column (i n_recycle + c).  At each point they are made
                        A(p_i)-orthogonal to V as it stands at the point start (the part the
@@ -152,9 +152,9 @@ typedef struct {
 } rom_record;
 
 /* Instrumented kernel classes (event timing for the classes set in opts.timing). */
-#define ROM_K_SPMV 0        /* stencil products */
-#define ROM_K_DCG_UPDATE 1  /* CG step: g += a p, s -= a w, s^T s, (A U_j)^T s */
-#define ROM_K_DCG_DIR 2     /* CG step: p = s + b p - U_j y */
+#define ROM_K_DCG_OP 0      /* CG operator step: w = A q - (A U_j) c and its dot products */
+#define ROM_K_DCG_UPDATE 1  /* CG update: s -= a w, g += a q, q = s + b q, s^T s */
+#define ROM_K_DCG_ENDS 2    /* start and end of each inner solve (g = U_j y0, g -= U_j e) */
 #define ROM_K_GEMVT 3       /* V^T x (tall-skinny transposed products) */
 #define ROM_K_GEMVN 4       /* V c (tall-skinny products) */
 #define ROM_K_GRAM 5        /* V^T diag(w) V (FP64 MFMA) */
@@ -172,6 +172,8 @@ typedef struct {
   double kernel_bytes[ROM_NK];   /* summed algorithmic bytes per class */
   double kernel_flops[ROM_NK];   /* summed algorithmic flops per class */
   long long kernel_launches[ROM_NK];
+  int n_uj_capped;       /* kept corrections that did not join U_j because U_j already had
+                            ROM_NJ_MAX columns (the paper's U_j grows without bound) */
 } rom_stats;
 
 /* Device bytes needed by rom_assemble_operator (variable_D = 1 for a per-node D). */
@@ -228,6 +230,35 @@ ROM_API rom_status rom_solve_sequence(rom_operator* op, const rom_mu* params, in
                               void* workspace, size_t ws_bytes, rom_basis** basis,
                               double* X_out, rom_record* records, rom_stats* stats,
                               void* stream);
+
+/* Algorithm 2 one parameter point at a time, for callers whose points arrive one by one
+ * (the iterates of an optimiser): the same method and results as rom_solve_sequence,
+ * whose K points are rom_sequence_point calls in order.
+ *   rom_sequence_begin: arguments as rom_solve_sequence; K is the most points the
+ *     sequence will take (it sizes the workspace through rom_sequence_bytes and sets the
+ *     default basis cap k_u + n_rhs K).  U0 is read during the first point (keep it alive
+ *     until then).  All later work runs on `stream`.  *seq receives the handle.
+ *   rom_sequence_point: the next point p (host); X_out (device, N x n_rhs, ld N, or NULL)
+ *     receives its solutions, records (host, n_rhs entries, or NULL) its records.
+ *     Returns when the point's work is complete: ROM_OK, ROM_ENOCONV (a solve of this point
+ *     reached maxit), ROM_EINVAL past K points, or an error that stops the sequence (later
+ *     calls other than rom_sequence_end then return ROM_EINVAL).
+ *   rom_sequence_basis: the basis as it stands (a view into the workspace, for
+ *     rom_reduced_transfer and the other basis calls; valid until the next call on seq).
+ *   rom_sequence_stats: the totals so far (as rom_stats; seconds since begin).
+ *   rom_sequence_end: releases seq; *basis (if not NULL) receives the global basis (as
+ *     from rom_solve_sequence; NULL after an error) and *stats (if not NULL) the totals. */
+typedef struct rom_sequence rom_sequence;
+ROM_API rom_status rom_sequence_begin(rom_operator* op, int K, const int64_t* src_idx,
+                                      const double* src_scale, int n_src, const int64_t* det_idx,
+                                      const double* det_scale, int n_det, const double* U0,
+                                      int k_u, const rom_opts* opts, void* workspace,
+                                      size_t ws_bytes, rom_sequence** seq, void* stream);
+ROM_API rom_status rom_sequence_point(rom_sequence* seq, const rom_mu* p, double* X_out,
+                                      rom_record* records);
+ROM_API rom_status rom_sequence_basis(rom_sequence* seq, const rom_basis** V);
+ROM_API rom_status rom_sequence_stats(rom_sequence* seq, rom_stats* stats);
+ROM_API rom_status rom_sequence_end(rom_sequence* seq, rom_basis** basis, rom_stats* stats);
 
 /* Several independent sequences at once (e.g. one per grid of a set of uneven grids):
  * each job holds the arguments of one rom_solve_sequence call; every job runs on its own

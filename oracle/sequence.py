@@ -25,6 +25,9 @@ uses CG with A-orthogonal projections):
   * U_j is stored orthonormal (U_0 part = the first columns of Q; each added
     column CGS2-orthogonalised against U_j); a correction joins U_j only if it
     joined V, so range(U_j) stays inside range(V).
+  * uj_cap (None: unbounded, as in the paper): the most columns U_j may hold; a kept
+    correction joins V but not U_j once U_j has uj_cap columns, and X_0(:, j) joins
+    U_j only while k_u < uj_cap (the GPU library holds U_j in at most 64 columns);
   * group g (the batched form; g = 1 is the paper's order): the right-hand sides of
     a point are taken in consecutive groups of g.  Every member of a group is
     projected on the basis as it stands at the start of the group and solved
@@ -87,7 +90,8 @@ def _inner_solve(A, b, nb, x0, r, Wj, tol, maxit):
 
 def solve_sequence(Astar: sp.csr_matrix, mus: List[np.ndarray], B: np.ndarray, U0: np.ndarray,
                    tol: float, trunc: float = 1e-8, cap: int = 0, maxit: Optional[int] = None,
-                   keep_X: bool = True, group: int = 1) -> SequenceResult:
+                   keep_X: bool = True, group: int = 1,
+                   uj_cap: Optional[int] = None) -> SequenceResult:
     n, n_rhs = B.shape
     if group < 1:
         raise ValueError("group must be >= 1")
@@ -139,7 +143,7 @@ def solve_sequence(Astar: sp.csr_matrix, mus: List[np.ndarray], B: np.ndarray, U
                     if kept:
                         Q = np.column_stack([Q, q])
                         AQ = np.column_stack([AQ, A @ q])
-                        if i > 0:
+                        if i > 0 and (uj_cap is None or Wj.shape[1] < uj_cap):
                             w, _ = cgs2_append(Wj, g, trunc)
                             if w is not None:
                                 W_extra[j].append(w)
@@ -149,7 +153,7 @@ def solve_sequence(Astar: sp.csr_matrix, mus: List[np.ndarray], B: np.ndarray, U
         if i == 0:
             for j in range(n_rhs):
                 w, _ = cgs2_append(Q[:, :k_u], Xi[:, j], trunc)
-                W_extra[j] = [w] if w is not None else []
+                W_extra[j] = [w] if w is not None and (uj_cap is None or k_u < uj_cap) else []
         X.append(Xi)
     return SequenceResult(Q, X, records, W_extra, k_u)
 

@@ -1,25 +1,47 @@
-"""Build the gfx950 shared library librom.so in-tree with hipcc."""
+"""Build the gfx950 shared library librom.so in-tree with hipcc (one object per source,
+compiled in parallel, then linked)."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librom.so")
 SOURCES = ["stencil.hip", "dense.hip", "gram.hip", "dcg.hip", "modes.hip", "freq.hip", "runtime.hip",
            "seednet.hip", "seedrt.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-fvisibility=hidden", "-pthread", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
+def _jobs() -> int:
+    try:
+        return max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    except ValueError:
+        return 1
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into librom.so (always recompiles)."""
+    """Compile every HIP source and link librom.so (always recompiles)."""
+    os.makedirs(OBJ, exist_ok=True)
+
+    def compile_one(src: str) -> str:
+        obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True, cwd=CSRC)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=CSRC)

@@ -197,6 +197,46 @@ __device__ __forceinline__ void stencil_walk2(const Stencil& S, const double* __
   stencil_walk2t<double, VAR>(S, diag, x, q, z0, z1, static_cast<F&&>(f));
 }
 
+// stencil_walk in arithmetic T (double, or float with the FP32 face coefficients): one
+// x-y position q through the z planes [z0, z1), f(i, (A x)_i, x_i) per node.
+template <typename T, bool VAR, class F>
+__device__ __forceinline__ void stencil_walk1t(const Stencil& S, const T* __restrict__ diag,
+                                               const T* __restrict__ x, int q, int z0, int z1,
+                                               F&& f) {
+  const T *Fx, *Fy, *Fz;
+  walk_faces(S, T(0), Fx, Fy, Fz);
+  const T cx = (T)S.cx, cy = (T)S.cy, cz = (T)S.cz;
+  const int nxy = S.nx * S.ny;
+  const int ix = q % S.nx, iy = q / S.nx;
+  const bool hl = ix > 0, hr = ix < S.nx - 1, hd = iy > 0, hu = iy < S.ny - 1;
+  int64_t i = (int64_t)z0 * nxy + q;
+  T xm = z0 > 0 ? x[i - nxy] : T(0);
+  T fm = (VAR && z0 > 0) ? Fz[i - nxy] : T(0);
+  T xc = x[i];
+  for (int z = z0; z < z1; ++z, i += nxy) {
+    const T xp = z < S.nz - 1 ? x[i + nxy] : T(0);
+    T v = diag[i] * xc;
+    if (!VAR) {
+      const T sx = (hl ? x[i - 1] : T(0)) + (hr ? x[i + 1] : T(0));
+      const T sy = (hd ? x[i - S.nx] : T(0)) + (hu ? x[i + S.nx] : T(0));
+      v -= cx * sx + cy * sy + cz * (xm + xp);
+    } else {
+      if (hl) v -= Fx[i - 1] * x[i - 1];
+      if (hr) v -= Fx[i] * x[i + 1];
+      if (hd) v -= Fy[i - S.nx] * x[i - S.nx];
+      if (hu) v -= Fy[i] * x[i + S.nx];
+      if (S.dim == 3) {
+        const T fp = Fz[i];
+        v -= fm * xm + fp * xp;
+        fm = fp;
+      }
+    }
+    f(i, v, xc);
+    xm = xc;
+    xc = xp;
+  }
+}
+
 // Whether the two-node walk applies: even nx and 16-byte aligned arrays at even leading
 // dimensions (ld of every column array passed in `ld`).
 inline bool stencil_pairs_ok(const Stencil& S, int64_t ld, std::initializer_list<const void*> ptrs,

@@ -1,53 +1,56 @@
-// Deflated (recycled) CG on A g = r with the recycle space U_j (Sec. 4.2.1, CG form):
-// directions are kept A-orthogonal to U_j by p = s + beta p - U_j (U_j^T A U_j)^{-1}
-// (A U_j)^T s.  Every step is three launches (operator, update, direction).  No kernel
-// synchronises across blocks: each writes per-block partial sums and the next launch
-// reduces them; the scalar state lives in device memory (s^T s double-buffered by
-// step parity), so chunks of steps run without host round trips.  Each thread loads
-// its first row before reducing the previous launch's partials, so the reduction
-// latency hides behind the loads.  T is the vector type: double for the plain form,
-// float for the inner sweeps of the mixed form (FP32 vectors and FP32 sums); the CG
-// scalars, the tolerance and (U^T A U)^{-1} stay FP64 in either case.
+// Deflated (recycled) CG on A g = r with the recycle space U = U_j (Sec. 4.2.1, CG form):
+// the directions are kept A-orthogonal to U, p_k = s_k + beta p_{k-1} - U G^{-1} (AU)^T s_k
+// with G = U^T A U.
+//
+// Two launches per step.  The direction is carried split as p_k = q_k - U c_k, with
+// q_k = s_k + beta q_{k-1} and c_k = G^{-1} (AU)^T s_k + beta c_{k-1}, so that U itself is
+// only read once per solve (g = g_q - U e at the end, e = sum of alpha_k c_k):
+//   operator step: gamma_k = s_k^T s_k (from the previous launch's partials), the stopping
+//     test, c_k; w_k = A p_k = A q_k - AU c_k, and in the same pass over the rows of AU the
+//     partial sums of q^T w, q^T (AU c), s^T w, w^T w, (AU)^T w and (AU)^T s;
+//   update: p^T w = q^T w - q^T (AU c) + c^T G c (U^T w = (AU)^T q - G c), alpha, the next
+//     s^T s = gamma - 2 alpha s^T w + alpha^2 w^T w (for beta only; the next operator step
+//     sums the exact value), s -= alpha w, g_q += alpha q, q = s + beta q, and the totals
+//     (AU)^T s_k, (AU)^T w_k, from which the next operator step forms
+//     (AU)^T s_{k+1} = (AU)^T s_k - alpha (AU)^T w_k.
+// Per step the rows of AU are read once and those of U not at all, against twice (AU and
+// U) for the unsplit recurrence.  No kernel synchronises across blocks: each writes
+// per-block partial sums and the next launch reduces them; the scalar state and the small
+// vectors live in device memory, so chunks of steps run without host round trips.
+// T is the vector type: double for the plain form, float for the inner sweeps of the
+// mixed form (FP32 vectors and FP32 sums); the CG scalars, c, e, the tolerance and
+// G, G^{-1} stay FP64 in either case.
 #include "kernels.h"
 
 namespace rom {
 
 namespace {
 
-// Step kernels: blocks of 256 threads, each thread RPT rows of a 256 * RPT-row chunk
-// (rows b * chunk + t + 256 q), a block's chunks strided by the grid.  A thread issues
-// every load of its first chunk (the rows of U_j or A U_j and the vectors) before it
-// reduces the previous launch's partials, so the reduction hides behind the loads.  RPT
-// is as large as keeps those values and the NJT + 1 running sums in registers without
-// spilling; at 64 columns nothing is preloaded (RPT 0: one row per thread per pass,
-// U_j read as it is used).
 constexpr int CG_BS = 256;
-template <typename T, int NJT>
-struct CgRows {
-  static constexpr int value =
-      sizeof(T) == 8 ? (NJT <= 16 ? 4 : NJT <= 32 ? 2 : 0) : (NJT <= 32 ? 4 : 0);
-  // the narrow variant: half the rows per thread, more waves per SIMD (batches of
-  // members, where a block walks several chunks, can prefer it; the tuner decides)
-  static constexpr int narrow = value >= 2 ? value / 2 : value;
-};
 constexpr int CG_GRID = 256;
 constexpr int START_BS = 256;
+constexpr int OP_BS = 256;
 
-__global__ void k_cg_setup(CGState* cg, CgSetup su, int nb) {
+__global__ void k_cg_setup(CGState* cg, CGVec* cv, CgSetup su, int nb) {
   const int y = threadIdx.x;
-  if (y >= nb) return;
-  CGState* c = cg + y;
-  c->tol2 = su.tol2[y];
-  c->rscale = su.rscale[y];
-  c->maxit = su.maxit[y];
-  c->nj = su.nj[y];
-  c->its = 0;
-  c->done = su.active[y] ? 0 : 1;
-  c->flag = 0;
-  c->gamma[0] = 0.0;
-  c->gamma[1] = 0.0;
-  c->pw = 0.0;
-  c->kcur = 0;
+  if (y < nb) {
+    CGState* c = cg + y;
+    c->tol2 = su.tol2[y];
+    c->rscale = su.rscale[y];
+    c->maxit = su.maxit[y];
+    c->nj = su.nj[y];
+    c->its = 0;
+    c->kcur = 0;
+    c->done = su.active[y] ? 0 : 1;
+    c->flag = 0;
+    c->gamma[0] = 0.0;
+    c->gamma[1] = 0.0;
+    c->pw = 0.0;
+    c->alpha = 0.0;
+    c->beta = 0.0;
+    c->cGc = 0.0;
+  }
+  for (int k = threadIdx.x; k < nb * NJ_MAX; k += blockDim.x) cv[k / NJ_MAX].e[k % NJ_MAX] = 0.0;
 }
 
 // Row j = threadIdx.x < nj of Ginv = (U^T A U)^{-1} (symmetric, FP64) is loaded early
@@ -67,36 +70,34 @@ __device__ __forceinline__ void gram_row(const double* __restrict__ Ginv, int nj
     if (j < nj && c < nj) gr[PF ? c : 0] = Ginv[j + c * nj];
 }
 
-// ys[j] = scale * sum_c Ginv[j + c nj] t[c], evaluated in FP64 (the loop is unrolled to
-// NJT so that the row loads, where not prefetched, issue together) and stored as T in
-// shared memory.
-template <int NJT, bool PF, typename T, typename S>
-__device__ __forceinline__ void gram_apply(const double* __restrict__ Ginv,
-                                           const double (&gr)[PF ? NJT : 1], int nj, const S* t,
-                                           double scale, T* ys) {
-  if (threadIdx.x < nj) {
-    const int j = threadIdx.x;
-    double y = 0.0;
+// y[j] = scale * sum_c Ginv[j + c nj] t[c] for threads j < nj, in FP64 (the loop is
+// unrolled to NJT so that the row loads, where not prefetched, issue together).
+template <int NJT, bool PF, typename S>
+__device__ __forceinline__ double gram_row_apply(const double* __restrict__ Ginv,
+                                                 const double (&gr)[PF ? NJT : 1], int nj,
+                                                 const S* t, double scale) {
+  const int j = threadIdx.x;
+  double y = 0.0;
+  if (j < nj) {
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
       if (c < nj) y += (PF ? gr[PF ? c : 0] : Ginv[j + c * nj]) * (double)t[c];
-    ys[j] = (T)(scale * y);
   }
-  __syncthreads();
+  return scale * y;
 }
 
-// Rows per thread of the start kernel (it reads both U_j and A U_j): as for the steps, as
-// many as keep the loaded rows and the running sums in registers.
+// Rows per thread of the start kernel (it reads both U and AU): as many as keep the loaded
+// rows and the running sums in registers.
 template <typename T, int NJT>
 struct StartRows {
   static constexpr int value = sizeof(T) == 8 ? (NJT <= 8 ? 4 : NJT <= 16 ? 2 : 0)
                                               : (NJT <= 16 ? 4 : 0);
 };
 
-// Start: y0 = G^{-1} U^T r (U^T r in cg->t), g = U y0, s = r - AU y0; partials of
+// Start: y0 = G^{-1} U^T r (U^T r in cg->t), g = U y0, s = q = r - AU y0; partials of
 // (AU)^T s (values 0..nj-1) and s^T s (value NJT).  The right-hand side is FP64 and is
-// read as rscale * r (the mixed form solves for a unit-norm residual in FP32).  Rows as
-// in the step kernels: a thread loads its first chunk's rows before y0 is formed.
+// read as rscale * r (the mixed form solves for a unit-norm residual in FP32).  A thread
+// loads its first chunk's rows before y0 is formed.
 template <typename T, int NJT, int RPT = StartRows<T, NJT>::value>
 __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
                                                          const T* __restrict__ AW,
@@ -105,10 +106,9 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
                                                          int64_t gstride,
                                                          const double* __restrict__ r,
                                                          int64_t rstride, T* __restrict__ g,
-                                                         T* __restrict__ s, int64_t vstride,
-                                                         const CGState* cgs,
-                                                         T* __restrict__ part2,
-                                                         int64_t p2stride) {
+                                                         T* __restrict__ s, T* __restrict__ qv,
+                                                         int64_t vstride, const CGState* cgs,
+                                                         T* __restrict__ ps, int64_t psstride) {
   const int y = blockIdx.y;
   const CGState* cg = cgs + y;
   if (cg->done) return;
@@ -118,7 +118,8 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
   r += y * rstride;
   g += y * vstride;
   s += y * vstride;
-  part2 += y * p2stride;
+  qv += y * vstride;
+  ps += y * psstride;
   const int nj = cg->nj;
   const double rscale = cg->rscale;
   constexpr bool PRE = RPT > 0;
@@ -146,7 +147,9 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
   constexpr bool GPF = GramPf<NJT>::value;
   double gr[GPF ? NJT : 1];
   gram_row<NJT, GPF>(Ginv, nj, gr);
-  gram_apply<NJT, GPF>(Ginv, gr, nj, cg->t, rscale, ys);
+  const double y0 = gram_row_apply<NJT, GPF>(Ginv, gr, nj, cg->t, rscale);
+  if (threadIdx.x < nj) ys[threadIdx.x] = (T)y0;
+  __syncthreads();
   const T rs = (T)rscale;
   T acc[NJT + 1];
 #pragma unroll
@@ -172,6 +175,7 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
       if (in) {
         g[i] = gi;
         s[i] = si;
+        qv[i] = si;
       }
       acc[NJT] += si * si;   // 0 past the end (rv and the rows are 0 there)
 #pragma unroll
@@ -184,143 +188,309 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
     if (base - threadIdx.x >= n) break;
     load(base);
   }
-  write_partials_t<NJT + 1, START_BS>(acc, part2, blockIdx.x, gridDim.x);
+  write_partials_t<NJT + 1, START_BS>(acc, ps, blockIdx.x, gridDim.x);
 }
 
-// Reduce the step's partials (s^T s, (AU)^T s); record s^T s for the next step, count
-// the step, stop on convergence / maxit / non-finite values; else the new direction
-// p = s + beta p - U G^{-1} (AU)^T s.  iter = -1 for the direction after the start.
-template <typename T, int NJT, int RPT = CgRows<T, NJT>::value>
-__global__ __launch_bounds__(CG_BS) void k_dcg_dir(const T* __restrict__ W, int64_t wstride,
-                                                    int64_t ld, int64_t n,
-                                                    const double* __restrict__ Ginv,
-                                                    int64_t gstride, const T* __restrict__ s,
-                                                    T* __restrict__ p, int64_t vstride, int iter,
-                                                    CGState* cgs, const T* __restrict__ part2,
-                                                    int64_t p2stride, int P2) {
-  const int y = blockIdx.y;
+// NP consecutive values at index i (two-element vector loads for NP = 2: i even and the
+// array aligned, as the two-node walk requires).
+template <typename T>
+__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[1]) {
+  v[0] = p[i];
+}
+template <typename T>
+__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[2]) {
+  const typename Vec2<T>::type t = *reinterpret_cast<const typename Vec2<T>::type*>(p + i);
+  v[0] = t.x;
+  v[1] = t.y;
+}
+template <typename T>
+__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[1]) {
+  p[i] = v[0];
+}
+template <typename T>
+__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[2]) {
+  *reinterpret_cast<typename Vec2<T>::type*>(p + i) = typename Vec2<T>::type{v[0], v[1]};
+}
+
+// How the operator step sums its 2 NJT vector dot products.  Below 64 columns every thread
+// keeps running sums in registers over its z planes and the block reduces them once at the
+// end.  At 64 columns (128 sums) each plane's values are reduced over the wave at once and
+// accumulated in LDS by the wave's first lane (every lane of the block then walks every
+// plane, lanes past the plane with zero values, so the wave reductions see full waves).
+// The rows of AU stay in registers between their two uses where they fit.
+template <typename T, int NJT>
+struct OpMode {
+  static constexpr bool imm = NJT >= 64;
+  static constexpr bool keep = NJT * sizeof(T) <= 128;
+};
+
+// The operator step of member y = blockIdx.z over the z planes [blockIdx.y zc, + zc) of
+// its x-y positions (NP consecutive x-nodes per thread).  See the file comment.
+template <typename T, bool VAR, int NP, int NJT>
+__global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict__ diag,
+                                                   const T* __restrict__ q0,
+                                                   const T* __restrict__ s0, T* __restrict__ w0,
+                                                   int64_t vstride, const T* __restrict__ AW0,
+                                                   int64_t wstride, int64_t ld,
+                                                   const double* __restrict__ Ginv0,
+                                                   const double* __restrict__ Gm0,
+                                                   int64_t gstride, int zc, CGState* cgs,
+                                                   CGVec* cvs, const T* __restrict__ ps0, int Ps,
+                                                   int64_t psstride, const T* __restrict__ pu0,
+                                                   int Pu, int64_t pustride, T* __restrict__ po0,
+                                                   int64_t postride) {
+  const int y = blockIdx.z;
   CGState* cg = cgs + y;
   if (cg->done) return;
-  W += y * wstride;
-  Ginv += y * gstride;
-  s += y * vstride;
-  p += y * vstride;
-  part2 += y * p2stride;
+  CGVec* cv = cvs + y;
+  const T* __restrict__ q = q0 + y * vstride;
+  const T* __restrict__ s = s0 + y * vstride;
+  T* __restrict__ w = w0 + y * vstride;
+  const T* __restrict__ AW = AW0 + y * wstride;
+  const double* __restrict__ Ginv = Ginv0 + y * gstride;
   const int nj = cg->nj;
-  if (iter == ITER_STATE) iter = cg->kcur;
-  const bool first = iter < 0;
-  constexpr bool PRE = RPT > 0;
-  constexpr int R = PRE ? RPT : 1;
-  constexpr int64_t CH = (int64_t)CG_BS * R;
-  int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
-  T wr[R][PRE ? NJT : 1], sv[R], pv[R];
-  auto load = [&](int64_t b0) {
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int64_t i = b0 + (int64_t)q * CG_BS;
-      const bool in = i < n;
-      sv[q] = in ? s[i] : T(0);
-      pv[q] = (in && !first) ? p[i] : T(0);
-      if (PRE) {
-#pragma unroll
-        for (int c = 0; c < NJT; ++c)
-          wr[q][PRE ? c : 0] = (in && c < nj) ? W[i + c * ld] : T(0);
-      }
-    }
-  };
-  load(base);
+  const int k = cg->its;
+  const bool first = k == 0;
+  const double tol2 = cg->tol2;
+  const int maxit = cg->maxit;
+  const double alpha = cg->alpha, beta = cg->beta;
   constexpr bool GPF = GramPf<NJT>::value;
   double gr[GPF ? NJT : 1];
   gram_row<NJT, GPF>(Ginv, nj, gr);
-  // the state's scalars are read with the rows, ahead of the partial sums
-  const double g0 = cg->gamma[0], g1 = cg->gamma[1], tol2 = cg->tol2;
-  const int maxit = cg->maxit;
+
+  // gamma_k = s_k^T s_k and t = (AU)^T s_k: from the start's partials at the first step,
+  // else gamma from the update's partials and t by the recurrence
   __shared__ T tot[NJT + 1];
-  __shared__ T ys[NJ_MAX];
-  sum_partials_t<NJT + 1, CG_BS>(part2, P2, tot);
-  const double gnew = (double)tot[NJT];
-  const double gold = first ? 1.0 : ((iter & 1) ? g1 : g0);
-  const bool nonfinite = !isfinite(gnew);
-  const bool conv = gnew <= tol2;
-  const bool hit = !first && iter + 1 >= maxit;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    cg->gamma[(iter + 1) & 1] = gnew;
-    if (!first) cg->its = iter + 1;
-    if (nonfinite) {
-      cg->flag = 2;
-      cg->done = 1;
-    } else if (conv || hit) {
-      cg->done = 1;
+  __shared__ double tv[NJ_MAX];
+  double gam;
+  if (first) {
+    sum_partials_t<NJT + 1, OP_BS>(ps0 + y * psstride, Ps, tot);
+    gam = (double)tot[NJT];
+    if (threadIdx.x < nj) tv[threadIdx.x] = (double)tot[threadIdx.x];
+  } else {
+    sum_partials_t<1, OP_BS>(pu0 + y * pustride, Pu, tot);
+    gam = (double)tot[0];
+    if (threadIdx.x < nj) tv[threadIdx.x] = cv->ts[threadIdx.x] - alpha * cv->tw[threadIdx.x];
+  }
+  const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+  const bool nonfinite = !isfinite(gam);
+  const bool stop = nonfinite || gam <= tol2 || k >= maxit;
+  if (lead && threadIdx.x == 0) {
+    cg->gamma[k & 1] = gam;
+    cg->kcur = k;
+    if (nonfinite) cg->flag = 2;
+    if (stop) cg->done = 1;
+  }
+  if (stop) return;
+  __syncthreads();
+  // c_k = G^{-1} t + beta c_{k-1} (c_0 = G^{-1} t)
+  __shared__ T cs[NJ_MAX];
+  __shared__ double cd[NJ_MAX];
+  {
+    const int j = threadIdx.x;
+    double cj = gram_row_apply<NJT, GPF>(Ginv, gr, nj, tv, 1.0);
+    if (j < nj) {
+      if (!first) cj += beta * cv->c[(k - 1) & 1][j];
+      cs[j] = (T)cj;
+      cd[j] = cj;
+      if (lead) cv->c[k & 1][j] = cj;
     }
   }
-  if (nonfinite || conv || hit) return;
-  gram_apply<NJT, GPF>(Ginv, gr, nj, tot, 1.0, ys);
-  const T beta = first ? T(0) : (T)(gnew / gold);
-  for (;;) {
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int64_t i = base + (int64_t)q * CG_BS;
-      T pi = sv[q] + beta * pv[q];
-#pragma unroll
-      for (int c = 0; c < NJT; ++c)
-        if (c < nj) pi -= (PRE ? wr[q][PRE ? c : 0] : (i < n ? W[i + c * ld] : T(0))) * ys[c];
-      if (i < n) p[i] = pi;
+  __syncthreads();
+  if (lead && threadIdx.x < WAVE) {
+    // c^T G c for the update's p^T w (one wave; lanes past nj add zero)
+    const double* __restrict__ Gm = Gm0 + y * gstride;
+    const int j = threadIdx.x;
+    double v = 0.0;
+    if (j < nj) {
+      double gc = 0.0;
+      for (int c = 0; c < nj; ++c) gc += Gm[j + c * nj] * cd[c];
+      v = cd[j] * gc;
     }
-    base += (int64_t)gridDim.x * CH;
-    if (base - threadIdx.x >= n) break;
-    load(base);
+    v = wave_sum(v);
+    if (j == 0) cg->cGc = v;
+  }
+
+  constexpr bool IMM = OpMode<T, NJT>::imm;
+  constexpr bool KEEP = OpMode<T, NJT>::keep;
+  constexpr int RV = 4 + (IMM ? 0 : 2 * NJT);
+  T acc[RV];
+#pragma unroll
+  for (int r = 0; r < RV; ++r) acc[r] = T(0);
+  __shared__ T imm[IMM ? (OP_BS / WAVE) * 2 * NJT : 1];
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  if (IMM) {
+    for (int r = threadIdx.x; r < (OP_BS / WAVE) * 2 * NJT; r += OP_BS) imm[r] = T(0);
+    __syncthreads();
+  }
+  // vector sum r: in registers, or reduced over the wave and added to the wave's LDS slot
+  auto vadd = [&](int r, T v) {
+    if (IMM) {
+      v = wave_sum(v);
+      if (lane == 0) imm[wid * 2 * NJT + r] += v;
+    } else {
+      acc[4 + r] += v;
+    }
+  };
+  const int npos = NP == 2 ? (S.nx / 2) * S.ny : S.nx * S.ny;
+  const int qpos = blockIdx.x * OP_BS + threadIdx.x;
+  const bool act = qpos < npos;
+  const int z0 = blockIdx.y * zc;
+  const int z1 = min(z0 + zc, S.nz);
+  auto body = [&](int64_t i, const T (&av0)[NP], const T (&xq0)[NP]) {
+    T av[NP], xq[NP], sv[NP], au[NP], wv[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      av[p] = act ? av0[p] : T(0);
+      xq[p] = act ? xq0[p] : T(0);
+      au[p] = T(0);
+    }
+    if (act) ldn(s, i, sv);
+    else
+#pragma unroll
+      for (int p = 0; p < NP; ++p) sv[p] = T(0);
+    T kept[KEEP ? NJT : 1][NP];
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) {
+        T a[NP];
+        if (act) ldn(AW + c * ld, i, a);
+        else
+#pragma unroll
+          for (int p = 0; p < NP; ++p) a[p] = T(0);
+        T t = T(0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          if (KEEP) kept[KEEP ? c : 0][p] = a[p];
+          au[p] += a[p] * cs[c];
+          t += a[p] * sv[p];
+        }
+        vadd(NJT + c, t);
+      }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      wv[p] = av[p] - au[p];
+      acc[0] += xq[p] * wv[p];
+      acc[1] += xq[p] * au[p];
+      acc[2] += sv[p] * wv[p];
+      acc[3] += wv[p] * wv[p];
+    }
+    if (act) stn(w, i, wv);
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) {
+        T a[NP];
+        if (KEEP) {
+#pragma unroll
+          for (int p = 0; p < NP; ++p) a[p] = kept[KEEP ? c : 0][p];
+        } else if (act) {
+          ldn(AW + c * ld, i, a);
+        } else {
+#pragma unroll
+          for (int p = 0; p < NP; ++p) a[p] = T(0);
+        }
+        T t = T(0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) t += a[p] * wv[p];
+        vadd(c, t);
+      }
+  };
+  // with wave reductions every lane walks (a lane past the plane reads position 0)
+  if (z0 < z1 && (act || IMM)) {
+    const int qq = act ? qpos : 0;
+    if constexpr (NP == 2)
+      stencil_walk2t<T, VAR>(S, diag, q, qq, z0, z1, [&](int64_t i, T v0, T v1, T x0, T x1) {
+        const T av[2] = {v0, v1};
+        const T xq[2] = {x0, x1};
+        body(i, av, xq);
+      });
+    else
+      stencil_walk1t<T, VAR>(S, diag, q, qq, z0, z1, [&](int64_t i, T v0, T x0) {
+        const T av[1] = {v0};
+        const T xq[1] = {x0};
+        body(i, av, xq);
+      });
+  }
+  T* __restrict__ po = po0 + y * postride;
+  const int P1 = gridDim.x * gridDim.y;
+  const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+  if (!IMM) {
+    write_partials_t<RV, OP_BS>(acc, po, bid, P1);
+  } else {
+    T a4[4] = {acc[0], acc[1], acc[2], acc[3]};
+    write_partials_t<4, OP_BS>(a4, po, bid, P1);
+    __syncthreads();
+    for (int r = threadIdx.x; r < 2 * NJT; r += OP_BS) {
+      T t = T(0);
+#pragma unroll
+      for (int v = 0; v < OP_BS / WAVE; ++v) t += imm[v * 2 * NJT + r];
+      po[(size_t)(4 + r) * P1 + bid] = t;
+    }
   }
 }
 
-// alpha = s^T s / p^T A p; g += alpha p; s -= alpha w; partials of (AU)^T s and s^T s.
-template <typename T, int NJT, int RPT = CgRows<T, NJT>::value>
-__global__ __launch_bounds__(CG_BS) void k_dcg_update(const T* __restrict__ AW, int64_t wstride,
-                                                       int64_t ld, int64_t n,
-                                                       const T* __restrict__ p,
-                                                       const T* __restrict__ w,
-                                                       T* __restrict__ g, T* __restrict__ s,
-                                                       int64_t vstride, int iter, CGState* cgs,
-                                                       const T* __restrict__ part1, int P1,
-                                                       int64_t p1stride, T* __restrict__ part2,
-                                                       int64_t p2stride) {
+// Rows per thread of the update (five vectors, no U rows): 4, or 2 in the narrow variant.
+template <int NARROW>
+struct UpdRows {
+  static constexpr int value = NARROW ? 2 : 4;
+};
+
+// The update of member y = blockIdx.y (see the file comment).  Block b also reduces the
+// operator step's vector totals r = b, b + P, ... < 2 nj into cv (tw first, then ts).
+template <typename T, int RPT>
+__global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const T* __restrict__ w0,
+                                                       T* __restrict__ g0, T* __restrict__ s0,
+                                                       int64_t vstride, int64_t n, int njt,
+                                                       CGState* cgs, CGVec* cvs,
+                                                       const T* __restrict__ po0, int P1,
+                                                       int64_t postride, T* __restrict__ pu0,
+                                                       int64_t pustride) {
   const int y = blockIdx.y;
   CGState* cg = cgs + y;
   if (cg->done) return;
-  AW += y * wstride;
-  p += y * vstride;
-  w += y * vstride;
-  g += y * vstride;
-  s += y * vstride;
-  part1 += y * p1stride;
-  part2 += y * p2stride;
+  CGVec* cv = cvs + y;
+  T* __restrict__ q = q0 + y * vstride;
+  const T* __restrict__ w = w0 + y * vstride;
+  T* __restrict__ g = g0 + y * vstride;
+  T* __restrict__ s = s0 + y * vstride;
+  const T* __restrict__ po = po0 + y * postride;
   const int nj = cg->nj;
-  if (iter == ITER_STATE) iter = cg->its;
-  constexpr bool PRE = RPT > 0;
-  constexpr int R = PRE ? RPT : 1;
+  const int k = cg->kcur;
+  const double gam = cg->gamma[k & 1], cGc = cg->cGc;
+  constexpr int R = RPT;
   constexpr int64_t CH = (int64_t)CG_BS * R;
   int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
-  T a[R][PRE ? NJT : 1], pv[R], wv[R], gv[R], sv[R];
+  T qv[R], wv[R], gv[R], sv[R];
   auto load = [&](int64_t b0) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int64_t i = b0 + (int64_t)q * CG_BS;
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = b0 + (int64_t)u * CG_BS;
       const bool in = i < n;
-      pv[q] = in ? p[i] : T(0);
-      wv[q] = in ? w[i] : T(0);
-      gv[q] = in ? g[i] : T(0);
-      sv[q] = in ? s[i] : T(0);
-      if (PRE) {
-#pragma unroll
-        for (int c = 0; c < NJT; ++c)
-          a[q][PRE ? c : 0] = (in && c < nj) ? AW[i + c * ld] : T(0);
-      }
+      qv[u] = in ? q[i] : T(0);
+      wv[u] = in ? w[i] : T(0);
+      gv[u] = in ? g[i] : T(0);
+      sv[u] = in ? s[i] : T(0);
     }
   };
-  const double g0 = cg->gamma[0], g1 = cg->gamma[1];   // read with the rows, used after the sum
   load(base);
-  __shared__ T pwt[1];
-  sum_partials_t<1, CG_BS>(part1, P1, pwt);
-  const double pw = (double)pwt[0];
+  __shared__ T tot[4];
+  sum_partials_t<4, CG_BS>(po, P1, tot);
+  // the vector totals this block owns, one wave reduction each
+  {
+    const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+    for (int v = blockIdx.x + gridDim.x * wid; v < 2 * nj; v += gridDim.x * (CG_BS / WAVE)) {
+      const int r = v < nj ? 4 + v : 4 + njt + (v - nj);
+      T a = T(0);
+      for (int b = lane; b < P1; b += WAVE) a += po[(size_t)r * P1 + b];
+      a = wave_sum(a);
+      if (lane == 0) {
+        if (v < nj) cv->tw[v] = (double)a;
+        else cv->ts[v - nj] = (double)a;
+      }
+    }
+  }
+  const double qw = tot[0], qau = tot[1], sw = tot[2], ww = tot[3];
+  const double pw = qw - qau + cGc;
   if (!(pw > 0.0) || !isfinite(pw)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       cg->flag = isfinite(pw) ? 1 : 2;
@@ -328,34 +498,64 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(const T* __restrict__ AW, 
     }
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    cg->pw = pw;
-    cg->kcur = iter;
+  const double al = gam / pw;
+  double gnext = gam - 2.0 * al * sw + al * al * ww;
+  if (!(gnext > 0.0)) gnext = 0.0;
+  const double be = gnext / gam;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < nj) cv->e[threadIdx.x] += al * cv->c[k & 1][threadIdx.x];
+    if (threadIdx.x == 0) {
+      cg->pw = pw;
+      cg->alpha = al;
+      cg->beta = be;
+      cg->gamma[(k + 1) & 1] = gnext;
+      cg->its = k + 1;
+    }
   }
-  const T alpha = (T)(((iter & 1) ? g1 : g0) / pw);
-  T acc[NJT + 1];
-#pragma unroll
-  for (int c = 0; c <= NJT; ++c) acc[c] = T(0);
+  const T a = (T)al, b = (T)be;
+  T acc[1] = {T(0)};
   for (;;) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int64_t i = base + (int64_t)q * CG_BS;
-      const T si = sv[q] - alpha * wv[q];   // 0 past the end (sv = wv = 0 there)
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = base + (int64_t)u * CG_BS;
+      const T si = sv[u] - a * wv[u];   // 0 past the end (sv = wv = 0 there)
       if (i < n) {
-        g[i] = gv[q] + alpha * pv[q];
         s[i] = si;
+        g[i] = gv[u] + a * qv[u];
+        q[i] = si + b * qv[u];
       }
-      acc[NJT] += si * si;
-#pragma unroll
-      for (int c = 0; c < NJT; ++c)
-        if (c < nj)
-          acc[c] += (PRE ? a[q][PRE ? c : 0] : (i < n ? AW[i + c * ld] : T(0))) * si;
+      acc[0] += si * si;
     }
     base += (int64_t)gridDim.x * CH;
     if (base - threadIdx.x >= n) break;
     load(base);
   }
-  write_partials_t<NJT + 1, CG_BS>(acc, part2, blockIdx.x, gridDim.x);
+  write_partials_t<1, CG_BS>(acc, pu0 + y * pustride, blockIdx.x, gridDim.x);
+}
+
+// g -= U e (member y = blockIdx.y): the U part of the split correction.
+template <typename T, int NJT>
+__global__ __launch_bounds__(CG_BS) void k_dcg_finish(const T* __restrict__ W0, int64_t wstride,
+                                                       int64_t ld, int64_t n,
+                                                       T* __restrict__ g0, int64_t vstride,
+                                                       const CGState* cgs, const CGVec* cvs) {
+  const int y = blockIdx.y;
+  const CGState* cg = cgs + y;
+  const int nj = cg->nj;
+  if (nj == 0) return;
+  __shared__ T es[NJ_MAX];
+  if (threadIdx.x < nj) es[threadIdx.x] = (T)cvs[y].e[threadIdx.x];
+  __syncthreads();
+  const T* __restrict__ W = W0 + y * wstride;
+  T* __restrict__ g = g0 + y * vstride;
+  for (int64_t i = (int64_t)blockIdx.x * CG_BS + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * CG_BS) {
+    T v = g[i];
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) v -= W[i + c * ld] * es[c];
+    g[i] = v;
+  }
 }
 
 }  // namespace
@@ -367,20 +567,20 @@ int dcg_blocks(int64_t n) {
   return b < CG_GRID ? (b < 1 ? 1 : b) : CG_GRID;
 }
 
-void launch_cg_setup(CGState* cg, const CgSetup& su, int nb, hipStream_t st) {
+void launch_cg_setup(CGState* cg, CGVec* cv, const CgSetup& su, int nb, hipStream_t st) {
   if (nb < 1 || nb > G_MAX) throw Error(ROM_EINVAL, "cg_setup: batch size out of range");
-  ROM_LAUNCH(k_cg_setup, dim3(1), dim3(64), 0, st, cg, su, nb);
+  ROM_LAUNCH(k_cg_setup, dim3(1), dim3(256), 0, st, cg, cv, su, nb);
   ROM_CHECK_LAUNCH();
 }
 
 template <typename T>
 void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax,
                       const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
-                      T* s, int64_t vstride, const CGState* cg, T* part2, int64_t p2stride, int nb,
-                      int P, hipStream_t st) {
+                      T* s, T* q, int64_t vstride, const CGState* cg, T* ps, int64_t psstride,
+                      int nb, int P, hipStream_t st) {
   const dim3 grid(P, nb);
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, wstride, ld, n, Ginv, gstride, r, rstride, g, s, vstride, cg, part2, p2stride); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, wstride, ld, n, Ginv, gstride, r, rstride, g, s, q, vstride, cg, ps, psstride); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -388,45 +588,56 @@ void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int6
 }
 
 template <typename T>
-void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
-                    const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
-                    int iter, CGState* cg, const T* part2, int64_t p2stride, int nb, int P,
-                    hipStream_t st, int P2, int narrow) {
-  const dim3 grid(P, nb);
-  if (P2 <= 0) P2 = P;
-  switch (njt_of(njmax)) {
-#define C(J)                                                                                    \
-  case J:                                                                                       \
-    if (narrow)                                                                                 \
-      ROM_LAUNCH((k_dcg_dir<T, J, CgRows<T, J>::narrow>), grid, dim3(CG_BS), 0, st, W, wstride,  \
-                 ld, n, Ginv, gstride, s, p, vstride, iter, cg, part2, p2stride, P2);           \
-    else                                                                                        \
-      ROM_LAUNCH((k_dcg_dir<T, J>), grid, dim3(CG_BS), 0, st, W, wstride, ld, n, Ginv, gstride,  \
-                 s, p, vstride, iter, cg, part2, p2stride, P2);                                 \
-    break;
-    C(8) C(16) C(32) C(64)
-#undef C
+void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, const T* q,
+                   const T* s, T* w, int64_t vstride, const T* AW, int64_t wstride, int64_t ld,
+                   int njmax, const double* Ginv, const double* Gm, int64_t gstride, CGState* cg,
+                   CGVec* cv, const T* ps, int Ps, int64_t psstride, const T* pu, int Pu,
+                   int64_t pustride, T* po, int64_t postride, int nb, hipStream_t st) {
+  const dim3 grid(sh.grid.x, sh.grid.y, nb);
+#define OPL(VAR, NP, J)                                                                       \
+  ROM_LAUNCH((k_dcg_op<T, VAR, NP, J>), grid, dim3(OP_BS), 0, st, S, diag, q, s, w, vstride,  \
+             AW, wstride, ld, Ginv, Gm, gstride, sh.zc, cg, cv, ps, Ps, psstride, pu, Pu,      \
+             pustride, po, postride)
+#define OPJ(VAR, NP)                      \
+  switch (njt_of(njmax)) {                \
+    case 8: OPL(VAR, NP, 8); break;       \
+    case 16: OPL(VAR, NP, 16); break;     \
+    case 32: OPL(VAR, NP, 32); break;     \
+    default: OPL(VAR, NP, 64); break;     \
   }
+  if (sh.pairs) {
+    if (S.var) { OPJ(true, 2) } else { OPJ(false, 2) }
+  } else {
+    if (S.var) { OPJ(true, 1) } else { OPJ(false, 1) }
+  }
+#undef OPJ
+#undef OPL
   ROM_CHECK_LAUNCH();
 }
 
 template <typename T>
-void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax, const T* p,
-                       const T* w, T* g, T* s, int64_t vstride, int iter, CGState* cg,
-                       const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
-                       int nb, int P, hipStream_t st, int narrow) {
+void launch_dcg_update(T* q, const T* w, T* g, T* s, int64_t vstride, int64_t n, int njmax,
+                       CGState* cg, CGVec* cv, const T* po, int P1, int64_t postride, T* pu,
+                       int64_t pustride, int nb, int P, hipStream_t st, int narrow) {
   const dim3 grid(P, nb);
+  const int njt = njt_of(njmax);
+  if (narrow)
+    ROM_LAUNCH((k_dcg_update<T, UpdRows<1>::value>), grid, dim3(CG_BS), 0, st, q, w, g, s, vstride,
+               n, njt, cg, cv, po, P1, postride, pu, pustride);
+  else
+    ROM_LAUNCH((k_dcg_update<T, UpdRows<0>::value>), grid, dim3(CG_BS), 0, st, q, w, g, s, vstride,
+               n, njt, cg, cv, po, P1, postride, pu, pustride);
+  ROM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_dcg_finish(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax, T* g,
+                       int64_t vstride, const CGState* cg, const CGVec* cv, int nb,
+                       hipStream_t st) {
+  if (njmax <= 0) return;
+  const dim3 grid(dcg_blocks(n), nb);
   switch (njt_of(njmax)) {
-#define C(J)                                                                                     \
-  case J:                                                                                        \
-    if (narrow)                                                                                  \
-      ROM_LAUNCH((k_dcg_update<T, J, CgRows<T, J>::narrow>), grid, dim3(CG_BS), 0, st, AW,        \
-                 wstride, ld, n, p, w, g, s, vstride, iter, cg, part1, P1, p1stride, part2,      \
-                 p2stride);                                                                      \
-    else                                                                                         \
-      ROM_LAUNCH((k_dcg_update<T, J>), grid, dim3(CG_BS), 0, st, AW, wstride, ld, n, p, w, g, s,  \
-                 vstride, iter, cg, part1, P1, p1stride, part2, p2stride);                       \
-    break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_finish<T, J>), grid, dim3(CG_BS), 0, st, W, wstride, ld, n, g, vstride, cg, cv); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -435,15 +646,19 @@ void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int 
 
 #define INSTANTIATE(T)                                                                          \
   template void launch_dcg_start<T>(const T*, const T*, int64_t, int64_t, int64_t, int,          \
-                                    const double*, int64_t, const double*, int64_t, T*, T*,      \
+                                    const double*, int64_t, const double*, int64_t, T*, T*, T*,  \
                                     int64_t, const CGState*, T*, int64_t, int, int,              \
                                     hipStream_t);                                                \
-  template void launch_dcg_dir<T>(const T*, int64_t, int64_t, int64_t, int, const double*,       \
-                                  int64_t, const T*, T*, int64_t, int, CGState*, const T*,       \
-                                  int64_t, int, int, hipStream_t, int, int);                     \
-  template void launch_dcg_update<T>(const T*, int64_t, int64_t, int64_t, int, const T*,         \
-                                     const T*, T*, T*, int64_t, int, CGState*, const T*, int,    \
-                                     int64_t, T*, int64_t, int, int, hipStream_t, int);
+  template void launch_dcg_op<T>(const Stencil&, const StencilShape&, const T*, const T*,        \
+                                 const T*, T*, int64_t, const T*, int64_t, int64_t, int,         \
+                                 const double*, const double*, int64_t, CGState*, CGVec*,        \
+                                 const T*, int, int64_t, const T*, int, int64_t, T*, int64_t,    \
+                                 int, hipStream_t);                                              \
+  template void launch_dcg_update<T>(T*, const T*, T*, T*, int64_t, int64_t, int, CGState*,      \
+                                     CGVec*, const T*, int, int64_t, T*, int64_t, int, int,      \
+                                     hipStream_t, int);                                          \
+  template void launch_dcg_finish<T>(const T*, int64_t, int64_t, int64_t, int, T*, int64_t,      \
+                                     const CGState*, const CGVec*, int, hipStream_t);
 INSTANTIATE(double)
 INSTANTIATE(float)
 #undef INSTANTIATE

@@ -5,26 +5,35 @@
 
 namespace rom {
 
-// CG scalar state shared by the deflated-CG kernels (device memory).
-// Scalar state of one deflated-CG solve (one per member of a batch of right-hand sides).
+// Scalar state of one deflated-CG solve (one per member of a batch of right-hand sides;
+// device memory, read back by the host at its convergence polls).
 struct CGState {
-  double gamma[2];     // s^T s, double-buffered by step parity
+  double gamma[2];     // s^T s by step parity (exact from the operator step; the update
+                       // writes its recurrence estimate of the next one first)
   double pw;           // p^T A p of the latest direction
   double tol2;         // (tol * ||b||)^2
   double rscale;       // the right-hand side is read as rscale * r
+  double alpha, beta;  // of the latest update
+  double cGc;          // c^T (U^T A U) c of the latest direction (p = q - U c)
   double t[NJ_MAX];    // U_j^T r (unscaled) for the start
   int nj;              // columns of U_j
-  int its;             // iterations done
+  int its;             // updates done: written by the update, read by the operator step
   int maxit;
   int done;            // 1: stop (converged, maxit, breakdown, or inactive member)
   int flag;            // 0 ok, 1 non-positive curvature, 2 non-finite
-  int kcur;            // step index of the latest update (read by the direction kernel)
+  int kcur;            // index of the latest operator step: written by it, read by the
+                       // update (no kernel reads a field that another block of the same
+                       // launch may already have rewritten)
 };
 
-// Step index argument meaning "take it from the CG state": the update uses its, the
-// direction kernel the index the update recorded.  Launches with it can be captured
-// once and replayed.
-constexpr int ITER_STATE = -2;
+// Per-member vectors of the deflated-CG recurrences (device memory beside the state).
+// The direction is kept split as p_k = q_k - U c_k, and the correction as g = g_q - U e.
+struct CGVec {
+  double ts[NJ_MAX];     // (A U)^T s_k of the latest operator step
+  double tw[NJ_MAX];     // (A U)^T w_k of the latest operator step
+  double c[2][NJ_MAX];   // c_k by step parity
+  double e[NJ_MAX];      // sum over the updates of alpha_k c_k
+};
 
 // Most right-hand sides solved together (members of one batch).
 constexpr int G_MAX = 16;
@@ -46,12 +55,12 @@ struct StencilShape {
   int pairs = 0;   // CG operator step with two x-nodes per thread (grid.x counts pairs)
 };
 StencilShape stencil_shape(const Stencil& S, int target_blocks);
-// Launch shape of the CG operator step (launch_dcg_apply) for these buffers: the two-node
+// Launch shape of the CG operator step (launch_dcg_op) for these buffers: the two-node
 // walk when nx is even and every array is aligned for it (then grid.x and blocks count
 // node pairs: the partials per member are `blocks`, at stride `blocks`).
 template <typename T>
 StencilShape cg_apply_shape(const Stencil& S, int target_blocks, const T* diag, const T* p,
-                            const T* w, int64_t vstride);
+                            const T* w, int64_t vstride, const T* AW = nullptr);
 
 // Absorption bumps of one parameter point, passed by value as a kernel argument.
 struct Bumps {
@@ -307,42 +316,52 @@ void launch_dot2_scale(int64_t n, const double* x, const double* a, const double
 
 // ---- deflated CG --------------------------------------------------------------------
 // T = double (plain form) or float (inner sweeps of the mixed form).  A batch of nb
-// members (blockIdx.y) runs together; member y uses cg[y] (its nj, rscale, tol2, maxit),
-// W + y*wstride, AW + y*wstride and Ginv + y*gstride (strides 0: one recycle space for
-// every member), the FP64 right-hand side r + y*rstride (read as rscale * r) and its
-// CG vectors at + y*vstride.  W, AW: n x nj contiguous (ld); Ginv: nj x nj FP64 inverse
-// of W^T A W.  P: blocks per member of the start, update and direction kernels
-// (1 <= P <= dcg_blocks(n)); each thread covers n / (P * block) rows.  Partials (values
-// of T): part1 >= stencil_shape(S, 1024).blocks per member, part2 >= (NJ_MAX + 1) * P
-// per member, at strides p1stride, p2stride.  iter: 0-based step index shared by the
-// batch (-1 for the direction after the start; ITER_STATE: from the state, see above).
-// P2 of the direction kernel: the partial rows it reduces, the grid of the launch before
-// it (0: P; the start may run on a wider grid than the steps).  narrow: the variant with
-// half the rows per thread (more waves per SIMD).
-// cg[y].t holds U_j^T r before the start.  Inactive members (done set at setup) return
-// at once from every kernel.
+// members runs together; member y uses cg[y] / cv[y] (its nj, rscale, tol2, maxit),
+// W + y*wstride, AW + y*wstride, Ginv / Gm + y*gstride (strides 0: one recycle space for
+// every member), the FP64 right-hand side r + y*rstride (read as rscale * r) and its CG
+// vectors at + y*vstride.  W, AW: n x nj column-major (ld); Ginv, Gm: nj x nj FP64
+// (W^T A W)^{-1} and W^T A W.  Inactive members (done set at setup) return at once from
+// every kernel.
+//
+// A solve is: setup; start (g = U y0, s = q = r - AU y0, y0 = Ginv U^T r with U^T r in
+// cg[y].t); then per step the operator kernel (the start's or the previous update's
+// partials give gamma = s^T s, the stopping test, and c; w = A q - AU c with every dot
+// product the update needs) and the update kernel (alpha, beta, s, g, q); finally
+// g -= U e.  The step kernels take the step index from the state, so chunks of steps
+// can be captured once and replayed.
 int dcg_blocks(int64_t n);
 // the width class (8, 16, 32 or 64 columns) the kernels are compiled for
 int njt_of(int nj);
-void launch_cg_setup(CGState* cg, const CgSetup& su, int nb, hipStream_t st);
+// values per block of the operator step's partials for width class njt
+inline int dcg_op_values(int njt) { return 4 + 2 * njt; }
+void launch_cg_setup(CGState* cg, CGVec* cv, const CgSetup& su, int nb, hipStream_t st);
+// P blocks per member; partials ps (NJ_MAX + 1 values per block, transposed) at stride
+// psstride per member.
 template <typename T>
 void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax,
                       const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
-                      T* s, int64_t vstride, const CGState* cg, T* part2, int64_t p2stride, int nb,
-                      int P, hipStream_t st);
+                      T* s, T* q, int64_t vstride, const CGState* cg, T* ps, int64_t psstride,
+                      int nb, int P, hipStream_t st);
+// The operator step on the launch shape sh (cg_apply_shape; sh.blocks partial rows of
+// dcg_op_values(njt_of(njmax)) values per member at stride postride).  Ps: blocks of the
+// start (its partials are read at the first step), Pu: blocks of the update kernel.
 template <typename T>
-void launch_dcg_dir(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax,
-                    const double* Ginv, int64_t gstride, const T* s, T* p, int64_t vstride,
-                    int iter, CGState* cg, const T* part2, int64_t p2stride, int nb, int P,
-                    hipStream_t st, int P2 = 0, int narrow = 0);
+void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, const T* q,
+                   const T* s, T* w, int64_t vstride, const T* AW, int64_t wstride, int64_t ld,
+                   int njmax, const double* Ginv, const double* Gm, int64_t gstride, CGState* cg,
+                   CGVec* cv, const T* ps, int Ps, int64_t psstride, const T* pu, int Pu,
+                   int64_t pustride, T* po, int64_t postride, int nb, hipStream_t st);
+// The update on P blocks per member (1 <= P <= dcg_blocks(n)); P1 = the operator step's
+// blocks.  narrow: half the rows per thread.
 template <typename T>
-void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
-                      int64_t vstride, CGState* cg, T* part1, int nb, hipStream_t st);
+void launch_dcg_update(T* q, const T* w, T* g, T* s, int64_t vstride, int64_t n, int njmax,
+                       CGState* cg, CGVec* cv, const T* po, int P1, int64_t postride, T* pu,
+                       int64_t pustride, int nb, int P, hipStream_t st, int narrow = 0);
+// g -= U e for every member (the U part of the split correction).
 template <typename T>
-void launch_dcg_update(const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax, const T* p,
-                       const T* w, T* g, T* s, int64_t vstride, int iter, CGState* cg,
-                       const T* part1, int P1, int64_t p1stride, T* part2, int64_t p2stride,
-                       int nb, int P, hipStream_t st, int narrow = 0);
+void launch_dcg_finish(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax, T* g,
+                       int64_t vstride, const CGState* cg, const CGVec* cv, int nb,
+                       hipStream_t st);
 
 // Error reporting shared by the entry points of every subsystem (sets rom_last_error).
 rom_status report(const Error& e);

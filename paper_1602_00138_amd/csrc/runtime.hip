@@ -11,6 +11,7 @@
 #include <string>
 #include <thread>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <type_traits>
@@ -80,6 +81,7 @@ struct Ctrl {
   int status[4];
   int pad[4];
   double rn[G_MAX];        // squared residual norms of a batch
+  double gs[3 * G_MAX];    // initial-guess step per member: d^T r, d^T A d, ||r1||^2
   CGState cg[G_MAX];
 };
 
@@ -292,6 +294,7 @@ class Sequencer {
       for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
     }
     if (cap_st_) (void)hipStreamDestroy(cap_st_);
+    if (h_) (void)hipHostFree(h_);
   }
 
   size_t layout(void* base) {
@@ -314,7 +317,7 @@ class Sequencer {
     vAB_ = a.take<double>(3 * ld_);   // u, A_* u, A_i u of an append
     fa_ = a.take<double>(ld_);
     fw_ = a.take<double>(ld_);
-    xg_ = a.take<double>(ld_);
+    xg_ = a.take<double>(ld_ * G);
     blk_ = G > 1 ? a.take<double>(ld_ * 2 * G) : nullptr;
     bblk_ = G > 1 ? a.take<double>((size_t)(cap_ + 8) * 2 * G) : nullptr;
     diag_i_ = a.take<double>(ld_);
@@ -337,10 +340,15 @@ class Sequencer {
     const StencilShape sh = stencil_shape(S_, 1024);
     const StencilShape sh5 = stencil_shape(S_, 512);
     red_part_ = a.take<double>(std::max<size_t>(2 * 1024, (size_t)std::max(sh5.blocks, 256) * G));
-    p1s_ = std::max(sh.blocks, 1);
-    part1_ = a.take<double>((size_t)p1s_ * G);
+    // CG partials per member: the operator step's (dcg_op_values(NJ_MAX) rows of at most
+    // sh.blocks), the start's (NJ_MAX + 1 rows) and the update's (one row)
+    pos_ = (int64_t)dcg_op_values(NJ_MAX) * std::max(sh.blocks, 1);
+    part_o_ = a.take<double>((size_t)pos_ * G);
     p2s_ = (int64_t)(NJ_MAX + 1) * dcg_blocks(n_);
     part2_ = a.take<double>((size_t)p2s_ * G);
+    pus_ = dcg_blocks(n_);
+    part_u_ = a.take<double>((size_t)pus_ * G);
+    cgv_ = a.take<CGVec>(G_MAX);
     size_t gt = std::max(gemvt_partials_max(n_, std::max(cap_ + 1, NJ_MAX), 3),
                          gemvt_partials_max(cap_, cap_, 2));
     gt = std::max(gt, proj_partials_max(std::max(cap_, NJ_MAX), G_MAX, n_));
@@ -353,7 +361,7 @@ class Sequencer {
     bvals_ = a.take<double>(4 * (cap_ + 8));   // [t | h | h_i | b row] of an append
     fcw_ = a.take<double>(2 * (cap_ + 8));     // [w | y]
     ftmp_ = a.take<double>(2 * (cap_ + 8));
-    GW_ = a.take<double>(NJ_MAX * NJ_MAX);
+    GWs_ = a.take<double>((size_t)NJ_MAX * NJ_MAX * G);
     if (n_rec_ > 0) {
       rec_ = a.take<double>(ld_ * REC_MAX);
       rAW_ = a.take<double>(ld_ * REC_MAX);
@@ -383,20 +391,16 @@ class Sequencer {
     return a.off + ALIGN;
   }
 
-  rom_status run(const rom_mu* params, const int64_t* src_idx, const double* src_scale,
-                 const int64_t* det_idx, const double* det_scale, const double* U0,
-                 double* X_out, rom_record* records, rom_stats* stats, hipStream_t st,
-                 rom_basis** out_basis) {
-    const auto t0 = std::chrono::steady_clock::now();
+  // Streaming form of Algorithm 2: begin() takes the right-hand sides and U_0, each
+  // point() runs one parameter point, finish() reports.  run() is the three in a row.
+  void begin(const int64_t* src_idx, const double* src_scale, const int64_t* det_idx,
+             const double* det_scale, const double* U0, hipStream_t st) {
+    t0_ = std::chrono::steady_clock::now();
     st_ = st;
-    Timer timer(o_.timing);
-    tm_ = &timer;
+    timer_.reset(new Timer(o_.timing));
+    tm_ = timer_.get();
     ROM_HIP(hipHostMalloc((void**)&h_, sizeof(Ctrl), hipHostMallocDefault));
-    struct Free {
-      Ctrl* h;
-      ~Free() { (void)hipHostFree(h); }
-    } guard{h_};
-
+    U0_ = U0;
     idx_.assign(src_idx, src_idx + n_src_);
     idx_.insert(idx_.end(), det_idx, det_idx + n_det_);
     scale_.assign(src_scale, src_scale + n_src_);
@@ -422,23 +426,48 @@ class Sequencer {
     m_ = 0;
     extra_.assign(n_rhs_, {});
     next_slot_ = n_rhs_;
+    next_point_ = 0;
     status_ = ROM_OK;
     recs_.clear();
     recs_.reserve((size_t)K_ * n_rhs_);
     total_its_ = 0;
-    n_solved_ = n_kept_ = n_drop_trunc_ = n_drop_cap_ = n_nonconv_ = 0;
+    n_solved_ = n_kept_ = n_drop_trunc_ = n_drop_cap_ = n_nonconv_ = n_uj_capped_ = 0;
+  }
 
-    try {
-      sweep_points(params, U0, X_out);
-    } catch (...) {
-      // the records of the right-hand sides completed before the error
-      if (records) {
-        std::memset(records, 0, (size_t)K_ * n_rhs_ * sizeof(rom_record));
-        std::memcpy(records, recs_.data(), recs_.size() * sizeof(rom_record));
-      }
-      throw;
-    }
+  // The next parameter point of the sequence; Xi (device, N x n_rhs, ld N) receives its
+  // solutions when not NULL, records (host, n_rhs) its records.  Returns ROM_OK, or
+  // ROM_ENOCONV if a solve of this point reached maxit.
+  rom_status point(const rom_mu& p, double* Xi, rom_record* records) {
+    if (next_point_ >= K_)
+      throw Error(ROM_EINVAL, "the sequence was sized for " + std::to_string(K_) + " points");
+    const size_t first = recs_.size();
+    const int nonconv = n_nonconv_;
+    const int i = next_point_++;
+    sweep_point(i, p, Xi);
     sync();
+    tm_->harvest();
+    if (records) std::memcpy(records, recs_.data() + first, (size_t)n_rhs_ * sizeof(rom_record));
+    return n_nonconv_ > nonconv ? ROM_ENOCONV : ROM_OK;
+  }
+
+  // The basis as it stands (a view into the workspace, refreshed by every call).
+  const rom_basis* basis_view() {
+    view_.op = op_;
+    view_.n = n_;
+    view_.ld = ld_;
+    view_.m = m_;
+    view_.cap = cap_;
+    view_.Q = Q_;
+    view_.Gstar = Gs_;
+    view_.ldg = ldg_;
+    view_.n_src = n_src_;
+    view_.n_det = n_det_;
+    view_.idx_dev = idx_dev_;
+    view_.scale_dev = scale_dev_;
+    return &view_;
+  }
+
+  void report(rom_record* records, rom_stats* stats) {
     if (records) std::memcpy(records, recs_.data(), recs_.size() * sizeof(rom_record));
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
@@ -449,31 +478,49 @@ class Sequencer {
       stats->n_dropped_trunc = n_drop_trunc_;
       stats->n_dropped_cap = n_drop_cap_;
       stats->n_nonconv = n_nonconv_;
+      stats->n_uj_capped = n_uj_capped_;
       stats->total_its = total_its_;
       stats->seconds =
-          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
       for (int k = 0; k < ROM_NK; ++k) {
-        stats->kernel_ms[k] = timer.ms[k];
-        stats->kernel_bytes[k] = timer.bytes[k];
-        stats->kernel_flops[k] = timer.flops[k];
-        stats->kernel_launches[k] = timer.launches[k];
+        stats->kernel_ms[k] = tm_->ms[k];
+        stats->kernel_bytes[k] = tm_->bytes[k];
+        stats->kernel_flops[k] = tm_->flops[k];
+        stats->kernel_launches[k] = tm_->launches[k];
       }
     }
+  }
+
+  rom_basis* make_basis() {
     rom_basis* V = new rom_basis;
-    V->op = op_;
-    V->n = n_;
-    V->ld = ld_;
-    V->m = m_;
-    V->cap = cap_;
-    V->Q = Q_;
-    V->Gstar = Gs_;
-    V->ldg = ldg_;
-    V->n_src = n_src_;
-    V->n_det = n_det_;
-    V->idx_dev = idx_dev_;
-    V->scale_dev = scale_dev_;
-    *out_basis = V;
-    tm_ = nullptr;
+    *V = *basis_view();
+    return V;
+  }
+
+  int points_done() const { return next_point_; }
+  int points_max() const { return K_; }
+  int grid_dim() const { return S_.dim; }
+  int n_rhs() const { return n_rhs_; }
+  hipStream_t stream() const { return st_; }
+
+  rom_status run(const rom_mu* params, const int64_t* src_idx, const double* src_scale,
+                 const int64_t* det_idx, const double* det_scale, const double* U0,
+                 double* X_out, rom_record* records, rom_stats* stats, hipStream_t st,
+                 rom_basis** out_basis) {
+    begin(src_idx, src_scale, det_idx, det_scale, U0, st);
+    try {
+      for (int i = 0; i < K_; ++i)
+        point(params[i], X_out ? X_out + (int64_t)i * n_rhs_ * n_ : nullptr, nullptr);
+    } catch (...) {
+      // the records of the right-hand sides completed before the error
+      if (records) {
+        std::memset(records, 0, (size_t)K_ * n_rhs_ * sizeof(rom_record));
+        std::memcpy(records, recs_.data(), recs_.size() * sizeof(rom_record));
+      }
+      throw;
+    }
+    report(records, stats);
+    *out_basis = make_basis();
     return status_;
   }
 
@@ -702,10 +749,11 @@ class Sequencer {
     launch_spmm(S_, diag_i_, W, ld_, nj, AW, st_);
     tm_->begin(ROM_K_GRAM);
     // symmetric by construction: the lower triangle W_i^T (A W_j), i >= j, is mirrored
-    launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, true, nullptr, 0, 0.0, GW_, nj,
+    double* GW = GWs_ + (int64_t)y * NJ_MAX * NJ_MAX;
+    launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, true, nullptr, 0, 0.0, GW, nj,
                 gram_part_, st_);
     tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
-    launch_small_chol_inv(GW_, nj, LWinv_ + (int64_t)y * NJ_MAX * NJ_MAX,
+    launch_small_chol_inv(GW, nj, LWinv_ + (int64_t)y * NJ_MAX * NJ_MAX,
                           GWinv_ + (int64_t)y * NJ_MAX * NJ_MAX, &ctrl_->status[1], st_);
     if (mixed_) {
       launch_cast_cols_f32(n_, nj, W, ld_, W32_ + off, st_);
@@ -714,13 +762,13 @@ class Sequencer {
     return nj;
   }
 
-  // Algorithm 2 over the parameter points.
-  void sweep_points(const rom_mu* params, const double* U0, double* X_out) {
+  // One parameter point of Algorithm 2 (point index i of the sequence).
+  void sweep_point(int i, const rom_mu& p, double* Xi) {
     hipStream_t st = st_;
-    for (int i = 0; i < K_; ++i) {
+    {
       cur_point_ = i;
-      mu0_ = params[i].mu0;
-      launch_mu_eval(S_, make_bumps(params[i], S_.dim), op_->diag_star, diag_i_, dmu_, st);
+      mu0_ = p.mu0;
+      launch_mu_eval(S_, make_bumps(p, S_.dim), op_->diag_star, diag_i_, dmu_, st);
       // the rows of bump support of this point, and V gathered on them
       launch_nz_rows(n_, dmu_, bidx_, dmub_, nzcap_, &ctrl_->status[2], nzwork_, st);
       sync();
@@ -732,7 +780,7 @@ class Sequencer {
         // V <- orth(U_0): CGS2 append of every column (Alg. 2 initialisation)
         for (int c = 0; c < ku_in_; ++c) {
           double rho;
-          append_q(U0 + (int64_t)c * n_, &rho);
+          append_q(U0_ + (int64_t)c * n_, &rho);
         }
         ku_ = m_;
       } else {
@@ -742,9 +790,9 @@ class Sequencer {
       fused_ready_ = false;
       for (int y = 0; y < G_MAX; ++y) w_key_[y] = -2;
       if (G_ == 1)
-        point_sequential(i, X_out);
+        point_sequential(i, Xi);
       else
-        point_grouped(i, X_out);
+        point_grouped(i, Xi);
       if (i == 0) {
         // U_j <- [U_0, X_0(:, j)] (Sec. 4.2.2), X_0(:, j) orthonormalised against U_0
         for (int j = 0; j < n_rhs_; ++j) {
@@ -840,13 +888,22 @@ class Sequencer {
     }
   }
 
-  // U_j grows by the correction of RHS j orthonormalised against the recycle space it
-  // was solved with (member slot y), when the correction joined V (i > 0).
+  // U_j grows by the correction of RHS j orthonormalised against the persistent columns
+  // of the recycle space it was solved with (member slot y: U_0, then RHS j's earlier
+  // corrections, all orthonormal), when the correction joined V (i > 0).  The point's
+  // learned recycle vectors, packed after them, are only A_i-orthogonal to V and are not
+  // part of U_j, so the Gram-Schmidt pass leaves them out.  U_j stops growing at NJ_MAX
+  // columns (counted in n_uj_capped_).
   void update_Uj(int i, int j, int y, const double* gptr, int nj) {
-    if (i == 0 || ku_ + (int)extra_[j].size() >= NJ_MAX || next_slot_ >= pool_cap_) return;
+    if (i == 0 || next_slot_ >= pool_cap_) return;
+    const int npers = ku_ + (int)extra_[j].size();
+    if (npers >= NJ_MAX) {
+      ++n_uj_capped_;
+      return;
+    }
     double* slot = pool_ + (int64_t)next_slot_ * ld_;
     launch_axpby(n_, 1.0, gptr, 0.0, nullptr, slot, nullptr, red_part_, st_);
-    const double ru = cgs2_inplace(slot, Wp_ + (int64_t)y * ld_ * NJ_MAX, nj);
+    const double ru = cgs2_inplace(slot, Wp_ + (int64_t)y * ld_ * NJ_MAX, std::min(npers, nj));
     if (ru > trunc_) {
       launch_normalize(n_, slot, &ctrl_->sc[4], st_);
       extra_[j].push_back(next_slot_++);
@@ -974,7 +1031,7 @@ class Sequencer {
   }
 
   // The right-hand sides of point i one at a time (the paper's order).
-  void point_sequential(int i, double* X_out) {
+  void point_sequential(int i, double* Xi) {
     hipStream_t st = st_;
     for (int j = 0; j < n_rhs_; ++j) {
       const int64_t idx = idx_[j];
@@ -1002,7 +1059,7 @@ class Sequencer {
       sync();
       const double rho0 = std::sqrt(h_->sc[0]) / nb;
       rec.rho0 = rho0;
-      double* xdst = X_out ? X_out + ((int64_t)i * n_rhs_ + j) * n_ : xt_;
+      double* xdst = Xi ? Xi + (int64_t)j * n_ : xt_;
       if (rho0 <= tol_) {
         ROM_HIP(hipMemcpyAsync(xdst, x0_, sizeof(double) * n_, hipMemcpyDeviceToDevice, st));
         if (i == 0)
@@ -1065,12 +1122,12 @@ class Sequencer {
   // The right-hand sides of point i in groups of G_: one outer projection per group
   // (the basis as it stands at the group start), the group's inner solves together,
   // then the appends in right-hand-side order.
-  void point_grouped(int i, double* X_out) {
+  void point_grouped(int i, double* Xi) {
     hipStream_t st = st_;
     for (int j0 = 0; j0 < n_rhs_; j0 += G_) {
       const int nb = std::min(G_, n_rhs_ - j0);
-      double* xdst = X_out ? X_out + ((int64_t)i * n_rhs_ + j0) * n_ : xt_;
-      const int64_t ldx = X_out ? n_ : ld_;
+      double* xdst = Xi ? Xi + (int64_t)j0 * n_ : xt_;
+      const int64_t ldx = Xi ? n_ : ld_;
       // ---- outer projection of the group: X0 = V G_i^{-1} V^T [b_j0 ..]
       if (m_ > 0) {
         // t = V^T B (rows of V), u = L^{-1} t = Lr^T t, c = L^{-T} u = Lc^T u
@@ -1118,8 +1175,20 @@ class Sequencer {
       if (any) {
         for (int y = 0; y < nb; ++y)
           if (act[y]) nj[y] = make_W(i, j0 + y, i == 0 ? 0 : y);
+        // initial guesses move the members' base points (the Galerkin starts kept in xg_)
+        bool moved[G_MAX] = {};
+        if (guess_) guess_group(i, j0, nb, act, nbv, res, rec, moved);
+        else
+          for (int y = 0; y < nb; ++y)
+            if (act[y]) rec[y].rho_guess = -1.0;
         int its[G_MAX], restarts[G_MAX], flag[G_MAX];
         solve_group(i == 0, nb, j0, act, nj, nbv, res, xdst, ldx, its, restarts, flag, rec);
+        // the correction that joins V and U_j is x - x0 (x0 the Galerkin start, in range(V))
+        for (int y = 0; y < nb; ++y)
+          if (moved[y]) {
+            launch_axpby(n_, 1.0, xdst + y * ldx, -1.0, xg_ + (int64_t)y * ld_,
+                         g_ + (int64_t)y * ld_, nullptr, red_part_, st);
+          }
         for (int y = 0; y < nb; ++y)
           if (act[y]) record_solve(its[y], restarts[y], res[y], flag[y], rec[y]);
         // ---- the group's corrections join V (in right-hand-side order), then U_j
@@ -1249,6 +1318,61 @@ class Sequencer {
     return rho1;
   }
 
+  // The initial-guess step of guess_step for the active members of a group (right-hand
+  // sides j0 + y at point i), with two host syncs for the whole group.  A member whose
+  // guess lowers its residual takes the moved start as its base point: x0_ column y
+  // becomes x0 + alpha d (the Galerkin start is kept in xg_ column y) and r_ column y its
+  // residual.  res[y] becomes the relative residual of the start taken, rec[y].rho_guess
+  // too; moved[y] says which members moved.
+  void guess_group(int i, int j0, int nb, const int* act, const double* nbv, double* res,
+                   rom_record* rec, bool* moved) {
+    bool any = false;
+    for (int y = 0; y < nb; ++y) {
+      moved[y] = false;
+      if (!act[y]) continue;
+      any = true;
+      launch_guess_dir(n_, guess_ + ((int64_t)i * n_rhs_ + j0 + y) * n_, x0_ + (int64_t)y * ld_,
+                       d_ + (int64_t)y * ld_, st_);
+    }
+    if (!any) return;
+    launch_spmm(S_, diag_i_, d_, ld_, nb, w_, st_);
+    for (int y = 0; y < nb; ++y) {
+      if (!act[y]) continue;
+      account_spmv(ROM_K_OTHER);
+      launch_dot2_scale(n_, d_ + (int64_t)y * ld_, r_ + (int64_t)y * ld_, w_ + (int64_t)y * ld_,
+                        dmu_, nullptr, &ctrl_->gs[3 * y], red_part_, st_);
+    }
+    sync();
+    double alpha[G_MAX];
+    bool step[G_MAX];
+    for (int y = 0; y < nb; ++y) {
+      step[y] = false;
+      if (!act[y]) continue;
+      rec[y].rho_guess = res[y];
+      const double dr = h_->gs[3 * y], dad = h_->gs[3 * y + 1];
+      if (!(dad > 0.0) || !std::isfinite(dr) || !std::isfinite(dad)) continue;
+      alpha[y] = dr / dad;
+      step[y] = true;
+      launch_axpby(n_, 1.0, r_ + (int64_t)y * ld_, -alpha[y], w_ + (int64_t)y * ld_,
+                   r2_ + (int64_t)y * ld_, &ctrl_->gs[3 * y + 2], red_part_, st_);
+    }
+    sync();
+    for (int y = 0; y < nb; ++y) {
+      if (!step[y]) continue;
+      const double rho1 = std::sqrt(h_->gs[3 * y + 2]) / nbv[y];
+      if (!(rho1 < res[y])) continue;
+      double* x0y = x0_ + (int64_t)y * ld_;
+      double* keep = xg_ + (int64_t)y * ld_;
+      launch_axpby(n_, 1.0, x0y, 0.0, nullptr, keep, nullptr, red_part_, st_);
+      launch_axpby(n_, 1.0, keep, alpha[y], d_ + (int64_t)y * ld_, x0y, nullptr, red_part_, st_);
+      ROM_HIP(hipMemcpyAsync(r_ + (int64_t)y * ld_, r2_ + (int64_t)y * ld_, sizeof(double) * n_,
+                             hipMemcpyDeviceToDevice, st_));
+      res[y] = rho1;
+      rec[y].rho_guess = rho1;
+      moved[y] = true;
+    }
+  }
+
   // r2 = b - A x in FP64 (b = sc e_idx); returns ||r2|| / nb.
   double true_residual(const double* x, int64_t idx, double sc, double nb) {
     launch_resid_unit(S_, diag_i_, x, idx, sc, r2_, &ctrl_->sc[3], red_part_, st_);
@@ -1301,18 +1425,22 @@ class Sequencer {
     return its;
   }
 
+  // The CG vectors (q holds the q part of the split direction) and partials of the
+  // operator step (po), the start (ps) and the update (pu), as the solve's type.
   struct CgBufs32 {
     const float *W, *AW, *diag;
-    float *s, *p, *w, *part1, *part2;
+    float *s, *q, *w, *po, *ps, *pu;
   };
   struct CgBufs64 {
     const double *W, *AW, *diag;
-    double *s, *p, *w, *part1, *part2;
+    double *s, *q, *w, *po, *ps, *pu;
   };
-  void bufs(CgBufs64& b) const { b = {Wp_, AWp_, diag_i_, s_, p_, w_, part1_, part2_}; }
+  void bufs(CgBufs64& b) const {
+    b = {Wp_, AWp_, diag_i_, s_, p_, w_, part_o_, part2_, part_u_};
+  }
   void bufs(CgBufs32& b) const {
-    b = {W32_, AW32_, diag32_, s32_, p32_, w32_, reinterpret_cast<float*>(part1_),
-         reinterpret_cast<float*>(part2_)};
+    b = {W32_, AW32_, diag32_, s32_, p32_, w32_, reinterpret_cast<float*>(part_o_),
+         reinterpret_cast<float*>(part2_), reinterpret_cast<float*>(part_u_)};
   }
 
   // One batched deflated-CG solve: member y (active[y]) solves A_i d_y = rscale[y] r_y
@@ -1331,19 +1459,19 @@ class Sequencer {
     int flag[G_MAX] = {};
   };
 
-  // Launch shape of the CG step kernels, 2 P + narrow: P blocks per member, narrow for
-  // the variant with half the rows per thread.  Fixed shape: the full grid for one member,
-  // split among the members of a batch (narrow for batches).  With opts.tune the first
-  // batch of each (arithmetic, batch size, U_j width class, grid size) in the process times
-  // every power-of-two P with both variants on its own data (three rounds of 8 CG steps
-  // each after a warm-up round, from its real start; the solve then restarts) and keeps the
-  // fastest (by its best round) for the rest of the process.
+  // Launch shape of the CG update kernel, 2 P + narrow: P blocks per member, narrow for
+  // the variant with half the rows per thread (the operator step always runs on the
+  // stencil shape).  Fixed shape: the full grid for one member, split among the members of
+  // a batch (narrow for batches).  With opts.tune the first batch of each (arithmetic,
+  // batch size, U_j width class, grid size) in the process times every power-of-two P
+  // with both variants on its own data (three rounds of 8 CG steps each after a warm-up
+  // round, from its real start; the solve then restarts) and keeps the fastest (by its
+  // best round) for the rest of the process.
   template <typename T, typename Bufs>
   int cg_shape(const Batch& bt, const Bufs& b, const double* rhs, T* dvec, int64_t wstride,
                int64_t gstride, int njmax) {
     const int nb = bt.nb;
     const int Pmax = dcg_blocks(n_);
-    // shape = 2 P + narrow (the variant with half the rows per thread)
     const int fixed = 2 * std::max(std::min(Pmax, 8), Pmax / nb) + (nb > 1 ? 1 : 0);
     if (!tune_) return fixed;
     int dev = 0;
@@ -1371,12 +1499,10 @@ class Sequencer {
         su.nj[y] = bt.nj[y];
         su.active[y] = bt.active[y];
       }
-      const StencilShape sh = cg_apply_shape<T>(S_, 1024, b.diag, b.p, b.w, ld_);
-      launch_cg_setup(cg, su, nb, st_);
+      const StencilShape sh = cg_apply_shape<T>(S_, 1024, b.diag, b.q, b.w, ld_, b.AW);
+      launch_cg_setup(cg, cgv_, su, nb, st_);
       launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec,
-                          b.s, ld_, cg, b.part2, p2s_, nb, Pmax, st_);
-      launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, -1, cg,
-                        b.part2, p2s_, nb, Pmax, st_);
+                          b.s, b.q, ld_, cg, b.ps, p2s_, nb, Pmax, st_);
       hipEvent_t e0, e1;
       ROM_HIP(hipEventCreate(&e0));
       ROM_HIP(hipEventCreate(&e1));
@@ -1387,7 +1513,7 @@ class Sequencer {
           (void)hipEventDestroy(b);
         }
       } guard{e0, e1};
-      int k = 0;
+      int Pprev = Pmax;   // blocks of the launch whose partials the next operator step sums
       // each shape's time is the minimum over 3 rounds of 8 steps (the first round only
       // warms up): single short windows were noisy enough to flip the choice between runs
       std::vector<float> tmin(cand.size(), 1e30f);
@@ -1396,12 +1522,13 @@ class Sequencer {
           const int shape = cand[ci];
           const int P = shape >> 1, nr = shape & 1;
           ROM_HIP(hipEventRecord(e0, st_));
-          for (int step = 0; step < 8; ++step, ++k) {
-            launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, st_);
-            launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
-                                 b.part1, sh.blocks, sh.blocks, b.part2, p2s_, nb, P, st_, nr);
-            launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,
-                              b.part2, p2s_, nb, P, st_, 0, nr);
+          for (int step = 0; step < 8; ++step) {
+            launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax,
+                             GWinv_, GWs_, gstride, cg, cgv_, b.ps, Pmax, p2s_, b.pu, Pprev,
+                             pus_, b.po, pos_, nb, st_);
+            launch_dcg_update<T>(b.q, b.w, dvec, b.s, ld_, n_, njmax, cg, cgv_, b.po, sh.blocks,
+                                 pos_, b.pu, pus_, nb, P, st_, nr);
+            Pprev = P;
           }
           ROM_HIP(hipEventRecord(e1, st_));
           ROM_HIP(hipEventSynchronize(e1));
@@ -1422,9 +1549,9 @@ class Sequencer {
     return best;
   }
 
-  // A captured chunk of GRAPH_STEPS CG steps (operator, update, direction) that takes its
-  // step index from the CG state, replayed instead of individual launches.  One graph per
-  // (value type, batch size, shared recycle space, width class, blocks, output vector),
+  // A captured chunk of GRAPH_STEPS CG steps (operator step, update; both take the step
+  // index from the CG state), replayed instead of individual launches.  One graph per
+  // (value type, batch size, shared recycle space, width class, shape, output vector),
   // kept for the rest of the call.
   template <typename T, typename Bufs>
   hipGraphExec_t chunk_graph(const Bufs& b, int nb, bool shared, int njmax, int shape,
@@ -1440,14 +1567,15 @@ class Sequencer {
     if (!cap_st_) ROM_HIP(hipStreamCreateWithFlags(&cap_st_, hipStreamNonBlocking));
     hipStream_t cs = cap_st_;
     hipGraph_t g = nullptr;
+    const int P0 = dcg_blocks(n_);
     ROM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
       for (int c = 0; c < GRAPH_STEPS; ++c) {
-        launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, cs);
-        launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, ITER_STATE,
-                             cg, b.part1, sh.blocks, sh.blocks, b.part2, p2s_, nb, P, cs, nr);
-        launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_,
-                          ITER_STATE, cg, b.part2, p2s_, nb, P, cs, 0, nr);
+        launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax, GWinv_,
+                         GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.pu, P, pus_, b.po, pos_, nb,
+                         cs);
+        launch_dcg_update<T>(b.q, b.w, dvec, b.s, ld_, n_, njmax, cg, cgv_, b.po, sh.blocks,
+                             pos_, b.pu, pus_, nb, P, cs, nr);
       }
     } catch (...) {
       hipGraph_t dummy = nullptr;
@@ -1471,8 +1599,8 @@ class Sequencer {
     const int nb = bt.nb;
     CGState* cg = ctrl_->cg;
     // the operator step's shape (two x-nodes per thread where the layout allows); its block
-    // count is both the number and the per-member stride of the operator's partials
-    const StencilShape sh = cg_apply_shape<T>(S_, 1024, b.diag, b.p, b.w, ld_);
+    // count is the number of the operator step's partial rows per member
+    const StencilShape sh = cg_apply_shape<T>(S_, 1024, b.diag, b.q, b.w, ld_, b.AW);
     const int64_t wstride = bt.shared ? 0 : ld_ * NJ_MAX;
     const int64_t gstride = bt.shared ? 0 : (int64_t)NJ_MAX * NJ_MAX;
     CgSetup su;
@@ -1493,7 +1621,7 @@ class Sequencer {
     if (nact == 0) return;
     const int shape = cg_shape<T>(bt, b, rhs, dvec, wstride, gstride, njmax);
     const int P = shape >> 1, nr = shape & 1;
-    launch_cg_setup(cg, su, nb, st_);
+    launch_cg_setup(cg, cgv_, su, nb, st_);
     // U_j^T r_j for the start
     if (njmax > 0) {
       if (bt.shared && nact > 1) {
@@ -1517,30 +1645,29 @@ class Sequencer {
       if (bt.active[y]) njavg += bt.nj[y];
     njavg /= nact;
     // the start runs once per solve on the full grid for every member (its 256-thread
-    // blocks would leave the chip idle on the steps' grid); the first direction step
+    // blocks would leave the chip idle on the update's grid); the first operator step
     // reduces its partial rows
     const int P0 = dcg_blocks(n_);
+    tm_->begin(ROM_K_DCG_ENDS);
     launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec, b.s,
-                        ld_, cg, b.part2, p2s_, nb, P0, st_);
-    tm_->begin(ROM_K_DCG_DIR);
-    launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, -1, cg,
-                      b.part2, p2s_, nb, P, st_, P0, nr);
-    tm_->end(ROM_K_DCG_DIR, nact * E * n_ * (2 + njavg), nact * n_ * (1.0 + 2.0 * njavg));
-    // per member and step
-    const double by_apply = E * n_ * (3 + (S_.var ? S_.dim : 0));
-    const double fl_apply = 15.0 * n_;
-    const double by_upd = E * n_ * (6 + njavg);
-    const double fl_upd = n_ * (6.0 + 2.0 * njavg);
-    const double by_dir = E * n_ * (3 + njavg);
-    const double fl_dir = n_ * (3.0 + 2.0 * njavg);
+                        b.q, ld_, cg, b.ps, p2s_, nb, P0, st_);
+    tm_->end(ROM_K_DCG_ENDS, nact * (8.0 * n_ + E * n_ * (2 * njavg + 3)),
+             nact * n_ * (2.0 + 4.0 * njavg));
+    // algorithmic bytes and flops per member and step: the operator step reads q, the
+    // diagonal (and face coefficients), s and AU and writes w; the update reads q, w, g, s
+    // and writes q, g, s
+    const double by_op = E * n_ * (4 + njavg + (S_.var ? S_.dim : 0));
+    const double fl_op = n_ * (21.0 + 6.0 * njavg);
+    const double by_upd = 7.0 * E * n_;
+    const double fl_upd = 8.0 * n_;
     int next = chunk_;
-    int k0 = 0;
     int its_before[G_MAX] = {};
     double gam_before[G_MAX];
     for (int y = 0; y < G_MAX; ++y) gam_before[y] = -1.0;
     int nlive = nact;
+    int Pu = P;   // blocks of the update whose partials the next operator step sums
     // CG steps as replays of a captured chunk when asked for and no step kernel is timed
-    const int cg_classes = (1 << ROM_K_SPMV) | (1 << ROM_K_DCG_UPDATE) | (1 << ROM_K_DCG_DIR);
+    const int cg_classes = (1 << ROM_K_DCG_OP) | (1 << ROM_K_DCG_UPDATE);
     const bool graphs = graph_ && !(o_.timing & cg_classes);
     for (;;) {
       if (graphs) {
@@ -1550,30 +1677,27 @@ class Sequencer {
         for (int r = 0; r < reps; ++r) ROM_HIP(hipGraphLaunch(ex, st_));
         next = reps * GRAPH_STEPS;
         for (int c = 0; c < next; ++c) {
-          tm_->add(ROM_K_SPMV, nlive * by_apply, nlive * fl_apply);
+          tm_->add(ROM_K_DCG_OP, nlive * by_op, nlive * fl_op);
           tm_->add(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
-          tm_->add(ROM_K_DCG_DIR, nlive * by_dir, nlive * fl_dir);
         }
       }
       for (int c = 0; c < (graphs ? 0 : next); ++c) {
-        const int k = k0 + c;
-        tm_->begin(ROM_K_SPMV);
-        launch_dcg_apply<T>(S_, sh, b.diag, b.p, b.w, ld_, cg, b.part1, nb, st_);
-        tm_->end(ROM_K_SPMV, nlive * by_apply, nlive * fl_apply);
+        tm_->begin(ROM_K_DCG_OP);
+        launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax, GWinv_,
+                         GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.pu, Pu, pus_, b.po, pos_, nb,
+                         st_);
+        tm_->end(ROM_K_DCG_OP, nlive * by_op, nlive * fl_op);
         tm_->begin(ROM_K_DCG_UPDATE);
-        launch_dcg_update<T>(b.AW, wstride, ld_, n_, njmax, b.p, b.w, dvec, b.s, ld_, k, cg,
-                             b.part1, sh.blocks, sh.blocks, b.part2, p2s_, nb, P, st_, nr);
+        launch_dcg_update<T>(b.q, b.w, dvec, b.s, ld_, n_, njmax, cg, cgv_, b.po, sh.blocks,
+                             pos_, b.pu, pus_, nb, P, st_, nr);
         tm_->end(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
-        tm_->begin(ROM_K_DCG_DIR);
-        launch_dcg_dir<T>(b.W, wstride, ld_, n_, njmax, GWinv_, gstride, b.s, b.p, ld_, k, cg,
-                          b.part2, p2s_, nb, P, st_, 0, nr);
-        tm_->end(ROM_K_DCG_DIR, nlive * by_dir, nlive * fl_dir);
+        Pu = P;
       }
       ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
       ROM_HIP(hipStreamSynchronize(st_));
-      // member-steps done in this chunk; launches after the last member stopped
-      // returned at once (the direction update of a stopping step is one of them)
-      int maxreal = 0, steps = 0, still = 0, nstopped = 0;
+      // member-steps (updates) done in this chunk; once the last member stopped, the
+      // launches after the operator step that stopped it returned at once
+      int maxreal = 0, steps = 0, still = 0;
       for (int y = 0; y < nb; ++y) {
         if (!bt.active[y] || its_before[y] < 0) continue;
         const CGState& c = h_->cg[y];
@@ -1581,7 +1705,6 @@ class Sequencer {
         maxreal = std::max(maxreal, real);
         steps += real;
         if (c.done) {
-          ++nstopped;
           its_before[y] = -1;
         } else {
           ++still;
@@ -1589,14 +1712,11 @@ class Sequencer {
         }
       }
       const bool stop = still == 0;
-      const int noop = stop ? next - maxreal : 0;
-      tm_->discard(ROM_K_SPMV, noop, 0.0, 0.0);
-      tm_->discard(ROM_K_DCG_UPDATE, noop, 0.0, 0.0);
-      tm_->discard(ROM_K_DCG_DIR, noop + (stop ? 1 : 0), 0.0, 0.0);
+      tm_->discard(ROM_K_DCG_OP, stop ? next - maxreal - 1 : 0, 0.0, 0.0);
+      tm_->discard(ROM_K_DCG_UPDATE, stop ? next - maxreal : 0, 0.0, 0.0);
       const double over = (double)nlive * next - steps;
-      tm_->adjust(ROM_K_SPMV, -over * by_apply, -over * fl_apply);
+      tm_->adjust(ROM_K_DCG_OP, -over * by_op, -over * fl_op);
       tm_->adjust(ROM_K_DCG_UPDATE, -over * by_upd, -over * fl_upd);
-      tm_->adjust(ROM_K_DCG_DIR, -(over + nstopped) * by_dir, -(over + nstopped) * fl_dir);
       tm_->harvest();
       if (stop) break;
       // next poll: extrapolate each live member's contraction of s^T s to its tolerance
@@ -1613,10 +1733,13 @@ class Sequencer {
         pred = std::max(pred, py);
         gam_before[y] = gam;
       }
-      k0 += next;
       nlive = still;
       next = std::min(64, std::max(2, pred));
     }
+    // the correction: g = g_q - U e
+    tm_->begin(ROM_K_DCG_ENDS);
+    launch_dcg_finish<T>(b.W, wstride, ld_, n_, njmax, dvec, ld_, cg, cgv_, nb, st_);
+    tm_->end(ROM_K_DCG_ENDS, nact * E * n_ * (2 + njavg), nact * 2.0 * n_ * njavg);
     for (int y = 0; y < nb; ++y) {
       if (!bt.active[y]) continue;
       bt.its[y] = h_->cg[y].its;
@@ -1652,7 +1775,7 @@ class Sequencer {
   int maxit_, chunk_;
   int G_ = 1;                // right-hand sides per group
   int cur_point_ = 0;
-  int64_t p1s_ = 0, p2s_ = 0;   // per-member strides of the CG partials
+  int64_t pos_ = 0, p2s_ = 0, pus_ = 0;   // per-member strides of the CG partials
   bool mixed_ = false;
   bool tune_ = false;
   bool graph_ = false;
@@ -1679,6 +1802,12 @@ class Sequencer {
   rom_status status_ = ROM_OK;
   long long total_its_ = 0;
   int n_solved_ = 0, n_kept_ = 0, n_drop_trunc_ = 0, n_drop_cap_ = 0, n_nonconv_ = 0;
+  int n_uj_capped_ = 0;
+  int next_point_ = 0;
+  const double* U0_ = nullptr;
+  std::unique_ptr<Timer> timer_;
+  std::chrono::steady_clock::time_point t0_;
+  rom_basis view_{};
   std::vector<std::vector<int>> extra_;
   std::vector<int64_t> idx_;
   std::vector<double> scale_;
@@ -1694,7 +1823,7 @@ class Sequencer {
   int* nzwork_ = nullptr;
   int64_t nzcap_ = 0, ldb_ = 0, nzr_ = 0;
   bool compact_ = false;
-  double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GW_, *LWinv_, *GWinv_, *lwork_;
+  double *tbuf_, *ubuf_, *cbuf_, *tmpl_, *tmpr_, *bvals_, *GWs_, *LWinv_, *GWinv_, *lwork_;
   // the next right-hand side's start fused into an append's first Gram-Schmidt pass:
   // fa_ = V y, fw_ = V w (y = G_i^{-1} V^T b_next, w = G_i^{-1} V^T A_i u)
   double *fa_ = nullptr, *fw_ = nullptr, *fcw_ = nullptr, *ftmp_ = nullptr;
@@ -1706,7 +1835,8 @@ class Sequencer {
   bool fused_ready_ = false, fused_kept_ = false;
   double fused_rho_ = 0.0;
   Ctrl* ctrl_;
-  double *part1_, *part2_;
+  double *part_o_, *part2_, *part_u_;
+  CGVec* cgv_ = nullptr;
   // mixed form: FP32 copies of U_j, A U_j, the diagonal and the face coefficients, and the
   // FP32 CG vectors
   float *W32_ = nullptr, *AW32_ = nullptr, *s32_ = nullptr, *p32_ = nullptr, *w32_ = nullptr;
@@ -1732,7 +1862,6 @@ void check_opts(const rom_opts* o) {
   if (o->group < 0 || o->group > G_MAX) throw Error(ROM_EINVAL, "group must be in [0, 16]");
   if (o->tune != 0 && o->tune != 1) throw Error(ROM_EINVAL, "tune must be 0 or 1");
   if (o->graph != 0 && o->graph != 1) throw Error(ROM_EINVAL, "graph must be 0 or 1");
-  if (o->guess && o->group > 1) throw Error(ROM_EINVAL, "initial guesses need group <= 1");
   if (o->recycle && (o->n_recycle < 1 || o->n_recycle > REC_MAX))
     throw Error(ROM_EINVAL, "n_recycle must be in [1, 16]");
 }
@@ -1909,6 +2038,126 @@ rom_status rom_sequence_bytes(const rom_operator* op, int n_src, int n_det, int 
     return ROM_OK;
   } catch (const Error& e) {
     return rom::fail(e);
+  }
+}
+
+}  // extern "C"
+
+namespace rom {
+namespace {
+// Arguments shared by rom_solve_sequence and rom_sequence_begin.
+void check_sequence_args(rom_operator* op, int K, const int64_t* src_idx, const double* src_scale,
+                         int n_src, const int64_t* det_idx, const double* det_scale, int n_det,
+                         const double* U0, int k_u, const rom_opts* opts, void* workspace) {
+  if (!op || !workspace) throw Error(ROM_EINVAL, "null operator or workspace");
+  check_opts(opts);
+  check_counts(n_src, n_det, k_u, K);
+  if (k_u > 0 && !U0) throw Error(ROM_EINVAL, "null U0 with k_u > 0");
+  if ((n_src > 0 && (!src_idx || !src_scale)) || (n_det > 0 && (!det_idx || !det_scale)))
+    throw Error(ROM_EINVAL, "null source/detector arrays");
+  for (int j = 0; j < n_src + n_det; ++j) {
+    const int64_t idx = j < n_src ? src_idx[j] : det_idx[j - n_src];
+    const double sc = j < n_src ? src_scale[j] : det_scale[j - n_src];
+    if (idx < 0 || idx >= op->n) throw Error(ROM_EINVAL, "source/detector index out of range");
+    if (!(sc != 0.0) || !std::isfinite(sc)) throw Error(ROM_EINVAL, "scale must be finite and nonzero");
+  }
+  if ((uintptr_t)workspace % 16) throw Error(ROM_EINVAL, "workspace must be 16-byte aligned");
+}
+}  // namespace
+}  // namespace rom
+
+// A sequence solved one parameter point at a time (rom_sequence_begin/point/end).
+struct rom_sequence {
+  std::unique_ptr<rom::Sequencer> s;
+  bool failed = false;
+};
+
+extern "C" {
+
+rom_status rom_sequence_begin(rom_operator* op, int K, const int64_t* src_idx,
+                              const double* src_scale, int n_src, const int64_t* det_idx,
+                              const double* det_scale, int n_det, const double* U0, int k_u,
+                              const rom_opts* opts, void* workspace, size_t ws_bytes,
+                              rom_sequence** seq, void* stream) {
+  try {
+    if (!seq) throw Error(ROM_EINVAL, "null sequence handle");
+    *seq = nullptr;
+    rom::check_sequence_args(op, K, src_idx, src_scale, n_src, det_idx, det_scale, n_det, U0,
+                             k_u, opts, workspace);
+    std::unique_ptr<rom_sequence> h(new rom_sequence);
+    h->s.reset(new rom::Sequencer(op, n_src, n_det, k_u, K, *opts));
+    const size_t need = h->s->layout(nullptr);
+    if (ws_bytes < need) throw Error(ROM_ECAPACITY, "workspace too small");
+    h->s->layout(workspace);
+    h->s->begin(src_idx, src_scale, det_idx, det_scale, U0, (hipStream_t)stream);
+    *seq = h.release();
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  } catch (const std::exception& e) {
+    rom::g_err = e.what();
+    return ROM_EHIP;
+  }
+}
+
+rom_status rom_sequence_point(rom_sequence* seq, const rom_mu* p, double* X_out,
+                              rom_record* records) {
+  try {
+    if (!seq || !seq->s) throw Error(ROM_EINVAL, "null sequence");
+    if (seq->failed) throw Error(ROM_EINVAL, "the sequence stopped at an earlier error");
+    rom::check_mu(p, seq->s->grid_dim());
+    if (seq->s->points_done() >= seq->s->points_max())
+      throw Error(ROM_EINVAL, "the sequence was sized for " +
+                                  std::to_string(seq->s->points_max()) + " points");
+    try {
+      return seq->s->point(*p, X_out, records);
+    } catch (...) {
+      seq->failed = true;
+      throw;
+    }
+  } catch (const Error& e) {
+    return rom::fail(e);
+  } catch (const std::exception& e) {
+    rom::g_err = e.what();
+    return ROM_EHIP;
+  }
+}
+
+rom_status rom_sequence_basis(rom_sequence* seq, const rom_basis** V) {
+  try {
+    if (!seq || !seq->s || !V) throw Error(ROM_EINVAL, "null argument");
+    if (seq->failed) throw Error(ROM_EINVAL, "the sequence stopped at an earlier error");
+    *V = seq->s->basis_view();
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_sequence_stats(rom_sequence* seq, rom_stats* stats) {
+  try {
+    if (!seq || !seq->s || !stats) throw Error(ROM_EINVAL, "null argument");
+    seq->s->report(nullptr, stats);
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  }
+}
+
+rom_status rom_sequence_end(rom_sequence* seq, rom_basis** basis, rom_stats* stats) {
+  try {
+    if (!seq) throw Error(ROM_EINVAL, "null sequence");
+    std::unique_ptr<rom_sequence> h(seq);
+    if (basis) *basis = nullptr;
+    if (h->failed) throw Error(ROM_EINVAL, "the sequence stopped at an earlier error");
+    h->s->report(nullptr, stats);
+    if (basis) *basis = h->s->make_basis();
+    return ROM_OK;
+  } catch (const Error& e) {
+    return rom::fail(e);
+  } catch (const std::exception& e) {
+    rom::g_err = e.what();
+    return ROM_EHIP;
   }
 }
 

@@ -143,7 +143,7 @@ __device__ __forceinline__ Faces<float> faces(const Stencil& S, float) {
   return {S.fx32, S.fy32, S.fz32};
 }
 
-// MODE 0: y = A x.  MODE 1: y = A x, partial x^T y (CG step; exits if cg[z].done).
+// MODE 0: y = A x.
 // MODE 2: y = b - A x with b = bscale e_bidx (or bscale_arr[z] e_{bidx_arr[z]}), partial
 // y^T y.  blockIdx.z selects a column (x + z*ldx, y + z*ldy; partials of column z at
 // + z * gridDim.x * gridDim.y).  T is the arithmetic type.
@@ -155,7 +155,6 @@ __global__ __launch_bounds__(BS) void k_stencil(Stencil S, const T* __restrict__
                                                  const int64_t* __restrict__ bidx_arr,
                                                  const double* __restrict__ bscale_arr,
                                                  T* __restrict__ partials, const CGState* cg) {
-  if (MODE == 1 && cg[blockIdx.z].done) return;
   if (MODE == 2 && bidx_arr) {
     bidx = bidx_arr[blockIdx.z];
     bscale = bscale_arr[blockIdx.z];
@@ -201,8 +200,6 @@ __global__ __launch_bounds__(BS) void k_stencil(Stencil S, const T* __restrict__
         v = -v;
         if (i == bidx) v += (T)bscale;
         acc[0] += v * v;
-      } else if (MODE == 1) {
-        acc[0] += xc * v;
       }
       y[i] = v;
       xm = xc;
@@ -357,30 +354,6 @@ __global__ __launch_bounds__(BS) void k_cheb_step2(Stencil S, const double* __re
                      });
 }
 
-// The CG operator step (k_stencil MODE 1) with two x-nodes per thread: w = A p and the
-// partial p^T w per block, members on blockIdx.z (a stopped member's blocks return).
-template <typename T, bool VAR>
-__global__ __launch_bounds__(BS) void k_cg_apply2(Stencil S, const T* __restrict__ diag,
-                                                   const T* __restrict__ p0, int64_t vstride,
-                                                   T* __restrict__ w0, int zc,
-                                                   T* __restrict__ partials, const CGState* cg) {
-  if (cg[blockIdx.z].done) return;
-  const T* __restrict__ p = p0 + (int64_t)blockIdx.z * vstride;
-  T* __restrict__ w = w0 + (int64_t)blockIdx.z * vstride;
-  const int q = blockIdx.x * BS + threadIdx.x;
-  const int z0 = blockIdx.y * zc;
-  const int z1 = min(z0 + zc, S.nz);
-  T acc[1] = {T(0)};
-  if (q < (S.nx / 2) * S.ny && z0 < z1)
-    stencil_walk2t<T, VAR>(S, diag, p, q, z0, z1, [&](int64_t i, T v0, T v1, T x0i, T x1i) {
-      using V = typename Vec2<T>::type;
-      *reinterpret_cast<V*>(w + i) = V{v0, v1};
-      acc[0] += x0i * v0 + x1i * v1;
-    });
-  write_partials<1, BS>(acc, partials + (int64_t)blockIdx.z * gridDim.x * gridDim.y,
-                        blockIdx.x + gridDim.x * blockIdx.y);
-}
-
 // out[z * ostride] = sum_b partials[z * P + b], one block per column z.
 __global__ void k_reduce_cols(const double* __restrict__ partials, int P, double* out,
                               int64_t ostride) {
@@ -524,9 +497,9 @@ void launch_resid_unit(const Stencil& S, const double* diag, const double* x, in
 
 template <typename T>
 StencilShape cg_apply_shape(const Stencil& S, int target_blocks, const T* diag, const T* p,
-                            const T* w, int64_t vstride) {
+                            const T* w, int64_t vstride, const T* AW) {
   StencilShape sh = stencil_shape(S, target_blocks);
-  if (stencil_pairs_ok(S, vstride, {diag, p, w}, sizeof(T) == 4)) {
+  if (stencil_pairs_ok(S, vstride, {diag, p, w, AW}, sizeof(T) == 4)) {
     sh.grid.x = ceil_div((int64_t)(S.nx / 2) * S.ny, BS);
     sh.blocks = (int)(sh.grid.x * sh.grid.y);
     sh.pairs = 1;
@@ -534,32 +507,9 @@ StencilShape cg_apply_shape(const Stencil& S, int target_blocks, const T* diag, 
   return sh;
 }
 template StencilShape cg_apply_shape<double>(const Stencil&, int, const double*, const double*,
-                                             const double*, int64_t);
+                                             const double*, int64_t, const double*);
 template StencilShape cg_apply_shape<float>(const Stencil&, int, const float*, const float*,
-                                            const float*, int64_t);
-
-template <typename T>
-void launch_dcg_apply(const Stencil& S, const StencilShape& sh, const T* diag, const T* p, T* w,
-                      int64_t vstride, CGState* cg, T* part1, int nb, hipStream_t st) {
-  const dim3 grid(sh.grid.x, sh.grid.y, nb);
-  if (sh.pairs) {
-    if (S.var)
-      ROM_LAUNCH((k_cg_apply2<T, true>), grid, dim3(BS), 0, st, S, diag, p, vstride, w, sh.zc,
-                 part1, (const CGState*)cg);
-    else
-      ROM_LAUNCH((k_cg_apply2<T, false>), grid, dim3(BS), 0, st, S, diag, p, vstride, w, sh.zc,
-                 part1, (const CGState*)cg);
-    return;
-  }
-  STENCIL_LAUNCH(T, 1, grid, diag, p, vstride, w, vstride, sh.zc, (int64_t)-1, 0.0,
-                 (const int64_t*)nullptr, (const double*)nullptr, part1, (const CGState*)cg);
-}
-template void launch_dcg_apply<double>(const Stencil&, const StencilShape&, const double*,
-                                       const double*, double*, int64_t, CGState*, double*, int,
-                                       hipStream_t);
-template void launch_dcg_apply<float>(const Stencil&, const StencilShape&, const float*,
-                                      const float*, float*, int64_t, CGState*, float*, int,
-                                      hipStream_t);
+                                            const float*, int64_t, const float*);
 
 void launch_resid_cols(const Stencil& S, const double* diag, const double* X, int64_t ldx, int nb,
                        const int64_t* idx, const double* scale, double* R, int64_t ldr,

@@ -64,6 +64,16 @@ class Problem:
         self.U0 = None if U0 is None or self.k_u == 0 else torch.as_tensor(
             np.ascontiguousarray(np.asarray(U0, dtype=np.float64).T), device=self.device)
 
+    def set_U0(self, U: Optional[torch.Tensor]) -> None:
+        """Use the rows of U ((k_u, N), e.g. rom_lowest_modes' eigenvectors of A(p_0)) as
+        the recycle seed U_0 of later sequences (None: no seed)."""
+        if U is None or U.shape[0] == 0:
+            self.U0, self.k_u = None, 0
+            return
+        assert U.dim() == 2 and U.shape[1] == self.n
+        self.U0 = U.to(dtype=torch.float64, device=self.device).contiguous()
+        self.k_u = int(U.shape[0])
+
     @property
     def n_rhs(self) -> int:
         return self.src_idx.size + self.det_idx.size
@@ -91,6 +101,20 @@ class Problem:
             self.k_u, opts, ws, X)
         n, m = R.rom_basis_dims(basis)
         return SequenceResult(status, basis, records, R.stats_dict(st), ws, X, n, m)
+
+    def stream(self, K: int, tol: float, trunc: float = 1e-8, cap: int = 0, **kw) -> "SequenceStream":
+        """A sequence taken one parameter point at a time (rom_sequence_begin): at most K
+        points; kw as for solve (precision, group, tune, timing, guess, recycle...)."""
+        opts = R.make_opts(tol, trunc, cap, kw.pop("maxit", 0), kw.pop("check_every", 0),
+                           kw.pop("timing", 0), kw.pop("precision", R.ROM_PREC_FP64),
+                           kw.pop("inner_tol", 0.0), kw.pop("group", 0), kw.pop("tune", 0),
+                           kw.pop("graph", 0), kw.pop("guess", None), kw.pop("recycle", None))
+        assert not kw, kw
+        nbytes = R.rom_sequence_bytes(self.op, self.src_idx.size, self.det_idx.size, self.k_u, K, opts)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = R.rom_sequence_begin(self.op, K, self.src_idx, self.src_scale, self.det_idx,
+                                 self.det_scale, self.U0, self.k_u, opts, ws)
+        return SequenceStream(self, h, ws)
 
     def reduced(self, res: SequenceResult, p: R.MuParams):
         """(A_r, B_r, C_r, E_r) of eq. (newreduced) as float64 tensors (column-major
@@ -177,6 +201,37 @@ class Problem:
         if self.op:
             R.rom_operator_destroy(self.op)
             self.op = 0
+
+
+class SequenceStream:
+    """Algorithm 2 fed one point at a time (rom_sequence_point); the basis so far is a
+    view (rom_sequence_basis) until end() returns the final SequenceResult."""
+
+    def __init__(self, prob: Problem, handle, workspace: torch.Tensor):
+        self.prob = prob
+        self.h = handle
+        self.workspace = workspace
+        self.records: List[dict] = []
+
+    def point(self, p: R.MuParams, X: Optional[torch.Tensor] = None):
+        """Solve point p; X ((n_rhs, N) float64, or None) receives its solutions."""
+        status, recs = R.rom_sequence_point(self.h, p, X)
+        self.records.extend(recs)
+        return status, recs
+
+    def basis_view(self) -> int:
+        return R.rom_sequence_basis(self.h)
+
+    def stats(self) -> dict:
+        """Totals so far (stats_dict of rom_sequence_stats)."""
+        return R.stats_dict(R.rom_sequence_stats(self.h))
+
+    def end(self) -> SequenceResult:
+        basis, st = R.rom_sequence_end(self.h)
+        n, m = R.rom_basis_dims(basis)
+        stats = R.stats_dict(st)
+        status = R.ROM_ENOCONV if stats["n_nonconv"] else R.ROM_OK
+        return SequenceResult(status, basis, self.records, stats, self.workspace, None, n, m)
 
 
 def solve_many(problems: List["Problem"], points: List[List[R.MuParams]], tol: float,

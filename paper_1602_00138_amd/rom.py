@@ -31,13 +31,14 @@ ROM_MAX_BUMPS = 64
 ROM_PREC_FP64 = 0
 ROM_PREC_MIXED = 1
 
-(ROM_K_SPMV, ROM_K_DCG_UPDATE, ROM_K_DCG_DIR, ROM_K_GEMVT, ROM_K_GEMVN, ROM_K_GRAM, ROM_K_OUTER,
+(ROM_K_DCG_OP, ROM_K_DCG_UPDATE, ROM_K_DCG_ENDS, ROM_K_GEMVT, ROM_K_GEMVN, ROM_K_GRAM, ROM_K_OUTER,
  ROM_K_OTHER) = range(8)
 ROM_NK = 8
-KERNEL_CLASSES = ["spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "outer", "other"]
+KERNEL_CLASSES = ["dcg_op", "dcg_update", "dcg_ends", "gemvt", "gemvn", "gram", "outer", "other"]
 
 EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator",
-            "rom_apply_operator_static", "rom_sequence_bytes",
+            "rom_apply_operator_static", "rom_sequence_bytes", "rom_sequence_begin",
+            "rom_sequence_point", "rom_sequence_basis", "rom_sequence_stats", "rom_sequence_end",
             "rom_solve_sequence", "rom_solve_sequences", "rom_reduced_bytes", "rom_reduced_transfer",
             "rom_reduced_jacobian_bytes", "rom_reduced_jacobian", "rom_lowest_modes_bytes",
             "rom_lowest_modes", "rom_shifted_solve_bytes", "rom_shifted_solve",
@@ -79,7 +80,8 @@ class rom_stats(C.Structure):
                 ("n_dropped_trunc", C.c_int), ("n_dropped_cap", C.c_int),
                 ("n_nonconv", C.c_int), ("total_its", C.c_longlong), ("seconds", C.c_double),
                 ("kernel_ms", C.c_double * ROM_NK), ("kernel_bytes", C.c_double * ROM_NK),
-                ("kernel_flops", C.c_double * ROM_NK), ("kernel_launches", C.c_longlong * ROM_NK)]
+                ("kernel_flops", C.c_double * ROM_NK), ("kernel_launches", C.c_longlong * ROM_NK),
+                ("n_uj_capped", C.c_int)]
 
 
 class rom_sequence_job(C.Structure):
@@ -116,6 +118,13 @@ def _load():
                                          P(rom_opts), vp, sz, P(vp), vp, P(rom_record),
                                          P(rom_stats), vp]),
         "rom_solve_sequences": (C.c_int, [P(rom_sequence_job), C.c_int]),
+        "rom_sequence_begin": (C.c_int, [vp, C.c_int, P(C.c_int64), P(C.c_double), C.c_int,
+                                         P(C.c_int64), P(C.c_double), C.c_int, vp, C.c_int,
+                                         P(rom_opts), vp, sz, P(vp), vp]),
+        "rom_sequence_point": (C.c_int, [vp, P(rom_mu), vp, P(rom_record)]),
+        "rom_sequence_basis": (C.c_int, [vp, P(vp)]),
+        "rom_sequence_stats": (C.c_int, [vp, P(rom_stats)]),
+        "rom_sequence_end": (C.c_int, [vp, P(vp), P(rom_stats)]),
         "rom_reduced_bytes": (C.c_int, [vp, P(sz)]),
         "rom_reduced_transfer": (C.c_int, [vp, P(rom_mu), vp, vp, vp, vp, vp, sz, vp]),
         "rom_reduced_jacobian_bytes": (C.c_int, [vp, P(sz)]),
@@ -292,6 +301,61 @@ def rom_solve_sequence(op: int, params: List[MuParams], src_idx, src_scale, det_
 
 
 
+class SequenceHandle:
+    """Host-side state of a streaming sequence (keeps the arrays the library reads)."""
+
+    def __init__(self, handle: int, n_rhs: int, keep):
+        self.handle = handle
+        self.n_rhs = n_rhs
+        self._keep = keep
+
+
+def rom_sequence_begin(op: int, K: int, src_idx, src_scale, det_idx, det_scale, U0, k_u: int,
+                       opts: rom_opts, workspace, stream=None) -> SequenceHandle:
+    si = np.ascontiguousarray(src_idx, dtype=np.int64)
+    ss = np.ascontiguousarray(src_scale, dtype=np.float64)
+    di = np.ascontiguousarray(det_idx, dtype=np.int64)
+    ds = np.ascontiguousarray(det_scale, dtype=np.float64)
+    h = C.c_void_p()
+    P = C.POINTER
+    _check(_lib.rom_sequence_begin(
+        op, int(K), si.ctypes.data_as(P(C.c_int64)), ss.ctypes.data_as(P(C.c_double)), si.size,
+        di.ctypes.data_as(P(C.c_int64)), ds.ctypes.data_as(P(C.c_double)), di.size, _ptr(U0),
+        int(k_u), C.byref(opts), _ptr(workspace), workspace.numel() * workspace.element_size(),
+        C.byref(h), _stream(stream)))
+    return SequenceHandle(h.value, si.size + di.size, (U0, opts, workspace))
+
+
+def rom_sequence_point(seq: SequenceHandle, p: MuParams, X_out=None):
+    """Returns (status, records of the point); raises on errors other than ROM_ENOCONV."""
+    mu = p.c_struct()
+    recs = (rom_record * seq.n_rhs)()
+    status = _check(_lib.rom_sequence_point(seq.handle, C.byref(mu), _ptr(X_out), recs),
+                    allow=(ROM_ENOCONV,))
+    return status, [{f: getattr(r, f) for f, _ in rom_record._fields_} for r in recs]
+
+
+def rom_sequence_basis(seq: SequenceHandle) -> int:
+    V = C.c_void_p()
+    _check(_lib.rom_sequence_basis(seq.handle, C.byref(V)))
+    return V.value
+
+
+def rom_sequence_stats(seq: SequenceHandle) -> rom_stats:
+    st = rom_stats()
+    _check(_lib.rom_sequence_stats(seq.handle, C.byref(st)))
+    return st
+
+
+def rom_sequence_end(seq: SequenceHandle):
+    """Returns (basis handle, stats)."""
+    basis = C.c_void_p()
+    st = rom_stats()
+    h, seq.handle = seq.handle, None
+    _check(_lib.rom_sequence_end(h, C.byref(basis), C.byref(st)))
+    return basis.value, st
+
+
 def rom_solve_sequences(jobs: List[dict]):
     """Run several sequences concurrently (one host thread and one stream each).  Each job
     is a dict of rom_solve_sequence arguments: op, params, src_idx, src_scale, det_idx,
@@ -452,7 +516,8 @@ def rom_basis_destroy(basis: int) -> None:
 
 def stats_dict(st: rom_stats) -> dict:
     d = {f: getattr(st, f) for f in ("m", "k_u", "n_solved", "n_kept", "n_dropped_trunc",
-                                     "n_dropped_cap", "n_nonconv", "total_its", "seconds")}
+                                     "n_dropped_cap", "n_nonconv", "total_its", "seconds",
+                                     "n_uj_capped")}
     d["kernels"] = {KERNEL_CLASSES[k]: {"ms": st.kernel_ms[k], "bytes": st.kernel_bytes[k],
                                         "flops": st.kernel_flops[k],
                                         "launches": int(st.kernel_launches[k])}

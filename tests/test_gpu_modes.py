@@ -119,3 +119,33 @@ def test_lowest_modes_errors(drv):
 def torch_from(a):
     import torch
     return torch.from_numpy(np.asarray(a, dtype=np.float64))
+
+
+def test_sequence_seeded_with_computed_modes(drv):
+    """U_0 of Algorithm 2 from rom_lowest_modes (the eigenvectors of A(p_0) the paper takes
+    offline) instead of the analytic smooth modes: the sequence passes the parity gates
+    against the oracle run on its own dense eigenvectors of A(p_0) (the two U_0 span the
+    same invariant subspace to the eigen-residual 1e-9 b), and both seeds' iteration
+    counts are reported."""
+    import torch
+    from oracle import sequence as oseq
+    from test_gpu_parity import _check_sequence
+    wl = ph.small(3, (13, 11, 10), n_src=4, n_det=4, K=3, D="lognormal")
+    orc = OracleProblem(wl)
+    lam_ref, V_ref = modes.lowest_modes(orc.A(0), 11)
+    assert lam_ref[10] - lam_ref[9] > 1e-3 * lam_ref[9]     # U_0 is well defined
+    prob = drv.problem_from_workload(wl)
+    pts = drv.points_from_workload(wl)
+    X0 = torch.from_numpy(np.ascontiguousarray(ph.smooth_modes(wl, 16).T))
+    U, lam, sweeps = prob.lowest_modes(pts[0], 10, X0, tol=1e-9, maxit=400)
+    analytic = prob.solve(pts, wl.tol, wl.trunc, keep_X=False)
+    prob.set_U0(U)
+    res = prob.solve(pts, wl.tol, wl.trunc)
+    ores = oseq.solve_sequence(orc.As, orc.mus, orc.B, V_ref[:, :10], wl.tol, wl.trunc)
+    _check_sequence(wl, orc, ores, res, prob, pts)
+    its = lambda r: sum(x["its"] for x in r.records)
+    print(f"\nU_0 from {sweeps} filter sweeps: iterations with eigenvectors {its(res)} "
+          f"(oracle {sum(r.its for r in ores.records)}), with the analytic modes {its(analytic)}")
+    res.close()
+    analytic.close()
+    prob.close()

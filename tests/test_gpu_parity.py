@@ -223,10 +223,15 @@ def test_kernel_timing_accounting(drv):
     assert torch.equal(res.X, res_t.X)
     k = res_t.stats["kernels"]
     its = res_t.stats["total_its"]
-    assert k["spmv"]["launches"] == its and k["dcg_update"]["launches"] == its
-    for name in ("spmv", "dcg_update", "dcg_dir", "gemvt", "gemvn", "gram", "outer"):
+    # one update per iteration; one operator step per iteration plus, per CG sweep, the one
+    # that found the sweep converged; a start and a finish per sweep
+    sweeps = sum(1 + r["restarts"] for r in res_t.records if r["solved"])
+    assert k["dcg_update"]["launches"] == its
+    assert k["dcg_op"]["launches"] == its + sweeps
+    assert k["dcg_ends"]["launches"] == 2 * sweeps
+    for name in ("dcg_op", "dcg_update", "dcg_ends", "gemvt", "gemvn", "gram", "outer"):
         assert k[name]["launches"] > 0 and k[name]["ms"] > 0 and k[name]["bytes"] > 0, name
-    assert res.stats["kernels"]["spmv"]["ms"] == 0.0      # no events when timing is off
+    assert res.stats["kernels"]["dcg_op"]["ms"] == 0.0      # no events when timing is off
 
 
 def test_invalid_inputs_rejected(drv):

@@ -4,7 +4,8 @@ cores) against the FP64 reference network.
 The reference runs on the same BF16-rounded parameters and inputs; the remaining
 differences come from the GPU storing every activation and gradient in BF16 (relative
 rounding 2^-9 per value, compounded over the layers).  Gates (relative L2 norms):
-output 2e-2, loss 2e-2, each layer's weight and bias gradient 1e-1.  Training on a fixed
+output 2e-2, loss 2e-2, each layer's weight and bias gradient 3e-2 (measured: 1.3e-2 at
+worst).  Training on a fixed
 batch must cut the loss by 4x in 60 Adam steps."""
 import numpy as np
 import pytest
@@ -79,7 +80,7 @@ def test_gradients_match_reference(case):
         for suf in (".w", ".b"):
             e = _rel(gg[name + suf], rg[name + suf])
             worst = max(worst, e)
-            assert e <= 1e-1, (name + suf, e)
+            assert e <= 3e-2, (name + suf, e)
     print(f"\nloss {loss:.6e} (reference {ref_loss:.6e}); worst gradient rel. error {worst:.2e}")
 
 

@@ -193,3 +193,28 @@ def test_group_one_is_the_sequential_order(slab2d_32):
     res = seq.solve_sequence(As, mus[:2], B, U0, wl.tol, wl.trunc, group=1)
     for a, b in zip(res.records, res1.records):
         assert (a.point, a.rhs, a.its, a.kept, a.m) == (b.point, b.rhs, b.its, b.kept, b.m)
+
+
+def test_uj_cap_bounds_recycle_spaces(slab2d_32):
+    """uj_cap: U_j never holds more than uj_cap columns (k_u + extra corrections), every
+    solution still meets tol, V is unchanged by the cap (the cap only limits the recycle
+    spaces), and uj_cap=None or a cap above every U_j reproduces the unbounded sequence."""
+    wl, As, mus, B, U0, res = slab2d_32
+    k_u = res.k_u
+    widest = max(len(w) for w in res.W_extra)
+    assert widest >= 2
+    same = seq.solve_sequence(As, mus, B, U0, wl.tol, wl.trunc, uj_cap=k_u + widest)
+    assert [r.its for r in same.records] == [r.its for r in res.records]
+    assert np.array_equal(same.Q, res.Q)
+    capped = seq.solve_sequence(As, mus, B, U0, wl.tol, wl.trunc, uj_cap=k_u + 1)
+    assert max(len(w) for w in capped.W_extra) == 1
+    for r in capped.records:
+        assert r.final_res <= wl.tol * (1 + 1e-9)
+    none = seq.solve_sequence(As, mus, B, U0, wl.tol, wl.trunc, uj_cap=k_u)
+    assert all(len(w) == 0 for w in none.W_extra)
+    # the recycle space only changes the inner solves, never what V must represent:
+    # every capped run's solutions lie in range(V)
+    for run in (capped, none):
+        for Xi in run.X:
+            P = run.Q @ (run.Q.T @ Xi)
+            assert np.linalg.norm(Xi - P) <= 1e-9 * np.linalg.norm(Xi)

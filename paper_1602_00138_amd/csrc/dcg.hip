@@ -49,6 +49,7 @@ __global__ void k_cg_setup(CGState* cg, CGVec* cv, CgSetup su, int nb) {
     c->alpha = 0.0;
     c->beta = 0.0;
     c->cGc = 0.0;
+    c->gcur = 0.0;
   }
   for (int k = threadIdx.x; k < nb * NJ_MAX; k += blockDim.x) cv[k / NJ_MAX].e[k % NJ_MAX] = 0.0;
 }
@@ -212,16 +213,30 @@ __device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[2
   *reinterpret_cast<typename Vec2<T>::type*>(p + i) = typename Vec2<T>::type{v[0], v[1]};
 }
 
-// How the operator step sums its 2 NJT vector dot products.  Below 64 columns every thread
-// keeps running sums in registers over its z planes and the block reduces them once at the
-// end.  At 64 columns (128 sums) each plane's values are reduced over the wave at once and
+// How the operator step sums its 2 NJT vector dot products.  Up to 8 FP64 or 16 FP32
+// columns every thread keeps running sums in registers over its z planes and the block
+// reduces them once at the end.  Wider (up to 128 sums) each plane's values are reduced
+// over the wave at once and
 // accumulated in LDS by the wave's first lane (every lane of the block then walks every
 // plane, lanes past the plane with zero values, so the wave reductions see full waves).
-// The rows of AU stay in registers between their two uses where they fit.
+// pre: the rows of AU are loaded with the rest of a plane (before the first plane's
+// prologue reductions, so their latency hides behind them) where they fit in registers.
 template <typename T, int NJT>
 struct OpMode {
-  static constexpr bool imm = NJT >= 64;
-  static constexpr bool keep = NJT * sizeof(T) <= 128;
+  static constexpr bool imm = NJT * sizeof(T) >= 128;
+  static constexpr bool pre = NJT * sizeof(T) <= 128;
+  // without pre, the rows are kept between their two uses where they fit, else reloaded
+  static constexpr bool keep = !imm && !pre && NJT * sizeof(T) <= 128;
+};
+
+// Everything one z plane of the operator step reads for NP consecutive x-nodes at i: the
+// next plane of q (the current and previous ones are carried), the lateral neighbours of q,
+// the diagonal, the face coefficients (D field), s and, with pre, the rows of AU.
+template <typename T, bool VAR, int NP, int NJT, bool PRE>
+struct OpPlane {
+  T xp[NP], xl, xr, yd[NP], yu[NP], d[NP], s[NP];
+  T fxl, fx[NP], fyd[NP], fyu[NP], fp[NP];
+  T a[PRE ? NJT : 1][NP];
 };
 
 // The operator step of member y = blockIdx.z over the z planes [blockIdx.y zc, + zc) of
@@ -239,6 +254,9 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
                                                    int64_t psstride, const T* __restrict__ pu0,
                                                    int Pu, int64_t pustride, T* __restrict__ po0,
                                                    int64_t postride) {
+  constexpr bool IMM = OpMode<T, NJT>::imm;
+  constexpr bool PRE = OpMode<T, NJT>::pre;
+  constexpr bool KEEP = OpMode<T, NJT>::keep;
   const int y = blockIdx.z;
   CGState* cg = cgs + y;
   if (cg->done) return;
@@ -250,6 +268,61 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   const double* __restrict__ Ginv = Ginv0 + y * gstride;
   const int nj = cg->nj;
   const int k = cg->its;
+
+  // ---- this thread's nodes, and the first plane's loads (issued before the reductions)
+  const T *Fx, *Fy, *Fz;
+  walk_faces(S, T(0), Fx, Fy, Fz);
+  const int nxy = S.nx * S.ny;
+  const int npos = NP == 2 ? (S.nx / 2) * S.ny : nxy;
+  const int qpos = blockIdx.x * OP_BS + threadIdx.x;
+  const bool act = qpos < npos;
+  const int qq = act ? qpos : 0;   // lanes past the plane read position 0 (zero weight)
+  const int ix = NP == 2 ? 2 * (qq % (S.nx / 2)) : qq % S.nx;
+  const int iy = NP == 2 ? qq / (S.nx / 2) : qq / S.nx;
+  const bool hl = ix > 0, hr = ix + NP < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
+  const int z0 = blockIdx.y * zc;
+  const int z1 = min(z0 + zc, S.nz);
+  const bool walk = z0 < z1 && (act || IMM);
+  int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
+  auto ldv = [&](const T* p, int64_t j, T (&v)[NP]) { ldn(p, j, v); };
+  auto zero = [](T (&v)[NP]) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) v[u] = T(0);
+  };
+  OpPlane<T, VAR, NP, NJT, PRE> P;
+  T xm[NP], xc[NP], fm[NP];
+  auto load_plane = [&](int64_t j, int z) {
+    if (z < S.nz - 1) ldv(q, j + nxy, P.xp); else zero(P.xp);
+    P.xl = hl ? q[j - 1] : T(0);
+    P.xr = hr ? q[j + NP] : T(0);
+    if (hd) ldv(q, j - S.nx, P.yd); else zero(P.yd);
+    if (hu) ldv(q, j + S.nx, P.yu); else zero(P.yu);
+    ldv(diag, j, P.d);
+    if (VAR) {
+      P.fxl = hl ? Fx[j - 1] : T(0);
+      ldv(Fx, j, P.fx);
+      if (hd) ldv(Fy, j - S.nx, P.fyd); else zero(P.fyd);
+      ldv(Fy, j, P.fyu);
+      if (S.dim == 3) ldv(Fz, j, P.fp); else zero(P.fp);
+    }
+    if (act) ldv(s, j, P.s); else zero(P.s);
+    if (PRE) {
+#pragma unroll
+      for (int c = 0; c < NJT; ++c)
+        if (c < nj) {
+          if (act) ldv(AW + c * ld, j, P.a[PRE ? c : 0]); else zero(P.a[PRE ? c : 0]);
+        }
+    }
+  };
+  if (walk) {
+    if (z0 > 0) ldv(q, i - nxy, xm); else zero(xm);
+    if (VAR && z0 > 0) ldv(Fz, i - nxy, fm); else zero(fm);
+    ldv(q, i, xc);
+    load_plane(i, z0);
+  }
+
+  // ---- gamma_k = s_k^T s_k and t = (AU)^T s_k: from the start's partials at the first step,
+  // else gamma from the update's partials and t by the recurrence
   const bool first = k == 0;
   const double tol2 = cg->tol2;
   const int maxit = cg->maxit;
@@ -257,9 +330,6 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   constexpr bool GPF = GramPf<NJT>::value;
   double gr[GPF ? NJT : 1];
   gram_row<NJT, GPF>(Ginv, nj, gr);
-
-  // gamma_k = s_k^T s_k and t = (AU)^T s_k: from the start's partials at the first step,
-  // else gamma from the update's partials and t by the recurrence
   __shared__ T tot[NJT + 1];
   __shared__ double tv[NJ_MAX];
   double gam;
@@ -268,15 +338,16 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     gam = (double)tot[NJT];
     if (threadIdx.x < nj) tv[threadIdx.x] = (double)tot[threadIdx.x];
   } else {
+    if (threadIdx.x < nj) tv[threadIdx.x] = cv->ts[threadIdx.x] - alpha * cv->tw[threadIdx.x];
     sum_partials_t<1, OP_BS>(pu0 + y * pustride, Pu, tot);
     gam = (double)tot[0];
-    if (threadIdx.x < nj) tv[threadIdx.x] = cv->ts[threadIdx.x] - alpha * cv->tw[threadIdx.x];
   }
   const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
   const bool nonfinite = !isfinite(gam);
   const bool stop = nonfinite || gam <= tol2 || k >= maxit;
   if (lead && threadIdx.x == 0) {
     cg->gamma[k & 1] = gam;
+    cg->gcur = gam;
     cg->kcur = k;
     if (nonfinite) cg->flag = 2;
     if (stop) cg->done = 1;
@@ -311,8 +382,7 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     if (j == 0) cg->cGc = v;
   }
 
-  constexpr bool IMM = OpMode<T, NJT>::imm;
-  constexpr bool KEEP = OpMode<T, NJT>::keep;
+  // ---- the planes
   constexpr int RV = 4 + (IMM ? 0 : 2 * NJT);
   T acc[RV];
 #pragma unroll
@@ -332,84 +402,93 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
       acc[4 + r] += v;
     }
   };
-  const int npos = NP == 2 ? (S.nx / 2) * S.ny : S.nx * S.ny;
-  const int qpos = blockIdx.x * OP_BS + threadIdx.x;
-  const bool act = qpos < npos;
-  const int z0 = blockIdx.y * zc;
-  const int z1 = min(z0 + zc, S.nz);
-  auto body = [&](int64_t i, const T (&av0)[NP], const T (&xq0)[NP]) {
-    T av[NP], xq[NP], sv[NP], au[NP], wv[NP];
+  const T cx = (T)S.cx, cy = (T)S.cy, cz = (T)S.cz;
+  const T m = act ? T(1) : T(0);
+  for (int z = z0; walk && z < z1; ++z, i += nxy) {
+    // (A q) at the NP nodes
+    T av[NP], xq[NP];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      av[p] = act ? av0[p] : T(0);
-      xq[p] = act ? xq0[p] : T(0);
-      au[p] = T(0);
+    for (int u = 0; u < NP; ++u) {
+      const T left = u == 0 ? P.xl : xc[u - 1];
+      const T right = u == NP - 1 ? P.xr : xc[u + 1];
+      T v = P.d[u] * xc[u];
+      if (!VAR) {
+        v -= cx * (left + right) + cy * (P.yd[u] + P.yu[u]) + cz * (xm[u] + P.xp[u]);
+      } else {
+        const T fl = u == 0 ? P.fxl : P.fx[u - 1];
+        v -= fl * left + P.fx[u] * right;
+        v -= P.fyd[u] * P.yd[u] + P.fyu[u] * P.yu[u];
+        if (S.dim == 3) v -= fm[u] * xm[u] + P.fp[u] * P.xp[u];
+      }
+      av[u] = m * v;
+      xq[u] = m * xc[u];
     }
-    if (act) ldn(s, i, sv);
-    else
-#pragma unroll
-      for (int p = 0; p < NP; ++p) sv[p] = T(0);
-    T kept[KEEP ? NJT : 1][NP];
+    // pass 1 over the rows of AU: AU c, (AU)^T s
+    T au[NP], wv[NP];
+    zero(au);
+    T keep[KEEP ? NJT : 1][NP];
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
       if (c < nj) {
         T a[NP];
-        if (act) ldn(AW + c * ld, i, a);
-        else
+        if (PRE) {
 #pragma unroll
-          for (int p = 0; p < NP; ++p) a[p] = T(0);
+          for (int u = 0; u < NP; ++u) a[u] = P.a[PRE ? c : 0][u];
+        } else if (act) {
+          ldv(AW + c * ld, i, a);
+        } else {
+          zero(a);
+        }
+        if (KEEP) {
+#pragma unroll
+          for (int u = 0; u < NP; ++u) keep[KEEP ? c : 0][u] = a[u];
+        }
         T t = T(0);
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (KEEP) kept[KEEP ? c : 0][p] = a[p];
-          au[p] += a[p] * cs[c];
-          t += a[p] * sv[p];
+        for (int u = 0; u < NP; ++u) {
+          au[u] += a[u] * cs[c];
+          t += a[u] * P.s[u];
         }
         vadd(NJT + c, t);
       }
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      wv[p] = av[p] - au[p];
-      acc[0] += xq[p] * wv[p];
-      acc[1] += xq[p] * au[p];
-      acc[2] += sv[p] * wv[p];
-      acc[3] += wv[p] * wv[p];
+    for (int u = 0; u < NP; ++u) {
+      wv[u] = av[u] - au[u];
+      acc[0] += xq[u] * wv[u];
+      acc[1] += xq[u] * au[u];
+      acc[2] += P.s[u] * wv[u];
+      acc[3] += wv[u] * wv[u];
     }
     if (act) stn(w, i, wv);
+    // pass 2: (AU)^T w
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
       if (c < nj) {
         T a[NP];
-        if (KEEP) {
+        if (PRE) {
 #pragma unroll
-          for (int p = 0; p < NP; ++p) a[p] = kept[KEEP ? c : 0][p];
+          for (int u = 0; u < NP; ++u) a[u] = P.a[PRE ? c : 0][u];
+        } else if (KEEP) {
+#pragma unroll
+          for (int u = 0; u < NP; ++u) a[u] = keep[KEEP ? c : 0][u];
         } else if (act) {
-          ldn(AW + c * ld, i, a);
+          ldv(AW + c * ld, i, a);
         } else {
-#pragma unroll
-          for (int p = 0; p < NP; ++p) a[p] = T(0);
+          zero(a);
         }
         T t = T(0);
 #pragma unroll
-        for (int p = 0; p < NP; ++p) t += a[p] * wv[p];
+        for (int u = 0; u < NP; ++u) t += a[u] * wv[u];
         vadd(c, t);
       }
-  };
-  // with wave reductions every lane walks (a lane past the plane reads position 0)
-  if (z0 < z1 && (act || IMM)) {
-    const int qq = act ? qpos : 0;
-    if constexpr (NP == 2)
-      stencil_walk2t<T, VAR>(S, diag, q, qq, z0, z1, [&](int64_t i, T v0, T v1, T x0, T x1) {
-        const T av[2] = {v0, v1};
-        const T xq[2] = {x0, x1};
-        body(i, av, xq);
-      });
-    else
-      stencil_walk1t<T, VAR>(S, diag, q, qq, z0, z1, [&](int64_t i, T v0, T x0) {
-        const T av[1] = {v0};
-        const T xq[1] = {x0};
-        body(i, av, xq);
-      });
+    // next plane
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      xm[u] = xc[u];
+      xc[u] = P.xp[u];
+      if (VAR) fm[u] = P.fp[u];
+    }
+    if (z + 1 < z1) load_plane(i + nxy, z + 1);
   }
   T* __restrict__ po = po0 + y * postride;
   const int P1 = gridDim.x * gridDim.y;
@@ -456,7 +535,7 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const 
   const T* __restrict__ po = po0 + y * postride;
   const int nj = cg->nj;
   const int k = cg->kcur;
-  const double gam = cg->gamma[k & 1], cGc = cg->cGc;
+  const double gam = cg->gcur, cGc = cg->cGc;
   constexpr int R = RPT;
   constexpr int64_t CH = (int64_t)CG_BS * R;
   int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
@@ -473,22 +552,43 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const 
     }
   };
   load(base);
+  // wave w sums the operator step's scalar w (one of q^T w, q^T (AU c), s^T w, w^T w) and,
+  // in the same loop, the vector total this block owns for that wave (value b + P w, if
+  // any, of the 2 nj totals), so that both sets of loads are in flight together
   __shared__ T tot[4];
-  sum_partials_t<4, CG_BS>(po, P1, tot);
-  // the vector totals this block owns, one wave reduction each
   {
     const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
-    for (int v = blockIdx.x + gridDim.x * wid; v < 2 * nj; v += gridDim.x * (CG_BS / WAVE)) {
-      const int r = v < nj ? 4 + v : 4 + njt + (v - nj);
-      T a = T(0);
-      for (int b = lane; b < P1; b += WAVE) a += po[(size_t)r * P1 + b];
-      a = wave_sum(a);
+    const int v = blockIdx.x + gridDim.x * wid;
+    const bool own = v < 2 * nj;
+    const int r = v < nj ? 4 + v : 4 + njt + (v - nj);
+    T a = T(0), o = T(0);
+#pragma unroll 4
+    for (int b = lane; b < P1; b += WAVE) {
+      a += po[(size_t)wid * P1 + b];
+      if (own) o += po[(size_t)r * P1 + b];
+    }
+    a = wave_sum(a);
+    if (lane == 0) tot[wid] = a;
+    if (own) {
+      o = wave_sum(o);
       if (lane == 0) {
-        if (v < nj) cv->tw[v] = (double)a;
-        else cv->ts[v - nj] = (double)a;
+        if (v < nj) cv->tw[v] = (double)o;
+        else cv->ts[v - nj] = (double)o;
+      }
+    }
+    // totals past the first P * 4 (when 2 nj exceeds the update's waves)
+    for (int u = v + gridDim.x * (CG_BS / WAVE); u < 2 * nj; u += gridDim.x * (CG_BS / WAVE)) {
+      const int ru = u < nj ? 4 + u : 4 + njt + (u - nj);
+      T e = T(0);
+      for (int b = lane; b < P1; b += WAVE) e += po[(size_t)ru * P1 + b];
+      e = wave_sum(e);
+      if (lane == 0) {
+        if (u < nj) cv->tw[u] = (double)e;
+        else cv->ts[u - nj] = (double)e;
       }
     }
   }
+  __syncthreads();
   const double qw = tot[0], qau = tot[1], sw = tot[2], ww = tot[3];
   const double pw = qw - qau + cGc;
   if (!(pw > 0.0) || !isfinite(pw)) {

@@ -15,6 +15,7 @@ struct CGState {
   double rscale;       // the right-hand side is read as rscale * r
   double alpha, beta;  // of the latest update
   double cGc;          // c^T (U^T A U) c of the latest direction (p = q - U c)
+  double gcur;         // gamma of the latest operator step (read by the update)
   double t[NJ_MAX];    // U_j^T r (unscaled) for the start
   int nj;              // columns of U_j
   int its;             // updates done: written by the update, read by the operator step

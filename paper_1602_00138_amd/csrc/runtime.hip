@@ -1459,20 +1459,36 @@ class Sequencer {
     int flag[G_MAX] = {};
   };
 
-  // Launch shape of the CG update kernel, 2 P + narrow: P blocks per member, narrow for
-  // the variant with half the rows per thread (the operator step always runs on the
-  // stencil shape).  Fixed shape: the full grid for one member, split among the members of
-  // a batch (narrow for batches).  With opts.tune the first batch of each (arithmetic,
-  // batch size, U_j width class, grid size) in the process times every power-of-two P
-  // with both variants on its own data (three rounds of 8 CG steps each after a warm-up
-  // round, from its real start; the solve then restarts) and keeps the fastest (by its
-  // best round) for the rest of the process.
+  // Launch shape of the CG step kernels, encoded as (P << 4) | (narrow << 3) | op: P blocks
+  // per member of the update kernel, narrow for its variant with half the rows per thread,
+  // op the operator step's target block count per member (op_target; the fewer blocks, the
+  // more z planes per thread and the fewer partial rows to reduce).  Fixed shape: the full
+  // grid for one member, split among the members of a batch (narrow for batches).  With
+  // opts.tune the first batch of each (arithmetic, batch size, U_j width class, grid size) in
+  // the process times every power-of-two P with both variants and every operator target on
+  // its own data (three rounds of 8 CG steps each after a warm-up round, from its real
+  // start; the solve then restarts) and keeps the fastest (by its best round) for the rest
+  // of the process.
+  static int shape_code(int P, int nr, int op) { return (P << 4) | (nr << 3) | op; }
+  static int shape_P(int code) { return code >> 4; }
+  static int shape_nr(int code) { return (code >> 3) & 1; }
+  // op 0: 1024 blocks per member divided among the members (at least 64); 1, 2, 3: 1024,
+  // 256, 64 blocks per member
+  static int op_target(int code, int nb) {
+    const int op = code & 7;
+    return op == 0 ? std::max(64, 1024 / nb) : op == 1 ? 1024 : op == 2 ? 256 : 64;
+  }
+  template <typename T, typename Bufs>
+  StencilShape op_shape(const Bufs& b, int code, int nb) const {
+    return cg_apply_shape<T>(S_, op_target(code, nb), b.diag, b.q, b.w, ld_, b.AW);
+  }
+
   template <typename T, typename Bufs>
   int cg_shape(const Batch& bt, const Bufs& b, const double* rhs, T* dvec, int64_t wstride,
                int64_t gstride, int njmax) {
     const int nb = bt.nb;
     const int Pmax = dcg_blocks(n_);
-    const int fixed = 2 * std::max(std::min(Pmax, 8), Pmax / nb) + (nb > 1 ? 1 : 0);
+    const int fixed = shape_code(std::max(std::min(Pmax, 8), Pmax / nb), nb > 1 ? 1 : 0, 0);
     if (!tune_) return fixed;
     int dev = 0;
     ROM_HIP(hipGetDevice(&dev));
@@ -1483,10 +1499,9 @@ class Sequencer {
       if (it != tune_map().end()) return it->second;
     }
     std::vector<int> cand;
-    for (int P = Pmax; P >= 8; P /= 2) {
-      cand.push_back(2 * P);
-      cand.push_back(2 * P + 1);
-    }
+    for (int P = Pmax; P >= 8; P /= 2)
+      for (int nr = 0; nr < 2; ++nr)
+        for (int op = 1; op <= 3; ++op) cand.push_back(shape_code(P, nr, op));
     int best = fixed;
     if (cand.size() > 1) {
       CGState* cg = ctrl_->cg;
@@ -1499,7 +1514,6 @@ class Sequencer {
         su.nj[y] = bt.nj[y];
         su.active[y] = bt.active[y];
       }
-      const StencilShape sh = cg_apply_shape<T>(S_, 1024, b.diag, b.q, b.w, ld_, b.AW);
       launch_cg_setup(cg, cgv_, su, nb, st_);
       launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec,
                           b.s, b.q, ld_, cg, b.ps, p2s_, nb, Pmax, st_);
@@ -1520,7 +1534,8 @@ class Sequencer {
       for (int rep = 0; rep < 4; ++rep) {
         for (size_t ci = 0; ci < cand.size(); ++ci) {
           const int shape = cand[ci];
-          const int P = shape >> 1, nr = shape & 1;
+          const int P = shape_P(shape), nr = shape_nr(shape);
+          const StencilShape sh = op_shape<T>(b, shape, nb);
           ROM_HIP(hipEventRecord(e0, st_));
           for (int step = 0; step < 8; ++step) {
             launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax,
@@ -1558,7 +1573,7 @@ class Sequencer {
                              int64_t wstride, int64_t gstride, T* dvec, const StencilShape& sh) {
     const GraphKey key{(int)sizeof(T), nb, shared ? 1 : 0, njt_of(njmax), shape,
                        (const void*)dvec};
-    const int P = shape >> 1, nr = shape & 1;
+    const int P = shape_P(shape), nr = shape_nr(shape);
     auto it = graphs_.find(key);
     if (it != graphs_.end()) return it->second;
     CGState* cg = ctrl_->cg;
@@ -1598,9 +1613,6 @@ class Sequencer {
     bufs(b);
     const int nb = bt.nb;
     CGState* cg = ctrl_->cg;
-    // the operator step's shape (two x-nodes per thread where the layout allows); its block
-    // count is the number of the operator step's partial rows per member
-    const StencilShape sh = cg_apply_shape<T>(S_, 1024, b.diag, b.q, b.w, ld_, b.AW);
     const int64_t wstride = bt.shared ? 0 : ld_ * NJ_MAX;
     const int64_t gstride = bt.shared ? 0 : (int64_t)NJ_MAX * NJ_MAX;
     CgSetup su;
@@ -1620,7 +1632,10 @@ class Sequencer {
     }
     if (nact == 0) return;
     const int shape = cg_shape<T>(bt, b, rhs, dvec, wstride, gstride, njmax);
-    const int P = shape >> 1, nr = shape & 1;
+    const int P = shape_P(shape), nr = shape_nr(shape);
+    // the operator step's shape (two x-nodes per thread where the layout allows); its block
+    // count is the number of the operator step's partial rows per member
+    const StencilShape sh = op_shape<T>(b, shape, nb);
     launch_cg_setup(cg, cgv_, su, nb, st_);
     // U_j^T r_j for the start
     if (njmax > 0) {

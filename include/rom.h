@@ -133,6 +133,10 @@ typedef struct {
                        point (not V); a vector with less than 1e-6 of its norm left is
                        dropped. */
   int n_recycle;    /* 1..16 when recycle is set */
+  int cg_step;      /* launches per CG step: 0 chosen by the tuner when tune is set (else 1),
+                       1 two (operator step, update), 2 one (the update of each step folded
+                       into the next operator step; same recurrences, s, q and w then kept
+                       in two buffers by step parity) */
 } rom_opts;
 
 /* One record per (point i, right-hand side j), in solve order. */
@@ -160,7 +164,8 @@ typedef struct {
 #define ROM_K_GRAM 5        /* V^T diag(w) V (FP64 MFMA) */
 #define ROM_K_OUTER 6       /* outer projection x0 = V c (one per right-hand side) */
 #define ROM_K_OTHER 7
-#define ROM_NK 8
+#define ROM_K_DCG_STEP 8    /* one-launch CG step: update of step k-1 and operator step k */
+#define ROM_NK 9
 
 typedef struct {
   int m;                 /* final basis size */

@@ -50,6 +50,8 @@ __global__ void k_cg_setup(CGState* cg, CGVec* cv, CgSetup su, int nb) {
     c->beta = 0.0;
     c->cGc = 0.0;
     c->gcur = 0.0;
+    c->its2[0] = c->its2[1] = 0;
+    c->cGc2[0] = c->cGc2[1] = 0.0;
   }
   for (int k = threadIdx.x; k < nb * NJ_MAX; k += blockDim.x) cv[k / NJ_MAX].e[k % NJ_MAX] = 0.0;
 }
@@ -508,6 +510,404 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   }
 }
 
+// Totals of R transposed partial rows of P blocks, every row's loads issued before any
+// reduction: wave w sums rows w, w + NW, ... (NW waves), each lane a strided share of the P
+// blocks, so a block waits one memory latency for all R totals instead of one per row.
+// tot[] (shared) is visible to every thread on return.
+template <int R, int BS, typename T>
+__device__ __forceinline__ void sum_rows_wide(const T* __restrict__ partials, int P, T* tot) {
+  constexpr int NW = BS / WAVE;
+  constexpr int RPW = (R + NW - 1) / NW;
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  T a[RPW];
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) a[k] = T(0);
+  for (int b = lane; b < P; b += WAVE) {
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int r = wid + k * NW;
+      if (r < R) a[k] += partials[(size_t)r * P + b];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int r = wid + k * NW;
+    const T v = wave_sum(a[k]);
+    if (lane == 0 && r < R) tot[r] = v;
+  }
+  __syncthreads();
+}
+
+// One whole step in one launch (member y = blockIdx.z), for latency-bound sizes: launch j
+// applies update j-1 at this block's nodes and then operator step j.  s, q and w are kept
+// in two buffers by step parity (par = j & 1, at + par pstride): launch j reads s_{j-1},
+// q_{j-1}, w_{j-1} from the other buffer and writes s_j, q_j, w_j; q_j at a node's
+// neighbours is formed there from s_{j-1}, w_{j-1}, q_{j-1}
+// (q_j = s_{j-1} - alpha w_{j-1} + beta q_{j-1}), so no launch waits for another's update.
+// Every block sums the previous launch's partial rows itself (5 scalars q^T w, q^T (AU c),
+// s^T w, w^T w, s^T s and the 2 NJT totals (AU)^T w, (AU)^T s): alpha, beta, c_j and the
+// stopping test on the exact s_{j-1}^T s_{j-1} follow.  The scalars the lead block writes
+// for the next launch (updates done, c, c^T G c, gamma) sit in parity slots, so no block
+// reads a value another block of the same launch rewrites.  first: the launch right after
+// the start (par 0): no update, q_0 = s_0 read directly, gamma_0 and (AU)^T s_0 from the
+// start's partials.  Pprev: the previous launch's block count (its partial rows).
+template <typename T, bool VAR, int NP, int NJT>
+__global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restrict__ diag,
+                                                     T* __restrict__ sb, T* __restrict__ qb,
+                                                     T* __restrict__ wb, int64_t pstride,
+                                                     int64_t vstride, T* __restrict__ g0,
+                                                     const T* __restrict__ AW0, int64_t wstride,
+                                                     int64_t ld, const double* __restrict__ Ginv0,
+                                                     const double* __restrict__ Gm0,
+                                                     int64_t gstride, int zc, CGState* cgs,
+                                                     CGVec* cvs, const T* __restrict__ ps0, int Ps,
+                                                     int64_t psstride, T* __restrict__ po0,
+                                                     int64_t postride, int64_t pohalf, int Pprev,
+                                                     int par, int first) {
+  constexpr bool IMM = OpMode<T, NJT>::imm;
+  constexpr bool PRE = OpMode<T, NJT>::pre;
+  constexpr bool KEEP = OpMode<T, NJT>::keep;
+  constexpr int RS = 5;                      // scalar partials
+  const int y = blockIdx.z;
+  CGState* cg = cgs + y;
+  if (cg->done) return;
+  CGVec* cv = cvs + y;
+  const int rp = first ? 0 : 1 - par;        // parity of the buffers read
+  const T* __restrict__ sr = sb + rp * pstride + y * vstride;
+  const T* __restrict__ qr = qb + rp * pstride + y * vstride;
+  // step 0 reads no w: its loads then read s (finite values, weight 0), so that no load
+  // depends on the step
+  const T* __restrict__ wr = first ? sr : wb + rp * pstride + y * vstride;
+  T* __restrict__ sw_ = sb + par * pstride + y * vstride;
+  T* __restrict__ qw_ = qb + par * pstride + y * vstride;
+  T* __restrict__ ww_ = wb + par * pstride + y * vstride;
+  T* __restrict__ g = g0 + y * vstride;
+  const T* __restrict__ AW = AW0 + y * wstride;
+  const double* __restrict__ Ginv = Ginv0 + y * gstride;
+  const int nj = cg->nj;
+
+  // ---- this thread's nodes, and the first plane's raw loads (before the reductions)
+  const T *Fx, *Fy, *Fz;
+  walk_faces(S, T(0), Fx, Fy, Fz);
+  const int nxy = S.nx * S.ny;
+  const int npos = NP == 2 ? (S.nx / 2) * S.ny : nxy;
+  const int qpos = blockIdx.x * OP_BS + threadIdx.x;
+  const bool act = qpos < npos;
+  const int qq = act ? qpos : 0;
+  const int ix = NP == 2 ? 2 * (qq % (S.nx / 2)) : qq % S.nx;
+  const int iy = NP == 2 ? qq / (S.nx / 2) : qq / S.nx;
+  const bool hl = ix > 0, hr = ix + NP < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
+  const int z0 = blockIdx.y * zc;
+  const int z1 = min(z0 + zc, S.nz);
+  const bool walk = z0 < z1 && (act || IMM);
+  int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
+  auto ldv = [&] __attribute__((always_inline)) (const T* p, int64_t j, T (&v)[NP]) { ldn(p, j, v); };
+  auto zero = [] __attribute__((always_inline)) (T (&v)[NP]) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) v[u] = T(0);
+  };
+  // raw (s, w, q) of the previous step at a position: NP values or one scalar
+  struct Tri {
+    T s[NP], w[NP], q[NP];
+  };
+  struct Tri1 {
+    T s, w, q;
+  };
+  auto ld3 = [&] __attribute__((always_inline)) (int64_t j, Tri& r) {
+    ldv(sr, j, r.s);
+    ldv(qr, j, r.q);
+    ldv(wr, j, r.w);
+  };
+  auto z3 = [&] __attribute__((always_inline)) (Tri& r) {
+    zero(r.s);
+    zero(r.w);
+    zero(r.q);
+  };
+  struct Plane {
+    Tri own, xp, yd, yu;
+    Tri1 xl, xr;
+    T gv[NP], d[NP];
+    T fxl, fx[NP], fyd[NP], fyu[NP], fp[NP];
+    T a[PRE ? NJT : 1][NP];
+    T mxp;   // 0 on the top plane (whose upper neighbours are read from the plane itself)
+  } P;
+  Tri xm3;           // raw values of the plane below the chunk (its q_j is formed later)
+  T fm[NP];
+  auto load_plane = [&] __attribute__((always_inline)) (int64_t j, int z) {
+    if (act) ld3(j, P.own); else z3(P.own);
+    if (act) ldv(g, j, P.gv); else zero(P.gv);
+    const bool zin = z < S.nz - 1;
+    ld3(j + (zin ? nxy : 0), P.xp);
+    P.mxp = zin ? T(1) : T(0);
+    P.xl.s = hl ? sr[j - 1] : T(0);
+    P.xl.q = hl ? qr[j - 1] : T(0);
+    P.xl.w = hl ? wr[j - 1] : T(0);
+    P.xr.s = hr ? sr[j + NP] : T(0);
+    P.xr.q = hr ? qr[j + NP] : T(0);
+    P.xr.w = hr ? wr[j + NP] : T(0);
+    if (hd) ld3(j - S.nx, P.yd); else z3(P.yd);
+    if (hu) ld3(j + S.nx, P.yu); else z3(P.yu);
+    ldv(diag, j, P.d);
+    if (VAR) {
+      P.fxl = hl ? Fx[j - 1] : T(0);
+      ldv(Fx, j, P.fx);
+      if (hd) ldv(Fy, j - S.nx, P.fyd); else zero(P.fyd);
+      ldv(Fy, j, P.fyu);
+      if (S.dim == 3) ldv(Fz, j, P.fp); else zero(P.fp);
+    }
+    if (PRE) {
+#pragma unroll
+      for (int c = 0; c < NJT; ++c)
+        if (c < nj) {
+          if (act) ldv(AW + c * ld, j, P.a[PRE ? c : 0]); else zero(P.a[PRE ? c : 0]);
+        }
+    }
+  };
+  if (walk) {
+    if (z0 > 0) ld3(i - nxy, xm3); else z3(xm3);
+    if (VAR && z0 > 0) ldv(Fz, i - nxy, fm); else zero(fm);
+    load_plane(i, z0);
+  }
+
+  // ---- the previous launch's (or the start's) sums
+  const double tol2 = cg->tol2;
+  const int maxit = cg->maxit;
+  const int done_its = first ? 0 : cg->its2[rp];
+  const double cGc_prev = first ? 0.0 : cg->cGc2[rp];
+  constexpr bool GPF = GramPf<NJT>::value;
+  double gr[GPF ? NJT : 1];
+  gram_row<NJT, GPF>(Ginv, nj, gr);
+  __shared__ T tot[RS + 2 * NJT];
+  __shared__ double tv[NJ_MAX];
+  __shared__ double cprev[NJ_MAX];
+  if (threadIdx.x < NJT) cprev[threadIdx.x] = first ? 0.0 : cv->c[rp][threadIdx.x];
+  double gam, al = 0.0, be = 0.0, pw = 1.0;
+  if (first) {
+    sum_rows_wide<NJT + 1, OP_BS>(ps0 + y * psstride, Ps, tot);
+    gam = (double)tot[NJT];
+    if (threadIdx.x < NJT) tv[threadIdx.x] = (double)tot[threadIdx.x];
+  } else {
+    sum_rows_wide<RS + 2 * NJT, OP_BS>(po0 + y * postride + rp * pohalf, Pprev, tot);
+    gam = (double)tot[4];
+    pw = (double)tot[0] - (double)tot[1] + cGc_prev;
+    al = gam / pw;
+    double gnext = gam - 2.0 * al * (double)tot[2] + al * al * (double)tot[3];
+    if (!(gnext > 0.0)) gnext = 0.0;
+    be = gnext / gam;
+    if (threadIdx.x < NJT)
+      tv[threadIdx.x] = (double)tot[RS + NJT + threadIdx.x] - al * (double)tot[RS + threadIdx.x];
+  }
+  const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+  const bool nonfinite = !isfinite(gam);
+  const bool conv = gam <= tol2;
+  const bool hit = done_its >= maxit;
+  const bool breakdown = !first && !nonfinite && !conv && !hit && (!(pw > 0.0) || !isfinite(pw));
+  const bool stop = nonfinite || conv || hit || breakdown;
+  if (lead && threadIdx.x == 0) {
+    cg->gamma[done_its & 1] = gam;   // s^T s after done_its updates, as the two-launch step
+    cg->gcur = gam;
+    if (nonfinite) cg->flag = 2;
+    if (breakdown) cg->flag = isfinite(pw) ? 1 : 2;
+    if (stop) {
+      cg->its = done_its;
+      cg->done = 1;
+    }
+  }
+  if (stop) return;
+  __syncthreads();
+  // c_j = G^{-1} t + beta c_{j-1}
+  __shared__ T cs[NJ_MAX];
+  __shared__ double cd[NJ_MAX];
+  {
+    const int j = threadIdx.x;
+    double cj = gram_row_apply<NJT, GPF>(Ginv, gr, nj, tv, 1.0);
+    if (j < nj) {
+      cj += be * cprev[j];
+      cs[j] = (T)cj;
+      cd[j] = cj;
+      if (lead) {
+        cv->c[par][j] = cj;
+        if (!first) cv->e[j] += al * cprev[j];
+      }
+    }
+  }
+  __syncthreads();
+  if (lead && threadIdx.x < WAVE) {
+    const double* __restrict__ Gm = Gm0 + y * gstride;
+    const int j = threadIdx.x;
+    double v = 0.0;
+    if (j < nj) {
+      double gc = 0.0;
+      for (int c = 0; c < nj; ++c) gc += Gm[j + c * nj] * cd[c];
+      v = cd[j] * gc;
+    }
+    v = wave_sum(v);
+    if (j == 0) {
+      cg->cGc2[par] = v;
+      cg->its2[par] = first ? 0 : done_its + 1;
+      cg->its = first ? 0 : done_its + 1;
+      cg->alpha = al;
+      cg->beta = be;
+    }
+  }
+
+  // ---- the planes
+  constexpr int RV = RS + (IMM ? 0 : 2 * NJT);
+  T acc[RV];
+#pragma unroll
+  for (int r = 0; r < RV; ++r) acc[r] = T(0);
+  __shared__ T imm[IMM ? (OP_BS / WAVE) * 2 * NJT : 1];
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  if (IMM) {
+    for (int r = threadIdx.x; r < (OP_BS / WAVE) * 2 * NJT; r += OP_BS) imm[r] = T(0);
+    __syncthreads();
+  }
+  auto vadd = [&] __attribute__((always_inline)) (int r, T v) {
+    if (IMM) {
+      v = wave_sum(v);
+      if (lane == 0) imm[wid * 2 * NJT + r] += v;
+    } else {
+      acc[RS + r] += v;
+    }
+  };
+  // q_j from raw values: q_0 = q (first), else s - alpha w + beta q
+  const T ks = first ? T(0) : T(1), kw = (T)(-al), kq = first ? T(1) : (T)be;
+  auto qj = [&] __attribute__((always_inline)) (T s_, T w_, T q_) { return ks * s_ + kw * w_ + kq * q_; };
+  const T cx = (T)S.cx, cy = (T)S.cy, cz = (T)S.cz;
+  const T a_ = (T)al;
+  const T m = act ? T(1) : T(0);
+  T xm[NP], xc[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    xm[u] = qj(xm3.s[u], xm3.w[u], xm3.q[u]);
+    xc[u] = qj(P.own.s[u], P.own.w[u], P.own.q[u]);
+  }
+  for (int z = z0; walk && z < z1; ++z, i += nxy) {
+    T xp[NP], yd[NP], yu[NP], sj[NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      xp[u] = P.mxp * qj(P.xp.s[u], P.xp.w[u], P.xp.q[u]);
+      yd[u] = qj(P.yd.s[u], P.yd.w[u], P.yd.q[u]);
+      yu[u] = qj(P.yu.s[u], P.yu.w[u], P.yu.q[u]);
+      sj[u] = P.own.s[u] - a_ * P.own.w[u];
+    }
+    const T xl = qj(P.xl.s, P.xl.w, P.xl.q), xr = qj(P.xr.s, P.xr.w, P.xr.q);
+    // the update of step j-1 at this thread's nodes
+    if (act) {
+      if (!first) {
+        T gn[NP];
+#pragma unroll
+        for (int u = 0; u < NP; ++u) gn[u] = P.gv[u] + a_ * P.own.q[u];
+        stn(g, i, gn);
+        stn(sw_, i, sj);
+        stn(qw_, i, xc);
+      }
+    }
+    // (A q_j) at the NP nodes
+    T av[NP], xq[NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const T left = u == 0 ? xl : xc[u - 1];
+      const T right = u == NP - 1 ? xr : xc[u + 1];
+      T v = P.d[u] * xc[u];
+      if (!VAR) {
+        v -= cx * (left + right) + cy * (yd[u] + yu[u]) + cz * (xm[u] + xp[u]);
+      } else {
+        const T fl = u == 0 ? P.fxl : P.fx[u - 1];
+        v -= fl * left + P.fx[u] * right;
+        v -= P.fyd[u] * yd[u] + P.fyu[u] * yu[u];
+        if (S.dim == 3) v -= fm[u] * xm[u] + P.fp[u] * xp[u];
+      }
+      av[u] = m * v;
+      xq[u] = m * xc[u];
+      sj[u] = m * sj[u];
+    }
+    // pass 1 over the rows of AU: AU c_j, (AU)^T s_j
+    T au[NP], wv[NP];
+    zero(au);
+    T keep[KEEP ? NJT : 1][NP];
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) {
+        T a[NP];
+        if (PRE) {
+#pragma unroll
+          for (int u = 0; u < NP; ++u) a[u] = P.a[PRE ? c : 0][u];
+        } else if (act) {
+          ldv(AW + c * ld, i, a);
+        } else {
+          zero(a);
+        }
+        if (KEEP) {
+#pragma unroll
+          for (int u = 0; u < NP; ++u) keep[KEEP ? c : 0][u] = a[u];
+        }
+        T t = T(0);
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+          au[u] += a[u] * cs[c];
+          t += a[u] * sj[u];
+        }
+        vadd(NJT + c, t);
+      }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      wv[u] = av[u] - au[u];
+      acc[0] += xq[u] * wv[u];
+      acc[1] += xq[u] * au[u];
+      acc[2] += sj[u] * wv[u];
+      acc[3] += wv[u] * wv[u];
+      acc[4] += sj[u] * sj[u];
+    }
+    if (act) stn(ww_, i, wv);
+    // pass 2: (AU)^T w_j
+#pragma unroll
+    for (int c = 0; c < NJT; ++c)
+      if (c < nj) {
+        T a[NP];
+        if (PRE) {
+#pragma unroll
+          for (int u = 0; u < NP; ++u) a[u] = P.a[PRE ? c : 0][u];
+        } else if (KEEP) {
+#pragma unroll
+          for (int u = 0; u < NP; ++u) a[u] = keep[KEEP ? c : 0][u];
+        } else if (act) {
+          ldv(AW + c * ld, i, a);
+        } else {
+          zero(a);
+        }
+        T t = T(0);
+#pragma unroll
+        for (int u = 0; u < NP; ++u) t += a[u] * wv[u];
+        vadd(c, t);
+      }
+    // next plane
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      xm[u] = xc[u];
+      xc[u] = xp[u];
+      if (VAR) fm[u] = P.fp[u];
+    }
+    if (z + 1 < z1) load_plane(i + nxy, z + 1);
+  }
+  T* __restrict__ po = po0 + y * postride + par * pohalf;
+  const int P1 = gridDim.x * gridDim.y;
+  const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+  if (!IMM) {
+    write_partials_t<RV, OP_BS>(acc, po, bid, P1);
+  } else {
+    T a5[RS] = {acc[0], acc[1], acc[2], acc[3], acc[4]};
+    write_partials_t<RS, OP_BS>(a5, po, bid, P1);
+    __syncthreads();
+    for (int r = threadIdx.x; r < 2 * NJT; r += OP_BS) {
+      T t = T(0);
+#pragma unroll
+      for (int v = 0; v < OP_BS / WAVE; ++v) t += imm[v * 2 * NJT + r];
+      po[(size_t)(RS + r) * P1 + bid] = t;
+    }
+  }
+}
+
 // Rows per thread of the update (five vectors, no U rows): 4, or 2 in the narrow variant.
 template <int NARROW>
 struct UpdRows {
@@ -716,6 +1116,44 @@ void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, cons
 }
 
 template <typename T>
+void launch_dcg_iter(const Stencil& S, const StencilShape& sh, const T* diag, T* s, T* q, T* w,
+                     int64_t pstride, int64_t vstride, T* g, const T* AW, int64_t wstride,
+                     int64_t ld, int njmax, const double* Ginv, const double* Gm,
+                     int64_t gstride, CGState* cg, CGVec* cv, const T* ps, int Ps,
+                     int64_t psstride, T* po, int64_t postride, int64_t pohalf, int Pprev,
+                     int par, int first, int nb, hipStream_t st) {
+  if (par != 0 && par != 1) throw Error(ROM_EINVAL, "dcg_iter: parity must be 0 or 1");
+  if (first && par != 0) throw Error(ROM_EINVAL, "dcg_iter: the first step has parity 0");
+  if (sh.pairs) {
+    // the two-node walk reads and writes s, q, w and g two values at a time
+    const uintptr_t m = 2 * sizeof(T) - 1;
+    if ((((uintptr_t)s | (uintptr_t)q | (uintptr_t)w | (uintptr_t)g) & m) || pstride % 2 ||
+        vstride % 2)
+      throw Error(ROM_EINVAL, "dcg_iter: vectors not aligned for the two-node walk");
+  }
+  const dim3 grid(sh.grid.x, sh.grid.y, nb);
+#define ITL(VAR, NP, J)                                                                        \
+  ROM_LAUNCH((k_dcg_iter<T, VAR, NP, J>), grid, dim3(OP_BS), 0, st, S, diag, s, q, w, pstride,  \
+             vstride, g, AW, wstride, ld, Ginv, Gm, gstride, sh.zc, cg, cv, ps, Ps, psstride,   \
+             po, postride, pohalf, Pprev, par, first)
+#define ITJ(VAR, NP)                      \
+  switch (njt_of(njmax)) {                \
+    case 8: ITL(VAR, NP, 8); break;       \
+    case 16: ITL(VAR, NP, 16); break;     \
+    case 32: ITL(VAR, NP, 32); break;     \
+    default: ITL(VAR, NP, 64); break;     \
+  }
+  if (sh.pairs) {
+    if (S.var) { ITJ(true, 2) } else { ITJ(false, 2) }
+  } else {
+    if (S.var) { ITJ(true, 1) } else { ITJ(false, 1) }
+  }
+#undef ITJ
+#undef ITL
+  ROM_CHECK_LAUNCH();
+}
+
+template <typename T>
 void launch_dcg_update(T* q, const T* w, T* g, T* s, int64_t vstride, int64_t n, int njmax,
                        CGState* cg, CGVec* cv, const T* po, int P1, int64_t postride, T* pu,
                        int64_t pustride, int nb, int P, hipStream_t st, int narrow) {
@@ -754,6 +1192,11 @@ void launch_dcg_finish(const T* W, int64_t wstride, int64_t ld, int64_t n, int n
                                  const double*, const double*, int64_t, CGState*, CGVec*,        \
                                  const T*, int, int64_t, const T*, int, int64_t, T*, int64_t,    \
                                  int, hipStream_t);                                              \
+  template void launch_dcg_iter<T>(const Stencil&, const StencilShape&, const T*, T*, T*, T*,     \
+                                   int64_t, int64_t, T*, const T*, int64_t, int64_t, int,        \
+                                   const double*, const double*, int64_t, CGState*, CGVec*,      \
+                                   const T*, int, int64_t, T*, int64_t, int64_t, int, int, int,  \
+                                   int, hipStream_t);                                            \
   template void launch_dcg_update<T>(T*, const T*, T*, T*, int64_t, int64_t, int, CGState*,      \
                                      CGVec*, const T*, int, int64_t, T*, int64_t, int, int,      \
                                      hipStream_t, int);                                          \

@@ -25,6 +25,10 @@ struct CGState {
   int kcur;            // index of the latest operator step: written by it, read by the
                        // update (no kernel reads a field that another block of the same
                        // launch may already have rewritten)
+  // one-launch step only, by step parity (written by launch j at j & 1, read by launch
+  // j + 1): updates done after the launch and c^T G c of its direction
+  int its2[2];
+  double cGc2[2];
 };
 
 // Per-member vectors of the deflated-CG recurrences (device memory beside the state).
@@ -335,6 +339,7 @@ int dcg_blocks(int64_t n);
 int njt_of(int nj);
 // values per block of the operator step's partials for width class njt
 inline int dcg_op_values(int njt) { return 4 + 2 * njt; }
+inline int dcg_iter_values(int njt) { return 5 + 2 * njt; }
 void launch_cg_setup(CGState* cg, CGVec* cv, const CgSetup& su, int nb, hipStream_t st);
 // P blocks per member; partials ps (NJ_MAX + 1 values per block, transposed) at stride
 // psstride per member.
@@ -358,6 +363,19 @@ template <typename T>
 void launch_dcg_update(T* q, const T* w, T* g, T* s, int64_t vstride, int64_t n, int njmax,
                        CGState* cg, CGVec* cv, const T* po, int P1, int64_t postride, T* pu,
                        int64_t pustride, int nb, int P, hipStream_t st, int narrow = 0);
+// One whole CG step per launch (update of step j-1 and operator step j) on the operator
+// step's shape sh.  s, q, w: two buffers each, parity p at + p pstride (the start writes
+// s_0, q_0 into parity 0); step j (par = j & 1) reads parity 1 - par and writes par, and
+// its partials (dcg_iter_values(njt_of(njmax)) values per member at stride postride) at
+// po + par pohalf.  first: step 0 (par 0, reads the start's Ps partial rows); else Pprev
+// = the previous step's blocks (sh.blocks).  g: the q part of the correction.
+template <typename T>
+void launch_dcg_iter(const Stencil& S, const StencilShape& sh, const T* diag, T* s, T* q, T* w,
+                     int64_t pstride, int64_t vstride, T* g, const T* AW, int64_t wstride,
+                     int64_t ld, int njmax, const double* Ginv, const double* Gm,
+                     int64_t gstride, CGState* cg, CGVec* cv, const T* ps, int Ps,
+                     int64_t psstride, T* po, int64_t postride, int64_t pohalf, int Pprev,
+                     int par, int first, int nb, hipStream_t st);
 // g -= U e for every member (the U part of the split correction).
 template <typename T>
 void launch_dcg_finish(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax, T* g,

@@ -58,6 +58,8 @@ constexpr int MAX_SWEEPS = 64;
 constexpr double FP32_GOAL_MIN = 1e-6;
 // CG steps per captured graph
 constexpr int GRAPH_STEPS = 8;
+// (even: a chunk of one-launch steps then ends on the parity it started from)
+static_assert(GRAPH_STEPS % 2 == 0, "one-launch graph chunks alternate the parity");
 
 struct Arena {
   char* base;
@@ -247,7 +249,7 @@ size_t operator_layout(const rom_grid& g, bool var, Arena& a, rom_operator* op) 
 
 // Launch shapes chosen by the CG autotuner, per process: (device, value size, batch
 // size, U_j width class, grid size) -> blocks per member.
-using TuneKey = std::tuple<int, int, int, int, int64_t>;
+using TuneKey = std::tuple<int, int, int, int, int64_t, int>;
 std::map<TuneKey, int>& tune_map() {
   static std::map<TuneKey, int> m;
   return m;
@@ -308,9 +310,10 @@ class Sequencer {
     x0_ = a.take<double>(ld_ * G);
     r_ = a.take<double>(ld_ * G);
     g_ = a.take<double>(ld_ * G);
-    s_ = a.take<double>(ld_ * G);
-    p_ = a.take<double>(ld_ * G);
-    w_ = a.take<double>(ld_ * G);
+    // s, q (p_) and w of the CG in two buffers each (the one-launch step alternates them)
+    s_ = a.take<double>(2 * ld_ * G);
+    p_ = a.take<double>(2 * ld_ * G);
+    w_ = a.take<double>(2 * ld_ * G);
     d_ = a.take<double>(ld_ * G);
     xt_ = a.take<double>(ld_ * G);
     r2_ = a.take<double>(ld_ * G);
@@ -340,10 +343,12 @@ class Sequencer {
     const StencilShape sh = stencil_shape(S_, 1024);
     const StencilShape sh5 = stencil_shape(S_, 512);
     red_part_ = a.take<double>(std::max<size_t>(2 * 1024, (size_t)std::max(sh5.blocks, 256) * G));
-    // CG partials per member: the operator step's (dcg_op_values(NJ_MAX) rows of at most
-    // sh.blocks), the start's (NJ_MAX + 1 rows) and the update's (one row)
-    pos_ = (int64_t)dcg_op_values(NJ_MAX) * std::max(sh.blocks, 1);
-    part_o_ = a.take<double>((size_t)pos_ * G);
+    // CG partials per member: the operator step's (dcg_iter_values(NJ_MAX) rows of at most
+    // sh.blocks, twice: the one-launch step alternates halves), the start's (NJ_MAX + 1
+    // rows) and the update's (one row)
+    pos_ = (int64_t)std::max(dcg_op_values(NJ_MAX), dcg_iter_values(NJ_MAX)) *
+           std::max(sh.blocks, 1);
+    part_o_ = a.take<double>((size_t)pos_ * G * 2);
     p2s_ = (int64_t)(NJ_MAX + 1) * dcg_blocks(n_);
     part2_ = a.take<double>((size_t)p2s_ * G);
     pus_ = dcg_blocks(n_);
@@ -374,9 +379,9 @@ class Sequencer {
     if (mixed_) {
       W32_ = a.take<float>(wsz * G);
       AW32_ = a.take<float>(wsz * G);
-      s32_ = a.take<float>(ld_ * G);
-      p32_ = a.take<float>(ld_ * G);
-      w32_ = a.take<float>(ld_ * G);
+      s32_ = a.take<float>(2 * ld_ * G);
+      p32_ = a.take<float>(2 * ld_ * G);
+      w32_ = a.take<float>(2 * ld_ * G);
       d32_ = a.take<float>(ld_ * G);
       diag32_ = a.take<float>(ld_);
       if (S_.var) {
@@ -1426,21 +1431,25 @@ class Sequencer {
   }
 
   // The CG vectors (q holds the q part of the split direction) and partials of the
-  // operator step (po), the start (ps) and the update (pu), as the solve's type.
+  // operator step (po), the start (ps) and the update (pu), as the solve's type; s, q and w
+  // of parity 1 at + pstride, the operator step's partials of parity 1 at po + pohalf.
   struct CgBufs32 {
     const float *W, *AW, *diag;
     float *s, *q, *w, *po, *ps, *pu;
+    int64_t pstride, pohalf;
   };
   struct CgBufs64 {
     const double *W, *AW, *diag;
     double *s, *q, *w, *po, *ps, *pu;
+    int64_t pstride, pohalf;
   };
   void bufs(CgBufs64& b) const {
-    b = {Wp_, AWp_, diag_i_, s_, p_, w_, part_o_, part2_, part_u_};
+    b = {Wp_, AWp_, diag_i_, s_, p_, w_, part_o_, part2_, part_u_, ld_ * G_, pos_ * G_};
   }
   void bufs(CgBufs32& b) const {
     b = {W32_, AW32_, diag32_, s32_, p32_, w32_, reinterpret_cast<float*>(part_o_),
-         reinterpret_cast<float*>(part2_), reinterpret_cast<float*>(part_u_)};
+         reinterpret_cast<float*>(part2_), reinterpret_cast<float*>(part_u_), ld_ * G_,
+         pos_ * G_};
   }
 
   // One batched deflated-CG solve: member y (active[y]) solves A_i d_y = rscale[y] r_y
@@ -1469,13 +1478,17 @@ class Sequencer {
   // its own data (three rounds of 8 CG steps each after a warm-up round, from its real
   // start; the solve then restarts) and keeps the fastest (by its best round) for the rest
   // of the process.
+  // Bit 2 of op selects the one-launch step (then P and narrow are unused): every block of
+  // it sums all partial rows of the previous step, so only the 256 and 64 block targets are
+  // candidates for it.
   static int shape_code(int P, int nr, int op) { return (P << 4) | (nr << 3) | op; }
   static int shape_P(int code) { return code >> 4; }
   static int shape_nr(int code) { return (code >> 3) & 1; }
+  static bool shape_one(int code) { return (code & 4) != 0; }
   // op 0: 1024 blocks per member divided among the members (at least 64); 1, 2, 3: 1024,
   // 256, 64 blocks per member
   static int op_target(int code, int nb) {
-    const int op = code & 7;
+    const int op = code & 3;
     return op == 0 ? std::max(64, 1024 / nb) : op == 1 ? 1024 : op == 2 ? 256 : 64;
   }
   template <typename T, typename Bufs>
@@ -1488,20 +1501,26 @@ class Sequencer {
                int64_t gstride, int njmax) {
     const int nb = bt.nb;
     const int Pmax = dcg_blocks(n_);
-    const int fixed = shape_code(std::max(std::min(Pmax, 8), Pmax / nb), nb > 1 ? 1 : 0, 0);
+    const int mode = o_.cg_step;   // 0 either form (tuned) / two launches, 1 two, 2 one
+    const int fixed = mode == 2 ? shape_code(Pmax, 0, 4 | 2)
+                                : shape_code(std::max(std::min(Pmax, 8), Pmax / nb),
+                                             nb > 1 ? 1 : 0, 0);
     if (!tune_) return fixed;
     int dev = 0;
     ROM_HIP(hipGetDevice(&dev));
-    const TuneKey key{dev, (int)sizeof(T), nb, njt_of(njmax), (int64_t)n_};
+    const TuneKey key{dev, (int)sizeof(T), nb, njt_of(njmax), (int64_t)n_, mode};
     {
       std::lock_guard<std::mutex> lk(tune_mu());
       auto it = tune_map().find(key);
       if (it != tune_map().end()) return it->second;
     }
     std::vector<int> cand;
-    for (int P = Pmax; P >= 8; P /= 2)
-      for (int nr = 0; nr < 2; ++nr)
-        for (int op = 1; op <= 3; ++op) cand.push_back(shape_code(P, nr, op));
+    if (mode != 2)
+      for (int P = Pmax; P >= 8; P /= 2)
+        for (int nr = 0; nr < 2; ++nr)
+          for (int op = 1; op <= 3; ++op) cand.push_back(shape_code(P, nr, op));
+    if (mode != 1)
+      for (int op = 2; op <= 3; ++op) cand.push_back(shape_code(Pmax, 0, 4 | op));
     int best = fixed;
     if (cand.size() > 1) {
       CGState* cg = ctrl_->cg;
@@ -1514,9 +1533,6 @@ class Sequencer {
         su.nj[y] = bt.nj[y];
         su.active[y] = bt.active[y];
       }
-      launch_cg_setup(cg, cgv_, su, nb, st_);
-      launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec,
-                          b.s, b.q, ld_, cg, b.ps, p2s_, nb, Pmax, st_);
       hipEvent_t e0, e1;
       ROM_HIP(hipEventCreate(&e0));
       ROM_HIP(hipEventCreate(&e1));
@@ -1527,23 +1543,33 @@ class Sequencer {
           (void)hipEventDestroy(b);
         }
       } guard{e0, e1};
-      int Pprev = Pmax;   // blocks of the launch whose partials the next operator step sums
       // each shape's time is the minimum over 3 rounds of 8 steps (the first round only
-      // warms up): single short windows were noisy enough to flip the choice between runs
+      // warms up): single short windows were noisy enough to flip the choice between runs.
+      // Every window starts the solve afresh (untimed), so that both forms time the same
+      // first 8 steps from the real start.
       std::vector<float> tmin(cand.size(), 1e30f);
       for (int rep = 0; rep < 4; ++rep) {
         for (size_t ci = 0; ci < cand.size(); ++ci) {
           const int shape = cand[ci];
           const int P = shape_P(shape), nr = shape_nr(shape);
           const StencilShape sh = op_shape<T>(b, shape, nb);
+          launch_cg_setup(cg, cgv_, su, nb, st_);
+          launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_,
+                              dvec, b.s, b.q, ld_, cg, b.ps, p2s_, nb, Pmax, st_);
           ROM_HIP(hipEventRecord(e0, st_));
           for (int step = 0; step < 8; ++step) {
-            launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax,
-                             GWinv_, GWs_, gstride, cg, cgv_, b.ps, Pmax, p2s_, b.pu, Pprev,
-                             pus_, b.po, pos_, nb, st_);
-            launch_dcg_update<T>(b.q, b.w, dvec, b.s, ld_, n_, njmax, cg, cgv_, b.po, sh.blocks,
-                                 pos_, b.pu, pus_, nb, P, st_, nr);
-            Pprev = P;
+            if (shape_one(shape)) {
+              launch_dcg_iter<T>(S_, sh, b.diag, b.s, b.q, b.w, b.pstride, ld_, dvec, b.AW,
+                                 wstride, ld_, njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps,
+                                 Pmax, p2s_, b.po, pos_, b.pohalf, sh.blocks, step & 1,
+                                 step == 0, nb, st_);
+            } else {
+              launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax,
+                               GWinv_, GWs_, gstride, cg, cgv_, b.ps, Pmax, p2s_, b.pu, P,
+                               pus_, b.po, pos_, nb, st_);
+              launch_dcg_update<T>(b.q, b.w, dvec, b.s, ld_, n_, njmax, cg, cgv_, b.po,
+                                   sh.blocks, pos_, b.pu, pus_, nb, P, st_, nr);
+            }
           }
           ROM_HIP(hipEventRecord(e1, st_));
           ROM_HIP(hipEventSynchronize(e1));
@@ -1564,10 +1590,11 @@ class Sequencer {
     return best;
   }
 
-  // A captured chunk of GRAPH_STEPS CG steps (operator step, update; both take the step
-  // index from the CG state), replayed instead of individual launches.  One graph per
-  // (value type, batch size, shared recycle space, width class, shape, output vector),
-  // kept for the rest of the call.
+  // A captured chunk of GRAPH_STEPS CG steps, replayed instead of individual launches:
+  // (operator step, update) pairs, which take the step index from the CG state, or
+  // one-launch steps of parities 1, 0, 1, ... (a chunk follows the eager step 0 or another
+  // chunk).  One graph per (value type, batch size, shared recycle space, width class,
+  // shape, output vector), kept for the rest of the call.
   template <typename T, typename Bufs>
   hipGraphExec_t chunk_graph(const Bufs& b, int nb, bool shared, int njmax, int shape,
                              int64_t wstride, int64_t gstride, T* dvec, const StencilShape& sh) {
@@ -1586,6 +1613,12 @@ class Sequencer {
     ROM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
       for (int c = 0; c < GRAPH_STEPS; ++c) {
+        if (shape_one(shape)) {
+          launch_dcg_iter<T>(S_, sh, b.diag, b.s, b.q, b.w, b.pstride, ld_, dvec, b.AW, wstride,
+                             ld_, njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.po,
+                             pos_, b.pohalf, sh.blocks, (c + 1) & 1, 0, nb, cs);
+          continue;
+        }
         launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax, GWinv_,
                          GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.pu, P, pus_, b.po, pos_, nb,
                          cs);
@@ -1675,6 +1708,12 @@ class Sequencer {
     const double fl_op = n_ * (21.0 + 6.0 * njavg);
     const double by_upd = 7.0 * E * n_;
     const double fl_upd = 8.0 * n_;
+    // the one-launch step reads s, q, w, g, the diagonal (and face coefficients) and AU and
+    // writes s, q, w, g
+    const bool one = shape_one(shape);
+    const double by_one = E * n_ * (9 + njavg + (S_.var ? S_.dim : 0));
+    const double fl_one = fl_op + fl_upd;
+    int step = 0;   // one-launch steps launched (the next one's index)
     int next = chunk_;
     int its_before[G_MAX] = {};
     double gam_before[G_MAX];
@@ -1682,9 +1721,85 @@ class Sequencer {
     int nlive = nact;
     int Pu = P;   // blocks of the update whose partials the next operator step sums
     // CG steps as replays of a captured chunk when asked for and no step kernel is timed
-    const int cg_classes = (1 << ROM_K_DCG_OP) | (1 << ROM_K_DCG_UPDATE);
+    const int cg_classes =
+        (1 << ROM_K_DCG_OP) | (1 << ROM_K_DCG_UPDATE) | (1 << ROM_K_DCG_STEP);
     const bool graphs = graph_ && !(o_.timing & cg_classes);
+    auto iter = [&](hipStream_t st) {
+      launch_dcg_iter<T>(S_, sh, b.diag, b.s, b.q, b.w, b.pstride, ld_, dvec, b.AW, wstride,
+                         ld_, njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.po,
+                         pos_, b.pohalf, step == 0 ? P0 : sh.blocks, step & 1, step == 0, nb,
+                         st);
+      ++step;
+    };
     for (;;) {
+      if (one) {
+        // launches in this chunk; step 0 (no update) runs eagerly before the first replay
+        const bool had0 = step == 0;
+        int launched = 0;
+        if (graphs) {
+          if (step == 0) {
+            iter(st_);
+            ++launched;
+          }
+          const int reps = std::max(1, (next - launched + GRAPH_STEPS - 1) / GRAPH_STEPS);
+          hipGraphExec_t ex =
+              chunk_graph<T>(b, nb, bt.shared, njmax, shape, wstride, gstride, dvec, sh);
+          for (int r = 0; r < reps; ++r) ROM_HIP(hipGraphLaunch(ex, st_));
+          step += reps * GRAPH_STEPS;
+          launched += reps * GRAPH_STEPS;
+          for (int c = 0; c < launched; ++c) tm_->add(ROM_K_DCG_STEP, nlive * by_one, nlive * fl_one);
+        } else {
+          for (int c = 0; c < next; ++c) {
+            tm_->begin(ROM_K_DCG_STEP);
+            iter(st_);
+            tm_->end(ROM_K_DCG_STEP, nlive * by_one, nlive * fl_one);
+          }
+          launched = next;
+        }
+        ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
+        ROM_HIP(hipStreamSynchronize(st_));
+        // updates done per member in this chunk; a member's launches that did the whole
+        // step are its updates plus step 0, then one more read its stopping test; launches
+        // after the last member's stop returned at once
+        int maxreal = 0, steps = 0, still = 0;
+        for (int y = 0; y < nb; ++y) {
+          if (!bt.active[y] || its_before[y] < 0) continue;
+          const CGState& c = h_->cg[y];
+          const int real = c.its - its_before[y];
+          maxreal = std::max(maxreal, real);
+          steps += real;
+          if (c.done) {
+            its_before[y] = -1;
+          } else {
+            ++still;
+            its_before[y] = c.its;
+          }
+        }
+        const bool stop = still == 0;
+        // (a stop read by step 0 itself: that one launch)
+        const int counted = had0 && maxreal == 0 ? 1 : maxreal + (had0 ? 1 : 0) + 1;
+        tm_->discard(ROM_K_DCG_STEP, stop ? launched - counted : 0, 0.0, 0.0);
+        const double over = (double)nlive * launched - steps - (had0 ? nlive : 0);
+        tm_->adjust(ROM_K_DCG_STEP, -over * by_one, -over * fl_one);
+        tm_->harvest();
+        if (stop) break;
+        int pred = 2;
+        for (int y = 0; y < nb; ++y) {
+          if (!bt.active[y] || its_before[y] < 0) continue;
+          const CGState& c = h_->cg[y];
+          const double gam = c.gamma[c.its & 1];
+          int py = chunk_;
+          if (gam_before[y] > 0.0 && gam > 0.0 && gam < gam_before[y] && launched > 0) {
+            const double rate = std::log(gam / gam_before[y]) / launched;   // < 0
+            py = (int)std::ceil(std::log(c.tol2 / gam) / rate);
+          }
+          pred = std::max(pred, py);
+          gam_before[y] = gam;
+        }
+        nlive = still;
+        next = std::min(64, std::max(2, pred));
+        continue;
+      }
       if (graphs) {
         const int reps = (next + GRAPH_STEPS - 1) / GRAPH_STEPS;
         hipGraphExec_t ex =
@@ -1877,6 +1992,7 @@ void check_opts(const rom_opts* o) {
   if (o->group < 0 || o->group > G_MAX) throw Error(ROM_EINVAL, "group must be in [0, 16]");
   if (o->tune != 0 && o->tune != 1) throw Error(ROM_EINVAL, "tune must be 0 or 1");
   if (o->graph != 0 && o->graph != 1) throw Error(ROM_EINVAL, "graph must be 0 or 1");
+  if (o->cg_step < 0 || o->cg_step > 2) throw Error(ROM_EINVAL, "cg_step must be 0, 1 or 2");
   if (o->recycle && (o->n_recycle < 1 || o->n_recycle > REC_MAX))
     throw Error(ROM_EINVAL, "n_recycle must be in [1, 16]");
 }

@@ -83,7 +83,7 @@ class Problem:
               keep_X: bool = True, precision: int = R.ROM_PREC_FP64,
               inner_tol: float = 0.0, group: int = 0, tune: int = 0,
               graph: int = 0, guess: Optional[torch.Tensor] = None,
-              recycle: Optional[torch.Tensor] = None) -> SequenceResult:
+              recycle: Optional[torch.Tensor] = None, cg_step: int = 0) -> SequenceResult:
         """recycle: (K, n_recycle, N) FP32 learned recycle vectors per point (they join the
         recycle spaces U_j at their point), or None."""
         if recycle is not None:
@@ -91,7 +91,7 @@ class Problem:
                 recycle.shape[2] == self.n and recycle.dtype == torch.float32
             recycle = recycle.contiguous()
         opts = R.make_opts(tol, trunc, cap, maxit, check_every, timing, precision, inner_tol,
-                           group, tune, graph, guess, recycle)
+                           group, tune, graph, guess, recycle, cg_step)
         K = len(points)
         nbytes = R.rom_sequence_bytes(self.op, self.src_idx.size, self.det_idx.size, self.k_u, K, opts)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -108,7 +108,8 @@ class Problem:
         opts = R.make_opts(tol, trunc, cap, kw.pop("maxit", 0), kw.pop("check_every", 0),
                            kw.pop("timing", 0), kw.pop("precision", R.ROM_PREC_FP64),
                            kw.pop("inner_tol", 0.0), kw.pop("group", 0), kw.pop("tune", 0),
-                           kw.pop("graph", 0), kw.pop("guess", None), kw.pop("recycle", None))
+                           kw.pop("graph", 0), kw.pop("guess", None), kw.pop("recycle", None),
+                           kw.pop("cg_step", 0))
         assert not kw, kw
         nbytes = R.rom_sequence_bytes(self.op, self.src_idx.size, self.det_idx.size, self.k_u, K, opts)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -248,7 +249,8 @@ def solve_many(problems: List["Problem"], points: List[List[R.MuParams]], tol: f
         opts = R.make_opts(tol, trunc, cap, opt_kw.get("maxit", 0), opt_kw.get("check_every", 0),
                            opt_kw.get("timing", 0), opt_kw.get("precision", R.ROM_PREC_FP64),
                            opt_kw.get("inner_tol", 0.0), opt_kw.get("group", 0),
-                           opt_kw.get("tune", 0), opt_kw.get("graph", 0))
+                           opt_kw.get("tune", 0), opt_kw.get("graph", 0),
+                           cg_step=opt_kw.get("cg_step", 0))
         K = len(pts)
         nbytes = R.rom_sequence_bytes(prob.op, prob.src_idx.size, prob.det_idx.size, prob.k_u, K,
                                       opts)

@@ -32,9 +32,10 @@ ROM_PREC_FP64 = 0
 ROM_PREC_MIXED = 1
 
 (ROM_K_DCG_OP, ROM_K_DCG_UPDATE, ROM_K_DCG_ENDS, ROM_K_GEMVT, ROM_K_GEMVN, ROM_K_GRAM, ROM_K_OUTER,
- ROM_K_OTHER) = range(8)
-ROM_NK = 8
-KERNEL_CLASSES = ["dcg_op", "dcg_update", "dcg_ends", "gemvt", "gemvn", "gram", "outer", "other"]
+ ROM_K_OTHER, ROM_K_DCG_STEP) = range(9)
+ROM_NK = 9
+KERNEL_CLASSES = ["dcg_op", "dcg_update", "dcg_ends", "gemvt", "gemvn", "gram", "outer", "other",
+                  "dcg_step"]
 
 EXPORTED = ["rom_operator_bytes", "rom_assemble_operator", "rom_apply_operator",
             "rom_apply_operator_static", "rom_sequence_bytes", "rom_sequence_begin",
@@ -65,7 +66,8 @@ class rom_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("trunc", C.c_double), ("inner_tol", C.c_double),
                 ("cap", C.c_int), ("maxit", C.c_int), ("check_every", C.c_int), ("timing", C.c_int),
                 ("precision", C.c_int), ("group", C.c_int), ("tune", C.c_int), ("graph", C.c_int),
-                ("guess", C.c_void_p), ("recycle", C.c_void_p), ("n_recycle", C.c_int)]
+                ("guess", C.c_void_p), ("recycle", C.c_void_p), ("n_recycle", C.c_int),
+                ("cg_step", C.c_int)]
 
 
 class rom_record(C.Structure):
@@ -211,14 +213,14 @@ def make_grid(dim: int, N: Sequence[int], bc: Sequence[int], robin_A: float) -> 
 def make_opts(tol: float, trunc: float = 1e-8, cap: int = 0, maxit: int = 0,
               check_every: int = 0, timing: int = 0, precision: int = ROM_PREC_FP64,
               inner_tol: float = 0.0, group: int = 0, tune: int = 0, graph: int = 0,
-              guess=None, recycle=None) -> rom_opts:
+              guess=None, recycle=None, cg_step: int = 0) -> rom_opts:
     """guess: device FP32 tensor (K * n_rhs, N) of initial guesses, or None; recycle: device
     FP32 tensor (K, n_recycle, N) of learned recycle vectors per point, or None (both kept
     alive by the caller during the solve)."""
     nrec = int(recycle.shape[1]) if recycle is not None else 0
     return rom_opts(float(tol), float(trunc), float(inner_tol), int(cap), int(maxit),
                     int(check_every), int(timing), int(precision), int(group), int(tune),
-                    int(graph), _ptr(guess), _ptr(recycle), nrec)
+                    int(graph), _ptr(guess), _ptr(recycle), nrec, int(cg_step))
 
 
 @dataclass

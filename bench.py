@@ -126,20 +126,21 @@ def stream_points(prob, pts, W: int, K: int, wl, timing: int = 0, reduce_each: b
     recs = s.records[nrec0:]
     res = s.end()
     return {"value": K * prob.n_rhs / dt, "seconds": dt, "per_point_s": per,
-            "timed": diff_stats(before, after), "records": recs, "result": res}
+            "timed": diff_stats(before, after), "all": after, "records": recs, "result": res}
 
 
-def dcg_roofline(timed: dict, precision: str, prob, wl) -> dict:
+def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None) -> dict:
     """Roofline of the CG operator step (k_dcg_op): its algorithmic bytes per launch (the
     timer's per-class byte count over the timed points) over its mean event-timed launch
-    duration."""
+    duration.  all_pts: the stats of the whole stream (warm-up points included), whose
+    bytes per launch are the like-for-like figure for counters taken over the whole run."""
     k = timed["kernels"]["dcg_op"]
     launches = max(k["launches"], 1)
     avg_ms = k["ms"] / launches
     by = k["bytes"] / launches
     achieved = k["bytes"] / max(k["ms"], 1e-12) / 1e6
     E = 4 if precision == "mixed" else 8
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "k_dcg_op (CG operator step: w = A q - (A U_j) c with its dot products)",
             "launches": int(k["launches"]), "avg_launch_us": 1e3 * avg_ms,
@@ -149,6 +150,11 @@ def dcg_roofline(timed: dict, precision: str, prob, wl) -> dict:
                              + ", s, the n_j columns of A U_j read, w written)",
             "note": "events on every launch of this class over the timed points; the update "
                     "kernel and the rest are in 'kernel_classes'"}
+    if all_pts is not None:
+        a = all_pts["kernels"]["dcg_op"]
+        out["bytes_per_launch_all_points"] = a["bytes"] / max(a["launches"], 1)
+        out["launches_all_points"] = int(a["launches"])
+    return out
 
 
 def class_table(timed: dict) -> dict:
@@ -485,6 +491,10 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--group", type=int, default=1, help="right-hand sides per batch (1: the paper's order)")
     ap.add_argument("--tune", type=int, default=1)
+    ap.add_argument("--cg-step", type=int, default=0,
+                    help="launches per CG step for the headline: 0 the tuner's choice, 1 two "
+                         "(operator step, update), 2 one (counter runs pin 1: a profiler's "
+                         "per-dispatch overhead would sway the tuner)")
     ap.add_argument("--extras", type=int, default=1,
                     help="also time the other forms and workloads, the SpMM, the reduced "
                          "Jacobian, U_0 and nonzero frequency (0: headline and roofline only)")
@@ -544,13 +554,13 @@ def main():
 
     # ---- headline: the timed points, the CG operator step timed with events
     h = stream_points(prob, pts, W, K, wl, timing=1 << R.ROM_K_DCG_OP, precision=prec,
-                      group=args.group, tune=args.tune)
+                      group=args.group, tune=args.tune, cg_step=args.cg_step)
     timed = h["timed"]
     value = h["value"]
     recs = h["records"]
     solved = [r for r in recs if r["solved"]]
     its_per_solve = timed["total_its"] / max(len(solved), 1)
-    roof = dcg_roofline(timed, args.precision, prob, wl)
+    roof = dcg_roofline(timed, args.precision, prob, wl, h["all"])
     log(f"headline: {value:.1f} solves/s over points {W}..{W + K - 1} "
         f"({K * prob.n_rhs} solves, {timed['total_its']} inner its, {len(solved)} solved); "
         f"k_dcg_op {roof['achieved']:.0f} GB/s ({100 * roof['frac']:.1f}% of peak), "

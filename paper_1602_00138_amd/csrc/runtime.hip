@@ -56,10 +56,15 @@ constexpr int MAX_SWEEPS = 64;
 // smallest residual reduction asked of one FP32 sweep (about 16 FP32 unit roundoffs:
 // below it the FP32 true residual no longer follows the recursive one)
 constexpr double FP32_GOAL_MIN = 1e-6;
-// CG steps per captured graph
+// CG steps per captured graph (even: a chunk of one-launch steps then ends on the parity
+// it started from)
 constexpr int GRAPH_STEPS = 8;
-// (even: a chunk of one-launch steps then ends on the parity it started from)
 static_assert(GRAPH_STEPS % 2 == 0, "one-launch graph chunks alternate the parity");
+// The next convergence poll is placed past the extrapolated stop by this factor and pad:
+// a launch after the stop returns at once (a few microseconds), while a poll that comes too
+// early idles the GPU for a host round trip and costs another one.
+constexpr double POLL_MARGIN = 1.15;
+constexpr int POLL_PAD = 2;
 
 struct Arena {
   char* base;
@@ -1791,7 +1796,7 @@ class Sequencer {
           int py = chunk_;
           if (gam_before[y] > 0.0 && gam > 0.0 && gam < gam_before[y] && launched > 0) {
             const double rate = std::log(gam / gam_before[y]) / launched;   // < 0
-            py = (int)std::ceil(std::log(c.tol2 / gam) / rate);
+            py = (int)std::ceil(POLL_MARGIN * std::log(c.tol2 / gam) / rate) + POLL_PAD;
           }
           pred = std::max(pred, py);
           gam_before[y] = gam;
@@ -1858,7 +1863,7 @@ class Sequencer {
         int py = chunk_;
         if (gam_before[y] > 0.0 && gam > 0.0 && gam < gam_before[y] && next > 0) {
           const double rate = std::log(gam / gam_before[y]) / next;   // < 0
-          py = (int)std::ceil(std::log(c.tol2 / gam) / rate);
+          py = (int)std::ceil(POLL_MARGIN * std::log(c.tol2 / gam) / rate) + POLL_PAD;
         }
         pred = std::max(pred, py);
         gam_before[y] = gam;

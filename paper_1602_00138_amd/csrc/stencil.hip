@@ -19,6 +19,17 @@ constexpr int BS = 256;
 // is fastest (2 and 4 measured 1% and 13% slower at 64^3).
 constexpr int SPMM_CPT_VAR = 8;
 constexpr int SPMM_CPT_CONST = 1;
+// The LDS-tiled SpMM: columns per block and the block count its z chunks aim at.  With a D
+// field 4 columns share the diagonal and face loads (96 columns at 128^3: 3.0 TB/s with one
+// column per block, 4.4 with four, against 3.2 for the register-walk k_spmm2c); with
+// constant D one column per block over about 16k blocks was fastest at 64^3 (4.8 TB/s
+// against 4.6 and 4.7 for 2 and 4 columns).  Fewer columns where their staged tiles would
+// pass SPMM_LDS_MAX bytes of LDS.
+constexpr int SPMM_LDS_C_VAR = 4;
+constexpr int SPMM_LDS_C_CONST = 1;
+constexpr int64_t SPMM_LDS_BLOCKS_VAR = 1024;
+constexpr int64_t SPMM_LDS_BLOCKS_CONST = 16384;
+constexpr size_t SPMM_LDS_MAX = 48 * 1024;
 
 __global__ void k_assemble(rom_grid g, double Dc, const double* __restrict__ D, int64_t n,
                            double* __restrict__ diag, double* __restrict__ fx,
@@ -254,60 +265,116 @@ __global__ __launch_bounds__(BS) void k_spmm2(Stencil S, const double* __restric
   });
 }
 
-// Y = A X (constant D) with LDS-staged x-y tiles (2.5D blocking): a block owns TY = 256 /
-// (nx / 2) full rows of the grid (two x-nodes per thread, nx even, nx <= 512) over a chunk
-// of zc planes and walks the planes; each plane's tile rows and the two rows next to the
-// tile are staged in LDS (two buffers, one barrier per plane), so the lateral neighbours come
-// from LDS instead of the caches, and the z neighbours stay in registers.  Columns on
-// blockIdx.z.  Against k_spmm2 it took 64 columns at 64^3 from 3.9 to 4.8 TB/s and 96 at
-// 128^3 from 3.6 to 4.6 TB/s (kernel alone).
-constexpr int LDS_TILE = 3 * BS;   // (TY + 2) * nx / 2 <= BS + nx <= 3 BS pairs
+// Y = A X with LDS-staged x-y tiles (2.5D blocking): a block owns TY = 256 / (nx / 2) full
+// rows of the grid (two x-nodes per thread, nx even, nx <= 512) over a chunk of zc planes,
+// for C columns, and walks the planes; each plane's tile rows and the two rows next to the
+// tile are staged in LDS for every column (two buffers, one barrier per plane), so the
+// lateral neighbours come from LDS, the z neighbours stay in registers, and the diagonal and
+// the face coefficients (D field) are read once per node for all C columns.  The launch is
+// one-dimensional: block b takes tile b % ntiles, z chunk (b / ntiles) % nzc and column
+// group b / (ntiles nzc).  (Giving each XCD a contiguous run of tiles, so that its own L2
+// would serve the rows two tiles share, measured no faster.)
+template <bool VAR, int C>
 __global__ __launch_bounds__(BS) void k_spmm_lds(Stencil S, const double* __restrict__ diag,
                                                   const double* __restrict__ x0, int64_t ld,
-                                                  double* __restrict__ y0, int zc) {
-  __shared__ double2 tile[2][LDS_TILE];
-  const double* __restrict__ x = x0 + (int64_t)blockIdx.z * ld;
-  double* __restrict__ y = y0 + (int64_t)blockIdx.z * ld;
+                                                  int k, double* __restrict__ y0, int zc,
+                                                  int ntiles, int nzc) {
+  extern __shared__ double2 smem[];
   const int PR = S.nx / 2;            // pairs per row
   const int TY = BS / PR;             // rows per tile
+  const int TT = (TY + 2) * PR;       // pairs of one staged plane tile
+  const int lg = blockIdx.x;
+  const int tile = lg % ntiles;
+  const int zch = (lg / ntiles) % nzc;
+  const int c0 = (lg / ntiles / nzc) * C;
+  const int nc = min(C, k - c0);
   const int t = threadIdx.x;
   const int px = t % PR, ry = t / PR;
-  const int y0r = blockIdx.x * TY;    // first row of the tile
+  const int y0r = tile * TY;          // first row of the tile
   const int iy = y0r + ry;
   const bool own = ry < TY && iy < S.ny;
-  const int z0 = blockIdx.y * zc, z1 = min(z0 + zc, S.nz);
-  if (z0 >= z1) return;
+  const int z0 = zch * zc, z1 = min(z0 + zc, S.nz);
+  if (z0 >= z1 || nc <= 0) return;
   const int nxy = S.nx * S.ny;
-  auto ld2 = [](const double* p, int64_t k) { return *reinterpret_cast<const double2*>(p + k); };
+  auto ld2 = [](const double* p, int64_t j) { return *reinterpret_cast<const double2*>(p + j); };
   const double2 zero = {0.0, 0.0};
+  const double* x[C];
+  double* y[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int64_t col = c0 + (c < nc ? c : 0);   // columns past k alias the first (never stored)
+    x[c] = x0 + col * ld;
+    y[c] = y0 + col * ld;
+  }
   int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + 2 * px;
-  double2 xm = (own && z0 > 0) ? ld2(x, i - nxy) : zero;
-  double2 xc = own ? ld2(x, i) : zero;
+  double2 xm[C], xc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    xm[c] = (own && z0 > 0) ? ld2(x[c], i - nxy) : zero;
+    xc[c] = own ? ld2(x[c], i) : zero;
+  }
+  double2 fm = (VAR && own && z0 > 0) ? ld2(S.fz, i - nxy) : zero;
+  const bool hl = px > 0, hd = iy > 0;
   const double cx = S.cx, cy = S.cy, cz = S.cz;
   int buf = 0;
   for (int z = z0; z < z1; ++z, i += nxy) {
-    double2* T = tile[buf];
-    if (ry < TY) T[(ry + 1) * PR + px] = xc;   // zero for rows past the grid
+    double2* T = smem + (size_t)buf * C * TT;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (ry < TY) T[c * TT + (ry + 1) * PR + px] = xc[c];   // zero for rows past the grid
     // the rows below and above the tile (zero outside the grid)
     for (int h = t; h < 2 * PR; h += BS) {
       const int hr = h / PR, hx = h % PR;
       const int hy = hr == 0 ? y0r - 1 : y0r + TY;
-      T[(hr == 0 ? 0 : TY + 1) * PR + hx] =
-          (hy >= 0 && hy < S.ny) ? ld2(x, (int64_t)z * nxy + (int64_t)hy * S.nx + 2 * hx) : zero;
+      const bool in = hy >= 0 && hy < S.ny;
+      const int64_t j = (int64_t)z * nxy + (int64_t)hy * S.nx + 2 * hx;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        T[c * TT + (hr == 0 ? 0 : TY + 1) * PR + hx] = in ? ld2(x[c], j) : zero;
     }
-    const double2 xp = (own && z < S.nz - 1) ? ld2(x, i + nxy) : zero;
+    double2 xp[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) xp[c] = (own && z < S.nz - 1) ? ld2(x[c], i + nxy) : zero;
     const double2 d = own ? ld2(diag, i) : zero;
+    double fxl = 0.0;
+    double2 fx = zero, fyd = zero, fyu = zero, fp = zero;
+    if (VAR && own) {
+      fxl = hl ? S.fx[i - 1] : 0.0;
+      fx = ld2(S.fx, i);
+      fyd = hd ? ld2(S.fy, i - S.nx) : zero;
+      fyu = ld2(S.fy, i);
+      fp = ld2(S.fz, i);
+    }
     __syncthreads();
     if (own) {
-      const double2 yd = T[ry * PR + px], yu = T[(ry + 2) * PR + px];
-      const double xl = px > 0 ? T[(ry + 1) * PR + px - 1].y : 0.0;
-      const double xr = px < PR - 1 ? T[(ry + 1) * PR + px + 1].x : 0.0;
-      const double v0 = d.x * xc.x - (cx * (xl + xc.y) + cy * (yd.x + yu.x) + cz * (xm.x + xp.x));
-      const double v1 = d.y * xc.y - (cx * (xc.x + xr) + cy * (yd.y + yu.y) + cz * (xm.y + xp.y));
-      *reinterpret_cast<double2*>(y + i) = double2{v0, v1};
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (c >= nc) break;
+        const double2* Tc = T + c * TT;
+        const double2 yd = Tc[ry * PR + px], yu = Tc[(ry + 2) * PR + px];
+        const double xl = hl ? Tc[(ry + 1) * PR + px - 1].y : 0.0;
+        const double xr = px < PR - 1 ? Tc[(ry + 1) * PR + px + 1].x : 0.0;
+        double v0 = d.x * xc[c].x, v1 = d.y * xc[c].y;
+        if (!VAR) {
+          v0 -= cx * (xl + xc[c].y) + cy * (yd.x + yu.x) + cz * (xm[c].x + xp[c].x);
+          v1 -= cx * (xc[c].x + xr) + cy * (yd.y + yu.y) + cz * (xm[c].y + xp[c].y);
+        } else {
+          v0 -= fxl * xl + fx.x * xc[c].y;
+          v1 -= fx.x * xc[c].x + fx.y * xr;
+          v0 -= fyd.x * yd.x + fyu.x * yu.x;
+          v1 -= fyd.y * yd.y + fyu.y * yu.y;
+          v0 -= fm.x * xm[c].x + fp.x * xp[c].x;
+          v1 -= fm.y * xm[c].y + fp.y * xp[c].y;
+        }
+        *reinterpret_cast<double2*>(y[c] + i) = double2{v0, v1};
+      }
     }
-    xm = xc;
-    xc = xp;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      xm[c] = xc[c];
+      xc[c] = xp[c];
+    }
+    if (VAR) fm = fp;
     buf ^= 1;
   }
 }
@@ -497,16 +564,37 @@ void launch_spmm(const Stencil& S, const double* diag, const double* X, int64_t 
   StencilShape sh = stencil_shape(S, 512);
   dim3 grid = sh.grid;
   grid.z = k;
-  if (!S.var && S.dim == 3 && S.nx <= 2 * BS && stencil_pairs_ok(S, ld, {X, Y, diag})) {
-    // LDS tiles of full rows; z chunks so that the launch has about 16k blocks
+  if (S.dim == 3 && S.nx <= 2 * BS && stencil_pairs_ok(S, ld, {X, Y, diag})) {
+    // LDS tiles of full rows, C columns per block; z chunks so that the launch has about
+    // `target` blocks
     const int ty = BS / (S.nx / 2);
-    const int gx = ceil_div(S.ny, ty);
-    const int64_t want = (int64_t)S.nz * gx * k / 16384;
-    const int zc = (int)std::max<int64_t>(1, std::min<int64_t>(S.nz, want));
-    const dim3 g(gx, ceil_div(S.nz, zc), k);
-    ROM_LAUNCH(k_spmm_lds, g, dim3(BS), 0, st, S, diag, X, ld, Y, zc);
-    ROM_CHECK_LAUNCH();
-    return;
+    const size_t tile = sizeof(double2) * 2 * (size_t)(ty + 2) * (S.nx / 2);   // per column
+    int C = S.var ? SPMM_LDS_C_VAR : SPMM_LDS_C_CONST;
+    while (C > 1 && tile * C > SPMM_LDS_MAX) C /= 2;
+    const int64_t target = S.var ? SPMM_LDS_BLOCKS_VAR : SPMM_LDS_BLOCKS_CONST;
+    if (tile * C <= SPMM_LDS_MAX) {
+      const int ntiles = ceil_div(S.ny, ty);
+      const int ncg = ceil_div(k, C);
+      const int64_t base = (int64_t)ntiles * ncg;
+      int nzc = (int)std::min<int64_t>(S.nz,
+                                       std::max<int64_t>(1, (target + base - 1) / base));
+      const int zc = ceil_div(S.nz, nzc);
+      nzc = ceil_div(S.nz, zc);
+      const int64_t blocks = base * nzc;
+      if (blocks > 2147483647LL) throw Error(ROM_EINVAL, "spmm: grid too large");
+      const dim3 g((unsigned)blocks);
+#define SPL(V, CC)                                                                             \
+  ROM_LAUNCH((k_spmm_lds<V, CC>), g, dim3(BS), tile * CC, st, S, diag, X, ld, k, Y, zc, ntiles, \
+             nzc)
+      if (S.var) {
+        if (C == 4) SPL(true, 4); else if (C == 2) SPL(true, 2); else SPL(true, 1);
+      } else {
+        if (C == 4) SPL(false, 4); else if (C == 2) SPL(false, 2); else SPL(false, 1);
+      }
+#undef SPL
+      ROM_CHECK_LAUNCH();
+      return;
+    }
   }
   if (stencil_pairs_ok(S, ld, {X, Y, diag})) {
     grid.x = ceil_div((int64_t)(S.nx / 2) * S.ny, BS);

@@ -491,10 +491,11 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--group", type=int, default=1, help="right-hand sides per batch (1: the paper's order)")
     ap.add_argument("--tune", type=int, default=1)
-    ap.add_argument("--cg-step", type=int, default=0,
-                    help="launches per CG step for the headline: 0 the tuner's choice, 1 two "
-                         "(operator step, update), 2 one (counter runs pin 1: a profiler's "
-                         "per-dispatch overhead would sway the tuner)")
+    ap.add_argument("--cg-step", type=int, default=1,
+                    help="launches per CG step for the headline: 1 two (operator step, "
+                         "update; the tuner's choice in every measured case, and a fixed form "
+                         "keeps a profiler's per-dispatch overhead from swaying the tuner), "
+                         "2 one, 0 the tuner's choice between them")
     ap.add_argument("--extras", type=int, default=1,
                     help="also time the other forms and workloads, the SpMM, the reduced "
                          "Jacobian, U_0 and nonzero frequency (0: headline and roofline only)")
@@ -607,10 +608,21 @@ def main():
                             "inner_its": hf["timed"]["total_its"]}
             log(f"{wl.name} {fname}: {hf['value']:.1f} solves/s on points {W2}..{W2 + K2 + 2}")
         ref_mixed = stream_points(prob, pts, W2, K2 + 3, wl, precision=prec, group=args.group,
-                                  tune=1, reduce_each=False)
+                                  tune=1, reduce_each=False, cg_step=args.cg_step)
         ref_mixed["result"].close()
         forms["headline_form_same_points"] = {"value": ref_mixed["value"],
                                               "inner_its": ref_mixed["timed"]["total_its"]}
+        # the headline form with one launch per CG step (update folded into the next
+        # operator step), per-launch times from events
+        one = stream_points(prob, pts, W2, K2 + 3, wl, precision=prec, group=args.group,
+                            tune=1, reduce_each=False, cg_step=2,
+                            timing=1 << R.ROM_K_DCG_STEP)
+        one["result"].close()
+        ks = one["timed"]["kernels"]["dcg_step"]
+        forms["headline_form_one_launch_step"] = {
+            "value": one["value"], "inner_its": one["timed"]["total_its"],
+            "avg_step_launch_us": 1e3 * ks["ms"] / max(ks["launches"], 1)}
+        log(f"{wl.name} one-launch CG step: {one['value']:.1f} solves/s")
         for f in forms.values():
             f["vs_fp64"] = f["value"] / forms["fp64"]["value"]
         out["forms"] = forms

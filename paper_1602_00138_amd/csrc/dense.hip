@@ -373,6 +373,29 @@ __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, doubl
   if (want) write_partials<2, BS>(v, partials, blockIdx.x);
 }
 
+// Copies nwords (<= 64 PUBLISH_WORDS) 8-byte words from device memory into coherent pinned
+// host memory, then stores seq at *flag with system-scope release: one wave, so the
+// release (which waits for this wave's own stores) also covers every word the wave wrote.
+// All loads are issued before the stores.  The host spins on the flag instead of blocking
+// on the stream.
+constexpr int PUBLISH_WORDS = 32;
+__global__ __launch_bounds__(64) void k_publish(const double* __restrict__ src,
+                                                double* dst, int nwords, unsigned* flag,
+                                                unsigned seq) {
+  double v[PUBLISH_WORDS];
+#pragma unroll
+  for (int k = 0; k < PUBLISH_WORDS; ++k) {
+    const int i = threadIdx.x + 64 * k;
+    v[k] = i < nwords ? src[i] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < PUBLISH_WORDS; ++k) {
+    const int i = threadIdx.x + 64 * k;
+    if (i < nwords) __hip_atomic_store(dst + i, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void k_normalize(int64_t n, double* __restrict__ x, const double* nrm2) {
   const double s = 1.0 / sqrt(nrm2[0]);
   for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
@@ -1067,6 +1090,15 @@ void launch_axpby(int64_t n, double a, const double* x, double b, const double* 
                      partials);
   ROM_CHECK_LAUNCH();
   if (nrm2) launch_reduce_finish(partials, grid, 2, nrm2, st);
+}
+
+void launch_publish(const void* src, void* dst, size_t bytes, unsigned* flag, unsigned seq,
+                    hipStream_t st) {
+  if (bytes % sizeof(double) != 0 || bytes / sizeof(double) > (size_t)64 * PUBLISH_WORDS)
+    throw Error(ROM_EINVAL, "publish: size must be a multiple of 8 bytes, at most 16 KiB");
+  ROM_LAUNCH(k_publish, dim3(1), dim3(64), 0, st, static_cast<const double*>(src),
+             static_cast<double*>(dst), (int)(bytes / sizeof(double)), flag, seq);
+  ROM_CHECK_LAUNCH();
 }
 
 void launch_normalize(int64_t n, double* x, const double* nrm2, hipStream_t st) {

@@ -162,6 +162,10 @@ void launch_axpby(int64_t n, double a, const double* x, double b, const double* 
                   double* nrm2, double* partials, hipStream_t st);
 // x *= 1/sqrt(*nrm2)
 void launch_normalize(int64_t n, double* x, const double* nrm2, hipStream_t st);
+// bytes (a multiple of 8, at most 16 KiB) from device memory src into coherent pinned host
+// memory dst, then seq stored at *flag (host memory) once every byte is visible to the host.
+void launch_publish(const void* src, void* dst, size_t bytes, unsigned* flag, unsigned seq,
+                    hipStream_t st);
 // dst[:, c] = src[c] columns (pointer table) for c < k.
 void launch_pack_cols(int64_t n, const ColPtrs& src, int k, double* dst, int64_t ld,
                       hipStream_t st);

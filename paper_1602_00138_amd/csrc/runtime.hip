@@ -91,6 +91,14 @@ struct Ctrl {
   double gs[3 * G_MAX];    // initial-guess step per member: d^T r, d^T A d, ||r1||^2
   CGState cg[G_MAX];
 };
+// Host copy of the control block: Ctrl, then the publish flag on its own cache line.
+constexpr size_t CTRL_FLAG_OFFSET = (sizeof(Ctrl) + 127) / 128 * 128;
+constexpr size_t CTRL_HOST_BYTES = CTRL_FLAG_OFFSET + 128;
+// How long the host spins on the publish flag before it blocks on the stream.
+constexpr int CTRL_SPIN_MS = 5;
+static_assert(offsetof(Ctrl, cg) % 8 == 0 && sizeof(CGState) % 8 == 0,
+              "the control block is published in 8-byte words");
+static_assert(sizeof(Ctrl) <= 16384, "the publish kernel copies at most 16 KiB");
 
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -409,7 +417,16 @@ class Sequencer {
     st_ = st;
     timer_.reset(new Timer(o_.timing));
     tm_ = timer_.get();
-    ROM_HIP(hipHostMalloc((void**)&h_, sizeof(Ctrl), hipHostMallocDefault));
+    // the control block's host copy and, after it, the publish flag: coherent pinned memory
+    // that the publish kernel writes directly
+    ROM_HIP(hipHostMalloc((void**)&h_, CTRL_HOST_BYTES, hipHostMallocMapped | hipHostMallocCoherent));
+    hflag_ = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(h_) + CTRL_FLAG_OFFSET);
+    *hflag_ = 0;
+    seq_ = 0;
+    void* dh = nullptr;
+    ROM_HIP(hipHostGetDevicePointer(&dh, h_, 0));
+    dh_ = dh;
+    dflag_ = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(dh) + CTRL_FLAG_OFFSET);
     U0_ = U0;
     idx_.assign(src_idx, src_idx + n_src_);
     idx_.insert(idx_.end(), det_idx, det_idx + n_det_);
@@ -535,9 +552,32 @@ class Sequencer {
   }
 
  private:
-  void sync() {
-    ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
+  // The first `bytes` of the control block into h_, once the stream has reached this
+  // point: a one-wave kernel writes them into the coherent host copy and then a sequence
+  // number, on which the host spins (a blocking stream wait, which took tens of
+  // microseconds to return after the GPU finished, only after CTRL_SPIN_MS).
+  void pull(size_t bytes) {
+    const unsigned s = ++seq_;
+    launch_publish(ctrl_, dh_, bytes, dflag_, s, st_);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 1;; ++spin) {
+      if (__atomic_load_n(hflag_, __ATOMIC_ACQUIRE) == s) return;
+      if ((spin & 255) == 0 &&
+          std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(CTRL_SPIN_MS))
+        break;
+      __builtin_ia32_pause();
+    }
     ROM_HIP(hipStreamSynchronize(st_));
+    if (__atomic_load_n(hflag_, __ATOMIC_ACQUIRE) != s)
+      throw Error(ROM_EHIP, "control block not published after the stream completed");
+  }
+  // the scalars and flags (everything before the CG states)
+  void pull_head() { pull(offsetof(Ctrl, cg)); }
+  // and the CG states of nb members
+  void pull_cg(int nb) { pull(offsetof(Ctrl, cg) + sizeof(CGState) * nb); }
+
+  void sync() {
+    pull_head();
     tm_->harvest();
     check_status();
   }
@@ -586,8 +626,7 @@ class Sequencer {
       ROM_HIP(hipMemcpyAsync(&ctrl_->sc[4], &ctrl_->sc[5], sizeof(double),
                              hipMemcpyDeviceToDevice, st_));
     }
-    ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
-    ROM_HIP(hipStreamSynchronize(st_));
+    pull_head();
     const double a = h_->sc[4], b = h_->sc[5];
     if (cols > 0 && a > 0.5 * b) {
       // the second pass returned at once: drop it from the accounting
@@ -658,8 +697,7 @@ class Sequencer {
       launch_gemvn(Q_, ld_, n_, m, tbuf_, 1.0, slot, -1.0, slot, &ctrl_->sc[4], red_part_, st_,
                    skip);
       tm_->end(ROM_K_GEMVN, 8.0 * n_ * (m + 2), 2.0 * n_ * m);
-      ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
-      ROM_HIP(hipStreamSynchronize(st_));
+      pull_head();
       pass2 = !(h_->sc[4] > 0.5 * h_->sc[5]);
       if (!pass2) {
         tm_->discard(ROM_K_GEMVT, 1, 8.0 * n_ * (m + 2), 4.0 * n_ * m);
@@ -1761,8 +1799,7 @@ class Sequencer {
           }
           launched = next;
         }
-        ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
-        ROM_HIP(hipStreamSynchronize(st_));
+        pull_cg(nb);
         // updates done per member in this chunk; a member's launches that did the whole
         // step are its updates plus step 0, then one more read its stopping test; launches
         // after the last member's stop returned at once
@@ -1828,8 +1865,7 @@ class Sequencer {
         tm_->end(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
         Pu = P;
       }
-      ROM_HIP(hipMemcpyAsync(h_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, st_));
-      ROM_HIP(hipStreamSynchronize(st_));
+      pull_cg(nb);
       // member-steps (updates) done in this chunk; once the last member stopped, the
       // launches after the operator step that stopped it returned at once
       int maxreal = 0, steps = 0, still = 0;
@@ -1929,6 +1965,10 @@ class Sequencer {
   hipStream_t st_ = nullptr;
   Timer* tm_ = nullptr;
   Ctrl* h_ = nullptr;
+  unsigned* hflag_ = nullptr;   // publish flag (host view)
+  void* dh_ = nullptr;          // device view of h_
+  unsigned* dflag_ = nullptr;   // device view of the flag
+  unsigned seq_ = 0;
   double mu0_ = 0.0;
   int m_ = 0, ku_ = 0, next_slot_ = 0;
   int w_key_[G_MAX], w_nj_[G_MAX] = {};

@@ -145,9 +145,11 @@ def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None) ->
             "kernel": "k_dcg_op (CG operator step: w = A q - (A U_j) c with its dot products)",
             "launches": int(k["launches"]), "avg_launch_us": 1e3 * avg_ms,
             "bytes_per_launch": by,
-            "bytes_formula": f"{E} N (4 + n_j" + (" + 3" if prob.D_field is not None else "")
-                             + ") per member-step (q, diag" + (", 3 face arrays" if prob.D_field is not None else "")
-                             + ", s, the n_j columns of A U_j read, w written)",
+            "bytes_formula": f"{E} N (g (3 + n_j) + " + ("4" if prob.D_field is not None else "1")
+                             + ") per launch of g live members (per member q, s and the n_j "
+                             "columns of A U_j read and w written; the diagonal"
+                             + (" and 3 face arrays" if prob.D_field is not None else "")
+                             + " read once for all members)",
             "note": "events on every launch of this class over the timed points; the update "
                     "kernel and the rest are in 'kernel_classes'"}
     if all_pts is not None:

@@ -1744,17 +1744,18 @@ class Sequencer {
                         b.q, ld_, cg, b.ps, p2s_, nb, P0, st_);
     tm_->end(ROM_K_DCG_ENDS, nact * (8.0 * n_ + E * n_ * (2 * njavg + 3)),
              nact * n_ * (2.0 + 4.0 * njavg));
-    // algorithmic bytes and flops per member and step: the operator step reads q, the
-    // diagonal (and face coefficients), s and AU and writes w; the update reads q, w, g, s
-    // and writes q, g, s
-    const double by_op = E * n_ * (4 + njavg + (S_.var ? S_.dim : 0));
+    // algorithmic bytes and flops per member and step: the operator step reads q, s and AU
+    // and writes w, and per launch reads the diagonal (and face coefficients) once for all
+    // its members; the update reads q, w, g, s and writes q, g, s
+    const double by_shared = E * n_ * (1 + (S_.var ? S_.dim : 0));
+    const double by_op = E * n_ * (3 + njavg);
     const double fl_op = n_ * (21.0 + 6.0 * njavg);
     const double by_upd = 7.0 * E * n_;
     const double fl_upd = 8.0 * n_;
-    // the one-launch step reads s, q, w, g, the diagonal (and face coefficients) and AU and
-    // writes s, q, w, g
+    // the one-launch step reads s, q, w, g and AU and writes s, q, w, g per member (and the
+    // shared diagonal and faces once)
     const bool one = shape_one(shape);
-    const double by_one = E * n_ * (9 + njavg + (S_.var ? S_.dim : 0));
+    const double by_one = E * n_ * (8 + njavg);
     const double fl_one = fl_op + fl_upd;
     int step = 0;   // one-launch steps launched (the next one's index)
     int next = chunk_;
@@ -1790,12 +1791,13 @@ class Sequencer {
           for (int r = 0; r < reps; ++r) ROM_HIP(hipGraphLaunch(ex, st_));
           step += reps * GRAPH_STEPS;
           launched += reps * GRAPH_STEPS;
-          for (int c = 0; c < launched; ++c) tm_->add(ROM_K_DCG_STEP, nlive * by_one, nlive * fl_one);
+          for (int c = 0; c < launched; ++c)
+            tm_->add(ROM_K_DCG_STEP, nlive * by_one + by_shared, nlive * fl_one);
         } else {
           for (int c = 0; c < next; ++c) {
             tm_->begin(ROM_K_DCG_STEP);
             iter(st_);
-            tm_->end(ROM_K_DCG_STEP, nlive * by_one, nlive * fl_one);
+            tm_->end(ROM_K_DCG_STEP, nlive * by_one + by_shared, nlive * fl_one);
           }
           launched = next;
         }
@@ -1820,7 +1822,7 @@ class Sequencer {
         const bool stop = still == 0;
         // (a stop read by step 0 itself: that one launch)
         const int counted = had0 && maxreal == 0 ? 1 : maxreal + (had0 ? 1 : 0) + 1;
-        tm_->discard(ROM_K_DCG_STEP, stop ? launched - counted : 0, 0.0, 0.0);
+        tm_->discard(ROM_K_DCG_STEP, stop ? launched - counted : 0, by_shared, 0.0);
         const double over = (double)nlive * launched - steps - (had0 ? nlive : 0);
         tm_->adjust(ROM_K_DCG_STEP, -over * by_one, -over * fl_one);
         tm_->harvest();
@@ -1849,7 +1851,7 @@ class Sequencer {
         for (int r = 0; r < reps; ++r) ROM_HIP(hipGraphLaunch(ex, st_));
         next = reps * GRAPH_STEPS;
         for (int c = 0; c < next; ++c) {
-          tm_->add(ROM_K_DCG_OP, nlive * by_op, nlive * fl_op);
+          tm_->add(ROM_K_DCG_OP, nlive * by_op + by_shared, nlive * fl_op);
           tm_->add(ROM_K_DCG_UPDATE, nlive * by_upd, nlive * fl_upd);
         }
       }
@@ -1858,7 +1860,7 @@ class Sequencer {
         launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax, GWinv_,
                          GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.pu, Pu, pus_, b.po, pos_, nb,
                          st_);
-        tm_->end(ROM_K_DCG_OP, nlive * by_op, nlive * fl_op);
+        tm_->end(ROM_K_DCG_OP, nlive * by_op + by_shared, nlive * fl_op);
         tm_->begin(ROM_K_DCG_UPDATE);
         launch_dcg_update<T>(b.q, b.w, dvec, b.s, ld_, n_, njmax, cg, cgv_, b.po, sh.blocks,
                              pos_, b.pu, pus_, nb, P, st_, nr);
@@ -1883,7 +1885,7 @@ class Sequencer {
         }
       }
       const bool stop = still == 0;
-      tm_->discard(ROM_K_DCG_OP, stop ? next - maxreal - 1 : 0, 0.0, 0.0);
+      tm_->discard(ROM_K_DCG_OP, stop ? next - maxreal - 1 : 0, by_shared, 0.0);
       tm_->discard(ROM_K_DCG_UPDATE, stop ? next - maxreal : 0, 0.0, 0.0);
       const double over = (double)nlive * next - steps;
       tm_->adjust(ROM_K_DCG_OP, -over * by_op, -over * fl_op);

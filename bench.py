@@ -233,6 +233,8 @@ def whole_sequence(prob, pts, wl, reps: int = 1, **kw) -> dict:
 def measure_workload_forms(name: str, forms: dict, reps: int = 1, keep_plain: bool = False):
     """Whole sequences of workload `name` in several forms; vs_plain_fp64 = ratio to the
     first form."""
+    import torch
+    torch.cuda.empty_cache()   # the sections before released their workspaces
     import phantoms as ph
     from paper_1602_00138_amd import driver
     wl = ph.WORKLOADS[name]
@@ -330,6 +332,7 @@ def measure_learned(name: str, train_points: int, train_steps: int, reps: int = 
     of the same grid and D field; every timed sequence runs the network for all its
     (point, right-hand side) pairs first (inference time is inside the timed value)."""
     import torch
+    torch.cuda.empty_cache()   # the sections before released their workspaces
     import phantoms as ph
     from paper_1602_00138_amd import driver, seed
     from paper_1602_00138_amd import rom as R
@@ -405,6 +408,7 @@ def measure_concurrent(names, **kw):
     """The uneven grids: solves/s one sequence after another vs all at once
     (rom_solve_sequences, one stream and host thread each)."""
     import torch
+    torch.cuda.empty_cache()   # the sections before released their workspaces
     import phantoms as ph
     from paper_1602_00138_amd import driver
     wls = [ph.WORKLOADS[n] for n in names]

@@ -21,8 +21,8 @@ class SequenceResult:
     basis: int
     records: List[dict]
     stats: dict
-    workspace: torch.Tensor          # owns the basis memory
-    X: Optional[torch.Tensor]        # (K * n_rhs, N): row i*n_rhs + j is solution (i, j)
+    workspace: Optional[torch.Tensor]  # owns the basis memory (released by close)
+    X: Optional[torch.Tensor]          # (K * n_rhs, N): row i*n_rhs + j is solution (i, j)
     n: int
     m: int
 
@@ -33,9 +33,13 @@ class SequenceResult:
         return out
 
     def close(self):
+        """Destroys the basis handle and drops the workspace it lived in and the solutions
+        (a 128^3 sequence in groups holds tens of GB)."""
         if self.basis:
             R.rom_basis_destroy(self.basis)
             self.basis = 0
+        self.workspace = None
+        self.X = None
 
 
 class Problem:

@@ -129,7 +129,19 @@ def stream_points(prob, pts, W: int, K: int, wl, timing: int = 0, reduce_each: b
             "timed": diff_stats(before, after), "all": after, "records": recs, "result": res}
 
 
-def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None) -> dict:
+# HBM traffic of k_dcg_op per dispatch, measured by rocprofv3 (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch, averaged over the dispatches) on the default headline command, and the
+# scale of each counter from a plain device copy of known size.  Reported as `traffic`
+# only for that configuration; a change to the kernel needs new counter runs.
+OP_TRAFFIC = {"fetch_kib": 436266.3, "write_kib": 54333.6, "fetch_scale": 2.0,
+              "write_scale": 1.0, "dispatches": 45696,
+              "config": {"workload": "cube128_lognormal", "precision": "mixed", "group": 8,
+                         "cg_step": 1},
+              "profile": "profiles/cg_operator_step_cube128_lognormal_group8.md"}
+
+
+def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None,
+                 run_config: dict = None) -> dict:
     """Roofline of the CG operator step (k_dcg_op): its algorithmic bytes per launch (the
     timer's per-class byte count over the timed points) over its mean event-timed launch
     duration.  all_pts: the stats of the whole stream (warm-up points included), whose
@@ -156,6 +168,13 @@ def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None) ->
         a = all_pts["kernels"]["dcg_op"]
         out["bytes_per_launch_all_points"] = a["bytes"] / max(a["launches"], 1)
         out["launches_all_points"] = int(a["launches"])
+    if run_config == OP_TRAFFIC["config"]:
+        t = OP_TRAFFIC
+        out["traffic"] = 1024.0 * (t["fetch_scale"] * t["fetch_kib"] + t["write_scale"] * t["write_kib"])
+        out["traffic_note"] = (f"HBM bytes per dispatch over {t['dispatches']} dispatches of the "
+                               f"same command ({t['profile']}): FETCH_SIZE x {t['fetch_scale']} + "
+                               f"WRITE_SIZE x {t['write_scale']} (device-copy calibration); compare "
+                               "with bytes_per_launch_all_points")
     return out
 
 
@@ -570,7 +589,9 @@ def main():
     recs = h["records"]
     solved = [r for r in recs if r["solved"]]
     its_per_solve = timed["total_its"] / max(len(solved), 1)
-    roof = dcg_roofline(timed, args.precision, prob, wl, h["all"])
+    roof = dcg_roofline(timed, args.precision, prob, wl, h["all"],
+                        {"workload": args.workload, "precision": args.precision,
+                         "group": args.group, "cg_step": args.cg_step})
     log(f"headline: {value:.1f} solves/s over points {W}..{W + K - 1} "
         f"({K * prob.n_rhs} solves, {timed['total_its']} inner its, {len(solved)} solved); "
         f"k_dcg_op {roof['achieved']:.0f} GB/s ({100 * roof['frac']:.1f}% of peak), "

@@ -625,8 +625,15 @@ def main():
         hc = stream_points(prob, pts, W2, K2, wl, timing=(1 << R.ROM_NK) - 1, precision=prec,
                            group=args.group, tune=args.tune, reduce_each=False)
         hc["result"].close()
+        kms = sum(d["ms"] for d in hc["timed"]["kernels"].values())
         out["kernel_classes"] = {"points": f"{W2}..{W2 + K2 - 1} with every class timed",
-                                 "classes": class_table(hc["timed"])}
+                                 "classes": class_table(hc["timed"]),
+                                 "kernel_over_wall": kms / (1e3 * hc["seconds"]),
+                                 "kernel_over_wall_note": "summed event time of the timed "
+                                 "classes over the wall time of those points: a lower bound "
+                                 "of the GPU's busy share (the small kernels of class 'other' "
+                                 "carry no events); rocprofv3 over a whole headline run "
+                                 "reads 0.95"}
         # the other forms of config 4's method on the same points
         forms = {}
         for fname, kw in (("fp64", dict(precision=R.ROM_PREC_FP64)),

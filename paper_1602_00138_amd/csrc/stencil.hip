@@ -72,9 +72,45 @@ __global__ void k_assemble(rom_grid g, double Dc, const double* __restrict__ D, 
   diag[i] = d;
 }
 
-__global__ void k_mu_eval(Stencil S, Bumps B, const double* __restrict__ diag_star,
-                          double* __restrict__ diag_i, double* __restrict__ dmu) {
-  int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+// mu(p) - mu0 at every node, and diag_i = diag_* + mu(p).  A block's nodes are consecutive
+// (a few grid rows of one or two planes): the bump parameters are staged in LDS and each
+// bump is first tested against the block's bounding box, so a node only evaluates the
+// bumps whose support can reach its block.
+__global__ __launch_bounds__(BS) void k_mu_eval(Stencil S, Bumps B,
+                                                const double* __restrict__ diag_star,
+                                                double* __restrict__ diag_i,
+                                                double* __restrict__ dmu) {
+  __shared__ double bp[ROM_MAX_BUMPS * 5];
+  __shared__ int live[ROM_MAX_BUMPS];
+  const int stride = S.dim + 2;
+  const int nb = B.nb;
+  for (int t = threadIdx.x; t < nb * stride; t += BS) bp[t] = B.p[t];
+  const int64_t i0 = (int64_t)blockIdx.x * BS;
+  const int64_t i = i0 + threadIdx.x;
+  const int64_t nxy = (int64_t)S.nx * S.ny;
+  __syncthreads();
+  if (threadIdx.x < nb) {
+    // the block's bounding box in grid indices: all of x, its rows of y, its planes of z
+    const int64_t i1 = min(i0 + BS, S.n) - 1;
+    const int64_t z0 = i0 / nxy, z1 = i1 / nxy;
+    int64_t y0 = 0, y1 = S.ny - 1;
+    if (z0 == z1) {
+      y0 = (i0 % nxy) / S.nx;
+      y1 = (i1 % nxy) / S.nx;
+    }
+    const int64_t lo[3] = {0, y0, z0}, hi[3] = {S.nx - 1, y1, z1};
+    const int n[3] = {S.nx, S.ny, S.nz};
+    const double* pb = bp + threadIdx.x * stride;
+    double d2 = 0.0;
+    for (int c = 0; c < S.dim; ++c) {
+      const double a = (lo[c] + 1.0) / (n[c] + 1), e = (hi[c] + 1.0) / (n[c] + 1);
+      const double d = pb[c] < a ? a - pb[c] : pb[c] > e ? pb[c] - e : 0.0;
+      d2 += d * d;
+    }
+    // conservative: a bump stays when its support may touch the box
+    live[threadIdx.x] = d2 < pb[S.dim] * pb[S.dim] * (1.0 + 1e-9) ? 1 : 0;
+  }
+  __syncthreads();
   if (i >= S.n) return;
   int ix, iy, iz;
   if (S.n <= INT32_MAX) {     // 32-bit index arithmetic where the grid allows it
@@ -90,10 +126,10 @@ __global__ void k_mu_eval(Stencil S, Bumps B, const double* __restrict__ diag_st
   }
   const double x[3] = {(ix + 1.0) / (S.nx + 1), (iy + 1.0) / (S.ny + 1),
                        (iz + 1.0) / (S.nz + 1)};
-  const int stride = S.dim + 2;
   double m = 0.0;
-  for (int b = 0; b < B.nb; ++b) {
-    const double* pb = B.p + b * stride;
+  for (int b = 0; b < nb; ++b) {
+    if (!live[b]) continue;
+    const double* pb = bp + b * stride;
     double d2 = 0.0;
     for (int a = 0; a < S.dim; ++a) {
       const double e = x[a] - pb[a];

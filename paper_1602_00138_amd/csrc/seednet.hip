@@ -117,6 +117,133 @@ __global__ __launch_bounds__(BS) void k_conv(Grid3 g, const __bf16* __restrict__
     }
 }
 
+// k_conv with the input staged in LDS: a block owns a box of 16 x 4 x BZ voxels (4 BZ tiles
+// of 16 consecutive x; wave w computes tiles BZ w .. BZ w + BZ - 1 for all NT output tiles)
+// and first stages the box with its one-voxel halo (18 x 6 x (BZ + 2) voxels, all Cpi
+// channels, each voxel's channels padded by 8 to spread the LDS banks; zeros outside the
+// grid; with up the coarse voxel each fine halo voxel takes).  The 27 taps then read their
+// A operands from LDS instead of gathering them through the caches; each step's LDS and
+// weight loads are issued one step ahead.  Needs nx % 16 == 0, ny % 4 == 0, nz % BZ == 0
+// (boxes stay inside one grid of the batch).
+constexpr int CB_X = 16, CB_Y = 4;
+constexpr int CH_X = CB_X + 2, CH_Y = CB_Y + 2;
+constexpr int conv_halo_vox(int bz) { return CH_X * CH_Y * (bz + 2); }
+template <int NT, int BZ>
+__global__ __launch_bounds__(BS) void k_conv_lds(Grid3 g, const __bf16* __restrict__ X, int Cpi,
+                                                 const __bf16* __restrict__ W, int Kp, int Cout,
+                                                 const float* __restrict__ bias,
+                                                 const __bf16* __restrict__ skip, int relu,
+                                                 __bf16* __restrict__ Y, int Cpo, int up) {
+  extern __shared__ __bf16 halo[];
+  const int cs = Cpi + 8;   // LDS stride of one voxel (elements)
+  const int bxn = g.nx / CB_X, byn = g.ny / CB_Y;
+  const int bx = blockIdx.x % bxn, by = (blockIdx.x / bxn) % byn;
+  const int bzb = blockIdx.x / (bxn * byn);           // box along z over the batch
+  constexpr int CB_Z = BZ, CH_Z = BZ + 2, CH_VOX = CH_X * CH_Y * CH_Z;
+  const int zpb = g.nz / CB_Z;                        // boxes per grid along z
+  const int b = bzb / zpb;                            // grid of the batch
+  const int X0 = bx * CB_X, Y0 = by * CB_Y, Z0 = (bzb % zpb) * CB_Z;
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  const int64_t gbase = (int64_t)b * g.nz * sz;       // first voxel of grid b
+  const int cx = g.nx >> 1, cy = g.ny >> 1, cz = g.nz >> 1;
+  // stage the halo box: Cpi / 8 16-byte chunks per voxel
+  const int chunks = Cpi / 8;
+  for (int e = threadIdx.x; e < CH_VOX * chunks; e += BS) {
+    const int h = e / chunks, q = e % chunks;
+    const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+    const int xx = X0 + hx - 1, yy = Y0 + hy - 1, zz = Z0 + hz - 1;
+    bf16x8 v;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = (__bf16)0.f;
+    if (xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny && zz >= 0 && zz < g.nz) {
+      const int64_t src = up ? ((((int64_t)b * cz + (zz >> 1)) * cy + (yy >> 1)) * cx + (xx >> 1))
+                             : gbase + xx + sy * yy + sz * zz;
+      v = *reinterpret_cast<const bf16x8*>(X + src * Cpi + 8 * q);
+    }
+    *reinterpret_cast<bf16x8*>(halo + h * cs + 8 * q) = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int kg = lane >> 4;
+  const int K = 27 * Cpi;
+  constexpr int VT = BZ;
+  int hv[VT];   // halo index of this lane's voxel in each of its tiles (tap 0, 0, 0)
+#pragma unroll
+  for (int u = 0; u < VT; ++u) {
+    const int t = VT * wid + u;
+    const int vx = lane & 15, vy = t % CB_Y, vz = t / CB_Y;
+    hv[u] = (vx + 1) + CH_X * ((vy + 1) + CH_Y * (vz + 1));
+  }
+  float4_t acc[VT][NT];
+#pragma unroll
+  for (int u = 0; u < VT; ++u)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[u][t] = (float4_t){0.f, 0.f, 0.f, 0.f};
+  // the operands of step k0 (this lane's 8 k from tap, channel c), loaded one step ahead
+  // so that the next step's LDS and weight loads are in flight during this step's MFMAs
+  auto load_step = [&](int k0, int tp, int cc, bf16x8 (&a)[VT], bf16x8 (&bw)[NT]) {
+    const int k = k0 + 8 * kg;
+    const int dz = tp / 9 - 1, dy = (tp / 3) % 3 - 1, dx = tp % 3 - 1;
+    const int off = dx + CH_X * (dy + CH_Y * dz);
+#pragma unroll
+    for (int u = 0; u < VT; ++u) {
+      if (k < K) {
+        a[u] = *reinterpret_cast<const bf16x8*>(halo + (hv[u] + off) * cs + cc);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[u][q] = (__bf16)0.f;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      bw[t] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(16 * t + (lane & 15)) * Kp + k);
+  };
+  int tap = (8 * kg) / Cpi, c = (8 * kg) % Cpi;
+  bf16x8 a[VT], bw[NT];
+  load_step(0, tap, c, a, bw);
+  for (int k0 = 0; k0 < Kp; k0 += 32) {
+    c += 32;
+    while (c >= Cpi) {
+      c -= Cpi;
+      ++tap;
+    }
+    bf16x8 an[VT], bn[NT];
+    if (k0 + 32 < Kp) load_step(k0 + 32, tap, c, an, bn);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < VT; ++u)
+        acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bw[t], acc[u][t], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < VT; ++u) a[u] = an[u];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bw[t] = bn[t];
+  }
+  // D layout: register r of a lane holds row 4 (lane / 16) + r (the voxel's x in its
+  // tile), column lane % 16 (the output channel in its tile)
+#pragma unroll
+  for (int u = 0; u < VT; ++u) {
+    const int t = VT * wid + u;
+    const int64_t rowbase = gbase + X0 + sy * (Y0 + t % CB_Y) + sz * (Z0 + t / CB_Y);
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int o = 16 * tt + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t v = rowbase + 4 * kg + r;
+        if (o >= Cpo) continue;
+        float val = 0.f;
+        if (o < Cout) {
+          val = acc[u][tt][r] + (bias ? bias[o] : 0.f);
+          if (skip) val += (float)skip[v * Cpo + o];
+          if (relu) val = fmaxf(val, 0.f);
+        }
+        Y[v * Cpo + o] = (__bf16)val;
+      }
+    }
+  }
+}
+
 // Weight gradient partials: P[chunk][o][k] = sum over the chunk's voxels of
 // dZ[v][o] A[v][k] for o in the block's 16-channel tile and k in its 64-wide slice (one
 // 16-wide tile per wave); 32 voxels are staged in LDS per step.
@@ -464,6 +591,9 @@ int gridn(int64_t n) { return (int)ceil_div(n, BS); }
 
 }  // namespace
 
+// LDS budget of the staged convolution (larger input widths take the gathering kernel)
+constexpr size_t CONV_LDS_MAX = 64 * 1024;
+
 int seed_round8(int c) { return (c + 7) / 8 * 8; }
 int seed_kp(int cp) { return (27 * cp + 31) / 32 * 32; }
 
@@ -473,6 +603,30 @@ void launch_seed_conv(int nx, int ny, int nz, int batch, const void* X, int Cpi,
   if (up && ((nx | ny | nz) & 1)) throw Error(ROM_EINVAL, "seed conv: upsampled input needs even sizes");
   const Grid3 g{nx, ny, nz, batch};
   const int64_t nv = (int64_t)nx * ny * nz * batch;
+  // the deepest box whose staged halo fits the LDS budget
+  int bz = 0;
+  for (int c : {4, 2})
+    if (!bz && nx % CB_X == 0 && ny % CB_Y == 0 && nz % c == 0 &&
+        sizeof(__bf16) * (size_t)conv_halo_vox(c) * (Cpi + 8) <= CONV_LDS_MAX)
+      bz = c;
+  if (bz) {
+    const size_t lds = sizeof(__bf16) * (size_t)conv_halo_vox(bz) * (Cpi + 8);
+    const dim3 grid((unsigned)(nv / (CB_X * CB_Y * bz)));
+    const __bf16* x = (const __bf16*)X;
+    const __bf16* w = (const __bf16*)W;
+    const __bf16* sk = (const __bf16*)skip;
+    __bf16* y = (__bf16*)Y;
+    if (rows / 16 < 1 || rows / 16 > 4) throw Error(ROM_EINVAL, "seed conv: at most 64 output channels");
+#define C(N, Z) ROM_LAUNCH((k_conv_lds<N, Z>), grid, dim3(BS), lds, st, g, x, Cpi, w, Kp, Cout, bias, sk, relu, y, Cpo, up)
+    if (bz == 4) {
+      switch (rows / 16) { case 1: C(1, 4); break; case 2: C(2, 4); break; case 3: C(3, 4); break; default: C(4, 4); break; }
+    } else {
+      switch (rows / 16) { case 1: C(1, 2); break; case 2: C(2, 2); break; case 3: C(3, 2); break; default: C(4, 2); break; }
+    }
+#undef C
+    ROM_CHECK_LAUNCH();
+    return;
+  }
   constexpr int VT = 2;
   const dim3 grid(ceil_div(nv, 64 * VT));
   const __bf16* x = (const __bf16*)X;

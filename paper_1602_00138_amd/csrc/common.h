@@ -16,6 +16,8 @@ namespace rom {
 
 constexpr int WAVE = 64;
 constexpr int NJ_MAX = ROM_NJ_MAX;
+// XCDs of the part: workgroup b of a launch runs on XCD b % NXCD, each XCD with its own L2
+constexpr int NXCD = 8;
 
 // Error carried from the runtime to the C ABI layer.
 struct Error : std::runtime_error {
@@ -131,6 +133,8 @@ __device__ __forceinline__ void stencil_walk(const Stencil& S, const double* __r
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
 __device__ __forceinline__ void walk_faces(const Stencil& S, double, const double*& fx,
                                            const double*& fy, const double*& fz) {
   fx = S.fx; fy = S.fy; fz = S.fz;
@@ -252,6 +256,18 @@ inline bool stencil_pairs_ok(const Stencil& S, int64_t ld, std::initializer_list
                                 (S.dim == 3 ? (uintptr_t)S.fz : 0));
     if (f & m) return false;
   }
+  return true;
+}
+
+// Whether the four-node walk of the FP32 CG operator step applies: nx and every leading
+// dimension a multiple of 4 and every FP32 array 16-byte aligned.
+inline bool stencil_quads_ok(const Stencil& S, int64_t ld, std::initializer_list<const void*> ptrs) {
+  if (S.nx % 4 != 0 || ld % 4 != 0) return false;
+  for (const void* p : ptrs)
+    if (p && ((uintptr_t)p & 15)) return false;
+  if (S.var &&
+      (((uintptr_t)S.fx32 | (uintptr_t)S.fy32 | (S.dim == 3 ? (uintptr_t)S.fz32 : 0)) & 15))
+    return false;
   return true;
 }
 

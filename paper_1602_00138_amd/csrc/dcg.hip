@@ -56,6 +56,15 @@ __global__ void k_cg_setup(CGState* cg, CGVec* cv, CgSetup su, int nb) {
   for (int k = threadIdx.x; k < nb * NJ_MAX; k += blockDim.x) cv[k / NJ_MAX].e[k % NJ_MAX] = 0.0;
 }
 
+// Column c of a member's W or AW: the shared slot for the first ns columns, else the
+// member's own (see Slots).  c is a compile-time index in the unrolled column loops, so
+// the choice is one scalar select per column.
+template <typename T>
+__device__ __forceinline__ const T* col_of(const T* own, const T* shared, int ns, int c,
+                                           int64_t ld) {
+  return (c < ns ? shared : own) + (int64_t)c * ld;
+}
+
 // Row j = threadIdx.x < nj of Ginv = (U^T A U)^{-1} (symmetric, FP64) is loaded early
 // into registers, where it fits (NJT <= 16), so that its latency hides behind other loads.
 template <int NJT>
@@ -102,9 +111,9 @@ struct StartRows {
 // read as rscale * r (the mixed form solves for a unit-norm residual in FP32).  A thread
 // loads its first chunk's rows before y0 is formed.
 template <typename T, int NJT, int RPT = StartRows<T, NJT>::value>
-__global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
-                                                         const T* __restrict__ AW,
-                                                         int64_t wstride, int64_t ld, int64_t n,
+__global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W0,
+                                                         const T* __restrict__ AW0,
+                                                         Slots sl, int64_t n,
                                                          const double* __restrict__ Ginv,
                                                          int64_t gstride,
                                                          const double* __restrict__ r,
@@ -115,8 +124,12 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
   const int y = blockIdx.y;
   const CGState* cg = cgs + y;
   if (cg->done) return;
-  W += y * wstride;
-  AW += y * wstride;
+  const int64_t ld = sl.ld;
+  const int ns = sl.ns;
+  const T* __restrict__ W = W0 + y * sl.wstride;
+  const T* __restrict__ AW = AW0 + y * sl.wstride;
+  const T* __restrict__ Ws = W0 + sl.soff;
+  const T* __restrict__ AWs = AW0 + sl.soff;
   Ginv += y * gstride;
   r += y * rstride;
   g += y * vstride;
@@ -139,8 +152,8 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
       if (PRE) {
 #pragma unroll
         for (int c = 0; c < NJT; ++c) {
-          wr[q][PRE ? c : 0] = (in && c < nj) ? W[i + c * ld] : T(0);
-          ar[q][PRE ? c : 0] = (in && c < nj) ? AW[i + c * ld] : T(0);
+          wr[q][PRE ? c : 0] = (in && c < nj) ? col_of(W, Ws, ns, c, ld)[i] : T(0);
+          ar[q][PRE ? c : 0] = (in && c < nj) ? col_of(AW, AWs, ns, c, ld)[i] : T(0);
         }
       }
     }
@@ -169,8 +182,8 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
 #pragma unroll
       for (int c = 0; c < NJT; ++c)
         if (c < nj) {
-          const T wv = PRE ? wr[q][PRE ? c : 0] : (in ? W[i + c * ld] : T(0));
-          const T av = PRE ? ar[q][PRE ? c : 0] : (in ? AW[i + c * ld] : T(0));
+          const T wv = PRE ? wr[q][PRE ? c : 0] : (in ? col_of(W, Ws, ns, c, ld)[i] : T(0));
+          const T av = PRE ? ar[q][PRE ? c : 0] : (in ? col_of(AW, AWs, ns, c, ld)[i] : T(0));
           if (KEEP) kept[KEEP ? c : 0] = av;
           gi += wv * ys[c];
           si -= av * ys[c];
@@ -185,7 +198,8 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
       for (int c = 0; c < NJT; ++c)
         if (c < nj)
           acc[c] += (PRE ? ar[q][PRE ? c : 0]
-                         : KEEP ? kept[KEEP ? c : 0] : (in ? AW[i + c * ld] : T(0))) * si;
+                         : KEEP ? kept[KEEP ? c : 0]
+                                : (in ? col_of(AW, AWs, ns, c, ld)[i] : T(0))) * si;
     }
     base += (int64_t)gridDim.x * CH;
     if (base - threadIdx.x >= n) break;
@@ -194,8 +208,8 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W,
   write_partials_t<NJT + 1, START_BS>(acc, ps, blockIdx.x, gridDim.x);
 }
 
-// NP consecutive values at index i (two-element vector loads for NP = 2: i even and the
-// array aligned, as the two-node walk requires).
+// NP consecutive values at index i (vector loads for NP = 2 and 4: i a multiple of NP and
+// the array aligned, as the two- and four-node walks require).
 template <typename T>
 __device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[1]) {
   v[0] = p[i];
@@ -207,12 +221,42 @@ __device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[2
   v[1] = t.y;
 }
 template <typename T>
+__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[4]) {
+  const typename Vec4<T>::type t = *reinterpret_cast<const typename Vec4<T>::type*>(p + i);
+  v[0] = t.x;
+  v[1] = t.y;
+  v[2] = t.z;
+  v[3] = t.w;
+}
+template <typename T>
 __device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[1]) {
   p[i] = v[0];
 }
 template <typename T>
 __device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[2]) {
   *reinterpret_cast<typename Vec2<T>::type*>(p + i) = typename Vec2<T>::type{v[0], v[1]};
+}
+template <typename T>
+__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[4]) {
+  *reinterpret_cast<typename Vec4<T>::type*>(p + i) = typename Vec4<T>::type{v[0], v[1], v[2], v[3]};
+}
+
+// The same loads and stores at byte offset bo from an array's base p (wave-uniform).  The
+// step kernels keep one 32-bit offset per lane, so each access is an SGPR base plus a
+// VGPR offset rather than a 64-bit address per array and lane; the launchers check that
+// every offset fits in 32 bits.
+template <typename T, int N>
+__device__ __forceinline__ void ldb(const T* p, uint32_t bo, T (&v)[N]) {
+  ldn(reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + bo), 0, v);
+}
+// one value OFF elements past offset bo (the constant shift goes into the instruction)
+template <int OFF, typename T>
+__device__ __forceinline__ T ld1(const T* p, uint32_t bo) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + bo)[OFF];
+}
+template <typename T, int N>
+__device__ __forceinline__ void stb(T* p, uint32_t bo, const T (&v)[N]) {
+  stn(reinterpret_cast<T*>(reinterpret_cast<char*>(p) + bo), 0, v);
 }
 
 // How the operator step sums its 2 NJT vector dot products.  Up to 8 FP64 or 16 FP32
@@ -241,17 +285,38 @@ struct OpPlane {
   T a[PRE ? NJT : 1][NP];
 };
 
-// The operator step of member y = blockIdx.z over the z planes [blockIdx.y zc, + zc) of
-// its x-y positions (NP consecutive x-nodes per thread).  See the file comment.
+// Block order of the step kernels (one-dimensional grid of round_up(ntiles, NXCD) * nb
+// blocks): the nb members' blocks of one tile are handed out one after another to the same
+// XCD, so the data they share (diagonal, face coefficients, the shared columns of AU) is
+// fetched from HBM once into that XCD's L2 whatever the grid size; tile t is x-position
+// block t % gx of z chunk t / gx.  Blocks past the last tile (t >= ntiles) have no work.
+struct StepBlock {
+  int y, t, tx, tz;
+  bool valid;
+};
+__device__ __forceinline__ StepBlock step_block(int gx, int ntiles, int nb) {
+  const int L = blockIdx.x;
+  const int r = L / NXCD;
+  StepBlock b;
+  b.y = r % nb;
+  b.t = (r / nb) * NXCD + L % NXCD;
+  b.valid = b.t < ntiles;
+  b.tx = b.t % gx;
+  b.tz = b.t / gx;
+  return b;
+}
+
+// The operator step of member y over the z planes [tz zc, + zc) of the x-y positions of
+// block tx (NP consecutive x-nodes per thread; see step_block).  See the file comment.
 template <typename T, bool VAR, int NP, int NJT>
 __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict__ diag,
                                                    const T* __restrict__ q0,
                                                    const T* __restrict__ s0, T* __restrict__ w0,
                                                    int64_t vstride, const T* __restrict__ AW0,
-                                                   int64_t wstride, int64_t ld,
-                                                   const double* __restrict__ Ginv0,
+                                                   Slots sl, const double* __restrict__ Ginv0,
                                                    const double* __restrict__ Gm0,
-                                                   int64_t gstride, int zc, CGState* cgs,
+                                                   int64_t gstride, int zc, int gx, int ntiles,
+                                                   int nb, CGState* cgs,
                                                    CGVec* cvs, const T* __restrict__ ps0, int Ps,
                                                    int64_t psstride, const T* __restrict__ pu0,
                                                    int Pu, int64_t pustride, T* __restrict__ po0,
@@ -259,14 +324,19 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   constexpr bool IMM = OpMode<T, NJT>::imm;
   constexpr bool PRE = OpMode<T, NJT>::pre;
   constexpr bool KEEP = OpMode<T, NJT>::keep;
-  const int y = blockIdx.z;
+  const StepBlock bk = step_block(gx, ntiles, nb);
+  if (!bk.valid) return;
+  const int y = bk.y;
   CGState* cg = cgs + y;
   if (cg->done) return;
   CGVec* cv = cvs + y;
   const T* __restrict__ q = q0 + y * vstride;
   const T* __restrict__ s = s0 + y * vstride;
   T* __restrict__ w = w0 + y * vstride;
-  const T* __restrict__ AW = AW0 + y * wstride;
+  const int64_t ld = sl.ld;
+  const int ns = sl.ns;
+  const T* __restrict__ AW = AW0 + y * sl.wstride;
+  const T* __restrict__ AWs = AW0 + sl.soff;
   const double* __restrict__ Ginv = Ginv0 + y * gstride;
   const int nj = cg->nj;
   const int k = cg->its;
@@ -275,52 +345,62 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   const T *Fx, *Fy, *Fz;
   walk_faces(S, T(0), Fx, Fy, Fz);
   const int nxy = S.nx * S.ny;
-  const int npos = NP == 2 ? (S.nx / 2) * S.ny : nxy;
-  const int qpos = blockIdx.x * OP_BS + threadIdx.x;
+  const int rowp = S.nx / NP;       // positions (groups of NP x-nodes) per row
+  const int npos = rowp * S.ny;
+  const int qpos = bk.tx * OP_BS + threadIdx.x;
   const bool act = qpos < npos;
   const int qq = act ? qpos : 0;   // lanes past the plane read position 0 (zero weight)
-  const int ix = NP == 2 ? 2 * (qq % (S.nx / 2)) : qq % S.nx;
-  const int iy = NP == 2 ? qq / (S.nx / 2) : qq / S.nx;
+  const int ix = NP * (qq % rowp);
+  const int iy = qq / rowp;
   const bool hl = ix > 0, hr = ix + NP < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
-  const int z0 = blockIdx.y * zc;
+  const int z0 = bk.tz * zc;
   const int z1 = min(z0 + zc, S.nz);
   const bool walk = z0 < z1 && (act || IMM);
-  int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
-  auto ldv = [&](const T* p, int64_t j, T (&v)[NP]) { ldn(p, j, v); };
+  // byte offset of this thread's first node: every load below is an array's base plus
+  // this offset, shifted by a row (bx) or a plane (bplane) where it reads a neighbour
+  uint32_t bi = (uint32_t)(((int64_t)z0 * nxy + (int64_t)iy * S.nx + ix) * (int64_t)sizeof(T));
+  const uint32_t bplane = (uint32_t)nxy * (uint32_t)sizeof(T);
+  const uint32_t bx = (uint32_t)S.nx * (uint32_t)sizeof(T);
   auto zero = [](T (&v)[NP]) {
 #pragma unroll
     for (int u = 0; u < NP; ++u) v[u] = T(0);
   };
   OpPlane<T, VAR, NP, NJT, PRE> P;
+  if (PRE) {
+#pragma unroll
+    for (int c = 0; c < NJT; ++c) zero(P.a[PRE ? c : 0]);
+  }
   T xm[NP], xc[NP], fm[NP];
-  auto load_plane = [&](int64_t j, int z) {
-    if (z < S.nz - 1) ldv(q, j + nxy, P.xp); else zero(P.xp);
-    P.xl = hl ? q[j - 1] : T(0);
-    P.xr = hr ? q[j + NP] : T(0);
-    if (hd) ldv(q, j - S.nx, P.yd); else zero(P.yd);
-    if (hu) ldv(q, j + S.nx, P.yu); else zero(P.yu);
-    ldv(diag, j, P.d);
+  auto load_plane = [&](uint32_t bj, int z) {
+    if (z < S.nz - 1) ldb(q, bj + bplane, P.xp); else zero(P.xp);
+    P.xl = hl ? ld1<-1>(q, bj) : T(0);
+    P.xr = hr ? ld1<NP>(q, bj) : T(0);
+    if (hd) ldb(q, bj - bx, P.yd); else zero(P.yd);
+    if (hu) ldb(q, bj + bx, P.yu); else zero(P.yu);
+    ldb(diag, bj, P.d);
     if (VAR) {
-      P.fxl = hl ? Fx[j - 1] : T(0);
-      ldv(Fx, j, P.fx);
-      if (hd) ldv(Fy, j - S.nx, P.fyd); else zero(P.fyd);
-      ldv(Fy, j, P.fyu);
-      if (S.dim == 3) ldv(Fz, j, P.fp); else zero(P.fp);
+      P.fxl = hl ? ld1<-1>(Fx, bj) : T(0);
+      ldb(Fx, bj, P.fx);
+      if (hd) ldb(Fy, bj - bx, P.fyd); else zero(P.fyd);
+      ldb(Fy, bj, P.fyu);
+      if (S.dim == 3) ldb(Fz, bj, P.fp); else zero(P.fp);
     }
-    if (act) ldv(s, j, P.s); else zero(P.s);
+    if (act) ldb(s, bj, P.s); else zero(P.s);
     if (PRE) {
+      // the loads are the kernel's limit (address processing per load instruction), so the
+      // columns past nj are not loaded: their rows stay 0 from the start (coefficient 0,
+      // rows unused), and no branch merges a column's registers with other values; lanes
+      // past the plane read position 0 and add nothing (their s and w are 0)
 #pragma unroll
       for (int c = 0; c < NJT; ++c)
-        if (c < nj) {
-          if (act) ldv(AW + c * ld, j, P.a[PRE ? c : 0]); else zero(P.a[PRE ? c : 0]);
-        }
+        if (c < nj) ldb(col_of(AW, AWs, ns, c, ld), bj, P.a[PRE ? c : 0]);
     }
   };
   if (walk) {
-    if (z0 > 0) ldv(q, i - nxy, xm); else zero(xm);
-    if (VAR && z0 > 0) ldv(Fz, i - nxy, fm); else zero(fm);
-    ldv(q, i, xc);
-    load_plane(i, z0);
+    if (z0 > 0) ldb(q, bi - bplane, xm); else zero(xm);
+    if (VAR && z0 > 0) ldb(Fz, bi - bplane, fm); else zero(fm);
+    ldb(q, bi, xc);
+    load_plane(bi, z0);
   }
 
   // ---- gamma_k = s_k^T s_k and t = (AU)^T s_k: from the start's partials at the first step,
@@ -344,7 +424,7 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     sum_partials_t<1, OP_BS>(pu0 + y * pustride, Pu, tot);
     gam = (double)tot[0];
   }
-  const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+  const bool lead = bk.t == 0;
   const bool nonfinite = !isfinite(gam);
   const bool stop = nonfinite || gam <= tol2 || k >= maxit;
   if (lead && threadIdx.x == 0) {
@@ -367,6 +447,8 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
       cs[j] = (T)cj;
       cd[j] = cj;
       if (lead) cv->c[k & 1][j] = cj;
+    } else if (j < NJT) {
+      cs[j] = T(0);   // the padding columns of the branch-free walk
     }
   }
   __syncthreads();
@@ -395,18 +477,23 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     for (int r = threadIdx.x; r < (OP_BS / WAVE) * 2 * NJT; r += OP_BS) imm[r] = T(0);
     __syncthreads();
   }
-  // vector sum r: in registers, or reduced over the wave and added to the wave's LDS slot
-  auto vadd = [&](int r, T v) {
+  // vector sum r of x^T y over this thread's nodes: in registers, or reduced over the wave
+  // and added to the wave's LDS slot
+  auto vadd = [&](int r, const T (&x)[NP], const T (&y)[NP]) {
     if (IMM) {
+      T v = T(0);
+#pragma unroll
+      for (int u = 0; u < NP; ++u) v += x[u] * y[u];
       v = wave_sum(v);
       if (lane == 0) imm[wid * 2 * NJT + r] += v;
     } else {
-      acc[4 + r] += v;
+#pragma unroll
+      for (int u = 0; u < NP; ++u) acc[4 + r] += x[u] * y[u];
     }
   };
   const T cx = (T)S.cx, cy = (T)S.cy, cz = (T)S.cz;
   const T m = act ? T(1) : T(0);
-  for (int z = z0; walk && z < z1; ++z, i += nxy) {
+  for (int z = z0; walk && z < z1; ++z, bi += bplane) {
     // (A q) at the NP nodes
     T av[NP], xq[NP];
 #pragma unroll
@@ -422,7 +509,7 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
         v -= P.fyd[u] * P.yd[u] + P.fyu[u] * P.yu[u];
         if (S.dim == 3) v -= fm[u] * xm[u] + P.fp[u] * P.xp[u];
       }
-      av[u] = m * v;
+      av[u] = v;   // masked in w below
       xq[u] = m * xc[u];
     }
     // pass 1 over the rows of AU: AU c, (AU)^T s
@@ -431,13 +518,13 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     T keep[KEEP ? NJT : 1][NP];
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (c < nj) {
+      if (PRE || c < nj) {
         T a[NP];
         if (PRE) {
 #pragma unroll
           for (int u = 0; u < NP; ++u) a[u] = P.a[PRE ? c : 0][u];
         } else if (act) {
-          ldv(AW + c * ld, i, a);
+          ldb(col_of(AW, AWs, ns, c, ld), bi, a);
         } else {
           zero(a);
         }
@@ -445,27 +532,24 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
 #pragma unroll
           for (int u = 0; u < NP; ++u) keep[KEEP ? c : 0][u] = a[u];
         }
-        T t = T(0);
+        const T cc = cs[c];
 #pragma unroll
-        for (int u = 0; u < NP; ++u) {
-          au[u] += a[u] * cs[c];
-          t += a[u] * P.s[u];
-        }
-        vadd(NJT + c, t);
+        for (int u = 0; u < NP; ++u) au[u] += a[u] * cc;
+        vadd(NJT + c, a, P.s);
       }
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
-      wv[u] = av[u] - au[u];
+      wv[u] = m * (av[u] - au[u]);
       acc[0] += xq[u] * wv[u];
       acc[1] += xq[u] * au[u];
       acc[2] += P.s[u] * wv[u];
       acc[3] += wv[u] * wv[u];
     }
-    if (act) stn(w, i, wv);
+    if (act) stb(w, bi, wv);
     // pass 2: (AU)^T w
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (c < nj) {
+      if (PRE || c < nj) {
         T a[NP];
         if (PRE) {
 #pragma unroll
@@ -474,14 +558,11 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
 #pragma unroll
           for (int u = 0; u < NP; ++u) a[u] = keep[KEEP ? c : 0][u];
         } else if (act) {
-          ldv(AW + c * ld, i, a);
+          ldb(col_of(AW, AWs, ns, c, ld), bi, a);
         } else {
           zero(a);
         }
-        T t = T(0);
-#pragma unroll
-        for (int u = 0; u < NP; ++u) t += a[u] * wv[u];
-        vadd(c, t);
+        vadd(c, a, wv);
       }
     // next plane
 #pragma unroll
@@ -490,11 +571,14 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
       xc[u] = P.xp[u];
       if (VAR) fm[u] = P.fp[u];
     }
-    if (z + 1 < z1) load_plane(i + nxy, z + 1);
+    // the next plane, unconditionally (the last plane loads itself again, unused): under a
+    // branch, the registers of the plane would be merged and copied every plane
+    const bool more = z + 1 < z1;
+    load_plane(more ? bi + bplane : bi, more ? z + 1 : z);
   }
   T* __restrict__ po = po0 + y * postride;
-  const int P1 = gridDim.x * gridDim.y;
-  const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+  const int P1 = ntiles;
+  const int bid = bk.t;
   if (!IMM) {
     write_partials_t<RV, OP_BS>(acc, po, bid, P1);
   } else {
@@ -538,7 +622,7 @@ __device__ __forceinline__ void sum_rows_wide(const T* __restrict__ partials, in
   __syncthreads();
 }
 
-// One whole step in one launch (member y = blockIdx.z), for latency-bound sizes: launch j
+// One whole step in one launch (member y; see step_block), for latency-bound sizes: launch j
 // applies update j-1 at this block's nodes and then operator step j.  s, q and w are kept
 // in two buffers by step parity (par = j & 1, at + par pstride): launch j reads s_{j-1},
 // q_{j-1}, w_{j-1} from the other buffer and writes s_j, q_j, w_j; q_j at a node's
@@ -556,10 +640,11 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
                                                      T* __restrict__ sb, T* __restrict__ qb,
                                                      T* __restrict__ wb, int64_t pstride,
                                                      int64_t vstride, T* __restrict__ g0,
-                                                     const T* __restrict__ AW0, int64_t wstride,
-                                                     int64_t ld, const double* __restrict__ Ginv0,
+                                                     const T* __restrict__ AW0, Slots sl,
+                                                     const double* __restrict__ Ginv0,
                                                      const double* __restrict__ Gm0,
-                                                     int64_t gstride, int zc, CGState* cgs,
+                                                     int64_t gstride, int zc, int gx, int ntiles,
+                                                     int nb, CGState* cgs,
                                                      CGVec* cvs, const T* __restrict__ ps0, int Ps,
                                                      int64_t psstride, T* __restrict__ po0,
                                                      int64_t postride, int64_t pohalf, int Pprev,
@@ -568,7 +653,9 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
   constexpr bool PRE = OpMode<T, NJT>::pre;
   constexpr bool KEEP = OpMode<T, NJT>::keep;
   constexpr int RS = 5;                      // scalar partials
-  const int y = blockIdx.z;
+  const StepBlock bk = step_block(gx, ntiles, nb);
+  if (!bk.valid) return;
+  const int y = bk.y;
   CGState* cg = cgs + y;
   if (cg->done) return;
   CGVec* cv = cvs + y;
@@ -582,7 +669,10 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
   T* __restrict__ qw_ = qb + par * pstride + y * vstride;
   T* __restrict__ ww_ = wb + par * pstride + y * vstride;
   T* __restrict__ g = g0 + y * vstride;
-  const T* __restrict__ AW = AW0 + y * wstride;
+  const int64_t ld = sl.ld;
+  const int ns = sl.ns;
+  const T* __restrict__ AW = AW0 + y * sl.wstride;
+  const T* __restrict__ AWs = AW0 + sl.soff;
   const double* __restrict__ Ginv = Ginv0 + y * gstride;
   const int nj = cg->nj;
 
@@ -591,13 +681,13 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
   walk_faces(S, T(0), Fx, Fy, Fz);
   const int nxy = S.nx * S.ny;
   const int npos = NP == 2 ? (S.nx / 2) * S.ny : nxy;
-  const int qpos = blockIdx.x * OP_BS + threadIdx.x;
+  const int qpos = bk.tx * OP_BS + threadIdx.x;
   const bool act = qpos < npos;
   const int qq = act ? qpos : 0;
   const int ix = NP == 2 ? 2 * (qq % (S.nx / 2)) : qq % S.nx;
   const int iy = NP == 2 ? qq / (S.nx / 2) : qq / S.nx;
   const bool hl = ix > 0, hr = ix + NP < S.nx, hd = iy > 0, hu = iy < S.ny - 1;
-  const int z0 = blockIdx.y * zc;
+  const int z0 = bk.tz * zc;
   const int z1 = min(z0 + zc, S.nz);
   const bool walk = z0 < z1 && (act || IMM);
   int64_t i = (int64_t)z0 * nxy + (int64_t)iy * S.nx + ix;
@@ -659,7 +749,8 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
 #pragma unroll
       for (int c = 0; c < NJT; ++c)
         if (c < nj) {
-          if (act) ldv(AW + c * ld, j, P.a[PRE ? c : 0]); else zero(P.a[PRE ? c : 0]);
+          if (act) ldv(col_of(AW, AWs, ns, c, ld), j, P.a[PRE ? c : 0]);
+          else zero(P.a[PRE ? c : 0]);
         }
     }
   };
@@ -697,7 +788,7 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
     if (threadIdx.x < NJT)
       tv[threadIdx.x] = (double)tot[RS + NJT + threadIdx.x] - al * (double)tot[RS + threadIdx.x];
   }
-  const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+  const bool lead = bk.t == 0;
   const bool nonfinite = !isfinite(gam);
   const bool conv = gam <= tol2;
   const bool hit = done_its >= maxit;
@@ -834,7 +925,7 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
 #pragma unroll
           for (int u = 0; u < NP; ++u) a[u] = P.a[PRE ? c : 0][u];
         } else if (act) {
-          ldv(AW + c * ld, i, a);
+          ldv(col_of(AW, AWs, ns, c, ld), i, a);
         } else {
           zero(a);
         }
@@ -872,7 +963,7 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
 #pragma unroll
           for (int u = 0; u < NP; ++u) a[u] = keep[KEEP ? c : 0][u];
         } else if (act) {
-          ldv(AW + c * ld, i, a);
+          ldv(col_of(AW, AWs, ns, c, ld), i, a);
         } else {
           zero(a);
         }
@@ -891,8 +982,8 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_iter(Stencil S, const T* __restri
     if (z + 1 < z1) load_plane(i + nxy, z + 1);
   }
   T* __restrict__ po = po0 + y * postride + par * pohalf;
-  const int P1 = gridDim.x * gridDim.y;
-  const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+  const int P1 = ntiles;
+  const int bid = bk.t;
   if (!IMM) {
     write_partials_t<RV, OP_BS>(acc, po, bid, P1);
   } else {
@@ -1035,8 +1126,8 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const 
 
 // g -= U e (member y = blockIdx.y): the U part of the split correction.
 template <typename T, int NJT>
-__global__ __launch_bounds__(CG_BS) void k_dcg_finish(const T* __restrict__ W0, int64_t wstride,
-                                                       int64_t ld, int64_t n,
+__global__ __launch_bounds__(CG_BS) void k_dcg_finish(const T* __restrict__ W0, Slots sl,
+                                                       int64_t n,
                                                        T* __restrict__ g0, int64_t vstride,
                                                        const CGState* cgs, const CGVec* cvs) {
   const int y = blockIdx.y;
@@ -1046,14 +1137,15 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_finish(const T* __restrict__ W0, 
   __shared__ T es[NJ_MAX];
   if (threadIdx.x < nj) es[threadIdx.x] = (T)cvs[y].e[threadIdx.x];
   __syncthreads();
-  const T* __restrict__ W = W0 + y * wstride;
+  const T* __restrict__ W = W0 + y * sl.wstride;
+  const T* __restrict__ Ws = W0 + sl.soff;
   T* __restrict__ g = g0 + y * vstride;
   for (int64_t i = (int64_t)blockIdx.x * CG_BS + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * CG_BS) {
     T v = g[i];
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (c < nj) v -= W[i + c * ld] * es[c];
+      if (c < nj) v -= col_of(W, Ws, sl.ns, c, sl.ld)[i] * es[c];
     g[i] = v;
   }
 }
@@ -1074,13 +1166,13 @@ void launch_cg_setup(CGState* cg, CGVec* cv, const CgSetup& su, int nb, hipStrea
 }
 
 template <typename T>
-void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax,
+void launch_dcg_start(const T* W, const T* AW, const Slots& sl, int64_t n, int njmax,
                       const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
                       T* s, T* q, int64_t vstride, const CGState* cg, T* ps, int64_t psstride,
                       int nb, int P, hipStream_t st) {
   const dim3 grid(P, nb);
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, wstride, ld, n, Ginv, gstride, r, rstride, g, s, q, vstride, cg, ps, psstride); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, sl, n, Ginv, gstride, r, rstride, g, s, q, vstride, cg, ps, psstride); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -1089,15 +1181,21 @@ void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int6
 
 template <typename T>
 void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, const T* q,
-                   const T* s, T* w, int64_t vstride, const T* AW, int64_t wstride, int64_t ld,
+                   const T* s, T* w, int64_t vstride, const T* AW, const Slots& sl,
                    int njmax, const double* Ginv, const double* Gm, int64_t gstride, CGState* cg,
                    CGVec* cv, const T* ps, int Ps, int64_t psstride, const T* pu, int Pu,
                    int64_t pustride, T* po, int64_t postride, int nb, hipStream_t st) {
-  const dim3 grid(sh.grid.x, sh.grid.y, nb);
+  const int gx = sh.grid.x, ntiles = sh.blocks;
+  if (nb < 1 || nb > G_MAX || ntiles != gx * (int)sh.grid.y)
+    throw Error(ROM_EINVAL, "dcg_op: launch shape and batch size do not match");
+  // the kernel addresses a vector's nodes by 32-bit byte offsets
+  if ((uint64_t)S.n * sizeof(T) > 0xffffffffull)
+    throw Error(ROM_EINVAL, "dcg_op: grid too large for 32-bit node offsets");
+  const dim3 grid(ceil_div(ntiles, NXCD) * NXCD * nb);
 #define OPL(VAR, NP, J)                                                                       \
   ROM_LAUNCH((k_dcg_op<T, VAR, NP, J>), grid, dim3(OP_BS), 0, st, S, diag, q, s, w, vstride,  \
-             AW, wstride, ld, Ginv, Gm, gstride, sh.zc, cg, cv, ps, Ps, psstride, pu, Pu,      \
-             pustride, po, postride)
+             AW, sl, Ginv, Gm, gstride, sh.zc, gx, ntiles, nb, cg, cv, ps, Ps, psstride, pu,   \
+             Pu, pustride, po, postride)
 #define OPJ(VAR, NP)                      \
   switch (njt_of(njmax)) {                \
     case 8: OPL(VAR, NP, 8); break;       \
@@ -1105,7 +1203,14 @@ void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, cons
     case 32: OPL(VAR, NP, 32); break;     \
     default: OPL(VAR, NP, 64); break;     \
   }
-  if (sh.pairs) {
+  if (sh.quads) {
+    // FP32 only (16-byte loads of four nodes)
+    if constexpr (sizeof(T) == 4) {
+      if (S.var) { OPJ(true, 4) } else { OPJ(false, 4) }
+    } else {
+      throw Error(ROM_EINVAL, "dcg_op: the four-node walk is FP32 only");
+    }
+  } else if (sh.pairs) {
     if (S.var) { OPJ(true, 2) } else { OPJ(false, 2) }
   } else {
     if (S.var) { OPJ(true, 1) } else { OPJ(false, 1) }
@@ -1117,12 +1222,13 @@ void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, cons
 
 template <typename T>
 void launch_dcg_iter(const Stencil& S, const StencilShape& sh, const T* diag, T* s, T* q, T* w,
-                     int64_t pstride, int64_t vstride, T* g, const T* AW, int64_t wstride,
-                     int64_t ld, int njmax, const double* Ginv, const double* Gm,
+                     int64_t pstride, int64_t vstride, T* g, const T* AW, const Slots& sl,
+                     int njmax, const double* Ginv, const double* Gm,
                      int64_t gstride, CGState* cg, CGVec* cv, const T* ps, int Ps,
                      int64_t psstride, T* po, int64_t postride, int64_t pohalf, int Pprev,
                      int par, int first, int nb, hipStream_t st) {
   if (par != 0 && par != 1) throw Error(ROM_EINVAL, "dcg_iter: parity must be 0 or 1");
+  if (sh.quads) throw Error(ROM_EINVAL, "dcg_iter: no four-node walk for the one-launch step");
   if (first && par != 0) throw Error(ROM_EINVAL, "dcg_iter: the first step has parity 0");
   if (sh.pairs) {
     // the two-node walk reads and writes s, q, w and g two values at a time
@@ -1131,11 +1237,14 @@ void launch_dcg_iter(const Stencil& S, const StencilShape& sh, const T* diag, T*
         vstride % 2)
       throw Error(ROM_EINVAL, "dcg_iter: vectors not aligned for the two-node walk");
   }
-  const dim3 grid(sh.grid.x, sh.grid.y, nb);
+  const int gx = sh.grid.x, ntiles = sh.blocks;
+  if (nb < 1 || nb > G_MAX || ntiles != gx * (int)sh.grid.y)
+    throw Error(ROM_EINVAL, "dcg_iter: launch shape and batch size do not match");
+  const dim3 grid(ceil_div(ntiles, NXCD) * NXCD * nb);
 #define ITL(VAR, NP, J)                                                                        \
   ROM_LAUNCH((k_dcg_iter<T, VAR, NP, J>), grid, dim3(OP_BS), 0, st, S, diag, s, q, w, pstride,  \
-             vstride, g, AW, wstride, ld, Ginv, Gm, gstride, sh.zc, cg, cv, ps, Ps, psstride,   \
-             po, postride, pohalf, Pprev, par, first)
+             vstride, g, AW, sl, Ginv, Gm, gstride, sh.zc, gx, ntiles, nb, cg, cv, ps, Ps,      \
+             psstride, po, postride, pohalf, Pprev, par, first)
 #define ITJ(VAR, NP)                      \
   switch (njt_of(njmax)) {                \
     case 8: ITL(VAR, NP, 8); break;       \
@@ -1169,13 +1278,13 @@ void launch_dcg_update(T* q, const T* w, T* g, T* s, int64_t vstride, int64_t n,
 }
 
 template <typename T>
-void launch_dcg_finish(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax, T* g,
+void launch_dcg_finish(const T* W, const Slots& sl, int64_t n, int njmax, T* g,
                        int64_t vstride, const CGState* cg, const CGVec* cv, int nb,
                        hipStream_t st) {
   if (njmax <= 0) return;
   const dim3 grid(dcg_blocks(n), nb);
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_finish<T, J>), grid, dim3(CG_BS), 0, st, W, wstride, ld, n, g, vstride, cg, cv); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_finish<T, J>), grid, dim3(CG_BS), 0, st, W, sl, n, g, vstride, cg, cv); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -1183,24 +1292,24 @@ void launch_dcg_finish(const T* W, int64_t wstride, int64_t ld, int64_t n, int n
 }
 
 #define INSTANTIATE(T)                                                                          \
-  template void launch_dcg_start<T>(const T*, const T*, int64_t, int64_t, int64_t, int,          \
+  template void launch_dcg_start<T>(const T*, const T*, const Slots&, int64_t, int,              \
                                     const double*, int64_t, const double*, int64_t, T*, T*, T*,  \
                                     int64_t, const CGState*, T*, int64_t, int, int,              \
                                     hipStream_t);                                                \
   template void launch_dcg_op<T>(const Stencil&, const StencilShape&, const T*, const T*,        \
-                                 const T*, T*, int64_t, const T*, int64_t, int64_t, int,         \
+                                 const T*, T*, int64_t, const T*, const Slots&, int,             \
                                  const double*, const double*, int64_t, CGState*, CGVec*,        \
                                  const T*, int, int64_t, const T*, int, int64_t, T*, int64_t,    \
                                  int, hipStream_t);                                              \
   template void launch_dcg_iter<T>(const Stencil&, const StencilShape&, const T*, T*, T*, T*,     \
-                                   int64_t, int64_t, T*, const T*, int64_t, int64_t, int,        \
+                                   int64_t, int64_t, T*, const T*, const Slots&, int,            \
                                    const double*, const double*, int64_t, CGState*, CGVec*,      \
                                    const T*, int, int64_t, T*, int64_t, int64_t, int, int, int,  \
                                    int, hipStream_t);                                            \
   template void launch_dcg_update<T>(T*, const T*, T*, T*, int64_t, int64_t, int, CGState*,      \
                                      CGVec*, const T*, int, int64_t, T*, int64_t, int, int,      \
                                      hipStream_t, int);                                          \
-  template void launch_dcg_finish<T>(const T*, int64_t, int64_t, int64_t, int, T*, int64_t,      \
+  template void launch_dcg_finish<T>(const T*, const Slots&, int64_t, int, T*, int64_t,          \
                                      const CGState*, const CGVec*, int, hipStream_t);
 INSTANTIATE(double)
 INSTANTIATE(float)

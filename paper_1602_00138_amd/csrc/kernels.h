@@ -58,14 +58,18 @@ struct StencilShape {
   int zc;
   int blocks;
   int pairs = 0;   // CG operator step with two x-nodes per thread (grid.x counts pairs)
+  int quads = 0;   // FP32 operator step with four x-nodes per thread (grid.x counts quads)
 };
 StencilShape stencil_shape(const Stencil& S, int target_blocks);
 // Launch shape of the CG operator step (launch_dcg_op) for these buffers: the two-node
 // walk when nx is even and every array is aligned for it (then grid.x and blocks count
-// node pairs: the partials per member are `blocks`, at stride `blocks`).
+// node pairs: the partials per member are `blocks`, at stride `blocks`); with quads (FP32
+// only), the four-node walk where nx, the leading dimension and the alignment allow it
+// (grid.x and blocks count groups of four nodes).
 template <typename T>
 StencilShape cg_apply_shape(const Stencil& S, int target_blocks, const T* diag, const T* p,
-                            const T* w, int64_t vstride, const T* AW = nullptr);
+                            const T* w, int64_t vstride, const T* AW = nullptr,
+                            bool quads = false);
 
 // Absorption bumps of one parameter point, passed by value as a kernel argument.
 struct Bumps {
@@ -325,12 +329,24 @@ void launch_dot2_scale(int64_t n, const double* x, const double* a, const double
 
 // ---- deflated CG --------------------------------------------------------------------
 // T = double (plain form) or float (inner sweeps of the mixed form).  A batch of nb
-// members runs together; member y uses cg[y] / cv[y] (its nj, rscale, tol2, maxit),
-// W + y*wstride, AW + y*wstride, Ginv / Gm + y*gstride (strides 0: one recycle space for
-// every member), the FP64 right-hand side r + y*rstride (read as rscale * r) and its CG
-// vectors at + y*vstride.  W, AW: n x nj column-major (ld); Ginv, Gm: nj x nj FP64
+// members runs together; member y uses cg[y] / cv[y] (its nj, rscale, tol2, maxit), the
+// recycle-space columns of slot y (Slots), Ginv / Gm + y*gstride (stride 0: one recycle
+// space for every member), the FP64 right-hand side r + y*rstride (read as rscale * r) and
+// its CG vectors at + y*vstride.  W, AW: n x nj column-major; Ginv, Gm: nj x nj FP64
 // (W^T A W)^{-1} and W^T A W.  Inactive members (done set at setup) return at once from
 // every kernel.
+//
+// Where column c of member y's W and AW sits: W + (c < ns ? soff : y*wstride) + c*ld.  The
+// first ns columns (U_0 and A_i U_0 after the first point: the same in every member's
+// recycle space) are read from one slot for all members, so that the members' blocks of
+// one tile, which run on the same XCD, share them in its L2 instead of each reading its
+// own copy from HBM.  ns = 0 (or soff = y*wstride) reads each member's own slot.
+struct Slots {
+  int64_t wstride;   // elements between members' slots (0: one slot for every member)
+  int64_t ld;        // elements between columns
+  int64_t soff;      // elements from the base to the slot holding the shared columns
+  int ns;            // leading columns read from there
+};
 //
 // A solve is: setup; start (g = U y0, s = q = r - AU y0, y0 = Ginv U^T r with U^T r in
 // cg[y].t); then per step the operator kernel (the start's or the previous update's
@@ -348,7 +364,7 @@ void launch_cg_setup(CGState* cg, CGVec* cv, const CgSetup& su, int nb, hipStrea
 // P blocks per member; partials ps (NJ_MAX + 1 values per block, transposed) at stride
 // psstride per member.
 template <typename T>
-void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int64_t n, int njmax,
+void launch_dcg_start(const T* W, const T* AW, const Slots& sl, int64_t n, int njmax,
                       const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
                       T* s, T* q, int64_t vstride, const CGState* cg, T* ps, int64_t psstride,
                       int nb, int P, hipStream_t st);
@@ -357,7 +373,7 @@ void launch_dcg_start(const T* W, const T* AW, int64_t wstride, int64_t ld, int6
 // start (its partials are read at the first step), Pu: blocks of the update kernel.
 template <typename T>
 void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, const T* q,
-                   const T* s, T* w, int64_t vstride, const T* AW, int64_t wstride, int64_t ld,
+                   const T* s, T* w, int64_t vstride, const T* AW, const Slots& sl,
                    int njmax, const double* Ginv, const double* Gm, int64_t gstride, CGState* cg,
                    CGVec* cv, const T* ps, int Ps, int64_t psstride, const T* pu, int Pu,
                    int64_t pustride, T* po, int64_t postride, int nb, hipStream_t st);
@@ -375,14 +391,14 @@ void launch_dcg_update(T* q, const T* w, T* g, T* s, int64_t vstride, int64_t n,
 // = the previous step's blocks (sh.blocks).  g: the q part of the correction.
 template <typename T>
 void launch_dcg_iter(const Stencil& S, const StencilShape& sh, const T* diag, T* s, T* q, T* w,
-                     int64_t pstride, int64_t vstride, T* g, const T* AW, int64_t wstride,
-                     int64_t ld, int njmax, const double* Ginv, const double* Gm,
+                     int64_t pstride, int64_t vstride, T* g, const T* AW, const Slots& sl,
+                     int njmax, const double* Ginv, const double* Gm,
                      int64_t gstride, CGState* cg, CGVec* cv, const T* ps, int Ps,
                      int64_t psstride, T* po, int64_t postride, int64_t pohalf, int Pprev,
                      int par, int first, int nb, hipStream_t st);
 // g -= U e for every member (the U part of the split correction).
 template <typename T>
-void launch_dcg_finish(const T* W, int64_t wstride, int64_t ld, int64_t n, int njmax, T* g,
+void launch_dcg_finish(const T* W, const Slots& sl, int64_t n, int njmax, T* g,
                        int64_t vstride, const CGState* cg, const CGVec* cv, int nb,
                        hipStream_t st);
 

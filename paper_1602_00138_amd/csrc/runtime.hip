@@ -1511,43 +1511,50 @@ class Sequencer {
     int flag[G_MAX] = {};
   };
 
-  // Launch shape of the CG step kernels, encoded as (P << 4) | (narrow << 3) | op: P blocks
+  // Launch shape of the CG step kernels, encoded as (P << 5) | (quad << 4) | (narrow << 3) |
+  // op: quad for the FP32 operator step's four-node walk (two-launch step only), P blocks
   // per member of the update kernel, narrow for its variant with half the rows per thread,
   // op the operator step's target block count per member (op_target; the fewer blocks, the
   // more z planes per thread and the fewer partial rows to reduce).  Fixed shape: the full
-  // grid for one member, split among the members of a batch (narrow for batches).  With
-  // opts.tune the first batch of each (arithmetic, batch size, U_j width class, grid size) in
-  // the process times every power-of-two P with both variants and every operator target on
+  // grid for one member, split among the members of a batch (narrow for batches), and the
+  // four-node walk in FP32 where it applies.  With opts.tune the first batch of each
+  // (arithmetic, batch size, U_j width class, grid size) in the process times every
+  // power-of-two P with both variants, every operator target and, in FP32, both walks on
   // its own data (three rounds of 8 CG steps each after a warm-up round, from its real
   // start; the solve then restarts) and keeps the fastest (by its best round) for the rest
   // of the process.
   // Bit 2 of op selects the one-launch step (then P and narrow are unused): every block of
   // it sums all partial rows of the previous step, so only the 256 and 64 block targets are
   // candidates for it.
-  static int shape_code(int P, int nr, int op) { return (P << 4) | (nr << 3) | op; }
-  static int shape_P(int code) { return code >> 4; }
+  static int shape_code(int P, int nr, int op, int quad = 0) {
+    return (P << 5) | (quad << 4) | (nr << 3) | op;
+  }
+  static int shape_P(int code) { return code >> 5; }
+  static bool shape_quad(int code) { return ((code >> 4) & 1) != 0; }
   static int shape_nr(int code) { return (code >> 3) & 1; }
   static bool shape_one(int code) { return (code & 4) != 0; }
   // op 0: 1024 blocks per member divided among the members (at least 64); 1, 2, 3: 1024,
   // 256, 64 blocks per member
   static int op_target(int code, int nb) {
     const int op = code & 3;
-    return op == 0 ? std::max(64, 1024 / nb) : op == 1 ? 1024 : op == 2 ? 256 : 64;
+    return op == 0 ? std::max(64, 1024 / nb) : op == 1 ? 1024 : op == 2 ? 256 : 192;
   }
   template <typename T, typename Bufs>
   StencilShape op_shape(const Bufs& b, int code, int nb) const {
-    return cg_apply_shape<T>(S_, op_target(code, nb), b.diag, b.q, b.w, ld_, b.AW);
+    return cg_apply_shape<T>(S_, op_target(code, nb), b.diag, b.q, b.w, ld_, b.AW,
+                             shape_quad(code) && !shape_one(code));
   }
 
   template <typename T, typename Bufs>
-  int cg_shape(const Batch& bt, const Bufs& b, const double* rhs, T* dvec, int64_t wstride,
+  int cg_shape(const Batch& bt, const Bufs& b, const double* rhs, T* dvec, const Slots& sl,
                int64_t gstride, int njmax) {
     const int nb = bt.nb;
     const int Pmax = dcg_blocks(n_);
     const int mode = o_.cg_step;   // 0 either form (tuned) / two launches, 1 two, 2 one
+    const int quad = sizeof(T) == 4 ? 1 : 0;
     const int fixed = mode == 2 ? shape_code(Pmax, 0, 4 | 2)
                                 : shape_code(std::max(std::min(Pmax, 8), Pmax / nb),
-                                             nb > 1 ? 1 : 0, 0);
+                                             nb > 1 ? 1 : 0, 0, quad);
     if (!tune_) return fixed;
     int dev = 0;
     ROM_HIP(hipGetDevice(&dev));
@@ -1561,7 +1568,8 @@ class Sequencer {
     if (mode != 2)
       for (int P = Pmax; P >= 8; P /= 2)
         for (int nr = 0; nr < 2; ++nr)
-          for (int op = 1; op <= 3; ++op) cand.push_back(shape_code(P, nr, op));
+          for (int op = 1; op <= 3; ++op)
+            for (int qd = 0; qd <= quad; ++qd) cand.push_back(shape_code(P, nr, op, qd));
     if (mode != 1)
       for (int op = 2; op <= 3; ++op) cand.push_back(shape_code(Pmax, 0, 4 | op));
     int best = fixed;
@@ -1597,17 +1605,17 @@ class Sequencer {
           const int P = shape_P(shape), nr = shape_nr(shape);
           const StencilShape sh = op_shape<T>(b, shape, nb);
           launch_cg_setup(cg, cgv_, su, nb, st_);
-          launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_,
+          launch_dcg_start<T>(b.W, b.AW, sl, n_, njmax, GWinv_, gstride, rhs, ld_,
                               dvec, b.s, b.q, ld_, cg, b.ps, p2s_, nb, Pmax, st_);
           ROM_HIP(hipEventRecord(e0, st_));
           for (int step = 0; step < 8; ++step) {
             if (shape_one(shape)) {
               launch_dcg_iter<T>(S_, sh, b.diag, b.s, b.q, b.w, b.pstride, ld_, dvec, b.AW,
-                                 wstride, ld_, njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps,
+                                 sl, njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps,
                                  Pmax, p2s_, b.po, pos_, b.pohalf, sh.blocks, step & 1,
                                  step == 0, nb, st_);
             } else {
-              launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax,
+              launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, sl, njmax,
                                GWinv_, GWs_, gstride, cg, cgv_, b.ps, Pmax, p2s_, b.pu, P,
                                pus_, b.po, pos_, nb, st_);
               launch_dcg_update<T>(b.q, b.w, dvec, b.s, ld_, n_, njmax, cg, cgv_, b.po,
@@ -1637,11 +1645,12 @@ class Sequencer {
   // (operator step, update) pairs, which take the step index from the CG state, or
   // one-launch steps of parities 1, 0, 1, ... (a chunk follows the eager step 0 or another
   // chunk).  One graph per (value type, batch size, shared recycle space, width class,
-  // shape, output vector), kept for the rest of the call.
+  // shape, slot and count of the shared leading columns, output vector), kept for the rest
+  // of the call.
   template <typename T, typename Bufs>
   hipGraphExec_t chunk_graph(const Bufs& b, int nb, bool shared, int njmax, int shape,
-                             int64_t wstride, int64_t gstride, T* dvec, const StencilShape& sh) {
-    const GraphKey key{(int)sizeof(T), nb, shared ? 1 : 0, njt_of(njmax), shape,
+                             const Slots& sl, int64_t gstride, T* dvec, const StencilShape& sh) {
+    const GraphKey key{(int)sizeof(T), nb, shared ? 1 : 0, njt_of(njmax), shape, sl.soff, sl.ns,
                        (const void*)dvec};
     const int P = shape_P(shape), nr = shape_nr(shape);
     auto it = graphs_.find(key);
@@ -1657,12 +1666,12 @@ class Sequencer {
     try {
       for (int c = 0; c < GRAPH_STEPS; ++c) {
         if (shape_one(shape)) {
-          launch_dcg_iter<T>(S_, sh, b.diag, b.s, b.q, b.w, b.pstride, ld_, dvec, b.AW, wstride,
-                             ld_, njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.po,
+          launch_dcg_iter<T>(S_, sh, b.diag, b.s, b.q, b.w, b.pstride, ld_, dvec, b.AW, sl,
+                             njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.po,
                              pos_, b.pohalf, sh.blocks, (c + 1) & 1, 0, nb, cs);
           continue;
         }
-        launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax, GWinv_,
+        launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, sl, njmax, GWinv_,
                          GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.pu, P, pus_, b.po, pos_, nb,
                          cs);
         launch_dcg_update<T>(b.q, b.w, dvec, b.s, ld_, n_, njmax, cg, cgv_, b.po, sh.blocks,
@@ -1707,7 +1716,21 @@ class Sequencer {
       }
     }
     if (nact == 0) return;
-    const int shape = cg_shape<T>(bt, b, rhs, dvec, wstride, gstride, njmax);
+    // after the first point every member's recycle space starts with the same ku_ columns
+    // (U_0 and A_i U_0, packed and multiplied the same way into every slot): the kernels
+    // read them from the first active member's slot for all members
+    Slots sl{wstride, ld_, 0, 0};
+    if (!bt.shared && nact > 1 && ku_ > 0) {
+      int ysrc = -1, ns = ku_;
+      for (int y = 0; y < nb; ++y)
+        if (bt.active[y]) {
+          if (ysrc < 0) ysrc = y;
+          ns = std::min(ns, bt.nj[y]);
+        }
+      sl.soff = ysrc * wstride;
+      sl.ns = ns;
+    }
+    const int shape = cg_shape<T>(bt, b, rhs, dvec, sl, gstride, njmax);
     const int P = shape_P(shape), nr = shape_nr(shape);
     // the operator step's shape (two x-nodes per thread where the layout allows); its block
     // count is the number of the operator step's partial rows per member
@@ -1739,23 +1762,26 @@ class Sequencer {
     // blocks would leave the chip idle on the update's grid); the first operator step
     // reduces its partial rows
     const int P0 = dcg_blocks(n_);
+    // the shared leading columns of U and AU count once per launch, the rest per member
+    const double ns = sl.ns;
     tm_->begin(ROM_K_DCG_ENDS);
-    launch_dcg_start<T>(b.W, b.AW, wstride, ld_, n_, njmax, GWinv_, gstride, rhs, ld_, dvec, b.s,
+    launch_dcg_start<T>(b.W, b.AW, sl, n_, njmax, GWinv_, gstride, rhs, ld_, dvec, b.s,
                         b.q, ld_, cg, b.ps, p2s_, nb, P0, st_);
-    tm_->end(ROM_K_DCG_ENDS, nact * (8.0 * n_ + E * n_ * (2 * njavg + 3)),
+    tm_->end(ROM_K_DCG_ENDS, nact * (8.0 * n_ + E * n_ * (2 * (njavg - ns) + 3)) + 2 * E * n_ * ns,
              nact * n_ * (2.0 + 4.0 * njavg));
-    // algorithmic bytes and flops per member and step: the operator step reads q, s and AU
-    // and writes w, and per launch reads the diagonal (and face coefficients) once for all
-    // its members; the update reads q, w, g, s and writes q, g, s
-    const double by_shared = E * n_ * (1 + (S_.var ? S_.dim : 0));
-    const double by_op = E * n_ * (3 + njavg);
+    // algorithmic bytes and flops per member and step: the operator step reads q, s and its
+    // own columns of AU and writes w, and per launch reads the diagonal (and face
+    // coefficients) and the shared columns of AU once for all its members; the update reads
+    // q, w, g, s and writes q, g, s
+    const double by_shared = E * n_ * (1 + (S_.var ? S_.dim : 0) + ns);
+    const double by_op = E * n_ * (3 + njavg - ns);
     const double fl_op = n_ * (21.0 + 6.0 * njavg);
     const double by_upd = 7.0 * E * n_;
     const double fl_upd = 8.0 * n_;
-    // the one-launch step reads s, q, w, g and AU and writes s, q, w, g per member (and the
-    // shared diagonal and faces once)
+    // the one-launch step reads s, q, w, g and its own columns of AU and writes s, q, w, g
+    // per member (and the diagonal, faces and shared columns of AU once)
     const bool one = shape_one(shape);
-    const double by_one = E * n_ * (8 + njavg);
+    const double by_one = E * n_ * (8 + njavg - ns);
     const double fl_one = fl_op + fl_upd;
     int step = 0;   // one-launch steps launched (the next one's index)
     int next = chunk_;
@@ -1769,8 +1795,8 @@ class Sequencer {
         (1 << ROM_K_DCG_OP) | (1 << ROM_K_DCG_UPDATE) | (1 << ROM_K_DCG_STEP);
     const bool graphs = graph_ && !(o_.timing & cg_classes);
     auto iter = [&](hipStream_t st) {
-      launch_dcg_iter<T>(S_, sh, b.diag, b.s, b.q, b.w, b.pstride, ld_, dvec, b.AW, wstride,
-                         ld_, njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.po,
+      launch_dcg_iter<T>(S_, sh, b.diag, b.s, b.q, b.w, b.pstride, ld_, dvec, b.AW, sl,
+                         njmax, GWinv_, GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.po,
                          pos_, b.pohalf, step == 0 ? P0 : sh.blocks, step & 1, step == 0, nb,
                          st);
       ++step;
@@ -1787,7 +1813,7 @@ class Sequencer {
           }
           const int reps = std::max(1, (next - launched + GRAPH_STEPS - 1) / GRAPH_STEPS);
           hipGraphExec_t ex =
-              chunk_graph<T>(b, nb, bt.shared, njmax, shape, wstride, gstride, dvec, sh);
+              chunk_graph<T>(b, nb, bt.shared, njmax, shape, sl, gstride, dvec, sh);
           for (int r = 0; r < reps; ++r) ROM_HIP(hipGraphLaunch(ex, st_));
           step += reps * GRAPH_STEPS;
           launched += reps * GRAPH_STEPS;
@@ -1847,7 +1873,7 @@ class Sequencer {
       if (graphs) {
         const int reps = (next + GRAPH_STEPS - 1) / GRAPH_STEPS;
         hipGraphExec_t ex =
-            chunk_graph<T>(b, nb, bt.shared, njmax, shape, wstride, gstride, dvec, sh);
+            chunk_graph<T>(b, nb, bt.shared, njmax, shape, sl, gstride, dvec, sh);
         for (int r = 0; r < reps; ++r) ROM_HIP(hipGraphLaunch(ex, st_));
         next = reps * GRAPH_STEPS;
         for (int c = 0; c < next; ++c) {
@@ -1857,7 +1883,7 @@ class Sequencer {
       }
       for (int c = 0; c < (graphs ? 0 : next); ++c) {
         tm_->begin(ROM_K_DCG_OP);
-        launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, wstride, ld_, njmax, GWinv_,
+        launch_dcg_op<T>(S_, sh, b.diag, b.q, b.s, b.w, ld_, b.AW, sl, njmax, GWinv_,
                          GWs_, gstride, cg, cgv_, b.ps, P0, p2s_, b.pu, Pu, pus_, b.po, pos_, nb,
                          st_);
         tm_->end(ROM_K_DCG_OP, nlive * by_op + by_shared, nlive * fl_op);
@@ -1911,8 +1937,9 @@ class Sequencer {
     }
     // the correction: g = g_q - U e
     tm_->begin(ROM_K_DCG_ENDS);
-    launch_dcg_finish<T>(b.W, wstride, ld_, n_, njmax, dvec, ld_, cg, cgv_, nb, st_);
-    tm_->end(ROM_K_DCG_ENDS, nact * E * n_ * (2 + njavg), nact * 2.0 * n_ * njavg);
+    launch_dcg_finish<T>(b.W, sl, n_, njmax, dvec, ld_, cg, cgv_, nb, st_);
+    tm_->end(ROM_K_DCG_ENDS, nact * E * n_ * (2 + njavg - ns) + E * n_ * ns,
+             nact * 2.0 * n_ * njavg);
     for (int y = 0; y < nb; ++y) {
       if (!bt.active[y]) continue;
       bt.its[y] = h_->cg[y].its;
@@ -1960,7 +1987,7 @@ class Sequencer {
   double* rtb_ = nullptr;          // V^T A_i w, then G_i^{-1} V^T A_i w
   double* rub_ = nullptr;
   const double* xbase_ = nullptr;  // base point of the current inner solve
-  using GraphKey = std::tuple<int, int, int, int, int, const void*>;
+  using GraphKey = std::tuple<int, int, int, int, int, int64_t, int, const void*>;
   std::map<GraphKey, hipGraphExec_t> graphs_;
   hipStream_t cap_st_ = nullptr;   // capture stream of the graphs
   double inner_tol_ = 1e-5;

@@ -692,9 +692,13 @@ void launch_resid_unit(const Stencil& S, const double* diag, const double* x, in
 
 template <typename T>
 StencilShape cg_apply_shape(const Stencil& S, int target_blocks, const T* diag, const T* p,
-                            const T* w, int64_t vstride, const T* AW) {
+                            const T* w, int64_t vstride, const T* AW, bool quads) {
   StencilShape sh = stencil_shape(S, target_blocks);
-  if (stencil_pairs_ok(S, vstride, {diag, p, w, AW}, sizeof(T) == 4)) {
+  if (quads && sizeof(T) == 4 && stencil_quads_ok(S, vstride, {diag, p, w, AW})) {
+    sh.grid.x = ceil_div((int64_t)(S.nx / 4) * S.ny, BS);
+    sh.blocks = (int)(sh.grid.x * sh.grid.y);
+    sh.quads = 1;
+  } else if (stencil_pairs_ok(S, vstride, {diag, p, w, AW}, sizeof(T) == 4)) {
     sh.grid.x = ceil_div((int64_t)(S.nx / 2) * S.ny, BS);
     sh.blocks = (int)(sh.grid.x * sh.grid.y);
     sh.pairs = 1;
@@ -702,9 +706,9 @@ StencilShape cg_apply_shape(const Stencil& S, int target_blocks, const T* diag, 
   return sh;
 }
 template StencilShape cg_apply_shape<double>(const Stencil&, int, const double*, const double*,
-                                             const double*, int64_t, const double*);
+                                             const double*, int64_t, const double*, bool);
 template StencilShape cg_apply_shape<float>(const Stencil&, int, const float*, const float*,
-                                            const float*, int64_t, const float*);
+                                            const float*, int64_t, const float*, bool);
 
 void launch_resid_cols(const Stencil& S, const double* diag, const double* X, int64_t ldx, int nb,
                        const int64_t* idx, const double* scale, double* R, int64_t ldr,

@@ -1007,7 +1007,11 @@ struct UpdRows {
 
 // The update of member y = blockIdx.y (see the file comment).  Block b also reduces the
 // operator step's vector totals r = b, b + P, ... < 2 nj into cv (tw first, then ts).
-template <typename T, int RPT>
+// Each access moves V consecutive values (V = 16 / sizeof(T) where the vectors are
+// aligned, else 1): the kernel is bound by the number of load and store instructions, not
+// by their bytes.  Values past n are read as 0 (the vectors' storage runs to a multiple of
+// 64 elements) and not written.
+template <typename T, int RPT, int V>
 __global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const T* __restrict__ w0,
                                                        T* __restrict__ g0, T* __restrict__ s0,
                                                        int64_t vstride, int64_t n, int njt,
@@ -1028,18 +1032,26 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const 
   const int k = cg->kcur;
   const double gam = cg->gcur, cGc = cg->cGc;
   constexpr int R = RPT;
-  constexpr int64_t CH = (int64_t)CG_BS * R;
+  constexpr int64_t CH = (int64_t)CG_BS * R;   // accesses (of V values) per block and pass
+  const int64_t nv = (n + V - 1) / V;
   int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
-  T qv[R], wv[R], gv[R], sv[R];
+  T qv[R][V], wv[R][V], gv[R][V], sv[R][V];
   auto load = [&](int64_t b0) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int64_t i = b0 + (int64_t)u * CG_BS;
-      const bool in = i < n;
-      qv[u] = in ? q[i] : T(0);
-      wv[u] = in ? w[i] : T(0);
-      gv[u] = in ? g[i] : T(0);
-      sv[u] = in ? s[i] : T(0);
+      const int64_t vi = b0 + (int64_t)u * CG_BS, i = vi * V;
+      if (vi < nv) {
+        ldn(q, i, qv[u]);
+        ldn(w, i, wv[u]);
+        ldn(g, i, gv[u]);
+        ldn(s, i, sv[u]);
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (i + e >= n) qv[u][e] = wv[u][e] = gv[u][e] = sv[u][e] = T(0);
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) qv[u][e] = wv[u][e] = gv[u][e] = sv[u][e] = T(0);
+      }
     }
   };
   load(base);
@@ -1108,17 +1120,32 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const 
   for (;;) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int64_t i = base + (int64_t)u * CG_BS;
-      const T si = sv[u] - a * wv[u];   // 0 past the end (sv = wv = 0 there)
-      if (i < n) {
-        s[i] = si;
-        g[i] = gv[u] + a * qv[u];
-        q[i] = si + b * qv[u];
+      const int64_t i = (base + (int64_t)u * CG_BS) * V;
+      T sn[V], gn[V], qn[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const T si = sv[u][e] - a * wv[u][e];   // 0 past the end (sv = wv = 0 there)
+        sn[e] = si;
+        gn[e] = gv[u][e] + a * qv[u][e];
+        qn[e] = si + b * qv[u][e];
+        acc[0] += si * si;
       }
-      acc[0] += si * si;
+      if (i + V <= n) {
+        stn(s, i, sn);
+        stn(g, i, gn);
+        stn(q, i, qn);
+      } else if (i < n) {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (i + e < n) {
+            s[i + e] = sn[e];
+            g[i + e] = gn[e];
+            q[i + e] = qn[e];
+          }
+      }
     }
     base += (int64_t)gridDim.x * CH;
-    if (base - threadIdx.x >= n) break;
+    if (base - threadIdx.x >= nv) break;
     load(base);
   }
   write_partials_t<1, CG_BS>(acc, pu0 + y * pustride, blockIdx.x, gridDim.x);
@@ -1268,12 +1295,19 @@ void launch_dcg_update(T* q, const T* w, T* g, T* s, int64_t vstride, int64_t n,
                        int64_t pustride, int nb, int P, hipStream_t st, int narrow) {
   const dim3 grid(P, nb);
   const int njt = njt_of(njmax);
-  if (narrow)
-    ROM_LAUNCH((k_dcg_update<T, UpdRows<1>::value>), grid, dim3(CG_BS), 0, st, q, w, g, s, vstride,
-               n, njt, cg, cv, po, P1, postride, pu, pustride);
-  else
-    ROM_LAUNCH((k_dcg_update<T, UpdRows<0>::value>), grid, dim3(CG_BS), 0, st, q, w, g, s, vstride,
-               n, njt, cg, cv, po, P1, postride, pu, pustride);
+  // 16-byte accesses where every vector is aligned for them
+  constexpr int V = 16 / sizeof(T);
+  const bool vec = !((((uintptr_t)q | (uintptr_t)w | (uintptr_t)g | (uintptr_t)s) & 15) ||
+                     vstride % V);
+#define UPL(RR, VV)                                                                         \
+  ROM_LAUNCH((k_dcg_update<T, RR, VV>), grid, dim3(CG_BS), 0, st, q, w, g, s, vstride, n, njt, \
+             cg, cv, po, P1, postride, pu, pustride)
+  if (vec) {
+    if (narrow) UPL(UpdRows<1>::value, V); else UPL(UpdRows<0>::value, V);
+  } else {
+    if (narrow) UPL(UpdRows<1>::value, 1); else UPL(UpdRows<0>::value, 1);
+  }
+#undef UPL
   ROM_CHECK_LAUNCH();
 }
 

@@ -133,11 +133,8 @@ def stream_points(prob, pts, W: int, K: int, wl, timing: int = 0, reduce_each: b
 # KiB per dispatch, averaged over the dispatches) on the default headline command, and the
 # scale of each counter from a plain device copy of known size.  Reported as `traffic`
 # only for that configuration; a change to the kernel needs new counter runs.
-OP_TRAFFIC = {"fetch_kib": 436266.3, "write_kib": 54333.6, "fetch_scale": 2.0,
-              "write_scale": 1.0, "dispatches": 45696,
-              "config": {"workload": "cube128_lognormal", "precision": "mixed", "group": 8,
-                         "cg_step": 1},
-              "profile": "profiles/cg_operator_step_cube128_lognormal_group8.md"}
+# None until the counters are taken on the current kernel.
+OP_TRAFFIC = None
 
 
 def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None,
@@ -157,10 +154,12 @@ def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None,
             "kernel": "k_dcg_op (CG operator step: w = A q - (A U_j) c with its dot products)",
             "launches": int(k["launches"]), "avg_launch_us": 1e3 * avg_ms,
             "bytes_per_launch": by,
-            "bytes_formula": f"{E} N (g (3 + n_j) + " + ("4" if prob.D_field is not None else "1")
-                             + ") per launch of g live members (per member q, s and the n_j "
-                             "columns of A U_j read and w written; the diagonal"
-                             + (" and 3 face arrays" if prob.D_field is not None else "")
+            "bytes_formula": f"{E} N (g (3 + n_j - n_s) + n_s + "
+                             + ("4" if prob.D_field is not None else "1")
+                             + ") per launch of g live members (per member q, s and its own "
+                             "n_j - n_s columns of A U_j read and w written; the n_s columns of "
+                             "A_i U_0 that every member shares after the first point, the "
+                             "diagonal" + (" and 3 face arrays" if prob.D_field is not None else "")
                              + " read once for all members)",
             "note": "events on every launch of this class over the timed points; the update "
                     "kernel and the rest are in 'kernel_classes'"}
@@ -168,7 +167,7 @@ def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None,
         a = all_pts["kernels"]["dcg_op"]
         out["bytes_per_launch_all_points"] = a["bytes"] / max(a["launches"], 1)
         out["launches_all_points"] = int(a["launches"])
-    if run_config == OP_TRAFFIC["config"]:
+    if OP_TRAFFIC is not None and run_config == OP_TRAFFIC["config"]:
         t = OP_TRAFFIC
         out["traffic"] = 1024.0 * (t["fetch_scale"] * t["fetch_kib"] + t["write_scale"] * t["write_kib"])
         out["traffic_note"] = (f"HBM bytes per dispatch over {t['dispatches']} dispatches of the "

@@ -284,6 +284,13 @@ __device__ __forceinline__ double dpp_move(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
   return __hiloint2double(hi, lo);
 }
+
+// Whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane l receives lane l - 1's
+// (shr) or lane l + 1's (shl) value; lane 0 (shr) and lane 63 (shl) receive 0.
+__device__ __forceinline__ float wave_shr1(float v) { return dpp_move<0x138, 0xf>(v); }
+__device__ __forceinline__ float wave_shl1(float v) { return dpp_move<0x130, 0xf>(v); }
+__device__ __forceinline__ double wave_shr1(double v) { return dpp_move<0x138, 0xf>(v); }
+__device__ __forceinline__ double wave_shl1(double v) { return dpp_move<0x130, 0xf>(v); }
 __device__ __forceinline__ float lane63(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }

@@ -371,15 +371,20 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     for (int c = 0; c < NJT; ++c) zero(P.a[PRE ? c : 0]);
   }
   T xm[NP], xc[NP], fm[NP];
+  // XS (the four-node walk): a wave holds consecutive positions, so the x-neighbours of a
+  // position are the adjacent lanes' end values (moved across the wave below); only the
+  // wave's first and last lanes load theirs
+  constexpr bool XS = NP == 4;
+  const int xln = threadIdx.x % WAVE;
   auto load_plane = [&](uint32_t bj, int z) {
     if (z < S.nz - 1) ldb(q, bj + bplane, P.xp); else zero(P.xp);
-    P.xl = hl ? ld1<-1>(q, bj) : T(0);
-    P.xr = hr ? ld1<NP>(q, bj) : T(0);
+    P.xl = (hl && (!XS || xln == 0)) ? ld1<-1>(q, bj) : T(0);
+    P.xr = (hr && (!XS || xln == WAVE - 1)) ? ld1<NP>(q, bj) : T(0);
     if (hd) ldb(q, bj - bx, P.yd); else zero(P.yd);
     if (hu) ldb(q, bj + bx, P.yu); else zero(P.yu);
     ldb(diag, bj, P.d);
     if (VAR) {
-      P.fxl = hl ? ld1<-1>(Fx, bj) : T(0);
+      P.fxl = (hl && (!XS || xln == 0)) ? ld1<-1>(Fx, bj) : T(0);
       ldb(Fx, bj, P.fx);
       if (hd) ldb(Fy, bj - bx, P.fyd); else zero(P.fyd);
       ldb(Fy, bj, P.fyu);
@@ -495,16 +500,28 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   const T m = act ? T(1) : T(0);
   for (int z = z0; walk && z < z1; ++z, bi += bplane) {
     // (A q) at the NP nodes
+    T xl = P.xl, xr = P.xr, fxl = P.fxl;
+    if (XS) {
+      // whole-wave shifts by one lane: lane l takes lane l - 1's last and lane l + 1's
+      // first value (the first and last lanes keep their loaded ones); 0 off the grid
+      const T sl = wave_shr1(xc[NP - 1]), sr = wave_shl1(xc[0]);
+      xl = hl ? (xln == 0 ? P.xl : sl) : T(0);
+      xr = hr ? (xln == WAVE - 1 ? P.xr : sr) : T(0);
+      if (VAR) {
+        const T sf = wave_shr1(P.fx[NP - 1]);
+        fxl = hl ? (xln == 0 ? P.fxl : sf) : T(0);
+      }
+    }
     T av[NP], xq[NP];
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
-      const T left = u == 0 ? P.xl : xc[u - 1];
-      const T right = u == NP - 1 ? P.xr : xc[u + 1];
+      const T left = u == 0 ? xl : xc[u - 1];
+      const T right = u == NP - 1 ? xr : xc[u + 1];
       T v = P.d[u] * xc[u];
       if (!VAR) {
         v -= cx * (left + right) + cy * (P.yd[u] + P.yu[u]) + cz * (xm[u] + P.xp[u]);
       } else {
-        const T fl = u == 0 ? P.fxl : P.fx[u - 1];
+        const T fl = u == 0 ? fxl : P.fx[u - 1];
         v -= fl * left + P.fx[u] * right;
         v -= P.fyd[u] * P.yd[u] + P.fyu[u] * P.yu[u];
         if (S.dim == 3) v -= fm[u] * xm[u] + P.fp[u] * P.xp[u];

@@ -324,6 +324,10 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   constexpr bool IMM = OpMode<T, NJT>::imm;
   constexpr bool PRE = OpMode<T, NJT>::pre;
   constexpr bool KEEP = OpMode<T, NJT>::keep;
+  // the column walk without a branch per column (the rows past nj are 0 and their sums
+  // unused) where the sums stay in registers; with per-plane wave reductions the columns
+  // past nj are skipped
+  constexpr bool FREE = PRE && !IMM;
   const StepBlock bk = step_block(gx, ntiles, nb);
   if (!bk.valid) return;
   const int y = bk.y;
@@ -498,7 +502,10 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   };
   const T cx = (T)S.cx, cy = (T)S.cy, cz = (T)S.cz;
   const T m = act ? T(1) : T(0);
-  for (int z = z0; walk && z < z1; ++z, bi += bplane) {
+  // one plane; more: load the next one (the last plane of the chunk is peeled off below, so
+  // that the loop's loads need no branch: under one, the registers of the plane would be
+  // merged and copied every plane)
+  auto plane = [&](int z, bool more) __attribute__((always_inline)) {
     // (A q) at the NP nodes
     T xl = P.xl, xr = P.xr, fxl = P.fxl;
     if (XS) {
@@ -535,7 +542,7 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     T keep[KEEP ? NJT : 1][NP];
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (PRE || c < nj) {
+      if (FREE || c < nj) {
         T a[NP];
         if (PRE) {
 #pragma unroll
@@ -566,7 +573,7 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     // pass 2: (AU)^T w
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (PRE || c < nj) {
+      if (FREE || c < nj) {
         T a[NP];
         if (PRE) {
 #pragma unroll
@@ -588,11 +595,11 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
       xc[u] = P.xp[u];
       if (VAR) fm[u] = P.fp[u];
     }
-    // the next plane, unconditionally (the last plane loads itself again, unused): under a
-    // branch, the registers of the plane would be merged and copied every plane
-    const bool more = z + 1 < z1;
-    load_plane(more ? bi + bplane : bi, more ? z + 1 : z);
-  }
+    if (more) load_plane(bi + bplane, z + 1);
+  };
+  int z = z0;
+  for (; walk && z < z1 - 1; ++z, bi += bplane) plane(z, true);
+  if (walk) plane(z, false);
   T* __restrict__ po = po0 + y * postride;
   const int P1 = ntiles;
   const int bid = bk.t;
@@ -1312,9 +1319,12 @@ void launch_dcg_update(T* q, const T* w, T* g, T* s, int64_t vstride, int64_t n,
                        int64_t pustride, int nb, int P, hipStream_t st, int narrow) {
   const dim3 grid(P, nb);
   const int njt = njt_of(njmax);
-  // 16-byte accesses where every vector is aligned for them
+  // 16-byte accesses where every vector is aligned for them and long enough that the
+  // instruction count, not the latency of fewer threads, bounds the kernel (at 64^3 the
+  // one-value form measured faster, at 128^3 the 16-byte form)
   constexpr int V = 16 / sizeof(T);
-  const bool vec = !((((uintptr_t)q | (uintptr_t)w | (uintptr_t)g | (uintptr_t)s) & 15) ||
+  const bool vec = n >= (int64_t(1) << 20) &&
+                   !((((uintptr_t)q | (uintptr_t)w | (uintptr_t)g | (uintptr_t)s) & 15) ||
                      vstride % V);
 #define UPL(RR, VV)                                                                         \
   ROM_LAUNCH((k_dcg_update<T, RR, VV>), grid, dim3(CG_BS), 0, st, q, w, g, s, vstride, n, njt, \

@@ -635,7 +635,7 @@ def main():
                                  "classes over the wall time of those points: a lower bound "
                                  "of the GPU's busy share (the small kernels of class 'other' "
                                  "carry no events); rocprofv3 over a whole headline run "
-                                 "reads 0.95"}
+                                 "reads 0.94"}
         # the other forms of config 4's method on the same points
         forms = {}
         for fname, kw in (("fp64", dict(precision=R.ROM_PREC_FP64)),

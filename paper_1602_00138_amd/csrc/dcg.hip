@@ -65,6 +65,29 @@ __device__ __forceinline__ const T* col_of(const T* own, const T* shared, int ns
   return (c < ns ? shared : own) + (int64_t)c * ld;
 }
 
+// Block order of the CG kernels that read the members' shared data (one-dimensional grid
+// of round_up(ntiles, NXCD) * nb blocks): the nb members' blocks of one tile are handed out
+// one after another to the same XCD, so the data they share (the shared columns of U and
+// AU; in the operator step also the diagonal and face coefficients) is fetched from HBM
+// once into that XCD's L2 whatever the grid size.  In the operator step tile t is
+// x-position block t % gx of z chunk t / gx; in the start and finish (gx = ntiles) it is
+// the row chunk.  Blocks past the last tile (t >= ntiles) have no work.
+struct StepBlock {
+  int y, t, tx, tz;
+  bool valid;
+};
+__device__ __forceinline__ StepBlock step_block(int gx, int ntiles, int nb) {
+  const int L = blockIdx.x;
+  const int r = L / NXCD;
+  StepBlock b;
+  b.y = r % nb;
+  b.t = (r / nb) * NXCD + L % NXCD;
+  b.valid = b.t < ntiles;
+  b.tx = b.t % gx;
+  b.tz = b.t / gx;
+  return b;
+}
+
 // Row j = threadIdx.x < nj of Ginv = (U^T A U)^{-1} (symmetric, FP64) is loaded early
 // into registers, where it fits (NJT <= 16), so that its latency hides behind other loads.
 template <int NJT>
@@ -120,8 +143,11 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W0
                                                          int64_t rstride, T* __restrict__ g,
                                                          T* __restrict__ s, T* __restrict__ qv,
                                                          int64_t vstride, const CGState* cgs,
-                                                         T* __restrict__ ps, int64_t psstride) {
-  const int y = blockIdx.y;
+                                                         T* __restrict__ ps, int64_t psstride,
+                                                         int P, int nb) {
+  const StepBlock bk = step_block(P, P, nb);
+  if (!bk.valid) return;
+  const int y = bk.y;
   const CGState* cg = cgs + y;
   if (cg->done) return;
   const int64_t ld = sl.ld;
@@ -141,7 +167,7 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W0
   constexpr bool PRE = RPT > 0;
   constexpr int R = PRE ? RPT : 1;
   constexpr int64_t CH = (int64_t)START_BS * R;
-  int64_t base = (int64_t)blockIdx.x * CH + threadIdx.x;
+  int64_t base = (int64_t)bk.t * CH + threadIdx.x;
   T wr[R][PRE ? NJT : 1], ar[R][PRE ? NJT : 1], rv[R];
   auto load = [&](int64_t b0) {
 #pragma unroll
@@ -201,11 +227,11 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W0
                          : KEEP ? kept[KEEP ? c : 0]
                                 : (in ? col_of(AW, AWs, ns, c, ld)[i] : T(0))) * si;
     }
-    base += (int64_t)gridDim.x * CH;
+    base += (int64_t)P * CH;
     if (base - threadIdx.x >= n) break;
     load(base);
   }
-  write_partials_t<NJT + 1, START_BS>(acc, ps, blockIdx.x, gridDim.x);
+  write_partials_t<NJT + 1, START_BS>(acc, ps, bk.t, P);
 }
 
 // NP consecutive values at index i (vector loads for NP = 2 and 4: i a multiple of NP and
@@ -284,27 +310,6 @@ struct OpPlane {
   T fxl, fx[NP], fyd[NP], fyu[NP], fp[NP];
   T a[PRE ? NJT : 1][NP];
 };
-
-// Block order of the step kernels (one-dimensional grid of round_up(ntiles, NXCD) * nb
-// blocks): the nb members' blocks of one tile are handed out one after another to the same
-// XCD, so the data they share (diagonal, face coefficients, the shared columns of AU) is
-// fetched from HBM once into that XCD's L2 whatever the grid size; tile t is x-position
-// block t % gx of z chunk t / gx.  Blocks past the last tile (t >= ntiles) have no work.
-struct StepBlock {
-  int y, t, tx, tz;
-  bool valid;
-};
-__device__ __forceinline__ StepBlock step_block(int gx, int ntiles, int nb) {
-  const int L = blockIdx.x;
-  const int r = L / NXCD;
-  StepBlock b;
-  b.y = r % nb;
-  b.t = (r / nb) * NXCD + L % NXCD;
-  b.valid = b.t < ntiles;
-  b.tx = b.t % gx;
-  b.tz = b.t / gx;
-  return b;
-}
 
 // The operator step of member y over the z planes [tz zc, + zc) of the x-y positions of
 // block tx (NP consecutive x-nodes per thread; see step_block).  See the file comment.
@@ -1175,13 +1180,16 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const 
   write_partials_t<1, CG_BS>(acc, pu0 + y * pustride, blockIdx.x, gridDim.x);
 }
 
-// g -= U e (member y = blockIdx.y): the U part of the split correction.
+// g -= U e (member y; see step_block): the U part of the split correction.
 template <typename T, int NJT>
 __global__ __launch_bounds__(CG_BS) void k_dcg_finish(const T* __restrict__ W0, Slots sl,
                                                        int64_t n,
                                                        T* __restrict__ g0, int64_t vstride,
-                                                       const CGState* cgs, const CGVec* cvs) {
-  const int y = blockIdx.y;
+                                                       const CGState* cgs, const CGVec* cvs,
+                                                       int P, int nb) {
+  const StepBlock bk = step_block(P, P, nb);
+  if (!bk.valid) return;
+  const int y = bk.y;
   const CGState* cg = cgs + y;
   const int nj = cg->nj;
   if (nj == 0) return;
@@ -1191,8 +1199,7 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_finish(const T* __restrict__ W0, 
   const T* __restrict__ W = W0 + y * sl.wstride;
   const T* __restrict__ Ws = W0 + sl.soff;
   T* __restrict__ g = g0 + y * vstride;
-  for (int64_t i = (int64_t)blockIdx.x * CG_BS + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * CG_BS) {
+  for (int64_t i = (int64_t)bk.t * CG_BS + threadIdx.x; i < n; i += (int64_t)P * CG_BS) {
     T v = g[i];
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
@@ -1221,9 +1228,10 @@ void launch_dcg_start(const T* W, const T* AW, const Slots& sl, int64_t n, int n
                       const double* Ginv, int64_t gstride, const double* r, int64_t rstride, T* g,
                       T* s, T* q, int64_t vstride, const CGState* cg, T* ps, int64_t psstride,
                       int nb, int P, hipStream_t st) {
-  const dim3 grid(P, nb);
+  if (nb < 1 || nb > G_MAX || P < 1) throw Error(ROM_EINVAL, "dcg_start: bad batch or grid");
+  const dim3 grid(ceil_div(P, NXCD) * NXCD * nb);
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, sl, n, Ginv, gstride, r, rstride, g, s, q, vstride, cg, ps, psstride); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, sl, n, Ginv, gstride, r, rstride, g, s, q, vstride, cg, ps, psstride, P, nb); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }
@@ -1343,9 +1351,11 @@ void launch_dcg_finish(const T* W, const Slots& sl, int64_t n, int njmax, T* g,
                        int64_t vstride, const CGState* cg, const CGVec* cv, int nb,
                        hipStream_t st) {
   if (njmax <= 0) return;
-  const dim3 grid(dcg_blocks(n), nb);
+  if (nb < 1 || nb > G_MAX) throw Error(ROM_EINVAL, "dcg_finish: bad batch");
+  const int P = dcg_blocks(n);
+  const dim3 grid(ceil_div(P, NXCD) * NXCD * nb);
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_finish<T, J>), grid, dim3(CG_BS), 0, st, W, sl, n, g, vstride, cg, cv); break;
+#define C(J) case J: ROM_LAUNCH((k_dcg_finish<T, J>), grid, dim3(CG_BS), 0, st, W, sl, n, g, vstride, cg, cv, P, nb); break;
     C(8) C(16) C(32) C(64)
 #undef C
   }

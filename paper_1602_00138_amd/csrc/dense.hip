@@ -1267,4 +1267,21 @@ void launch_small_chol_inv(const double* G, int m, double* Linv, double* Ginv, i
   ROM_CHECK_LAUNCH();
 }
 
+namespace {
+__global__ void k_gram_assemble(const double* __restrict__ Gs, int lds, int k,
+                                double* __restrict__ G, int m) {
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int i = e % m, j = e / m;
+    if (i < k && j < k) G[i + j * m] = Gs[i + j * lds];
+    else if (j < k) G[i + j * m] = G[j + i * m];   // i >= k: mirror of the computed border
+  }
+}
+}  // namespace
+
+void launch_gram_assemble(const double* Gs, int lds, int k, double* G, int m, hipStream_t st) {
+  if (m <= 0 || k < 0 || k > m || m > NJ_MAX) throw Error(ROM_EINVAL, "gram_assemble: bad sizes");
+  ROM_LAUNCH(k_gram_assemble, dim3(1), dim3(BS), 0, st, Gs, lds, k, G, m);
+  ROM_CHECK_LAUNCH();
+}
+
 }  // namespace rom

@@ -307,6 +307,10 @@ void launch_gather_idx(const double* M, int64_t ld, const int64_t* idx, int64_t 
 // qb[t] = q[idx[t]] (qb may be NULL), zb[t] = wc[t] q[idx[t]] for t < cnt.
 void launch_gather_scale(const double* q, const int64_t* idx, const double* wc, int64_t cnt,
                          double* qb, double* zb, hipStream_t st);
+// The rest of a symmetric m x m Gram matrix G (col-major, ld = m, m <= NJ_MAX) whose
+// columns k..m-1 are computed: G[0:k, 0:k] = Gs[0:k, 0:k] (ld lds), and the block below it
+// G[k:m, 0:k] the transpose of G[0:k, k:m].
+void launch_gram_assemble(const double* Gs, int lds, int k, double* G, int m, hipStream_t st);
 // Small SPD m x m (m <= NJ_MAX) in one workgroup: Linv (inverse of its Cholesky factor)
 // and Ginv (its inverse), col-major, ld = m.  status[0] = 1 if not SPD.
 void launch_small_chol_inv(const double* G, int m, double* Linv, double* Ginv, int* status,

@@ -777,7 +777,13 @@ class Sequencer {
   // Pack U_j = [U_0 part of V, extra columns of RHS j] into member slot y and form
   // A_i U_j, its Gram matrix and the inverse (FP64; FP32 copies of U_j and A_i U_j in the
   // mixed form).  At point 0 every U_j is U_0 (slot 0, built once per point).
-  int make_W(int i, int j, int y) {
+  // src (groups after the first point): the group's slot that holds the first ku_ columns
+  // of A_i U_j (and their FP32 copies), the same for every member; -1 before the group's
+  // first member is built, which then builds them in full and becomes the source.  Later
+  // members form A_i only on their own columns (the CG kernels read the shared ones from
+  // the source slot) and take the U_0 block of their Gram matrix from the source's.  The
+  // FP64 U_j is always packed in full (U^T r and the Gram-Schmidt pass of U_j read it).
+  int make_W(int i, int j, int y, int* src = nullptr) {
     const int key = i == 0 ? -1 : j;
     ColPtrs cp;
     int nj = 0;
@@ -786,27 +792,46 @@ class Sequencer {
       for (int sl : extra_[j])
         if (nj < NJ_MAX) cp.p[nj++] = pool_ + (int64_t)sl * ld_;
     for (int c = 0; c < n_rec_kept_ && nj < NJ_MAX; ++c) cp.p[nj++] = rec_ + (int64_t)c * ld_;
-    if (key == w_key_[y] && nj == w_nj_[y]) return nj;
+    const bool part = src && *src >= 0 && *src != y && i > 0 && ku_ > 0 && nj >= ku_;
+    const int from = part ? *src : y;   // the slot holding the first ku_ columns of A_i U_j
+    if (key == w_key_[y] && nj == w_nj_[y] && from == w_src_[y]) {
+      if (src && *src < 0) *src = y;
+      return nj;
+    }
     w_key_[y] = key;
     w_nj_[y] = nj;
+    w_src_[y] = from;
     if (nj == 0) return 0;
     const int64_t off = (int64_t)y * ld_ * NJ_MAX;
     double* W = Wp_ + off;
     double* AW = AWp_ + off;
-    launch_pack_cols(n_, cp, nj, W, ld_, st_);
-    launch_spmm(S_, diag_i_, W, ld_, nj, AW, st_);
-    tm_->begin(ROM_K_GRAM);
-    // symmetric by construction: the lower triangle W_i^T (A W_j), i >= j, is mirrored
     double* GW = GWs_ + (int64_t)y * NJ_MAX * NJ_MAX;
-    launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, true, nullptr, 0, 0.0, GW, nj,
-                gram_part_, st_);
-    tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
+    const int k0 = part ? ku_ : 0;   // first column formed here
+    const int ne = nj - k0;
+    launch_pack_cols(n_, cp, nj, W, ld_, st_);
+    if (ne > 0) launch_spmm(S_, diag_i_, W + k0 * ld_, ld_, ne, AW + k0 * ld_, st_);
+    tm_->begin(ROM_K_GRAM);
+    if (!part) {
+      // symmetric by construction: the lower triangle W_i^T (A W_j), i >= j, is mirrored
+      launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, true, nullptr, 0, 0.0, GW, nj,
+                  gram_part_, st_);
+      tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
+    } else {
+      // columns ku_.. : W^T (A E); the U_0 block from the source; the block below it mirrored
+      if (ne > 0)
+        launch_gram(W, ld_, nj, AW + k0 * ld_, ld_, ne, n_, nullptr, false, nullptr, 0, 0.0,
+                    GW + (int64_t)k0 * nj, nj, gram_part_, st_);
+      launch_gram_assemble(GWs_ + (int64_t)from * NJ_MAX * NJ_MAX, w_nj_[from], k0, GW, nj,
+                           st_);
+      tm_->end(ROM_K_GRAM, 8.0 * n_ * (nj + ne), 2.0 * n_ * nj * ne);
+    }
     launch_small_chol_inv(GW, nj, LWinv_ + (int64_t)y * NJ_MAX * NJ_MAX,
                           GWinv_ + (int64_t)y * NJ_MAX * NJ_MAX, &ctrl_->status[1], st_);
-    if (mixed_) {
-      launch_cast_cols_f32(n_, nj, W, ld_, W32_ + off, st_);
-      launch_cast_cols_f32(n_, nj, AW, ld_, AW32_ + off, st_);
+    if (mixed_ && ne > 0) {
+      launch_cast_cols_f32(n_, ne, W + k0 * ld_, ld_, W32_ + off + k0 * ld_, st_);
+      launch_cast_cols_f32(n_, ne, AW + k0 * ld_, ld_, AW32_ + off + k0 * ld_, st_);
     }
+    if (src && *src < 0) *src = y;
     return nj;
   }
 
@@ -1221,8 +1246,11 @@ class Sequencer {
       // skipped members: x = x0
       launch_axpby_cols(n_, nb, 1.0, x0_, ld_, 0.0, nullptr, 0, xdst, ldx, st);
       if (any) {
+        // after the first point, the group's first member builds the shared columns of its
+        // recycle space and the others read them from its slot
+        int src = -1;
         for (int y = 0; y < nb; ++y)
-          if (act[y]) nj[y] = make_W(i, j0 + y, i == 0 ? 0 : y);
+          if (act[y]) nj[y] = make_W(i, j0 + y, i == 0 ? 0 : y, i == 0 ? nullptr : &src);
         // initial guesses move the members' base points (the Galerkin starts kept in xg_)
         bool moved[G_MAX] = {};
         if (guess_) guess_group(i, j0, nb, act, nbv, res, rec, moved);
@@ -1230,7 +1258,8 @@ class Sequencer {
           for (int y = 0; y < nb; ++y)
             if (act[y]) rec[y].rho_guess = -1.0;
         int its[G_MAX], restarts[G_MAX], flag[G_MAX];
-        solve_group(i == 0, nb, j0, act, nj, nbv, res, xdst, ldx, its, restarts, flag, rec);
+        solve_group(i == 0, i == 0 ? -1 : src, nb, j0, act, nj, nbv, res, xdst, ldx, its,
+                    restarts, flag, rec);
         // the correction that joins V and U_j is x - x0 (x0 the Galerkin start, in range(V))
         for (int y = 0; y < nb; ++y)
           if (moved[y]) {
@@ -1259,7 +1288,8 @@ class Sequencer {
   // FP64 refinement, a stalled member continuing in FP64).  On entry r_ holds the
   // members' residuals b - A x0 and res[] their relative norms; on exit g_ holds the
   // corrections, xdst the solutions and res[] the final relative residuals.
-  void solve_group(bool shared, int nb, int j0, const int* act, const int* nj, const double* nbv,
+  void solve_group(bool shared, int src, int nb, int j0, const int* act, const int* nj,
+                   const double* nbv,
                    double* res, double* xdst, int64_t ldx, int* its, int* restarts, int* flag,
                    rom_record* rec) {
     ROM_HIP(hipMemsetAsync(g_, 0, sizeof(double) * ld_ * nb, st_));
@@ -1274,6 +1304,7 @@ class Sequencer {
       Batch b32, b64;
       b32.nb = b64.nb = nb;
       b32.shared = b64.shared = shared;
+      b32.src = b64.src = src;
       Coefs c32, c64;
       bool any32 = false, any64 = false;
       for (int y = 0; y < nb; ++y) {
@@ -1502,6 +1533,7 @@ class Sequencer {
   struct Batch {
     int nb = 0;
     bool shared = false;
+    int src = -1;   // slot of the shared leading columns (see make_W), -1: each its own
     int active[G_MAX] = {};
     int nj[G_MAX] = {};
     int maxit[G_MAX] = {};
@@ -1717,18 +1749,12 @@ class Sequencer {
     }
     if (nact == 0) return;
     // after the first point every member's recycle space starts with the same ku_ columns
-    // (U_0 and A_i U_0, packed and multiplied the same way into every slot): the kernels
-    // read them from the first active member's slot for all members
+    // (U_0 and A_i U_0), built in the group's source slot only (make_W): the kernels read
+    // them from there for every member
     Slots sl{wstride, ld_, 0, 0};
-    if (!bt.shared && nact > 1 && ku_ > 0) {
-      int ysrc = -1, ns = ku_;
-      for (int y = 0; y < nb; ++y)
-        if (bt.active[y]) {
-          if (ysrc < 0) ysrc = y;
-          ns = std::min(ns, bt.nj[y]);
-        }
-      sl.soff = ysrc * wstride;
-      sl.ns = ns;
+    if (!bt.shared && bt.src >= 0 && ku_ > 0) {
+      sl.soff = bt.src * wstride;
+      sl.ns = ku_;
     }
     const int shape = cg_shape<T>(bt, b, rhs, dvec, sl, gstride, njmax);
     const int P = shape_P(shape), nr = shape_nr(shape);
@@ -2000,7 +2026,7 @@ class Sequencer {
   unsigned seq_ = 0;
   double mu0_ = 0.0;
   int m_ = 0, ku_ = 0, next_slot_ = 0;
-  int w_key_[G_MAX], w_nj_[G_MAX] = {};
+  int w_key_[G_MAX], w_nj_[G_MAX] = {}, w_src_[G_MAX] = {};
   // results
   std::vector<rom_record> recs_;
   rom_status status_ = ROM_OK;

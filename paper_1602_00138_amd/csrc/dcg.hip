@@ -65,6 +65,39 @@ __device__ __forceinline__ const T* col_of(const T* own, const T* shared, int ns
   return (c < ns ? shared : own) + (int64_t)c * ld;
 }
 
+// NP consecutive values at index i (vector loads for NP = 2 and 4: i a multiple of NP and
+// the array aligned, as the two- and four-node walks require).
+template <typename T>
+__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[1]) {
+  v[0] = p[i];
+}
+template <typename T>
+__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[2]) {
+  const typename Vec2<T>::type t = *reinterpret_cast<const typename Vec2<T>::type*>(p + i);
+  v[0] = t.x;
+  v[1] = t.y;
+}
+template <typename T>
+__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[4]) {
+  const typename Vec4<T>::type t = *reinterpret_cast<const typename Vec4<T>::type*>(p + i);
+  v[0] = t.x;
+  v[1] = t.y;
+  v[2] = t.z;
+  v[3] = t.w;
+}
+template <typename T>
+__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[1]) {
+  p[i] = v[0];
+}
+template <typename T>
+__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[2]) {
+  *reinterpret_cast<typename Vec2<T>::type*>(p + i) = typename Vec2<T>::type{v[0], v[1]};
+}
+template <typename T>
+__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[4]) {
+  *reinterpret_cast<typename Vec4<T>::type*>(p + i) = typename Vec4<T>::type{v[0], v[1], v[2], v[3]};
+}
+
 // Block order of the CG kernels that read the members' shared data (one-dimensional grid
 // of round_up(ntiles, NXCD) * nb blocks): the nb members' blocks of one tile are handed out
 // one after another to the same XCD, so the data they share (the shared columns of U and
@@ -132,8 +165,10 @@ struct StartRows {
 // Start: y0 = G^{-1} U^T r (U^T r in cg->t), g = U y0, s = q = r - AU y0; partials of
 // (AU)^T s (values 0..nj-1) and s^T s (value NJT).  The right-hand side is FP64 and is
 // read as rscale * r (the mixed form solves for a unit-norm residual in FP32).  A thread
-// loads its first chunk's rows before y0 is formed.
-template <typename T, int NJT, int RPT = StartRows<T, NJT>::value>
+// loads its first chunk's rows before y0 is formed.  V: values per access (16-byte
+// accesses where the launcher finds n, the strides and the arrays aligned for them; the
+// kernel is bound by its load instructions), RPT / V accesses per thread and pass.
+template <typename T, int NJT, int RPT = StartRows<T, NJT>::value, int V = 1>
 __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W0,
                                                          const T* __restrict__ AW0,
                                                          Slots sl, int64_t n,
@@ -165,21 +200,46 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W0
   const int nj = cg->nj;
   const double rscale = cg->rscale;
   constexpr bool PRE = RPT > 0;
-  constexpr int R = PRE ? RPT : 1;
-  constexpr int64_t CH = (int64_t)START_BS * R;
-  int64_t base = (int64_t)bk.t * CH + threadIdx.x;
-  T wr[R][PRE ? NJT : 1], ar[R][PRE ? NJT : 1], rv[R];
+  static_assert(V == 1 || (PRE && RPT % V == 0), "vector accesses need the preloaded rows");
+  constexpr int R = PRE ? RPT / V : 1;
+  constexpr int64_t STEP = (int64_t)START_BS * V;   // elements between a thread's accesses
+  constexpr int64_t CH = STEP * R;
+  int64_t base = (int64_t)bk.t * CH + (int64_t)threadIdx.x * V;
+  T wr[R][PRE ? NJT : 1][V], ar[R][PRE ? NJT : 1][V], rv[R][V];
+  auto zero = [](T (&v)[V]) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) v[e] = T(0);
+  };
+  // V FP64 values of r at i (16-byte loads for V > 1)
+  auto ldr = [&](int64_t i, T (&v)[V]) {
+    if (V == 1) {
+      v[0] = (T)r[i];
+    } else {
+#pragma unroll
+      for (int h = 0; h < V; h += 2) {
+        const double2 t = *reinterpret_cast<const double2*>(r + i + h);
+        v[h] = (T)t.x;
+        v[h + 1] = (T)t.y;
+      }
+    }
+  };
+  // with V > 1, n is a multiple of V: an access's values are all in range or all past it
   auto load = [&](int64_t b0) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int64_t i = b0 + (int64_t)q * START_BS;
+      const int64_t i = b0 + (int64_t)q * STEP;
       const bool in = i < n;
-      rv[q] = in ? (T)r[i] : T(0);
+      if (in) ldr(i, rv[q]); else zero(rv[q]);
       if (PRE) {
 #pragma unroll
         for (int c = 0; c < NJT; ++c) {
-          wr[q][PRE ? c : 0] = (in && c < nj) ? col_of(W, Ws, ns, c, ld)[i] : T(0);
-          ar[q][PRE ? c : 0] = (in && c < nj) ? col_of(AW, AWs, ns, c, ld)[i] : T(0);
+          if (in && c < nj) {
+            ldn(col_of(W, Ws, ns, c, ld), i, wr[q][PRE ? c : 0]);
+            ldn(col_of(AW, AWs, ns, c, ld), i, ar[q][PRE ? c : 0]);
+          } else {
+            zero(wr[q][PRE ? c : 0]);
+            zero(ar[q][PRE ? c : 0]);
+          }
         }
       }
     }
@@ -201,70 +261,52 @@ __global__ __launch_bounds__(START_BS) void k_dcg_start(const T* __restrict__ W0
     constexpr bool KEEP = !PRE && NJT * sizeof(T) <= 256;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int64_t i = base + (int64_t)q * START_BS;
+      const int64_t i = base + (int64_t)q * STEP;
       const bool in = i < n;
-      T gi = T(0), si = rs * rv[q];
+      T gi[V], si[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        gi[e] = T(0);
+        si[e] = rs * rv[q][e];
+      }
       T kept[KEEP ? NJT : 1];
 #pragma unroll
       for (int c = 0; c < NJT; ++c)
         if (c < nj) {
-          const T wv = PRE ? wr[q][PRE ? c : 0] : (in ? col_of(W, Ws, ns, c, ld)[i] : T(0));
-          const T av = PRE ? ar[q][PRE ? c : 0] : (in ? col_of(AW, AWs, ns, c, ld)[i] : T(0));
-          if (KEEP) kept[KEEP ? c : 0] = av;
-          gi += wv * ys[c];
-          si -= av * ys[c];
+          const T yc = ys[c];
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            const T wv = PRE ? wr[q][PRE ? c : 0][e]
+                             : (in ? col_of(W, Ws, ns, c, ld)[i] : T(0));
+            const T av = PRE ? ar[q][PRE ? c : 0][e]
+                             : (in ? col_of(AW, AWs, ns, c, ld)[i] : T(0));
+            if (KEEP) kept[KEEP ? c : 0] = av;
+            gi[e] += wv * yc;
+            si[e] -= av * yc;
+          }
         }
       if (in) {
-        g[i] = gi;
-        s[i] = si;
-        qv[i] = si;
+        stn(g, i, gi);
+        stn(s, i, si);
+        stn(qv, i, si);
       }
-      acc[NJT] += si * si;   // 0 past the end (rv and the rows are 0 there)
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[NJT] += si[e] * si[e];   // 0 past the end
 #pragma unroll
       for (int c = 0; c < NJT; ++c)
-        if (c < nj)
-          acc[c] += (PRE ? ar[q][PRE ? c : 0]
-                         : KEEP ? kept[KEEP ? c : 0]
-                                : (in ? col_of(AW, AWs, ns, c, ld)[i] : T(0))) * si;
+        if (c < nj) {
+#pragma unroll
+          for (int e = 0; e < V; ++e)
+            acc[c] += (PRE ? ar[q][PRE ? c : 0][e]
+                           : KEEP ? kept[KEEP ? c : 0]
+                                  : (in ? col_of(AW, AWs, ns, c, ld)[i] : T(0))) * si[e];
+        }
     }
     base += (int64_t)P * CH;
-    if (base - threadIdx.x >= n) break;
+    if (base - (int64_t)threadIdx.x * V >= n) break;
     load(base);
   }
   write_partials_t<NJT + 1, START_BS>(acc, ps, bk.t, P);
-}
-
-// NP consecutive values at index i (vector loads for NP = 2 and 4: i a multiple of NP and
-// the array aligned, as the two- and four-node walks require).
-template <typename T>
-__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[1]) {
-  v[0] = p[i];
-}
-template <typename T>
-__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[2]) {
-  const typename Vec2<T>::type t = *reinterpret_cast<const typename Vec2<T>::type*>(p + i);
-  v[0] = t.x;
-  v[1] = t.y;
-}
-template <typename T>
-__device__ __forceinline__ void ldn(const T* __restrict__ p, int64_t i, T (&v)[4]) {
-  const typename Vec4<T>::type t = *reinterpret_cast<const typename Vec4<T>::type*>(p + i);
-  v[0] = t.x;
-  v[1] = t.y;
-  v[2] = t.z;
-  v[3] = t.w;
-}
-template <typename T>
-__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[1]) {
-  p[i] = v[0];
-}
-template <typename T>
-__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[2]) {
-  *reinterpret_cast<typename Vec2<T>::type*>(p + i) = typename Vec2<T>::type{v[0], v[1]};
-}
-template <typename T>
-__device__ __forceinline__ void stn(T* __restrict__ p, int64_t i, const T (&v)[4]) {
-  *reinterpret_cast<typename Vec4<T>::type*>(p + i) = typename Vec4<T>::type{v[0], v[1], v[2], v[3]};
 }
 
 // The same loads and stores at byte offset bo from an array's base p (wave-uniform).  The
@@ -1230,11 +1272,28 @@ void launch_dcg_start(const T* W, const T* AW, const Slots& sl, int64_t n, int n
                       int nb, int P, hipStream_t st) {
   if (nb < 1 || nb > G_MAX || P < 1) throw Error(ROM_EINVAL, "dcg_start: bad batch or grid");
   const dim3 grid(ceil_div(P, NXCD) * NXCD * nb);
+  // 16-byte accesses where n, the strides and every array allow them (the widths whose
+  // rows are preloaded)
+  constexpr int V = 16 / sizeof(T);
+  const uintptr_t al = (uintptr_t)W | (uintptr_t)AW | (uintptr_t)(W + sl.soff) |
+                       (uintptr_t)(AW + sl.soff) | (uintptr_t)g | (uintptr_t)s | (uintptr_t)q |
+                       (uintptr_t)r;
+  const bool vec = n % V == 0 && sl.ld % V == 0 && sl.wstride % V == 0 && vstride % V == 0 &&
+                   rstride % 2 == 0 && (al & 15) == 0;
+#define C(J)                                                                                  \
+  case J:                                                                                     \
+    if (vec && StartRows<T, J>::value > 0)                                                    \
+      ROM_LAUNCH((k_dcg_start<T, J, StartRows<T, J>::value, (StartRows<T, J>::value > 0 ? V : 1)>), \
+                 grid, dim3(START_BS), 0, st, W, AW, sl, n, Ginv, gstride, r, rstride, g, s, q,  \
+                 vstride, cg, ps, psstride, P, nb);                                             \
+    else                                                                                      \
+      ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, sl, n, Ginv, gstride, \
+                 r, rstride, g, s, q, vstride, cg, ps, psstride, P, nb);                        \
+    break;
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_start<T, J>), grid, dim3(START_BS), 0, st, W, AW, sl, n, Ginv, gstride, r, rstride, g, s, q, vstride, cg, ps, psstride, P, nb); break;
     C(8) C(16) C(32) C(64)
-#undef C
   }
+#undef C
   ROM_CHECK_LAUNCH();
 }
 

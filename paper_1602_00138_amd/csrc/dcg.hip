@@ -1222,8 +1222,9 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_update(T* __restrict__ q0, const 
   write_partials_t<1, CG_BS>(acc, pu0 + y * pustride, blockIdx.x, gridDim.x);
 }
 
-// g -= U e (member y; see step_block): the U part of the split correction.
-template <typename T, int NJT>
+// g -= U e (member y; see step_block): the U part of the split correction.  V values per
+// access (16-byte accesses where the launcher finds n and the layout aligned for them).
+template <typename T, int NJT, int V = 1>
 __global__ __launch_bounds__(CG_BS) void k_dcg_finish(const T* __restrict__ W0, Slots sl,
                                                        int64_t n,
                                                        T* __restrict__ g0, int64_t vstride,
@@ -1241,12 +1242,21 @@ __global__ __launch_bounds__(CG_BS) void k_dcg_finish(const T* __restrict__ W0, 
   const T* __restrict__ W = W0 + y * sl.wstride;
   const T* __restrict__ Ws = W0 + sl.soff;
   T* __restrict__ g = g0 + y * vstride;
-  for (int64_t i = (int64_t)bk.t * CG_BS + threadIdx.x; i < n; i += (int64_t)P * CG_BS) {
-    T v = g[i];
+  // with V > 1, n is a multiple of V
+  for (int64_t i = ((int64_t)bk.t * CG_BS + threadIdx.x) * V; i < n;
+       i += (int64_t)P * CG_BS * V) {
+    T v[V];
+    ldn(g, i, v);
 #pragma unroll
     for (int c = 0; c < NJT; ++c)
-      if (c < nj) v -= col_of(W, Ws, sl.ns, c, sl.ld)[i] * es[c];
-    g[i] = v;
+      if (c < nj) {
+        T w[V];
+        ldn(col_of(W, Ws, sl.ns, c, sl.ld), i, w);
+        const T ec = es[c];
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] -= w[e] * ec;
+      }
+    stn(g, i, v);
   }
 }
 
@@ -1413,11 +1423,22 @@ void launch_dcg_finish(const T* W, const Slots& sl, int64_t n, int njmax, T* g,
   if (nb < 1 || nb > G_MAX) throw Error(ROM_EINVAL, "dcg_finish: bad batch");
   const int P = dcg_blocks(n);
   const dim3 grid(ceil_div(P, NXCD) * NXCD * nb);
+  constexpr int V = 16 / sizeof(T);
+  const bool vec = n % V == 0 && sl.ld % V == 0 && sl.wstride % V == 0 && vstride % V == 0 &&
+                   (((uintptr_t)W | (uintptr_t)(W + sl.soff) | (uintptr_t)g) & 15) == 0;
+#define C(J)                                                                                  \
+  case J:                                                                                     \
+    if (vec)                                                                                  \
+      ROM_LAUNCH((k_dcg_finish<T, J, V>), grid, dim3(CG_BS), 0, st, W, sl, n, g, vstride, cg, cv, \
+                 P, nb);                                                                      \
+    else                                                                                      \
+      ROM_LAUNCH((k_dcg_finish<T, J>), grid, dim3(CG_BS), 0, st, W, sl, n, g, vstride, cg, cv, P, \
+                 nb);                                                                         \
+    break;
   switch (njt_of(njmax)) {
-#define C(J) case J: ROM_LAUNCH((k_dcg_finish<T, J>), grid, dim3(CG_BS), 0, st, W, sl, n, g, vstride, cg, cv, P, nb); break;
     C(8) C(16) C(32) C(64)
-#undef C
   }
+#undef C
   ROM_CHECK_LAUNCH();
 }
 

@@ -817,8 +817,12 @@ class Sequencer {
                   gram_part_, st_);
       tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
     } else {
-      // columns ku_.. : W^T (A E); the U_0 block from the source; the block below it mirrored
-      if (ne > 0)
+      // columns ku_.. : W^T (A E) (the MFMA projection for up to 16 columns, one pass over
+      // W); the U_0 block from the source; the block below it mirrored
+      if (ne > 0 && ne <= G_MAX)
+        launch_proj(W, ld_, nj, AW + k0 * ld_, ld_, ne, n_, GW + (int64_t)k0 * nj, nj,
+                    gt_part_, st_);
+      else if (ne > 0)
         launch_gram(W, ld_, nj, AW + k0 * ld_, ld_, ne, n_, nullptr, false, nullptr, 0, 0.0,
                     GW + (int64_t)k0 * nj, nj, gram_part_, st_);
       launch_gram_assemble(GWs_ + (int64_t)from * NJ_MAX * NJ_MAX, w_nj_[from], k0, GW, nj,

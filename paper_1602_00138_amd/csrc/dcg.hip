@@ -355,7 +355,11 @@ struct OpPlane {
 
 // The operator step of member y over the z planes [tz zc, + zc) of the x-y positions of
 // block tx (NP consecutive x-nodes per thread; see step_block).  See the file comment.
-template <typename T, bool VAR, int NP, int NJT>
+// LY (four-node walk, a block's positions whole rows of the plane): each plane's q and
+// y-face coefficients are staged in LDS (two buffers, one barrier per plane), and a
+// position's y-neighbours inside the block's rows are read from there; only the block's
+// first and last rows load theirs.
+template <typename T, bool VAR, int NP, int NJT, bool LY = false>
 __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict__ diag,
                                                    const T* __restrict__ q0,
                                                    const T* __restrict__ s0, T* __restrict__ w0,
@@ -426,18 +430,23 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   // position are the adjacent lanes' end values (moved across the wave below); only the
   // wave's first and last lanes load theirs
   constexpr bool XS = NP == 4;
+  static_assert(!LY || XS, "the LDS y-neighbours need the four-node walk");
   const int xln = threadIdx.x % WAVE;
+  const int lrw = LY ? threadIdx.x / rowp : 0;   // row within the block's rows
+  const bool frow = !LY || lrw == 0, lrow = !LY || lrw == OP_BS / rowp - 1;
+  __shared__ __align__(16) T lyq[LY ? 2 * OP_BS * NP : 1];
+  __shared__ __align__(16) T lyf[(LY && VAR) ? 2 * OP_BS * NP : 1];
   auto load_plane = [&](uint32_t bj, int z) {
     if (z < S.nz - 1) ldb(q, bj + bplane, P.xp); else zero(P.xp);
     P.xl = (hl && (!XS || xln == 0)) ? ld1<-1>(q, bj) : T(0);
     P.xr = (hr && (!XS || xln == WAVE - 1)) ? ld1<NP>(q, bj) : T(0);
-    if (hd) ldb(q, bj - bx, P.yd); else zero(P.yd);
-    if (hu) ldb(q, bj + bx, P.yu); else zero(P.yu);
+    if (hd && frow) ldb(q, bj - bx, P.yd); else zero(P.yd);
+    if (hu && lrow) ldb(q, bj + bx, P.yu); else zero(P.yu);
     ldb(diag, bj, P.d);
     if (VAR) {
       P.fxl = (hl && (!XS || xln == 0)) ? ld1<-1>(Fx, bj) : T(0);
       ldb(Fx, bj, P.fx);
-      if (hd) ldb(Fy, bj - bx, P.fyd); else zero(P.fyd);
+      if (hd && frow) ldb(Fy, bj - bx, P.fyd); else zero(P.fyd);
       ldb(Fy, bj, P.fyu);
       if (S.dim == 3) ldb(Fz, bj, P.fp); else zero(P.fp);
     }
@@ -553,6 +562,29 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
   // that the loop's loads need no branch: under one, the registers of the plane would be
   // merged and copied every plane)
   auto plane = [&](int z, bool more) __attribute__((always_inline)) {
+    // y-neighbours: loaded, or with LY from the plane's rows staged in LDS
+    T yd[NP], yu[NP], fyd[NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      yd[u] = P.yd[u];
+      yu[u] = P.yu[u];
+      fyd[u] = VAR ? P.fyd[u] : T(0);
+    }
+    if (LY) {
+      const int bo = ((z - z0) & 1) * OP_BS * NP;
+      T* tq = lyq + bo;
+      T* tf = lyf + ((LY && VAR) ? bo : 0);
+      const int me = threadIdx.x * NP;
+      stn(tq, me, xc);
+      if (VAR) stn(tf, me, P.fyu);
+      __syncthreads();
+      // inside the block's rows the neighbour rows exist (hd, hu hold there)
+      if (!frow) {
+        ldn(tq, me - rowp * NP, yd);
+        if (VAR) ldn(tf, me - rowp * NP, fyd);
+      }
+      if (!lrow) ldn(tq, me + rowp * NP, yu);
+    }
     // (A q) at the NP nodes
     T xl = P.xl, xr = P.xr, fxl = P.fxl;
     if (XS) {
@@ -573,11 +605,11 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
       const T right = u == NP - 1 ? xr : xc[u + 1];
       T v = P.d[u] * xc[u];
       if (!VAR) {
-        v -= cx * (left + right) + cy * (P.yd[u] + P.yu[u]) + cz * (xm[u] + P.xp[u]);
+        v -= cx * (left + right) + cy * (yd[u] + yu[u]) + cz * (xm[u] + P.xp[u]);
       } else {
         const T fl = u == 0 ? fxl : P.fx[u - 1];
         v -= fl * left + P.fx[u] * right;
-        v -= P.fyd[u] * P.yd[u] + P.fyu[u] * P.yu[u];
+        v -= fyd[u] * yd[u] + P.fyu[u] * yu[u];
         if (S.dim == 3) v -= fm[u] * xm[u] + P.fp[u] * P.xp[u];
       }
       av[u] = v;   // masked in w below
@@ -1331,10 +1363,27 @@ void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, cons
     case 32: OPL(VAR, NP, 32); break;     \
     default: OPL(VAR, NP, 64); break;     \
   }
+#define OPLY(VAR, J)                                                                          \
+  ROM_LAUNCH((k_dcg_op<T, VAR, 4, J, true>), grid, dim3(OP_BS), 0, st, S, diag, q, s, w,      \
+             vstride, AW, sl, Ginv, Gm, gstride, sh.zc, gx, ntiles, nb, cg, cv, ps, Ps,       \
+             psstride, pu, Pu, pustride, po, postride)
+#define OPJY(VAR)                         \
+  switch (njt_of(njmax)) {                \
+    case 8: OPLY(VAR, 8); break;          \
+    case 16: OPLY(VAR, 16); break;        \
+    case 32: OPLY(VAR, 32); break;        \
+    default: OPLY(VAR, 64); break;        \
+  }
   if (sh.quads) {
-    // FP32 only (16-byte loads of four nodes)
+    // FP32 only (16-byte loads of four nodes); the LDS y-neighbours where a block's
+    // positions are whole rows and every block is full
     if constexpr (sizeof(T) == 4) {
-      if (S.var) { OPJ(true, 4) } else { OPJ(false, 4) }
+      const int rowp = S.nx / 4;
+      if (OP_BS % rowp == 0 && ((int64_t)rowp * S.ny) % OP_BS == 0) {
+        if (S.var) { OPJY(true) } else { OPJY(false) }
+      } else {
+        if (S.var) { OPJ(true, 4) } else { OPJ(false, 4) }
+      }
     } else {
       throw Error(ROM_EINVAL, "dcg_op: the four-node walk is FP32 only");
     }
@@ -1343,6 +1392,8 @@ void launch_dcg_op(const Stencil& S, const StencilShape& sh, const T* diag, cons
   } else {
     if (S.var) { OPJ(true, 1) } else { OPJ(false, 1) }
   }
+#undef OPJY
+#undef OPLY
 #undef OPJ
 #undef OPL
   ROM_CHECK_LAUNCH();

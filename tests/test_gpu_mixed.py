@@ -108,6 +108,22 @@ def test_mixed_sequence_parity(drv, wl):
     prob.close()
 
 
+@pytest.mark.parametrize("D,group", [("const", 1), ("lognormal", 1), ("lognormal", 8)])
+def test_mixed_whole_row_tiles(drv, D, group):
+    """32 x 32 planes: the FP32 operator step's four-node walk fills every block with whole
+    rows (8 positions of four nodes per row, 256 per plane), so it takes the y-neighbours
+    inside a block from LDS; the same gates as the other mixed sequences."""
+    kw = {} if D == "const" else {"D": "lognormal"}
+    wl = ph.small(3, (32, 32, 6), n_src=5, n_det=4, K=3, **kw)
+    print(f"\nmixed whole-row tiles {wl.N} D {D} group {group}", flush=True)
+    orc = OracleProblem(wl)
+    ores = orc.run(group=group)
+    prob, pts, res = _mixed_run(drv, wl, group=group)
+    _check_mixed(wl, orc, ores, prob, pts, res)
+    res.close()
+    prob.close()
+
+
 def test_mixed_inner_tolerance_and_fallback(drv):
     """A loose inner tolerance needs more refinement sweeps but meets the same FP64
     tolerance; an inner tolerance below what FP32 can deliver (1e-9, raised to the

@@ -133,11 +133,8 @@ def stream_points(prob, pts, W: int, K: int, wl, timing: int = 0, reduce_each: b
 # KiB per dispatch, averaged over the dispatches) on the default headline command, and the
 # scale of each counter from a plain device copy of known size.  Reported as `traffic`
 # only for that configuration; a change to the kernel needs new counter runs.
-OP_TRAFFIC = {"fetch_kib": 178274.4, "write_kib": 53765.2, "fetch_scale": 2.0,
-              "write_scale": 1.0, "dispatches": 45707,
-              "config": {"workload": "cube128_lognormal", "precision": "mixed", "group": 8,
-                         "cg_step": 1},
-              "profile": "profiles/cg_operator_step_cube128_lognormal_group8.md"}
+# None until the counters are taken on the current kernel.
+OP_TRAFFIC = None
 
 
 def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None,

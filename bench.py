@@ -133,8 +133,11 @@ def stream_points(prob, pts, W: int, K: int, wl, timing: int = 0, reduce_each: b
 # KiB per dispatch, averaged over the dispatches) on the default headline command, and the
 # scale of each counter from a plain device copy of known size.  Reported as `traffic`
 # only for that configuration; a change to the kernel needs new counter runs.
-# None until the counters are taken on the current kernel.
-OP_TRAFFIC = None
+OP_TRAFFIC = {"fetch_kib": 174923.2, "write_kib": 53728.1, "fetch_scale": 2.0,
+              "write_scale": 1.0, "dispatches": 45774,
+              "config": {"workload": "cube128_lognormal", "precision": "mixed", "group": 8,
+                         "cg_step": 1},
+              "profile": "profiles/cg_operator_step_cube128_lognormal_group8.md"}
 
 
 def dcg_roofline(timed: dict, precision: str, prob, wl, all_pts: dict = None,

@@ -812,9 +812,14 @@ class Sequencer {
     if (ne > 0) launch_spmm(S_, diag_i_, W + k0 * ld_, ld_, ne, AW + k0 * ld_, st_);
     tm_->begin(ROM_K_GRAM);
     if (!part) {
-      // symmetric by construction: the lower triangle W_i^T (A W_j), i >= j, is mirrored
-      launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, true, nullptr, 0, 0.0, GW, nj,
-                  gram_part_, st_);
+      // up to 16 columns the MFMA projection W^T (A W) in one pass over W (the factorisation
+      // below symmetrises it); wider, the tile Gram kernel, whose lower triangle
+      // W_i^T (A W_j), i >= j, is mirrored
+      if (nj <= G_MAX)
+        launch_proj(W, ld_, nj, AW, ld_, nj, n_, GW, nj, gt_part_, st_);
+      else
+        launch_gram(W, ld_, nj, AW, ld_, nj, n_, nullptr, true, nullptr, 0, 0.0, GW, nj,
+                    gram_part_, st_);
       tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
     } else {
       // columns ku_.. : W^T (A E) (the MFMA projection for up to 16 columns, one pass over

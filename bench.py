@@ -34,7 +34,7 @@ FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
 METRIC = "full-order solves/sec at 1e-8 rel. residual; SpMM HBM GB/s vs peak"
 
-# The paper's own numbers for this path (context, not a target; BASELINE.md): no wall-clock
+# The paper's own numbers for this path (context, not a target): no wall-clock
 # time is reported, only iteration counts (Table 1: MINRES iterations without / with
 # inner-outer recycling, 2D 201 x 201 mesh, 32 + 32 right-hand sides, 10 eigenvectors in
 # U_0, tolerance 1e-7) and the totals of the comparison with per-right-hand-side recycling.
@@ -346,7 +346,7 @@ def measure_modes(prob, pts, wl, reps: int = 3, guards: int = 6):
 
 
 def measure_learned(name: str, train_points: int, train_steps: int, reps: int = 1):
-    """The benchmark spec's target comparison on workload `name`: plain FP64 recycled CG in the
+    """The learned-seed comparison on workload `name`: plain FP64 recycled CG in the
     paper's order against the batched (groups of 8) mixed-precision form with and without
     the learned seed, whole sequences on the same problem.  The seed network is trained on
     the GPU (untimed, reported) on solutions the method produced at other parameter points

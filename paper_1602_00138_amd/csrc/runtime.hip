@@ -781,8 +781,10 @@ class Sequencer {
   // of A_i U_j (and their FP32 copies), the same for every member; -1 before the group's
   // first member is built, which then builds them in full and becomes the source.  Later
   // members form A_i only on their own columns (the CG kernels read the shared ones from
-  // the source slot) and take the U_0 block of their Gram matrix from the source's.  The
-  // FP64 U_j is always packed in full (U^T r and the Gram-Schmidt pass of U_j read it).
+  // the source slot) and take the U_0 block of their Gram matrix from the source's.  They
+  // pack only their own columns of U_j too: U_0's are V's first ku_ columns, read from Q_
+  // for U^T r and the Gram border, and packed into the slot only before a Gram-Schmidt
+  // pass against U_j (update_Uj).
   int make_W(int i, int j, int y, int* src = nullptr) {
     const int key = i == 0 ? -1 : j;
     ColPtrs cp;
@@ -808,7 +810,14 @@ class Sequencer {
     double* GW = GWs_ + (int64_t)y * NJ_MAX * NJ_MAX;
     const int k0 = part ? ku_ : 0;   // first column formed here
     const int ne = nj - k0;
-    launch_pack_cols(n_, cp, nj, W, ld_, st_);
+    if (part) {
+      ColPtrs co;
+      for (int c = 0; c < ne; ++c) co.p[c] = cp.p[k0 + c];
+      if (ne > 0) launch_pack_cols(n_, co, ne, W + k0 * ld_, ld_, st_);
+    } else {
+      launch_pack_cols(n_, cp, nj, W, ld_, st_);
+    }
+    w_full_[y] = !part;
     if (ne > 0) launch_spmm(S_, diag_i_, W + k0 * ld_, ld_, ne, AW + k0 * ld_, st_);
     tm_->begin(ROM_K_GRAM);
     if (!part) {
@@ -822,14 +831,20 @@ class Sequencer {
                     gram_part_, st_);
       tm_->end(ROM_K_GRAM, 16.0 * n_ * nj, 2.0 * n_ * nj * nj);
     } else {
-      // columns ku_.. : W^T (A E) (the MFMA projection for up to 16 columns, one pass over
-      // W); the U_0 block from the source; the block below it mirrored
-      if (ne > 0 && ne <= G_MAX)
-        launch_proj(W, ld_, nj, AW + k0 * ld_, ld_, ne, n_, GW + (int64_t)k0 * nj, nj,
-                    gt_part_, st_);
-      else if (ne > 0)
-        launch_gram(W, ld_, nj, AW + k0 * ld_, ld_, ne, n_, nullptr, false, nullptr, 0, 0.0,
-                    GW + (int64_t)k0 * nj, nj, gram_part_, st_);
+      // columns ku_.. : [U_0, E]^T (A E), U_0 from Q_ and E from the slot (the MFMA
+      // projection for up to 16 columns); the U_0 block from the source; the block below
+      // it mirrored
+      double* Gb = GW + (int64_t)k0 * nj;
+      if (ne > 0 && ne <= G_MAX) {
+        launch_proj(Q_, ld_, k0, AW + k0 * ld_, ld_, ne, n_, Gb, nj, gt_part_, st_);
+        launch_proj(W + k0 * ld_, ld_, ne, AW + k0 * ld_, ld_, ne, n_, Gb + k0, nj, gt_part_,
+                    st_);
+      } else if (ne > 0) {
+        launch_gram(Q_, ld_, k0, AW + k0 * ld_, ld_, ne, n_, nullptr, false, nullptr, 0, 0.0, Gb,
+                    nj, gram_part_, st_);
+        launch_gram(W + k0 * ld_, ld_, ne, AW + k0 * ld_, ld_, ne, n_, nullptr, false, nullptr,
+                    0, 0.0, Gb + k0, nj, gram_part_, st_);
+      }
       launch_gram_assemble(GWs_ + (int64_t)from * NJ_MAX * NJ_MAX, w_nj_[from], k0, GW, nj,
                            st_);
       tm_->end(ROM_K_GRAM, 8.0 * n_ * (nj + ne), 2.0 * n_ * nj * ne);
@@ -985,6 +1000,12 @@ class Sequencer {
     }
     double* slot = pool_ + (int64_t)next_slot_ * ld_;
     launch_axpby(n_, 1.0, gptr, 0.0, nullptr, slot, nullptr, red_part_, st_);
+    if (!w_full_[y]) {
+      ColPtrs cu;
+      for (int c = 0; c < ku_; ++c) cu.p[c] = Q_ + (int64_t)c * ld_;
+      launch_pack_cols(n_, cu, ku_, Wp_ + (int64_t)y * ld_ * NJ_MAX, ld_, st_);
+      w_full_[y] = true;
+    }
     const double ru = cgs2_inplace(slot, Wp_ + (int64_t)y * ld_ * NJ_MAX, std::min(npers, nj));
     if (ru > trunc_) {
       launch_normalize(n_, slot, &ctrl_->sc[4], st_);
@@ -1778,6 +1799,22 @@ class Sequencer {
         launch_proj(Wp_, ld_, njmax, rhs, ld_, nb, n_, cg[0].t, sizeof(CGState) / sizeof(double),
                     gt_part_, st_);
         tm_->end(ROM_K_GEMVT, 8.0 * n_ * (njmax + nb), 2.0 * n_ * njmax * nb);
+      } else if (!bt.shared && bt.src >= 0 && ku_ > 0) {
+        // U_0's part of every member's U_j^T r from V's first ku_ columns in one projection
+        // over the batch's right-hand sides (the values of inactive members are unused),
+        // then each active member's own columns
+        tm_->begin(ROM_K_GEMVT);
+        launch_proj(Q_, ld_, ku_, rhs, ld_, nb, n_, cg[0].t, sizeof(CGState) / sizeof(double),
+                    gt_part_, st_);
+        tm_->end(ROM_K_GEMVT, 8.0 * n_ * (ku_ + nb), 2.0 * n_ * ku_ * nb);
+        for (int y = 0; y < nb; ++y)
+          if (bt.active[y] && bt.nj[y] > ku_) {
+            const int ne = bt.nj[y] - ku_;
+            tm_->begin(ROM_K_GEMVT);
+            launch_gemvt(Wp_ + y * wstride + (int64_t)ku_ * ld_, ld_, n_, ne,
+                         rhs + (int64_t)y * ld_, 0, 1, cg[y].t + ku_, gt_part_, st_);
+            tm_->end(ROM_K_GEMVT, 8.0 * n_ * (ne + 1), 2.0 * n_ * ne);
+          }
       } else {
         for (int y = 0; y < nb; ++y)
           if (bt.active[y] && bt.nj[y] > 0) {
@@ -2036,6 +2073,7 @@ class Sequencer {
   double mu0_ = 0.0;
   int m_ = 0, ku_ = 0, next_slot_ = 0;
   int w_key_[G_MAX], w_nj_[G_MAX] = {}, w_src_[G_MAX] = {};
+  bool w_full_[G_MAX] = {};   // the slot holds U_0's columns too (see make_W)
   // results
   std::vector<rom_record> recs_;
   rom_status status_ = ROM_OK;

@@ -453,9 +453,9 @@ __global__ __launch_bounds__(OP_BS) void k_dcg_op(Stencil S, const T* __restrict
     if (act) ldb(s, bj, P.s); else zero(P.s);
     if (PRE) {
       // the loads are the kernel's limit (address processing per load instruction), so the
-      // columns past nj are not loaded: their rows stay 0 from the start (coefficient 0,
-      // rows unused), and no branch merges a column's registers with other values; lanes
-      // past the plane read position 0 and add nothing (their s and w are 0)
+      // columns past nj are not loaded (a uniform branch per column, without an else: their
+      // registers keep the 0 they start with, their coefficient is 0 and their sums unused);
+      // lanes past the plane read position 0 and add nothing (their s and w are 0)
 #pragma unroll
       for (int c = 0; c < NJT; ++c)
         if (c < nj) ldb(col_of(AW, AWs, ns, c, ld), bj, P.a[PRE ? c : 0]);
